@@ -1,0 +1,170 @@
+/*
+ * df.h -- C ABI of the MI355X (gfx950) per-cell chemistry step library.
+ *
+ * The library advances the thermochemical state of N independent cells over
+ * one chemistry sub-step of an operator-split reacting-flow solver, in the
+ * two forms of DeepFlame (arXiv 2210.07094):
+ *   (a) detailed chemistry integrated by a stiff solver (the paper integrates
+ *       the species source-term equation of Sec. "Chemistry Integration" with
+ *       CVODE; this library uses the L-stable Rosenbrock method RODAS4 with
+ *       error control, Hairer & Wanner, Solving ODEs II, Sec. IV.7), and
+ *   (b) the paper's DNN integrator (same section: input T, P and the Box-Cox
+ *       transform of Y; three hidden layers; output = change of the input
+ *       over a 1 us step), in the three stages of DNNInferencer::inference
+ *       (Sec. "Description of the new classes").
+ * The flow solver hands over (p, T, Y) per cell and receives the new state and
+ * the reaction rates (the OpenFOAM <-> chemistry coupling of Sec. "DeepFlame
+ * Code Structure"; dfChemistryModel::solve() and RR()).
+ *
+ * Conventions shared by every call
+ *  - All state arrays are caller-owned DEVICE memory on the handle's device.
+ *    The library never frees them and keeps no reference after the call.
+ *  - Layout is structure-of-arrays: per-cell scalars are [n] arrays; species
+ *    arrays are species-major, element (k, i) at Y[k * ld + i], ld >= n.
+ *  - Units are SI: p [Pa], T [K], dt [s], rr [kg/m^3/s]; Y are mass fractions.
+ *  - Calls that take a hip_stream (a hipStream_t, NULL = default stream) are
+ *    asynchronous on it.  Argument errors are detected on the host and
+ *    returned before anything is launched; outputs are valid once the stream
+ *    has completed.
+ *  - Return value: DF_OK (0) on success, a negative DF_E_* code on error (no
+ *    output has been written).  df_last_error() then describes the error.
+ *  - Per-cell outcomes go to cell_status[i] (DF_CELL_*), when given.
+ *  - Handles are immutable after load and may be shared by threads.
+ */
+#ifndef DF_H
+#define DF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t df_status;
+
+/* return codes */
+#define DF_OK 0
+#define DF_E_INVALID (-1)     /* bad argument (null pointer, n < 0, ld < n, dt <= 0, ...) */
+#define DF_E_UNSUPPORTED (-2) /* valid but not supported (too many species, dt != DNN training dt, ...) */
+#define DF_E_HIP (-3)         /* HIP runtime error (allocation, copy, launch) */
+#define DF_E_IO (-4)          /* file cannot be opened or read */
+#define DF_E_FORMAT (-5)      /* file content malformed */
+
+/* per-cell status codes */
+#define DF_CELL_OK 0
+#define DF_CELL_MAX_STEPS 1    /* integrator stopped after max_steps attempts; state as reached */
+#define DF_CELL_H_UNDERFLOW 2  /* a rejected step pushed h below h_min; state as reached */
+#define DF_CELL_NONFINITE 3    /* input not finite / T <= 0 / p <= 0 (state untouched), or the DNN
+                                  temperature recovery did not converge */
+#define DF_CELL_DNN_FALLBACK 4 /* DNN form: cell outside the network's training range, advanced by
+                                  the integrator instead (success) */
+
+typedef struct df_mech df_mech; /* opaque mechanism handle */
+typedef struct df_dnn df_dnn;   /* opaque DNN handle */
+
+/* Integrator options (see df_chem_default_opts for the defaults). */
+typedef struct {
+    double rtol;       /* relative tolerance, default 1e-8 */
+    double atol_T;     /* absolute tolerance on T [K], default 1e-6 */
+    double atol_Y;     /* absolute tolerance on Y, default 1e-14 */
+    double h_min;      /* smallest sub-step [s], default 1e-20 */
+    int32_t max_steps; /* attempted sub-steps per cell and call, default 100000 */
+    int32_t reserved;  /* must be 0 */
+} df_chem_opts;
+
+/* DNN options. */
+typedef struct {
+    int32_t renormalise; /* 1 (default): rescale the predicted Y to sum 1 */
+    int32_t fallback;    /* 1 (default): integrate cells outside the training range;
+                            0: leave them unchanged and flag DF_CELL_DNN_FALLBACK */
+    int32_t reserved0, reserved1; /* must be 0 */
+} df_dnn_opts;
+
+/* Message describing the last error of this thread; valid until the next df_* call. */
+const char *df_last_error(void);
+
+/* Library version string. */
+const char *df_version(void);
+
+void df_chem_default_opts(df_chem_opts *opts);
+void df_dnn_default_opts(df_dnn_opts *opts);
+
+/*
+ * Load a mechanism file ("dfmech 1" text format: elements, species molar
+ * masses and compositions, single-range NASA-7 thermo, reactions with
+ * reactant/product stoichiometry, Arrhenius parameters in cm-mol-s units,
+ * third-body efficiencies, Troe falloff parameters) and upload its tables to
+ * `device`.  The species source term follows the paper's equation in Sec.
+ * "Chemistry Integration"; the rate-constant forms (Arrhenius, third body,
+ * Troe falloff, reverse rate from the equilibrium constant) are the standard
+ * forms the paper leaves to Cantera.  At most 3 molecules per reaction side.
+ * Errors: DF_E_INVALID (null path/out), DF_E_IO, DF_E_FORMAT, DF_E_HIP.
+ * On success *out owns host and device tables; release with df_mech_free.
+ */
+df_status df_mech_load(const char *path, int32_t device, df_mech **out);
+void df_mech_free(df_mech *mech);
+df_status df_mech_info(const df_mech *mech, int32_t *n_species, int32_t *n_reactions, int32_t *n_elements);
+
+/*
+ * Advance n_cells constant-pressure adiabatic reactors by dt (detailed
+ * chemistry, the paper's dfChemistryModel::solve() with its stiff solver;
+ * the species line is the source-term equation of Sec. "Chemistry
+ * Integration" with the density written out, and T follows from constant
+ * enthalpy at fixed p).
+ *   p           [n]      in      pressure per cell
+ *   T           [n]      in/out  temperature
+ *   Y           [K*ld]   in/out  mass fractions
+ *   h_inout     [n]      in/out  sub-step hint carried across calls (<= 0 or NULL: estimate)
+ *   rr          [K*ld]   out     rho0 (Y - Y0) / dt, rho0 the density at the start (nullable)
+ *   cell_status [n]      out     DF_CELL_* (nullable)
+ *   n_steps     [2*n]    out     accepted sub-steps at [i], rejected at [n + i] (nullable)
+ *   opts        nullable = defaults
+ * Cells with non-finite input are left untouched with DF_CELL_NONFINITE.
+ * Errors: DF_E_INVALID (null handle/array, n < 0, ld < n, dt not > 0 and
+ * finite, bad opts), DF_E_UNSUPPORTED (species count beyond the compiled
+ * kernels), DF_E_HIP.
+ */
+df_status df_chem_step(const df_mech *mech, int64_t n_cells, int64_t ld, double dt, const double *p, double *T,
+                       double *Y, double *h_inout, double *rr, int32_t *cell_status, int32_t *n_steps,
+                       const df_chem_opts *opts, void *hip_stream);
+
+/*
+ * Load a DNN weights file ("DFDNN01", little-endian: int32 L, dims[L+1], K,
+ * reserved; f64 lambda, dt_train; f64 mu_in[K+2], sig_in[K+2], mu_out[K],
+ * sig_out[K], box_lo[K+2], box_hi[K+2]; per layer bf16 W[out][in], f32
+ * b[out]).  Inputs are (T, p, BoxCox(Y_1..Y_K)) and outputs the normalised
+ * increments of BoxCox(Y) over dt_train, the structure of Sec. "Chemistry
+ * Integration" (three hidden layers, GELU).  `mech` must have the same K.
+ * Errors: DF_E_INVALID, DF_E_IO, DF_E_FORMAT, DF_E_UNSUPPORTED (layer count
+ * or widths the kernels do not take), DF_E_HIP.
+ */
+df_status df_dnn_load(const char *path, const df_mech *mech, int32_t device, df_dnn **out);
+void df_dnn_free(df_dnn *dnn);
+df_status df_dnn_info(const df_dnn *dnn, int32_t *n_layers, int32_t *dims /* [n_layers+1] */, double *lambda,
+                      double *dt_train);
+
+/* Bytes of device workspace df_dnn_step needs for n_cells. */
+df_status df_dnn_workspace_size(const df_dnn *dnn, int64_t n_cells, size_t *bytes);
+
+/*
+ * DNN chemistry step (DNNInferencer::inference): (1) Box-Cox transform and
+ * normalisation of (T, p, Y) with the training-range test, (2) the MLP in
+ * BF16 with FP32 accumulation, (3) inverse transform, optional
+ * renormalisation of Y, T from enthalpy conservation at fixed p, and rr.
+ * Cells outside the training range are advanced by df_chem_step instead
+ * (fallback_opts) and flagged DF_CELL_DNN_FALLBACK.  Arguments as in
+ * df_chem_step; `workspace` is caller-owned device memory of at least
+ * df_dnn_workspace_size bytes, 256-byte aligned.
+ * Errors: DF_E_INVALID, DF_E_UNSUPPORTED (dt != the network's dt_train,
+ * relative difference above 1e-12), DF_E_HIP.
+ */
+df_status df_dnn_step(const df_dnn *dnn, const df_mech *mech, int64_t n_cells, int64_t ld, double dt,
+                      const double *p, double *T, double *Y, double *rr, int32_t *cell_status, void *workspace,
+                      size_t workspace_bytes, const df_dnn_opts *opts, const df_chem_opts *fallback_opts,
+                      void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DF_H */

@@ -1,0 +1,173 @@
+"""Per-cell chemistry step on MI355X (gfx950): Python binding of libdf.so.
+
+Every step of the computation runs in the HIP library; this module only
+passes torch tensors (device memory) and the current HIP stream through the
+C ABI declared in ``include/df.h``.
+
+    import paper_2210_07094_amd as df
+    mech = df.Mechanism("synth/data/h2_synth_9sp_24r.mech")
+    st = mech.chem_step(T, p, Y, 1e-6)        # T[n], p[n], Y[K, ld] float64 cuda tensors, in place
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+from ._lib import (CELL_DNN_FALLBACK, CELL_H_UNDERFLOW, CELL_MAX_STEPS, CELL_NONFINITE, CELL_OK, ChemOpts,  # noqa
+                   DfError, DnnOpts, check, lib)
+
+__all__ = ["Mechanism", "DNN", "chem_opts", "dnn_opts", "DfError", "lib"]
+
+
+def chem_opts(**kw) -> ChemOpts:
+    o = ChemOpts()
+    lib().df_chem_default_opts(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def dnn_opts(**kw) -> DnnOpts:
+    o = DnnOpts()
+    lib().df_dnn_default_opts(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _ptr(t, dtype, name, numel=None, device=None):
+    """data pointer of a contiguous cuda tensor of the given dtype (None passes NULL)."""
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name}: expected a device (cuda/HIP) tensor, got {t.device}")
+    if device is not None and t.device.index != device:
+        raise ValueError(f"{name}: tensor on device {t.device.index}, handle on device {device}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: tensor must be contiguous")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"{name}: needs at least {numel} elements, has {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Mechanism:
+    """A loaded mechanism (df_mech_load); tables live on `device`."""
+
+    def __init__(self, path, device: int = 0):
+        self.path = str(path)
+        self.device = int(device)
+        h = C.c_void_p()
+        check(lib().df_mech_load(self.path.encode(), self.device, C.byref(h)))
+        self._h = h
+        K, M, E = C.c_int32(), C.c_int32(), C.c_int32()
+        check(lib().df_mech_info(self._h, C.byref(K), C.byref(M), C.byref(E)))
+        self.n_species, self.n_reactions, self.n_elements = K.value, M.value, E.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().df_mech_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def chem_step(self, T, p, Y, dt, h=None, rr=None, status=None, n_steps=None, opts=None, stream=None):
+        """Advance every cell by dt in place (df_chem_step).
+
+        T, p: float64 [n]; Y: float64 [K, ld] (species-major, ld >= n); optional
+        h [n] (sub-step hint, in/out), rr [K, ld], status int32 [n], n_steps
+        int32 [2n].  Asynchronous on `stream` (default: torch's current stream).
+        """
+        import torch
+        n = T.numel()
+        K = self.n_species
+        if Y.dim() != 2 or Y.shape[0] != K:
+            raise ValueError(f"Y must have shape [{K}, ld]")
+        ld = Y.shape[1]
+        dev = self.device
+        args = (self._h, n, ld, float(dt),
+                _ptr(p, torch.float64, "p", n, dev), _ptr(T, torch.float64, "T", n, dev),
+                _ptr(Y, torch.float64, "Y", K * ld, dev), _ptr(h, torch.float64, "h", n, dev),
+                _ptr(rr, torch.float64, "rr", K * ld, dev), _ptr(status, torch.int32, "status", n, dev),
+                _ptr(n_steps, torch.int32, "n_steps", 2 * n, dev),
+                C.byref(opts) if opts is not None else None, _stream(stream))
+        return check(lib().df_chem_step(*args))
+
+
+class DNN:
+    """A loaded DNN chemistry integrator (df_dnn_load)."""
+
+    def __init__(self, path, mech: Mechanism, device: int = 0):
+        self.path = str(path)
+        self.mech = mech
+        self.device = int(device)
+        h = C.c_void_p()
+        check(lib().df_dnn_load(self.path.encode(), mech.handle, self.device, C.byref(h)))
+        self._h = h
+        L = C.c_int32()
+        dims = (C.c_int32 * 16)()
+        lam, dtt = C.c_double(), C.c_double()
+        check(lib().df_dnn_info(self._h, C.byref(L), dims, C.byref(lam), C.byref(dtt)))
+        self.n_layers = L.value
+        self.dims = [dims[i] for i in range(L.value + 1)]
+        self.lam = lam.value
+        self.dt_train = dtt.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().df_dnn_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self, n_cells: int) -> int:
+        b = C.c_size_t()
+        check(lib().df_dnn_workspace_size(self._h, int(n_cells), C.byref(b)))
+        return b.value
+
+    def workspace(self, n_cells: int):
+        import torch
+        nb = self.workspace_bytes(n_cells)
+        return torch.empty(max(nb, 1), dtype=torch.uint8, device=f"cuda:{self.device}")
+
+    def step(self, T, p, Y, dt, rr=None, status=None, workspace=None, opts=None, fallback_opts=None, stream=None):
+        """DNN chemistry step in place (df_dnn_step); arguments as Mechanism.chem_step."""
+        import torch
+        n = T.numel()
+        K = self.mech.n_species
+        if Y.dim() != 2 or Y.shape[0] != K:
+            raise ValueError(f"Y must have shape [{K}, ld]")
+        ld = Y.shape[1]
+        dev = self.device
+        if workspace is None:
+            workspace = self.workspace(n)
+        if workspace.dtype != torch.uint8:
+            raise TypeError("workspace must be a uint8 tensor")
+        args = (self._h, self.mech.handle, n, ld, float(dt),
+                _ptr(p, torch.float64, "p", n, dev), _ptr(T, torch.float64, "T", n, dev),
+                _ptr(Y, torch.float64, "Y", K * ld, dev), _ptr(rr, torch.float64, "rr", K * ld, dev),
+                _ptr(status, torch.int32, "status", n, dev), _ptr(workspace, torch.uint8, "workspace", None, dev),
+                workspace.numel(), C.byref(opts) if opts is not None else None,
+                C.byref(fallback_opts) if fallback_opts is not None else None, _stream(stream))
+        return check(lib().df_dnn_step(*args))

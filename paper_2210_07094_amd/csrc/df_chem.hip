@@ -1,0 +1,663 @@
+// Detailed-chemistry step on gfx950: one cell per lane, FP64 throughout.
+//
+// Each lane integrates the constant-pressure adiabatic reactor of its cell,
+//   dY_k/dt = W_k wdot_k / rho,  dT/dt = -sum_k h_k dY_k/dt / cp
+// (the species source term of the paper's Sec. "Chemistry Integration", with
+// the density written out), with the L-stable Rosenbrock method RODAS4
+// (Hairer & Wanner, Solving ODEs II, Sec. IV.7, transformed form) and an
+// embedded error estimate.  The kernel is table-driven: the species and
+// reaction tables live in one read-only allocation and are read with
+// wave-uniform indices, so they arrive through the scalar cache as SGPR
+// operands; per-lane state (y, Jacobian/LU, stage vectors) stays in
+// registers.  Per-species arrays are indexed 1..K with index 0 a neutral
+// element, so a reaction side with fewer than three molecules needs no
+// branch.
+#include <cmath>
+
+#include "df_internal.h"
+
+namespace df {
+namespace {
+
+// ---- RODAS4, transformed coefficients: (I/(g h) - J) u_i = f(y + sum a_ij u_j) + sum (c_ij/h) u_j
+struct Rodas4 {
+    static constexpr double g = 0.25;
+    static constexpr double a[6][5] = {
+        {0, 0, 0, 0, 0},
+        {1.544, 0, 0, 0, 0},
+        {0.9466785280815826, 0.2557011698983284, 0, 0, 0},
+        {3.314825187068521, 2.896124015972201, 0.9986419139977817, 0, 0},
+        {1.221224509226641, 6.019134481288629, 12.53708332932087, -0.6878860361058950, 0},
+        {1.221224509226641, 6.019134481288629, 12.53708332932087, -0.6878860361058950, 1.0},
+    };
+    static constexpr double c[6][5] = {
+        {0, 0, 0, 0, 0},
+        {-5.6688, 0, 0, 0, 0},
+        {-2.430093356833875, -0.2063599157091915, 0, 0, 0},
+        {-0.1073529058151375, -9.594562251023355, -20.47028614809616, 0, 0},
+        {7.496443313967647, -10.24680431464352, -33.99990352819905, 11.70890893206160, 0},
+        {8.083246795921522, -7.981132988064893, -31.52159432874371, 16.31930543123136, -6.058818238834054},
+    };
+    // stage 6 starts from the embedded (order 3) solution; the order-4 solution adds u6,
+    // so the error estimate is u6 itself.
+};
+
+constexpr double kInvLn10 = 0.43429448190325182765;
+constexpr double kLn10 = 2.30258509299404568402;
+
+struct Opts {
+    double rtol, atol_T, atol_Y, h_min;
+    int max_steps;
+};
+
+// Per-lane species arrays live in LDS, slot-major with a stride of one wave
+// (element k of lane l at sh[k * 64 + l]): a gather with a wave-uniform species
+// index is then a single conflict-free ds_read_b64 instead of a select chain
+// over registers.  Slot 0 of each array is the neutral element.
+constexpr int kWave = 64;
+
+template <int K>
+struct Cell {
+    static constexpr int N = K + 1;
+    // LDS slot offsets (in units of one wave-wide row of doubles).  The Jacobian-only
+    // arrays (H/RT, dq/dc) overlay the stage vectors u0..u3, which are dead while the
+    // Jacobian is formed.
+    static constexpr int kC = 0;       // concentrations, mol/cm^3; [0] = 1
+    static constexpr int kE = N;       // exp(-G_k/RT); [0] = 1
+    static constexpr int kIE = 2 * N;  // exp(+G_k/RT); [0] = 1
+    static constexpr int kU = 3 * N;   // stage vectors u0..u3 (N each)
+    static constexpr int kH = 3 * N;   // H_k/RT; [0] = 0   (Jacobian phase only)
+    static constexpr int kDQ = 4 * N;  // dq/dc scatter target (Jacobian phase only)
+    static constexpr int kULds = 4;    // stage vectors kept in LDS; the rest stay in registers
+    static constexpr int kRows = 3 * N + kULds * N;
+
+    __device__ __forceinline__ static double &at(double *sh, int slot) { return sh[slot * kWave]; }
+
+    struct Mix {
+        double T, iT, lT;
+        double rho, Wbar, cp;  // kg/m^3, kg/mol, J/kg/K
+        double cref, icref;    // p0/(RT) in mol/cm^3 and its inverse
+    };
+
+    // thermo of every species and the mixture at (T, Y); fills the LDS arrays c, e, ie
+    // (H/RT and cp/R are returned in registers: the H rows overlay stage vector u0)
+    __device__ __forceinline__ static void state(const MechDev &m, double p, const double (&y)[N], double *sh,
+                                                 Mix &s, double (&cpR)[N], double (&hRT)[N]) {
+        const double T = y[0];
+        s.T = T;
+        s.iT = 1.0 / T;
+        s.lT = log(T);
+        double sYW = 0.0, cpm = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const double *r = m.sp + k * kSpTab;
+            const double cp = r[2] + T * (r[3] + T * (r[4] + T * (r[5] + T * r[6])));
+            const double h = r[2] + T * (r[9] + T * (r[10] + T * (r[11] + T * r[12]))) + r[7] * s.iT;
+            const double sr = r[2] * s.lT + T * (r[3] + T * (r[13] + T * (r[14] + T * r[15]))) + r[8];
+            cpR[1 + k] = cp;
+            hRT[1 + k] = h;
+            const double ek = exp(sr - h);
+            at(sh, kE + 1 + k) = ek;
+            at(sh, kIE + 1 + k) = 1.0 / ek;
+            sYW += y[1 + k] * r[1];
+            cpm += y[1 + k] * cp * r[1];
+        }
+        s.Wbar = 1.0 / sYW;
+        s.rho = p * s.Wbar * s.iT * (1.0 / kR);
+        s.cp = cpm * kR;
+        const double cfac = 1e-6 * s.rho;
+#pragma unroll
+        for (int k = 0; k < K; ++k) at(sh, kC + 1 + k) = cfac * y[1 + k] * m.sp[k * kSpTab + 1];
+        cpR[0] = 0.0;
+        hRT[0] = 0.0;
+        s.cref = 1e-6 * kPref * s.iT * (1.0 / kR);
+        s.icref = 1.0 / s.cref;
+    }
+
+    // neutral slots, written once per kernel
+    __device__ __forceinline__ static void init_lds(double *sh) {
+        at(sh, kC) = 1.0;
+        at(sh, kE) = 1.0;
+        at(sh, kIE) = 1.0;
+    }
+
+    __device__ __forceinline__ static double cref_pow(const Mix &s, int dnu) {
+        // (p0/RT)^(-dnu): the reverse rate constant is kf / Kc, Kc = prod(e)^nu (p0/RT)^dnu
+        double r = 1.0;
+        if (dnu > 0)
+            for (int i = 0; i < dnu; ++i) r *= s.icref;
+        else
+            for (int i = 0; i < -dnu; ++i) r *= s.cref;
+        return r;
+    }
+
+    // Forward rate constant; for Troe rows also d ln kf/dT at fixed [M] and d kf/d[M].
+    template <bool DERIV>
+    __device__ __forceinline__ static double kforward(const double *rd, int type, const Mix &s, double Mc,
+                                                      double &dlnkf, double &dkfdM) {
+        const double kinf = exp(rd[0] + rd[1] * s.lT - rd[2] * s.iT);
+        const double dlninf = (rd[1] + rd[2] * s.iT) * s.iT;
+        if (type != 2) {
+            if (DERIV) {
+                dlnkf = dlninf;
+                dkfdM = 0.0;
+            }
+            return kinf;
+        }
+        const double T = s.T;
+        const double k0 = exp(rd[3] + rd[4] * s.lT - rd[5] * s.iT);
+        const double al = rd[6], i3 = rd[7], i1 = rd[8], T2 = rd[9];
+        const double e3 = exp(-T * i3), e1 = exp(-T * i1), e2 = exp(-T2 * s.iT);
+        const double Fc = (1.0 - al) * e3 + al * e1 + e2;
+        const double lFc = log(Fc) * kInvLn10;
+        const double Pr = k0 * Mc / kinf;
+        const double lPr = log(Pr) * kInvLn10;
+        const double cc = -0.4 - 0.67 * lFc;
+        const double nn = 0.75 - 1.27 * lFc;
+        const double x = lPr + cc;
+        const double iden = 1.0 / (nn - 0.14 * x);
+        const double f1 = x * iden;
+        const double q1 = 1.0 / (1.0 + f1 * f1);
+        const double F = exp(lFc * q1 * kLn10);
+        const double iPr1 = 1.0 / (1.0 + Pr);
+        const double kf = kinf * Pr * iPr1 * F;
+        if (DERIV) {
+            const double dlnk0 = (rd[4] + rd[5] * s.iT) * s.iT;
+            const double gq = 2.0 * f1 * q1 * q1;
+            const double dlF_dlPr = -lFc * gq * nn * iden * iden;
+            const double dlF_dlFc = q1 - lFc * gq * (1.27 * x - 0.67 * nn) * iden * iden;
+            const double dFc = -(1.0 - al) * i3 * e3 - al * i1 * e1 + T2 * s.iT * s.iT * e2;
+            const double dlFc_dT = dFc / Fc * kInvLn10;
+            dlnkf = dlninf + (iPr1 + dlF_dlPr) * (dlnk0 - dlninf) + kLn10 * dlF_dlFc * dlFc_dT;
+            dkfdM = k0 * F * iPr1 * (iPr1 + dlF_dlPr);
+        }
+        return kf;
+    }
+
+    __device__ __forceinline__ static double third_body(const MechDev &m, int j, double *sh) {
+        const double *ef = m.eff + j * K;
+        double Mc = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) Mc = fma(ef[k], at(sh, kC + 1 + k), Mc);
+        return Mc;
+    }
+
+    // f(y)
+    __device__ __forceinline__ static void rhs(const MechDev &m, double p, const double (&y)[N], double *sh,
+                                               double (&f)[N]) {
+        Mix s;
+        double cpR[N], hRT[N];
+        state(m, p, y, sh, s, cpR, hRT);
+        double wd[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) wd[k] = 0.0;
+        for (int j = 0; j < m.M; ++j) {
+            const int *ri = m.rx + j * kRxInt;
+            const double *rd = m.rk + j * kRxDbl;
+            const int type = ri[0];
+            const int r0 = ri[1], r1 = ri[2], r2 = ri[3], p0 = ri[4], p1 = ri[5], p2 = ri[6], dnu = ri[7];
+            const double Mc = (type != 0) ? third_body(m, j, sh) : 0.0;
+            double dl, dm;
+            const double kf = kforward<false>(rd, type, s, Mc, dl, dm);
+            const double iKc = at(sh, kE + r0) * at(sh, kE + r1) * at(sh, kE + r2) * at(sh, kIE + p0) *
+                               at(sh, kIE + p1) * at(sh, kIE + p2) * cref_pow(s, dnu);
+            const double fwd = kf * (at(sh, kC + r0) * at(sh, kC + r1) * at(sh, kC + r2));
+            const double rev = kf * iKc * (at(sh, kC + p0) * at(sh, kC + p1) * at(sh, kC + p2));
+            double q = fwd - rev;
+            if (type == 1) q *= Mc;
+            const int *nuj = m.nu + j * K;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int nk = nuj[k];
+                if (nk != 0) wd[1 + k] = fma(double(nk), q, wd[1 + k]);
+            }
+        }
+        const double fy = 1e6 / s.rho;
+        double hsum = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            f[1 + k] = fy * m.sp[k * kSpTab] * wd[1 + k];
+            hsum = fma(hRT[1 + k], wd[1 + k], hsum);
+        }
+        f[0] = -hsum * (1e6 * kR) * s.T / (s.rho * s.cp);
+    }
+
+    // Analytic Jacobian J = df/dy and f(y).  Reaction derivatives are taken in
+    // concentration space (A_kl = sum_j nu_kj dq_j/dc_l, s_k = sum_j nu_kj sum_m c_m dq_j/dc_m,
+    // dT_k = sum_j nu_kj dq_j/dT at fixed c), then mapped to (T, Y) with
+    //   dc_m/dY_l = 1e-6 rho delta_ml / W_m - c_m Wbar / W_l,   dc_m/dT = -c_m / T.
+    // A is accumulated in the species block of J (row/column 1 + k) by rows with
+    // compile-time indices and wave-uniform stoichiometric coefficients, so J stays in
+    // registers; the T row and column are filled afterwards.
+    __device__ __forceinline__ static void jacobian(const MechDev &m, double p, const double (&y)[N], double *sh,
+                                                    double (&J)[N][N], double (&f)[N]) {
+        Mix s;
+        double cpR[N], hRT[N];
+        state(m, p, y, sh, s, cpR, hRT);
+#pragma unroll
+        for (int k = 0; k < N; ++k) at(sh, kH + k) = hRT[k];  // u0 is dead while J is formed
+        double wd[N], sq[N], dt[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            wd[k] = sq[k] = dt[k] = 0.0;
+#pragma unroll
+            for (int l = 0; l < N; ++l) J[k][l] = 0.0;
+        }
+        for (int j = 0; j < m.M; ++j) {
+            const int *ri = m.rx + j * kRxInt;
+            const double *rd = m.rk + j * kRxDbl;
+            const int type = ri[0];
+            const int r0 = ri[1], r1 = ri[2], r2 = ri[3], p0 = ri[4], p1 = ri[5], p2 = ri[6], dnu = ri[7];
+            const double nr = rd[10], np = rd[11];
+            const double Mc = (type != 0) ? third_body(m, j, sh) : 0.0;
+            double dlnkf, dkfdM;
+            const double kf = kforward<true>(rd, type, s, Mc, dlnkf, dkfdM);
+            const double iKc = at(sh, kE + r0) * at(sh, kE + r1) * at(sh, kE + r2) * at(sh, kIE + p0) *
+                               at(sh, kIE + p1) * at(sh, kIE + p2) * cref_pow(s, dnu);
+            const double kr = kf * iKc;
+            const double c0 = at(sh, kC + r0), c1 = at(sh, kC + r1), c2 = at(sh, kC + r2);
+            const double d0 = at(sh, kC + p0), d1 = at(sh, kC + p1), d2 = at(sh, kC + p2);
+            const double Pf = c0 * c1 * c2, Pb = d0 * d1 * d2;
+            const double fwd = kf * Pf, rev = kr * Pb, X = fwd - rev;
+            const double dlnKc = (at(sh, kH + p0) + at(sh, kH + p1) + at(sh, kH + p2) - at(sh, kH + r0) -
+                                  at(sh, kH + r1) - at(sh, kH + r2) - dnu) *
+                                 s.iT;
+            const double dXdT = fwd * dlnkf - rev * (dlnkf - dlnKc);
+            const double Mq = (type == 1) ? Mc : 1.0;
+            const double q = Mq * X;
+            const double dqdT = Mq * dXdT;
+            double S = Mq * (nr * fwd - np * rev);
+            double G = 0.0;  // coefficient of the dense third-body term eff_l * G
+            if (type == 1) {
+                G = X;
+                S += Mc * X;
+            } else if (type == 2) {
+                G = dkfdM * (Pf - Pb * iKc);
+                S += G * Mc;
+            }
+            // dq/dc: the slot terms (each slot's derivative is the product of the other slots)
+            // are scattered into LDS, the dense third-body term is added on the way out;
+            // slot 0 collects the empty slots
+            const double *ef = m.eff + j * K;
+#pragma unroll
+            for (int l = 0; l < N; ++l) at(sh, kDQ + l) = 0.0;
+            at(sh, kDQ + r0) += Mq * kf * c1 * c2;
+            at(sh, kDQ + r1) += Mq * kf * c0 * c2;
+            at(sh, kDQ + r2) += Mq * kf * c0 * c1;
+            at(sh, kDQ + p0) -= Mq * kr * d1 * d2;
+            at(sh, kDQ + p1) -= Mq * kr * d0 * d2;
+            at(sh, kDQ + p2) -= Mq * kr * d0 * d1;
+            double dq[K];
+#pragma unroll
+            for (int l = 0; l < K; ++l) dq[l] = (type != 0) ? fma(G, ef[l], at(sh, kDQ + 1 + l)) : at(sh, kDQ + 1 + l);
+            const int *nuj = m.nu + j * K;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int nk = nuj[k];
+                if (nk == 0) continue;  // wave-uniform branch
+                const double sg = double(nk);
+#pragma unroll
+                for (int l = 0; l < K; ++l) J[1 + k][1 + l] = fma(sg, dq[l], J[1 + k][1 + l]);
+                sq[1 + k] = fma(sg, S, sq[1 + k]);
+                dt[1 + k] = fma(sg, dqdT, dt[1 + k]);
+                wd[1 + k] = fma(sg, q, wd[1 + k]);
+            }
+        }
+        // species rows
+        double hm[N], cpm[N];
+        const double fy = 1e6 / s.rho;
+        double dcpdT = 0.0, hf = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const double *r = m.sp + k * kSpTab;
+            const double Wk = r[0];
+            const int row = 1 + k;
+            const double coef = fy * Wk;
+            const double gk = coef * s.Wbar * (wd[row] - sq[row]);
+            J[row][0] = coef * (dt[row] + (wd[row] - sq[row]) * s.iT);
+#pragma unroll
+            for (int l = 0; l < K; ++l) {
+                const double iWl = m.sp[l * kSpTab + 1];
+                J[row][1 + l] = (Wk * J[row][1 + l] + gk) * iWl;
+            }
+            f[row] = coef * wd[row];
+            hm[row] = hRT[row] * kR * s.T * r[1];  // J/kg
+            cpm[row] = cpR[row] * kR * r[1];              // J/kg/K
+            dcpdT += y[row] * (r[3] + s.T * (r[16] + s.T * (r[17] + s.T * r[18]))) * kR * r[1];
+            hf += hm[row] * f[row];
+        }
+        const double icp = 1.0 / s.cp;
+        f[0] = -hf * icp;
+        // temperature row: f_T = -sum_k h_k f_k / cp
+#pragma unroll
+        for (int l = 0; l < N; ++l) {
+            double acc = 0.0;
+#pragma unroll
+            for (int k = 1; k < N; ++k) acc += hm[k] * J[k][l];
+            const double dcp = (l == 0) ? dcpdT : cpm[l];
+            if (l == 0) {
+#pragma unroll
+                for (int k = 1; k < N; ++k) acc += cpm[k] * f[k];
+            }
+            J[0][l] = -(acc + f[0] * dcp) * icp;
+        }
+    }
+
+    // In-place LU with partial pivoting (largest magnitude, ties to the lowest row);
+    // row exchanges are done with selects so the matrix stays in registers.  The
+    // diagonal holds 1/U_kk on return.
+    __device__ __forceinline__ static void lu(double (&A)[N][N], int (&piv)[N]) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            int pk = k;
+            if (k < N - 1) {
+                double best = fabs(A[k][k]);
+#pragma unroll
+                for (int r = k + 1; r < N; ++r) {
+                    const double v = fabs(A[r][k]);
+                    const bool gt = v > best;
+                    best = gt ? v : best;
+                    pk = gt ? r : pk;
+                }
+#pragma unroll
+                for (int r = k + 1; r < N; ++r) {
+                    const bool sw = (pk == r);
+#pragma unroll
+                    for (int c = 0; c < N; ++c) {
+                        const double a = A[k][c], b = A[r][c];
+                        A[k][c] = sw ? b : a;
+                        A[r][c] = sw ? a : b;
+                    }
+                }
+            }
+            piv[k] = pk;
+            const double inv = 1.0 / A[k][k];
+            A[k][k] = inv;
+#pragma unroll
+            for (int r = k + 1; r < N; ++r) {
+                const double l = A[r][k] * inv;
+                A[r][k] = l;
+#pragma unroll
+                for (int c = k + 1; c < N; ++c) A[r][c] = fma(-l, A[k][c], A[r][c]);
+            }
+        }
+    }
+
+    __device__ __forceinline__ static void solve(const double (&A)[N][N], const int (&piv)[N], double (&b)[N]) {
+#pragma unroll
+        for (int k = 0; k < N - 1; ++k) {
+#pragma unroll
+            for (int r = k + 1; r < N; ++r) {
+                const bool sw = (piv[k] == r);
+                const double a = b[k], c = b[r];
+                b[k] = sw ? c : a;
+                b[r] = sw ? a : c;
+            }
+        }
+#pragma unroll
+        for (int i = 1; i < N; ++i)
+#pragma unroll
+            for (int j = 0; j < i; ++j) b[i] = fma(-A[i][j], b[j], b[i]);
+#pragma unroll
+        for (int i = N - 1; i >= 0; --i) {
+#pragma unroll
+            for (int j = i + 1; j < N; ++j) b[i] = fma(-A[i][j], b[j], b[i]);
+            b[i] *= A[i][i];
+        }
+    }
+};
+
+template <int K>
+__global__ __launch_bounds__(kWave) void chem_step_kernel(MechDev m, int64_t n, int64_t ld, double dt,
+                                                       const double *__restrict__ pres, double *__restrict__ Tio,
+                                                       double *__restrict__ Yio, double *__restrict__ h_io,
+                                                       double *__restrict__ rr, int32_t *__restrict__ status,
+                                                       int32_t *__restrict__ nsteps, Opts o,
+                                                       const int32_t *__restrict__ cidx,
+                                                       const int32_t *__restrict__ dcount, int32_t status_ok) {
+    using C = Cell<K>;
+    constexpr int N = C::N;
+    __shared__ double lds[C::kRows * kWave];
+    double *sh = lds + threadIdx.x;
+    C::init_lds(sh);
+    const int64_t lane = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t limit = dcount ? int64_t(*dcount) : n;
+    if (lane >= limit) return;
+    const int64_t i = cidx ? int64_t(cidx[lane]) : lane;
+
+    double y[N];
+    const double p = pres[i];
+    y[0] = Tio[i];
+#pragma unroll
+    for (int k = 0; k < K; ++k) y[1 + k] = Yio[k * ld + i];
+    bool finite = isfinite(p) && p > 0.0 && isfinite(y[0]) && y[0] > 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) finite = finite && isfinite(y[1 + k]);
+    if (!finite) {
+        if (status) status[i] = DF_CELL_NONFINITE;
+        if (nsteps) {
+            nsteps[i] = 0;
+            nsteps[n + i] = 0;
+        }
+        if (rr)
+            for (int k = 0; k < K; ++k) rr[k * ld + i] = 0.0;
+        return;
+    }
+    double atol[N];
+    atol[0] = o.atol_T;
+#pragma unroll
+    for (int k = 1; k < N; ++k) atol[k] = o.atol_Y;
+
+    // initial sub-step
+    double h;
+    double f0[N];
+    const double h_in = h_io ? h_io[i] : 0.0;
+    if (h_in > 0.0) {
+        h = fmin(h_in, dt);
+    } else {
+        C::rhs(m, p, y, sh, f0);
+        double ny = 0.0, nf = 0.0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            const double sc = atol[k] + o.rtol * fabs(y[k]);
+            ny += (y[k] / sc) * (y[k] / sc);
+            nf += (f0[k] / sc) * (f0[k] / sc);
+        }
+        ny = sqrt(ny / N);
+        nf = sqrt(nf / N);
+        h = (nf > 0.0) ? fmin(0.01 * ny / nf, dt) : dt;
+    }
+    if (!(h >= o.h_min)) h = o.h_min;
+
+    double t = 0.0, h_final = 0.0;
+    int acc = 0, rej = 0, st = DF_CELL_OK;
+    bool prev_rej = false;
+    for (;;) {
+        if (acc + rej >= o.max_steps) {
+            st = DF_CELL_MAX_STEPS;
+            break;
+        }
+        const bool last = (t + h >= dt);
+        const double ht = last ? dt - t : h;
+        double W[N][N];
+        int piv[N];
+        C::jacobian(m, p, y, sh, W, f0);
+        const double ig = 1.0 / (Rodas4::g * ht);
+#pragma unroll
+        for (int a = 0; a < N; ++a)
+#pragma unroll
+            for (int b = 0; b < N; ++b) W[a][b] = (a == b ? ig : 0.0) - W[a][b];
+        C::lu(W, piv);
+
+        // stages; u0..u3 are kept in LDS, u4 and u5 in registers
+        double u4[N], u5[N], ys[N];
+        const double ih = 1.0 / ht;
+#pragma unroll
+        for (int sidx = 0; sidx < 6; ++sidx) {
+            double v[N];
+            if (sidx == 0) {
+#pragma unroll
+                for (int k = 0; k < N; ++k) v[k] = f0[k];
+            } else {
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    double w = y[k];
+#pragma unroll
+                    for (int jj = 0; jj < sidx; ++jj) {
+                        const double uj = (jj < C::kULds) ? C::at(sh, C::kU + jj * N + k) : u4[k];
+                        w = fma(Rodas4::a[sidx][jj], uj, w);
+                    }
+                    ys[k] = w;
+                }
+                C::rhs(m, p, ys, sh, v);
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    double w = 0.0;
+#pragma unroll
+                    for (int jj = 0; jj < sidx; ++jj) {
+                        const double uj = (jj < C::kULds) ? C::at(sh, C::kU + jj * N + k) : u4[k];
+                        w = fma(Rodas4::c[sidx][jj], uj, w);
+                    }
+                    v[k] = fma(w, ih, v[k]);
+                }
+            }
+            C::solve(W, piv, v);
+            if (sidx < C::kULds) {
+#pragma unroll
+                for (int k = 0; k < N; ++k) C::at(sh, C::kU + sidx * N + k) = v[k];
+            } else if (sidx == 4) {
+#pragma unroll
+                for (int k = 0; k < N; ++k) u4[k] = v[k];
+            } else {
+#pragma unroll
+                for (int k = 0; k < N; ++k) u5[k] = v[k];
+            }
+        }
+        // y_new = (stage-6 state) + u5 ; error = u5
+        double err = 0.0;
+        double yn[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            yn[k] = ys[k] + u5[k];
+            const double sc = atol[k] + o.rtol * fmax(fabs(y[k]), fabs(yn[k]));
+            const double r = u5[k] / sc;
+            err += r * r;
+        }
+        err = sqrt(err / N);
+
+        const double fmx = prev_rej ? 1.0 : 6.0;
+        double fac;
+        if (!isfinite(err))
+            fac = 0.2;
+        else if (err == 0.0)
+            fac = fmx;
+        else
+            fac = fmin(fmx, fmax(0.2, 0.9 * pow(err, -0.25)));
+
+        if (isfinite(err) && err <= 1.0) {
+            ++acc;
+#pragma unroll
+            for (int k = 0; k < N; ++k) y[k] = yn[k];
+            h_final = h;
+            prev_rej = false;
+            if (last) break;
+            t += ht;
+            h = ht * fac;
+        } else {
+            ++rej;
+            prev_rej = true;
+            h = ht * fac;
+            if (h < o.h_min) {
+                st = DF_CELL_H_UNDERFLOW;
+                break;
+            }
+        }
+    }
+
+    if (rr) {
+        // rr = rho0 (Y - Y0) / dt with rho0 the density of the input state, which is
+        // still in memory: read it back instead of keeping it live through the loop
+        const double T0 = Tio[i];
+        double Y0[K], sYW = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            Y0[k] = Yio[k * ld + i];
+            sYW += Y0[k] * m.sp[k * kSpTab + 1];
+        }
+        const double rdt = p / (sYW * kR * T0) / dt;
+#pragma unroll
+        for (int k = 0; k < K; ++k) rr[k * ld + i] = rdt * (y[1 + k] - Y0[k]);
+    }
+    Tio[i] = y[0];
+#pragma unroll
+    for (int k = 0; k < K; ++k) Yio[k * ld + i] = y[1 + k];
+    if (h_io) h_io[i] = (st == DF_CELL_OK) ? h_final : h;
+    if (status) status[i] = (st == DF_CELL_OK) ? status_ok : st;
+    if (nsteps) {
+        nsteps[i] = acc;
+        nsteps[n + i] = rej;
+    }
+}
+
+}  // namespace
+}  // namespace df
+
+namespace df {
+
+template <int K>
+static df_status launch_k(const MechDev &m, int64_t n, int64_t ld, double dt, const double *p, double *T, double *Y,
+                          double *h_inout, double *rr, int32_t *status, int32_t *n_steps, const Opts &o,
+                          const int32_t *cidx, const int32_t *dcount, int32_t status_ok, hipStream_t stream) {
+    const int64_t blocks = (n + 63) / 64;
+    hipLaunchKernelGGL(chem_step_kernel<K>, dim3(unsigned(blocks)), dim3(64), 0, stream, m, n, ld, dt, p, T, Y,
+                       h_inout, rr, status, n_steps, o, cidx, dcount, status_ok);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(DF_E_HIP, std::string("chem_step launch: ") + hipGetErrorString(e));
+    return DF_OK;
+}
+
+// species counts with a compiled per-lane kernel
+#define DF_CHEM_SPECIES_LIST(X) X(2) X(4) X(9)
+
+df_status launch_chem_step(const MechDev &m, int64_t n, int64_t ld, double dt, const double *p, double *T, double *Y,
+                           double *h_inout, double *rr, int32_t *status, int32_t *n_steps, const df_chem_opts &opts,
+                           const int32_t *cidx, const int32_t *dcount, int32_t status_ok, hipStream_t stream) {
+    if (n == 0) return DF_OK;
+    if (n > int64_t(64) * 0x7fffffff) return fail(DF_E_UNSUPPORTED, "df_chem_step: too many cells for one launch");
+    const Opts o{opts.rtol, opts.atol_T, opts.atol_Y, opts.h_min, opts.max_steps};
+    switch (m.K) {
+#define DF_CASE(k) \
+    case k:        \
+        return launch_k<k>(m, n, ld, dt, p, T, Y, h_inout, rr, status, n_steps, o, cidx, dcount, status_ok, stream);
+        DF_CHEM_SPECIES_LIST(DF_CASE)
+#undef DF_CASE
+        default:
+            return fail(DF_E_UNSUPPORTED, "df_chem_step: no compiled kernel for " + std::to_string(m.K) + " species");
+    }
+}
+
+}  // namespace df
+
+extern "C" df_status df_chem_step(const df_mech *mech, int64_t n_cells, int64_t ld, double dt, const double *p,
+                                  double *T, double *Y, double *h_inout, double *rr, int32_t *cell_status,
+                                  int32_t *n_steps, const df_chem_opts *opts, void *hip_stream) {
+    using namespace df;
+    clear_error();
+    if (!mech) return fail(DF_E_INVALID, "df_chem_step: null mechanism handle");
+    if (n_cells < 0 || ld < n_cells) return fail(DF_E_INVALID, "df_chem_step: need 0 <= n_cells <= ld");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DF_E_INVALID, "df_chem_step: dt must be finite and > 0");
+    if (n_cells > 0 && (!p || !T || !Y)) return fail(DF_E_INVALID, "df_chem_step: null p, T or Y");
+    df_chem_opts o;
+    df_chem_default_opts(&o);
+    if (opts) o = *opts;
+    df_status st = validate_chem_opts(o);
+    if (st != DF_OK) return st;
+    int prev = 0;
+    if (hipGetDevice(&prev) != hipSuccess) return fail(DF_E_HIP, "df_chem_step: hipGetDevice failed");
+    if (prev != mech->device && hipSetDevice(mech->device) != hipSuccess)
+        return fail(DF_E_HIP, "df_chem_step: cannot select the mechanism's device");
+    st = launch_chem_step(mech->dev, n_cells, ld, dt, p, T, Y, h_inout, rr, cell_status, n_steps, o, nullptr, nullptr,
+                          DF_CELL_OK, static_cast<hipStream_t>(hip_stream));
+    if (prev != mech->device) (void)hipSetDevice(prev);
+    return st;
+}

@@ -1,0 +1,73 @@
+// Internal declarations of the chemistry-step library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "df.h"
+
+namespace df {
+
+constexpr double kR = 8.31446261815324;  // J/mol/K
+constexpr double kPref = 101325.0;       // Pa, standard state of the NASA-7 fits
+constexpr int kSlots = 3;                // molecules per reaction side
+constexpr int kSpTab = 20;               // doubles per species row
+constexpr int kRxInt = 8;                // ints per reaction row
+constexpr int kRxDbl = 12;               // doubles per reaction row
+
+// Species row (doubles): W, 1/W, a1..a7, a2/2, a3/3, a4/4, a5/5, a3/2, a4/3, a5/4, 2a3, 3a4, 4a5, pad.
+// Reaction row (ints): type, r0, r1, r2, p0, p1, p2, dnu.  Slots hold 1 + species index, 0 = empty;
+//   the kernels keep index 0 of every per-species array as a neutral element (concentration 1,
+//   enthalpy 0, dummy accumulator) so that empty slots need no branch.
+// Reaction row (doubles): ln A, b, Ta, ln A0, b0, Ta0, alpha, 1/T***, 1/T*, T**, n_reac, n_prod.
+struct MechDev {
+    int K, M;
+    const double *sp;   // [K][kSpTab]
+    const int *rx;      // [M][kRxInt]
+    const double *rk;   // [M][kRxDbl]
+    const double *eff;  // [M][K]
+    const int *nu;      // [M][K] net stoichiometric coefficients nu'' - nu'
+};
+
+struct HostMech {
+    std::string name;
+    long seed = 0;
+    int E = 0, K = 0, M = 0;
+    std::vector<double> W;        // kg/mol
+    std::vector<int> comp;        // [K][E]
+    std::vector<double> nasa;     // [K][7]
+    std::vector<int> type;        // [M]
+    std::vector<int> nu_r, nu_p;  // [M][K]
+    std::vector<double> arr;      // [M][3]
+    std::vector<double> eff;      // [M][K]
+    std::vector<double> low;      // [M][3]
+    std::vector<double> troe;     // [M][4]
+};
+
+// error reporting (thread-local message)
+df_status fail(df_status code, const std::string &msg);
+void clear_error();
+
+// parse a "dfmech 1" file; returns DF_OK or an error code (message set)
+df_status parse_mech_file(const char *path, HostMech &out);
+
+// integrator launch (df_chem.hip); arrays already validated
+df_status launch_chem_step(const MechDev &m, int64_t n, int64_t ld, double dt, const double *p, double *T, double *Y,
+                           double *h_inout, double *rr, int32_t *status, int32_t *n_steps, const df_chem_opts &o,
+                           const int32_t *cell_index, const int32_t *d_count, int32_t status_ok, hipStream_t stream);
+// cell_index/d_count (both nullable): lane i < *d_count works on cell cell_index[i] (compacted subset);
+// status_ok is the code written for cells that succeed (DF_CELL_OK, or DF_CELL_DNN_FALLBACK).
+
+df_status validate_chem_opts(const df_chem_opts &o);
+
+}  // namespace df
+
+struct df_mech {
+    int device;
+    df::HostMech host;
+    void *dev_blob;   // one device allocation holding all tables
+    df::MechDev dev;  // pointers into dev_blob
+};
