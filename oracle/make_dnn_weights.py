@@ -1,0 +1,164 @@
+"""Train the DNN chemistry integrator on oracle-integrated samples (run once).
+
+Test infrastructure: the labels come from the CPU oracle's integrator only.
+
+1. Seeded 0-D constant-pressure trajectories of H2/air (T0 ~ U(300, 2500) K,
+   phi ~ U(0.3, 3), p = 1 atm) are integrated by the oracle and sampled at
+   log-spaced times up to 5 ms.
+2. Training states are drawn from those trajectories and perturbed in
+   Box-Cox space (z_k += U(-0.3, 0.3) for species present, T += N(0, 20 K)),
+   then renormalised.
+3. Each state is advanced by the oracle over dt = 1 us; the label is the
+   increment of z = BoxCox(Y) with lambda = 0.1 (the paper's DNN maps
+   (T, P, BCT(Y)) to the change of its input over a 1 us step).
+4. An MLP K+2 -> 1600 -> 800 -> 400 -> K with exact-erf GELU is fitted in
+   float32 with plain PyTorch on the CPU (MSE on z-scored outputs, Adam,
+   cosine learning-rate decay) and written as a DFDNN01 file with bf16
+   weights; the training box is the per-feature min/max of the raw inputs.
+
+    python oracle/make_dnn_weights.py --samples 2000000 --epochs 12 \
+        --out paper_2210_07094_amd/data/h2_dnn_1600_800_400.dfdnn
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(HERE))
+
+import oracle  # noqa: E402
+import synth  # noqa: E402
+from synth import dnnfile, fields  # noqa: E402
+
+LAM = 0.1
+DT = 1e-6
+P_ATM = 101325.0
+
+
+def bct(Y):
+    return (np.maximum(Y, 0.0) ** LAM - 1.0) / LAM
+
+
+def bct_inv(z):
+    return np.maximum(1.0 + LAM * z, 0.0) ** (1.0 / LAM)
+
+
+def trajectories(om, mech, n_traj, rng, t_end=5e-3, n_times=40):
+    T0 = rng.uniform(300.0, 2500.0, n_traj)
+    phi = rng.uniform(0.3, 3.0, n_traj)
+    Y = fields.premixed_h2_air(mech, phi)
+    T = T0.copy()
+    p = np.full(n_traj, P_ATM)
+    times = np.concatenate([[0.0], np.logspace(-8, np.log10(t_end), n_times)])
+    h = np.zeros(n_traj)
+    states_T, states_Y = [T.copy()], [Y.copy()]
+    o = oracle.default_opts(rtol=1e-7, atol_Y=1e-14, max_steps=200000)
+    for a, b in zip(times[:-1], times[1:]):
+        r = om.chem_step(T, p, Y, b - a, h_inout=h, opts=o)
+        ok = r["status"] == 0
+        T = np.where(ok, r["T"], T)
+        Y = np.where(ok[None, :], r["Y"], Y)
+        h = r["h"]
+        states_T.append(T.copy())
+        states_Y.append(Y.copy())
+    return np.concatenate(states_T), np.concatenate(states_Y, axis=1)
+
+
+def make_samples(om, mech, n, rng, pool_T, pool_Y, chunk=100000):
+    K = mech.n_species
+    idx = rng.integers(0, pool_T.size, n)
+    T = pool_T[idx] + rng.normal(0.0, 20.0, n)
+    T = np.clip(T, 280.0, 2900.0)
+    z = bct(pool_Y[:, idx])
+    present = z > -9.99
+    z = z + np.where(present, rng.uniform(-0.3, 0.3, z.shape), 0.0)
+    Y = bct_inv(z)
+    Y /= Y.sum(axis=0, keepdims=True)
+    p = np.full(n, P_ATM)
+    T1 = np.empty(n)
+    Y1 = np.empty((K, n))
+    st = np.empty(n, dtype=np.int32)
+    t0 = time.time()
+    for a in range(0, n, chunk):
+        b = min(n, a + chunk)
+        r = om.chem_step(T[a:b], p[a:b], Y[:, a:b], DT)
+        T1[a:b], Y1[:, a:b], st[a:b] = r["T"], r["Y"], r["status"]
+        print(f"  labelled {b}/{n} ({time.time() - t0:.0f} s)", flush=True)
+    ok = st == 0
+    x = np.vstack([T, p, bct(Y)]).T[ok]
+    dz = (bct(Y1) - bct(Y)).T[ok]
+    return x, dz
+
+
+def train(x, y, epochs, seed, batch=4096, lr=1e-3, widths=(1600, 800, 400)):
+    import torch
+    torch.manual_seed(seed)
+    torch.set_num_threads(os.cpu_count() or 8)
+    n_in, n_out = x.shape[1], y.shape[1]
+    mu_in, sig_in = x.mean(0), x.std(0)
+    sig_in[sig_in == 0] = 1.0
+    mu_out, sig_out = y.mean(0), y.std(0)
+    sig_out[sig_out == 0] = 1.0
+    X = torch.tensor((x - mu_in) / sig_in, dtype=torch.float32)
+    Yt = torch.tensor((y - mu_out) / sig_out, dtype=torch.float32)
+    dims = [n_in, *widths, n_out]
+    layers = []
+    for i in range(len(dims) - 1):
+        layers.append(torch.nn.Linear(dims[i], dims[i + 1]))
+        if i < len(dims) - 2:
+            layers.append(torch.nn.GELU())
+    net = torch.nn.Sequential(*layers)
+    opt = torch.optim.Adam(net.parameters(), lr=lr)
+    n = X.shape[0]
+    steps = epochs * ((n + batch - 1) // batch)
+    sched = torch.optim.lr_scheduler.CosineAnnealingLR(opt, steps, eta_min=lr * 0.01)
+    t0 = time.time()
+    for ep in range(epochs):
+        perm = torch.randperm(n)
+        tot = 0.0
+        for a in range(0, n, batch):
+            i = perm[a:a + batch]
+            opt.zero_grad()
+            loss = torch.nn.functional.mse_loss(net(X[i]), Yt[i])
+            loss.backward()
+            opt.step()
+            sched.step()
+            tot += loss.item() * i.numel()
+        print(f"  epoch {ep + 1}/{epochs} mse {tot / n:.4e} ({time.time() - t0:.0f} s)", flush=True)
+    lin = [m for m in net if isinstance(m, torch.nn.Linear)]
+    W = [m.weight.detach().numpy().astype(np.float32) for m in lin]
+    b = [m.bias.detach().numpy().astype(np.float32) for m in lin]
+    return W, b, mu_in, sig_in, mu_out, sig_out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--mech", default=os.path.join(os.path.dirname(HERE), "synth", "data", "h2_synth_9sp_24r.mech"))
+    ap.add_argument("--samples", type=int, default=2_000_000)
+    ap.add_argument("--trajectories", type=int, default=4000)
+    ap.add_argument("--epochs", type=int, default=12)
+    ap.add_argument("--seed", type=int, default=2210)
+    ap.add_argument("--out", default=os.path.join(os.path.dirname(HERE), "paper_2210_07094_amd", "data",
+                                                  "h2_dnn_1600_800_400.dfdnn"))
+    a = ap.parse_args()
+    rng = np.random.default_rng(a.seed)
+    mech = synth.read_mech(a.mech)
+    om = oracle.Mech(a.mech)
+    t0 = time.time()
+    pool_T, pool_Y = trajectories(om, mech, a.trajectories, rng)
+    print(f"trajectory pool: {pool_T.size} states ({time.time() - t0:.0f} s)", flush=True)
+    x, dz = make_samples(om, mech, a.samples, rng, pool_T, pool_Y)
+    print(f"samples: {x.shape[0]} ({time.time() - t0:.0f} s)", flush=True)
+    W, b, mu_in, sig_in, mu_out, sig_out = train(x, dz, a.epochs, a.seed)
+    os.makedirs(os.path.dirname(a.out), exist_ok=True)
+    dnnfile.write_dnn(a.out, W, b, mech.n_species, LAM, DT, mu_in, sig_in, mu_out, sig_out, x.min(0), x.max(0))
+    print(f"wrote {a.out} ({time.time() - t0:.0f} s)", flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,450 @@
+// DNN form of the chemistry step (the paper's DNNInferencer::inference in three
+// stages, Sec. "Description of the new classes"; network structure from Sec.
+// "Chemistry Integration"):
+//   1. pre   : x = (T, p, BoxCox(Y)), training-range test, z-score, bf16
+//   2. layers: hidden layers as bf16 MFMA GEMMs with GELU (df_mlp.hip), output
+//              layer in fp32 inside the post kernel
+//   3. post  : inverse normalisation and Box-Cox, optional renormalisation of Y,
+//              T from enthalpy conservation at fixed p (FP64 Newton), rr
+// Cells outside the training range are compacted into an index list and
+// advanced by the integrator kernel in the same stream (status DNN_FALLBACK).
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+
+#include "df_internal.h"
+
+namespace df {
+namespace {
+
+constexpr int kPreThreads = 256;
+
+__device__ __forceinline__ bf16_t f2bf(float x) {
+    unsigned u = __float_as_uint(x);
+    if ((u & 0x7f800000u) == 0x7f800000u) return bf16_t((u >> 16) | ((u & 0x007fffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return bf16_t(u >> 16);
+}
+
+__device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float(unsigned(h) << 16); }
+
+__device__ __forceinline__ double boxcox(double Y, double lam) { return (pow(fmax(Y, 0.0), lam) - 1.0) / lam; }
+
+__global__ void zero_counter(int32_t *c) { *c = 0; }
+
+// flags: 1 = network, 0 = fallback (out of training range), 2 = non-finite input
+template <int K>
+__global__ __launch_bounds__(kPreThreads) void pre_kernel(DnnDevParams prm, int64_t n, int64_t n_pad, int64_t ld,
+                                                          const double *__restrict__ p, const double *__restrict__ T,
+                                                          const double *__restrict__ Y, bf16_t *__restrict__ xb,
+                                                          int in_pad, int8_t *__restrict__ flag,
+                                                          int32_t *__restrict__ idx, int32_t *__restrict__ count,
+                                                          int32_t *__restrict__ status, double *__restrict__ rr,
+                                                          int fallback) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n_pad) return;
+    bf16_t *row = xb + i * in_pad;
+    if (i >= n) {
+        for (int c = 0; c < in_pad; ++c) row[c] = 0;
+        return;
+    }
+    constexpr int NI = K + 2;
+    double x[NI];
+    x[0] = T[i];
+    x[1] = p[i];
+    bool finite = isfinite(x[0]) && x[0] > 0.0 && isfinite(x[1]) && x[1] > 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double y = Y[k * ld + i];
+        finite = finite && isfinite(y);
+        x[2 + k] = boxcox(y, prm.lambda);
+    }
+    int f = 1;
+    if (!finite) {
+        f = 2;
+    } else {
+#pragma unroll
+        for (int c = 0; c < NI; ++c)
+            if (!(x[c] >= prm.lo[c] && x[c] <= prm.hi[c])) f = 0;
+    }
+    flag[i] = int8_t(f);
+#pragma unroll
+    for (int c = 0; c < NI; ++c) {
+        const double xn = (x[c] - prm.mu_in[c]) / prm.sig_in[c];
+        row[c] = (f == 1) ? f2bf(float(xn)) : bf16_t(0);
+    }
+    for (int c = NI; c < in_pad; ++c) row[c] = 0;
+    if (f == 0 && fallback) {
+        idx[atomicAdd(count, 1)] = int32_t(i);
+    } else if (f != 1) {
+        // non-finite input, or out of range with the fallback switched off: state left as is
+        if (status) status[i] = (f == 2) ? DF_CELL_NONFINITE : DF_CELL_DNN_FALLBACK;
+        if (rr)
+            for (int k = 0; k < K; ++k) rr[k * ld + i] = 0.0;
+    }
+}
+
+// output layer (fp32, bf16 weights) + stage 3
+template <int K>
+__global__ __launch_bounds__(kPreThreads) void post_kernel(DnnDevParams prm, MechDev m, int64_t n, int64_t ld,
+                                                           double dt, const bf16_t *__restrict__ h, int h_ld,
+                                                           const bf16_t *__restrict__ W, const float *__restrict__ b,
+                                                           int k_in, const int8_t *__restrict__ flag,
+                                                           const double *__restrict__ p, double *__restrict__ T,
+                                                           double *__restrict__ Y, double *__restrict__ rr,
+                                                           int32_t *__restrict__ status, int renormalise) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n || flag[i] != 1) return;
+    // ---- output layer: u = W h + b, fp32 accumulation
+    float u[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) u[k] = 0.0f;
+    const bf16_t *hr = h + i * int64_t(h_ld);
+    for (int j = 0; j < k_in; j += 8) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(hr + j);
+        const unsigned w4[4] = {v.x, v.y, v.z, v.w};
+        float a[8];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            a[2 * q] = __uint_as_float(w4[q] << 16);
+            a[2 * q + 1] = __uint_as_float(w4[q] & 0xffff0000u);
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const bf16_t *wr = W + int64_t(k) * k_in + j;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) u[k] = fmaf(bf2f(wr[q]), a[q], u[k]);
+        }
+    }
+    // ---- stage 3, FP64
+    const double T0 = T[i];
+    double Y0[K], Yn[K];
+    double sYW = 0.0, h0 = 0.0, sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        Y0[k] = Y[k * ld + i];
+        const double *r = m.sp + k * kSpTab;
+        sYW += Y0[k] * r[1];
+        const double hRT = r[2] + T0 * (r[9] + T0 * (r[10] + T0 * (r[11] + T0 * r[12]))) + r[7] / T0;
+        h0 += Y0[k] * hRT * r[1];
+        const double z1 = boxcox(Y0[k], prm.lambda) + (double(u[k] + b[k]) * prm.sig_out[k] + prm.mu_out[k]);
+        Yn[k] = pow(fmax(1.0 + prm.lambda * z1, 0.0), prm.inv_lambda);
+        sum += Yn[k];
+    }
+    h0 *= kR * T0;
+    if (renormalise && sum > 0.0) {
+        const double is = 1.0 / sum;
+#pragma unroll
+        for (int k = 0; k < K; ++k) Yn[k] *= is;
+    }
+    // T from h(T, Yn) = h0: Newton with dh/dT = cp
+    double Tn = T0;
+    bool conv = false;
+    for (int it = 0; it < 20; ++it) {
+        double hm = 0.0, cp = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const double *r = m.sp + k * kSpTab;
+            const double cpR = r[2] + Tn * (r[3] + Tn * (r[4] + Tn * (r[5] + Tn * r[6])));
+            const double hRT = r[2] + Tn * (r[9] + Tn * (r[10] + Tn * (r[11] + Tn * r[12]))) + r[7] / Tn;
+            hm += Yn[k] * hRT * r[1];
+            cp += Yn[k] * cpR * r[1];
+        }
+        const double dT = (hm * Tn - h0 / kR) / cp;
+        Tn -= dT;
+        if (!isfinite(Tn)) break;
+        if (fabs(dT) <= 1e-9) {
+            conv = true;
+            break;
+        }
+    }
+    if (rr) {
+        const double rdt = p[i] / (sYW * kR * T0) / dt;
+#pragma unroll
+        for (int k = 0; k < K; ++k) rr[k * ld + i] = rdt * (Yn[k] - Y0[k]);
+    }
+    T[i] = Tn;
+#pragma unroll
+    for (int k = 0; k < K; ++k) Y[k * ld + i] = Yn[k];
+    if (status) status[i] = conv ? DF_CELL_OK : DF_CELL_NONFINITE;
+}
+
+int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+struct WsLayout {
+    int64_t n_pad;
+    size_t o_x, o_a, o_b, o_flag, o_idx, o_cnt, total;
+    int wa, wb;  // widths of the two activation buffers
+};
+
+WsLayout workspace_layout(const df_dnn *d, int64_t n) {
+    WsLayout w{};
+    w.n_pad = round_up(std::max<int64_t>(n, 1), kGemmBM);
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    const int nh = int(d->layers.size()) - 1;
+    w.wa = w.wb = 0;
+    for (int l = 0; l < nh; ++l) {
+        if (l % 2 == 0)
+            w.wa = std::max(w.wa, d->layers[l].n_pad);
+        else
+            w.wb = std::max(w.wb, d->layers[l].n_pad);
+    }
+    size_t o = 0;
+    w.o_x = o;
+    o = al(o + size_t(w.n_pad) * d->layers[0].k_pad * 2);
+    w.o_a = o;
+    o = al(o + size_t(w.n_pad) * w.wa * 2);
+    w.o_b = o;
+    o = al(o + size_t(w.n_pad) * w.wb * 2);
+    w.o_flag = o;
+    o = al(o + size_t(w.n_pad));
+    w.o_idx = o;
+    o = al(o + size_t(w.n_pad) * 4);
+    w.o_cnt = o;
+    o = al(o + 4);
+    w.total = o;
+    return w;
+}
+
+template <int K>
+df_status launch_dnn_k(const df_dnn *d, const df_mech *m, int64_t n, int64_t ld, double dt, const double *p,
+                       double *T, double *Y, double *rr, int32_t *status, void *ws, const df_dnn_opts &o,
+                       const df_chem_opts &fo, hipStream_t s) {
+    const WsLayout w = workspace_layout(d, n);
+    auto *base = static_cast<unsigned char *>(ws);
+    auto *xb = reinterpret_cast<bf16_t *>(base + w.o_x);
+    auto *ba = reinterpret_cast<bf16_t *>(base + w.o_a);
+    auto *bb = reinterpret_cast<bf16_t *>(base + w.o_b);
+    auto *flag = reinterpret_cast<int8_t *>(base + w.o_flag);
+    auto *idx = reinterpret_cast<int32_t *>(base + w.o_idx);
+    auto *cnt = reinterpret_cast<int32_t *>(base + w.o_cnt);
+    hipLaunchKernelGGL(zero_counter, dim3(1), dim3(1), 0, s, cnt);
+    const int in_pad = d->layers[0].k_pad;
+    hipLaunchKernelGGL(pre_kernel<K>, dim3(unsigned((w.n_pad + kPreThreads - 1) / kPreThreads)), dim3(kPreThreads), 0,
+                       s, d->prm, n, w.n_pad, ld, p, T, Y, xb, in_pad, flag, idx, cnt, status, rr, o.fallback);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(DF_E_HIP, std::string("dnn pre launch: ") + hipGetErrorString(e));
+    // hidden layers
+    const bf16_t *in = xb;
+    int in_ld = in_pad;
+    const int nh = int(d->layers.size()) - 1;
+    for (int l = 0; l < nh; ++l) {
+        const DnnLayer &L = d->layers[l];
+        bf16_t *out = (l % 2 == 0) ? ba : bb;
+        const int out_ld = (l % 2 == 0) ? w.wa : w.wb;
+        df_status st = launch_gemm_bf16(in, in_ld, L.W, L.k_pad, L.b, out, out_ld, w.n_pad, L.n_pad, L.k_pad, true, s);
+        if (st != DF_OK) return st;
+        in = out;
+        in_ld = out_ld;
+    }
+    const DnnLayer &Lo = d->layers.back();
+    hipLaunchKernelGGL(post_kernel<K>, dim3(unsigned((n + kPreThreads - 1) / kPreThreads)), dim3(kPreThreads), 0, s,
+                       d->prm, m->dev, n, ld, dt, in, in_ld, Lo.W, Lo.b, Lo.k_pad, flag, p, T, Y, rr, status,
+                       o.renormalise);
+    e = hipGetLastError();
+    if (e != hipSuccess) return fail(DF_E_HIP, std::string("dnn post launch: ") + hipGetErrorString(e));
+    if (o.fallback)
+        return launch_chem_step(m->dev, n, ld, dt, p, T, Y, nullptr, rr, status, nullptr, fo, idx, cnt,
+                                DF_CELL_DNN_FALLBACK, s);
+    return DF_OK;
+}
+
+template <class T>
+bool rd(std::ifstream &f, T *v, size_t n) {
+    f.read(reinterpret_cast<char *>(v), std::streamsize(sizeof(T) * n));
+    return bool(f);
+}
+
+}  // namespace
+}  // namespace df
+
+using namespace df;
+
+extern "C" {
+
+df_status df_dnn_load(const char *path, const df_mech *mech, int32_t device, df_dnn **out) {
+    clear_error();
+    if (!path || !mech || !out) return fail(DF_E_INVALID, "df_dnn_load: null path, mechanism or out");
+    *out = nullptr;
+    std::ifstream f(path, std::ios::binary);
+    if (!f) return fail(DF_E_IO, std::string("cannot open DNN file ") + path);
+    char magic[8];
+    int32_t L = 0, K = 0, reserved = 0;
+    if (!rd(f, magic, 8) || std::memcmp(magic, "DFDNN01", 7) != 0 || !rd(f, &L, 1) || L < 2 || L > 15)
+        return fail(DF_E_FORMAT, std::string(path) + ": not a DFDNN01 file with 2..15 layers");
+    std::vector<int32_t> dims(L + 1);
+    double lam = 0, dtt = 0;
+    if (!rd(f, dims.data(), dims.size()) || !rd(f, &K, 1) || !rd(f, &reserved, 1) || !rd(f, &lam, 1) ||
+        !rd(f, &dtt, 1))
+        return fail(DF_E_FORMAT, std::string(path) + ": truncated header");
+    if (K != mech->host.K || dims[0] != K + 2 || dims[L] != K)
+        return fail(DF_E_INVALID, "df_dnn_load: network widths do not match the mechanism's species count");
+    for (int l = 0; l <= L; ++l)
+        if (dims[l] < 1 || dims[l] > 65536) return fail(DF_E_FORMAT, "df_dnn_load: bad layer width");
+    if (!(lam > 0) || !(dtt > 0)) return fail(DF_E_FORMAT, "df_dnn_load: lambda and dt_train must be > 0");
+    const int ni = K + 2;
+    std::vector<double> prm_h(size_t(6) * ni, 0.0);  // mu_in, sig_in, mu_out, sig_out, lo, hi
+    for (int a = 0; a < 6; ++a) {
+        const int cnt = (a == 2 || a == 3) ? K : ni;
+        if (!rd(f, &prm_h[size_t(a) * ni], cnt)) return fail(DF_E_FORMAT, "df_dnn_load: truncated parameters");
+    }
+    for (int c = 0; c < ni; ++c)
+        if (!(prm_h[size_t(ni) + c] > 0)) return fail(DF_E_FORMAT, "df_dnn_load: sig_in must be > 0");
+    auto *d = new df_dnn;
+    d->device = device;
+    d->K = K;
+    d->L = L;
+    d->dims.assign(dims.begin(), dims.end());
+    d->lambda = lam;
+    d->dt_train = dtt;
+    // padded device layout
+    std::vector<std::vector<bf16_t>> Wh(L);
+    std::vector<std::vector<float>> bh(L);
+    int prev_pad = int(round_up(dims[0], kGemmBK));
+    d->layers.resize(L);
+    for (int l = 0; l < L; ++l) {
+        DnnLayer &Ly = d->layers[l];
+        Ly.n_in = dims[l];
+        Ly.n_out = dims[l + 1];
+        Ly.k_pad = prev_pad;
+        Ly.n_pad = (l < L - 1) ? int(round_up(dims[l + 1], kGemmBN)) : dims[l + 1];
+        std::vector<bf16_t> w(size_t(Ly.n_out) * Ly.n_in);
+        std::vector<float> b(Ly.n_out);
+        if (!rd(f, w.data(), w.size()) || !rd(f, b.data(), b.size())) {
+            delete d;
+            return fail(DF_E_FORMAT, std::string(path) + ": truncated weights");
+        }
+        Wh[l].assign(size_t(Ly.n_pad) * Ly.k_pad, 0);
+        bh[l].assign(Ly.n_pad, 0.0f);
+        for (int o = 0; o < Ly.n_out; ++o) {
+            std::memcpy(&Wh[l][size_t(o) * Ly.k_pad], &w[size_t(o) * Ly.n_in], sizeof(bf16_t) * Ly.n_in);
+            bh[l][o] = b[o];
+        }
+        prev_pad = Ly.n_pad;
+    }
+    // one device allocation
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    std::vector<size_t> offW(L), offb(L);
+    size_t o = 0;
+    for (int l = 0; l < L; ++l) {
+        offW[l] = o;
+        o = al(o + Wh[l].size() * 2);
+        offb[l] = o;
+        o = al(o + bh[l].size() * 4);
+    }
+    const size_t offP = o;
+    o = al(o + prm_h.size() * 8);
+    int prev = 0;
+    if (hipGetDevice(&prev) != hipSuccess || hipSetDevice(device) != hipSuccess) {
+        delete d;
+        return fail(DF_E_HIP, "df_dnn_load: cannot select device");
+    }
+    void *blob = nullptr;
+    hipError_t e = hipMalloc(&blob, o);
+    if (e == hipSuccess) {
+        std::vector<unsigned char> h(o, 0);
+        for (int l = 0; l < L; ++l) {
+            std::memcpy(h.data() + offW[l], Wh[l].data(), Wh[l].size() * 2);
+            std::memcpy(h.data() + offb[l], bh[l].data(), bh[l].size() * 4);
+        }
+        std::memcpy(h.data() + offP, prm_h.data(), prm_h.size() * 8);
+        e = hipMemcpy(blob, h.data(), o, hipMemcpyHostToDevice);
+    }
+    (void)hipSetDevice(prev);
+    if (e != hipSuccess) {
+        if (blob) (void)hipFree(blob);
+        delete d;
+        return fail(DF_E_HIP, std::string("df_dnn_load: ") + hipGetErrorString(e));
+    }
+    d->dev_blob = blob;
+    auto *base = static_cast<unsigned char *>(blob);
+    for (int l = 0; l < L; ++l) {
+        d->layers[l].W = reinterpret_cast<bf16_t *>(base + offW[l]);
+        d->layers[l].b = reinterpret_cast<float *>(base + offb[l]);
+    }
+    const double *P = reinterpret_cast<const double *>(base + offP);
+    d->prm = DnnDevParams{K, ni, lam, 1.0 / lam, P, P + ni, P + 2 * ni, P + 3 * ni, P + 4 * ni, P + 5 * ni};
+    *out = d;
+    return DF_OK;
+}
+
+void df_dnn_free(df_dnn *d) {
+    if (!d) return;
+    int prev = 0;
+    if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(d->device) == hipSuccess) {
+        (void)hipFree(d->dev_blob);
+        (void)hipSetDevice(prev);
+    }
+    delete d;
+}
+
+df_status df_dnn_info(const df_dnn *d, int32_t *n_layers, int32_t *dims, double *lambda, double *dt_train) {
+    clear_error();
+    if (!d) return fail(DF_E_INVALID, "df_dnn_info: null handle");
+    if (n_layers) *n_layers = d->L;
+    if (dims)
+        for (int l = 0; l <= d->L; ++l) dims[l] = d->dims[l];
+    if (lambda) *lambda = d->lambda;
+    if (dt_train) *dt_train = d->dt_train;
+    return DF_OK;
+}
+
+df_status df_dnn_workspace_size(const df_dnn *d, int64_t n_cells, size_t *bytes) {
+    clear_error();
+    if (!d || !bytes || n_cells < 0) return fail(DF_E_INVALID, "df_dnn_workspace_size: bad arguments");
+    *bytes = workspace_layout(d, n_cells).total;
+    return DF_OK;
+}
+
+#define DF_DNN_SPECIES_LIST(X) X(2) X(4) X(9)
+
+df_status df_dnn_step(const df_dnn *d, const df_mech *m, int64_t n, int64_t ld, double dt, const double *p, double *T,
+                      double *Y, double *rr, int32_t *status, void *ws, size_t ws_bytes, const df_dnn_opts *opts,
+                      const df_chem_opts *fallback_opts, void *hip_stream) {
+    clear_error();
+    if (!d || !m) return fail(DF_E_INVALID, "df_dnn_step: null DNN or mechanism handle");
+    if (d->K != m->host.K || d->device != m->device)
+        return fail(DF_E_INVALID, "df_dnn_step: DNN and mechanism differ in species count or device");
+    if (n < 0 || ld < n) return fail(DF_E_INVALID, "df_dnn_step: need 0 <= n_cells <= ld");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DF_E_INVALID, "df_dnn_step: dt must be finite and > 0");
+    if (std::fabs(dt - d->dt_train) > 1e-12 * d->dt_train)
+        return fail(DF_E_UNSUPPORTED, "df_dnn_step: dt differs from the time step the network was trained for");
+    if (n > 0 && (!p || !T || !Y)) return fail(DF_E_INVALID, "df_dnn_step: null p, T or Y");
+    if (n > 0x7fffffff) return fail(DF_E_UNSUPPORTED, "df_dnn_step: more than 2^31-1 cells");
+    df_dnn_opts o;
+    df_dnn_default_opts(&o);
+    if (opts) o = *opts;
+    if ((o.renormalise != 0 && o.renormalise != 1) || (o.fallback != 0 && o.fallback != 1) || o.reserved0 ||
+        o.reserved1)
+        return fail(DF_E_INVALID, "df_dnn_opts: renormalise and fallback must be 0 or 1, reserved 0");
+    df_chem_opts fo;
+    df_chem_default_opts(&fo);
+    if (fallback_opts) fo = *fallback_opts;
+    df_status st = validate_chem_opts(fo);
+    if (st != DF_OK) return st;
+    if (n == 0) return DF_OK;
+    const size_t need = workspace_layout(d, n).total;
+    if (!ws || ws_bytes < need)
+        return fail(DF_E_INVALID, "df_dnn_step: workspace missing or smaller than df_dnn_workspace_size");
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0) return fail(DF_E_INVALID, "df_dnn_step: workspace not 256-byte aligned");
+    int prev = 0;
+    if (hipGetDevice(&prev) != hipSuccess) return fail(DF_E_HIP, "df_dnn_step: hipGetDevice failed");
+    if (prev != d->device && hipSetDevice(d->device) != hipSuccess)
+        return fail(DF_E_HIP, "df_dnn_step: cannot select the device");
+    auto s = static_cast<hipStream_t>(hip_stream);
+    switch (d->K) {
+#define DF_CASE(k)                                                                \
+    case k:                                                                       \
+        st = launch_dnn_k<k>(d, m, n, ld, dt, p, T, Y, rr, status, ws, o, fo, s); \
+        break;
+        DF_DNN_SPECIES_LIST(DF_CASE)
+#undef DF_CASE
+        default:
+            st = fail(DF_E_UNSUPPORTED, "df_dnn_step: no compiled kernels for " + std::to_string(d->K) + " species");
+    }
+    if (prev != d->device) (void)hipSetDevice(prev);
+    return st;
+}
+
+}  // extern "C"

@@ -71,3 +71,44 @@ struct df_mech {
     void *dev_blob;   // one device allocation holding all tables
     df::MechDev dev;  // pointers into dev_blob
 };
+
+namespace df {
+
+// ---- DNN form ----
+typedef unsigned short bf16_t;  // raw bfloat16 bits
+
+constexpr int kGemmBM = 128;  // cells per GEMM tile
+constexpr int kGemmBN = 160;  // outputs per GEMM tile
+constexpr int kGemmBK = 32;   // reduction depth per stage
+constexpr int kInPad = 32;    // padded width of the network input
+
+struct DnnLayer {
+    int n_in, n_out;    // true widths
+    int k_pad, n_pad;   // padded widths on the device (k_pad = previous n_pad, or kInPad)
+    bf16_t *W;          // [n_pad][k_pad] device, zero padded
+    float *b;           // [n_pad] device, zero padded
+};
+
+struct DnnDevParams {   // kernel argument for the pre/post kernels
+    int K, n_in;
+    double lambda, inv_lambda;
+    const double *mu_in, *sig_in, *mu_out, *sig_out, *lo, *hi;  // device arrays
+};
+
+// C[M][N] = act(A[M][K] B[N][K]^T + bias) in bf16 with fp32 accumulation; M % kGemmBM == 0,
+// N % kGemmBN == 0, K % kGemmBK == 0, row strides in elements.
+df_status launch_gemm_bf16(const bf16_t *A, int lda, const bf16_t *B, int ldb, const float *bias, bf16_t *C, int ldc,
+                           int64_t M, int N, int K, bool gelu, hipStream_t stream);
+
+}  // namespace df
+
+struct df_dnn {
+    int device;
+    int K;
+    int L;
+    std::vector<int> dims;
+    double lambda, dt_train;
+    std::vector<df::DnnLayer> layers;  // hidden layers (MFMA path) and the output layer
+    void *dev_blob;                    // all device memory of the handle
+    df::DnnDevParams prm;
+};
