@@ -1,0 +1,243 @@
+"""Benchmark of the per-cell chemistry step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--no-cpu]
+
+Workload: the 256 x 256 = 65,536-cell hot-kernel field (premixed H2/air at
+phi = 1, 300 K background with eight Gaussian hot kernels up to 1800 K,
+p = 1 atm) with the seeded 9-species / 24-reaction mechanism, dt = 1 us.
+One step is one pass of the whole hot path over the field: the FP64
+RODAS4 integrator (df_chem_step) and the BF16 DNN step with its FP64
+fallback (df_dnn_step), each starting from the same resident input state.
+`value` is cells per second of that step; the per-form rates, the DNN's
+error against the oracle integrator, the roofline of the dominant kernel
+and the oracle timed on the host cores are printed in the same JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+MECH = os.path.join(ROOT, "synth", "data", "h2_synth_9sp_24r.mech")
+DNN_W = os.path.join(ROOT, "paper_2210_07094_amd", "data", "h2_dnn_1600_800_400.dfdnn")
+DT = 1e-6
+
+# MI355X peaks (datasheet): FP64 vector 78.6 TFLOP/s = 256 CU x 4 SIMD x 16 lanes x 2.4 GHz x 2 (FMA);
+# dense BF16 MFMA 2.5 PFLOP/s
+PEAK_FP64_TFLOPS = 78.6
+PEAK_BF16_TFLOPS = 2500.0
+
+# cost of operations without a native FP64 instruction, in FP64 lane-ops (an FMA is one lane-op)
+TRANSCENDENTAL_OPS = 25
+DIVISION_OPS = 10
+
+
+def integrator_lane_ops(mech):
+    """Algorithmic FP64 lane-ops of one RODAS4 attempt (Jacobian, LU, 6 stages, error test).
+
+    Counted from the method's steps for the given mechanism (not from the
+    instructions the compiler emitted): polynomial thermo, rate constants,
+    mass action, third-body sums, Troe falloff, analytic Jacobian in
+    concentration space and its mapping to (T, Y), LU of the N x N iteration
+    matrix, six triangular solves, stage combinations and the error norm.
+    """
+    K, M = mech.n_species, mech.n_reactions
+    N = K + 1
+    T_, D_ = TRANSCENDENTAL_OPS, DIVISION_OPS
+    nu = mech.nu_prod - mech.nu_reac
+    nnz = (nu != 0).sum(axis=1)
+    n_tb = int(np.count_nonzero(mech.reaction_type != 0))
+    n_troe = int(np.count_nonzero(mech.reaction_type == 2))
+    thermo = K * (18 + T_ + D_)                       # cp, h, s polynomials; exp(-G/RT) and its inverse; sums
+    mixture = T_ + 3 * D_ + 4 + 2 * K                  # log T, 1/T, mean molar mass, density, p0/RT, concentrations
+    rates = int(np.sum(41 + nnz)) + n_tb * (K + 1)     # kf, Kc, mass action, q, accumulation; [M]
+    troe = n_troe * (7 * T_ + 4 * D_ + 25)
+    out = 3 * K + 4 + D_
+    rhs = thermo + mixture + rates + troe + out
+    jac_extra = int(np.sum(41 + nnz * (K + 3))) + n_tb * K + n_troe * (32 + D_) + K * (2 * K + 6) + N * (K + 2) + \
+        3 * K + D_
+    jac = rhs + jac_extra
+    lu = sum(j + j * j for j in range(N)) + N * D_
+    solves = 6 * N * N
+    form_w = N * N + D_
+    stages = 15 * N * 2 + 5 * N + N + N * (5 + D_) + 2 * T_
+    total = 5 * rhs + jac + lu + solves + form_w + stages
+    return {"per_attempt": int(total), "rhs": int(rhs), "jacobian": int(jac), "lu": int(lu), "solves": int(solves),
+            "stage_ops": int(stages + form_w)}
+
+
+def mlp_flops(dims):
+    return 2 * sum(a * b for a, b in zip(dims[:-1], dims[1:]))
+
+
+def dnn_error(T0, Y0, Td, Yd, To, Yo, status):
+    """DNN result against the oracle integrator on the same inputs."""
+    dT = np.abs(Td - To)
+    dY = np.abs(Yd - Yo)
+    inc_o = Yo - Y0
+    inc_d = Yd - Y0
+    rel_l2 = []
+    for k in range(Y0.shape[0]):
+        m = np.abs(inc_o[k]) > 1e-8
+        rel_l2.append(float(np.linalg.norm(inc_d[k, m] - inc_o[k, m]) / np.linalg.norm(inc_o[k, m])) if m.any()
+                      else None)
+    return {"max_abs_dT_K": float(dT.max()), "mean_abs_dT_K": float(dT.mean()),
+            "max_abs_dY_per_species": [float(v) for v in dY.max(axis=1)],
+            "rel_l2_dY_increment_per_species": rel_l2,
+            "fallback_frac": float(np.mean(status == 4))}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing (cpu_baseline null)")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported (cells are independent, "
+              "so N GPUs would each run this benchmark on their own shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2210_07094_amd as df
+    import synth
+    from synth import fields
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    dev = "cuda:0"
+    mech_h = synth.read_mech(MECH)
+    f = fields.hot_kernel_field_2d(mech_h)
+    n = f["T"].size
+    K = mech_h.n_species
+    gm = df.Mechanism(MECH)
+    dnn = df.DNN(DNN_W, gm)
+
+    T_in = torch.tensor(f["T"], dtype=torch.float64, device=dev)
+    p = torch.tensor(f["p"], dtype=torch.float64, device=dev)
+    Y_in = torch.tensor(f["Y"], dtype=torch.float64, device=dev)
+    Tc, Yc = T_in.clone(), Y_in.clone()
+    Td, Yd = T_in.clone(), Y_in.clone()
+    st_c = torch.zeros(n, dtype=torch.int32, device=dev)
+    st_d = torch.zeros(n, dtype=torch.int32, device=dev)
+    nsteps = torch.zeros(2 * n, dtype=torch.int32, device=dev)
+    ws = dnn.workspace(n)
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        Tc.copy_(T_in)
+        Yc.copy_(Y_in)
+        Td.copy_(T_in)
+        Yd.copy_(Y_in)
+        if ev:
+            ev[0].record(stream)
+        gm.chem_step(Tc, p, Yc, DT, status=st_c, n_steps=nsteps, stream=stream)
+        if ev:
+            ev[1].record(stream)
+        dnn.step(Td, p, Yd, DT, status=st_d, workspace=ws, stream=stream)
+        if ev:
+            ev[2].record(stream)
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(a.steps)]
+    t0 = time.perf_counter()
+    for s in range(a.steps):
+        step(events[s])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    chem_ms = np.array([e[0].elapsed_time(e[1]) for e in events])
+    dnn_ms = np.array([e[1].elapsed_time(e[2]) for e in events])
+    ms_step = wall * 1e3 / a.steps
+
+    # work actually done by the integrator (useful attempts per cell)
+    ns = nsteps.cpu().numpy()
+    attempts = int(ns.sum())
+    ops = integrator_lane_ops(mech_h)
+    chem_flops = 2.0 * ops["per_attempt"] * attempts        # an FMA lane-op is 2 FLOP
+    chem_tflops = chem_flops / (chem_ms.mean() * 1e-3) / 1e12
+    dnn_flops = mlp_flops(dnn.dims) * n
+    dnn_tflops = dnn_flops / (dnn_ms.mean() * 1e-3) / 1e12
+
+    # DNN error against the oracle integrator (renormalisation on, as timed, and off)
+    T_c, Y_c, stc = Tc.cpu().numpy(), Yc.cpu().numpy(), st_c.cpu().numpy()
+    T_d, Y_d, std = Td.cpu().numpy(), Yd.cpu().numpy(), st_d.cpu().numpy()
+    Td2, Yd2 = T_in.clone(), Y_in.clone()
+    st2 = torch.zeros(n, dtype=torch.int32, device=dev)
+    dnn.step(Td2, p, Yd2, DT, status=st2, workspace=ws, opts=df.dnn_opts(renormalise=0))
+    torch.cuda.synchronize()
+
+    cpu = None
+    err = None
+    if not a.no_cpu:
+        import oracle
+        om = oracle.Mech(MECH)
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        t1 = time.perf_counter()
+        ro = om.chem_step(f["T"], f["p"], f["Y"], DT, nthreads=threads)
+        t_int = time.perf_counter() - t1
+        # the oracle's DNN step (bf16-emulated network) on a strided sample of the field
+        od = oracle.DNN(DNN_W)
+        sample = np.arange(0, n, 16)
+        t1 = time.perf_counter()
+        od.step(om, f["T"][sample], f["p"][sample], f["Y"][:, sample], DT, mode=1, nthreads=threads)
+        t_dnn_s = time.perf_counter() - t1
+        t_dnn = t_dnn_s * n / sample.size
+        cpu = {"value": n / (t_int + t_dnn), "unit": "cells/s", "cores": threads, "kind": "oracle",
+               "sample": f"integrator on all {n} cells ({t_int:.2f} s) + DNN step on every 16th cell "
+                         f"({sample.size} cells, {t_dnn_s:.2f} s, scaled to {n})",
+               "integrator_cells_per_s": n / t_int, "dnn_cells_per_s": n / t_dnn}
+        err = {"renormalised": dnn_error(f["T"], f["Y"], T_d, Y_d, ro["T"], ro["Y"], std),
+               "not_renormalised": dnn_error(f["T"], f["Y"], Td2.cpu().numpy(), Yd2.cpu().numpy(), ro["T"], ro["Y"],
+                                             st2.cpu().numpy())}
+        # the integrator result itself against the oracle (sampled parity at full size)
+        relT = np.abs(T_c - ro["T"]) / ro["T"]
+        mask = ro["Y"] > 1e-10
+        relY = np.where(mask, np.abs(Y_c - ro["Y"]) / np.where(mask, ro["Y"], 1.0), 0.0)
+        err["integrator_max_rel_vs_oracle"] = float(max(relT.max(), relY.max()))
+
+    out = {
+        "metric": "cells/s per chemistry step: FP64 stiff integrator vs BF16 DNN at stated error",
+        "value": n / (ms_step * 1e-3),
+        "unit": "cells/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "hot-kernel field 256x256=65536 cells, H2/air phi=1, 9 species/24 reactions "
+                               "(seeded), p=1 atm, dt=1e-6 s; step = FP64 RODAS4 integrator + BF16 DNN "
+                               "11-1600-800-400-9 with FP64 fallback",
+                   "n_cells": n, "dt": DT, "rtol": 1e-8, "mechanism": os.path.basename(MECH),
+                   "dnn": os.path.basename(DNN_W)},
+        "forms": {
+            "fp64_integrator": {"cells_per_s": n / (chem_ms.mean() * 1e-3), "ms": float(chem_ms.mean()),
+                                "attempts_total": attempts, "attempts_per_cell_mean": attempts / n,
+                                "accepted_max": int(ns[:n].max()), "status_counts": np.bincount(stc).tolist()},
+            "bf16_dnn": {"cells_per_s": n / (dnn_ms.mean() * 1e-3), "ms": float(dnn_ms.mean()),
+                         "tflops": dnn_tflops, "mfma_frac": dnn_tflops / PEAK_BF16_TFLOPS,
+                         "fallback_frac": float(np.mean(std == 4)), "status_counts": np.bincount(std).tolist()},
+        },
+        "roofline": {"bound": "alu", "kernel": "chem_step_kernel<9> (FP64 VALU)", "achieved": chem_tflops,
+                     "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": chem_tflops / PEAK_FP64_TFLOPS,
+                     "traffic": None, "lane_ops_per_attempt": ops},
+        "dnn_error_vs_oracle_integrator": err,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
