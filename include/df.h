@@ -70,7 +70,8 @@ typedef struct {
     double atol_Y;     /* absolute tolerance on Y, default 1e-14 */
     double h_min;      /* smallest sub-step [s], default 1e-20 */
     int32_t max_steps; /* attempted sub-steps per cell and call, default 100000 */
-    int32_t reserved;  /* must be 0 */
+    int32_t mapping;   /* work mapping: 0 (default) automatic, 1 one cell per lane,
+                          2 sixteen lanes per cell (species count <= 15) */
 } df_chem_opts;
 
 /* DNN options. */

@@ -23,7 +23,7 @@ CELL_DNN_FALLBACK = 4
 
 class ChemOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol_T", C.c_double), ("atol_Y", C.c_double), ("h_min", C.c_double),
-                ("max_steps", C.c_int32), ("reserved", C.c_int32)]
+                ("max_steps", C.c_int32), ("mapping", C.c_int32)]
 
 
 class DnnOpts(C.Structure):

@@ -15,40 +15,10 @@
 #include <cmath>
 
 #include "df_internal.h"
+#include "df_kinetics.h"
 
 namespace df {
 namespace {
-
-// ---- RODAS4, transformed coefficients: (I/(g h) - J) u_i = f(y + sum a_ij u_j) + sum (c_ij/h) u_j
-struct Rodas4 {
-    static constexpr double g = 0.25;
-    static constexpr double a[6][5] = {
-        {0, 0, 0, 0, 0},
-        {1.544, 0, 0, 0, 0},
-        {0.9466785280815826, 0.2557011698983284, 0, 0, 0},
-        {3.314825187068521, 2.896124015972201, 0.9986419139977817, 0, 0},
-        {1.221224509226641, 6.019134481288629, 12.53708332932087, -0.6878860361058950, 0},
-        {1.221224509226641, 6.019134481288629, 12.53708332932087, -0.6878860361058950, 1.0},
-    };
-    static constexpr double c[6][5] = {
-        {0, 0, 0, 0, 0},
-        {-5.6688, 0, 0, 0, 0},
-        {-2.430093356833875, -0.2063599157091915, 0, 0, 0},
-        {-0.1073529058151375, -9.594562251023355, -20.47028614809616, 0, 0},
-        {7.496443313967647, -10.24680431464352, -33.99990352819905, 11.70890893206160, 0},
-        {8.083246795921522, -7.981132988064893, -31.52159432874371, 16.31930543123136, -6.058818238834054},
-    };
-    // stage 6 starts from the embedded (order 3) solution; the order-4 solution adds u6,
-    // so the error estimate is u6 itself.
-};
-
-constexpr double kInvLn10 = 0.43429448190325182765;
-constexpr double kLn10 = 2.30258509299404568402;
-
-struct Opts {
-    double rtol, atol_T, atol_Y, h_min;
-    int max_steps;
-};
 
 // Per-lane species arrays live in LDS, slot-major with a stride of one wave
 // (element k of lane l at sh[k * 64 + l]): a gather with a wave-uniform species
@@ -121,57 +91,10 @@ struct Cell {
         at(sh, kIE) = 1.0;
     }
 
-    __device__ __forceinline__ static double cref_pow(const Mix &s, int dnu) {
-        // (p0/RT)^(-dnu): the reverse rate constant is kf / Kc, Kc = prod(e)^nu (p0/RT)^dnu
-        double r = 1.0;
-        if (dnu > 0)
-            for (int i = 0; i < dnu; ++i) r *= s.icref;
-        else
-            for (int i = 0; i < -dnu; ++i) r *= s.cref;
-        return r;
-    }
-
-    // Forward rate constant; for Troe rows also d ln kf/dT at fixed [M] and d kf/d[M].
     template <bool DERIV>
     __device__ __forceinline__ static double kforward(const double *rd, int type, const Mix &s, double Mc,
                                                       double &dlnkf, double &dkfdM) {
-        const double kinf = exp(rd[0] + rd[1] * s.lT - rd[2] * s.iT);
-        const double dlninf = (rd[1] + rd[2] * s.iT) * s.iT;
-        if (type != 2) {
-            if (DERIV) {
-                dlnkf = dlninf;
-                dkfdM = 0.0;
-            }
-            return kinf;
-        }
-        const double T = s.T;
-        const double k0 = exp(rd[3] + rd[4] * s.lT - rd[5] * s.iT);
-        const double al = rd[6], i3 = rd[7], i1 = rd[8], T2 = rd[9];
-        const double e3 = exp(-T * i3), e1 = exp(-T * i1), e2 = exp(-T2 * s.iT);
-        const double Fc = (1.0 - al) * e3 + al * e1 + e2;
-        const double lFc = log(Fc) * kInvLn10;
-        const double Pr = k0 * Mc / kinf;
-        const double lPr = log(Pr) * kInvLn10;
-        const double cc = -0.4 - 0.67 * lFc;
-        const double nn = 0.75 - 1.27 * lFc;
-        const double x = lPr + cc;
-        const double iden = 1.0 / (nn - 0.14 * x);
-        const double f1 = x * iden;
-        const double q1 = 1.0 / (1.0 + f1 * f1);
-        const double F = exp(lFc * q1 * kLn10);
-        const double iPr1 = 1.0 / (1.0 + Pr);
-        const double kf = kinf * Pr * iPr1 * F;
-        if (DERIV) {
-            const double dlnk0 = (rd[4] + rd[5] * s.iT) * s.iT;
-            const double gq = 2.0 * f1 * q1 * q1;
-            const double dlF_dlPr = -lFc * gq * nn * iden * iden;
-            const double dlF_dlFc = q1 - lFc * gq * (1.27 * x - 0.67 * nn) * iden * iden;
-            const double dFc = -(1.0 - al) * i3 * e3 - al * i1 * e1 + T2 * s.iT * s.iT * e2;
-            const double dlFc_dT = dFc / Fc * kInvLn10;
-            dlnkf = dlninf + (iPr1 + dlF_dlPr) * (dlnk0 - dlninf) + kLn10 * dlF_dlFc * dlFc_dT;
-            dkfdM = k0 * F * iPr1 * (iPr1 + dlF_dlPr);
-        }
-        return kf;
+        return rate_constant<DERIV>(rd, type, s.T, s.iT, s.lT, Mc, dlnkf, dkfdM);
     }
 
     __device__ __forceinline__ static double third_body(const MechDev &m, int j, double *sh) {
@@ -200,7 +123,7 @@ struct Cell {
             double dl, dm;
             const double kf = kforward<false>(rd, type, s, Mc, dl, dm);
             const double iKc = at(sh, kE + r0) * at(sh, kE + r1) * at(sh, kE + r2) * at(sh, kIE + p0) *
-                               at(sh, kIE + p1) * at(sh, kIE + p2) * cref_pow(s, dnu);
+                               at(sh, kIE + p1) * at(sh, kIE + p2) * cref_pow(s.cref, s.icref, dnu);
             const double fwd = kf * (at(sh, kC + r0) * at(sh, kC + r1) * at(sh, kC + r2));
             const double rev = kf * iKc * (at(sh, kC + p0) * at(sh, kC + p1) * at(sh, kC + p2));
             double q = fwd - rev;
@@ -253,7 +176,7 @@ struct Cell {
             double dlnkf, dkfdM;
             const double kf = kforward<true>(rd, type, s, Mc, dlnkf, dkfdM);
             const double iKc = at(sh, kE + r0) * at(sh, kE + r1) * at(sh, kE + r2) * at(sh, kIE + p0) *
-                               at(sh, kIE + p1) * at(sh, kIE + p2) * cref_pow(s, dnu);
+                               at(sh, kIE + p1) * at(sh, kIE + p2) * cref_pow(s.cref, s.icref, dnu);
             const double kr = kf * iKc;
             const double c0 = at(sh, kC + r0), c1 = at(sh, kC + r1), c2 = at(sh, kC + r2);
             const double d0 = at(sh, kC + p0), d1 = at(sh, kC + p1), d2 = at(sh, kC + p2);
@@ -623,6 +546,11 @@ df_status launch_chem_step(const MechDev &m, int64_t n, int64_t ld, double dt, c
                            double *h_inout, double *rr, int32_t *status, int32_t *n_steps, const df_chem_opts &opts,
                            const int32_t *cidx, const int32_t *dcount, int32_t status_ok, hipStream_t stream) {
     if (n == 0) return DF_OK;
+    // mapping 0 picks 16 lanes per cell whenever a kernel is compiled for K: one sub-step
+    // then takes a fraction of the latency, which bounds a stiff cell's step time
+    if (opts.mapping == 2 || (opts.mapping == 0 && chem_coop_supported(m.K)))
+        return launch_chem_coop(m, n, ld, dt, p, T, Y, h_inout, rr, status, n_steps, opts, cidx, dcount, status_ok,
+                                stream);
     if (n > int64_t(64) * 0x7fffffff) return fail(DF_E_UNSUPPORTED, "df_chem_step: too many cells for one launch");
     const Opts o{opts.rtol, opts.atol_T, opts.atol_Y, opts.h_min, opts.max_steps};
     switch (m.K) {

@@ -30,6 +30,8 @@ struct MechDev {
     const double *rk;   // [M][kRxDbl]
     const double *eff;  // [M][K]
     const int *nu;      // [M][K] net stoichiometric coefficients nu'' - nu'
+    int lmax;           // longest per-species reaction list
+    const int *spl;     // [K][lmax][2]: (reaction j, nu_kj) for nu_kj != 0, padded with (M, 0)
 };
 
 struct HostMech {
@@ -62,6 +64,12 @@ df_status launch_chem_step(const MechDev &m, int64_t n, int64_t ld, double dt, c
 // status_ok is the code written for cells that succeed (DF_CELL_OK, or DF_CELL_DNN_FALLBACK).
 
 df_status validate_chem_opts(const df_chem_opts &o);
+
+// cooperative integrator (df_chem_coop.hip): 16 lanes per cell, K <= 15
+bool chem_coop_supported(int K);
+df_status launch_chem_coop(const MechDev &m, int64_t n, int64_t ld, double dt, const double *p, double *T, double *Y,
+                           double *h_inout, double *rr, int32_t *status, int32_t *n_steps, const df_chem_opts &o,
+                           const int32_t *cell_index, const int32_t *d_count, int32_t status_ok, hipStream_t stream);
 
 }  // namespace df
 

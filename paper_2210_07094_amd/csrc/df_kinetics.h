@@ -1,0 +1,97 @@
+// Device-side pieces shared by the integrator kernels: the RODAS4 tableau, the
+// integrator options and the forward rate constant (Arrhenius, Lindemann/Troe).
+#pragma once
+
+#include "df_internal.h"
+
+namespace df {
+
+// ---- RODAS4, transformed coefficients: (I/(g h) - J) u_i = f(y + sum a_ij u_j) + sum (c_ij/h) u_j
+struct Rodas4 {
+    static constexpr double g = 0.25;
+    static constexpr double a[6][5] = {
+        {0, 0, 0, 0, 0},
+        {1.544, 0, 0, 0, 0},
+        {0.9466785280815826, 0.2557011698983284, 0, 0, 0},
+        {3.314825187068521, 2.896124015972201, 0.9986419139977817, 0, 0},
+        {1.221224509226641, 6.019134481288629, 12.53708332932087, -0.6878860361058950, 0},
+        {1.221224509226641, 6.019134481288629, 12.53708332932087, -0.6878860361058950, 1.0},
+    };
+    static constexpr double c[6][5] = {
+        {0, 0, 0, 0, 0},
+        {-5.6688, 0, 0, 0, 0},
+        {-2.430093356833875, -0.2063599157091915, 0, 0, 0},
+        {-0.1073529058151375, -9.594562251023355, -20.47028614809616, 0, 0},
+        {7.496443313967647, -10.24680431464352, -33.99990352819905, 11.70890893206160, 0},
+        {8.083246795921522, -7.981132988064893, -31.52159432874371, 16.31930543123136, -6.058818238834054},
+    };
+    // stage 6 starts from the embedded (order 3) solution; the order-4 solution adds u6,
+    // so the error estimate is u6 itself.
+};
+
+constexpr double kInvLn10 = 0.43429448190325182765;
+constexpr double kLn10 = 2.30258509299404568402;
+
+struct Opts {
+    double rtol, atol_T, atol_Y, h_min;
+    int max_steps;
+};
+
+
+// Forward rate constant of one reaction row (rd = ln A, b, Ta, ln A0, b0, Ta0, alpha,
+// 1/T***, 1/T*, T**, ...): Arrhenius k = A T^b exp(-Ta/T); for Troe rows the
+// Lindemann form k_inf Pr/(1+Pr) times the broadening factor F, Pr = k_0 [M]/k_inf.
+// With DERIV also d ln kf/dT at fixed [M] and d kf/d[M].
+template <bool DERIV>
+__device__ __forceinline__ double rate_constant(const double *rd, int type, double T, double iT, double lT, double Mc,
+                                                double &dlnkf, double &dkfdM) {
+    const double kinf = exp(rd[0] + rd[1] * lT - rd[2] * iT);
+    const double dlninf = (rd[1] + rd[2] * iT) * iT;
+    if (type != 2) {
+        if (DERIV) {
+            dlnkf = dlninf;
+            dkfdM = 0.0;
+        }
+        return kinf;
+    }
+    const double k0 = exp(rd[3] + rd[4] * lT - rd[5] * iT);
+    const double al = rd[6], i3 = rd[7], i1 = rd[8], T2 = rd[9];
+    const double e3 = exp(-T * i3), e1 = exp(-T * i1), e2 = exp(-T2 * iT);
+    const double Fc = (1.0 - al) * e3 + al * e1 + e2;
+    const double lFc = log(Fc) * kInvLn10;
+    const double Pr = k0 * Mc / kinf;
+    const double lPr = log(Pr) * kInvLn10;
+    const double cc = -0.4 - 0.67 * lFc;
+    const double nn = 0.75 - 1.27 * lFc;
+    const double x = lPr + cc;
+    const double iden = 1.0 / (nn - 0.14 * x);
+    const double f1 = x * iden;
+    const double q1 = 1.0 / (1.0 + f1 * f1);
+    const double F = exp(lFc * q1 * kLn10);
+    const double iPr1 = 1.0 / (1.0 + Pr);
+    const double kf = kinf * Pr * iPr1 * F;
+    if (DERIV) {
+        const double dlnk0 = (rd[4] + rd[5] * iT) * iT;
+        const double gq = 2.0 * f1 * q1 * q1;
+        const double dlF_dlPr = -lFc * gq * nn * iden * iden;
+        const double dlF_dlFc = q1 - lFc * gq * (1.27 * x - 0.67 * nn) * iden * iden;
+        const double dFc = -(1.0 - al) * i3 * e3 - al * i1 * e1 + T2 * iT * iT * e2;
+        const double dlFc_dT = dFc / Fc * kInvLn10;
+        dlnkf = dlninf + (iPr1 + dlF_dlPr) * (dlnk0 - dlninf) + kLn10 * dlF_dlFc * dlFc_dT;
+        dkfdM = k0 * F * iPr1 * (iPr1 + dlF_dlPr);
+    }
+    return kf;
+}
+
+// (p0/RT)^(-dnu) from p0/RT and its inverse: the reverse rate constant is kf / Kc with
+// Kc = prod_k exp(-G_k/RT)^nu_k (p0/RT)^dnu in mol/cm^3 units
+__device__ __forceinline__ double cref_pow(double cref, double icref, int dnu) {
+    double r = 1.0;
+    if (dnu > 0)
+        for (int i = 0; i < dnu; ++i) r *= icref;
+    else
+        for (int i = 0; i < -dnu; ++i) r *= cref;
+    return r;
+}
+
+}  // namespace df

@@ -125,10 +125,40 @@ df_status parse_mech_file(const char *path, HostMech &m) {
     return DF_OK;
 }
 
+// Order in which the reactions are stored on the device.  The cooperative kernel
+// evaluates stored reaction j on lane j % 16, so the order spreads the costly
+// reactions (Troe falloff: seven transcendentals; third body: a K-term sum) over
+// the lanes: longest-processing-time assignment of reactions, in decreasing cost,
+// to the lane with the least work that still has a free slot.  Results do not
+// depend on the order beyond the summation order of production rates.
+static std::vector<int> lane_balanced_order(const HostMech &m, int lanes = 16) {
+    const int M = m.M;
+    std::vector<int> slots(lanes, 0);
+    for (int j = 0; j < M; ++j) ++slots[j % lanes];
+    auto cost = [&](int j) { return m.type[j] == 2 ? 8.0 : (m.type[j] == 1 ? 1.5 : 1.0); };
+    std::vector<int> byc(M);
+    for (int j = 0; j < M; ++j) byc[j] = j;
+    std::stable_sort(byc.begin(), byc.end(), [&](int a, int b) { return cost(a) > cost(b); });
+    std::vector<double> load(lanes, 0.0);
+    std::vector<std::vector<int>> assigned(lanes);
+    for (int j : byc) {
+        int best = -1;
+        for (int l = 0; l < lanes; ++l)
+            if (int(assigned[l].size()) < slots[l] && (best < 0 || load[l] < load[best])) best = l;
+        assigned[best].push_back(j);
+        load[best] += cost(j);
+    }
+    std::vector<int> order(M);
+    for (int l = 0; l < lanes; ++l)
+        for (size_t q = 0; q < assigned[l].size(); ++q) order[l + q * lanes] = assigned[l][q];
+    return order;
+}
+
 // Pack the host mechanism into the device table layout described in df_internal.h.
 static void pack_tables(const HostMech &m, std::vector<double> &sp, std::vector<int> &rx, std::vector<double> &rk,
-                        std::vector<double> &eff, std::vector<int> &nu) {
+                        std::vector<double> &eff, std::vector<int> &nu, std::vector<int> &spl, int &lmax) {
     const int K = m.K, M = m.M;
+    const std::vector<int> order = lane_balanced_order(m);
     sp.assign(size_t(K) * kSpTab, 0.0);
     for (int k = 0; k < K; ++k) {
         const double *a = &m.nasa[7 * k];
@@ -151,9 +181,10 @@ static void pack_tables(const HostMech &m, std::vector<double> &sp, std::vector<
     rk.assign(size_t(std::max(M, 1)) * kRxDbl, 0.0);
     eff.assign(size_t(std::max(M, 1)) * K, 1.0);
     nu.assign(size_t(std::max(M, 1)) * K, 0);
-    for (int j = 0; j < M; ++j) {
-        int *ri = &rx[size_t(j) * kRxInt];
-        double *rd = &rk[size_t(j) * kRxDbl];
+    for (int jd = 0; jd < M; ++jd) {
+        const int j = order[jd];  // source reaction stored at device position jd
+        int *ri = &rx[size_t(jd) * kRxInt];
+        double *rd = &rk[size_t(jd) * kRxDbl];
         ri[0] = m.type[j];
         int nr = 0, np = 0, dnu = 0;
         for (int k = 0; k < K; ++k) {
@@ -177,17 +208,32 @@ static void pack_tables(const HostMech &m, std::vector<double> &sp, std::vector<
         rd[10] = nr;
         rd[11] = np;
         for (int k = 0; k < K; ++k) {
-            eff[size_t(j) * K + k] = m.eff[size_t(j) * K + k];
-            nu[size_t(j) * K + k] = m.nu_p[size_t(j) * K + k] - m.nu_r[size_t(j) * K + k];
+            eff[size_t(jd) * K + k] = m.eff[size_t(j) * K + k];
+            nu[size_t(jd) * K + k] = m.nu_p[size_t(j) * K + k] - m.nu_r[size_t(j) * K + k];
         }
     }
+    // per-species lists of the reactions that change it
+    std::vector<std::vector<std::pair<int, int>>> lists(K);
+    for (int j = 0; j < M; ++j)
+        for (int k = 0; k < K; ++k)
+            if (nu[size_t(j) * K + k] != 0) lists[k].push_back({j, nu[size_t(j) * K + k]});
+    lmax = 1;
+    for (auto &l : lists) lmax = std::max<int>(lmax, int(l.size()));
+    spl.assign(size_t(K) * lmax * 2, 0);
+    for (int k = 0; k < K; ++k)
+        for (int e = 0; e < lmax; ++e) {
+            const bool have = e < int(lists[k].size());
+            spl[(size_t(k) * lmax + e) * 2] = have ? lists[k][e].first : M;  // padding: slot M holds zeros
+            spl[(size_t(k) * lmax + e) * 2 + 1] = have ? lists[k][e].second : 0;
+        }
 }
 
 df_status validate_chem_opts(const df_chem_opts &o) {
     if (!(o.rtol > 0 && o.rtol < 1) || !(o.atol_T > 0) || !(o.atol_Y > 0) || !(o.h_min > 0) || o.max_steps < 1 ||
-        o.reserved != 0 || !std::isfinite(o.atol_T) || !std::isfinite(o.atol_Y) || !std::isfinite(o.h_min))
+        o.mapping < 0 || o.mapping > 2 || !std::isfinite(o.atol_T) || !std::isfinite(o.atol_Y) ||
+        !std::isfinite(o.h_min))
         return fail(DF_E_INVALID, "df_chem_opts: need 0 < rtol < 1, atol_T, atol_Y, h_min > 0 and finite, "
-                                  "max_steps >= 1, reserved = 0");
+                                  "max_steps >= 1, mapping in {0, 1, 2}");
     return DF_OK;
 }
 
@@ -208,7 +254,7 @@ void df_chem_default_opts(df_chem_opts *o) {
     o->atol_Y = 1e-14;
     o->h_min = 1e-20;
     o->max_steps = 100000;
-    o->reserved = 0;
+    o->mapping = 0;
 }
 
 void df_dnn_default_opts(df_dnn_opts *o) {
@@ -227,12 +273,14 @@ df_status df_mech_load(const char *path, int32_t device, df_mech **out) {
     df_status st = parse_mech_file(path, hm);
     if (st != DF_OK) return st;
     std::vector<double> sp, rk, eff;
-    std::vector<int> rx, nu;
-    pack_tables(hm, sp, rx, rk, eff, nu);
-    // one allocation: [sp | rk | eff | rx | nu], each part 256-byte aligned
+    std::vector<int> rx, nu, spl;
+    int lmax = 1;
+    pack_tables(hm, sp, rx, rk, eff, nu, spl, lmax);
+    // one allocation: [sp | rk | eff | rx | nu | spl], each part 256-byte aligned
     auto align = [](size_t b) { return (b + 255) & ~size_t(255); };
     size_t o_sp = 0, o_rk = align(o_sp + sp.size() * 8), o_eff = align(o_rk + rk.size() * 8),
-           o_rx = align(o_eff + eff.size() * 8), o_nu = align(o_rx + rx.size() * 4), total = align(o_nu + nu.size() * 4);
+           o_rx = align(o_eff + eff.size() * 8), o_nu = align(o_rx + rx.size() * 4),
+           o_spl = align(o_nu + nu.size() * 4), total = align(o_spl + spl.size() * 4);
     int prev = 0;
     if (hipGetDevice(&prev) != hipSuccess) return fail(DF_E_HIP, "df_mech_load: hipGetDevice failed");
     if (hipSetDevice(device) != hipSuccess) return fail(DF_E_INVALID, "df_mech_load: invalid device");
@@ -245,6 +293,7 @@ df_status df_mech_load(const char *path, int32_t device, df_mech **out) {
         std::memcpy(h.data() + o_eff, eff.data(), eff.size() * 8);
         std::memcpy(h.data() + o_rx, rx.data(), rx.size() * 4);
         std::memcpy(h.data() + o_nu, nu.data(), nu.size() * 4);
+        std::memcpy(h.data() + o_spl, spl.data(), spl.size() * 4);
         e = hipMemcpy(blob, h.data(), total, hipMemcpyHostToDevice);
     }
     (void)hipSetDevice(prev);
@@ -264,6 +313,8 @@ df_status df_mech_load(const char *path, int32_t device, df_mech **out) {
     m->dev.eff = reinterpret_cast<const double *>(base + o_eff);
     m->dev.rx = reinterpret_cast<const int *>(base + o_rx);
     m->dev.nu = reinterpret_cast<const int *>(base + o_nu);
+    m->dev.spl = reinterpret_cast<const int *>(base + o_spl);
+    m->dev.lmax = lmax;
     *out = m;
     return DF_OK;
 }

@@ -26,6 +26,14 @@ def _torch():
     return torch
 
 
+MAPPINGS = [1, 2]   # one cell per lane; sixteen lanes per cell
+
+
+def _opts(mapping, **kw):
+    import paper_2210_07094_amd as df
+    return df.chem_opts(mapping=mapping, **kw)
+
+
 def _gpu_step(mech, f, dt, h=None, rr=False, opts=None, ld=None):
     torch = _torch()
     n = f["T"].size
@@ -76,10 +84,11 @@ def gmech(h2_path):
     return df.Mechanism(h2_path)
 
 
-def test_parity_ignition_cells(gmech, h2_oracle, h2_mech):
+@pytest.mark.parametrize("mapping", MAPPINGS)
+def test_parity_ignition_cells(gmech, h2_oracle, h2_mech, mapping):
     f = fields.ignition_cells(h2_mech)
-    print("case: 1024 ignition cells, dt=1e-6", flush=True)
-    g = _gpu_step(gmech, f, 1e-6, h=np.zeros(f["T"].size), rr=True)
+    print(f"case: 1024 ignition cells, dt=1e-6, mapping {mapping}", flush=True)
+    g = _gpu_step(gmech, f, 1e-6, h=np.zeros(f["T"].size), rr=True, opts=_opts(mapping))
     o = h2_oracle.chem_step(f["T"], f["p"], f["Y"], 1e-6, h_inout=np.zeros(f["T"].size), want_rr=True)
     assert np.all(g["status"] == 0) and np.all(o["status"] == 0)
     worst, nflip, tol_err = compare(g, o)
@@ -96,10 +105,11 @@ def test_parity_ignition_cells(gmech, h2_oracle, h2_mech):
     assert np.abs(g["rr"][:, same] - o["rr"][:, same]).max() <= 1e-6 * scale
 
 
-def test_parity_hot_kernel_field(gmech, h2_oracle, h2_mech):
+@pytest.mark.parametrize("mapping", MAPPINGS)
+def test_parity_hot_kernel_field(gmech, h2_oracle, h2_mech, mapping):
     f = fields.hot_kernel_field_2d(h2_mech)
-    print("case: 65536-cell hot-kernel field, dt=1e-6", flush=True)
-    g = _gpu_step(gmech, f, 1e-6)
+    print(f"case: 65536-cell hot-kernel field, dt=1e-6, mapping {mapping}", flush=True)
+    g = _gpu_step(gmech, f, 1e-6, opts=_opts(mapping))
     o = h2_oracle.chem_step(f["T"], f["p"], f["Y"], 1e-6, nthreads=0)
     assert np.all(g["status"] == 0)
     worst, nflip, tol_err = compare(g, o)
@@ -110,15 +120,16 @@ def test_parity_hot_kernel_field(gmech, h2_oracle, h2_mech):
     np.testing.assert_array_equal(g["n_acc"] + g["n_rej"] > 0, True)
 
 
-def test_ragged_ld_and_tail(gmech, h2_oracle, h2_mech):
+@pytest.mark.parametrize("mapping", MAPPINGS)
+def test_ragged_ld_and_tail(gmech, h2_oracle, h2_mech, mapping):
     """n not a multiple of the wave size, ld > n: padding columns untouched."""
-    f = fields.ignition_cells(h2_mech, n=1000, seed=77)
-    print("case: n=1000, ld=1100", flush=True)
-    g = _gpu_step(gmech, f, 1e-6, ld=1100)
+    f = fields.ignition_cells(h2_mech, n=1001, seed=77)
+    print(f"case: n=1001, ld=1100, mapping {mapping}", flush=True)
+    g = _gpu_step(gmech, f, 1e-6, ld=1100, opts=_opts(mapping))
     o = h2_oracle.chem_step(f["T"], f["p"], f["Y"], 1e-6)
     worst, nflip, tol_err = compare(g, o)
     assert worst <= RTOL_PARITY and tol_err <= 10.0
-    assert np.all(g["Y_full"][:, 1000:] == 0.0)
+    assert np.all(g["Y_full"][:, 1001:] == 0.0)
 
 
 def test_empty_launch(gmech):
@@ -128,14 +139,15 @@ def test_empty_launch(gmech):
     assert gmech.chem_step(z, z, Y, 1e-6) == 0
 
 
-def test_nonfinite_and_limits(gmech, h2_oracle, h2_mech):
+@pytest.mark.parametrize("mapping", MAPPINGS)
+def test_nonfinite_and_limits(gmech, h2_oracle, h2_mech, mapping):
     import paper_2210_07094_amd as df
     f = fields.ignition_cells(h2_mech, n=70, seed=5)
     f["T"][3] = np.nan
     f["T"][4] = -5.0
     f["Y"][2, 5] = np.inf
-    print("case: non-finite inputs", flush=True)
-    g = _gpu_step(gmech, f, 1e-6)
+    print(f"case: non-finite inputs, mapping {mapping}", flush=True)
+    g = _gpu_step(gmech, f, 1e-6, opts=_opts(mapping))
     assert list(g["status"][3:6]) == [3, 3, 3]
     assert np.isnan(g["T"][3]) and g["T"][4] == -5.0 and np.isinf(g["Y"][2, 5])
     ok = np.ones(70, bool)
@@ -144,7 +156,7 @@ def test_nonfinite_and_limits(gmech, h2_oracle, h2_mech):
     # max_steps = 2 -> MAX_STEPS, same partial state as the oracle
     f2 = fields.ignition_cells(h2_mech, n=64, seed=6)
     print("case: max_steps=2", flush=True)
-    g2 = _gpu_step(gmech, f2, 1e-6, opts=df.chem_opts(max_steps=2))
+    g2 = _gpu_step(gmech, f2, 1e-6, opts=_opts(mapping, max_steps=2))
     o2 = h2_oracle.chem_step(f2["T"], f2["p"], f2["Y"], 1e-6, opts=oracle.default_opts(max_steps=2))
     np.testing.assert_array_equal(g2["status"], o2["status"])
     assert np.all(g2["status"] == 1)
@@ -158,14 +170,15 @@ def test_nonfinite_and_limits(gmech, h2_oracle, h2_mech):
     assert max(eT.max(), eY.max()) <= 10.0
     # h_min above every proposal -> H_UNDERFLOW after the first rejection
     print("case: h_min large", flush=True)
-    g3 = _gpu_step(gmech, f2, 1e-6, h=np.full(64, 1e-6), opts=df.chem_opts(h_min=5e-7, rtol=1e-12))
+    g3 = _gpu_step(gmech, f2, 1e-6, h=np.full(64, 1e-6), opts=_opts(mapping, h_min=5e-7, rtol=1e-12))
     o3 = h2_oracle.chem_step(f2["T"], f2["p"], f2["Y"], 1e-6, h_inout=np.full(64, 1e-6),
                              opts=oracle.default_opts(h_min=5e-7, rtol=1e-12))
     np.testing.assert_array_equal(g3["status"], o3["status"])
     assert np.any(g3["status"] == 2)
 
 
-def test_small_mechanisms_closed_form(tmp_path, h2_mech):
+@pytest.mark.parametrize("mapping", MAPPINGS)
+def test_small_mechanisms_closed_form(tmp_path, h2_mech, mapping):
     """K = 2 and K = 4 kernels against the oracle and the closed forms."""
     import paper_2210_07094_amd as df
     m = testmechs.isomerisation()
@@ -176,7 +189,7 @@ def test_small_mechanisms_closed_form(tmp_path, h2_mech):
     YA0 = np.linspace(0.05, 0.95, n)
     f = {"T": np.full(n, 900.0), "p": np.full(n, 101325.0), "Y": np.vstack([YA0, 1 - YA0])}
     print("case: isomerisation K=2", flush=True)
-    g = _gpu_step(gm, f, 1e-5)
+    g = _gpu_step(gm, f, 1e-5, opts=_opts(mapping))
     kf = m.arrhenius[0, 0]
     kr = kf / np.exp(m.nasa7[1, 6] - m.nasa7[0, 6])
     YAeq = kr / (kf + kr)
@@ -193,7 +206,7 @@ def test_small_mechanisms_closed_form(tmp_path, h2_mech):
     fb = {"T": np.full(64, 1000.0), "p": np.full(64, 101325.0),
           "Y": np.repeat(np.array([[0.05], [0.08], [0.0], [0.87]]), 64, axis=1)}
     print("case: bimolecular + M K=4", flush=True)
-    g = _gpu_step(gb, fb, 2e-5)
+    g = _gpu_step(gb, fb, 2e-5, opts=_opts(mapping))
     ob = oracle.Mech(pb).chem_step(fb["T"], fb["p"], fb["Y"], 2e-5)
     worst, nflip, _ = compare(g, ob)
     assert worst <= RTOL_PARITY and nflip == 0
