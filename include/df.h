@@ -107,6 +107,9 @@ df_status df_mech_load(const char *path, int32_t device, df_mech **out);
 void df_mech_free(df_mech *mech);
 df_status df_mech_info(const df_mech *mech, int32_t *n_species, int32_t *n_reactions, int32_t *n_elements);
 
+/* Bytes of device workspace df_chem_step can use for n_cells (see its `workspace`). */
+df_status df_chem_workspace_size(const df_mech *mech, int64_t n_cells, size_t *bytes);
+
 /*
  * Advance n_cells constant-pressure adiabatic reactors by dt (detailed
  * chemistry, the paper's dfChemistryModel::solve() with its stiff solver;
@@ -120,15 +123,19 @@ df_status df_mech_info(const df_mech *mech, int32_t *n_species, int32_t *n_react
  *   rr          [K*ld]   out     rho0 (Y - Y0) / dt, rho0 the density at the start (nullable)
  *   cell_status [n]      out     DF_CELL_* (nullable)
  *   n_steps     [2*n]    out     accepted sub-steps at [i], rejected at [n + i] (nullable)
+ *   workspace   device memory of df_chem_workspace_size bytes, 256-byte aligned (nullable).
+ *               With it, cells are integrated hottest first (a counting sort on temperature),
+ *               so that the stiffest cells, whose sub-steps set the time of the call, start
+ *               first; without it they are taken in index order.  Results do not depend on it.
  *   opts        nullable = defaults
  * Cells with non-finite input are left untouched with DF_CELL_NONFINITE.
  * Errors: DF_E_INVALID (null handle/array, n < 0, ld < n, dt not > 0 and
- * finite, bad opts), DF_E_UNSUPPORTED (species count beyond the compiled
- * kernels), DF_E_HIP.
+ * finite, bad opts, workspace given but too small or misaligned),
+ * DF_E_UNSUPPORTED (species count beyond the compiled kernels), DF_E_HIP.
  */
 df_status df_chem_step(const df_mech *mech, int64_t n_cells, int64_t ld, double dt, const double *p, double *T,
                        double *Y, double *h_inout, double *rr, int32_t *cell_status, int32_t *n_steps,
-                       const df_chem_opts *opts, void *hip_stream);
+                       void *workspace, size_t workspace_bytes, const df_chem_opts *opts, void *hip_stream);
 
 /*
  * Load a DNN weights file ("DFDNN01", little-endian: int32 L, dims[L+1], K,

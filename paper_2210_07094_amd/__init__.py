@@ -88,12 +88,23 @@ class Mechanism:
         except Exception:
             pass
 
-    def chem_step(self, T, p, Y, dt, h=None, rr=None, status=None, n_steps=None, opts=None, stream=None):
+    def workspace_bytes(self, n_cells: int) -> int:
+        b = C.c_size_t()
+        check(lib().df_chem_workspace_size(self._h, int(n_cells), C.byref(b)))
+        return b.value
+
+    def workspace(self, n_cells: int):
+        import torch
+        return torch.empty(max(self.workspace_bytes(n_cells), 1), dtype=torch.uint8, device=f"cuda:{self.device}")
+
+    def chem_step(self, T, p, Y, dt, h=None, rr=None, status=None, n_steps=None, workspace=None, opts=None,
+                  stream=None):
         """Advance every cell by dt in place (df_chem_step).
 
         T, p: float64 [n]; Y: float64 [K, ld] (species-major, ld >= n); optional
         h [n] (sub-step hint, in/out), rr [K, ld], status int32 [n], n_steps
-        int32 [2n].  Asynchronous on `stream` (default: torch's current stream).
+        int32 [2n], workspace uint8 (hottest-first ordering; see workspace()).
+        Asynchronous on `stream` (default: torch's current stream).
         """
         import torch
         n = T.numel()
@@ -107,6 +118,7 @@ class Mechanism:
                 _ptr(Y, torch.float64, "Y", K * ld, dev), _ptr(h, torch.float64, "h", n, dev),
                 _ptr(rr, torch.float64, "rr", K * ld, dev), _ptr(status, torch.int32, "status", n, dev),
                 _ptr(n_steps, torch.int32, "n_steps", 2 * n, dev),
+                _ptr(workspace, torch.uint8, "workspace", None, dev), 0 if workspace is None else workspace.numel(),
                 C.byref(opts) if opts is not None else None, _stream(stream))
         return check(lib().df_chem_step(*args))
 

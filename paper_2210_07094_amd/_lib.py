@@ -59,8 +59,10 @@ def lib():
     L.df_mech_free.argtypes = [vp]
     L.df_mech_info.restype = i32
     L.df_mech_info.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+    L.df_chem_workspace_size.restype = i32
+    L.df_chem_workspace_size.argtypes = [vp, i64, C.POINTER(C.c_size_t)]
     L.df_chem_step.restype = i32
-    L.df_chem_step.argtypes = [vp, i64, i64, d, vp, vp, vp, vp, vp, vp, vp, C.POINTER(ChemOpts), vp]
+    L.df_chem_step.argtypes = [vp, i64, i64, d, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, C.POINTER(ChemOpts), vp]
     if hasattr(L, "df_dnn_load"):
         L.df_dnn_load.restype = i32
         L.df_dnn_load.argtypes = [C.c_char_p, vp, i32, C.POINTER(vp)]

@@ -564,28 +564,131 @@ df_status launch_chem_step(const MechDev &m, int64_t n, int64_t ld, double dt, c
     }
 }
 
+// ---- hottest-first ordering: counting sort of the cells on temperature buckets ----
+namespace {
+
+constexpr int kBuckets = 256;
+constexpr double kTlo = 200.0, kThi = 3500.0;
+constexpr int kOrdThreads = 256;
+
+// bucket 0 holds the hottest cells; non-finite temperatures go last
+__device__ __forceinline__ int t_bucket(double T) {
+    if (!(T == T) || !isfinite(T)) return kBuckets - 1;
+    const double x = (kThi - T) * (double(kBuckets) / (kThi - kTlo));
+    const int b = int(fmin(fmax(x, 0.0), double(kBuckets - 1)));
+    return b;
+}
+
+__global__ __launch_bounds__(kOrdThreads) void order_zero(int32_t *cnt) {
+    const int t = threadIdx.x;
+    for (int b = t; b < 2 * kBuckets; b += kOrdThreads) cnt[b] = 0;
+}
+
+__global__ __launch_bounds__(kOrdThreads) void order_hist(const double *__restrict__ T, int64_t n,
+                                                          int32_t *__restrict__ cnt) {
+    __shared__ int32_t loc[kBuckets];
+    for (int b = threadIdx.x; b < kBuckets; b += kOrdThreads) loc[b] = 0;
+    __syncthreads();
+    const int64_t i = int64_t(blockIdx.x) * kOrdThreads + threadIdx.x;
+    if (i < n) atomicAdd(&loc[t_bucket(T[i])], 1);
+    __syncthreads();
+    for (int b = threadIdx.x; b < kBuckets; b += kOrdThreads)
+        if (loc[b]) atomicAdd(&cnt[b], loc[b]);
+}
+
+// exclusive scan of the bucket counts into the second half of cnt (one block)
+__global__ __launch_bounds__(kOrdThreads) void order_scan(int32_t *cnt) {
+    __shared__ int32_t v[kBuckets];
+    const int t = threadIdx.x;
+    v[t] = cnt[t];
+    __syncthreads();
+    for (int off = 1; off < kBuckets; off <<= 1) {
+        const int a = (t >= off) ? v[t - off] : 0;
+        __syncthreads();
+        v[t] += a;
+        __syncthreads();
+    }
+    cnt[kBuckets + t] = v[t] - cnt[t];
+}
+
+__global__ __launch_bounds__(kOrdThreads) void order_scatter(const double *__restrict__ T, int64_t n,
+                                                             int32_t *__restrict__ cnt, int32_t *__restrict__ idx) {
+    __shared__ int32_t loc[kBuckets], base[kBuckets];
+    for (int b = threadIdx.x; b < kBuckets; b += kOrdThreads) loc[b] = 0;
+    __syncthreads();
+    const int64_t i = int64_t(blockIdx.x) * kOrdThreads + threadIdx.x;
+    int b = 0, rank = 0;
+    if (i < n) {
+        b = t_bucket(T[i]);
+        rank = atomicAdd(&loc[b], 1);
+    }
+    __syncthreads();
+    for (int q = threadIdx.x; q < kBuckets; q += kOrdThreads)
+        if (loc[q]) base[q] = atomicAdd(&cnt[kBuckets + q], loc[q]);
+    __syncthreads();
+    if (i < n) idx[base[b] + rank] = int32_t(i);
+}
+
+size_t order_bytes(int64_t n) {
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    return al(size_t(2 * kBuckets) * 4) + al(size_t(n) * 4);
+}
+
+}  // namespace
+
 }  // namespace df
+
+extern "C" df_status df_chem_workspace_size(const df_mech *mech, int64_t n_cells, size_t *bytes) {
+    using namespace df;
+    clear_error();
+    if (!mech || !bytes || n_cells < 0) return fail(DF_E_INVALID, "df_chem_workspace_size: bad arguments");
+    *bytes = order_bytes(n_cells);
+    return DF_OK;
+}
 
 extern "C" df_status df_chem_step(const df_mech *mech, int64_t n_cells, int64_t ld, double dt, const double *p,
                                   double *T, double *Y, double *h_inout, double *rr, int32_t *cell_status,
-                                  int32_t *n_steps, const df_chem_opts *opts, void *hip_stream) {
+                                  int32_t *n_steps, void *workspace, size_t ws_bytes, const df_chem_opts *opts,
+                                  void *hip_stream) {
     using namespace df;
     clear_error();
     if (!mech) return fail(DF_E_INVALID, "df_chem_step: null mechanism handle");
     if (n_cells < 0 || ld < n_cells) return fail(DF_E_INVALID, "df_chem_step: need 0 <= n_cells <= ld");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DF_E_INVALID, "df_chem_step: dt must be finite and > 0");
     if (n_cells > 0 && (!p || !T || !Y)) return fail(DF_E_INVALID, "df_chem_step: null p, T or Y");
+    if (n_cells > 0x7fffffff) return fail(DF_E_UNSUPPORTED, "df_chem_step: more than 2^31-1 cells");
     df_chem_opts o;
     df_chem_default_opts(&o);
     if (opts) o = *opts;
     df_status st = validate_chem_opts(o);
     if (st != DF_OK) return st;
+    if (workspace && (ws_bytes < order_bytes(n_cells) || reinterpret_cast<uintptr_t>(workspace) % 256 != 0))
+        return fail(DF_E_INVALID, "df_chem_step: workspace smaller than df_chem_workspace_size or not 256-byte aligned");
+    if (n_cells == 0) return DF_OK;
     int prev = 0;
     if (hipGetDevice(&prev) != hipSuccess) return fail(DF_E_HIP, "df_chem_step: hipGetDevice failed");
     if (prev != mech->device && hipSetDevice(mech->device) != hipSuccess)
         return fail(DF_E_HIP, "df_chem_step: cannot select the mechanism's device");
-    st = launch_chem_step(mech->dev, n_cells, ld, dt, p, T, Y, h_inout, rr, cell_status, n_steps, o, nullptr, nullptr,
-                          DF_CELL_OK, static_cast<hipStream_t>(hip_stream));
+    auto s = static_cast<hipStream_t>(hip_stream);
+    const int32_t *cidx = nullptr;
+    if (workspace) {
+        auto *cnt = static_cast<int32_t *>(workspace);
+        auto *idx = reinterpret_cast<int32_t *>(static_cast<unsigned char *>(workspace) +
+                                                ((size_t(2 * kBuckets) * 4 + 255) & ~size_t(255)));
+        const unsigned blocks = unsigned((n_cells + kOrdThreads - 1) / kOrdThreads);
+        hipLaunchKernelGGL(order_zero, dim3(1), dim3(kOrdThreads), 0, s, cnt);
+        hipLaunchKernelGGL(order_hist, dim3(blocks), dim3(kOrdThreads), 0, s, T, n_cells, cnt);
+        hipLaunchKernelGGL(order_scan, dim3(1), dim3(kOrdThreads), 0, s, cnt);
+        hipLaunchKernelGGL(order_scatter, dim3(blocks), dim3(kOrdThreads), 0, s, T, n_cells, cnt, idx);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) {
+            if (prev != mech->device) (void)hipSetDevice(prev);
+            return fail(DF_E_HIP, std::string("df_chem_step ordering: ") + hipGetErrorString(e));
+        }
+        cidx = idx;
+    }
+    st = launch_chem_step(mech->dev, n_cells, ld, dt, p, T, Y, h_inout, rr, cell_status, n_steps, o, cidx, nullptr,
+                          DF_CELL_OK, s);
     if (prev != mech->device) (void)hipSetDevice(prev);
     return st;
 }

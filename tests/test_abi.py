@@ -25,7 +25,7 @@ def test_exports_every_declared_symbol(L):
 
 def test_default_opts(L):
     o = df.chem_opts()
-    assert (o.rtol, o.atol_T, o.atol_Y, o.h_min, o.max_steps) == (1e-8, 1e-6, 1e-14, 1e-20, 100000)
+    assert (o.rtol, o.atol_T, o.atol_Y, o.h_min, o.max_steps, o.mapping) == (1e-8, 1e-6, 1e-14, 1e-20, 100000, 0)
     d = df.dnn_opts()
     assert (d.renormalise, d.fallback) == (1, 1)
 
@@ -43,7 +43,7 @@ def test_mech_load_errors(L, tmp_path):
 
 def test_chem_step_host_checks(L):
     o = df.chem_opts()
-    assert L.df_chem_step(None, 1, 1, 1e-6, None, None, None, None, None, None, None, C.byref(o), None) \
+    assert L.df_chem_step(None, 1, 1, 1e-6, None, None, None, None, None, None, None, None, 0, C.byref(o), None) \
         == _lib.DF_E_INVALID
     assert b"null mechanism" in L.df_last_error()
 

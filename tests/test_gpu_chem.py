@@ -34,7 +34,7 @@ def _opts(mapping, **kw):
     return df.chem_opts(mapping=mapping, **kw)
 
 
-def _gpu_step(mech, f, dt, h=None, rr=False, opts=None, ld=None):
+def _gpu_step(mech, f, dt, h=None, rr=False, opts=None, ld=None, ordered=False):
     torch = _torch()
     n = f["T"].size
     K = f["Y"].shape[0]
@@ -49,7 +49,8 @@ def _gpu_step(mech, f, dt, h=None, rr=False, opts=None, ld=None):
     rrt = torch.zeros((K, ld), dtype=torch.float64, device=dev) if rr else None
     st = torch.full((n,), -7, dtype=torch.int32, device=dev)
     ns = torch.zeros(2 * n, dtype=torch.int32, device=dev)
-    mech.chem_step(T, p, Y, dt, h=hh, rr=rrt, status=st, n_steps=ns, opts=opts)
+    ws = mech.workspace(n) if ordered else None
+    mech.chem_step(T, p, Y, dt, h=hh, rr=rrt, status=st, n_steps=ns, workspace=ws, opts=opts)
     torch.cuda.synchronize()
     out = {"T": T.cpu().numpy(), "Y": Y.cpu().numpy()[:, :n], "status": st.cpu().numpy(),
            "n_acc": ns[:n].cpu().numpy(), "n_rej": ns[n:].cpu().numpy(), "Y_full": Y.cpu().numpy()}
@@ -105,11 +106,11 @@ def test_parity_ignition_cells(gmech, h2_oracle, h2_mech, mapping):
     assert np.abs(g["rr"][:, same] - o["rr"][:, same]).max() <= 1e-6 * scale
 
 
-@pytest.mark.parametrize("mapping", MAPPINGS)
-def test_parity_hot_kernel_field(gmech, h2_oracle, h2_mech, mapping):
+@pytest.mark.parametrize("mapping,ordered", [(1, False), (2, False), (2, True)])
+def test_parity_hot_kernel_field(gmech, h2_oracle, h2_mech, mapping, ordered):
     f = fields.hot_kernel_field_2d(h2_mech)
-    print(f"case: 65536-cell hot-kernel field, dt=1e-6, mapping {mapping}", flush=True)
-    g = _gpu_step(gmech, f, 1e-6, opts=_opts(mapping))
+    print(f"case: 65536-cell hot-kernel field, dt=1e-6, mapping {mapping}, hottest-first {ordered}", flush=True)
+    g = _gpu_step(gmech, f, 1e-6, opts=_opts(mapping), ordered=ordered)
     o = h2_oracle.chem_step(f["T"], f["p"], f["Y"], 1e-6, nthreads=0)
     assert np.all(g["status"] == 0)
     worst, nflip, tol_err = compare(g, o)
@@ -124,8 +125,8 @@ def test_parity_hot_kernel_field(gmech, h2_oracle, h2_mech, mapping):
 def test_ragged_ld_and_tail(gmech, h2_oracle, h2_mech, mapping):
     """n not a multiple of the wave size, ld > n: padding columns untouched."""
     f = fields.ignition_cells(h2_mech, n=1001, seed=77)
-    print(f"case: n=1001, ld=1100, mapping {mapping}", flush=True)
-    g = _gpu_step(gmech, f, 1e-6, ld=1100, opts=_opts(mapping))
+    print(f"case: n=1001, ld=1100, mapping {mapping}, hottest-first", flush=True)
+    g = _gpu_step(gmech, f, 1e-6, ld=1100, opts=_opts(mapping), ordered=True)
     o = h2_oracle.chem_step(f["T"], f["p"], f["Y"], 1e-6)
     worst, nflip, tol_err = compare(g, o)
     assert worst <= RTOL_PARITY and tol_err <= 10.0
@@ -147,7 +148,7 @@ def test_nonfinite_and_limits(gmech, h2_oracle, h2_mech, mapping):
     f["T"][4] = -5.0
     f["Y"][2, 5] = np.inf
     print(f"case: non-finite inputs, mapping {mapping}", flush=True)
-    g = _gpu_step(gmech, f, 1e-6, opts=_opts(mapping))
+    g = _gpu_step(gmech, f, 1e-6, opts=_opts(mapping), ordered=True)
     assert list(g["status"][3:6]) == [3, 3, 3]
     assert np.isnan(g["T"][3]) and g["T"][4] == -5.0 and np.isinf(g["Y"][2, 5])
     ok = np.ones(70, bool)
@@ -210,6 +211,17 @@ def test_small_mechanisms_closed_form(tmp_path, h2_mech, mapping):
     ob = oracle.Mech(pb).chem_step(fb["T"], fb["p"], fb["Y"], 2e-5)
     worst, nflip, _ = compare(g, ob)
     assert worst <= RTOL_PARITY and nflip == 0
+
+
+def test_workspace_checks(gmech):
+    import paper_2210_07094_amd as df
+    torch = _torch()
+    T = torch.full((100,), 1200.0, dtype=torch.float64, device="cuda:0")
+    Y = torch.full((9, 100), 1 / 9, dtype=torch.float64, device="cuda:0")
+    small = torch.empty(64, dtype=torch.uint8, device="cuda:0")
+    with pytest.raises(df.DfError) as e:
+        gmech.chem_step(T, T.clone(), Y, 1e-6, workspace=small)
+    assert e.value.code == -1
 
 
 def test_unsupported_species_count(tmp_path):
