@@ -35,7 +35,7 @@ extern "C" {
 #define ORC_MAX_SPECIES 128
 
 typedef struct {
-    char name[128];
+    char name[256];
     long seed;
     int E, K, M;
     double *element_mass; /* [E] g/mol */
