@@ -38,6 +38,14 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Row strides of the LDS copies of the tables and of the per-reaction records: an
+// odd number of doubles (or ints), so that the 16 lanes of a cell reading 16
+// different rows at the same column hit 16 different banks.
+constexpr int kSpS = kSpTab + 1;   // 21 doubles per species row
+constexpr int kRkS = kRxDbl + 1;   // 13 doubles per reaction row
+constexpr int kRxS = kRxInt + 1;   // 9 ints per reaction row
+__host__ __device__ constexpr int odd(int x) { return x | 1; }
+
 // per-cell LDS layout, in doubles
 struct Lay {
     int c, e, ie, h, vec, vec2, red, piv, prow, q, rec, rows, stride;
@@ -57,9 +65,10 @@ __host__ __device__ inline Lay lay(int K, int M) {
     L.piv = o, o += N;
     L.prow = o, o += 2 * N;
     L.q = o, o += M + 1;            // slot M stays zero: it pads the species lists
-    L.rec = o, o += (M + 1) * (K + 3);
+    L.rec = o, o += (M + 1) * odd(K + 3);
     L.rows = o, o += N * N;
-    L.stride = o;
+    // cells of a wave start 10 doubles (20 banks) apart modulo the 64 banks
+    L.stride = o + ((10 - o % 32) + 32) % 32;
     return L;
 }
 
@@ -74,11 +83,11 @@ __host__ __device__ inline TabLay tab_lay(int K, int M, int lmax) {
     TabLay t;
     const int Mm = M > 0 ? M : 1;
     int o = 0;
-    t.sp = o, o += K * kSpTab * 8;
-    t.rk = o, o += Mm * kRxDbl * 8;
-    t.eff = o, o += Mm * K * 8;
-    t.rx = o, o += Mm * kRxInt * 4;
-    t.spl = o, o += K * lmax * 2 * 4;
+    t.sp = o, o += K * kSpS * 8;
+    t.rk = o, o += Mm * kRkS * 8;
+    t.eff = o, o += Mm * odd(K) * 8;
+    t.rx = o, o += Mm * kRxS * 4;
+    t.spl = o, o += K * odd(2 * lmax) * 4;
     t.bytes = (o + 15) & ~15;
     return t;
 }
@@ -101,14 +110,14 @@ struct Coop {
         o.lT = log(T);
         double sYW = 0.0;
 #pragma unroll
-        for (int k = 0; k < K; ++k) sYW = fma(y[1 + k], m.sp[k * kSpTab + 1], sYW);
+        for (int k = 0; k < K; ++k) sYW = fma(y[1 + k], m.sp[k * kSpS + 1], sYW);
         o.Wbar = 1.0 / sYW;
         o.rho = p * o.Wbar * o.iT * (1.0 / kR);
         o.cref = 1e-6 * kPref * o.iT * (1.0 / kR);
         o.icref = 1.0 / o.cref;
         o.hRT = o.cpR = o.dcpR = 0.0;
         if (r >= 1 && r <= K) {
-            const double *s = m.sp + (r - 1) * kSpTab;
+            const double *s = m.sp + (r - 1) * kSpS;
             o.cpR = s[2] + T * (s[3] + T * (s[4] + T * (s[5] + T * s[6])));
             o.dcpR = s[3] + T * (s[16] + T * (s[17] + T * s[18]));
             o.hRT = s[2] + T * (s[9] + T * (s[10] + T * (s[11] + T * s[12]))) + s[7] * o.iT;
@@ -133,13 +142,13 @@ struct Coop {
         prologue(m, L, sh, r, p, y, o);
         wave_sync();
         for (int j = r; j < m.M; j += G) {
-            const int *ri = m.rx + j * kRxInt;
-            const double *rd = m.rk + j * kRxDbl;
+            const int *ri = m.rx + j * kRxS;
+            const double *rd = m.rk + j * kRkS;
             const int type = ri[0];
             const int r0 = ri[1], r1 = ri[2], r2 = ri[3], p0 = ri[4], p1 = ri[5], p2 = ri[6], dnu = ri[7];
             double Mc = 0.0;
             if (type != 0) {
-                const double *ef = m.eff + j * K;
+                const double *ef = m.eff + j * odd(K);
 #pragma unroll
                 for (int k = 0; k < K; ++k) Mc = fma(ef[k], sh[L.c + 1 + k], Mc);
             }
@@ -157,13 +166,13 @@ struct Coop {
         double f = 0.0;
         if (r >= 1 && r <= K) {
             const int k = r - 1;
-            const int *lst = m.spl + k * m.lmax * 2;
+            const int *lst = m.spl + k * odd(2 * m.lmax);
             // fixed trip count (lists are padded with the zero slot M) so the loads of
             // several entries are in flight at once
             double w = 0.0;
 #pragma unroll 4
             for (int e = 0; e < m.lmax; ++e) w = fma(double(lst[2 * e + 1]), sh[L.q + lst[2 * e]], w);
-            const double *s = m.sp + k * kSpTab;
+            const double *s = m.sp + k * kSpS;
             f = 1e6 * s[0] * w / o.rho;
             sh[L.red + r] = o.hRT * w;
             sh[L.red + N + r] = y[r] * o.cpR * s[1];
@@ -190,12 +199,12 @@ struct Coop {
         prologue(m, L, sh, r, p, y, o);
         wave_sync();
         for (int j = r; j < m.M; j += G) {
-            const int *ri = m.rx + j * kRxInt;
-            const double *rd = m.rk + j * kRxDbl;
+            const int *ri = m.rx + j * kRxS;
+            const double *rd = m.rk + j * kRkS;
             const int type = ri[0];
             const int r0 = ri[1], r1 = ri[2], r2 = ri[3], p0 = ri[4], p1 = ri[5], p2 = ri[6], dnu = ri[7];
             const double nr = rd[10], np = rd[11];
-            const double *ef = m.eff + j * K;
+            const double *ef = m.eff + j * odd(K);
             double Mc = 0.0;
             if (type != 0) {
 #pragma unroll
@@ -223,7 +232,7 @@ struct Coop {
                 Gd = dkfdM * (Pf - Pb * iKc);
                 S += Gd * Mc;
             }
-            double *rc = sh + L.rec + j * (K + 3);
+            double *rc = sh + L.rec + j * odd(K + 3);
 #pragma unroll
             for (int l = 0; l < K; ++l) rc[l] = Gd * ef[l];
             if (r0) rc[r0 - 1] += Mq * kf * c1 * c2;
@@ -242,7 +251,7 @@ struct Coop {
         for (int l = 0; l < N; ++l) Jr[l] = 0.0;
         if (r >= 1 && r <= K) {
             const int k = r - 1;
-            const int *lst = m.spl + k * m.lmax * 2;
+            const int *lst = m.spl + k * odd(2 * m.lmax);
             double A[K];
 #pragma unroll
             for (int l = 0; l < K; ++l) A[l] = 0.0;
@@ -251,20 +260,20 @@ struct Coop {
             for (int e = 0; e < m.lmax; ++e) {
                 const int j = lst[2 * e];
                 const double nu = double(lst[2 * e + 1]);
-                const double *rc = sh + L.rec + j * (K + 3);
+                const double *rc = sh + L.rec + j * odd(K + 3);
 #pragma unroll
                 for (int l = 0; l < K; ++l) A[l] = fma(nu, rc[l], A[l]);
                 wd = fma(nu, rc[K], wd);
                 dt = fma(nu, rc[K + 1], dt);
                 sq = fma(nu, rc[K + 2], sq);
             }
-            const double *s = m.sp + k * kSpTab;
+            const double *s = m.sp + k * kSpS;
             const double Wk = s[0];
             const double coef = 1e6 * Wk / o.rho;
             const double gk = coef * o.Wbar * (wd - sq);
             Jr[0] = coef * (dt + (wd - sq) * o.iT);
 #pragma unroll
-            for (int l = 0; l < K; ++l) Jr[1 + l] = (Wk * A[l] + gk) * m.sp[l * kSpTab + 1];
+            for (int l = 0; l < K; ++l) Jr[1 + l] = (Wk * A[l] + gk) * m.sp[l * kSpS + 1];
             f = coef * wd;
             const double hm = o.hRT * kR * o.T * s[1];  // J/kg
             cpm_own = o.cpR * kR * s[1];                 // J/kg/K
@@ -395,25 +404,26 @@ __global__ __launch_bounds__(64) void chem_coop_kernel(MechDev mg, int64_t n, in
     const TabLay tl = tab_lay(K, mg.M, mg.lmax);
     const int lane = threadIdx.x;
     const int r = lane & (G - 1);
+    const int64_t limit = dcount ? int64_t(*dcount) : n;
+    if (int64_t(blockIdx.x) * kCellsPerBlock >= limit) return;  // whole block idle (e.g. no fallback cells)
     // stage the tables: one copy per block, read by all its cells
     {
         auto *dst = reinterpret_cast<unsigned char *>(lds);
-        auto cp8 = [&](int off, const void *src, int bytes) {
-            const double *s8 = static_cast<const double *>(src);
+        // copy rows x cols from a dense table to an LDS table with row stride `st`
+        auto cp8 = [&](int off, const double *src, int rows, int cols, int st) {
             double *d8 = reinterpret_cast<double *>(dst + off);
-            for (int q = lane; q < bytes / 8; q += 64) d8[q] = s8[q];
+            for (int q = lane; q < rows * cols; q += 64) d8[(q / cols) * st + q % cols] = src[q];
         };
-        auto cp4 = [&](int off, const void *src, int bytes) {
-            const int *s4 = static_cast<const int *>(src);
+        auto cp4 = [&](int off, const int *src, int rows, int cols, int st) {
             int *d4 = reinterpret_cast<int *>(dst + off);
-            for (int q = lane; q < bytes / 4; q += 64) d4[q] = s4[q];
+            for (int q = lane; q < rows * cols; q += 64) d4[(q / cols) * st + q % cols] = src[q];
         };
         const int Mm = mg.M > 0 ? mg.M : 1;
-        cp8(tl.sp, mg.sp, K * kSpTab * 8);
-        cp8(tl.rk, mg.rk, Mm * kRxDbl * 8);
-        cp8(tl.eff, mg.eff, Mm * K * 8);
-        cp4(tl.rx, mg.rx, Mm * kRxInt * 4);
-        cp4(tl.spl, mg.spl, K * mg.lmax * 2 * 4);
+        cp8(tl.sp, mg.sp, K, kSpTab, kSpS);
+        cp8(tl.rk, mg.rk, Mm, kRxDbl, kRkS);
+        cp8(tl.eff, mg.eff, Mm, K, odd(K));
+        cp4(tl.rx, mg.rx, Mm, kRxInt, kRxS);
+        cp4(tl.spl, mg.spl, K, 2 * mg.lmax, odd(2 * mg.lmax));
     }
     __syncthreads();
     MechDev m = mg;
@@ -427,12 +437,11 @@ __global__ __launch_bounds__(64) void chem_coop_kernel(MechDev mg, int64_t n, in
     }
     double *sh = lds + tl.bytes / 8 + (lane / G) * L.stride;
     const int64_t cell = int64_t(blockIdx.x) * kCellsPerBlock + lane / G;
-    const int64_t limit = dcount ? int64_t(*dcount) : n;
     if (cell >= limit) return;  // the 16 lanes of a cell leave together
     const int64_t i = cidx ? int64_t(cidx[cell]) : cell;
     // the zero slot that pads the species lists
     if (r == 0) sh[L.q + m.M] = 0.0;
-    for (int c = r; c < K + 3; c += G) sh[L.rec + m.M * (K + 3) + c] = 0.0;
+    for (int c = r; c < K + 3; c += G) sh[L.rec + m.M * odd(K + 3) + c] = 0.0;
 
     double y[N];
     const double p = pres[i];
@@ -458,7 +467,7 @@ __global__ __launch_bounds__(64) void chem_coop_kernel(MechDev mg, int64_t n, in
     if (rr) {
         double sYW = 0.0;
 #pragma unroll
-        for (int k = 0; k < K; ++k) sYW += y[1 + k] * m.sp[k * kSpTab + 1];
+        for (int k = 0; k < K; ++k) sYW += y[1 + k] * m.sp[k * kSpS + 1];
         rho0 = p / (sYW * kR * y[0]);
         y0own = (r >= 1 && r <= K) ? y[r] : 0.0;
     }
