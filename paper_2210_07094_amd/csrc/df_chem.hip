@@ -548,7 +548,7 @@ df_status launch_chem_step(const MechDev &m, int64_t n, int64_t ld, double dt, c
     if (n == 0) return DF_OK;
     // mapping 0 picks 16 lanes per cell whenever a kernel is compiled for K: one sub-step
     // then takes a fraction of the latency, which bounds a stiff cell's step time
-    if (opts.mapping == 2 || (opts.mapping == 0 && chem_coop_supported(m.K)))
+    if (opts.mapping == 2 || (opts.mapping == 0 && chem_coop_supported(m)))
         return launch_chem_coop(m, n, ld, dt, p, T, Y, h_inout, rr, status, n_steps, opts, cidx, dcount, status_ok,
                                 stream);
     if (n > int64_t(64) * 0x7fffffff) return fail(DF_E_UNSUPPORTED, "df_chem_step: too many cells for one launch");

@@ -3,17 +3,23 @@
 // Same integration as the one-cell-per-lane kernel (constant-pressure reactor,
 // RODAS4, identical step-size controller), with the work of one attempt spread
 // over the lanes of the cell so that the latency of a sub-step -- which sets
-// the time of a stiff cell's hundreds of sequential sub-steps -- shrinks:
-//   * thermo: lane r (1..K) evaluates species r-1 and publishes its
-//     concentration, exp(-G/RT), exp(+G/RT) and H/RT in LDS;
-//   * rates: lane r evaluates reactions r, r+16, ...; the species lanes sum
-//     their own production rates over per-species reaction lists;
-//   * Jacobian: the reaction lanes write a dense dq/dc record per reaction to
-//     LDS, species lane r assembles row r, the T row is a column reduction;
-//   * linear algebra: row i of the iteration matrix W = I/(gamma h) - J lives in
-//     lane i; a row-distributed Gauss-Jordan elimination with partial pivoting
-//     gives W^-1, so each of the six stage solves is one N-term dot product per
-//     lane instead of a sequential substitution.
+// the time of a stiff cell's hundreds of sequential sub-steps -- shrinks.  The
+// wave issues one instruction stream for its 64 lanes, so the cost of a phase is
+// the number of instructions any lane needs; the layout keeps every lane on the
+// same short stream:
+//   * rates: lane l evaluates the reactions stored at l, l + 16, ...; ln k_f and
+//     ln k_r = ln k_f - ln K_c are dot products of per-reaction coefficient rows
+//     with functions of T (ln T, 1/T, T..T^4), so a rate constant costs one exp and
+//     no species data; only the concentrations cross lanes (one LDS exchange);
+//   * production rates: species lane k sums nu q over a fixed-length list; lane 0
+//     sums the 16 partial sums of q_j dH_j/(R T), which gives dT/dt in the same pass;
+//   * Jacobian: each reaction writes one dense record dq/dc (plus dq/dT, q and the
+//     density term) to LDS, species lane k assembles row k from its list, and lane c
+//     then reads column c and adds the T-row entry;
+//   * linear algebra: row i of W = I/(gamma h) - J lives in lane i; Gauss-Jordan
+//     elimination with partial pivoting (pivot search as a cross-lane maximum within
+//     the 16 lanes, pivot row broadcast through LDS) gives W^-1, so each stage solve is
+//     one N-term dot product per lane.
 // State vectors are replicated in the lanes of a cell; every scalar that steers
 // control flow (error norm, step size, accept/reject) is computed from the same
 // LDS data in the same order by all 16 lanes, so a cell's lanes never diverge.
@@ -26,8 +32,9 @@
 namespace df {
 namespace {
 
-constexpr int G = 16;               // lanes per cell
+constexpr int G = kCoopLanes;       // lanes per cell
 constexpr int kCellsPerBlock = 4;   // one wave64 per block
+constexpr int kMaxRPL = 4;          // reaction slots per lane instantiated (M <= 64)
 
 // Order LDS accesses of the lanes of a wave: the wave executes in lockstep and LDS
 // requests of one wave are served in order, so only the compiler must not move
@@ -38,334 +45,394 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Row strides of the LDS copies of the tables and of the per-reaction records: an
-// odd number of doubles (or ints), so that the 16 lanes of a cell reading 16
-// different rows at the same column hit 16 different banks.
-constexpr int kSpS = kSpTab + 1;   // 21 doubles per species row
-constexpr int kRkS = kRxDbl + 1;   // 13 doubles per reaction row
-constexpr int kRxS = kRxInt + 1;   // 9 ints per reaction row
+// Row strides of LDS tables read by the 16 lanes of a cell at different rows and the
+// same column: an odd number of doubles (or ints) puts the 16 reads in 16 banks.
 __host__ __device__ constexpr int odd(int x) { return x | 1; }
+constexpr int kSpS = kSpTab + 1;  // 21 doubles per species row
 
-// per-cell LDS layout, in doubles
-struct Lay {
-    int c, e, ie, h, vec, vec2, red, piv, prow, q, rec, rows, stride;
-};
-
-__host__ __device__ inline Lay lay(int K, int M) {
-    const int N = K + 1;
-    Lay L;
-    int o = 0;
-    L.c = o, o += N;
-    L.e = o, o += N;
-    L.ie = o, o += N;
-    L.h = o, o += N;
-    L.vec = o, o += N;
-    L.vec2 = o, o += N;
-    L.red = o, o += 4 * N;
-    L.piv = o, o += N;
-    L.prow = o, o += 2 * N;
-    L.q = o, o += M + 1;            // slot M stays zero: it pads the species lists
-    L.rec = o, o += (M + 1) * odd(K + 3);
-    L.rows = o, o += N * N;
-    // cells of a wave start 10 doubles (20 banks) apart modulo the 64 banks
-    L.stride = o + ((10 - o % 32) + 32) % 32;
-    return L;
-}
-
-// Mechanism tables staged in LDS once per block (the per-lane table reads of the
-// cooperative kernel are data-dependent gathers, which would otherwise be global
-// loads on the critical path of every sub-step).  Offsets in bytes.
-struct TabLay {
-    int sp, rk, eff, rx, spl, bytes;
-};
-
-__host__ __device__ inline TabLay tab_lay(int K, int M, int lmax) {
-    TabLay t;
-    const int Mm = M > 0 ? M : 1;
-    int o = 0;
-    t.sp = o, o += K * kSpS * 8;
-    t.rk = o, o += Mm * kRkS * 8;
-    t.eff = o, o += Mm * odd(K) * 8;
-    t.rx = o, o += Mm * kRxS * 4;
-    t.spl = o, o += K * odd(2 * lmax) * 4;
-    t.bytes = (o + 15) & ~15;
-    return t;
-}
-
-template <int K>
+template <int K, int RPL>
 struct Coop {
     static constexpr int N = K + 1;
+    static constexpr int MP = G * RPL;     // stored reactions incl. inert padding
+    static constexpr int RS = odd(K + 4);  // record: dq/dc_0..K-1, q, dq/dT, S, scratch
+    static constexpr int EFS = odd(K + 4);
+    static constexpr int EWS = odd(K);
+    static constexpr int LM = kCoopList;
 
-    // Mixture terms every lane needs; species thermo of the lane's own species
-    struct Own {
-        double T, iT, lT, rho, Wbar, cref, icref;
-        double hRT, cpR, dcpR;  // of the lane's species (lanes 1..K)
+    // per-cell LDS layout, in doubles
+    static constexpr int oC = 0;                 // concentrations (slot 0 = 1)
+    static constexpr int oCpt = oC + N;          // y_k cp_k/(R W_k) (slot 0 = 0)
+    static constexpr int oHm = oCpt + N;         // h_k in J/kg
+    static constexpr int oDcp = oHm + N;         // y_k dcp_k/dT in J/kg/K^2
+    static constexpr int oExt = oDcp + N;        // h_k f_k | cp_k f_k
+    static constexpr int oQ = oExt + 2 * N;      // q_0..q_{MP-1}, zero, 16 lane partial sums
+    static constexpr int oRec = oQ + MP + 1 + G; // records, row MP stays zero
+    static constexpr int oRows = oRec + (MP + 1) * RS;
+    static constexpr int oProw = oRows + N * N;  // pivot-row broadcast, two buffers
+    static constexpr int oVec = oProw + 4 * N;
+    static constexpr int oVec2 = oVec + N;
+    static constexpr int oRed = oVec2 + N;
+    static constexpr int kEnd = oRed + 3 * N;
+    // cells of a wave start 10 doubles (20 banks) apart modulo the 64 banks
+    static constexpr int kStride = kEnd + ((10 - kEnd % 32) + 32) % 32;
+
+    // mechanism tables staged in LDS once per block, offsets in bytes
+    static constexpr int tSp = 0;
+    static constexpr int tCr = tSp + K * kSpS * 8;
+    static constexpr int tEff = tCr + MP * kCrDbl * 8;
+    static constexpr int tEw = tEff + MP * EFS * 8;
+    static constexpr int tCi = tEw + MP * EWS * 8;
+    static constexpr int tBytes = (tCi + MP * kCiInt * 4 + 15) & ~15;
+    static constexpr size_t lds_bytes() { return size_t(tBytes) + size_t(kStride) * kCellsPerBlock * 8; }
+
+    struct Tab {
+        const double *sp, *cr, *eff, *ew;
+        const int *ci;
     };
 
-    __device__ __forceinline__ static void prologue(const MechDev &m, const Lay &L, double *sh, int r, double p,
-                                                    const double (&y)[N], Own &o) {
-        const double T = y[0];
-        o.T = T;
-        o.iT = 1.0 / T;
-        o.lT = log(T);
-        double sYW = 0.0;
+    // functions of the stage state shared by all lanes
+    struct St {
+        double T, iT, lT, T2, T3, T4, rho, irho, Wbar, c6;
+    };
+
+    __device__ __forceinline__ static void state(const Tab &tb, double p, double ip, const double (&y)[N], St &s) {
+        s.T = y[0];
+        s.iT = 1.0 / s.T;
+        s.lT = dlog(s.T);
+        s.T2 = s.T * s.T;
+        s.T3 = s.T2 * s.T;
+        s.T4 = s.T2 * s.T2;
+        double a0 = 0.0, a1 = 0.0;
 #pragma unroll
-        for (int k = 0; k < K; ++k) sYW = fma(y[1 + k], m.sp[k * kSpS + 1], sYW);
-        o.Wbar = 1.0 / sYW;
-        o.rho = p * o.Wbar * o.iT * (1.0 / kR);
-        o.cref = 1e-6 * kPref * o.iT * (1.0 / kR);
-        o.icref = 1.0 / o.cref;
-        o.hRT = o.cpR = o.dcpR = 0.0;
-        if (r >= 1 && r <= K) {
-            const double *s = m.sp + (r - 1) * kSpS;
-            o.cpR = s[2] + T * (s[3] + T * (s[4] + T * (s[5] + T * s[6])));
-            o.dcpR = s[3] + T * (s[16] + T * (s[17] + T * s[18]));
-            o.hRT = s[2] + T * (s[9] + T * (s[10] + T * (s[11] + T * s[12]))) + s[7] * o.iT;
-            const double sr = s[2] * o.lT + T * (s[3] + T * (s[13] + T * (s[14] + T * s[15]))) + s[8];
-            const double e = exp(sr - o.hRT);
-            sh[L.e + r] = e;
-            sh[L.ie + r] = 1.0 / e;
-            sh[L.h + r] = o.hRT;
-            sh[L.c + r] = 1e-6 * o.rho * y[r] * s[1];
-        } else if (r == 0) {
-            sh[L.c] = 1.0;
-            sh[L.e] = 1.0;
-            sh[L.ie] = 1.0;
-            sh[L.h] = 0.0;
+        for (int k = 0; k < K; k += 2) a0 = fma(y[1 + k], tb.sp[k * kSpS + 1], a0);
+#pragma unroll
+        for (int k = 1; k < K; k += 2) a1 = fma(y[1 + k], tb.sp[k * kSpS + 1], a1);
+        const double sYW = a0 + a1;
+        s.Wbar = 1.0 / sYW;
+        s.rho = p * s.Wbar * s.iT * (1.0 / kR);
+        s.irho = kR * s.T * sYW * ip;
+        s.c6 = 1e-6 * s.rho;
+    }
+
+    struct Rate {
+        double kf, kr, Mc, dH, dlf, dlr, dkfM, dkrM;
+        int type;
+        int sl[6];  // reactant and product slots (1 + species index, 0 = empty)
+    };
+
+    // rate constants of stored reaction jd (CGS); with D also d ln k/dT at fixed [M] and dk/d[M]
+    template <bool D>
+    __device__ __forceinline__ static void rate(const Tab &tb, int jd, const St &s, const double (&y)[N], Rate &o) {
+        const double *cr = tb.cr + jd * kCrDbl;
+        const int *ci = tb.ci + jd * kCiInt;
+        const int type = ci[0];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) o.sl[i] = ci[1 + i];
+        // reaction enthalpy sum_k nu_k H_k/(R T)
+        o.dH = fma(s.T, fma(s.T, fma(s.T, fma(s.T, cr[14], cr[13]), cr[12]), cr[11]), fma(cr[15], s.iT, cr[10]));
+        double lf = fma(cr[1], s.lT, fma(cr[2], s.iT, cr[0]));
+        double lr = fma(cr[4], s.lT, fma(cr[5], s.iT, cr[3]));
+        lr = fma(cr[6], s.T, lr);
+        lr = fma(cr[7], s.T2, lr);
+        lr = fma(cr[8], s.T3, lr);
+        lr = fma(cr[9], s.T4, lr);
+        double Mc = 0.0;
+        if (type != 0) {  // third-body concentration sum_k eff_k c_k
+            const double *ew = tb.ew + jd * EWS;
+            double m0 = 0.0, m1 = 0.0;
+#pragma unroll
+            for (int k = 0; k < K; k += 2) m0 = fma(ew[k], y[1 + k], m0);
+#pragma unroll
+            for (int k = 1; k < K; k += 2) m1 = fma(ew[k], y[1 + k], m1);
+            Mc = (m0 + m1) * s.c6;
+        }
+        double phi = 1.0, dphiM = 0.0, dlphi = 0.0;
+        if (type == 2) {
+            // Lindemann form times the Troe broadening factor F; ln F is folded into the two
+            // exponentials, phi = Pr/(1 + Pr)
+            const double e3 = exp(cr[20] * s.T), e1 = exp(cr[21] * s.T), e2 = exp(cr[22] * s.iT);
+            const double ek0 = exp(fma(cr[17], s.lT, fma(cr[18], s.iT, cr[16])));  // k0 / k_inf
+            const double al = cr[19];
+            const double Fc = fma(1.0 - al, e3, fma(al, e1, e2));
+            const double Pr = ek0 * Mc;
+            const double lFc = dlog(Fc) * kInvLn10;
+            const double lPr = dlog(Pr) * kInvLn10;
+            const double cc = -0.4 - 0.67 * lFc;
+            const double nn = 0.75 - 1.27 * lFc;
+            const double x = lPr + cc;
+            const double iden = 1.0 / (nn - 0.14 * x);
+            const double f1 = x * iden;
+            const double q1 = 1.0 / (1.0 + f1 * f1);
+            const double lF = lFc * q1;
+            const double iPr1 = 1.0 / (1.0 + Pr);
+            lf = fma(kLn10, lF, lf);
+            lr = fma(kLn10, lF, lr);
+            phi = Pr * iPr1;
+            if (D) {
+                const double gq = 2.0 * f1 * q1 * q1;
+                const double dlF_dlPr = -lFc * gq * nn * iden * iden;
+                const double dlF_dlFc = q1 - lFc * gq * (1.27 * x - 0.67 * nn) * iden * iden;
+                const double dFc = (1.0 - al) * cr[20] * e3 + al * cr[21] * e1 - cr[22] * s.iT * s.iT * e2;
+                const double dlnPr = (cr[17] - cr[18] * s.iT) * s.iT;
+                dlphi = (iPr1 + dlF_dlPr) * dlnPr + dlF_dlFc * dFc / Fc;
+                dphiM = ek0 * iPr1 * (iPr1 + dlF_dlPr);
+            }
+        }
+        const double Ef = exp(lf), Er = exp(lr);
+        o.kf = Ef * phi;
+        o.kr = Er * phi;
+        o.Mc = Mc;
+        o.type = type;
+        if (D) {
+            o.dlf = (cr[1] - cr[2] * s.iT) * s.iT + dlphi;
+            o.dlr = (cr[4] - cr[5] * s.iT) * s.iT + fma(s.T, fma(s.T, fma(4.0 * cr[9], s.T, 3.0 * cr[8]), 2.0 * cr[7]), cr[6]) +
+                    dlphi;
+            o.dkfM = Ef * dphiM;
+            o.dkrM = Er * dphiM;
         }
     }
 
-    // component r of f(y) in lane r (r < N)
-    __device__ __forceinline__ static double rhs(const MechDev &m, const Lay &L, double *sh, int r, double p,
-                                                 const double (&y)[N]) {
-        Own o;
-        prologue(m, L, sh, r, p, y, o);
-        wave_sync();
-        for (int j = r; j < m.M; j += G) {
-            const int *ri = m.rx + j * kRxS;
-            const double *rd = m.rk + j * kRkS;
-            const int type = ri[0];
-            const int r0 = ri[1], r1 = ri[2], r2 = ri[3], p0 = ri[4], p1 = ri[5], p2 = ri[6], dnu = ri[7];
-            double Mc = 0.0;
-            if (type != 0) {
-                const double *ef = m.eff + j * odd(K);
+    // component r of f(y) in lane r (r < N); yo = y[r]
+    __device__ static double rhs(const Tab &tb, double *sh, int r, double p, double ip, const double (&y)[N], double yo,
+                                 const int (&li)[LM], const double (&lc)[LM]) {
+        St s;
+        state(tb, p, ip, y, s);
+        const bool spl = (r >= 1 && r <= K);
+        const double *sp = tb.sp + (spl ? r - 1 : 0) * kSpS;
+        if (spl) {
+            const double cpR = fma(s.T, fma(s.T, fma(s.T, fma(s.T, sp[6], sp[5]), sp[4]), sp[3]), sp[2]);
+            sh[oC + r] = s.c6 * yo * sp[1];
+            sh[oCpt + r] = yo * cpR * sp[1];
+        }
+        Rate rt[RPL];
 #pragma unroll
-                for (int k = 0; k < K; ++k) Mc = fma(ef[k], sh[L.c + 1 + k], Mc);
-            }
-            double dl, dm;
-            const double kf = rate_constant<false>(rd, type, o.T, o.iT, o.lT, Mc, dl, dm);
-            const double iKc = sh[L.e + r0] * sh[L.e + r1] * sh[L.e + r2] * sh[L.ie + p0] * sh[L.ie + p1] *
-                               sh[L.ie + p2] * cref_pow(o.cref, o.icref, dnu);
-            const double fwd = kf * (sh[L.c + r0] * sh[L.c + r1] * sh[L.c + r2]);
-            const double rev = kf * iKc * (sh[L.c + p0] * sh[L.c + p1] * sh[L.c + p2]);
-            double q = fwd - rev;
-            if (type == 1) q *= Mc;
-            sh[L.q + j] = q;
-        }
+        for (int q = 0; q < RPL; ++q) rate<false>(tb, r + G * q, s, y, rt[q]);
         wave_sync();
-        double f = 0.0;
-        if (r >= 1 && r <= K) {
-            const int k = r - 1;
-            const int *lst = m.spl + k * odd(2 * m.lmax);
-            // fixed trip count (lists are padded with the zero slot M) so the loads of
-            // several entries are in flight at once
-            double w = 0.0;
-#pragma unroll 4
-            for (int e = 0; e < m.lmax; ++e) w = fma(double(lst[2 * e + 1]), sh[L.q + lst[2 * e]], w);
-            const double *s = m.sp + k * kSpS;
-            f = 1e6 * s[0] * w / o.rho;
-            sh[L.red + r] = o.hRT * w;
-            sh[L.red + N + r] = y[r] * o.cpR * s[1];
-        }
-        wave_sync();
-        if (r == 0) {
-            double hs = 0.0, cpm = 0.0;
+        double hs = 0.0;
 #pragma unroll
-            for (int k = 1; k <= K; ++k) {
-                hs += sh[L.red + k];
-                cpm += sh[L.red + N + k];
-            }
-            f = -hs * 1e6 * o.T / (o.rho * cpm);
+        for (int q = 0; q < RPL; ++q) {
+            const int jd = r + G * q;
+            const int *sl = rt[q].sl;
+            const double Pf = sh[oC + sl[0]] * sh[oC + sl[1]] * sh[oC + sl[2]];
+            const double Pb = sh[oC + sl[3]] * sh[oC + sl[4]] * sh[oC + sl[5]];
+            double X = rt[q].kf * Pf - rt[q].kr * Pb;
+            X = (rt[q].type == 1) ? X * rt[q].Mc : X;
+            hs = fma(X, rt[q].dH, hs);
+            sh[oQ + jd] = X;
         }
-        return f;
+        sh[oQ + MP + 1 + r] = hs;
+        double c0 = 0.0, c1 = 0.0;
+#pragma unroll
+        for (int k = 1; k <= K; k += 2) c0 += sh[oCpt + k];
+#pragma unroll
+        for (int k = 2; k <= K; k += 2) c1 += sh[oCpt + k];
+        const double icp = 1.0 / (c0 + c1);  // 1/(cp/R) per unit mass
+        wave_sync();
+        double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+        for (int e = 0; e < LM; e += 2) {
+            a0 = fma(lc[e], sh[oQ + li[e]], a0);
+            a1 = fma(lc[e + 1], sh[oQ + li[e + 1]], a1);
+        }
+        const double acc = a0 + a1;
+        // dT/dt = -sum_k h_k dY_k/dt / cp = -1e6 T sum_j q_j dH_j/(R T) / (rho cp/R)
+        return (r == 0) ? -1e6 * s.T * acc * s.irho * icp : 1e6 * sp[0] * acc * s.irho;
     }
 
-    // row r of the analytic Jacobian (lanes r < N) and f_r; see the one-lane kernel for the
-    // derivation: derivatives in concentration space, mapped to (T, Y), T row from
-    // f_T = -sum_k h_k f_k / cp
-    __device__ __forceinline__ static double jacobian(const MechDev &m, const Lay &L, double *sh, int r, double p,
-                                                      const double (&y)[N], double (&Jr)[N]) {
-        Own o;
-        prologue(m, L, sh, r, p, y, o);
+    // the analytic Jacobian J = d f/d y, row-major in LDS (rows), and f_r.  Derivatives are
+    // taken in concentration space and mapped to (T, Y); species lane k writes row k, lane c
+    // then adds the T-row entry of column c from f_T = -sum_k h_k f_k / cp.
+    __device__ static double jacobian(const Tab &tb, double *sh, int r, double p, double ip, const double (&y)[N],
+                                      double yo, const int (&li)[LM], const double (&lc)[LM]) {
+        St s;
+        state(tb, p, ip, y, s);
+        const bool spl = (r >= 1 && r <= K);
+        const double *sp = tb.sp + (spl ? r - 1 : 0) * kSpS;
+        const double T = s.T;
+        const double cpR = fma(T, fma(T, fma(T, fma(T, sp[6], sp[5]), sp[4]), sp[3]), sp[2]);
+        const double dcpR = fma(T, fma(T, fma(T, sp[18], sp[17]), sp[16]), sp[3]);
+        const double hRT = fma(T, fma(T, fma(T, fma(T, sp[12], sp[11]), sp[10]), sp[9]), sp[2]) + sp[7] * s.iT;
+        const double cpm = cpR * kR * sp[1];    // J/kg/K of the lane's species
+        const double hm = hRT * kR * T * sp[1]; // J/kg
+        if (spl) {
+            sh[oC + r] = s.c6 * yo * sp[1];
+            sh[oCpt + r] = yo * cpR * sp[1];
+            sh[oHm + r] = hm;
+            sh[oDcp + r] = yo * dcpR * kR * sp[1];
+        }
+        Rate rt[RPL];
+        int ecol[RPL][kCoopEnt], emsk[RPL][kCoopEnt];
+        double eeff[RPL][kCoopEnt], nrp[RPL][2], effr[RPL][K];
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+            const int jd = r + G * q;
+            rate<true>(tb, jd, s, y, rt[q]);
+            const int *ci = tb.ci + jd * kCiInt;
+            const double *ef = tb.eff + jd * EFS;
+#pragma unroll
+            for (int e = 0; e < kCoopEnt; ++e) {
+                ecol[q][e] = ci[7 + 2 * e];
+                emsk[q][e] = ci[8 + 2 * e];
+                eeff[q][e] = ef[ecol[q][e]];
+            }
+#pragma unroll
+            for (int l = 0; l < K; ++l) effr[q][l] = ef[l];
+            nrp[q][0] = tb.cr[jd * kCrDbl + 23];
+            nrp[q][1] = tb.cr[jd * kCrDbl + 24];
+        }
         wave_sync();
-        for (int j = r; j < m.M; j += G) {
-            const int *ri = m.rx + j * kRxS;
-            const double *rd = m.rk + j * kRkS;
-            const int type = ri[0];
-            const int r0 = ri[1], r1 = ri[2], r2 = ri[3], p0 = ri[4], p1 = ri[5], p2 = ri[6], dnu = ri[7];
-            const double nr = rd[10], np = rd[11];
-            const double *ef = m.eff + j * odd(K);
-            double Mc = 0.0;
-            if (type != 0) {
 #pragma unroll
-                for (int k = 0; k < K; ++k) Mc = fma(ef[k], sh[L.c + 1 + k], Mc);
-            }
-            double dlnkf, dkfdM;
-            const double kf = rate_constant<true>(rd, type, o.T, o.iT, o.lT, Mc, dlnkf, dkfdM);
-            const double iKc = sh[L.e + r0] * sh[L.e + r1] * sh[L.e + r2] * sh[L.ie + p0] * sh[L.ie + p1] *
-                               sh[L.ie + p2] * cref_pow(o.cref, o.icref, dnu);
-            const double kr = kf * iKc;
-            const double c0 = sh[L.c + r0], c1 = sh[L.c + r1], c2 = sh[L.c + r2];
-            const double d0 = sh[L.c + p0], d1 = sh[L.c + p1], d2 = sh[L.c + p2];
-            const double Pf = c0 * c1 * c2, Pb = d0 * d1 * d2;
-            const double fwd = kf * Pf, rev = kr * Pb, X = fwd - rev;
-            const double dlnKc =
-                (sh[L.h + p0] + sh[L.h + p1] + sh[L.h + p2] - sh[L.h + r0] - sh[L.h + r1] - sh[L.h + r2] - dnu) * o.iT;
-            const double dXdT = fwd * dlnkf - rev * (dlnkf - dlnKc);
-            const double Mq = (type == 1) ? Mc : 1.0;
-            double S = Mq * (nr * fwd - np * rev);
-            double Gd = 0.0;
-            if (type == 1) {
-                Gd = X;
-                S += Mc * X;
-            } else if (type == 2) {
-                Gd = dkfdM * (Pf - Pb * iKc);
-                S += Gd * Mc;
-            }
-            double *rc = sh + L.rec + j * odd(K + 3);
+        for (int q = 0; q < RPL; ++q) {
+            const int jd = r + G * q;
+            const Rate &k = rt[q];
+            const int *sl = k.sl;
+            const double c0 = sh[oC + sl[0]], c1 = sh[oC + sl[1]], c2 = sh[oC + sl[2]];
+            const double d0 = sh[oC + sl[3]], d1 = sh[oC + sl[4]], d2 = sh[oC + sl[5]];
+            const double P0 = c1 * c2, P1 = c0 * c2, P2 = c0 * c1;  // d Pf / d c of reactant slot i
+            const double Q0 = d1 * d2, Q1 = d0 * d2, Q2 = d0 * d1;
+            const double Pf = c0 * P0, Pb = d0 * Q0;
+            const double fwd = k.kf * Pf, rev = k.kr * Pb, X = fwd - rev;
+            const double Mq = (k.type == 1) ? k.Mc : 1.0;
+            // d q / d [M] (times d[M]/dc_l = eff_l): X for third-body rows, falloff term for Troe rows
+            const double Gd = (k.type == 1) ? X : k.dkfM * Pf - k.dkrM * Pb;
+            const double S = fma(Gd, k.Mc, Mq * (nrp[q][0] * fwd - nrp[q][1] * rev));  // sum_l c_l dq/dc_l
+            double *rc = sh + oRec + jd * RS;
 #pragma unroll
-            for (int l = 0; l < K; ++l) rc[l] = Gd * ef[l];
-            if (r0) rc[r0 - 1] += Mq * kf * c1 * c2;
-            if (r1) rc[r1 - 1] += Mq * kf * c0 * c2;
-            if (r2) rc[r2 - 1] += Mq * kf * c0 * c1;
-            if (p0) rc[p0 - 1] -= Mq * kr * d1 * d2;
-            if (p1) rc[p1 - 1] -= Mq * kr * d0 * d2;
-            if (p2) rc[p2 - 1] -= Mq * kr * d0 * d1;
+            for (int l = 0; l < K; ++l) rc[l] = Gd * effr[q][l];
+            const double fk = Mq * k.kf, rk = Mq * k.kr;
+#pragma unroll
+            for (int e = 0; e < kCoopEnt; ++e) {
+                const int msk = emsk[q][e];
+                const double dr = ((msk & 1) ? P0 : 0.0) + ((msk & 2) ? P1 : 0.0) + ((msk & 4) ? P2 : 0.0);
+                const double dp = ((msk & 8) ? Q0 : 0.0) + ((msk & 16) ? Q1 : 0.0) + ((msk & 32) ? Q2 : 0.0);
+                rc[ecol[q][e]] = fma(Gd, eeff[q][e], fk * dr - rk * dp);
+            }
             rc[K] = Mq * X;
-            rc[K + 1] = Mq * dXdT;
+            rc[K + 1] = Mq * (fwd * k.dlf - rev * k.dlr);
             rc[K + 2] = S;
         }
         wave_sync();
-        double f = 0.0, cpm_own = 0.0;
+        // species rows: sum of nu times the records of the species' reactions
+        double A[K];
 #pragma unroll
-        for (int l = 0; l < N; ++l) Jr[l] = 0.0;
-        if (r >= 1 && r <= K) {
-            const int k = r - 1;
-            const int *lst = m.spl + k * odd(2 * m.lmax);
-            double A[K];
+        for (int l = 0; l < K; ++l) A[l] = 0.0;
+        double wd = 0.0, dt = 0.0, sq = 0.0;
 #pragma unroll
-            for (int l = 0; l < K; ++l) A[l] = 0.0;
-            double sq = 0.0, dt = 0.0, wd = 0.0;
-#pragma unroll 2
-            for (int e = 0; e < m.lmax; ++e) {
-                const int j = lst[2 * e];
-                const double nu = double(lst[2 * e + 1]);
-                const double *rc = sh + L.rec + j * odd(K + 3);
+        for (int e = 0; e < LM; ++e) {
+            const int j = li[e] < MP ? li[e] : MP;  // lane 0's entries address the zero record
+            const double *rc = sh + oRec + j * RS;
+            double v[K + 3];
 #pragma unroll
-                for (int l = 0; l < K; ++l) A[l] = fma(nu, rc[l], A[l]);
-                wd = fma(nu, rc[K], wd);
-                dt = fma(nu, rc[K + 1], dt);
-                sq = fma(nu, rc[K + 2], sq);
-            }
-            const double *s = m.sp + k * kSpS;
-            const double Wk = s[0];
-            const double coef = 1e6 * Wk / o.rho;
-            const double gk = coef * o.Wbar * (wd - sq);
-            Jr[0] = coef * (dt + (wd - sq) * o.iT);
+            for (int l = 0; l < K + 3; ++l) v[l] = rc[l];
+            const double nu = lc[e];
 #pragma unroll
-            for (int l = 0; l < K; ++l) Jr[1 + l] = (Wk * A[l] + gk) * m.sp[l * kSpS + 1];
+            for (int l = 0; l < K; ++l) A[l] = fma(nu, v[l], A[l]);
+            wd = fma(nu, v[K], wd);
+            dt = fma(nu, v[K + 1], dt);
+            sq = fma(nu, v[K + 2], sq);
+        }
+        double f = 0.0;
+        if (spl) {
+            const double Wk = sp[0];
+            const double coef = 1e6 * Wk * s.irho;
+            const double gk = coef * s.Wbar * (wd - sq);
+            sh[oRows + r * N] = coef * (dt + (wd - sq) * s.iT);
+#pragma unroll
+            for (int l = 0; l < K; ++l) sh[oRows + r * N + 1 + l] = fma(Wk, A[l], gk) * tb.sp[l * kSpS + 1];
             f = coef * wd;
-            const double hm = o.hRT * kR * o.T * s[1];  // J/kg
-            cpm_own = o.cpR * kR * s[1];                 // J/kg/K
-#pragma unroll
-            for (int l = 0; l < N; ++l) sh[L.rows + k * N + l] = hm * Jr[l];
-            sh[L.red + r] = hm * f;
-            sh[L.red + N + r] = cpm_own * f;
-            sh[L.red + 2 * N + r] = y[r] * o.dcpR * kR * s[1];
-            sh[L.red + 3 * N + r] = y[r] * cpm_own;
+            sh[oExt + r] = hm * f;
+            sh[oExt + N + r] = cpm * f;
         }
         wave_sync();
-        double hf = 0.0, cf = 0.0, dcpdT = 0.0, cp = 0.0;
+        // T-row entry of column r
+        const int rc = (r < N) ? r : 0;
+        double acc = 0.0, hf = 0.0, cf = 0.0, cps = 0.0, dcpT = 0.0;
 #pragma unroll
-        for (int k = 1; k <= K; ++k) {
-            hf += sh[L.red + k];
-            cf += sh[L.red + N + k];
-            dcpdT += sh[L.red + 2 * N + k];
-            cp += sh[L.red + 3 * N + k];
+        for (int i = 1; i <= K; ++i) {
+            acc = fma(sh[oHm + i], sh[oRows + i * N + rc], acc);
+            hf += sh[oExt + i];
+            cf += sh[oExt + N + i];
+            cps += sh[oCpt + i];
+            dcpT += sh[oDcp + i];
         }
-        const double fT = -hf / cp;
-        if (r < N) {
-            double acc = 0.0;
-#pragma unroll
-            for (int k = 0; k < K; ++k) acc += sh[L.rows + k * N + r];
-            if (r == 0) acc += cf;
-            const double dcp = (r == 0) ? dcpdT : cpm_own;
-            sh[L.vec + r] = -(acc + fT * dcp) / cp;
-        }
-        wave_sync();
-        if (r == 0) {
-#pragma unroll
-            for (int l = 0; l < N; ++l) Jr[l] = sh[L.vec + l];
-            f = fT;
-        }
-        return f;
+        const double icp = 1.0 / (kR * cps);
+        const double fT = -hf * icp;
+        acc += (r == 0) ? cf : 0.0;
+        const double dcp = (r == 0) ? dcpT : cpm;
+        if (r < N) sh[oRows + r] = -fma(fT, dcp, acc) * icp;
+        return (r == 0) ? fT : f;
     }
 
-    // Gauss-Jordan inverse of W = I/(g h) - J, rows distributed over the lanes (lane i holds row i
-    // of W on entry and row i of W^-1 on return).  Partial pivoting: largest magnitude among the
-    // rows not yet used as pivots, ties to the lowest row.
-    __device__ __forceinline__ static void invert(const Lay &L, double *sh, int r, const double (&Jr)[N], double ig,
-                                                  double (&winv)[N]) {
+    // 16-lane maximum of a non-negative key (a DPP row is the 16 lanes of a cell): butterfly
+    // over quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror and row_mirror
+    template <int CTRL>
+    __device__ __forceinline__ static double dpp_max(double x) {
+        const long long b = __double_as_longlong(x);
+        const int lo = __builtin_amdgcn_update_dpp(0, int(b), CTRL, 0xf, 0xf, false);
+        const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), CTRL, 0xf, 0xf, false);
+        return fmax(x, __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32)));
+    }
+
+    // W^-1 for W = I/(g h) - J, from J row-major in LDS.  Row-distributed Gauss-Jordan
+    // elimination with partial pivoting: lane i holds row i of [W | I].  At step k the pivot is
+    // the row of largest |W_ik| among the rows not yet used (ties to the lowest row), found by a
+    // cross-lane maximum of |W_ik| whose four lowest mantissa bits are replaced by 15 - i; the
+    // pivot lane publishes its row unscaled and the other rows subtract multiples of it.  Pivot
+    // rows are scaled at the end; row i of the result goes to the row of its pivot column.  On
+    // return lane r holds row r of W^-1.
+    __device__ static void invert(double *sh, int r, double ig, double (&winv)[N]) {
+        wave_sync();
+        const int rr = (r < N) ? r : 0;
         double a[N], b[N];
 #pragma unroll
         for (int c = 0; c < N; ++c) {
-            a[c] = (r == c ? ig : 0.0) - Jr[c];
-            b[c] = (r == c) ? 1.0 : 0.0;
+            a[c] = ((c == r) ? ig : 0.0) - sh[oRows + rr * N + c];
+            b[c] = (c == r) ? 1.0 : 0.0;
         }
         bool used = (r >= N);
-        int myrow = 0;
+        int mycol = 0;
+        double myd = 1.0;
 #pragma unroll
         for (int k = 0; k < N; ++k) {
-            if (r < N) sh[L.piv + r] = used ? -1.0 : fabs(a[k]);
-            wave_sync();
-            int pk = 0;
-            double best = sh[L.piv];
-#pragma unroll
-            for (int t = 1; t < N; ++t) {
-                const double v = sh[L.piv + t];
-                const bool gt = v > best;
-                best = gt ? v : best;
-                pk = gt ? t : pk;
-            }
+            long long kb = __double_as_longlong(fabs(a[k]));
+            kb = (kb & ~15ll) | (15 - r);
+            double key = used ? -1.0 : __longlong_as_double(kb);
+            key = dpp_max<0xb1>(key);
+            key = dpp_max<0x4e>(key);
+            key = dpp_max<0x141>(key);
+            key = dpp_max<0x140>(key);
+            int pk = 15 - int(__double_as_longlong(key) & 15);
+            // a NaN column leaves no valid maximum: take any row, the step is rejected later
+            pk = (key >= 0.0 && pk < N) ? pk : 0;
+            double *pr = sh + oProw + (k & 1) * (2 * N);
             if (r == pk) {
-                const double inv = 1.0 / a[k];
 #pragma unroll
-                for (int c = 0; c < N; ++c) {
-                    a[c] *= inv;
-                    b[c] *= inv;
-                    sh[L.prow + c] = a[c];
-                    sh[L.prow + N + c] = b[c];
-                }
+                for (int c = k; c < N; ++c) pr[c] = a[c];
+#pragma unroll
+                for (int c = 0; c < N; ++c) pr[N + c] = b[c];
                 used = true;
-                myrow = k;
+                mycol = k;
+                myd = a[k];
             }
             wave_sync();
-            if (r < N && r != pk) {
-                const double fct = a[k];
+            double row[2 * N];
 #pragma unroll
-                for (int c = 0; c < N; ++c) {
-                    a[c] = fma(-fct, sh[L.prow + c], a[c]);
-                    b[c] = fma(-fct, sh[L.prow + N + c], b[c]);
-                }
-            }
+            for (int c = k; c < 2 * N; ++c) row[c] = pr[c];
+            double f = a[k] / row[k];
+            f = (r == pk || r >= N) ? 0.0 : f;
+#pragma unroll
+            for (int c = k + 1; c < N; ++c) a[c] = fma(-f, row[c], a[c]);
+#pragma unroll
+            for (int c = 0; c < N; ++c) b[c] = fma(-f, row[N + c], b[c]);
         }
-        // the lane that pivoted column k holds row k of the inverse: put the rows in order
-        if (r < N)
+        const double id = 1.0 / myd;
+        if (r < N) {
 #pragma unroll
-            for (int c = 0; c < N; ++c) sh[L.rows + myrow * N + c] = b[c];
+            for (int c = 0; c < N; ++c) sh[oRows + mycol * N + c] = b[c] * id;
+        }
         wave_sync();
 #pragma unroll
-        for (int c = 0; c < N; ++c) winv[c] = (r < N) ? sh[L.rows + r * N + c] : 0.0;
+        for (int c = 0; c < N; ++c) winv[c] = (r < N) ? sh[oRows + r * N + c] : 0.0;
     }
 
     // gather the component held by lane i (i < N) into every lane
@@ -389,7 +456,7 @@ struct Coop {
     }
 };
 
-template <int K>
+template <int K, int RPL>
 __global__ __launch_bounds__(64) void chem_coop_kernel(MechDev mg, int64_t n, int64_t ld, double dt,
                                                        const double *__restrict__ pres, double *__restrict__ Tio,
                                                        double *__restrict__ Yio, double *__restrict__ h_io,
@@ -397,11 +464,9 @@ __global__ __launch_bounds__(64) void chem_coop_kernel(MechDev mg, int64_t n, in
                                                        int32_t *__restrict__ nsteps, Opts o,
                                                        const int32_t *__restrict__ cidx,
                                                        const int32_t *__restrict__ dcount, int32_t status_ok) {
-    using C = Coop<K>;
-    constexpr int N = C::N;
+    using C = Coop<K, RPL>;
+    constexpr int N = C::N, MP = C::MP, LM = C::LM;
     extern __shared__ double lds[];
-    const Lay L = lay(K, mg.M);
-    const TabLay tl = tab_lay(K, mg.M, mg.lmax);
     const int lane = threadIdx.x;
     const int r = lane & (G - 1);
     const int64_t limit = dcount ? int64_t(*dcount) : n;
@@ -418,30 +483,42 @@ __global__ __launch_bounds__(64) void chem_coop_kernel(MechDev mg, int64_t n, in
             int *d4 = reinterpret_cast<int *>(dst + off);
             for (int q = lane; q < rows * cols; q += 64) d4[(q / cols) * st + q % cols] = src[q];
         };
-        const int Mm = mg.M > 0 ? mg.M : 1;
-        cp8(tl.sp, mg.sp, K, kSpTab, kSpS);
-        cp8(tl.rk, mg.rk, Mm, kRxDbl, kRkS);
-        cp8(tl.eff, mg.eff, Mm, K, odd(K));
-        cp4(tl.rx, mg.rx, Mm, kRxInt, kRxS);
-        cp4(tl.spl, mg.spl, K, 2 * mg.lmax, odd(2 * mg.lmax));
+        cp8(C::tSp, mg.sp, K, kSpTab, kSpS);
+        cp8(C::tCr, mg.cr, MP, kCrDbl, kCrDbl);
+        cp8(C::tEff, mg.ceff, MP, K + 4, C::EFS);
+        cp8(C::tEw, mg.ceffw, MP, K, C::EWS);
+        cp4(C::tCi, mg.ci, MP, kCiInt, kCiInt);
     }
     __syncthreads();
-    MechDev m = mg;
+    typename C::Tab tb;
     {
         auto *base = reinterpret_cast<unsigned char *>(lds);
-        m.sp = reinterpret_cast<const double *>(base + tl.sp);
-        m.rk = reinterpret_cast<const double *>(base + tl.rk);
-        m.eff = reinterpret_cast<const double *>(base + tl.eff);
-        m.rx = reinterpret_cast<const int *>(base + tl.rx);
-        m.spl = reinterpret_cast<const int *>(base + tl.spl);
+        tb.sp = reinterpret_cast<const double *>(base + C::tSp);
+        tb.cr = reinterpret_cast<const double *>(base + C::tCr);
+        tb.eff = reinterpret_cast<const double *>(base + C::tEff);
+        tb.ew = reinterpret_cast<const double *>(base + C::tEw);
+        tb.ci = reinterpret_cast<const int *>(base + C::tCi);
     }
-    double *sh = lds + tl.bytes / 8 + (lane / G) * L.stride;
+    double *sh = lds + C::tBytes / 8 + (lane / G) * C::kStride;
     const int64_t cell = int64_t(blockIdx.x) * kCellsPerBlock + lane / G;
     if (cell >= limit) return;  // the 16 lanes of a cell leave together
     const int64_t i = cidx ? int64_t(cidx[cell]) : cell;
-    // the zero slot that pads the species lists
-    if (r == 0) sh[L.q + m.M] = 0.0;
-    for (int c = r; c < K + 3; c += G) sh[L.rec + m.M * odd(K + 3) + c] = 0.0;
+    // the lane's production-rate list and the constant slots of the cell region
+    int li[LM];
+    double lc[LM];
+#pragma unroll
+    for (int e = 0; e < LM; ++e) {
+        li[e] = mg.cli[r * LM + e];
+        lc[e] = mg.clc[r * LM + e];
+    }
+    if (r == 0) {
+        sh[C::oC] = 1.0;
+        sh[C::oCpt] = 0.0;
+        sh[C::oHm] = 0.0;
+        sh[C::oDcp] = 0.0;
+        sh[C::oQ + MP] = 0.0;
+    }
+    for (int c = r; c < C::RS; c += G) sh[C::oRec + MP * C::RS + c] = 0.0;
 
     double y[N];
     const double p = pres[i];
@@ -462,14 +539,18 @@ __global__ __launch_bounds__(64) void chem_coop_kernel(MechDev mg, int64_t n, in
         if (rr && r >= 1 && r <= K) rr[(r - 1) * ld + i] = 0.0;
         return;
     }
+    const double ip = 1.0 / p;
+    double yr = 0.0;  // the lane's own component y[r]
+#pragma unroll
+    for (int c = 0; c < N; ++c) yr = (c == r) ? y[c] : yr;
     // input density and own mass fraction for rr
-    double rho0 = 0.0, y0own = 0.0;
+    double rho0 = 0.0;
+    const double y0own = (r >= 1 && r <= K) ? yr : 0.0;
     if (rr) {
         double sYW = 0.0;
 #pragma unroll
-        for (int k = 0; k < K; ++k) sYW += y[1 + k] * m.sp[k * kSpS + 1];
+        for (int k = 0; k < K; ++k) sYW += y[1 + k] * tb.sp[k * kSpS + 1];
         rho0 = p / (sYW * kR * y[0]);
-        y0own = (r >= 1 && r <= K) ? y[r] : 0.0;
     }
     const double atol = (r == 0) ? o.atol_T : o.atol_Y;
 
@@ -479,14 +560,10 @@ __global__ __launch_bounds__(64) void chem_coop_kernel(MechDev mg, int64_t n, in
     if (h_in > 0.0) {
         h = fmin(h_in, dt);
     } else {
-        const double f = C::rhs(m, L, sh, r, p, y);
-        double yr = 0.0;
-#pragma unroll
-        for (int c = 0; c < N; ++c)
-            if (c == r) yr = y[c];
+        const double f = C::rhs(tb, sh, r, p, ip, y, yr, li, lc);
         const double sc = atol + o.rtol * fabs(yr);
-        const double ny = sqrt(C::lane_sum(sh + L.red, r, (yr / sc) * (yr / sc)) / N);
-        const double nf = sqrt(C::lane_sum(sh + L.red + N, r, (f / sc) * (f / sc)) / N);
+        const double ny = sqrt(C::lane_sum(sh + C::oRed, r, (yr / sc) * (yr / sc)) / N);
+        const double nf = sqrt(C::lane_sum(sh + C::oRed + N, r, (f / sc) * (f / sc)) / N);
         h = (nf > 0.0) ? fmin(0.01 * ny / nf, dt) : dt;
     }
     if (!(h >= o.h_min)) h = o.h_min;
@@ -501,15 +578,11 @@ __global__ __launch_bounds__(64) void chem_coop_kernel(MechDev mg, int64_t n, in
         }
         const bool last = (t + h >= dt);
         const double ht = last ? dt - t : h;
-        double Jr[N], winv[N];
-        const double f0 = C::jacobian(m, L, sh, r, p, y, Jr);
-        C::invert(L, sh, r, Jr, 1.0 / (Rodas4::g * ht), winv);
+        double winv[N];
+        const double f0 = C::jacobian(tb, sh, r, p, ip, y, yr, li, lc);
+        C::invert(sh, r, 1.0 / (Rodas4::g * ht), winv);
 
-        // own components: y_r, stage vectors u_s[r]
-        double yr = 0.0;
-#pragma unroll
-        for (int c = 0; c < N; ++c)
-            if (c == r) yr = y[c];
+        // own components: stage vectors u_s[r]
         double u[6], ysr = yr;
         const double ih = 1.0 / ht;
 #pragma unroll
@@ -522,14 +595,14 @@ __global__ __launch_bounds__(64) void chem_coop_kernel(MechDev mg, int64_t n, in
 #pragma unroll
                 for (int j = 0; j < s; ++j) ysr = fma(Rodas4::a[s][j], u[j], ysr);
                 double ys[N];
-                C::gather(sh + L.vec, r, ysr, ys);
-                fs = C::rhs(m, L, sh, r, p, ys);
+                C::gather(sh + C::oVec, r, ysr, ys);
+                fs = C::rhs(tb, sh, r, p, ip, ys, ysr, li, lc);
             }
             double cu = 0.0;
 #pragma unroll
             for (int j = 0; j < s; ++j) cu = fma(Rodas4::c[s][j], u[j], cu);
             double rv[N];
-            C::gather(sh + L.vec2, r, fma(cu, ih, fs), rv);
+            C::gather(sh + C::oVec2, r, fma(cu, ih, fs), rv);
             double us = 0.0;
 #pragma unroll
             for (int c = 0; c < N; ++c) us = fma(winv[c], rv[c], us);
@@ -539,7 +612,7 @@ __global__ __launch_bounds__(64) void chem_coop_kernel(MechDev mg, int64_t n, in
         const double ynr = ysr + u[5];
         const double sc = atol + o.rtol * fmax(fabs(yr), fabs(ynr));
         const double er = (r < N) ? u[5] / sc : 0.0;
-        const double err = sqrt(C::lane_sum(sh + L.red + 2 * N, r, er * er) / N);
+        const double err = sqrt(C::lane_sum(sh + C::oRed + 2 * N, r, er * er) / N);
 
         const double fmx = prev_rej ? 1.0 : 6.0;
         double fac;
@@ -548,11 +621,12 @@ __global__ __launch_bounds__(64) void chem_coop_kernel(MechDev mg, int64_t n, in
         else if (err == 0.0)
             fac = fmx;
         else
-            fac = fmin(fmx, fmax(0.2, 0.9 * pow(err, -0.25)));
+            fac = fmin(fmx, fmax(0.2, 0.9 / sqrt(sqrt(err))));  // 0.9 err^(-1/4)
 
         if (isfinite(err) && err <= 1.0) {
             ++acc;
-            C::gather(sh + L.vec, r, ynr, y);
+            C::gather(sh + C::oVec, r, ynr, y);
+            yr = (r < N) ? ynr : 0.0;
             h_final = h;
             prev_rej = false;
             if (last) break;
@@ -578,12 +652,8 @@ __global__ __launch_bounds__(64) void chem_coop_kernel(MechDev mg, int64_t n, in
             nsteps[n + i] = rej;
         }
     } else if (r <= K) {
-        double yk = 0.0;
-#pragma unroll
-        for (int c = 1; c < N; ++c)
-            if (c == r) yk = y[c];
-        if (rr) rr[(r - 1) * ld + i] = rho0 * (yk - y0own) / dt;
-        Yio[(r - 1) * ld + i] = yk;
+        if (rr) rr[(r - 1) * ld + i] = rho0 * (yr - y0own) / dt;
+        Yio[(r - 1) * ld + i] = yr;
     }
 }
 
@@ -591,30 +661,47 @@ __global__ __launch_bounds__(64) void chem_coop_kernel(MechDev mg, int64_t n, in
 
 #define DF_COOP_SPECIES_LIST(X) X(2) X(4) X(9)
 
-bool chem_coop_supported(int K) {
+template <int K, int RPL>
+static size_t coop_lds_bytes() {
+    return Coop<K, RPL>::lds_bytes();
+}
+
+static size_t coop_lds_for(int K, int RPL) {
     switch (K) {
-#define DF_CASE(k) \
-    case k:        \
-        return true;
+#define DF_CASE(k)                                            \
+    case k:                                                   \
+        switch (RPL) {                                        \
+            case 1: return coop_lds_bytes<k, 1>();            \
+            case 2: return coop_lds_bytes<k, 2>();            \
+            case 3: return coop_lds_bytes<k, 3>();            \
+            case 4: return coop_lds_bytes<k, 4>();            \
+            default: return 0;                                \
+        }
         DF_COOP_SPECIES_LIST(DF_CASE)
 #undef DF_CASE
         default:
-            return false;
+            return 0;
     }
 }
 
-template <int K>
+constexpr size_t kCoopMaxLds = 64 * 1024;
+
+bool chem_coop_supported(const MechDev &m) {
+    if (m.RPL < 1 || m.RPL > kMaxRPL || m.lmax > kCoopList) return false;
+    const size_t b = coop_lds_for(m.K, m.RPL);
+    return b > 0 && b <= kCoopMaxLds;
+}
+
+template <int K, int RPL>
 static df_status launch_coop_k(const MechDev &m, int64_t n, int64_t ld, double dt, const double *p, double *T,
                                double *Y, double *h_inout, double *rr, int32_t *status, int32_t *n_steps,
                                const Opts &o, const int32_t *cidx, const int32_t *dcount, int32_t status_ok,
                                hipStream_t stream) {
     const int64_t blocks = (n + kCellsPerBlock - 1) / kCellsPerBlock;
     if (blocks > 0x7fffffff) return fail(DF_E_UNSUPPORTED, "chem_step: too many cells for one launch");
-    const size_t lds = size_t(tab_lay(K, m.M, m.lmax).bytes) +
-                       size_t(lay(K, m.M).stride) * kCellsPerBlock * sizeof(double);
-    if (lds > 64 * 1024) return fail(DF_E_UNSUPPORTED, "chem_step: mechanism too large for the cooperative kernel");
-    hipLaunchKernelGGL(chem_coop_kernel<K>, dim3(unsigned(blocks)), dim3(64), lds, stream, m, n, ld, dt, p, T, Y,
-                       h_inout, rr, status, n_steps, o, cidx, dcount, status_ok);
+    const size_t lds = Coop<K, RPL>::lds_bytes();
+    hipLaunchKernelGGL((chem_coop_kernel<K, RPL>), dim3(unsigned(blocks)), dim3(64), lds, stream, m, n, ld, dt, p, T,
+                       Y, h_inout, rr, status, n_steps, o, cidx, dcount, status_ok);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(DF_E_HIP, std::string("chem_step launch: ") + hipGetErrorString(e));
     return DF_OK;
@@ -624,12 +711,28 @@ df_status launch_chem_coop(const MechDev &m, int64_t n, int64_t ld, double dt, c
                            double *h_inout, double *rr, int32_t *status, int32_t *n_steps, const df_chem_opts &opts,
                            const int32_t *cidx, const int32_t *dcount, int32_t status_ok, hipStream_t stream) {
     if (n == 0) return DF_OK;
+    if (!chem_coop_supported(m))
+        return fail(DF_E_UNSUPPORTED, "chem_step: no cooperative kernel for " + std::to_string(m.K) + " species, " +
+                                          std::to_string(m.M) + " reactions (needs K in {2, 4, 9}, M <= 64, at most " +
+                                          std::to_string(kCoopList) + " reactions per species)");
     const Opts o{opts.rtol, opts.atol_T, opts.atol_Y, opts.h_min, opts.max_steps};
     switch (m.K) {
-#define DF_CASE(k)                                                                                               \
-    case k:                                                                                                      \
-        return launch_coop_k<k>(m, n, ld, dt, p, T, Y, h_inout, rr, status, n_steps, o, cidx, dcount, status_ok, \
-                                stream);
+#define DF_CASE(k)                                                                                                 \
+    case k:                                                                                                        \
+        switch (m.RPL) {                                                                                           \
+            case 1:                                                                                                \
+                return launch_coop_k<k, 1>(m, n, ld, dt, p, T, Y, h_inout, rr, status, n_steps, o, cidx, dcount,   \
+                                           status_ok, stream);                                                     \
+            case 2:                                                                                                \
+                return launch_coop_k<k, 2>(m, n, ld, dt, p, T, Y, h_inout, rr, status, n_steps, o, cidx, dcount,   \
+                                           status_ok, stream);                                                     \
+            case 3:                                                                                                \
+                return launch_coop_k<k, 3>(m, n, ld, dt, p, T, Y, h_inout, rr, status, n_steps, o, cidx, dcount,   \
+                                           status_ok, stream);                                                     \
+            default:                                                                                               \
+                return launch_coop_k<k, 4>(m, n, ld, dt, p, T, Y, h_inout, rr, status, n_steps, o, cidx, dcount,   \
+                                           status_ok, stream);                                                     \
+        }
         DF_COOP_SPECIES_LIST(DF_CASE)
 #undef DF_CASE
         default:

@@ -23,6 +23,24 @@ constexpr int kRxDbl = 12;               // doubles per reaction row
 //   the kernels keep index 0 of every per-species array as a neutral element (concentration 1,
 //   enthalpy 0, dummy accumulator) so that empty slots need no branch.
 // Reaction row (doubles): ln A, b, Ta, ln A0, b0, Ta0, alpha, 1/T***, 1/T*, T**, n_reac, n_prod.
+//
+// Tables of the cooperative kernel (16 lanes per cell; stored reaction j is evaluated by lane
+// j % 16 as its slot j / 16).  Reaction rows are padded to MP = 16 * RPL with inert rows whose
+// rate of progress is exactly zero.
+constexpr int kCoopLanes = 16;
+constexpr int kCoopList = 16;  // entries of the per-lane production-rate list
+constexpr int kCoopEnt = 6;    // Jacobian entries per reaction (distinct species)
+// coop reaction row (doubles):
+//   [0..2]   ln k_f (ln k_inf for falloff rows) over (1, ln T, 1/T)
+//   [3..9]   ln k_f - ln K_c (concentration units) over (1, ln T, 1/T, T, T^2, T^3, T^4)
+//   [10..15] reaction enthalpy sum_k nu_k H_k/(R T) over (1, T, T^2, T^3, T^4, 1/T)
+//   [16..18] ln(k_0 / k_inf) over (1, ln T, 1/T)
+//   [19] alpha, [20] -1/T***, [21] -1/T*, [22] -T**, [23] n_reac, [24] n_prod
+constexpr int kCrDbl = 25;
+// coop reaction row (ints): type, r0, r1, r2, p0, p1, p2, then kCoopEnt pairs (column, mask):
+//   column = species index of a distinct species of the reaction (K + 3 = scratch column for
+//   unused entries); mask bits 0..2 = reactant slots holding it, bits 3..5 = product slots.
+constexpr int kCiInt = 7 + 2 * kCoopEnt;
 struct MechDev {
     int K, M;
     const double *sp;   // [K][kSpTab]
@@ -30,8 +48,14 @@ struct MechDev {
     const double *rk;   // [M][kRxDbl]
     const double *eff;  // [M][K]
     const int *nu;      // [M][K] net stoichiometric coefficients nu'' - nu'
+    int RPL;            // reaction slots per lane of the cooperative kernel (MP = 16 * RPL rows)
     int lmax;           // longest per-species reaction list
-    const int *spl;     // [K][lmax][2]: (reaction j, nu_kj) for nu_kj != 0, padded with (M, 0)
+    const double *cr;    // [MP][kCrDbl]
+    const int *ci;       // [MP][kCiInt]
+    const double *ceff;  // [MP][K + 4] third-body efficiencies (zero beyond K)
+    const double *ceffw; // [MP][K] efficiencies divided by W_k
+    const int *cli;      // [16][kCoopList] per-lane list: index into the per-cell rate array
+    const double *clc;   // [16][kCoopList] per-lane list: coefficient
 };
 
 struct HostMech {
@@ -65,8 +89,9 @@ df_status launch_chem_step(const MechDev &m, int64_t n, int64_t ld, double dt, c
 
 df_status validate_chem_opts(const df_chem_opts &o);
 
-// cooperative integrator (df_chem_coop.hip): 16 lanes per cell, K <= 15
-bool chem_coop_supported(int K);
+// cooperative integrator (df_chem_coop.hip): 16 lanes per cell, for the species counts and
+// table sizes it is instantiated for
+bool chem_coop_supported(const MechDev &m);
 df_status launch_chem_coop(const MechDev &m, int64_t n, int64_t ld, double dt, const double *p, double *T, double *Y,
                            double *h_inout, double *rr, int32_t *status, int32_t *n_steps, const df_chem_opts &o,
                            const int32_t *cell_index, const int32_t *d_count, int32_t status_ok, hipStream_t stream);

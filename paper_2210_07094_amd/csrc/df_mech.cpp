@@ -1,5 +1,6 @@
 // Mechanism loading: "dfmech 1" parser, device-table packing, handle lifetime,
 // error reporting and option helpers of the C ABI.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -125,40 +126,24 @@ df_status parse_mech_file(const char *path, HostMech &m) {
     return DF_OK;
 }
 
-// Order in which the reactions are stored on the device.  The cooperative kernel
-// evaluates stored reaction j on lane j % 16, so the order spreads the costly
-// reactions (Troe falloff: seven transcendentals; third body: a K-term sum) over
-// the lanes: longest-processing-time assignment of reactions, in decreasing cost,
-// to the lane with the least work that still has a free slot.  Results do not
-// depend on the order beyond the summation order of production rates.
-static std::vector<int> lane_balanced_order(const HostMech &m, int lanes = 16) {
-    const int M = m.M;
-    std::vector<int> slots(lanes, 0);
-    for (int j = 0; j < M; ++j) ++slots[j % lanes];
-    auto cost = [&](int j) { return m.type[j] == 2 ? 8.0 : (m.type[j] == 1 ? 1.5 : 1.0); };
-    std::vector<int> byc(M);
-    for (int j = 0; j < M; ++j) byc[j] = j;
-    std::stable_sort(byc.begin(), byc.end(), [&](int a, int b) { return cost(a) > cost(b); });
-    std::vector<double> load(lanes, 0.0);
-    std::vector<std::vector<int>> assigned(lanes);
-    for (int j : byc) {
-        int best = -1;
-        for (int l = 0; l < lanes; ++l)
-            if (int(assigned[l].size()) < slots[l] && (best < 0 || load[l] < load[best])) best = l;
-        assigned[best].push_back(j);
-        load[best] += cost(j);
-    }
-    std::vector<int> order(M);
-    for (int l = 0; l < lanes; ++l)
-        for (size_t q = 0; q < assigned[l].size(); ++q) order[l + q * lanes] = assigned[l][q];
+// Order in which the reactions are stored on the device: falloff rows first, then
+// third-body rows, then the rest (stable within each type).  The cooperative kernel
+// evaluates stored reaction j on lane j % 16 in slot j / 16, and a wave runs the code
+// of a reaction type in a slot only if one of its lanes holds that type there; grouping
+// the types keeps the falloff code (several transcendentals) out of all but the first
+// slots.  Results do not depend on the order beyond the summation order of rates.
+static std::vector<int> device_order(const HostMech &m) {
+    std::vector<int> order(m.M);
+    for (int j = 0; j < m.M; ++j) order[j] = j;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return m.type[a] > m.type[b]; });
     return order;
 }
 
-// Pack the host mechanism into the device table layout described in df_internal.h.
-static void pack_tables(const HostMech &m, std::vector<double> &sp, std::vector<int> &rx, std::vector<double> &rk,
-                        std::vector<double> &eff, std::vector<int> &nu, std::vector<int> &spl, int &lmax) {
+// Tables of the one-cell-per-lane kernel (layout in df_internal.h).
+static void pack_tables(const HostMech &m, const std::vector<int> &order, std::vector<double> &sp,
+                        std::vector<int> &rx, std::vector<double> &rk, std::vector<double> &eff,
+                        std::vector<int> &nu) {
     const int K = m.K, M = m.M;
-    const std::vector<int> order = lane_balanced_order(m);
     sp.assign(size_t(K) * kSpTab, 0.0);
     for (int k = 0; k < K; ++k) {
         const double *a = &m.nasa[7 * k];
@@ -212,19 +197,113 @@ static void pack_tables(const HostMech &m, std::vector<double> &sp, std::vector<
             nu[size_t(jd) * K + k] = m.nu_p[size_t(j) * K + k] - m.nu_r[size_t(j) * K + k];
         }
     }
-    // per-species lists of the reactions that change it
+}
+
+// Tables of the cooperative kernel (layout in df_internal.h).  The equilibrium constant
+// and the reaction enthalpy are linear in the NASA-7 coefficients, so each reaction gets
+// its own coefficient rows over a few functions of T: with
+//   H_k/(R T) = a1 + a2 T/2 + a3 T^2/3 + a4 T^3/4 + a5 T^4/5 + a6/T,
+//   S_k/R     = a1 ln T + a2 T + a3 T^2/2 + a4 T^3/3 + a5 T^4/4 + a7,
+//   g_k = H_k/(R T) - S_k/R,  1/K_c = exp(sum_k nu_k g_k) (p0/(R T))^(-dnu)  [mol/cm^3],
+// ln k_r = ln k_f + ln(1/K_c) is one dot product, and so is sum_k nu_k H_k/(R T).
+struct CoopTables {
+    int RPL = 1, MP = 16, lmax = 0;
+    std::vector<double> cr, ceff, ceffw, clc;
+    std::vector<int> ci, cli;
+};
+
+static void pack_coop_tables(const HostMech &m, const std::vector<int> &order, CoopTables &t) {
+    const int K = m.K, M = m.M;
+    t.RPL = std::max(1, (M + kCoopLanes - 1) / kCoopLanes);
+    t.MP = kCoopLanes * t.RPL;
+    const int MP = t.MP, KE = K + 4;
+    t.cr.assign(size_t(MP) * kCrDbl, 0.0);
+    t.ci.assign(size_t(MP) * kCiInt, 0);
+    t.ceff.assign(size_t(MP) * KE, 0.0);
+    t.ceffw.assign(size_t(MP) * K, 0.0);
+    const double lncref0 = std::log(1e-6 * kPref / kR);  // ln(p0/(R T)) + ln T, mol/cm^3
     std::vector<std::vector<std::pair<int, int>>> lists(K);
-    for (int j = 0; j < M; ++j)
-        for (int k = 0; k < K; ++k)
-            if (nu[size_t(j) * K + k] != 0) lists[k].push_back({j, nu[size_t(j) * K + k]});
-    lmax = 1;
-    for (auto &l : lists) lmax = std::max<int>(lmax, int(l.size()));
-    spl.assign(size_t(K) * lmax * 2, 0);
-    for (int k = 0; k < K; ++k)
-        for (int e = 0; e < lmax; ++e) {
-            const bool have = e < int(lists[k].size());
-            spl[(size_t(k) * lmax + e) * 2] = have ? lists[k][e].first : M;  // padding: slot M holds zeros
-            spl[(size_t(k) * lmax + e) * 2 + 1] = have ? lists[k][e].second : 0;
+    for (int jd = 0; jd < MP; ++jd) {
+        int *ri = &t.ci[size_t(jd) * kCiInt];
+        for (int e = 0; e < kCoopEnt; ++e) ri[7 + 2 * e] = K + 3;  // unused entries: scratch column
+        if (jd >= M) continue;  // inert padding row: all coefficients zero, empty slots
+        const int j = order[jd];
+        double *cr = &t.cr[size_t(jd) * kCrDbl];
+        int nr = 0, np = 0, dnu = 0;
+        for (int k = 0; k < K; ++k) {
+            for (int c = 0; c < m.nu_r[j * K + k]; ++c) ri[1 + nr++] = 1 + k;
+            for (int c = 0; c < m.nu_p[j * K + k]; ++c) ri[4 + np++] = 1 + k;
+            dnu += m.nu_p[j * K + k] - m.nu_r[j * K + k];
+        }
+        ri[0] = m.type[j];
+        // distinct species and the slots they occupy
+        int ne = 0;
+        for (int s = 0; s < 6; ++s) {
+            const int sp = ri[1 + s];
+            if (sp == 0) continue;
+            int e = 0;
+            while (e < ne && ri[7 + 2 * e] != sp - 1) ++e;
+            if (e == ne) {
+                ri[7 + 2 * e] = sp - 1;
+                ri[8 + 2 * e] = 0;
+                ++ne;
+            }
+            ri[8 + 2 * e] |= 1 << s;
+        }
+        double snu[7] = {0, 0, 0, 0, 0, 0, 0};  // sum_k nu_k a_i
+        for (int k = 0; k < K; ++k) {
+            const int n = m.nu_p[j * K + k] - m.nu_r[j * K + k];
+            for (int i = 0; i < 7; ++i) snu[i] += n * m.nasa[7 * k + i];
+            if (n != 0) lists[k].push_back({jd, n});
+        }
+        const double lnA = std::log(m.arr[3 * j]), b = m.arr[3 * j + 1], Ta = m.arr[3 * j + 2];
+        cr[0] = lnA;
+        cr[1] = b;
+        cr[2] = -Ta;
+        cr[3] = lnA + snu[0] - snu[6] - dnu * lncref0;
+        cr[4] = b - snu[0] + dnu;
+        cr[5] = -Ta + snu[5];
+        cr[6] = -snu[1] / 2;
+        cr[7] = -snu[2] / 6;
+        cr[8] = -snu[3] / 12;
+        cr[9] = -snu[4] / 20;
+        cr[10] = snu[0];
+        cr[11] = snu[1] / 2;
+        cr[12] = snu[2] / 3;
+        cr[13] = snu[3] / 4;
+        cr[14] = snu[4] / 5;
+        cr[15] = snu[5];
+        if (m.type[j] == 2) {
+            cr[16] = std::log(m.low[3 * j]) - lnA;
+            cr[17] = m.low[3 * j + 1] - b;
+            cr[18] = -(m.low[3 * j + 2] - Ta);
+            cr[19] = m.troe[4 * j];
+            cr[20] = -1.0 / m.troe[4 * j + 1];
+            cr[21] = -1.0 / m.troe[4 * j + 2];
+            cr[22] = -m.troe[4 * j + 3];
+        }
+        cr[23] = nr;
+        cr[24] = np;
+        if (m.type[j] != 0)
+            for (int k = 0; k < K; ++k) {
+                t.ceff[size_t(jd) * KE + k] = m.eff[size_t(j) * K + k];
+                t.ceffw[size_t(jd) * K + k] = m.eff[size_t(j) * K + k] / m.W[k];
+            }
+    }
+    // per-lane lists over the per-cell rate array [q_0 .. q_{MP-1}, 0, partial sums of lanes 0..15]:
+    // species lanes 1..K sum nu q over their reactions, lane 0 sums the 16 partial enthalpy sums
+    t.lmax = 0;
+    for (auto &l : lists) t.lmax = std::max<int>(t.lmax, int(l.size()));
+    t.cli.assign(size_t(kCoopLanes) * kCoopList, MP);
+    t.clc.assign(size_t(kCoopLanes) * kCoopList, 0.0);
+    for (int e = 0; e < kCoopList; ++e) {
+        t.cli[e] = MP + 1 + e;
+        t.clc[e] = 1.0;
+    }
+    for (int k = 0; k < K && k + 1 < kCoopLanes; ++k)
+        for (int e = 0; e < std::min<int>(kCoopList, int(lists[k].size())); ++e) {
+            t.cli[size_t(k + 1) * kCoopList + e] = lists[k][e].first;
+            t.clc[size_t(k + 1) * kCoopList + e] = lists[k][e].second;
         }
 }
 
@@ -273,14 +352,27 @@ df_status df_mech_load(const char *path, int32_t device, df_mech **out) {
     df_status st = parse_mech_file(path, hm);
     if (st != DF_OK) return st;
     std::vector<double> sp, rk, eff;
-    std::vector<int> rx, nu, spl;
-    int lmax = 1;
-    pack_tables(hm, sp, rx, rk, eff, nu, spl, lmax);
-    // one allocation: [sp | rk | eff | rx | nu | spl], each part 256-byte aligned
-    auto align = [](size_t b) { return (b + 255) & ~size_t(255); };
-    size_t o_sp = 0, o_rk = align(o_sp + sp.size() * 8), o_eff = align(o_rk + rk.size() * 8),
-           o_rx = align(o_eff + eff.size() * 8), o_nu = align(o_rx + rx.size() * 4),
-           o_spl = align(o_nu + nu.size() * 4), total = align(o_spl + spl.size() * 4);
+    std::vector<int> rx, nu;
+    const std::vector<int> order = device_order(hm);
+    pack_tables(hm, order, sp, rx, rk, eff, nu);
+    CoopTables ct;
+    pack_coop_tables(hm, order, ct);
+    // one allocation holding every table, each part 256-byte aligned
+    struct Part {
+        const void *src;
+        size_t bytes, off;
+    };
+    Part parts[] = {{sp.data(), sp.size() * 8, 0},          {rk.data(), rk.size() * 8, 0},
+                    {eff.data(), eff.size() * 8, 0},        {rx.data(), rx.size() * 4, 0},
+                    {nu.data(), nu.size() * 4, 0},          {ct.cr.data(), ct.cr.size() * 8, 0},
+                    {ct.ci.data(), ct.ci.size() * 4, 0},    {ct.ceff.data(), ct.ceff.size() * 8, 0},
+                    {ct.ceffw.data(), ct.ceffw.size() * 8, 0}, {ct.cli.data(), ct.cli.size() * 4, 0},
+                    {ct.clc.data(), ct.clc.size() * 8, 0}};
+    size_t total = 0;
+    for (auto &q : parts) {
+        q.off = total;
+        total = (total + q.bytes + 255) & ~size_t(255);
+    }
     int prev = 0;
     if (hipGetDevice(&prev) != hipSuccess) return fail(DF_E_HIP, "df_mech_load: hipGetDevice failed");
     if (hipSetDevice(device) != hipSuccess) return fail(DF_E_INVALID, "df_mech_load: invalid device");
@@ -288,12 +380,7 @@ df_status df_mech_load(const char *path, int32_t device, df_mech **out) {
     hipError_t e = hipMalloc(&blob, total);
     if (e == hipSuccess) {
         std::vector<unsigned char> h(total, 0);
-        std::memcpy(h.data() + o_sp, sp.data(), sp.size() * 8);
-        std::memcpy(h.data() + o_rk, rk.data(), rk.size() * 8);
-        std::memcpy(h.data() + o_eff, eff.data(), eff.size() * 8);
-        std::memcpy(h.data() + o_rx, rx.data(), rx.size() * 4);
-        std::memcpy(h.data() + o_nu, nu.data(), nu.size() * 4);
-        std::memcpy(h.data() + o_spl, spl.data(), spl.size() * 4);
+        for (auto &q : parts) std::memcpy(h.data() + q.off, q.src, q.bytes);
         e = hipMemcpy(blob, h.data(), total, hipMemcpyHostToDevice);
     }
     (void)hipSetDevice(prev);
@@ -306,15 +393,23 @@ df_status df_mech_load(const char *path, int32_t device, df_mech **out) {
     m->host = std::move(hm);
     m->dev_blob = blob;
     auto *base = static_cast<unsigned char *>(blob);
+    auto D = [&](int i) { return reinterpret_cast<const double *>(base + parts[i].off); };
+    auto I = [&](int i) { return reinterpret_cast<const int *>(base + parts[i].off); };
     m->dev.K = m->host.K;
     m->dev.M = m->host.M;
-    m->dev.sp = reinterpret_cast<const double *>(base + o_sp);
-    m->dev.rk = reinterpret_cast<const double *>(base + o_rk);
-    m->dev.eff = reinterpret_cast<const double *>(base + o_eff);
-    m->dev.rx = reinterpret_cast<const int *>(base + o_rx);
-    m->dev.nu = reinterpret_cast<const int *>(base + o_nu);
-    m->dev.spl = reinterpret_cast<const int *>(base + o_spl);
-    m->dev.lmax = lmax;
+    m->dev.sp = D(0);
+    m->dev.rk = D(1);
+    m->dev.eff = D(2);
+    m->dev.rx = I(3);
+    m->dev.nu = I(4);
+    m->dev.RPL = ct.RPL;
+    m->dev.lmax = ct.lmax;
+    m->dev.cr = D(5);
+    m->dev.ci = I(6);
+    m->dev.ceff = D(7);
+    m->dev.ceffw = D(8);
+    m->dev.cli = I(9);
+    m->dev.clc = D(10);
     *out = m;
     return DF_OK;
 }
