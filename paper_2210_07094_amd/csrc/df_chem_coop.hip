@@ -69,7 +69,7 @@ struct Coop {
     static constexpr int oRec = oQ + MP + 1 + G; // records, row MP stays zero
     static constexpr int oRows = oRec + (MP + 1) * RS;
     static constexpr int oProw = oRows + N * N;  // pivot-row broadcast, two buffers
-    static constexpr int oVec = oProw + 4 * N;
+    static constexpr int oVec = oProw + 2 * (2 * N + 1);
     static constexpr int oVec2 = oVec + N;
     static constexpr int oRed = oVec2 + N;
     static constexpr int kEnd = oRed + 3 * N;
@@ -97,7 +97,7 @@ struct Coop {
 
     __device__ __forceinline__ static void state(const Tab &tb, double p, double ip, const double (&y)[N], St &s) {
         s.T = y[0];
-        s.iT = 1.0 / s.T;
+        s.iT = frcp(s.T);
         s.lT = dlog(s.T);
         s.T2 = s.T * s.T;
         s.T3 = s.T2 * s.T;
@@ -108,7 +108,7 @@ struct Coop {
 #pragma unroll
         for (int k = 1; k < K; k += 2) a1 = fma(y[1 + k], tb.sp[k * kSpS + 1], a1);
         const double sYW = a0 + a1;
-        s.Wbar = 1.0 / sYW;
+        s.Wbar = frcp(sYW);
         s.rho = p * s.Wbar * s.iT * (1.0 / kR);
         s.irho = kR * s.T * sYW * ip;
         s.c6 = 1e-6 * s.rho;
@@ -160,11 +160,11 @@ struct Coop {
             const double cc = -0.4 - 0.67 * lFc;
             const double nn = 0.75 - 1.27 * lFc;
             const double x = lPr + cc;
-            const double iden = 1.0 / (nn - 0.14 * x);
+            const double iden = frcp(nn - 0.14 * x);
             const double f1 = x * iden;
-            const double q1 = 1.0 / (1.0 + f1 * f1);
+            const double q1 = frcp(1.0 + f1 * f1);
             const double lF = lFc * q1;
-            const double iPr1 = 1.0 / (1.0 + Pr);
+            const double iPr1 = frcp(1.0 + Pr);
             lf = fma(kLn10, lF, lf);
             lr = fma(kLn10, lF, lr);
             phi = Pr * iPr1;
@@ -174,7 +174,7 @@ struct Coop {
                 const double dlF_dlFc = q1 - lFc * gq * (1.27 * x - 0.67 * nn) * iden * iden;
                 const double dFc = (1.0 - al) * cr[20] * e3 + al * cr[21] * e1 - cr[22] * s.iT * s.iT * e2;
                 const double dlnPr = (cr[17] - cr[18] * s.iT) * s.iT;
-                dlphi = (iPr1 + dlF_dlPr) * dlnPr + dlF_dlFc * dFc / Fc;
+                dlphi = (iPr1 + dlF_dlPr) * dlnPr + dlF_dlFc * fdiv(dFc, Fc);
                 dphiM = ek0 * iPr1 * (iPr1 + dlF_dlPr);
             }
         }
@@ -226,7 +226,7 @@ struct Coop {
         for (int k = 1; k <= K; k += 2) c0 += sh[oCpt + k];
 #pragma unroll
         for (int k = 2; k <= K; k += 2) c1 += sh[oCpt + k];
-        const double icp = 1.0 / (c0 + c1);  // 1/(cp/R) per unit mass
+        const double icp = frcp(c0 + c1);  // 1/(cp/R) per unit mass
         wave_sync();
         double a0 = 0.0, a1 = 0.0;
 #pragma unroll
@@ -355,7 +355,7 @@ struct Coop {
             cps += sh[oCpt + i];
             dcpT += sh[oDcp + i];
         }
-        const double icp = 1.0 / (kR * cps);
+        const double icp = frcp(kR * cps);
         const double fT = -hf * icp;
         acc += (r == 0) ? cf : 0.0;
         const double dcp = (r == 0) ? dcpT : cpm;
@@ -363,23 +363,24 @@ struct Coop {
         return (r == 0) ? fT : f;
     }
 
-    // 16-lane maximum of a non-negative key (a DPP row is the 16 lanes of a cell): butterfly
-    // over quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror and row_mirror
-    template <int CTRL>
-    __device__ __forceinline__ static double dpp_max(double x) {
-        const long long b = __double_as_longlong(x);
-        const int lo = __builtin_amdgcn_update_dpp(0, int(b), CTRL, 0xf, 0xf, false);
-        const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), CTRL, 0xf, 0xf, false);
-        return fmax(x, __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32)));
+    // 16-lane maximum of an int (a DPP row is the 16 lanes of a cell): butterfly over
+    // quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror and row_mirror
+    __device__ __forceinline__ static int row_max(int x) {
+        x = max(x, __builtin_amdgcn_update_dpp(0, x, 0xb1, 0xf, 0xf, false));
+        x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x4e, 0xf, 0xf, false));
+        x = max(x, __builtin_amdgcn_update_dpp(0, x, 0x141, 0xf, 0xf, false));
+        return max(x, __builtin_amdgcn_update_dpp(0, x, 0x140, 0xf, 0xf, false));
     }
 
     // W^-1 for W = I/(g h) - J, from J row-major in LDS.  Row-distributed Gauss-Jordan
     // elimination with partial pivoting: lane i holds row i of [W | I].  At step k the pivot is
-    // the row of largest |W_ik| among the rows not yet used (ties to the lowest row), found by a
-    // cross-lane maximum of |W_ik| whose four lowest mantissa bits are replaced by 15 - i; the
-    // pivot lane publishes its row unscaled and the other rows subtract multiples of it.  Pivot
-    // rows are scaled at the end; row i of the result goes to the row of its pivot column.  On
-    // return lane r holds row r of W^-1.
+    // the unused row of largest |W_ik|, found as a cross-lane maximum of a 32-bit key: the
+    // exponent and leading 16 mantissa bits of |W_ik| with the low 4 bits replaced by 15 - i,
+    // so candidates that agree to 2^-16 count as ties and go to the lowest row.  Every lane
+    // forms 1/W_ik of its own row meanwhile; the pivot lane publishes its row unscaled with
+    // that reciprocal, the other rows subtract multiples of it, and pivot rows are scaled at
+    // the end and stored as the row of their pivot column.  On return lane r holds row r of
+    // W^-1.
     __device__ static void invert(double *sh, int r, double ig, double (&winv)[N]) {
         wave_sync();
         const int rr = (r < N) ? r : 0;
@@ -391,44 +392,39 @@ struct Coop {
         }
         bool used = (r >= N);
         int mycol = 0;
-        double myd = 1.0;
+        double myinv = 1.0;
 #pragma unroll
         for (int k = 0; k < N; ++k) {
-            long long kb = __double_as_longlong(fabs(a[k]));
-            kb = (kb & ~15ll) | (15 - r);
-            double key = used ? -1.0 : __longlong_as_double(kb);
-            key = dpp_max<0xb1>(key);
-            key = dpp_max<0x4e>(key);
-            key = dpp_max<0x141>(key);
-            key = dpp_max<0x140>(key);
-            int pk = 15 - int(__double_as_longlong(key) & 15);
-            // a NaN column leaves no valid maximum: take any row, the step is rejected later
-            pk = (key >= 0.0 && pk < N) ? pk : 0;
-            double *pr = sh + oProw + (k & 1) * (2 * N);
+            const double inv = frcp(a[k]);
+            const int hi = int(__double_as_longlong(a[k]) >> 32) & 0x7fffffff;
+            const int key = row_max(used ? -1 : ((hi & ~15) | (15 - r)));
+            int pk = 15 - (key & 15);
+            pk = pk < N ? pk : N - 1;
+            double *pr = sh + oProw + (k & 1) * (2 * N + 1);
             if (r == pk) {
 #pragma unroll
-                for (int c = k; c < N; ++c) pr[c] = a[c];
+                for (int c = k + 1; c < N; ++c) pr[c] = a[c];
 #pragma unroll
                 for (int c = 0; c < N; ++c) pr[N + c] = b[c];
+                pr[k] = inv;
                 used = true;
                 mycol = k;
-                myd = a[k];
+                myinv = inv;
             }
             wave_sync();
             double row[2 * N];
 #pragma unroll
             for (int c = k; c < 2 * N; ++c) row[c] = pr[c];
-            double f = a[k] / row[k];
+            double f = a[k] * row[k];
             f = (r == pk || r >= N) ? 0.0 : f;
 #pragma unroll
             for (int c = k + 1; c < N; ++c) a[c] = fma(-f, row[c], a[c]);
 #pragma unroll
             for (int c = 0; c < N; ++c) b[c] = fma(-f, row[N + c], b[c]);
         }
-        const double id = 1.0 / myd;
         if (r < N) {
 #pragma unroll
-            for (int c = 0; c < N; ++c) sh[oRows + mycol * N + c] = b[c] * id;
+            for (int c = 0; c < N; ++c) sh[oRows + mycol * N + c] = b[c] * myinv;
         }
         wave_sync();
 #pragma unroll

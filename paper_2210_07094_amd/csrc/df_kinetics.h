@@ -32,6 +32,24 @@ struct Rodas4 {
 constexpr double kInvLn10 = 0.43429448190325182765;
 constexpr double kLn10 = 2.30258509299404568402;
 
+// Reciprocal and quotient for normal finite divisors: the hardware reciprocal estimate refined
+// by two Newton steps (each doubles the correct bits), and one residual correction of the
+// quotient; within an ulp of the rounded result, at about half the instructions of the
+// IEEE division sequence.  A zero or infinite divisor gives NaN.
+__device__ __forceinline__ double frcp(double b) {
+    double r = __builtin_amdgcn_rcp(b);
+    double e = fma(-b, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-b, r, 1.0);
+    return fma(r, e, r);
+}
+
+__device__ __forceinline__ double fdiv(double a, double b) {
+    const double r = frcp(b);
+    const double q = a * r;
+    return fma(r, fma(-b, q, a), q);
+}
+
 // Natural logarithm for positive finite x, at about half the latency of the library call:
 // x = 2^e m with m in [1/sqrt(2), sqrt(2)), ln m = 2 atanh(s) with s = (m - 1)/(m + 1), so
 // |s| <= 0.1716 and the odd power series of atanh through s^21 leaves a truncation error
@@ -46,7 +64,7 @@ __device__ __forceinline__ double dlog(double x) {
     const bool lo = m < 0.70710678118654752440;
     m = lo ? m + m : m;
     e = lo ? e - 1 : e;
-    const double s = (m - 1.0) / (m + 1.0);
+    const double s = fdiv(m - 1.0, m + 1.0);
     const double z = s * s;
     double q = 1.0 / 21;
     q = fma(q, z, 1.0 / 19);
