@@ -70,8 +70,18 @@ typedef struct {
     double atol_Y;     /* absolute tolerance on Y, default 1e-14 */
     double h_min;      /* smallest sub-step [s], default 1e-20 */
     int32_t max_steps; /* attempted sub-steps per cell and call, default 100000 */
-    int32_t mapping;   /* work mapping: 0 (default) automatic, 1 one cell per lane,
-                          2 sixteen lanes per cell (species count <= 15) */
+    int32_t mapping;   /* work mapping of the static schedule: 0 (default) automatic, 1 one cell
+                          per lane, 2 sixteen lanes per cell (species count <= 15) */
+    int32_t schedule;  /* 0 (default) or 1: static, one launch that gives each lane (or group of
+                          16 lanes) one cell; 2: persistent work queue (needs the workspace):
+                          cells sorted by estimated cost (temperature, then step length) are
+                          claimed from a device queue as lanes become free, by 16-lane groups
+                          from the stiff end; optionally some waves first take the cold cells
+                          (about 500 K and below) from the other end one cell per lane */
+    int32_t coop_blocks; /* queue schedule: waves that start as 16-lane groups; the others start
+                            one cell per lane on the cold cells and then join the groups.
+                            0 (default) all resident waves, -1 none, k > 0 k waves (capped at
+                            the resident count); df_chem_autotune picks it */
 } df_chem_opts;
 
 /* DNN options. */
@@ -107,7 +117,8 @@ df_status df_mech_load(const char *path, int32_t device, df_mech **out);
 void df_mech_free(df_mech *mech);
 df_status df_mech_info(const df_mech *mech, int32_t *n_species, int32_t *n_reactions, int32_t *n_elements);
 
-/* Bytes of device workspace df_chem_step can use for n_cells (see its `workspace`). */
+/* Bytes of device workspace df_chem_step / df_chem_step_cells can use for n_cells (see their
+   `workspace`). */
 df_status df_chem_workspace_size(const df_mech *mech, int64_t n_cells, size_t *bytes);
 
 /*
@@ -123,19 +134,55 @@ df_status df_chem_workspace_size(const df_mech *mech, int64_t n_cells, size_t *b
  *   rr          [K*ld]   out     rho0 (Y - Y0) / dt, rho0 the density at the start (nullable)
  *   cell_status [n]      out     DF_CELL_* (nullable)
  *   n_steps     [2*n]    out     accepted sub-steps at [i], rejected at [n + i] (nullable)
- *   workspace   device memory of df_chem_workspace_size bytes, 256-byte aligned (nullable).
- *               With it, cells are integrated hottest first (a counting sort on temperature),
- *               so that the stiffest cells, whose sub-steps set the time of the call, start
- *               first; without it they are taken in index order.  Results do not depend on it.
+ *   workspace   device memory of df_chem_workspace_size bytes, 256-byte aligned (nullable;
+ *               required by the queue schedule).  With it, cells are integrated hottest first
+ *               (a counting sort on temperature), so that the stiffest cells, whose sub-steps
+ *               set the time of the call, start first; without it they are taken in index
+ *               order.  Results do not depend on it beyond rounding of the first sub-step.
  *   opts        nullable = defaults
  * Cells with non-finite input are left untouched with DF_CELL_NONFINITE.
  * Errors: DF_E_INVALID (null handle/array, n < 0, ld < n, dt not > 0 and
- * finite, bad opts, workspace given but too small or misaligned),
- * DF_E_UNSUPPORTED (species count beyond the compiled kernels), DF_E_HIP.
+ * finite, bad opts, workspace given but too small or misaligned, queue schedule without
+ * workspace), DF_E_UNSUPPORTED (species count beyond the compiled kernels), DF_E_HIP.
  */
 df_status df_chem_step(const df_mech *mech, int64_t n_cells, int64_t ld, double dt, const double *p, double *T,
                        double *Y, double *h_inout, double *rr, int32_t *cell_status, int32_t *n_steps,
                        void *workspace, size_t workspace_bytes, const df_chem_opts *opts, void *hip_stream);
+
+/*
+ * df_chem_step with a step length per cell (a chemistry step of a solver with local time
+ * steps, or cells of different sub-systems in one call):
+ *   dt          [n]      in      step length per cell [s], device memory, not NULL for n > 0
+ * A cell whose dt is not positive and finite is left untouched with DF_CELL_NONFINITE; rr is
+ * divided by the cell's own dt.  With the workspace, cells are ordered hottest first and,
+ * within a temperature bucket, longest step first.  Other arguments and errors as
+ * df_chem_step.
+ */
+df_status df_chem_step_cells(const df_mech *mech, int64_t n_cells, int64_t ld, const double *dt, const double *p,
+                             double *T, double *Y, double *h_inout, double *rr, int32_t *cell_status,
+                             int32_t *n_steps, void *workspace, size_t workspace_bytes, const df_chem_opts *opts,
+                             void *hip_stream);
+
+/* Bytes of device workspace df_chem_autotune needs for n_cells. */
+df_status df_chem_autotune_workspace_size(const df_mech *mech, int64_t n_cells, size_t *bytes);
+
+/*
+ * Pick the schedule of df_chem_step / df_chem_step_cells for a workload (the cells-per-wave
+ * choice of uneven stiffness: one cell per 16 lanes, or one cell per lane for the cold cells
+ * first): time one step of each candidate -- static schedule with the cost order; queue
+ * schedule with every wave as 16-lane groups; queue schedule with a half or a quarter of the
+ * waves as 16-lane groups from the start -- on copies of the input, and write the fastest into
+ * opts->schedule and opts->coop_blocks (the other fields are kept and used for the trials).
+ *   dt, dt_cells  step length of every cell, or per cell (dt_cells [n] device, nullable)
+ *   p, T, Y       the workload, device memory, layouts as df_chem_step; not modified
+ *   workspace     device memory of df_chem_autotune_workspace_size bytes, 256-byte aligned
+ * Synchronous: returns after the trials have run on hip_stream.
+ * Errors: DF_E_INVALID (null handle/opts/array, n < 0, ld < n, dt, bad opts, workspace missing,
+ * too small or misaligned), DF_E_UNSUPPORTED, DF_E_HIP.
+ */
+df_status df_chem_autotune(const df_mech *mech, int64_t n_cells, int64_t ld, double dt, const double *dt_cells,
+                           const double *p, const double *T, const double *Y, void *workspace, size_t workspace_bytes,
+                           df_chem_opts *opts, void *hip_stream);
 
 /*
  * Load a DNN weights file ("DFDNN01", little-endian: int32 L, dims[L+1], K,

@@ -70,6 +70,9 @@ def lib():
     L.orc_chem_step.restype = C.c_int
     L.orc_chem_step.argtypes = [vp, C.c_int64, C.c_int64, C.c_double, dp, dp, dp, dp, dp, ip, ip, ip,
                                 C.POINTER(_Opts), C.c_int]
+    L.orc_chem_step_dt.restype = C.c_int
+    L.orc_chem_step_dt.argtypes = [vp, C.c_int64, C.c_int64, C.c_double, dp, dp, dp, dp, dp, dp, ip, ip, ip,
+                                   C.POINTER(_Opts), C.c_int]
     L.orc_dnn_load.restype = vp
     L.orc_dnn_load.argtypes = [C.c_char_p]
     L.orc_dnn_free.argtypes = [vp]
@@ -159,7 +162,7 @@ class Mech:
         return J
 
     def chem_step(self, T, p, Y, dt, h_inout=None, want_rr=False, opts=None, nthreads=0):
-        """Advance all cells by dt.  T[n], p[n], Y[K, n] (copied); returns dict."""
+        """Advance all cells by dt (scalar, or one value per cell).  T[n], p[n], Y[K, n] (copied); returns dict."""
         T = np.array(T, dtype=np.float64, copy=True)
         p = np.ascontiguousarray(p, dtype=np.float64)
         Y = np.array(Y, dtype=np.float64, copy=True, order="C")
@@ -171,8 +174,13 @@ class Mech:
         na = np.zeros(n, dtype=np.int32)
         nr = np.zeros(n, dtype=np.int32)
         o = opts if opts is not None else default_opts()
-        ret = lib().orc_chem_step(self._h, n, n, float(dt), _dp(p), _dp(T), _dp(Y), _dp(h), _dp(rr), _ip(st), _ip(na),
-                                  _ip(nr), C.byref(o), int(nthreads))
+        if np.ndim(dt) == 0:
+            dtv, dts = float(dt), None
+        else:
+            dtv, dts = 0.0, np.ascontiguousarray(dt, dtype=np.float64)
+            assert dts.shape == (n,)
+        ret = lib().orc_chem_step_dt(self._h, n, n, dtv, _dp(dts), _dp(p), _dp(T), _dp(Y), _dp(h), _dp(rr), _ip(st),
+                                     _ip(na), _ip(nr), C.byref(o), int(nthreads))
         if ret < 0:
             raise ValueError("oracle chem_step: bad arguments")
         return {"T": T, "Y": Y, "h": h, "rr": rr, "status": st, "n_acc": na, "n_rej": nr}

@@ -738,7 +738,17 @@ static int chem_cell(const orc_mech *m, double dt, double p, double *y, double *
 int orc_chem_step(const orc_mech *m, int64_t n, int64_t ld, double dt, const double *p, double *T, double *Y,
                   double *h_inout, double *rr, int32_t *status, int32_t *n_acc, int32_t *n_rej, const orc_opts *opts,
                   int nthreads) {
-    if (!m || n < 0 || ld < n || !(dt > 0) || !p || !T || !Y) return -1;
+    return orc_chem_step_dt(m, n, ld, dt, NULL, p, T, Y, h_inout, rr, status, n_acc, n_rej, opts, nthreads);
+}
+
+int orc_chem_step_dt(const orc_mech *m, int64_t n, int64_t ld, double dt, const double *dt_cells, const double *p,
+                     double *T, double *Y, double *h_inout, double *rr, int32_t *status, int32_t *n_acc,
+                     int32_t *n_rej, const orc_opts *opts, int nthreads) {
+    if (!m || n < 0 || ld < n || !p || !T || !Y) return -1;
+    if (!dt_cells && !(dt > 0)) return -1;
+    if (dt_cells)
+        for (int64_t i = 0; i < n; ++i)
+            if (!(dt_cells[i] > 0)) return -1;
     orc_opts o = default_opts(opts);
     int K = m->K;
     int fails = 0;
@@ -755,13 +765,14 @@ int orc_chem_step(const orc_mech *m, int64_t n, int64_t ld, double dt, const dou
         double rho0 = 0.0;
         if (rr) orc_mixture(m, T[i], p[i], Y0, NULL, &rho0, NULL, NULL);
         int acc, rej;
-        int st = chem_cell(m, dt, p[i], y, h_inout ? &h_inout[i] : NULL, &o, &acc, &rej);
+        const double dti = dt_cells ? dt_cells[i] : dt;
+        int st = chem_cell(m, dti, p[i], y, h_inout ? &h_inout[i] : NULL, &o, &acc, &rej);
         if (st != ORC_NONFINITE) {
             T[i] = y[0];
             for (int k = 0; k < K; ++k) Y[k * ld + i] = y[1 + k];
         }
         if (rr)
-            for (int k = 0; k < K; ++k) rr[k * ld + i] = rho0 * (Y[k * ld + i] - Y0[k]) / dt;
+            for (int k = 0; k < K; ++k) rr[k * ld + i] = rho0 * (Y[k * ld + i] - Y0[k]) / dti;
         if (status) status[i] = st;
         if (n_acc) n_acc[i] = acc;
         if (n_rej) n_rej[i] = rej;

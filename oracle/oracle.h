@@ -88,6 +88,10 @@ void orc_linear_fixed_step(int n, const double *A, double *y, double h, double *
 int orc_chem_step(const orc_mech *m, int64_t n, int64_t ld, double dt, const double *p, double *T, double *Y,
                   double *h_inout, double *rr, int32_t *status, int32_t *n_acc, int32_t *n_rej,
                   const orc_opts *o, int nthreads);
+/* The same with a step length per cell: dt_cells[n] (each > 0), or NULL to use dt for all. */
+int orc_chem_step_dt(const orc_mech *m, int64_t n, int64_t ld, double dt, const double *dt_cells, const double *p,
+                     double *T, double *Y, double *h_inout, double *rr, int32_t *status, int32_t *n_acc,
+                     int32_t *n_rej, const orc_opts *o, int nthreads);
 
 /* ---- DNN form ---- */
 typedef struct orc_dnn orc_dnn;

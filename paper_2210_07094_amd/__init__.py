@@ -99,12 +99,13 @@ class Mechanism:
 
     def chem_step(self, T, p, Y, dt, h=None, rr=None, status=None, n_steps=None, workspace=None, opts=None,
                   stream=None):
-        """Advance every cell by dt in place (df_chem_step).
+        """Advance every cell by dt in place (df_chem_step, or df_chem_step_cells when dt is a
+        float64 device tensor [n] of per-cell step lengths).
 
         T, p: float64 [n]; Y: float64 [K, ld] (species-major, ld >= n); optional
         h [n] (sub-step hint, in/out), rr [K, ld], status int32 [n], n_steps
-        int32 [2n], workspace uint8 (hottest-first ordering; see workspace()).
-        Asynchronous on `stream` (default: torch's current stream).
+        int32 [2n], workspace uint8 (cost ordering and the queue schedule; see
+        workspace()).  Asynchronous on `stream` (default: torch's current stream).
         """
         import torch
         n = T.numel()
@@ -113,14 +114,43 @@ class Mechanism:
             raise ValueError(f"Y must have shape [{K}, ld]")
         ld = Y.shape[1]
         dev = self.device
-        args = (self._h, n, ld, float(dt),
+        per_cell = isinstance(dt, torch.Tensor)
+        dt_arg = _ptr(dt, torch.float64, "dt", n, dev) if per_cell else float(dt)
+        args = (self._h, n, ld, dt_arg,
                 _ptr(p, torch.float64, "p", n, dev), _ptr(T, torch.float64, "T", n, dev),
                 _ptr(Y, torch.float64, "Y", K * ld, dev), _ptr(h, torch.float64, "h", n, dev),
                 _ptr(rr, torch.float64, "rr", K * ld, dev), _ptr(status, torch.int32, "status", n, dev),
                 _ptr(n_steps, torch.int32, "n_steps", 2 * n, dev),
                 _ptr(workspace, torch.uint8, "workspace", None, dev), 0 if workspace is None else workspace.numel(),
                 C.byref(opts) if opts is not None else None, _stream(stream))
-        return check(lib().df_chem_step(*args))
+        return check(lib().df_chem_step_cells(*args) if per_cell else lib().df_chem_step(*args))
+
+
+    def autotune(self, T, p, Y, dt, opts=None, stream=None) -> ChemOpts:
+        """Schedule for this workload (df_chem_autotune): times the candidates on copies of
+        (T, Y) and returns `opts` (or the defaults) with schedule and coop_blocks set."""
+        import torch
+        n = T.numel()
+        K = self.n_species
+        if Y.dim() != 2 or Y.shape[0] != K:
+            raise ValueError(f"Y must have shape [{K}, ld]")
+        ld = Y.shape[1]
+        dev = self.device
+        o = ChemOpts()
+        if opts is None:
+            lib().df_chem_default_opts(C.byref(o))
+        else:
+            C.pointer(o)[0] = opts
+        b = C.c_size_t()
+        check(lib().df_chem_autotune_workspace_size(self._h, n, C.byref(b)))
+        ws = torch.empty(max(b.value, 1), dtype=torch.uint8, device=f"cuda:{dev}")
+        per_cell = isinstance(dt, torch.Tensor)
+        check(lib().df_chem_autotune(self._h, n, ld, 0.0 if per_cell else float(dt),
+                                     _ptr(dt, torch.float64, "dt", n, dev) if per_cell else None,
+                                     _ptr(p, torch.float64, "p", n, dev), _ptr(T, torch.float64, "T", n, dev),
+                                     _ptr(Y, torch.float64, "Y", K * ld, dev), _ptr(ws, torch.uint8, "ws", None, dev),
+                                     ws.numel(), C.byref(o), _stream(stream)))
+        return o
 
 
 class DNN:

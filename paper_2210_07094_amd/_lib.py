@@ -23,7 +23,7 @@ CELL_DNN_FALLBACK = 4
 
 class ChemOpts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol_T", C.c_double), ("atol_Y", C.c_double), ("h_min", C.c_double),
-                ("max_steps", C.c_int32), ("mapping", C.c_int32)]
+                ("max_steps", C.c_int32), ("mapping", C.c_int32), ("schedule", C.c_int32), ("coop_blocks", C.c_int32)]
 
 
 class DnnOpts(C.Structure):
@@ -63,6 +63,13 @@ def lib():
     L.df_chem_workspace_size.argtypes = [vp, i64, C.POINTER(C.c_size_t)]
     L.df_chem_step.restype = i32
     L.df_chem_step.argtypes = [vp, i64, i64, d, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, C.POINTER(ChemOpts), vp]
+    L.df_chem_autotune_workspace_size.restype = i32
+    L.df_chem_autotune_workspace_size.argtypes = [vp, i64, C.POINTER(C.c_size_t)]
+    L.df_chem_autotune.restype = i32
+    L.df_chem_autotune.argtypes = [vp, i64, i64, d, vp, vp, vp, vp, vp, C.c_size_t, C.POINTER(ChemOpts), vp]
+    L.df_chem_step_cells.restype = i32
+    L.df_chem_step_cells.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t,
+                                     C.POINTER(ChemOpts), vp]
     if hasattr(L, "df_dnn_load"):
         L.df_dnn_load.restype = i32
         L.df_dnn_load.argtypes = [C.c_char_p, vp, i32, C.POINTER(vp)]

@@ -16,510 +16,24 @@
 
 #include "df_internal.h"
 #include "df_kinetics.h"
+#include "df_lane.h"
 
 namespace df {
 namespace {
 
-// Per-lane species arrays live in LDS, slot-major with a stride of one wave
-// (element k of lane l at sh[k * 64 + l]): a gather with a wave-uniform species
-// index is then a single conflict-free ds_read_b64 instead of a select chain
-// over registers.  Slot 0 of each array is the neutral element.
-constexpr int kWave = 64;
-
 template <int K>
-struct Cell {
-    static constexpr int N = K + 1;
-    // LDS slot offsets (in units of one wave-wide row of doubles).  The Jacobian-only
-    // arrays (H/RT, dq/dc) overlay the stage vectors u0..u3, which are dead while the
-    // Jacobian is formed.
-    static constexpr int kC = 0;       // concentrations, mol/cm^3; [0] = 1
-    static constexpr int kE = N;       // exp(-G_k/RT); [0] = 1
-    static constexpr int kIE = 2 * N;  // exp(+G_k/RT); [0] = 1
-    static constexpr int kU = 3 * N;   // stage vectors u0..u3 (N each)
-    static constexpr int kH = 3 * N;   // H_k/RT; [0] = 0   (Jacobian phase only)
-    static constexpr int kDQ = 4 * N;  // dq/dc scatter target (Jacobian phase only)
-    static constexpr int kULds = 4;    // stage vectors kept in LDS; the rest stay in registers
-    static constexpr int kRows = 3 * N + kULds * N;
-
-    __device__ __forceinline__ static double &at(double *sh, int slot) { return sh[slot * kWave]; }
-
-    struct Mix {
-        double T, iT, lT;
-        double rho, Wbar, cp;  // kg/m^3, kg/mol, J/kg/K
-        double cref, icref;    // p0/(RT) in mol/cm^3 and its inverse
-    };
-
-    // thermo of every species and the mixture at (T, Y); fills the LDS arrays c, e, ie
-    // (H/RT and cp/R are returned in registers: the H rows overlay stage vector u0)
-    __device__ __forceinline__ static void state(const MechDev &m, double p, const double (&y)[N], double *sh,
-                                                 Mix &s, double (&cpR)[N], double (&hRT)[N]) {
-        const double T = y[0];
-        s.T = T;
-        s.iT = 1.0 / T;
-        s.lT = log(T);
-        double sYW = 0.0, cpm = 0.0;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const double *r = m.sp + k * kSpTab;
-            const double cp = r[2] + T * (r[3] + T * (r[4] + T * (r[5] + T * r[6])));
-            const double h = r[2] + T * (r[9] + T * (r[10] + T * (r[11] + T * r[12]))) + r[7] * s.iT;
-            const double sr = r[2] * s.lT + T * (r[3] + T * (r[13] + T * (r[14] + T * r[15]))) + r[8];
-            cpR[1 + k] = cp;
-            hRT[1 + k] = h;
-            const double ek = exp(sr - h);
-            at(sh, kE + 1 + k) = ek;
-            at(sh, kIE + 1 + k) = 1.0 / ek;
-            sYW += y[1 + k] * r[1];
-            cpm += y[1 + k] * cp * r[1];
-        }
-        s.Wbar = 1.0 / sYW;
-        s.rho = p * s.Wbar * s.iT * (1.0 / kR);
-        s.cp = cpm * kR;
-        const double cfac = 1e-6 * s.rho;
-#pragma unroll
-        for (int k = 0; k < K; ++k) at(sh, kC + 1 + k) = cfac * y[1 + k] * m.sp[k * kSpTab + 1];
-        cpR[0] = 0.0;
-        hRT[0] = 0.0;
-        s.cref = 1e-6 * kPref * s.iT * (1.0 / kR);
-        s.icref = 1.0 / s.cref;
-    }
-
-    // neutral slots, written once per kernel
-    __device__ __forceinline__ static void init_lds(double *sh) {
-        at(sh, kC) = 1.0;
-        at(sh, kE) = 1.0;
-        at(sh, kIE) = 1.0;
-    }
-
-    template <bool DERIV>
-    __device__ __forceinline__ static double kforward(const double *rd, int type, const Mix &s, double Mc,
-                                                      double &dlnkf, double &dkfdM) {
-        return rate_constant<DERIV>(rd, type, s.T, s.iT, s.lT, Mc, dlnkf, dkfdM);
-    }
-
-    __device__ __forceinline__ static double third_body(const MechDev &m, int j, double *sh) {
-        const double *ef = m.eff + j * K;
-        double Mc = 0.0;
-#pragma unroll
-        for (int k = 0; k < K; ++k) Mc = fma(ef[k], at(sh, kC + 1 + k), Mc);
-        return Mc;
-    }
-
-    // f(y)
-    __device__ __forceinline__ static void rhs(const MechDev &m, double p, const double (&y)[N], double *sh,
-                                               double (&f)[N]) {
-        Mix s;
-        double cpR[N], hRT[N];
-        state(m, p, y, sh, s, cpR, hRT);
-        double wd[N];
-#pragma unroll
-        for (int k = 0; k < N; ++k) wd[k] = 0.0;
-        for (int j = 0; j < m.M; ++j) {
-            const int *ri = m.rx + j * kRxInt;
-            const double *rd = m.rk + j * kRxDbl;
-            const int type = ri[0];
-            const int r0 = ri[1], r1 = ri[2], r2 = ri[3], p0 = ri[4], p1 = ri[5], p2 = ri[6], dnu = ri[7];
-            const double Mc = (type != 0) ? third_body(m, j, sh) : 0.0;
-            double dl, dm;
-            const double kf = kforward<false>(rd, type, s, Mc, dl, dm);
-            const double iKc = at(sh, kE + r0) * at(sh, kE + r1) * at(sh, kE + r2) * at(sh, kIE + p0) *
-                               at(sh, kIE + p1) * at(sh, kIE + p2) * cref_pow(s.cref, s.icref, dnu);
-            const double fwd = kf * (at(sh, kC + r0) * at(sh, kC + r1) * at(sh, kC + r2));
-            const double rev = kf * iKc * (at(sh, kC + p0) * at(sh, kC + p1) * at(sh, kC + p2));
-            double q = fwd - rev;
-            if (type == 1) q *= Mc;
-            const int *nuj = m.nu + j * K;
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const int nk = nuj[k];
-                if (nk != 0) wd[1 + k] = fma(double(nk), q, wd[1 + k]);
-            }
-        }
-        const double fy = 1e6 / s.rho;
-        double hsum = 0.0;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            f[1 + k] = fy * m.sp[k * kSpTab] * wd[1 + k];
-            hsum = fma(hRT[1 + k], wd[1 + k], hsum);
-        }
-        f[0] = -hsum * (1e6 * kR) * s.T / (s.rho * s.cp);
-    }
-
-    // Analytic Jacobian J = df/dy and f(y).  Reaction derivatives are taken in
-    // concentration space (A_kl = sum_j nu_kj dq_j/dc_l, s_k = sum_j nu_kj sum_m c_m dq_j/dc_m,
-    // dT_k = sum_j nu_kj dq_j/dT at fixed c), then mapped to (T, Y) with
-    //   dc_m/dY_l = 1e-6 rho delta_ml / W_m - c_m Wbar / W_l,   dc_m/dT = -c_m / T.
-    // A is accumulated in the species block of J (row/column 1 + k) by rows with
-    // compile-time indices and wave-uniform stoichiometric coefficients, so J stays in
-    // registers; the T row and column are filled afterwards.
-    __device__ __forceinline__ static void jacobian(const MechDev &m, double p, const double (&y)[N], double *sh,
-                                                    double (&J)[N][N], double (&f)[N]) {
-        Mix s;
-        double cpR[N], hRT[N];
-        state(m, p, y, sh, s, cpR, hRT);
-#pragma unroll
-        for (int k = 0; k < N; ++k) at(sh, kH + k) = hRT[k];  // u0 is dead while J is formed
-        double wd[N], sq[N], dt[N];
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-            wd[k] = sq[k] = dt[k] = 0.0;
-#pragma unroll
-            for (int l = 0; l < N; ++l) J[k][l] = 0.0;
-        }
-        for (int j = 0; j < m.M; ++j) {
-            const int *ri = m.rx + j * kRxInt;
-            const double *rd = m.rk + j * kRxDbl;
-            const int type = ri[0];
-            const int r0 = ri[1], r1 = ri[2], r2 = ri[3], p0 = ri[4], p1 = ri[5], p2 = ri[6], dnu = ri[7];
-            const double nr = rd[10], np = rd[11];
-            const double Mc = (type != 0) ? third_body(m, j, sh) : 0.0;
-            double dlnkf, dkfdM;
-            const double kf = kforward<true>(rd, type, s, Mc, dlnkf, dkfdM);
-            const double iKc = at(sh, kE + r0) * at(sh, kE + r1) * at(sh, kE + r2) * at(sh, kIE + p0) *
-                               at(sh, kIE + p1) * at(sh, kIE + p2) * cref_pow(s.cref, s.icref, dnu);
-            const double kr = kf * iKc;
-            const double c0 = at(sh, kC + r0), c1 = at(sh, kC + r1), c2 = at(sh, kC + r2);
-            const double d0 = at(sh, kC + p0), d1 = at(sh, kC + p1), d2 = at(sh, kC + p2);
-            const double Pf = c0 * c1 * c2, Pb = d0 * d1 * d2;
-            const double fwd = kf * Pf, rev = kr * Pb, X = fwd - rev;
-            const double dlnKc = (at(sh, kH + p0) + at(sh, kH + p1) + at(sh, kH + p2) - at(sh, kH + r0) -
-                                  at(sh, kH + r1) - at(sh, kH + r2) - dnu) *
-                                 s.iT;
-            const double dXdT = fwd * dlnkf - rev * (dlnkf - dlnKc);
-            const double Mq = (type == 1) ? Mc : 1.0;
-            const double q = Mq * X;
-            const double dqdT = Mq * dXdT;
-            double S = Mq * (nr * fwd - np * rev);
-            double G = 0.0;  // coefficient of the dense third-body term eff_l * G
-            if (type == 1) {
-                G = X;
-                S += Mc * X;
-            } else if (type == 2) {
-                G = dkfdM * (Pf - Pb * iKc);
-                S += G * Mc;
-            }
-            // dq/dc: the slot terms (each slot's derivative is the product of the other slots)
-            // are scattered into LDS, the dense third-body term is added on the way out;
-            // slot 0 collects the empty slots
-            const double *ef = m.eff + j * K;
-#pragma unroll
-            for (int l = 0; l < N; ++l) at(sh, kDQ + l) = 0.0;
-            at(sh, kDQ + r0) += Mq * kf * c1 * c2;
-            at(sh, kDQ + r1) += Mq * kf * c0 * c2;
-            at(sh, kDQ + r2) += Mq * kf * c0 * c1;
-            at(sh, kDQ + p0) -= Mq * kr * d1 * d2;
-            at(sh, kDQ + p1) -= Mq * kr * d0 * d2;
-            at(sh, kDQ + p2) -= Mq * kr * d0 * d1;
-            double dq[K];
-#pragma unroll
-            for (int l = 0; l < K; ++l) dq[l] = (type != 0) ? fma(G, ef[l], at(sh, kDQ + 1 + l)) : at(sh, kDQ + 1 + l);
-            const int *nuj = m.nu + j * K;
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                const int nk = nuj[k];
-                if (nk == 0) continue;  // wave-uniform branch
-                const double sg = double(nk);
-#pragma unroll
-                for (int l = 0; l < K; ++l) J[1 + k][1 + l] = fma(sg, dq[l], J[1 + k][1 + l]);
-                sq[1 + k] = fma(sg, S, sq[1 + k]);
-                dt[1 + k] = fma(sg, dqdT, dt[1 + k]);
-                wd[1 + k] = fma(sg, q, wd[1 + k]);
-            }
-        }
-        // species rows
-        double hm[N], cpm[N];
-        const double fy = 1e6 / s.rho;
-        double dcpdT = 0.0, hf = 0.0;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const double *r = m.sp + k * kSpTab;
-            const double Wk = r[0];
-            const int row = 1 + k;
-            const double coef = fy * Wk;
-            const double gk = coef * s.Wbar * (wd[row] - sq[row]);
-            J[row][0] = coef * (dt[row] + (wd[row] - sq[row]) * s.iT);
-#pragma unroll
-            for (int l = 0; l < K; ++l) {
-                const double iWl = m.sp[l * kSpTab + 1];
-                J[row][1 + l] = (Wk * J[row][1 + l] + gk) * iWl;
-            }
-            f[row] = coef * wd[row];
-            hm[row] = hRT[row] * kR * s.T * r[1];  // J/kg
-            cpm[row] = cpR[row] * kR * r[1];              // J/kg/K
-            dcpdT += y[row] * (r[3] + s.T * (r[16] + s.T * (r[17] + s.T * r[18]))) * kR * r[1];
-            hf += hm[row] * f[row];
-        }
-        const double icp = 1.0 / s.cp;
-        f[0] = -hf * icp;
-        // temperature row: f_T = -sum_k h_k f_k / cp
-#pragma unroll
-        for (int l = 0; l < N; ++l) {
-            double acc = 0.0;
-#pragma unroll
-            for (int k = 1; k < N; ++k) acc += hm[k] * J[k][l];
-            const double dcp = (l == 0) ? dcpdT : cpm[l];
-            if (l == 0) {
-#pragma unroll
-                for (int k = 1; k < N; ++k) acc += cpm[k] * f[k];
-            }
-            J[0][l] = -(acc + f[0] * dcp) * icp;
-        }
-    }
-
-    // In-place LU with partial pivoting (largest magnitude, ties to the lowest row);
-    // row exchanges are done with selects so the matrix stays in registers.  The
-    // diagonal holds 1/U_kk on return.
-    __device__ __forceinline__ static void lu(double (&A)[N][N], int (&piv)[N]) {
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-            int pk = k;
-            if (k < N - 1) {
-                double best = fabs(A[k][k]);
-#pragma unroll
-                for (int r = k + 1; r < N; ++r) {
-                    const double v = fabs(A[r][k]);
-                    const bool gt = v > best;
-                    best = gt ? v : best;
-                    pk = gt ? r : pk;
-                }
-#pragma unroll
-                for (int r = k + 1; r < N; ++r) {
-                    const bool sw = (pk == r);
-#pragma unroll
-                    for (int c = 0; c < N; ++c) {
-                        const double a = A[k][c], b = A[r][c];
-                        A[k][c] = sw ? b : a;
-                        A[r][c] = sw ? a : b;
-                    }
-                }
-            }
-            piv[k] = pk;
-            const double inv = 1.0 / A[k][k];
-            A[k][k] = inv;
-#pragma unroll
-            for (int r = k + 1; r < N; ++r) {
-                const double l = A[r][k] * inv;
-                A[r][k] = l;
-#pragma unroll
-                for (int c = k + 1; c < N; ++c) A[r][c] = fma(-l, A[k][c], A[r][c]);
-            }
-        }
-    }
-
-    __device__ __forceinline__ static void solve(const double (&A)[N][N], const int (&piv)[N], double (&b)[N]) {
-#pragma unroll
-        for (int k = 0; k < N - 1; ++k) {
-#pragma unroll
-            for (int r = k + 1; r < N; ++r) {
-                const bool sw = (piv[k] == r);
-                const double a = b[k], c = b[r];
-                b[k] = sw ? c : a;
-                b[r] = sw ? a : c;
-            }
-        }
-#pragma unroll
-        for (int i = 1; i < N; ++i)
-#pragma unroll
-            for (int j = 0; j < i; ++j) b[i] = fma(-A[i][j], b[j], b[i]);
-#pragma unroll
-        for (int i = N - 1; i >= 0; --i) {
-#pragma unroll
-            for (int j = i + 1; j < N; ++j) b[i] = fma(-A[i][j], b[j], b[i]);
-            b[i] *= A[i][i];
-        }
-    }
-};
-
-template <int K>
-__global__ __launch_bounds__(kWave) void chem_step_kernel(MechDev m, int64_t n, int64_t ld, double dt,
-                                                       const double *__restrict__ pres, double *__restrict__ Tio,
-                                                       double *__restrict__ Yio, double *__restrict__ h_io,
-                                                       double *__restrict__ rr, int32_t *__restrict__ status,
-                                                       int32_t *__restrict__ nsteps, Opts o,
-                                                       const int32_t *__restrict__ cidx,
-                                                       const int32_t *__restrict__ dcount, int32_t status_ok) {
+__global__ __launch_bounds__(kWave) void chem_step_kernel(MechDev m, StepArgs a, const int32_t *__restrict__ cidx,
+                                                       const int32_t *__restrict__ dcount) {
     using C = Cell<K>;
-    constexpr int N = C::N;
     __shared__ double lds[C::kRows * kWave];
     double *sh = lds + threadIdx.x;
     C::init_lds(sh);
-    const int64_t lane = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t limit = dcount ? int64_t(*dcount) : n;
-    if (lane >= limit) return;
-    const int64_t i = cidx ? int64_t(cidx[lane]) : lane;
-
-    double y[N];
-    const double p = pres[i];
-    y[0] = Tio[i];
-#pragma unroll
-    for (int k = 0; k < K; ++k) y[1 + k] = Yio[k * ld + i];
-    bool finite = isfinite(p) && p > 0.0 && isfinite(y[0]) && y[0] > 0.0;
-#pragma unroll
-    for (int k = 0; k < K; ++k) finite = finite && isfinite(y[1 + k]);
-    if (!finite) {
-        if (status) status[i] = DF_CELL_NONFINITE;
-        if (nsteps) {
-            nsteps[i] = 0;
-            nsteps[n + i] = 0;
-        }
-        if (rr)
-            for (int k = 0; k < K; ++k) rr[k * ld + i] = 0.0;
-        return;
-    }
-    double atol[N];
-    atol[0] = o.atol_T;
-#pragma unroll
-    for (int k = 1; k < N; ++k) atol[k] = o.atol_Y;
-
-    // initial sub-step
-    double h;
-    double f0[N];
-    const double h_in = h_io ? h_io[i] : 0.0;
-    if (h_in > 0.0) {
-        h = fmin(h_in, dt);
-    } else {
-        C::rhs(m, p, y, sh, f0);
-        double ny = 0.0, nf = 0.0;
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-            const double sc = atol[k] + o.rtol * fabs(y[k]);
-            ny += (y[k] / sc) * (y[k] / sc);
-            nf += (f0[k] / sc) * (f0[k] / sc);
-        }
-        ny = sqrt(ny / N);
-        nf = sqrt(nf / N);
-        h = (nf > 0.0) ? fmin(0.01 * ny / nf, dt) : dt;
-    }
-    if (!(h >= o.h_min)) h = o.h_min;
-
-    double t = 0.0, h_final = 0.0;
-    int acc = 0, rej = 0, st = DF_CELL_OK;
-    bool prev_rej = false;
-    for (;;) {
-        if (acc + rej >= o.max_steps) {
-            st = DF_CELL_MAX_STEPS;
-            break;
-        }
-        const bool last = (t + h >= dt);
-        const double ht = last ? dt - t : h;
-        double W[N][N];
-        int piv[N];
-        C::jacobian(m, p, y, sh, W, f0);
-        const double ig = 1.0 / (Rodas4::g * ht);
-#pragma unroll
-        for (int a = 0; a < N; ++a)
-#pragma unroll
-            for (int b = 0; b < N; ++b) W[a][b] = (a == b ? ig : 0.0) - W[a][b];
-        C::lu(W, piv);
-
-        // stages; u0..u3 are kept in LDS, u4 and u5 in registers
-        double u4[N], u5[N], ys[N];
-        const double ih = 1.0 / ht;
-#pragma unroll
-        for (int sidx = 0; sidx < 6; ++sidx) {
-            double v[N];
-            if (sidx == 0) {
-#pragma unroll
-                for (int k = 0; k < N; ++k) v[k] = f0[k];
-            } else {
-#pragma unroll
-                for (int k = 0; k < N; ++k) {
-                    double w = y[k];
-#pragma unroll
-                    for (int jj = 0; jj < sidx; ++jj) {
-                        const double uj = (jj < C::kULds) ? C::at(sh, C::kU + jj * N + k) : u4[k];
-                        w = fma(Rodas4::a[sidx][jj], uj, w);
-                    }
-                    ys[k] = w;
-                }
-                C::rhs(m, p, ys, sh, v);
-#pragma unroll
-                for (int k = 0; k < N; ++k) {
-                    double w = 0.0;
-#pragma unroll
-                    for (int jj = 0; jj < sidx; ++jj) {
-                        const double uj = (jj < C::kULds) ? C::at(sh, C::kU + jj * N + k) : u4[k];
-                        w = fma(Rodas4::c[sidx][jj], uj, w);
-                    }
-                    v[k] = fma(w, ih, v[k]);
-                }
-            }
-            C::solve(W, piv, v);
-            if (sidx < C::kULds) {
-#pragma unroll
-                for (int k = 0; k < N; ++k) C::at(sh, C::kU + sidx * N + k) = v[k];
-            } else if (sidx == 4) {
-#pragma unroll
-                for (int k = 0; k < N; ++k) u4[k] = v[k];
-            } else {
-#pragma unroll
-                for (int k = 0; k < N; ++k) u5[k] = v[k];
-            }
-        }
-        // y_new = (stage-6 state) + u5 ; error = u5
-        double err = 0.0;
-        double yn[N];
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-            yn[k] = ys[k] + u5[k];
-            const double sc = atol[k] + o.rtol * fmax(fabs(y[k]), fabs(yn[k]));
-            const double r = u5[k] / sc;
-            err += r * r;
-        }
-        err = sqrt(err / N);
-
-        const double fmx = prev_rej ? 1.0 : 6.0;
-        double fac;
-        if (!isfinite(err))
-            fac = 0.2;
-        else if (err == 0.0)
-            fac = fmx;
-        else
-            fac = fmin(fmx, fmax(0.2, 0.9 * pow(err, -0.25)));
-
-        if (isfinite(err) && err <= 1.0) {
-            ++acc;
-#pragma unroll
-            for (int k = 0; k < N; ++k) y[k] = yn[k];
-            h_final = h;
-            prev_rej = false;
-            if (last) break;
-            t += ht;
-            h = ht * fac;
-        } else {
-            ++rej;
-            prev_rej = true;
-            h = ht * fac;
-            if (h < o.h_min) {
-                st = DF_CELL_H_UNDERFLOW;
-                break;
-            }
-        }
-    }
-
-    if (rr) {
-        // rr = rho0 (Y - Y0) / dt with rho0 the density of the input state, which is
-        // still in memory: read it back instead of keeping it live through the loop
-        const double T0 = Tio[i];
-        double Y0[K], sYW = 0.0;
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            Y0[k] = Yio[k * ld + i];
-            sYW += Y0[k] * m.sp[k * kSpTab + 1];
-        }
-        const double rdt = p / (sYW * kR * T0) / dt;
-#pragma unroll
-        for (int k = 0; k < K; ++k) rr[k * ld + i] = rdt * (y[1 + k] - Y0[k]);
-    }
-    Tio[i] = y[0];
-#pragma unroll
-    for (int k = 0; k < K; ++k) Yio[k * ld + i] = y[1 + k];
-    if (h_io) h_io[i] = (st == DF_CELL_OK) ? h_final : h;
-    if (status) status[i] = (st == DF_CELL_OK) ? status_ok : st;
-    if (nsteps) {
-        nsteps[i] = acc;
-        nsteps[n + i] = rej;
-    }
+    const int64_t slot = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t limit = dcount ? int64_t(*dcount) : a.n;
+    if (slot >= limit) return;
+    LaneTask<K> c;
+    bool have = lane_load<K>(a, cidx ? int64_t(cidx[slot]) : slot, c);
+    while (have) have = !lane_attempt<K>(m, a, sh, c);
 }
 
 }  // namespace
@@ -528,12 +42,10 @@ __global__ __launch_bounds__(kWave) void chem_step_kernel(MechDev m, int64_t n, 
 namespace df {
 
 template <int K>
-static df_status launch_k(const MechDev &m, int64_t n, int64_t ld, double dt, const double *p, double *T, double *Y,
-                          double *h_inout, double *rr, int32_t *status, int32_t *n_steps, const Opts &o,
-                          const int32_t *cidx, const int32_t *dcount, int32_t status_ok, hipStream_t stream) {
-    const int64_t blocks = (n + 63) / 64;
-    hipLaunchKernelGGL(chem_step_kernel<K>, dim3(unsigned(blocks)), dim3(64), 0, stream, m, n, ld, dt, p, T, Y,
-                       h_inout, rr, status, n_steps, o, cidx, dcount, status_ok);
+static df_status launch_k(const MechDev &m, const StepArgs &a, const int32_t *cidx, const int32_t *dcount,
+                          hipStream_t stream) {
+    const int64_t blocks = (a.n + 63) / 64;
+    hipLaunchKernelGGL(chem_step_kernel<K>, dim3(unsigned(blocks)), dim3(64), 0, stream, m, a, cidx, dcount);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(DF_E_HIP, std::string("chem_step launch: ") + hipGetErrorString(e));
     return DF_OK;
@@ -542,21 +54,18 @@ static df_status launch_k(const MechDev &m, int64_t n, int64_t ld, double dt, co
 // species counts with a compiled per-lane kernel
 #define DF_CHEM_SPECIES_LIST(X) X(2) X(4) X(9)
 
-df_status launch_chem_step(const MechDev &m, int64_t n, int64_t ld, double dt, const double *p, double *T, double *Y,
-                           double *h_inout, double *rr, int32_t *status, int32_t *n_steps, const df_chem_opts &opts,
-                           const int32_t *cidx, const int32_t *dcount, int32_t status_ok, hipStream_t stream) {
-    if (n == 0) return DF_OK;
+df_status launch_chem_step(const MechDev &m, const StepArgs &a, int mapping, const int32_t *cidx,
+                           const int32_t *dcount, hipStream_t stream) {
+    if (a.n == 0) return DF_OK;
     // mapping 0 picks 16 lanes per cell whenever a kernel is compiled for K: one sub-step
     // then takes a fraction of the latency, which bounds a stiff cell's step time
-    if (opts.mapping == 2 || (opts.mapping == 0 && chem_coop_supported(m)))
-        return launch_chem_coop(m, n, ld, dt, p, T, Y, h_inout, rr, status, n_steps, opts, cidx, dcount, status_ok,
-                                stream);
-    if (n > int64_t(64) * 0x7fffffff) return fail(DF_E_UNSUPPORTED, "df_chem_step: too many cells for one launch");
-    const Opts o{opts.rtol, opts.atol_T, opts.atol_Y, opts.h_min, opts.max_steps};
+    if (mapping == 2 || (mapping == 0 && chem_coop_supported(m)))
+        return launch_chem_coop(m, a, CellQueue{cidx, dcount, nullptr, nullptr, nullptr, 0}, stream);
+    if (a.n > int64_t(64) * 0x7fffffff) return fail(DF_E_UNSUPPORTED, "df_chem_step: too many cells for one launch");
     switch (m.K) {
 #define DF_CASE(k) \
     case k:        \
-        return launch_k<k>(m, n, ld, dt, p, T, Y, h_inout, rr, status, n_steps, o, cidx, dcount, status_ok, stream);
+        return launch_k<k>(m, a, cidx, dcount, stream);
         DF_CHEM_SPECIES_LIST(DF_CASE)
 #undef DF_CASE
         default:
@@ -564,54 +73,82 @@ df_status launch_chem_step(const MechDev &m, int64_t n, int64_t ld, double dt, c
     }
 }
 
-// ---- hottest-first ordering: counting sort of the cells on temperature buckets ----
+// ---- cost ordering: counting sort of the cells on (temperature, step length) buckets ----
 namespace {
 
-constexpr int kBuckets = 256;
+constexpr int kTB = 256, kDB = 16;      // temperature and step-length buckets
+constexpr int kBuckets = kTB * kDB;     // bucket = tb * kDB + db; bucket 0 = hottest, longest step
 constexpr double kTlo = 200.0, kThi = 3500.0;
 constexpr int kOrdThreads = 256;
+// cells of the buckets at or below about this temperature form the cold tail of the queue,
+// the only cells one-cell-per-lane waves take (they need about one sub-step each)
+constexpr double kTcold = 500.0;
 
-// bucket 0 holds the hottest cells; non-finite temperatures go last
+// hottest first; non-finite temperatures go last
 __device__ __forceinline__ int t_bucket(double T) {
-    if (!(T == T) || !isfinite(T)) return kBuckets - 1;
-    const double x = (kThi - T) * (double(kBuckets) / (kThi - kTlo));
-    const int b = int(fmin(fmax(x, 0.0), double(kBuckets - 1)));
-    return b;
+    if (!(T == T) || !isfinite(T)) return kTB - 1;
+    const double x = (kThi - T) * (double(kTB) / (kThi - kTlo));
+    return int(fmin(fmax(x, 0.0), double(kTB - 1)));
 }
 
-__global__ __launch_bounds__(kOrdThreads) void order_zero(int32_t *cnt) {
-    const int t = threadIdx.x;
-    for (int b = t; b < 2 * kBuckets; b += kOrdThreads) cnt[b] = 0;
+// longest step first: four buckets per decade below 1 ms; non-positive or non-finite last
+__device__ __forceinline__ int d_bucket(double dt) {
+    if (!(dt > 0.0) || !isfinite(dt)) return kDB - 1;
+    const double x = 4.0 * log10(1e-3 / dt);
+    return int(fmin(fmax(x, 0.0), double(kDB - 1)));
 }
 
-__global__ __launch_bounds__(kOrdThreads) void order_hist(const double *__restrict__ T, int64_t n,
-                                                          int32_t *__restrict__ cnt) {
+__device__ __forceinline__ int cost_bucket(const double *T, const double *dts, double dt, int64_t i) {
+    return t_bucket(T[i]) * kDB + d_bucket(dts ? dts[i] : dt);
+}
+
+// zero the bucket counts and the queue counter
+__global__ __launch_bounds__(kOrdThreads) void order_zero(int32_t *cnt, unsigned long long *ctr) {
+    for (int b = threadIdx.x; b < 2 * kBuckets; b += kOrdThreads) cnt[b] = 0;
+    if (threadIdx.x == 0) *ctr = 0ull;
+}
+
+__global__ __launch_bounds__(kOrdThreads) void order_hist(const double *__restrict__ T, const double *__restrict__ dts,
+                                                          double dt, int64_t n, int32_t *__restrict__ cnt) {
     __shared__ int32_t loc[kBuckets];
     for (int b = threadIdx.x; b < kBuckets; b += kOrdThreads) loc[b] = 0;
     __syncthreads();
     const int64_t i = int64_t(blockIdx.x) * kOrdThreads + threadIdx.x;
-    if (i < n) atomicAdd(&loc[t_bucket(T[i])], 1);
+    if (i < n) atomicAdd(&loc[cost_bucket(T, dts, dt, i)], 1);
     __syncthreads();
     for (int b = threadIdx.x; b < kBuckets; b += kOrdThreads)
         if (loc[b]) atomicAdd(&cnt[b], loc[b]);
 }
 
-// exclusive scan of the bucket counts into the second half of cnt (one block)
+// exclusive scan of the bucket counts into the second half of cnt (one block: each thread
+// scans a run of kBuckets / kOrdThreads buckets, then the run totals are scanned); also the
+// number of cells in the cold buckets, at cnt[2 * kBuckets]
 __global__ __launch_bounds__(kOrdThreads) void order_scan(int32_t *cnt) {
-    __shared__ int32_t v[kBuckets];
+    constexpr int R = kBuckets / kOrdThreads;
+    __shared__ int32_t v[kOrdThreads];
     const int t = threadIdx.x;
-    v[t] = cnt[t];
+    int32_t run = 0;
+    for (int q = 0; q < R; ++q) run += cnt[t * R + q];
+    v[t] = run;
     __syncthreads();
-    for (int off = 1; off < kBuckets; off <<= 1) {
-        const int a = (t >= off) ? v[t - off] : 0;
+    for (int off = 1; off < kOrdThreads; off <<= 1) {
+        const int32_t add = (t >= off) ? v[t - off] : 0;
         __syncthreads();
-        v[t] += a;
+        v[t] += add;
         __syncthreads();
     }
-    cnt[kBuckets + t] = v[t] - cnt[t];
+    int32_t base = v[t] - run;
+    const int32_t total = v[kOrdThreads - 1];
+    const int bcold = t_bucket(kTcold) * kDB;
+    for (int q = 0; q < R; ++q) {
+        if (t * R + q == bcold) cnt[2 * kBuckets] = total - base;
+        cnt[kBuckets + t * R + q] = base;
+        base += cnt[t * R + q];
+    }
 }
 
-__global__ __launch_bounds__(kOrdThreads) void order_scatter(const double *__restrict__ T, int64_t n,
+__global__ __launch_bounds__(kOrdThreads) void order_scatter(const double *__restrict__ T,
+                                                             const double *__restrict__ dts, double dt, int64_t n,
                                                              int32_t *__restrict__ cnt, int32_t *__restrict__ idx) {
     __shared__ int32_t loc[kBuckets], base[kBuckets];
     for (int b = threadIdx.x; b < kBuckets; b += kOrdThreads) loc[b] = 0;
@@ -619,7 +156,7 @@ __global__ __launch_bounds__(kOrdThreads) void order_scatter(const double *__res
     const int64_t i = int64_t(blockIdx.x) * kOrdThreads + threadIdx.x;
     int b = 0, rank = 0;
     if (i < n) {
-        b = t_bucket(T[i]);
+        b = cost_bucket(T, dts, dt, i);
         rank = atomicAdd(&loc[b], 1);
     }
     __syncthreads();
@@ -629,9 +166,82 @@ __global__ __launch_bounds__(kOrdThreads) void order_scatter(const double *__res
     if (i < n) idx[base[b] + rank] = int32_t(i);
 }
 
-size_t order_bytes(int64_t n) {
-    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-    return al(size_t(2 * kBuckets) * 4) + al(size_t(n) * 4);
+size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// workspace: bucket counts and offsets | queue counter | cell order
+constexpr size_t kCntBytes = size_t(2 * kBuckets + 64) * 4;
+size_t order_bytes(int64_t n) { return al256(kCntBytes) + 256 + al256(size_t(n) * 4); }
+
+struct Work {
+    int32_t *cnt;
+    unsigned long long *ctr;
+    int32_t *idx;
+    int32_t *tail;  // cells in the cold buckets
+};
+
+Work work_parts(void *ws) {
+    auto *b = static_cast<unsigned char *>(ws);
+    auto *cnt = reinterpret_cast<int32_t *>(b);
+    return Work{cnt, reinterpret_cast<unsigned long long *>(b + al256(kCntBytes)),
+                reinterpret_cast<int32_t *>(b + al256(kCntBytes) + 256), cnt + 2 * kBuckets};
+}
+
+// cells in order of decreasing estimated cost into w.idx; zeroes the queue counter
+df_status order_cells(const StepArgs &a, const Work &w, hipStream_t s) {
+    const unsigned blocks = unsigned((a.n + kOrdThreads - 1) / kOrdThreads);
+    hipLaunchKernelGGL(order_zero, dim3(1), dim3(kOrdThreads), 0, s, w.cnt, w.ctr);
+    hipLaunchKernelGGL(order_hist, dim3(blocks), dim3(kOrdThreads), 0, s, a.T, a.dts, a.dt, a.n, w.cnt);
+    hipLaunchKernelGGL(order_scan, dim3(1), dim3(kOrdThreads), 0, s, w.cnt);
+    hipLaunchKernelGGL(order_scatter, dim3(blocks), dim3(kOrdThreads), 0, s, a.T, a.dts, a.dt, a.n, w.cnt, w.idx);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(DF_E_HIP, std::string("df_chem_step ordering: ") + hipGetErrorString(e));
+    return DF_OK;
+}
+
+// scalar dt (dts == nullptr) or per-cell dt
+df_status chem_step_impl(const char *who, const df_mech *mech, int64_t n_cells, int64_t ld, double dt,
+                         const double *dts, const double *p, double *T, double *Y, double *h_inout, double *rr,
+                         int32_t *cell_status, int32_t *n_steps, void *workspace, size_t ws_bytes,
+                         const df_chem_opts *opts, void *hip_stream) {
+    const std::string w(who);
+    if (!mech) return fail(DF_E_INVALID, w + ": null mechanism handle");
+    if (n_cells < 0 || ld < n_cells) return fail(DF_E_INVALID, w + ": need 0 <= n_cells <= ld");
+    if (!dts && (!(dt > 0.0) || !std::isfinite(dt))) return fail(DF_E_INVALID, w + ": dt must be finite and > 0");
+    if (n_cells > 0 && (!p || !T || !Y)) return fail(DF_E_INVALID, w + ": null p, T or Y");
+    if (n_cells > 0x7fffffff) return fail(DF_E_UNSUPPORTED, w + ": more than 2^31-1 cells");
+    df_chem_opts o;
+    df_chem_default_opts(&o);
+    if (opts) o = *opts;
+    df_status st = validate_chem_opts(o);
+    if (st != DF_OK) return st;
+    if (workspace && (ws_bytes < order_bytes(n_cells) || reinterpret_cast<uintptr_t>(workspace) % 256 != 0))
+        return fail(DF_E_INVALID, w + ": workspace smaller than df_chem_workspace_size or not 256-byte aligned");
+    if (o.schedule == 2 && !workspace) return fail(DF_E_INVALID, w + ": the queue schedule needs the workspace");
+    if (n_cells == 0) return DF_OK;
+    int prev = 0;
+    if (hipGetDevice(&prev) != hipSuccess) return fail(DF_E_HIP, w + ": hipGetDevice failed");
+    if (prev != mech->device && hipSetDevice(mech->device) != hipSuccess)
+        return fail(DF_E_HIP, w + ": cannot select the mechanism's device");
+    auto s = static_cast<hipStream_t>(hip_stream);
+    const StepArgs a{n_cells, ld, dt, dts, p, T, Y, h_inout, rr, cell_status, n_steps, kernel_opts(o), DF_CELL_OK};
+    const Work wk = workspace ? work_parts(workspace) : Work{nullptr, nullptr, nullptr, nullptr};
+    if (workspace) st = order_cells(a, wk, s);
+    if (st == DF_OK) {
+        if (o.schedule == 2) {
+            const int32_t cap = chem_queue_capacity(mech->dev);
+            int32_t head = o.coop_blocks == 0 ? cap : (o.coop_blocks < 0 ? 0 : o.coop_blocks);
+            head = head > cap ? cap : head;
+            if (cap <= 0)
+                st = fail(DF_E_UNSUPPORTED, w + ": no persistent kernel for this mechanism");
+            else
+                st = launch_chem_queue(mech->dev, a, CellQueue{nullptr, nullptr, wk.idx, wk.ctr, wk.tail, head}, cap,
+                                       s);
+        } else {
+            st = launch_chem_step(mech->dev, a, o.mapping, workspace ? wk.idx : nullptr, nullptr, s);
+        }
+    }
+    if (prev != mech->device) (void)hipSetDevice(prev);
+    return st;
 }
 
 }  // namespace
@@ -650,45 +260,112 @@ extern "C" df_status df_chem_step(const df_mech *mech, int64_t n_cells, int64_t 
                                   double *T, double *Y, double *h_inout, double *rr, int32_t *cell_status,
                                   int32_t *n_steps, void *workspace, size_t ws_bytes, const df_chem_opts *opts,
                                   void *hip_stream) {
+    df::clear_error();
+    return df::chem_step_impl("df_chem_step", mech, n_cells, ld, dt, nullptr, p, T, Y, h_inout, rr, cell_status,
+                              n_steps, workspace, ws_bytes, opts, hip_stream);
+}
+
+extern "C" df_status df_chem_step_cells(const df_mech *mech, int64_t n_cells, int64_t ld, const double *dt,
+                                        const double *p, double *T, double *Y, double *h_inout, double *rr,
+                                        int32_t *cell_status, int32_t *n_steps, void *workspace, size_t ws_bytes,
+                                        const df_chem_opts *opts, void *hip_stream) {
+    df::clear_error();
+    if (n_cells > 0 && !dt) return df::fail(DF_E_INVALID, "df_chem_step_cells: null dt");
+    return df::chem_step_impl("df_chem_step_cells", mech, n_cells, ld, 0.0, dt, p, T, Y, h_inout, rr, cell_status,
+                              n_steps, workspace, ws_bytes, opts, hip_stream);
+}
+
+// ---- schedule autotuning ----
+namespace df {
+namespace {
+
+size_t autotune_bytes(int K, int64_t n) {
+    return order_bytes(n) + al256(size_t(n) * 8) + al256(size_t(K) * size_t(n) * 8);
+}
+
+}  // namespace
+}  // namespace df
+
+extern "C" df_status df_chem_autotune_workspace_size(const df_mech *mech, int64_t n_cells, size_t *bytes) {
     using namespace df;
     clear_error();
-    if (!mech) return fail(DF_E_INVALID, "df_chem_step: null mechanism handle");
-    if (n_cells < 0 || ld < n_cells) return fail(DF_E_INVALID, "df_chem_step: need 0 <= n_cells <= ld");
-    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DF_E_INVALID, "df_chem_step: dt must be finite and > 0");
-    if (n_cells > 0 && (!p || !T || !Y)) return fail(DF_E_INVALID, "df_chem_step: null p, T or Y");
-    if (n_cells > 0x7fffffff) return fail(DF_E_UNSUPPORTED, "df_chem_step: more than 2^31-1 cells");
-    df_chem_opts o;
-    df_chem_default_opts(&o);
-    if (opts) o = *opts;
-    df_status st = validate_chem_opts(o);
+    if (!mech || !bytes || n_cells < 0) return fail(DF_E_INVALID, "df_chem_autotune_workspace_size: bad arguments");
+    *bytes = autotune_bytes(mech->host.K, n_cells);
+    return DF_OK;
+}
+
+extern "C" df_status df_chem_autotune(const df_mech *mech, int64_t n_cells, int64_t ld, double dt,
+                                      const double *dt_cells, const double *p, const double *T, const double *Y,
+                                      void *workspace, size_t ws_bytes, df_chem_opts *opts, void *hip_stream) {
+    using namespace df;
+    clear_error();
+    const char *who = "df_chem_autotune";
+    if (!mech || !opts) return fail(DF_E_INVALID, std::string(who) + ": null mechanism handle or opts");
+    if (n_cells < 0 || ld < n_cells) return fail(DF_E_INVALID, std::string(who) + ": need 0 <= n_cells <= ld");
+    if (!dt_cells && (!(dt > 0.0) || !std::isfinite(dt)))
+        return fail(DF_E_INVALID, std::string(who) + ": dt must be finite and > 0");
+    if (n_cells > 0 && (!p || !T || !Y)) return fail(DF_E_INVALID, std::string(who) + ": null p, T or Y");
+    df_status st = validate_chem_opts(*opts);
     if (st != DF_OK) return st;
-    if (workspace && (ws_bytes < order_bytes(n_cells) || reinterpret_cast<uintptr_t>(workspace) % 256 != 0))
-        return fail(DF_E_INVALID, "df_chem_step: workspace smaller than df_chem_workspace_size or not 256-byte aligned");
+    const int K = mech->host.K;
+    if (!workspace || ws_bytes < autotune_bytes(K, n_cells) || reinterpret_cast<uintptr_t>(workspace) % 256 != 0)
+        return fail(DF_E_INVALID, std::string(who) + ": workspace smaller than df_chem_autotune_workspace_size or "
+                                                     "not 256-byte aligned");
     if (n_cells == 0) return DF_OK;
     int prev = 0;
-    if (hipGetDevice(&prev) != hipSuccess) return fail(DF_E_HIP, "df_chem_step: hipGetDevice failed");
+    if (hipGetDevice(&prev) != hipSuccess) return fail(DF_E_HIP, std::string(who) + ": hipGetDevice failed");
     if (prev != mech->device && hipSetDevice(mech->device) != hipSuccess)
-        return fail(DF_E_HIP, "df_chem_step: cannot select the mechanism's device");
+        return fail(DF_E_HIP, std::string(who) + ": cannot select the mechanism's device");
     auto s = static_cast<hipStream_t>(hip_stream);
-    const int32_t *cidx = nullptr;
-    if (workspace) {
-        auto *cnt = static_cast<int32_t *>(workspace);
-        auto *idx = reinterpret_cast<int32_t *>(static_cast<unsigned char *>(workspace) +
-                                                ((size_t(2 * kBuckets) * 4 + 255) & ~size_t(255)));
-        const unsigned blocks = unsigned((n_cells + kOrdThreads - 1) / kOrdThreads);
-        hipLaunchKernelGGL(order_zero, dim3(1), dim3(kOrdThreads), 0, s, cnt);
-        hipLaunchKernelGGL(order_hist, dim3(blocks), dim3(kOrdThreads), 0, s, T, n_cells, cnt);
-        hipLaunchKernelGGL(order_scan, dim3(1), dim3(kOrdThreads), 0, s, cnt);
-        hipLaunchKernelGGL(order_scatter, dim3(blocks), dim3(kOrdThreads), 0, s, T, n_cells, cnt, idx);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) {
-            if (prev != mech->device) (void)hipSetDevice(prev);
-            return fail(DF_E_HIP, std::string("df_chem_step ordering: ") + hipGetErrorString(e));
-        }
-        cidx = idx;
+    auto *base = static_cast<unsigned char *>(workspace);
+    void *ows = base;
+    auto *Tc = reinterpret_cast<double *>(base + order_bytes(n_cells));
+    auto *Yc = reinterpret_cast<double *>(base + order_bytes(n_cells) + al256(size_t(n_cells) * 8));
+    const int32_t cap = chem_queue_capacity(mech->dev);
+    struct Cand {
+        int32_t schedule, coop_blocks;
+    };
+    std::vector<Cand> cands = {{1, 0}};
+    if (cap > 0) {
+        cands.push_back({2, 0});
+        cands.push_back({2, cap / 2});
+        cands.push_back({2, (3 * cap) / 4});
     }
-    st = launch_chem_step(mech->dev, n_cells, ld, dt, p, T, Y, h_inout, rr, cell_status, n_steps, o, cidx, nullptr,
-                          DF_CELL_OK, s);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    float best_ms = -1.0f;
+    Cand best = cands[0];
+    hipError_t he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
+    for (size_t c = 0; c < cands.size() && he == hipSuccess && st == DF_OK; ++c) {
+        df_chem_opts o = *opts;
+        o.schedule = cands[c].schedule;
+        o.coop_blocks = cands[c].coop_blocks;
+        for (int rep = 0; rep < 2 && he == hipSuccess && st == DF_OK; ++rep) {
+            he = hipMemcpyAsync(Tc, T, size_t(n_cells) * 8, hipMemcpyDeviceToDevice, s);
+            if (he == hipSuccess)
+                he = hipMemcpy2DAsync(Yc, size_t(n_cells) * 8, Y, size_t(ld) * 8, size_t(n_cells) * 8, size_t(K),
+                                      hipMemcpyDeviceToDevice, s);
+            if (he == hipSuccess) he = hipEventRecord(e0, s);
+            if (he != hipSuccess) break;
+            st = chem_step_impl(who, mech, n_cells, n_cells, dt, dt_cells, p, Tc, Yc, nullptr, nullptr, nullptr,
+                                nullptr, ows, order_bytes(n_cells), &o, hip_stream);
+            if (st != DF_OK) break;
+            he = hipEventRecord(e1, s);
+            if (he == hipSuccess) he = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+            if (he == hipSuccess && (best_ms < 0.0f || ms < best_ms)) {
+                best_ms = ms;
+                best = cands[c];
+            }
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
     if (prev != mech->device) (void)hipSetDevice(prev);
-    return st;
+    if (st != DF_OK) return st;
+    if (he != hipSuccess) return fail(DF_E_HIP, std::string(who) + ": " + hipGetErrorString(he));
+    opts->schedule = best.schedule;
+    opts->coop_blocks = best.coop_blocks;
+    return DF_OK;
 }

@@ -28,6 +28,7 @@
 
 #include "df_internal.h"
 #include "df_kinetics.h"
+#include "df_lane.h"
 
 namespace df {
 namespace {
@@ -72,7 +73,8 @@ struct Coop {
     static constexpr int oVec = oProw + 2 * (2 * N + 1);
     static constexpr int oVec2 = oVec + N;
     static constexpr int oRed = oVec2 + N;
-    static constexpr int kEnd = oRed + 3 * N;
+    static constexpr int oClaim = oRed + 3 * N;  // a claimed cell index (int64), broadcast to the group
+    static constexpr int kEnd = oClaim + 1;
     // cells of a wave start 10 doubles (20 banks) apart modulo the 64 banks
     static constexpr int kStride = kEnd + ((10 - kEnd % 32) + 32) % 32;
 
@@ -452,205 +454,306 @@ struct Coop {
     }
 };
 
+// Tables staged in LDS once per block (read by all cells of the block), and the constant
+// slots of the cell regions.
 template <int K, int RPL>
-__global__ __launch_bounds__(64) void chem_coop_kernel(MechDev mg, int64_t n, int64_t ld, double dt,
-                                                       const double *__restrict__ pres, double *__restrict__ Tio,
-                                                       double *__restrict__ Yio, double *__restrict__ h_io,
-                                                       double *__restrict__ rr, int32_t *__restrict__ status,
-                                                       int32_t *__restrict__ nsteps, Opts o,
-                                                       const int32_t *__restrict__ cidx,
-                                                       const int32_t *__restrict__ dcount, int32_t status_ok) {
+__device__ typename Coop<K, RPL>::Tab stage_tables(const MechDev &mg, double *lds, int lane) {
     using C = Coop<K, RPL>;
-    constexpr int N = C::N, MP = C::MP, LM = C::LM;
-    extern __shared__ double lds[];
-    const int lane = threadIdx.x;
-    const int r = lane & (G - 1);
-    const int64_t limit = dcount ? int64_t(*dcount) : n;
-    if (int64_t(blockIdx.x) * kCellsPerBlock >= limit) return;  // whole block idle (e.g. no fallback cells)
-    // stage the tables: one copy per block, read by all its cells
-    {
-        auto *dst = reinterpret_cast<unsigned char *>(lds);
-        // copy rows x cols from a dense table to an LDS table with row stride `st`
-        auto cp8 = [&](int off, const double *src, int rows, int cols, int st) {
-            double *d8 = reinterpret_cast<double *>(dst + off);
-            for (int q = lane; q < rows * cols; q += 64) d8[(q / cols) * st + q % cols] = src[q];
-        };
-        auto cp4 = [&](int off, const int *src, int rows, int cols, int st) {
-            int *d4 = reinterpret_cast<int *>(dst + off);
-            for (int q = lane; q < rows * cols; q += 64) d4[(q / cols) * st + q % cols] = src[q];
-        };
-        cp8(C::tSp, mg.sp, K, kSpTab, kSpS);
-        cp8(C::tCr, mg.cr, MP, kCrDbl, kCrDbl);
-        cp8(C::tEff, mg.ceff, MP, K + 4, C::EFS);
-        cp8(C::tEw, mg.ceffw, MP, K, C::EWS);
-        cp4(C::tCi, mg.ci, MP, kCiInt, kCiInt);
-    }
+    constexpr int MP = C::MP;
+    auto *dst = reinterpret_cast<unsigned char *>(lds);
+    // copy rows x cols from a dense table to an LDS table with row stride `st`
+    auto cp8 = [&](int off, const double *src, int rows, int cols, int st) {
+        double *d8 = reinterpret_cast<double *>(dst + off);
+        for (int q = lane; q < rows * cols; q += 64) d8[(q / cols) * st + q % cols] = src[q];
+    };
+    auto cp4 = [&](int off, const int *src, int rows, int cols, int st) {
+        int *d4 = reinterpret_cast<int *>(dst + off);
+        for (int q = lane; q < rows * cols; q += 64) d4[(q / cols) * st + q % cols] = src[q];
+    };
+    cp8(C::tSp, mg.sp, K, kSpTab, kSpS);
+    cp8(C::tCr, mg.cr, MP, kCrDbl, kCrDbl);
+    cp8(C::tEff, mg.ceff, MP, K + 4, C::EFS);
+    cp8(C::tEw, mg.ceffw, MP, K, C::EWS);
+    cp4(C::tCi, mg.ci, MP, kCiInt, kCiInt);
     __syncthreads();
     typename C::Tab tb;
-    {
-        auto *base = reinterpret_cast<unsigned char *>(lds);
-        tb.sp = reinterpret_cast<const double *>(base + C::tSp);
-        tb.cr = reinterpret_cast<const double *>(base + C::tCr);
-        tb.eff = reinterpret_cast<const double *>(base + C::tEff);
-        tb.ew = reinterpret_cast<const double *>(base + C::tEw);
-        tb.ci = reinterpret_cast<const int *>(base + C::tCi);
-    }
-    double *sh = lds + C::tBytes / 8 + (lane / G) * C::kStride;
-    const int64_t cell = int64_t(blockIdx.x) * kCellsPerBlock + lane / G;
-    if (cell >= limit) return;  // the 16 lanes of a cell leave together
-    const int64_t i = cidx ? int64_t(cidx[cell]) : cell;
-    // the lane's production-rate list and the constant slots of the cell region
-    int li[LM];
-    double lc[LM];
+    tb.sp = reinterpret_cast<const double *>(dst + C::tSp);
+    tb.cr = reinterpret_cast<const double *>(dst + C::tCr);
+    tb.eff = reinterpret_cast<const double *>(dst + C::tEff);
+    tb.ew = reinterpret_cast<const double *>(dst + C::tEw);
+    tb.ci = reinterpret_cast<const int *>(dst + C::tCi);
+    return tb;
+}
+
+// the lane's production-rate list (index into the per-cell rate array, coefficient)
+__device__ __forceinline__ void load_lists(const MechDev &mg, int r, int (&li)[kCoopList], double (&lc)[kCoopList]) {
 #pragma unroll
-    for (int e = 0; e < LM; ++e) {
-        li[e] = mg.cli[r * LM + e];
-        lc[e] = mg.clc[r * LM + e];
+    for (int e = 0; e < kCoopList; ++e) {
+        li[e] = mg.cli[r * kCoopList + e];
+        lc[e] = mg.clc[r * kCoopList + e];
     }
+}
+
+template <int K, int RPL>
+__device__ void init_cell_region(double *sh, int r) {
+    using C = Coop<K, RPL>;
     if (r == 0) {
         sh[C::oC] = 1.0;
         sh[C::oCpt] = 0.0;
         sh[C::oHm] = 0.0;
         sh[C::oDcp] = 0.0;
-        sh[C::oQ + MP] = 0.0;
+        sh[C::oQ + C::MP] = 0.0;
     }
-    for (int c = r; c < C::RS; c += G) sh[C::oRec + MP * C::RS + c] = 0.0;
+    for (int c = r; c < C::RS; c += G) sh[C::oRec + C::MP * C::RS + c] = 0.0;
+}
 
+// State of the cell a 16-lane group is integrating: replicated in the group's lanes, except
+// the lane's own component yr = y[r] and the quantities derived from it.  The group advances
+// it one RODAS4 attempt at a time, so that a group whose cell is done can take another cell
+// while the other groups of its wave continue.
+template <int K>
+struct GroupTask {
+    static constexpr int N = K + 1;
+    int64_t i;  // cell index
     double y[N];
-    const double p = pres[i];
-    y[0] = Tio[i];
+    double yr, p, ip, dtc, rho0, y0own, atol, t, h, h_final;
+    int acc, rej;
+    bool prev_rej, fresh;
+};
+
+// Load cell i into the group (all 16 lanes).  A cell whose input is unusable (non-finite,
+// p or T not positive, or a step length that is not positive and finite) gets status
+// DF_CELL_NONFINITE, zero steps and zero rr, and false is returned.
+template <int K>
+__device__ bool group_load(const StepArgs &a, const double *sp, int r, int64_t i, GroupTask<K> &c) {
+    constexpr int N = K + 1;
+    c.i = i;
+    c.p = a.p[i];
+    c.dtc = a.dts ? a.dts[i] : a.dt;
+    c.y[0] = a.T[i];
 #pragma unroll
-    for (int k = 0; k < K; ++k) y[1 + k] = Yio[k * ld + i];
-    bool finite = isfinite(p) && p > 0.0 && isfinite(y[0]) && y[0] > 0.0;
+    for (int k = 0; k < K; ++k) c.y[1 + k] = a.Y[k * a.ld + i];
+    bool ok = isfinite(c.p) && c.p > 0.0 && isfinite(c.y[0]) && c.y[0] > 0.0 && isfinite(c.dtc) && c.dtc > 0.0;
 #pragma unroll
-    for (int k = 0; k < K; ++k) finite = finite && isfinite(y[1 + k]);
-    if (!finite) {
+    for (int k = 0; k < K; ++k) ok = ok && isfinite(c.y[1 + k]);
+    if (!ok) {
         if (r == 0) {
-            if (status) status[i] = DF_CELL_NONFINITE;
-            if (nsteps) {
-                nsteps[i] = 0;
-                nsteps[n + i] = 0;
+            if (a.status) a.status[i] = DF_CELL_NONFINITE;
+            if (a.nsteps) {
+                a.nsteps[i] = 0;
+                a.nsteps[a.n + i] = 0;
             }
         }
-        if (rr && r >= 1 && r <= K) rr[(r - 1) * ld + i] = 0.0;
-        return;
+        if (a.rr && r >= 1 && r <= K) a.rr[(r - 1) * a.ld + i] = 0.0;
+        return false;
     }
-    const double ip = 1.0 / p;
-    double yr = 0.0;  // the lane's own component y[r]
+    c.ip = 1.0 / c.p;
+    c.yr = 0.0;
 #pragma unroll
-    for (int c = 0; c < N; ++c) yr = (c == r) ? y[c] : yr;
-    // input density and own mass fraction for rr
-    double rho0 = 0.0;
-    const double y0own = (r >= 1 && r <= K) ? yr : 0.0;
-    if (rr) {
+    for (int q = 0; q < N; ++q) c.yr = (q == r) ? c.y[q] : c.yr;
+    c.y0own = (r >= 1 && r <= K) ? c.yr : 0.0;
+    c.rho0 = 0.0;
+    if (a.rr) {  // input density, for rr
         double sYW = 0.0;
 #pragma unroll
-        for (int k = 0; k < K; ++k) sYW += y[1 + k] * tb.sp[k * kSpS + 1];
-        rho0 = p / (sYW * kR * y[0]);
+        for (int k = 0; k < K; ++k) sYW += c.y[1 + k] * sp[k * kSpS + 1];
+        c.rho0 = c.p / (sYW * kR * c.y[0]);
     }
-    const double atol = (r == 0) ? o.atol_T : o.atol_Y;
+    c.atol = (r == 0) ? a.o.atol_T : a.o.atol_Y;
+    const double h_in = a.h_io ? a.h_io[i] : 0.0;
+    c.fresh = !(h_in > 0.0);
+    c.h = c.fresh ? 0.0 : fmin(h_in, c.dtc);
+    if (!c.fresh && !(c.h >= a.o.h_min)) c.h = a.o.h_min;
+    c.t = 0.0;
+    c.h_final = 0.0;
+    c.acc = c.rej = 0;
+    c.prev_rej = false;
+    return true;
+}
 
-    // initial sub-step
-    double h;
-    const double h_in = h_io ? h_io[i] : 0.0;
-    if (h_in > 0.0) {
-        h = fmin(h_in, dt);
-    } else {
-        const double f = C::rhs(tb, sh, r, p, ip, y, yr, li, lc);
-        const double sc = atol + o.rtol * fabs(yr);
-        const double ny = sqrt(C::lane_sum(sh + C::oRed, r, (yr / sc) * (yr / sc)) / N);
-        const double nf = sqrt(C::lane_sum(sh + C::oRed + N, r, (f / sc) * (f / sc)) / N);
-        h = (nf > 0.0) ? fmin(0.01 * ny / nf, dt) : dt;
-    }
-    if (!(h >= o.h_min)) h = o.h_min;
-
-    double t = 0.0, h_final = 0.0;
-    int acc = 0, rej = 0, st = DF_CELL_OK;
-    bool prev_rej = false;
-    for (;;) {
-        if (acc + rej >= o.max_steps) {
-            st = DF_CELL_MAX_STEPS;
-            break;
-        }
-        const bool last = (t + h >= dt);
-        const double ht = last ? dt - t : h;
-        double winv[N];
-        const double f0 = C::jacobian(tb, sh, r, p, ip, y, yr, li, lc);
-        C::invert(sh, r, 1.0 / (Rodas4::g * ht), winv);
-
-        // own components: stage vectors u_s[r]
-        double u[6], ysr = yr;
-        const double ih = 1.0 / ht;
-#pragma unroll
-        for (int s = 0; s < 6; ++s) {
-            double fs;
-            if (s == 0) {
-                fs = f0;
-            } else {
-                ysr = yr;
-#pragma unroll
-                for (int j = 0; j < s; ++j) ysr = fma(Rodas4::a[s][j], u[j], ysr);
-                double ys[N];
-                C::gather(sh + C::oVec, r, ysr, ys);
-                fs = C::rhs(tb, sh, r, p, ip, ys, ysr, li, lc);
-            }
-            double cu = 0.0;
-#pragma unroll
-            for (int j = 0; j < s; ++j) cu = fma(Rodas4::c[s][j], u[j], cu);
-            double rv[N];
-            C::gather(sh + C::oVec2, r, fma(cu, ih, fs), rv);
-            double us = 0.0;
-#pragma unroll
-            for (int c = 0; c < N; ++c) us = fma(winv[c], rv[c], us);
-            u[s] = us;
-        }
-        // y_new = (stage-6 state) + u6 ; error = u6
-        const double ynr = ysr + u[5];
-        const double sc = atol + o.rtol * fmax(fabs(yr), fabs(ynr));
-        const double er = (r < N) ? u[5] / sc : 0.0;
-        const double err = sqrt(C::lane_sum(sh + C::oRed + 2 * N, r, er * er) / N);
-
-        const double fmx = prev_rej ? 1.0 : 6.0;
-        double fac;
-        if (!isfinite(err))
-            fac = 0.2;
-        else if (err == 0.0)
-            fac = fmx;
-        else
-            fac = fmin(fmx, fmax(0.2, 0.9 / sqrt(sqrt(err))));  // 0.9 err^(-1/4)
-
-        if (isfinite(err) && err <= 1.0) {
-            ++acc;
-            C::gather(sh + C::oVec, r, ynr, y);
-            yr = (r < N) ? ynr : 0.0;
-            h_final = h;
-            prev_rej = false;
-            if (last) break;
-            t += ht;
-            h = ht * fac;
-        } else {
-            ++rej;
-            prev_rej = true;
-            h = ht * fac;
-            if (h < o.h_min) {
-                st = DF_CELL_H_UNDERFLOW;
-                break;
-            }
-        }
-    }
-
+// write the results of the group's cell: lane 0 the scalars, lanes 1..K their species
+template <int K>
+__device__ void group_finish(const StepArgs &a, int r, const GroupTask<K> &c, int st) {
+    const int64_t i = c.i;
     if (r == 0) {
-        Tio[i] = y[0];
-        if (h_io) h_io[i] = (st == DF_CELL_OK) ? h_final : h;
-        if (status) status[i] = (st == DF_CELL_OK) ? status_ok : st;
-        if (nsteps) {
-            nsteps[i] = acc;
-            nsteps[n + i] = rej;
+        a.T[i] = c.y[0];
+        if (a.h_io) a.h_io[i] = (st == DF_CELL_OK) ? c.h_final : c.h;
+        if (a.status) a.status[i] = (st == DF_CELL_OK) ? a.status_ok : st;
+        if (a.nsteps) {
+            a.nsteps[i] = c.acc;
+            a.nsteps[a.n + i] = c.rej;
         }
     } else if (r <= K) {
-        if (rr) rr[(r - 1) * ld + i] = rho0 * (yr - y0own) / dt;
-        Yio[(r - 1) * ld + i] = yr;
+        if (a.rr) a.rr[(r - 1) * a.ld + i] = c.rho0 * (c.yr - c.y0own) / c.dtc;
+        a.Y[(r - 1) * a.ld + i] = c.yr;
     }
+}
+
+// One RODAS4 attempt of the group's cell (the first attempt of a cell without a step hint
+// also picks the initial step from f(y0)).  Returns true when the cell is done and its
+// results have been written.
+template <int K, int RPL>
+__device__ bool group_attempt(const StepArgs &a, const typename Coop<K, RPL>::Tab &tb, double *sh, int r,
+                              const int (&li)[kCoopList], const double (&lc)[kCoopList], GroupTask<K> &c) {
+    using C = Coop<K, RPL>;
+    constexpr int N = K + 1;
+    const Opts &o = a.o;
+    if (c.acc + c.rej >= o.max_steps) {
+        group_finish<K>(a, r, c, DF_CELL_MAX_STEPS);
+        return true;
+    }
+    const double f0 = C::jacobian(tb, sh, r, c.p, c.ip, c.y, c.yr, li, lc);
+    if (c.fresh) {
+        // initial sub-step from the weighted norms of y0 and f(y0)
+        const double sc = c.atol + o.rtol * fabs(c.yr);
+        const double ny = sqrt(C::lane_sum(sh + C::oRed, r, (c.yr / sc) * (c.yr / sc)) / N);
+        const double nf = sqrt(C::lane_sum(sh + C::oRed + N, r, (f0 / sc) * (f0 / sc)) / N);
+        c.h = (nf > 0.0) ? fmin(0.01 * ny / nf, c.dtc) : c.dtc;
+        if (!(c.h >= o.h_min)) c.h = o.h_min;
+        c.fresh = false;
+    }
+    const bool last = (c.t + c.h >= c.dtc);
+    const double ht = last ? c.dtc - c.t : c.h;
+    double winv[N];
+    C::invert(sh, r, 1.0 / (Rodas4::g * ht), winv);
+
+    // own components: stage vectors u_s[r]
+    double u[6], ysr = c.yr;
+    const double ih = 1.0 / ht;
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+        double fs;
+        if (s == 0) {
+            fs = f0;
+        } else {
+            ysr = c.yr;
+#pragma unroll
+            for (int j = 0; j < s; ++j) ysr = fma(Rodas4::a[s][j], u[j], ysr);
+            double ys[N];
+            C::gather(sh + C::oVec, r, ysr, ys);
+            fs = C::rhs(tb, sh, r, c.p, c.ip, ys, ysr, li, lc);
+        }
+        double cu = 0.0;
+#pragma unroll
+        for (int j = 0; j < s; ++j) cu = fma(Rodas4::c[s][j], u[j], cu);
+        double rv[N];
+        C::gather(sh + C::oVec2, r, fma(cu, ih, fs), rv);
+        double us = 0.0;
+#pragma unroll
+        for (int q = 0; q < N; ++q) us = fma(winv[q], rv[q], us);
+        u[s] = us;
+    }
+    // y_new = (stage-6 state) + u6 ; error = u6
+    const double ynr = ysr + u[5];
+    const double sc = c.atol + o.rtol * fmax(fabs(c.yr), fabs(ynr));
+    const double er = (r < N) ? u[5] / sc : 0.0;
+    const double err = sqrt(C::lane_sum(sh + C::oRed + 2 * N, r, er * er) / N);
+
+    const double fmx = c.prev_rej ? 1.0 : 6.0;
+    double fac;
+    if (!isfinite(err))
+        fac = 0.2;
+    else if (err == 0.0)
+        fac = fmx;
+    else
+        fac = fmin(fmx, fmax(0.2, 0.9 / sqrt(sqrt(err))));  // 0.9 err^(-1/4)
+
+    if (isfinite(err) && err <= 1.0) {
+        ++c.acc;
+        C::gather(sh + C::oVec, r, ynr, c.y);
+        c.yr = (r < N) ? ynr : 0.0;
+        c.h_final = c.h;
+        c.prev_rej = false;
+        if (last) {
+            group_finish<K>(a, r, c, DF_CELL_OK);
+            return true;
+        }
+        c.t += ht;
+        c.h = ht * fac;
+    } else {
+        ++c.rej;
+        c.prev_rej = true;
+        c.h = ht * fac;
+        if (c.h < o.h_min) {
+            group_finish<K>(a, r, c, DF_CELL_H_UNDERFLOW);
+            return true;
+        }
+    }
+    return false;
+}
+
+// Static schedule: group s of the launch (four per block) integrates cell cidx[s] (or s).
+template <int K, int RPL>
+__global__ __launch_bounds__(64) void chem_coop_kernel(MechDev mg, StepArgs a, CellQueue q) {
+    using C = Coop<K, RPL>;
+    extern __shared__ double lds[];
+    const int lane = threadIdx.x;
+    const int r = lane & (G - 1);
+    const int64_t limit = q.dcount ? int64_t(*q.dcount) : a.n;
+    if (int64_t(blockIdx.x) * kCellsPerBlock >= limit) return;  // whole block idle (e.g. no fallback cells)
+    const typename C::Tab tb = stage_tables<K, RPL>(mg, lds, lane);
+    double *sh = lds + C::tBytes / 8 + (lane / G) * C::kStride;
+    const int64_t slot = int64_t(blockIdx.x) * kCellsPerBlock + lane / G;
+    if (slot >= limit) return;  // the 16 lanes of a cell leave together
+    init_cell_region<K, RPL>(sh, r);
+    int li[kCoopList];
+    double lc[kCoopList];
+    load_lists(mg, r, li, lc);
+    GroupTask<K> c;
+    bool have = group_load<K>(a, tb.sp, r, q.cidx ? int64_t(q.cidx[slot]) : slot, c);
+    while (have) have = !group_attempt<K, RPL>(a, tb, sh, r, li, lc, c);
+}
+
+// Queue schedule: a persistent grid.  Blocks [0, head_blocks) run four 16-lane groups that
+// take the most expensive cells from the front of the queue.  The other blocks first run one
+// cell per lane on the cold cells at the back, then join the front claims as 16-lane groups.
+// A group or lane that finishes a cell claims the next one at once, until the queue is empty.
+// LANES = false compiles the 16-lane body alone (every block starts as 16-lane groups), so
+// that it keeps the registers of the static kernel.
+template <int K, int RPL, bool LANES>
+__global__ __launch_bounds__(64) void chem_queue_kernel(MechDev mg, StepArgs a, CellQueue q) {
+    using C = Coop<K, RPL>;
+    extern __shared__ double lds[];
+    const int lane = threadIdx.x;
+    if (LANES && int(blockIdx.x) >= q.head_blocks) {
+        using L = Cell<K>;
+        double *sh = lds + lane;  // per-lane arrays, slot-major with a stride of one wave
+        L::init_lds(sh);
+        LaneTask<K> c;
+        auto next = [&]() -> bool {
+            for (;;) {
+                const int64_t i = queue_claim(q, a.n, false);
+                if (i < 0) return false;
+                if (lane_load<K>(a, i, c)) return true;
+            }
+        };
+        bool have = next();
+        while (have)
+            if (lane_attempt<K>(mg, a, sh, c)) have = next();
+        __syncthreads();  // the per-lane arrays are dead before the tables overwrite them
+    }
+    const int r = lane & (G - 1);
+    const typename C::Tab tb = stage_tables<K, RPL>(mg, lds, lane);
+    double *sh = lds + C::tBytes / 8 + (lane / G) * C::kStride;
+    init_cell_region<K, RPL>(sh, r);
+    auto *claim = reinterpret_cast<long long *>(sh + C::oClaim);
+    int li[kCoopList];
+    double lc[kCoopList];
+    load_lists(mg, r, li, lc);
+    GroupTask<K> c;
+    auto next = [&]() -> bool {
+        for (;;) {
+            if (r == 0) *claim = queue_claim(q, a.n, true);
+            wave_sync();
+            const int64_t i = *claim;
+            wave_sync();
+            if (i < 0) return false;
+            if (group_load<K>(a, tb.sp, r, i, c)) return true;
+        }
+    };
+    bool have = next();
+    while (have)
+        if (group_attempt<K, RPL>(a, tb, sh, r, li, lc, c)) have = next();
 }
 
 }  // namespace
@@ -689,51 +792,114 @@ bool chem_coop_supported(const MechDev &m) {
 }
 
 template <int K, int RPL>
-static df_status launch_coop_k(const MechDev &m, int64_t n, int64_t ld, double dt, const double *p, double *T,
-                               double *Y, double *h_inout, double *rr, int32_t *status, int32_t *n_steps,
-                               const Opts &o, const int32_t *cidx, const int32_t *dcount, int32_t status_ok,
-                               hipStream_t stream) {
-    const int64_t blocks = (n + kCellsPerBlock - 1) / kCellsPerBlock;
+static df_status launch_coop_k(const MechDev &m, const StepArgs &a, const CellQueue &q, hipStream_t stream) {
+    const int64_t blocks = (a.n + kCellsPerBlock - 1) / kCellsPerBlock;
     if (blocks > 0x7fffffff) return fail(DF_E_UNSUPPORTED, "chem_step: too many cells for one launch");
     const size_t lds = Coop<K, RPL>::lds_bytes();
-    hipLaunchKernelGGL((chem_coop_kernel<K, RPL>), dim3(unsigned(blocks)), dim3(64), lds, stream, m, n, ld, dt, p, T,
-                       Y, h_inout, rr, status, n_steps, o, cidx, dcount, status_ok);
+    hipLaunchKernelGGL((chem_coop_kernel<K, RPL>), dim3(unsigned(blocks)), dim3(64), lds, stream, m, a, q);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(DF_E_HIP, std::string("chem_step launch: ") + hipGetErrorString(e));
     return DF_OK;
 }
 
-df_status launch_chem_coop(const MechDev &m, int64_t n, int64_t ld, double dt, const double *p, double *T, double *Y,
-                           double *h_inout, double *rr, int32_t *status, int32_t *n_steps, const df_chem_opts &opts,
-                           const int32_t *cidx, const int32_t *dcount, int32_t status_ok, hipStream_t stream) {
-    if (n == 0) return DF_OK;
+// LDS of the persistent kernel: the larger of the two bodies
+template <int K, int RPL>
+static size_t queue_lds_bytes() {
+    const size_t lane = size_t(Cell<K>::kRows) * 64 * sizeof(double);
+    const size_t coop = Coop<K, RPL>::lds_bytes();
+    return lane > coop ? lane : coop;
+}
+
+// blocks resident at once: the smaller count of the two variants, so that one grid size fits both
+template <int K, int RPL>
+static int32_t queue_capacity_k() {
+    int dev = 0, cus = 0, a = 0, b = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, chem_queue_kernel<K, RPL, true>, 64,
+                                                     queue_lds_bytes<K, RPL>()) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, chem_queue_kernel<K, RPL, false>, 64,
+                                                     Coop<K, RPL>::lds_bytes()) != hipSuccess)
+        return 0;
+    return int32_t(cus) * int32_t(a < b ? a : b);
+}
+
+template <int K, int RPL>
+static df_status launch_queue_k(const MechDev &m, const StepArgs &a, const CellQueue &q, int32_t blocks,
+                                hipStream_t stream) {
+    if (q.head_blocks >= blocks) {
+        const size_t lds = Coop<K, RPL>::lds_bytes();
+        hipLaunchKernelGGL((chem_queue_kernel<K, RPL, false>), dim3(unsigned(blocks)), dim3(64), lds, stream, m, a,
+                           q);
+    } else {
+        const size_t lds = queue_lds_bytes<K, RPL>();
+        hipLaunchKernelGGL((chem_queue_kernel<K, RPL, true>), dim3(unsigned(blocks)), dim3(64), lds, stream, m, a,
+                           q);
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(DF_E_HIP, std::string("chem_step queue launch: ") + hipGetErrorString(e));
+    return DF_OK;
+}
+
+#define DF_RPL_SWITCH(k, CALL)                 \
+    switch (m.RPL) {                           \
+        case 1: return CALL(k, 1);             \
+        case 2: return CALL(k, 2);             \
+        case 3: return CALL(k, 3);             \
+        default: return CALL(k, 4);            \
+    }
+
+df_status launch_chem_coop(const MechDev &m, const StepArgs &a, const CellQueue &q, hipStream_t stream) {
+    if (a.n == 0) return DF_OK;
     if (!chem_coop_supported(m))
         return fail(DF_E_UNSUPPORTED, "chem_step: no cooperative kernel for " + std::to_string(m.K) + " species, " +
                                           std::to_string(m.M) + " reactions (needs K in {2, 4, 9}, M <= 64, at most " +
                                           std::to_string(kCoopList) + " reactions per species)");
-    const Opts o{opts.rtol, opts.atol_T, opts.atol_Y, opts.h_min, opts.max_steps};
+#define DF_CALL(k, rpl) launch_coop_k<k, rpl>(m, a, q, stream)
     switch (m.K) {
-#define DF_CASE(k)                                                                                                 \
-    case k:                                                                                                        \
-        switch (m.RPL) {                                                                                           \
-            case 1:                                                                                                \
-                return launch_coop_k<k, 1>(m, n, ld, dt, p, T, Y, h_inout, rr, status, n_steps, o, cidx, dcount,   \
-                                           status_ok, stream);                                                     \
-            case 2:                                                                                                \
-                return launch_coop_k<k, 2>(m, n, ld, dt, p, T, Y, h_inout, rr, status, n_steps, o, cidx, dcount,   \
-                                           status_ok, stream);                                                     \
-            case 3:                                                                                                \
-                return launch_coop_k<k, 3>(m, n, ld, dt, p, T, Y, h_inout, rr, status, n_steps, o, cidx, dcount,   \
-                                           status_ok, stream);                                                     \
-            default:                                                                                               \
-                return launch_coop_k<k, 4>(m, n, ld, dt, p, T, Y, h_inout, rr, status, n_steps, o, cidx, dcount,   \
-                                           status_ok, stream);                                                     \
-        }
+#define DF_CASE(k)              \
+    case k:                     \
+        DF_RPL_SWITCH(k, DF_CALL)
         DF_COOP_SPECIES_LIST(DF_CASE)
 #undef DF_CASE
         default:
             return fail(DF_E_UNSUPPORTED, "chem_step: no cooperative kernel for " + std::to_string(m.K) + " species");
     }
+#undef DF_CALL
 }
+
+int32_t chem_queue_capacity(const MechDev &m) {
+    if (!chem_coop_supported(m)) return 0;
+#define DF_CALL(k, rpl) queue_capacity_k<k, rpl>()
+    switch (m.K) {
+#define DF_CASE(k)              \
+    case k:                     \
+        DF_RPL_SWITCH(k, DF_CALL)
+        DF_COOP_SPECIES_LIST(DF_CASE)
+#undef DF_CASE
+        default:
+            return 0;
+    }
+#undef DF_CALL
+}
+
+df_status launch_chem_queue(const MechDev &m, const StepArgs &a, const CellQueue &q, int32_t blocks,
+                            hipStream_t stream) {
+    if (a.n == 0) return DF_OK;
+    if (blocks <= 0 || !chem_coop_supported(m))
+        return fail(DF_E_UNSUPPORTED, "chem_step: no persistent kernel for this mechanism");
+#define DF_CALL(k, rpl) launch_queue_k<k, rpl>(m, a, q, blocks, stream)
+    switch (m.K) {
+#define DF_CASE(k)              \
+    case k:                     \
+        DF_RPL_SWITCH(k, DF_CALL)
+        DF_COOP_SPECIES_LIST(DF_CASE)
+#undef DF_CASE
+        default:
+            return fail(DF_E_UNSUPPORTED, "chem_step: no persistent kernel for " + std::to_string(m.K) + " species");
+    }
+#undef DF_CALL
+}
+#undef DF_RPL_SWITCH
 
 }  // namespace df

@@ -244,9 +244,11 @@ df_status launch_dnn_k(const df_dnn *d, const df_mech *m, int64_t n, int64_t ld,
                        o.renormalise);
     e = hipGetLastError();
     if (e != hipSuccess) return fail(DF_E_HIP, std::string("dnn post launch: ") + hipGetErrorString(e));
-    if (o.fallback)
-        return launch_chem_step(m->dev, n, ld, dt, p, T, Y, nullptr, rr, status, nullptr, fo, idx, cnt,
-                                DF_CELL_DNN_FALLBACK, s);
+    if (o.fallback) {
+        const StepArgs a{n, ld, dt, nullptr, p, T, Y, nullptr, rr, status, nullptr, kernel_opts(fo),
+                         DF_CELL_DNN_FALLBACK};
+        return launch_chem_step(m->dev, a, fo.mapping, idx, cnt, s);
+    }
     return DF_OK;
 }
 

@@ -80,21 +80,58 @@ void clear_error();
 // parse a "dfmech 1" file; returns DF_OK or an error code (message set)
 df_status parse_mech_file(const char *path, HostMech &out);
 
-// integrator launch (df_chem.hip); arrays already validated
-df_status launch_chem_step(const MechDev &m, int64_t n, int64_t ld, double dt, const double *p, double *T, double *Y,
-                           double *h_inout, double *rr, int32_t *status, int32_t *n_steps, const df_chem_opts &o,
-                           const int32_t *cell_index, const int32_t *d_count, int32_t status_ok, hipStream_t stream);
-// cell_index/d_count (both nullable): lane i < *d_count works on cell cell_index[i] (compacted subset);
-// status_ok is the code written for cells that succeed (DF_CELL_OK, or DF_CELL_DNN_FALLBACK).
+struct Opts {
+    double rtol, atol_T, atol_Y, h_min;
+    int max_steps;
+};
+
+// Arguments of one chemistry-step launch (device pointers, layouts as in df_chem_step).
+struct StepArgs {
+    int64_t n, ld;
+    double dt;          // step length of every cell, unless dts is given
+    const double *dts;  // [n] step length per cell, or nullptr
+    const double *p;
+    double *T, *Y, *h_io, *rr;
+    int32_t *status, *nsteps;
+    Opts o;
+    int32_t status_ok;  // status written for cells that succeed (DF_CELL_OK or DF_CELL_DNN_FALLBACK)
+};
+
+// Where the lanes (or 16-lane groups) of a launch get their cells.
+//   static: slot s (global lane or group index) takes cell cidx[s] (or s), for s < *dcount (or n);
+//   queue:  ctr != nullptr; cells are taken from order[] (most expensive first).  Blocks
+//           [0, head_blocks) run 16-lane groups that claim from the front.  The other blocks
+//           first run one cell per lane on cells claimed from the back, at most *tail_max of
+//           them (the cells of the cold buckets), then join the front claims as 16-lane
+//           groups.  The low 32 bits of *ctr count front claims, the high 32 bits back
+//           claims (queue_claim tells the valid ones), so every cell is taken exactly once.
+struct CellQueue {
+    const int32_t *cidx;
+    const int32_t *dcount;
+    const int32_t *order;
+    unsigned long long *ctr;
+    const int32_t *tail_max;
+    int32_t head_blocks;
+};
+
+inline Opts kernel_opts(const df_chem_opts &o) { return Opts{o.rtol, o.atol_T, o.atol_Y, o.h_min, o.max_steps}; }
+
+// integrator launch with the static schedule (df_chem.hip); arrays already validated.
+// cidx/dcount (both nullable): slot s < *dcount works on cell cidx[s] (compacted subset).
+df_status launch_chem_step(const MechDev &m, const StepArgs &a, int mapping, const int32_t *cidx,
+                           const int32_t *dcount, hipStream_t stream);
 
 df_status validate_chem_opts(const df_chem_opts &o);
 
 // cooperative integrator (df_chem_coop.hip): 16 lanes per cell, for the species counts and
 // table sizes it is instantiated for
 bool chem_coop_supported(const MechDev &m);
-df_status launch_chem_coop(const MechDev &m, int64_t n, int64_t ld, double dt, const double *p, double *T, double *Y,
-                           double *h_inout, double *rr, int32_t *status, int32_t *n_steps, const df_chem_opts &o,
-                           const int32_t *cell_index, const int32_t *d_count, int32_t status_ok, hipStream_t stream);
+df_status launch_chem_coop(const MechDev &m, const StepArgs &a, const CellQueue &q, hipStream_t stream);
+// persistent work-queue launch mixing the 16-lane and the one-cell-per-lane bodies
+// (df_chem_coop.hip): blocks resident at once on the current device, and the launch
+int32_t chem_queue_capacity(const MechDev &m);
+df_status launch_chem_queue(const MechDev &m, const StepArgs &a, const CellQueue &q, int32_t blocks,
+                            hipStream_t stream);
 
 }  // namespace df
 

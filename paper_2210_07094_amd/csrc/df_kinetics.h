@@ -86,10 +86,17 @@ __device__ __forceinline__ double dlog(double x) {
     return r;
 }
 
-struct Opts {
-    double rtol, atol_T, atol_Y, h_min;
-    int max_steps;
-};
+// claim from the front (+1) or the back (+2^32) of the queue; the cell index or -1
+// Claims are ordered by the atomic: until the queue is exhausted every front claim is valid
+// and the back claims are valid while t < tail_max, so the cells taken so far are
+// h + min(t, tail_max); a claim takes the next cell while that is below n.
+__device__ __forceinline__ int64_t queue_claim(const CellQueue &q, int64_t n, bool front) {
+    const unsigned long long old = atomicAdd(q.ctr, front ? 1ull : (1ull << 32));
+    const int64_t h = int64_t(old & 0xffffffffull), t = int64_t(old >> 32);
+    const int64_t tm = int64_t(*q.tail_max);
+    if (front) return (h + (t < tm ? t : tm) < n) ? int64_t(q.order[h]) : -1;
+    return (t < tm && h + t < n) ? int64_t(q.order[n - 1 - t]) : -1;
+}
 
 
 // Forward rate constant of one reaction row (rd = ln A, b, Ta, ln A0, b0, Ta0, alpha,

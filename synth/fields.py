@@ -13,6 +13,15 @@ All fields are returned as float64 structure-of-arrays: ``T[n]`` (K),
   300 K plus eight Gaussian hot kernels of amplitude U(900, 1500) K and width
   U(4, 16) cells at uniform random centres, capped at 1800 K; p = 1 atm.
   It stands in for the paper's 2-D hydrogen jet/triple-flame field.
+* ``mixing_layer_3d`` (100^3 = 1,000,000 cells): a fuel/air mixing layer with
+  uneven stiffness for the scheduling study: mixture fraction
+  Z = (1 - tanh((y - y0)/delta))/2 + N(0, 0.02^2) clipped to [0, 1]
+  (delta = 10 cells, y0 mid-domain), fuel H2/N2 50/50 by moles, oxidiser air;
+  progress c = exp(-((Z - Z_st)/0.1)^2) blends the unburnt mixture with its
+  complete-combustion products (H2 + O2/2 -> H2O until the deficient reactant
+  is used up); T = 300 + 2200 c + N(0, 50^2) clipped to [300, 2500] K;
+  p = 1 atm; per-cell dt log-uniform in [1e-7, 1e-5] s.  It stands in for the
+  paper's uneven chemistry load across a flame (its DLB motivation).
 """
 from __future__ import annotations
 
@@ -22,6 +31,7 @@ P_ATM = 101325.0
 
 FIELD_SEED_1 = 1001
 FIELD_SEED_2 = 2002
+FIELD_SEED_3 = 3003
 
 
 def premixed_h2_air(mech, phi):
@@ -62,3 +72,44 @@ def hot_kernel_field_2d(mech, nx=256, ny=256, seed=FIELD_SEED_2, n_kernels=8, T_
     n = T.size
     Y = np.repeat(premixed_h2_air(mech, 1.0), n, axis=1)
     return {"T": T, "p": np.full(n, float(p)), "Y": np.ascontiguousarray(Y), "shape": (ny, nx)}
+
+
+def _mole_to_mass(mech, moles):
+    W = np.asarray(mech.molar_mass, dtype=np.float64)
+    m = moles * W
+    return m / m.sum()
+
+
+def mixing_layer_3d(mech, n_side=100, seed=FIELD_SEED_3, delta=10.0, z_noise=0.02, T_noise=50.0,
+                    dt_range=(1e-7, 1e-5), p=P_ATM):
+    rng = np.random.default_rng(seed)
+    K = mech.n_species
+    iH2, iO2, iH2O, iN2 = mech.index("H2"), mech.index("O2"), mech.index("H2O"), mech.index("N2")
+    W = np.asarray(mech.molar_mass, dtype=np.float64)
+    xf = np.zeros(K)
+    xf[iH2], xf[iN2] = 0.5, 0.5
+    xo = np.zeros(K)
+    xo[iO2], xo[iN2] = 1.0, 3.76
+    Yf, Yo = _mole_to_mass(mech, xf), _mole_to_mass(mech, xo)
+    s_ox = 0.5 * W[iO2] / W[iH2]  # kg O2 per kg H2 at stoichiometry
+    z_st = Yo[iO2] / (s_ox * Yf[iH2] + Yo[iO2])
+    n = n_side ** 3
+    yidx = (np.arange(n) // n_side) % n_side  # cell index along y of a (z, y, x) grid
+    y0 = 0.5 * (n_side - 1)
+    Z = 0.5 * (1.0 - np.tanh((yidx - y0) / delta)) + rng.normal(0.0, z_noise, size=n)
+    Z = np.clip(Z, 0.0, 1.0)
+    Yu = Z[None, :] * Yf[:, None] + (1.0 - Z)[None, :] * Yo[:, None]
+    h2, o2 = Yu[iH2], Yu[iO2]
+    burn_h2 = np.minimum(h2, o2 / s_ox)  # H2 burnt, kg per kg of mixture
+    Yb = Yu.copy()
+    Yb[iH2] = h2 - burn_h2
+    Yb[iO2] = o2 - s_ox * burn_h2
+    Yb[iH2O] = Yu[iH2O] + (1.0 + s_ox) * burn_h2
+    c = np.exp(-((Z - z_st) / 0.1) ** 2)
+    Y = (1.0 - c)[None, :] * Yu + c[None, :] * Yb
+    Y = np.maximum(Y, 0.0)
+    Y /= Y.sum(axis=0, keepdims=True)
+    T = np.clip(300.0 + 2200.0 * c + rng.normal(0.0, T_noise, size=n), 300.0, 2500.0)
+    dt = np.exp(rng.uniform(np.log(dt_range[0]), np.log(dt_range[1]), size=n))
+    return {"T": T, "p": np.full(n, float(p)), "Y": np.ascontiguousarray(Y), "dt": dt, "Z": Z, "c": c,
+            "z_st": z_st, "shape": (n_side, n_side, n_side)}

@@ -26,6 +26,7 @@ def test_exports_every_declared_symbol(L):
 def test_default_opts(L):
     o = df.chem_opts()
     assert (o.rtol, o.atol_T, o.atol_Y, o.h_min, o.max_steps, o.mapping) == (1e-8, 1e-6, 1e-14, 1e-20, 100000, 0)
+    assert (o.schedule, o.coop_blocks) == (0, 0)
     d = df.dnn_opts()
     assert (d.renormalise, d.fallback) == (1, 1)
 
@@ -46,6 +47,19 @@ def test_chem_step_host_checks(L):
     assert L.df_chem_step(None, 1, 1, 1e-6, None, None, None, None, None, None, None, None, 0, C.byref(o), None) \
         == _lib.DF_E_INVALID
     assert b"null mechanism" in L.df_last_error()
+
+
+def test_chem_step_cells_and_autotune_host_checks(L):
+    o = df.chem_opts()
+    # per-cell step lengths: a null dt array is refused before anything else
+    assert L.df_chem_step_cells(None, 1, 1, None, None, None, None, None, None, None, None, None, 0, C.byref(o),
+                                None) == _lib.DF_E_INVALID
+    assert b"null dt" in L.df_last_error()
+    b = C.c_size_t()
+    assert L.df_chem_autotune_workspace_size(None, 1, C.byref(b)) == _lib.DF_E_INVALID
+    assert L.df_chem_autotune(None, 1, 1, 1e-6, None, None, None, None, None, 0, C.byref(o), None) \
+        == _lib.DF_E_INVALID
+    assert L.df_chem_autotune(None, 1, 1, 1e-6, None, None, None, None, None, 0, None, None) == _lib.DF_E_INVALID
 
 
 def test_dnn_step_host_checks(L):
