@@ -73,6 +73,10 @@ def lib():
     L.orc_chem_step_dt.restype = C.c_int
     L.orc_chem_step_dt.argtypes = [vp, C.c_int64, C.c_int64, C.c_double, dp, dp, dp, dp, dp, dp, ip, ip, ip,
                                    C.POINTER(_Opts), C.c_int]
+    L.orc_chem_cell_record.restype = C.c_int
+    L.orc_chem_cell_record.argtypes = [vp, C.c_double, C.c_double, dp, C.POINTER(_Opts), dp, C.c_int32, ip, ip]
+    L.orc_chem_replay.argtypes = [vp, C.c_double, dp, dp, C.c_int32]
+    L.orc_mech_scale_A.argtypes = [vp, C.c_int32, C.c_double]
     L.orc_dnn_load.restype = vp
     L.orc_dnn_load.argtypes = [C.c_char_p]
     L.orc_dnn_free.argtypes = [vp]
@@ -184,6 +188,28 @@ class Mech:
         if ret < 0:
             raise ValueError("oracle chem_step: bad arguments")
         return {"T": T, "Y": Y, "h": h, "rr": rr, "status": st, "n_acc": na, "n_rej": nr}
+
+    def record(self, T, p, Y, dt, opts=None, cap=100000):
+        """Integrate one cell (T, Y[K]) over dt from a fresh start; returns (T, Y, status, h_list, n_rej)
+        with h_list the lengths of the accepted sub-steps."""
+        y = np.concatenate([[float(T)], np.asarray(Y, dtype=np.float64)])
+        hs = np.zeros(cap)
+        na, nr = np.zeros(1, np.int32), np.zeros(1, np.int32)
+        o = opts if opts is not None else default_opts()
+        st = lib().orc_chem_cell_record(self._h, float(dt), float(p), _dp(y), C.byref(o), _dp(hs), int(cap),
+                                        _ip(na), _ip(nr))
+        return y[0], y[1:].copy(), int(st), hs[:min(int(na[0]), cap)].copy(), int(nr[0])
+
+    def replay(self, p, y0, hs):
+        """The fixed sequence of RODAS4 sub-steps of lengths hs from y0 = (T, Y) (no error control)."""
+        y = np.array(y0, dtype=np.float64, copy=True)
+        hs = np.ascontiguousarray(hs, dtype=np.float64)
+        lib().orc_chem_replay(self._h, float(p), _dp(y), _dp(hs), int(hs.size))
+        return y
+
+    def scale_A(self, j, factor):
+        """Multiply the pre-exponential factor of reaction j (k_inf for Troe rows) by factor, in place."""
+        lib().orc_mech_scale_A(self._h, int(j), float(factor))
 
 
 def rodas4_tableau():

@@ -520,8 +520,75 @@ typedef void (*jac_fn)(void *ctx, const double *y, double *J);
  * h_next is the controller's step proposal in force when the final step was
  * taken (before it was shortened to land on dt).
  */
+/*
+ * One RODAS4 attempt of length ht from y, with f0 = f(y): writes the new state
+ * yn and the embedded error vector ev, and returns the weighted RMS error
+ * norm (scale atol_i + rtol max(|y_i|, |yn_i|)), or +inf when the iteration
+ * matrix is singular.  Work arrays: J, Wm (N*N), u (NS*N), ys, fs (N), piv.
+ */
+static double ros_attempt(int N, const double *y, const double *f0, double ht, const double *atol, double rtol,
+                          rhs_fn rhs, jac_fn jac, void *ctx, double *J, double *Wm, double *u, double *ys, double *fs,
+                          int *piv, double *yn, double *ev) {
+    jac(ctx, y, J);
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) Wm[i * N + j] = (i == j ? 1.0 / (ROS_GAMMA * ht) : 0.0) - J[i * N + j];
+    if (lu_factor(N, Wm, piv) != 0) return INFINITY;
+    for (int s = 0; s < NS; ++s) {
+        double *us = &u[s * N];
+        if (s == 0) {
+            for (int i = 0; i < N; ++i) fs[i] = f0[i];
+        } else {
+            for (int i = 0; i < N; ++i) {
+                double v = y[i];
+                for (int j = 0; j < s; ++j) v += ROS_A[s][j] * u[j * N + i];
+                ys[i] = v;
+            }
+            rhs(ctx, ys, fs);
+        }
+        for (int i = 0; i < N; ++i) {
+            double v = fs[i];
+            for (int j = 0; j < s; ++j) v += (ROS_C[s][j] / ht) * u[j * N + i];
+            us[i] = v;
+        }
+        lu_solve(N, Wm, piv, us);
+    }
+    for (int i = 0; i < N; ++i) {
+        double v = y[i], e = 0.0;
+        for (int s = 0; s < NS; ++s) {
+            v += ROS_M[s] * u[s * N + i];
+            e += (ROS_M[s] - ROS_MHAT[s]) * u[s * N + i];
+        }
+        yn[i] = v;
+        ev[i] = e;
+    }
+    if (!atol) return 0.0;
+    double sum = 0.0;
+    for (int i = 0; i < N; ++i) {
+        double ay = fabs(y[i]), an = fabs(yn[i]);
+        double sc = atol[i] + rtol * (ay > an ? ay : an);
+        sum += (ev[i] / sc) * (ev[i] / sc);
+    }
+    return sqrt(sum / N);
+}
+
+/*
+ * Adaptive RODAS4 integration of y' = f(y) over [0, dt].
+ *  - initial step: h_in if > 0 (capped at dt), else 0.01 |y|/|f(y)| in the
+ *    weighted RMS norm (dt if f = 0), at least h_min;
+ *  - the last step is shortened to land exactly on dt;
+ *  - weighted RMS error norm with scale atol_i + rtol max(|y_i|, |ynew_i|);
+ *  - accept if err <= 1; new h = h * min(fmax, max(0.2, 0.9 err^(-1/4)))
+ *    with fmax = 6, or 1 right after a rejection; a non-finite error is a
+ *    rejection with factor 0.2;
+ *  - stops with MAX_STEPS after max_steps attempts, H_UNDERFLOW when a
+ *    rejection pushes h below h_min.
+ * h_next is the controller's step proposal in force when the final step was
+ * taken (before it was shortened to land on dt).  When h_rec is given, the
+ * length of accepted step s is stored in h_rec[s] for s < rec_cap.
+ */
 static int ros_integrate(int N, double *y, double dt, double h_in, const double *atol, double rtol, double h_min,
-                         int max_steps, rhs_fn rhs, jac_fn jac, void *ctx, double *h_next, int *n_acc, int *n_rej) {
+                         int max_steps, rhs_fn rhs, jac_fn jac, void *ctx, double *h_next, int *n_acc, int *n_rej,
+                         double *h_rec, int rec_cap) {
     double *J = (double *)malloc(sizeof(double) * N * N);
     double *Wm = (double *)malloc(sizeof(double) * N * N);
     double *u = (double *)malloc(sizeof(double) * NS * N);
@@ -555,50 +622,7 @@ static int ros_integrate(int N, double *y, double dt, double h_in, const double 
         if (acc + rej >= max_steps) { status = ORC_MAX_STEPS; break; }
         int last = (t + h >= dt);
         double ht = last ? dt - t : h;
-        double err;
-
-        jac(ctx, y, J);
-        for (int i = 0; i < N; ++i)
-            for (int j = 0; j < N; ++j) Wm[i * N + j] = (i == j ? 1.0 / (ROS_GAMMA * ht) : 0.0) - J[i * N + j];
-        if (lu_factor(N, Wm, piv) != 0) {
-            err = INFINITY;
-        } else {
-            for (int s = 0; s < NS; ++s) {
-                double *us = &u[s * N];
-                if (s == 0) {
-                    for (int i = 0; i < N; ++i) fs[i] = f0[i];
-                } else {
-                    for (int i = 0; i < N; ++i) {
-                        double v = y[i];
-                        for (int j = 0; j < s; ++j) v += ROS_A[s][j] * u[j * N + i];
-                        ys[i] = v;
-                    }
-                    rhs(ctx, ys, fs);
-                }
-                for (int i = 0; i < N; ++i) {
-                    double v = fs[i];
-                    for (int j = 0; j < s; ++j) v += (ROS_C[s][j] / ht) * u[j * N + i];
-                    us[i] = v;
-                }
-                lu_solve(N, Wm, piv, us);
-            }
-            for (int i = 0; i < N; ++i) {
-                double v = y[i], e = 0.0;
-                for (int s = 0; s < NS; ++s) {
-                    v += ROS_M[s] * u[s * N + i];
-                    e += (ROS_M[s] - ROS_MHAT[s]) * u[s * N + i];
-                }
-                yn[i] = v;
-                ev[i] = e;
-            }
-            double sum = 0.0;
-            for (int i = 0; i < N; ++i) {
-                double ay = fabs(y[i]), an = fabs(yn[i]);
-                double sc = atol[i] + rtol * (ay > an ? ay : an);
-                sum += (ev[i] / sc) * (ev[i] / sc);
-            }
-            err = sqrt(sum / N);
-        }
+        double err = ros_attempt(N, y, f0, ht, atol, rtol, rhs, jac, ctx, J, Wm, u, ys, fs, piv, yn, ev);
 
         double fmax = prev_rejected ? 1.0 : 6.0;
         double fac;
@@ -611,6 +635,7 @@ static int ros_integrate(int N, double *y, double dt, double h_in, const double 
         }
 
         if (isfinite(err) && err <= 1.0) {
+            if (h_rec && acc < rec_cap) h_rec[acc] = ht;
             ++acc;
             for (int i = 0; i < N; ++i) y[i] = yn[i];
             h_final = h;
@@ -655,7 +680,8 @@ int orc_linear_integrate(int n, const double *A, double *y, double dt, double h_
                          double *h_next, int32_t *n_acc, int32_t *n_rej) {
     lin_ctx c = {n, A};
     int a = 0, r = 0;
-    int st = ros_integrate(n, y, dt, h_in, atol, o->rtol, o->h_min, o->max_steps, lin_rhs, lin_jac, &c, h_next, &a, &r);
+    int st = ros_integrate(n, y, dt, h_in, atol, o->rtol, o->h_min, o->max_steps, lin_rhs, lin_jac, &c, h_next, &a, &r,
+                           NULL, 0);
     if (n_acc) *n_acc = a;
     if (n_rej) *n_rej = r;
     return st;
@@ -730,7 +756,7 @@ static int chem_cell(const orc_mech *m, double dt, double p, double *y, double *
     chem_ctx c = {m, p};
     double h_in = h_io ? *h_io : 0.0, h_next = 0.0;
     int st = ros_integrate(N, y, dt, h_in, atol, o->rtol, o->h_min, o->max_steps, chem_rhs, chem_jac, &c, &h_next,
-                           acc, rej);
+                           acc, rej, NULL, 0);
     if (h_io) *h_io = h_next;
     return st;
 }
@@ -779,6 +805,49 @@ int orc_chem_step_dt(const orc_mech *m, int64_t n, int64_t ld, double dt, const 
         if (st != ORC_OK) fails += 1;
     }
     return fails;
+}
+
+/*
+ * Sensitivities of the step (test support): the integration of one cell from
+ * a fresh start (no step hint), recording the length of every accepted
+ * sub-step; the replay of such a recorded sequence without error control
+ * (the same arithmetic as the accepted attempts, so a replay of a cell's own
+ * record reproduces its result exactly); and a scaling of one reaction's
+ * pre-exponential factor (for Troe rows the high-pressure limit), for finite
+ * differences in ln A.
+ */
+int orc_chem_cell_record(const orc_mech *m, double dt, double p, double *y, const orc_opts *opts, double *h_rec,
+                         int32_t rec_cap, int32_t *n_acc, int32_t *n_rej) {
+    orc_opts o = default_opts(opts);
+    int K = m->K, N = K + 1;
+    double atol[ORC_MAX_SPECIES + 1];
+    atol[0] = o.atol_T;
+    for (int k = 0; k < K; ++k) atol[1 + k] = o.atol_Y;
+    chem_ctx c = {m, p};
+    int a = 0, r = 0;
+    int st = ros_integrate(N, y, dt, 0.0, atol, o.rtol, o.h_min, o.max_steps, chem_rhs, chem_jac, &c, NULL, &a, &r,
+                           h_rec, rec_cap);
+    if (n_acc) *n_acc = a;
+    if (n_rej) *n_rej = r;
+    return st;
+}
+
+void orc_chem_replay(const orc_mech *m, double p, double *y, const double *hs, int32_t nh) {
+    int N = m->K + 1;
+    chem_ctx c = {m, p};
+    double J[(ORC_MAX_SPECIES + 1) * (ORC_MAX_SPECIES + 1)], Wm[(ORC_MAX_SPECIES + 1) * (ORC_MAX_SPECIES + 1)];
+    double u[NS * (ORC_MAX_SPECIES + 1)], f0[ORC_MAX_SPECIES + 1], ys[ORC_MAX_SPECIES + 1], fs[ORC_MAX_SPECIES + 1];
+    double yn[ORC_MAX_SPECIES + 1], ev[ORC_MAX_SPECIES + 1];
+    int piv[ORC_MAX_SPECIES + 1];
+    for (int s = 0; s < nh; ++s) {
+        chem_rhs(&c, y, f0);
+        ros_attempt(N, y, f0, hs[s], NULL, 0.0, chem_rhs, chem_jac, &c, J, Wm, u, ys, fs, piv, yn, ev);
+        for (int i = 0; i < N; ++i) y[i] = yn[i];
+    }
+}
+
+void orc_mech_scale_A(orc_mech *m, int32_t j, double factor) {
+    if (m && j >= 0 && j < m->M) m->arr[3 * j] *= factor;
 }
 
 /* ------------------------------------------------------------------------- */

@@ -78,6 +78,16 @@ void orc_jacobian(const orc_mech *m, double p, const double *y, double *J);
 /* RODAS4 coefficients in transformed form: gamma, a[6*6], c[6*6], m[6], mhat[6] */
 void orc_rodas4_tableau(double *gamma, double *a, double *c, double *mm, double *mhat);
 
+/* sensitivities of the step (test support): integrate one cell y = (T, Y) in
+ * place from a fresh start, recording accepted sub-step lengths in
+ * h_rec[0 .. min(n_acc, rec_cap)); replay nh fixed RODAS4 sub-steps of
+ * lengths hs from y (no error control); scale A of reaction j (k_inf for
+ * Troe rows) by factor */
+int orc_chem_cell_record(const orc_mech *m, double dt, double p, double *y, const orc_opts *opts, double *h_rec,
+                         int32_t rec_cap, int32_t *n_acc, int32_t *n_rej);
+void orc_chem_replay(const orc_mech *m, double p, double *y, const double *hs, int32_t nh);
+void orc_mech_scale_A(orc_mech *m, int32_t j, double factor);
+
 /* Adaptive integration of y' = A y over dt (tests of the integrator core). */
 int orc_linear_integrate(int n, const double *A, double *y, double dt, double h_in, const orc_opts *o,
                          double *atol, double *h_next, int32_t *n_acc, int32_t *n_rej);
