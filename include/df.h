@@ -59,6 +59,8 @@ typedef int32_t df_status;
                                   temperature recovery did not converge */
 #define DF_CELL_DNN_FALLBACK 4 /* DNN form: cell outside the network's training range, advanced by
                                   the integrator instead (success) */
+#define DF_CELL_TAPE_FULL 5    /* taped step: more accepted sub-steps than the tape holds; state as
+                                  integrated, no tape (the adjoint gives zero gradients) */
 
 typedef struct df_mech df_mech; /* opaque mechanism handle */
 typedef struct df_dnn df_dnn;   /* opaque DNN handle */
@@ -183,6 +185,65 @@ df_status df_chem_autotune_workspace_size(const df_mech *mech, int64_t n_cells, 
 df_status df_chem_autotune(const df_mech *mech, int64_t n_cells, int64_t ld, double dt, const double *dt_cells,
                            const double *p, const double *T, const double *Y, void *workspace, size_t workspace_bytes,
                            df_chem_opts *opts, void *hip_stream);
+
+/*
+ * ---- Discrete adjoint of the chemistry step ----
+ * Gradients of the state after one chemistry step with respect to the state before it and to
+ * the log pre-exponential factors (the integration of the source-term equation of Sec.
+ * "Chemistry Integration" as df_chem_step does it, differentiated).  The step is the sequence
+ * of accepted RODAS4 sub-steps that df_chem_step_taped took, with their lengths held fixed
+ * (the step-size controller's choices are not differentiated), so the gradient is the exact
+ * derivative of the computed result, up to rounding.
+ *
+ * Bytes of tape (the adjoint's checkpoints: the start state and length of each accepted
+ * sub-step) for n_cells and at most max_substeps accepted sub-steps per cell:
+ * 8 max_substeps (K + 2) n_cells + 4 n_cells.
+ */
+df_status df_chem_tape_size(const df_mech *mech, int64_t n_cells, int32_t max_substeps, size_t *bytes);
+
+/*
+ * df_chem_step (one cell per lane, each cell from a fresh start: no sub-step hint, no rr)
+ * that also records the tape for df_chem_adjoint.
+ *   p, T, Y, cell_status, n_steps, opts: as df_chem_step
+ *   tape          device memory of df_chem_tape_size(mech, n_cells, max_substeps) bytes,
+ *                 256-byte aligned, written; keep it (and p) unchanged until the adjoint ran.
+ *                 Layout, with N = K + 1 and S = max_substeps: f64 [S][N][n_cells] start
+ *                 states, f64 [S][n_cells] sub-step lengths, int32 [n_cells] sub-step counts
+ *                 (-1: the cell has no tape).
+ * A cell with more accepted sub-steps than max_substeps keeps its integrated state and gets
+ * DF_CELL_TAPE_FULL (no tape); cells that fail as in df_chem_step get no tape either.
+ * Errors: DF_E_INVALID (as df_chem_step; max_substeps < 1; tape null, too small or misaligned),
+ * DF_E_UNSUPPORTED (no adjoint kernel for the species count, or its per-lane tables do not fit
+ * in 64 KiB of LDS), DF_E_HIP.
+ */
+df_status df_chem_step_taped(const df_mech *mech, int64_t n_cells, int64_t ld, double dt, const double *p,
+                             double *T, double *Y, int32_t *cell_status, int32_t *n_steps, void *tape,
+                             size_t tape_bytes, int32_t max_substeps, const df_chem_opts *opts, void *hip_stream);
+
+/* Bytes of device workspace df_chem_adjoint needs for n_cells: 8 n_cells (12 N + N^2 + N + M). */
+df_status df_chem_adjoint_workspace_size(const df_mech *mech, int64_t n_cells, size_t *bytes);
+
+/*
+ * Reverse sweep: given the adjoint (T_bar, Y_bar) of the state after the taped step (for a
+ * scalar loss L, dL/dT and dL/dY), return the adjoint of the state before it and of ln A:
+ *   (T0_bar, Y0_bar) = (dy/dy0)^T (T_bar, Y_bar) and lnA_bar = (dy/dlnA)^T (T_bar, Y_bar) per cell.
+ *   p              [n]           in    the pressures the taped step used
+ *   tape, max_substeps                 as written by df_chem_step_taped for the same n_cells
+ *   T_bar [n], Y_bar [K*ld]      in    seeds
+ *   T0_bar [n], Y0_bar [K*ld]    out   adjoint of (T0, Y0)
+ *   lnA_bar_cells [M*ld]         out   per cell, d L / d ln A_j (row j in the mechanism file's
+ *                                      reaction order; k_inf's A for falloff rows) (nullable)
+ *   lnA_bar [M]                  out   the same summed over cells, in a fixed order (nullable)
+ *   workspace     device memory of df_chem_adjoint_workspace_size bytes, 256-byte aligned
+ * Cells without a tape get zero gradients.  Inputs are not modified.  The tape, the seeds and
+ * the outputs are caller-owned device memory; nothing is kept after the call.
+ * Errors: DF_E_INVALID (null handle/array, n < 0, ld < n, max_substeps < 1, tape or workspace
+ * too small or misaligned), DF_E_UNSUPPORTED, DF_E_HIP.
+ */
+df_status df_chem_adjoint(const df_mech *mech, int64_t n_cells, int64_t ld, const double *p, const void *tape,
+                          size_t tape_bytes, int32_t max_substeps, const double *T_bar, const double *Y_bar,
+                          double *T0_bar, double *Y0_bar, double *lnA_bar_cells, double *lnA_bar, void *workspace,
+                          size_t workspace_bytes, void *hip_stream);
 
 /*
  * Load a DNN weights file ("DFDNN01", little-endian: int32 L, dims[L+1], K,

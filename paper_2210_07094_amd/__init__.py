@@ -12,10 +12,10 @@ from __future__ import annotations
 
 import ctypes as C
 
-from ._lib import (CELL_DNN_FALLBACK, CELL_H_UNDERFLOW, CELL_MAX_STEPS, CELL_NONFINITE, CELL_OK, ChemOpts,  # noqa
-                   DfError, DnnOpts, check, lib)
+from ._lib import (CELL_DNN_FALLBACK, CELL_H_UNDERFLOW, CELL_MAX_STEPS, CELL_NONFINITE, CELL_OK,  # noqa
+                   CELL_TAPE_FULL, ChemOpts, DfError, DnnOpts, check, lib)
 
-__all__ = ["Mechanism", "DNN", "chem_opts", "dnn_opts", "DfError", "lib"]
+__all__ = ["Mechanism", "DNN", "chem_opts", "dnn_opts", "chem_step_diff", "DfError", "lib"]
 
 
 def chem_opts(**kw) -> ChemOpts:
@@ -151,6 +151,113 @@ class Mechanism:
                                      _ptr(Y, torch.float64, "Y", K * ld, dev), _ptr(ws, torch.uint8, "ws", None, dev),
                                      ws.numel(), C.byref(o), _stream(stream)))
         return o
+
+    # ---- discrete adjoint (df_chem_step_taped / df_chem_adjoint)
+
+    def tape_bytes(self, n_cells: int, max_substeps: int) -> int:
+        b = C.c_size_t()
+        check(lib().df_chem_tape_size(self._h, int(n_cells), int(max_substeps), C.byref(b)))
+        return b.value
+
+    def chem_step_taped(self, T, p, Y, dt, max_substeps=2048, status=None, n_steps=None, opts=None, stream=None):
+        """df_chem_step (each cell from a fresh start) that records the adjoint's tape; T, Y in
+        place.  Returns the tape (uint8 device tensor) for chem_adjoint."""
+        import torch
+        n = T.numel()
+        K = self.n_species
+        if Y.dim() != 2 or Y.shape[0] != K:
+            raise ValueError(f"Y must have shape [{K}, ld]")
+        ld = Y.shape[1]
+        dev = self.device
+        tape = torch.empty(max(self.tape_bytes(n, max_substeps), 1), dtype=torch.uint8, device=f"cuda:{dev}")
+        check(lib().df_chem_step_taped(self._h, n, ld, float(dt), _ptr(p, torch.float64, "p", n, dev),
+                                       _ptr(T, torch.float64, "T", n, dev), _ptr(Y, torch.float64, "Y", K * ld, dev),
+                                       _ptr(status, torch.int32, "status", n, dev),
+                                       _ptr(n_steps, torch.int32, "n_steps", 2 * n, dev),
+                                       _ptr(tape, torch.uint8, "tape", None, dev), tape.numel(), int(max_substeps),
+                                       C.byref(opts) if opts is not None else None, _stream(stream)))
+        return tape
+
+    def chem_adjoint(self, p, tape, max_substeps, T_bar, Y_bar, per_cell=True, summed=True, stream=None):
+        """Reverse sweep over a tape (df_chem_adjoint).  T_bar [n], Y_bar [K, ld] seeds.  Returns
+        (T0_bar [n], Y0_bar [K, ld], lnA_bar_cells [M, ld] or None, lnA_bar [M] or None)."""
+        import torch
+        n = T_bar.numel()
+        K, M = self.n_species, self.n_reactions
+        if Y_bar.dim() != 2 or Y_bar.shape[0] != K:
+            raise ValueError(f"Y_bar must have shape [{K}, ld]")
+        ld = Y_bar.shape[1]
+        dev = self.device
+        opt = dict(dtype=torch.float64, device=f"cuda:{dev}")
+        T0b = torch.empty(n, **opt)
+        Y0b = torch.empty(K, ld, **opt)
+        thc = torch.empty(M, ld, **opt) if per_cell else None
+        ths = torch.empty(M, **opt) if summed else None
+        b = C.c_size_t()
+        check(lib().df_chem_adjoint_workspace_size(self._h, n, C.byref(b)))
+        ws = torch.empty(max(b.value, 1), dtype=torch.uint8, device=f"cuda:{dev}")
+        check(lib().df_chem_adjoint(self._h, n, ld, _ptr(p, torch.float64, "p", n, dev),
+                                    _ptr(tape, torch.uint8, "tape", None, dev), tape.numel(), int(max_substeps),
+                                    _ptr(T_bar, torch.float64, "T_bar", n, dev),
+                                    _ptr(Y_bar, torch.float64, "Y_bar", K * ld, dev),
+                                    _ptr(T0b, torch.float64, "T0_bar", n, dev),
+                                    _ptr(Y0b, torch.float64, "Y0_bar", K * ld, dev),
+                                    _ptr(thc, torch.float64, "lnA_bar_cells", M * ld, dev),
+                                    _ptr(ths, torch.float64, "lnA_bar", M, dev),
+                                    _ptr(ws, torch.uint8, "workspace", None, dev), ws.numel(), _stream(stream)))
+        return T0b, Y0b, thc, ths
+
+
+def _chem_step_function():
+    import torch
+
+    class ChemStepFunction(torch.autograd.Function):
+        """(T0, Y0, lnA) -> (T, Y) after one chemistry step; backward = the discrete adjoint."""
+
+        @staticmethod
+        def forward(ctx, T0, Y0, lnA, mech, p, dt, max_substeps, opts):
+            T = T0.detach().clone()
+            Y = Y0.detach().contiguous().clone()
+            status = torch.empty(T.numel(), dtype=torch.int32, device=T.device)
+            tape = mech.chem_step_taped(T, p, Y, dt, max_substeps=max_substeps, status=status, opts=opts)
+            ctx.mech, ctx.max_substeps = mech, max_substeps
+            ctx.save_for_backward(p, tape)
+            ctx.status = status
+            return T, Y
+
+        @staticmethod
+        def backward(ctx, gT, gY):
+            p, tape = ctx.saved_tensors
+            mech = ctx.mech
+            n = p.numel()
+            gT = torch.zeros(n, dtype=torch.float64, device=p.device) if gT is None else gT.contiguous()
+            gY = (torch.zeros(mech.n_species, n, dtype=torch.float64, device=p.device) if gY is None
+                  else gY.contiguous())
+            want_lnA = ctx.needs_input_grad[2]
+            T0b, Y0b, _, lnAb = mech.chem_adjoint(p, tape, ctx.max_substeps, gT, gY, per_cell=False, summed=want_lnA)
+            return T0b, Y0b, lnAb, None, None, None, None, None
+
+    return ChemStepFunction
+
+
+_ChemStepFunction = None
+
+
+def chem_step_diff(mech: Mechanism, T0, Y0, p, dt, lnA=None, max_substeps=2048, opts=None):
+    """Differentiable chemistry step: returns (T, Y) after dt, with gradients to T0 [n], Y0 [K, n]
+    and, when lnA is given, to it.  lnA is a float64 device tensor [M] standing for the natural
+    logs of the mechanism's pre-exponential factors (k_inf's for falloff rows) in the file's
+    reaction order; the step uses the loaded mechanism, so lnA only receives d loss / d ln A
+    (summed over cells).  Backward runs df_chem_adjoint over the tape of the forward step; cells
+    whose step failed or overflowed max_substeps get zero gradients (Mechanism.chem_step_taped
+    reports the per-cell status)."""
+    global _ChemStepFunction
+    import torch
+    if _ChemStepFunction is None:
+        _ChemStepFunction = _chem_step_function()
+    if lnA is None:
+        lnA = torch.zeros(mech.n_reactions, dtype=torch.float64, device=T0.device)
+    return _ChemStepFunction.apply(T0, Y0, lnA, mech, p, dt, max_substeps, opts)
 
 
 class DNN:

@@ -19,6 +19,7 @@ CELL_MAX_STEPS = 1
 CELL_H_UNDERFLOW = 2
 CELL_NONFINITE = 3
 CELL_DNN_FALLBACK = 4
+CELL_TAPE_FULL = 5
 
 
 class ChemOpts(C.Structure):
@@ -47,6 +48,11 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2210_07094_amd.build`")
+    # torch brings its own HIP runtime; it has to be initialised before the library's first HIP
+    # call, or torch no longer sees the device in this process
+    import torch
+    if torch.cuda.is_available():
+        torch.cuda.init()
     L = C.CDLL(LIB_PATH)
     vp, i32, i64, d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     L.df_last_error.restype = C.c_char_p
@@ -67,6 +73,15 @@ def lib():
     L.df_chem_autotune_workspace_size.argtypes = [vp, i64, C.POINTER(C.c_size_t)]
     L.df_chem_autotune.restype = i32
     L.df_chem_autotune.argtypes = [vp, i64, i64, d, vp, vp, vp, vp, vp, C.c_size_t, C.POINTER(ChemOpts), vp]
+    L.df_chem_tape_size.restype = i32
+    L.df_chem_tape_size.argtypes = [vp, i64, i32, C.POINTER(C.c_size_t)]
+    L.df_chem_step_taped.restype = i32
+    L.df_chem_step_taped.argtypes = [vp, i64, i64, d, vp, vp, vp, vp, vp, vp, C.c_size_t, i32, C.POINTER(ChemOpts),
+                                     vp]
+    L.df_chem_adjoint_workspace_size.restype = i32
+    L.df_chem_adjoint_workspace_size.argtypes = [vp, i64, C.POINTER(C.c_size_t)]
+    L.df_chem_adjoint.restype = i32
+    L.df_chem_adjoint.argtypes = [vp, i64, i64, vp, vp, C.c_size_t, i32, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]
     L.df_chem_step_cells.restype = i32
     L.df_chem_step_cells.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t,
                                      C.POINTER(ChemOpts), vp]

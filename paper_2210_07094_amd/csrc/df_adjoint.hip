@@ -1,0 +1,620 @@
+// Discrete adjoint of the detailed-chemistry step on gfx950: one cell per lane, FP64.
+//
+// The step y0 = (T0, Y0) -> y(dt) is the sequence of accepted RODAS4 sub-steps of the taped
+// forward integration (df_chem_step_taped), with the step lengths held fixed: the
+// controller's choices are part of the sequence and are not differentiated.  One sub-step
+// from y with length h is
+//   W = I/(g h) - J(y),   Y_i = y + sum_{j<i} a_ij u_j,
+//   W u_i = f(Y_i) + (1/h) sum_{j<i} c_ij u_j,   y_new = y + sum_i b_i u_i
+// (b_i = a_5i for i < 5, b_5 = 1: the new state is the stage-6 state plus u_5).  Given the
+// adjoint lam of y_new, the reverse sweep over the sub-steps, last to first, recomputes the
+// stages from the checkpointed start state and sets
+//   ubar_i = b_i lam,  ybar = lam;  for i = 5 .. 0:
+//     rbar = W^-T ubar_i
+//     v = J(Y_i)^T rbar:  ybar += v,  ubar_j += a_ij v + (c_ij / h) rbar   (j < i)
+//     thbar += (df/dlnA)(Y_i)^T rbar
+//     ybar += grad_y <rbar, J(y) u_i>,  thbar += grad_lnA <rbar, J(y) u_i>
+//   lam = ybar
+// The last line is the derivative of the iteration matrix: W depends on y through J.  The
+// products with J^T are vector-Jacobian products of f written out in reverse mode (no
+// Jacobian is formed), and the second-order terms are the same products evaluated in
+// dual-number arithmetic at y + eps u_i, whose eps part is the directional derivative
+// (a Hessian-vector product of <rbar, f>).  ln A is the natural log of the pre-exponential
+// factor of each reaction, k_inf's for falloff rows.
+#include <cmath>
+
+#include "df_internal.h"
+#include "df_kinetics.h"
+#include "df_lane.h"
+
+namespace df {
+namespace {
+
+// ---- dual numbers: value v and derivative d along one direction
+struct Dual {
+    double v, d;
+};
+__device__ __forceinline__ Dual operator+(Dual a, Dual b) { return {a.v + b.v, a.d + b.d}; }
+__device__ __forceinline__ Dual operator+(Dual a, double b) { return {a.v + b, a.d}; }
+__device__ __forceinline__ Dual operator+(double a, Dual b) { return {a + b.v, b.d}; }
+__device__ __forceinline__ Dual operator-(Dual a, Dual b) { return {a.v - b.v, a.d - b.d}; }
+__device__ __forceinline__ Dual operator-(Dual a, double b) { return {a.v - b, a.d}; }
+__device__ __forceinline__ Dual operator-(double a, Dual b) { return {a - b.v, -b.d}; }
+__device__ __forceinline__ Dual operator-(Dual a) { return {-a.v, -a.d}; }
+__device__ __forceinline__ Dual operator*(Dual a, Dual b) { return {a.v * b.v, fma(a.v, b.d, a.d * b.v)}; }
+__device__ __forceinline__ Dual operator*(Dual a, double b) { return {a.v * b, a.d * b}; }
+__device__ __forceinline__ Dual operator*(double a, Dual b) { return {a * b.v, a * b.d}; }
+__device__ __forceinline__ Dual &operator+=(Dual &a, Dual b) { return a = a + b; }
+__device__ __forceinline__ Dual &operator-=(Dual &a, Dual b) { return a = a - b; }
+__device__ __forceinline__ Dual rcp(Dual a) {
+    const double r = 1.0 / a.v;
+    return {r, -a.d * r * r};
+}
+__device__ __forceinline__ double rcp(double a) { return 1.0 / a; }
+__device__ __forceinline__ Dual sexp(Dual a) {
+    const double e = exp(a.v);
+    return {e, a.d * e};
+}
+__device__ __forceinline__ double sexp(double a) { return exp(a); }
+__device__ __forceinline__ Dual slog(Dual a) { return {log(a.v), a.d / a.v}; }
+__device__ __forceinline__ double slog(double a) { return log(a); }
+template <class S>
+__device__ __forceinline__ S mk(double v) {
+    return S(v);
+}
+template <>
+__device__ __forceinline__ Dual mk<Dual>(double v) {
+    return Dual{v, 0.0};
+}
+// the part of a product accumulated into a gradient: the value for plain numbers; for duals the
+// derivative, plus the value when the first-order term is wanted too
+__device__ __forceinline__ double part(double x, bool) { return x; }
+__device__ __forceinline__ double part(Dual x, bool with_value) { return with_value ? x.v + x.d : x.d; }
+
+// LDS of one lane: element k of an array at base[k * kWave]
+template <class S>
+__device__ __forceinline__ S &at(S *base, int k) {
+    return base[k * kWave];
+}
+// the concentration arrays of the products are laid out as one dual per lane and slot; the
+// plain-number product uses the value half of its lane's slots (element k at base[k * 2 kWave])
+template <class S>
+__device__ __forceinline__ S &slot(S *base, int k) {
+    return base[k * kWave * int(sizeof(Dual) / sizeof(S))];
+}
+// arrays in the Cell region keep its layout, one double per lane in each wave-wide row: a plain
+// number takes row k, a dual rows 2k (value) and 2k + 1 (derivative)
+__device__ __forceinline__ double rget(const double *b, int k, double) { return b[k * kWave]; }
+__device__ __forceinline__ Dual rget(const double *b, int k, Dual) { return {b[2 * k * kWave], b[(2 * k + 1) * kWave]}; }
+__device__ __forceinline__ void rput(double *b, int k, double x) { b[k * kWave] = x; }
+__device__ __forceinline__ void rput(double *b, int k, Dual x) {
+    b[2 * k * kWave] = x.v;
+    b[(2 * k + 1) * kWave] = x.d;
+}
+
+// Reverse-mode product of lam with the Jacobian of f at y (the reactor right-hand side of
+// Cell<K>::rhs): yb = J(y)^T lam, and for each reaction j (stored order)
+// th[j] += part(lam . df/dlnA_j).  cs, cb: the lane's LDS slots (see slot()) of concentrations
+// and their adjoints (N elements, element 0 the neutral slot); om, wd: the lane's rows (see
+// rget()) of the adjoint weights of the production rates and the production rates (K
+// elements); th: M doubles.
+//   f_k = (1e6/rho) W_k wd_k,  f_T = -sum_k hm_k f_k / cp,  wd_k = sum_j nu_kj q_j,
+//   q_j = Mq (kf prod c^nu' - kf/Kc prod c^nu''),  c_k = 1e-6 rho Y_k / W_k.
+// The equilibrium constant and the reaction enthalpy come from the per-reaction coefficient
+// rows over (1, ln T, 1/T, T, .., T^4), so no per-species thermo is live in the reaction loop.
+template <int K, class S>
+__device__ void vjp(const MechDev &m, double p, const S (&y)[K + 1], const double (&lam)[K + 1], S *cs, S *cb,
+                    double *om, double *wd, double *th, bool with_value, S (&yb)[K + 1]) {
+    const S T = y[0];
+    const S iT = rcp(T);
+    const S lT = slog(T);
+    const S T2 = T * T, T3 = T2 * T, T4 = T3 * T;
+    auto cpR_of = [&](const double *r) { return r[2] + T * (r[3] + T * (r[4] + T * (r[5] + T * r[6]))); };
+    auto hRT_of = [&](const double *r) {
+        return r[2] + T * (r[9] + T * (r[10] + T * (r[11] + T * r[12]))) + r[7] * iT;
+    };
+    S sYW = mk<S>(0.0), cpm = mk<S>(0.0), dcpm = mk<S>(0.0);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double *r = m.sp + k * kSpTab;
+        sYW += y[1 + k] * r[1];
+        cpm += y[1 + k] * cpR_of(r) * r[1];
+        dcpm += y[1 + k] * (r[3] + T * (r[16] + T * (r[17] + T * r[18]))) * r[1];
+    }
+    const S Wbar = rcp(sYW);
+    const S rho = (p / kR) * Wbar * iT;
+    const S irho = rcp(rho);
+    const S fy = 1e6 * irho;
+    const S cp = kR * cpm;
+    const S icp = rcp(cp);
+    const S cfac = 1e-6 * rho;
+    slot(cs, 0) = mk<S>(1.0);
+    slot(cb, 0) = mk<S>(0.0);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double *r = m.sp + k * kSpTab;
+        slot(cs, 1 + k) = cfac * y[1 + k] * r[1];
+        slot(cb, 1 + k) = mk<S>(0.0);
+        // adjoint weight of wd_k: (lam_k - lam_T hm_k / cp) (1e6/rho) W_k, hm_k = h_k/RT * R T / W_k
+        const S hm = hRT_of(r) * T * (kR * r[1]);
+        rput(om, k, (lam[1 + k] - lam[0] * hm * icp) * fy * r[0]);
+        rput(wd, k, mk<S>(0.0));
+    }
+    S cbd[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) cbd[k] = mk<S>(0.0);
+    S Tb = mk<S>(0.0);
+    for (int j = 0; j < m.M; ++j) {
+        const int *ri = m.rx + j * kRxInt;
+        const double *rd = m.rk + j * kRxDbl;
+        const double *cr = m.cr + j * kCrDbl;
+        const int type = ri[0];
+        const int r0 = ri[1], r1 = ri[2], r2 = ri[3], p0 = ri[4], p1 = ri[5], p2 = ri[6], dnu = ri[7];
+        const double *ef = m.eff + j * K;
+        const int *nuj = m.nu + j * K;
+        S Mc = mk<S>(0.0);
+        if (type != 0) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) Mc += ef[k] * slot(cs, 1 + k);
+        }
+        // forward rate constant, d ln kf/dT at fixed [M], d kf/d[M], d ln kf/d ln A
+        const S kinf = sexp(rd[0] + rd[1] * lT - rd[2] * iT);
+        const S dlninf = (rd[1] + rd[2] * iT) * iT;
+        S kf = kinf, dlnkf = dlninf, dkfdM = mk<S>(0.0), rA = mk<S>(1.0);
+        if (type == 2) {
+            const S k0 = sexp(rd[3] + rd[4] * lT - rd[5] * iT);
+            const double al = rd[6], i3 = rd[7], i1 = rd[8], Tss = rd[9];
+            const S e3 = sexp(-i3 * T), e1 = sexp(-i1 * T), e2 = sexp(-Tss * iT);
+            const S Fc = (1.0 - al) * e3 + al * e1 + e2;
+            const S lFc = kInvLn10 * slog(Fc);
+            const S Pr = k0 * Mc * rcp(kinf);
+            const S lPr = kInvLn10 * slog(Pr);
+            const S cc = -0.4 - 0.67 * lFc;
+            const S nn = 0.75 - 1.27 * lFc;
+            const S x = lPr + cc;
+            const S iden = rcp(nn - 0.14 * x);
+            const S f1 = x * iden;
+            const S q1 = rcp(1.0 + f1 * f1);
+            const S F = sexp(kLn10 * (lFc * q1));
+            const S iPr1 = rcp(1.0 + Pr);
+            kf = kinf * Pr * iPr1 * F;
+            const S dlnk0 = (rd[4] + rd[5] * iT) * iT;
+            const S gq = 2.0 * f1 * q1 * q1;
+            const S dlF_dlPr = -1.0 * (lFc * gq * nn * iden * iden);
+            const S dlF_dlFc = q1 - lFc * gq * (1.27 * x - 0.67 * nn) * iden * iden;
+            const S dFc = -(1.0 - al) * i3 * e3 - al * i1 * e1 + Tss * iT * iT * e2;
+            const S dlFc_dT = kInvLn10 * (dFc * rcp(Fc));
+            dlnkf = dlninf + (iPr1 + dlF_dlPr) * (dlnk0 - dlninf) + kLn10 * (dlF_dlFc * dlFc_dT);
+            dkfdM = k0 * F * iPr1 * (iPr1 + dlF_dlPr);
+            rA = 1.0 - iPr1 - dlF_dlPr;
+        }
+        // 1/Kc = k_r / k_f from the rows of ln k_r and ln k_f; d ln Kc/dT = (sum nu H/RT - dnu)/T
+        const S iKc = sexp((cr[3] - cr[0]) + (cr[4] - cr[1]) * lT + (cr[5] - cr[2]) * iT + cr[6] * T + cr[7] * T2 +
+                           cr[8] * T3 + cr[9] * T4);
+        const S dlnKc = (cr[10] + cr[11] * T + cr[12] * T2 + cr[13] * T3 + cr[14] * T4 + cr[15] * iT - double(dnu)) * iT;
+        S Qb = mk<S>(0.0);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int nk = nuj[k];
+            if (nk != 0) Qb += double(nk) * rget(om, k, S());  // wave-uniform branch
+        }
+        const S kr = kf * iKc;
+        const S c0 = slot(cs, r0), c1 = slot(cs, r1), c2 = slot(cs, r2);
+        const S d0 = slot(cs, p0), d1 = slot(cs, p1), d2 = slot(cs, p2);
+        const S Pf = c0 * c1 * c2, Pb = d0 * d1 * d2;
+        const S fwd = kf * Pf, rev = kr * Pb, X = fwd - rev;
+        const S Mq = (type == 1) ? Mc : mk<S>(1.0);
+        const S q = Mq * X;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int nk = nuj[k];
+            if (nk != 0) rput(wd, k, rget(wd, k, S()) + double(nk) * q);
+        }
+        // adjoint of q_j: T at fixed c, the concentrations of its slots, [M], ln A
+        Tb += Qb * Mq * (fwd * dlnkf - rev * (dlnkf - dlnKc));
+        const S af = Qb * Mq * kf, ar = Qb * Mq * kr;
+        slot(cb, r0) += af * c1 * c2;
+        slot(cb, r1) += af * c0 * c2;
+        slot(cb, r2) += af * c0 * c1;
+        slot(cb, p0) -= ar * d1 * d2;
+        slot(cb, p1) -= ar * d0 * d2;
+        slot(cb, p2) -= ar * d0 * d1;
+        if (type != 0) {
+            const S G = Qb * ((type == 1) ? X : dkfdM * (Pf - Pb * iKc));
+#pragma unroll
+            for (int k = 0; k < K; ++k) cbd[k] += G * ef[k];
+        }
+        at(th, j) += part(Qb * q * rA, with_value);
+    }
+    // mixture: f_k, f_T and the adjoints of fy, hm_k, cp, rho
+    S fyb = mk<S>(0.0), H = mk<S>(0.0);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double *r = m.sp + k * kSpTab;
+        const S hm = hRT_of(r) * T * (kR * r[1]);
+        const S wk = rget(wd, k, S());
+        H += hm * (fy * r[0] * wk);
+        fyb += (lam[1 + k] - lam[0] * hm * icp) * r[0] * wk;
+    }
+    const S fT = -1.0 * (H * icp);
+    const S cpb = -lam[0] * fT * icp;
+    S rhob = -1.0 * (fyb * fy * irho);
+    S T_hm = mk<S>(0.0);
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double *r = m.sp + k * kSpTab;
+        const S cbk = slot(cb, 1 + k) + cbd[k];
+        cbd[k] = cbk;
+        rhob += cbk * slot(cs, 1 + k) * irho;
+        const S fk = fy * r[0] * rget(wd, k, S());
+        T_hm += (-lam[0] * fk * icp) * cpR_of(r) * (kR * r[1]);  // hm_k' = cp_k (mass)
+    }
+    yb[0] = Tb + T_hm + cpb * (kR * dcpm) - rhob * rho * iT;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double *r = m.sp + k * kSpTab;
+        yb[1 + k] = (cbd[k] * cfac + cpb * kR * cpR_of(r) - rhob * rho * Wbar) * r[1];
+    }
+}
+
+// A^T x = b with the LU of Cell<K>::lu (P A = L U, unit L below the diagonal, 1/U_kk on it,
+// row exchanges piv applied in order): U^T w = b, L^T z = w, x = P^T z.
+template <int N>
+__device__ __forceinline__ void solve_T(const double (&A)[N][N], const int (&piv)[N], double (&b)[N]) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+#pragma unroll
+        for (int j = 0; j < i; ++j) b[i] = fma(-A[j][i], b[j], b[i]);
+        b[i] *= A[i][i];
+    }
+#pragma unroll
+    for (int i = N - 1; i >= 0; --i)
+#pragma unroll
+        for (int j = i + 1; j < N; ++j) b[i] = fma(-A[j][i], b[j], b[i]);
+#pragma unroll
+    for (int k = N - 2; k >= 0; --k) {
+#pragma unroll
+        for (int r = N - 1; r > k; --r) {
+            const bool sw = (piv[k] == r);
+            const double x = b[k], y = b[r];
+            b[k] = sw ? y : x;
+            b[r] = sw ? x : y;
+        }
+    }
+}
+
+struct AdjArgs {
+    int64_t n, ld;
+    const double *p;
+    const double *tape;
+    int32_t cap;
+    const double *Tb, *Yb;   // seeds, [n] and [K][ld]
+    double *T0b, *Y0b;       // [n], [K][ld]
+    double *thc;             // [M][ld] per-cell ln A adjoints in file order, or nullptr
+    double *ws;              // per-cell work: [6N] u, [6N] ubar, [N*N] LU, [N] pivots, [M] thbar (stride n)
+};
+
+template <int K>
+__global__ __launch_bounds__(kWave) void adjoint_kernel(MechDev m, AdjArgs a) {
+    using C = Cell<K>;
+    constexpr int N = K + 1;
+    // LDS per lane: Cell's arrays (5N slots: c, e, 1/e, H/RT, dq/dc), the dual concentrations
+    // and their adjoints (2N + 2N slots), ln A adjoints (M slots, dynamic)
+    extern __shared__ double lds[];
+    double *sh = lds + threadIdx.x;
+    Dual *cs = reinterpret_cast<Dual *>(lds + 5 * N * kWave) + threadIdx.x;
+    Dual *cb = cs + N * kWave;
+    // production-rate weights and rates of the products: in the Cell region, which is idle while
+    // the reverse phase runs (its neutral slots are set again before each forward recompute)
+    double *omr = sh, *wdr = sh + 2 * K * kWave;
+    static_assert(4 * K <= 5 * N, "product arrays must fit in the Cell region");
+    // the plain-number products use the value half of the same slots
+    double *csd = reinterpret_cast<double *>(cs), *cbd = reinterpret_cast<double *>(cb);
+    double *th = lds + 9 * N * kWave + threadIdx.x;
+    const int64_t i = int64_t(blockIdx.x) * kWave + threadIdx.x;
+    if (i >= a.n) return;
+    const int64_t n = a.n, ld = a.ld;
+    const int32_t cnt = reinterpret_cast<const int32_t *>(a.tape + int64_t(a.cap) * (K + 2) * n)[i];
+    double lam[N];
+    lam[0] = a.Tb[i];
+#pragma unroll
+    for (int k = 0; k < K; ++k) lam[1 + k] = a.Yb[k * ld + i];
+    for (int j = 0; j < m.M; ++j) at(th, j) = 0.0;
+    double *wu = a.ws + i, *wub = wu + 6 * N * n, *wlu = wub + 6 * N * n, *wpv = wlu + N * N * n;
+    double *wth = wpv + N * n;
+    const double p = a.p[i];
+    for (int s = (cnt > 0 ? cnt : 0) - 1; s >= 0; --s) {
+        double y[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) y[k] = a.tape[(int64_t(s) * N + k) * n + i];
+        const double h = a.tape[int64_t(a.cap) * N * n + int64_t(s) * n + i];
+        // ---- forward: the sub-step's iteration matrix and stages, as the integrator took them
+        C::init_lds(sh);
+        {
+            double W[N][N], f0[N];
+            int piv[N];
+            C::jacobian(m, p, y, sh, W, f0);
+            const double ig = 1.0 / (Rodas4::g * h);
+#pragma unroll
+            for (int r = 0; r < N; ++r)
+#pragma unroll
+                for (int q = 0; q < N; ++q) W[r][q] = (r == q ? ig : 0.0) - W[r][q];
+            C::lu(W, piv);
+#pragma unroll
+            for (int r = 0; r < N; ++r) {
+                wpv[r * n] = double(piv[r]);
+#pragma unroll
+                for (int q = 0; q < N; ++q) wlu[(r * N + q) * n] = W[r][q];
+            }
+            const double ih = 1.0 / h;
+#pragma unroll
+            for (int si = 0; si < 6; ++si) {
+                double v[N];
+                if (si == 0) {
+#pragma unroll
+                    for (int k = 0; k < N; ++k) v[k] = f0[k];
+                } else {
+                    double ys[N];
+#pragma unroll
+                    for (int k = 0; k < N; ++k) {
+                        double w = y[k];
+#pragma unroll
+                        for (int jj = 0; jj < si; ++jj) w = fma(Rodas4::a[si][jj], wu[(jj * N + k) * n], w);
+                        ys[k] = w;
+                    }
+                    C::rhs(m, p, ys, sh, v);
+#pragma unroll
+                    for (int k = 0; k < N; ++k) {
+                        double w = 0.0;
+#pragma unroll
+                        for (int jj = 0; jj < si; ++jj) w = fma(Rodas4::c[si][jj], wu[(jj * N + k) * n], w);
+                        v[k] = fma(w, ih, v[k]);
+                    }
+                }
+                C::solve(W, piv, v);
+#pragma unroll
+                for (int k = 0; k < N; ++k) wu[(si * N + k) * n] = v[k];
+            }
+        }
+        // ---- reverse
+        double yb[N];
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            yb[k] = lam[k];
+#pragma unroll
+            for (int si = 0; si < 6; ++si) wub[(si * N + k) * n] = (si < 5 ? Rodas4::a[5][si] : 1.0) * lam[k];
+        }
+        const double ih = 1.0 / h;
+#pragma unroll 1
+        for (int si = 5; si >= 0; --si) {
+            double rb[N];
+            {
+                double A[N][N];
+                int piv[N];
+#pragma unroll
+                for (int r = 0; r < N; ++r) {
+                    piv[r] = int(wpv[r * n]);
+#pragma unroll
+                    for (int q = 0; q < N; ++q) A[r][q] = wlu[(r * N + q) * n];
+                }
+#pragma unroll
+                for (int k = 0; k < N; ++k) rb[k] = wub[(si * N + k) * n];
+                solve_T<N>(A, piv, rb);
+            }
+            if (si > 0) {
+                double ys[N], v[N];
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    double w = y[k];
+                    for (int jj = 0; jj < si; ++jj) w = fma(Rodas4::a[si][jj], wu[(jj * N + k) * n], w);
+                    ys[k] = w;
+                }
+                vjp<K, double>(m, p, ys, rb, csd, cbd, omr, wdr, th, true, v);
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    yb[k] += v[k];
+                    for (int jj = 0; jj < si; ++jj)
+                        wub[(jj * N + k) * n] += Rodas4::a[si][jj] * v[k] + Rodas4::c[si][jj] * ih * rb[k];
+                }
+            }
+            // derivative of W through J(y): the dual product at y + eps u_i (stage 0: also the
+            // first-order term J(y)^T rbar, the value part)
+            Dual yd[N], vd[N];
+#pragma unroll
+            for (int k = 0; k < N; ++k) yd[k] = Dual{y[k], wu[(si * N + k) * n]};
+            vjp<K, Dual>(m, p, yd, rb, cs, cb, omr, wdr, th, si == 0, vd);
+#pragma unroll
+            for (int k = 0; k < N; ++k) yb[k] += (si == 0) ? vd[k].v + vd[k].d : vd[k].d;
+        }
+#pragma unroll
+        for (int k = 0; k < N; ++k) lam[k] = yb[k];
+    }
+    const bool ok = cnt > 0;
+    a.T0b[i] = ok ? lam[0] : 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) a.Y0b[k * ld + i] = ok ? lam[1 + k] : 0.0;
+    for (int j = 0; j < m.M; ++j) {
+        const double v = ok ? at(th, j) : 0.0;
+        wth[j * n] = v;
+        if (a.thc) a.thc[int64_t(m.src[j]) * ld + i] = v;
+    }
+}
+
+// lnA_bar[src[j]] = sum over cells of the per-cell adjoints of stored reaction j: one block per
+// reaction, a fixed-order tree over a fixed-stride partition (deterministic)
+__global__ __launch_bounds__(256) void sum_cells_kernel(const double *__restrict__ wth, int64_t n,
+                                                        const int *__restrict__ src, double *__restrict__ out) {
+    extern __shared__ double part_sum[];  // 256 doubles
+    const int j = blockIdx.x, t = threadIdx.x;
+    double s = 0.0;
+    for (int64_t i = t; i < n; i += 256) s += wth[int64_t(j) * n + i];
+    part_sum[t] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) part_sum[t] += part_sum[t + w];
+        __syncthreads();
+    }
+    if (t == 0) out[src[j]] = part_sum[0];
+}
+
+size_t adj_ws_bytes(int K, int M, int64_t n) {
+    const size_t N = size_t(K + 1);
+    return size_t(8) * (12 * N + N * N + N + size_t(M)) * size_t(n);
+}
+
+size_t adj_lds_bytes(int K, int M) { return size_t(8) * kWave * (9 * size_t(K + 1) + size_t(M)); }
+
+constexpr size_t kAdjLdsMax = 64 * 1024;
+
+template <int K>
+df_status launch_adjoint_k(const MechDev &m, const AdjArgs &a, hipStream_t s) {
+    const int64_t blocks = (a.n + kWave - 1) / kWave;
+    const size_t lds = adj_lds_bytes(K, m.M);
+    hipLaunchKernelGGL(adjoint_kernel<K>, dim3(unsigned(blocks)), dim3(kWave), lds, s, m, a);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(DF_E_HIP, std::string("df_chem_adjoint launch: ") + hipGetErrorString(e));
+    return DF_OK;
+}
+
+// species counts with a compiled adjoint kernel
+#define DF_ADJ_SPECIES_LIST(X) X(2) X(4) X(9)
+
+bool adjoint_supported(const MechDev &m) {
+    bool k_ok = false;
+#define DF_CASE(k) k_ok = k_ok || m.K == k;
+    DF_ADJ_SPECIES_LIST(DF_CASE)
+#undef DF_CASE
+    return k_ok && adj_lds_bytes(m.K, m.M) <= kAdjLdsMax;
+}
+
+struct DeviceScope {
+    int prev = 0;
+    bool changed = false;
+    df_status st = DF_OK;
+    DeviceScope(int dev, const char *who) {
+        if (hipGetDevice(&prev) != hipSuccess) {
+            st = fail(DF_E_HIP, std::string(who) + ": hipGetDevice failed");
+            return;
+        }
+        if (prev != dev) {
+            if (hipSetDevice(dev) != hipSuccess) {
+                st = fail(DF_E_HIP, std::string(who) + ": cannot select the mechanism's device");
+                return;
+            }
+            changed = true;
+        }
+    }
+    ~DeviceScope() {
+        if (changed) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+}  // namespace df
+
+extern "C" df_status df_chem_tape_size(const df_mech *mech, int64_t n_cells, int32_t max_substeps, size_t *bytes) {
+    using namespace df;
+    clear_error();
+    if (!mech || !bytes || n_cells < 0 || max_substeps < 1)
+        return fail(DF_E_INVALID, "df_chem_tape_size: bad arguments");
+    *bytes = tape_bytes(mech->host.K, n_cells, max_substeps);
+    return DF_OK;
+}
+
+extern "C" df_status df_chem_step_taped(const df_mech *mech, int64_t n_cells, int64_t ld, double dt, const double *p,
+                                        double *T, double *Y, int32_t *cell_status, int32_t *n_steps, void *tape,
+                                        size_t tape_size, int32_t max_substeps, const df_chem_opts *opts,
+                                        void *hip_stream) {
+    using namespace df;
+    clear_error();
+    const char *who = "df_chem_step_taped";
+    if (!mech) return fail(DF_E_INVALID, std::string(who) + ": null mechanism handle");
+    if (n_cells < 0 || ld < n_cells) return fail(DF_E_INVALID, std::string(who) + ": need 0 <= n_cells <= ld");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(DF_E_INVALID, std::string(who) + ": dt must be finite and > 0");
+    if (max_substeps < 1) return fail(DF_E_INVALID, std::string(who) + ": max_substeps must be >= 1");
+    if (n_cells > 0 && (!p || !T || !Y || !tape)) return fail(DF_E_INVALID, std::string(who) + ": null p, T, Y or tape");
+    if (n_cells > 0x7fffffff) return fail(DF_E_UNSUPPORTED, std::string(who) + ": more than 2^31-1 cells");
+    if (n_cells > 0 && (tape_size < tape_bytes(mech->host.K, n_cells, max_substeps) ||
+                        reinterpret_cast<uintptr_t>(tape) % 256 != 0))
+        return fail(DF_E_INVALID, std::string(who) + ": tape smaller than df_chem_tape_size or not 256-byte aligned");
+    if (!adjoint_supported(mech->dev))
+        return fail(DF_E_UNSUPPORTED, std::string(who) + ": no adjoint kernel for this mechanism");
+    df_chem_opts o;
+    df_chem_default_opts(&o);
+    if (opts) o = *opts;
+    df_status st = validate_chem_opts(o);
+    if (st != DF_OK) return st;
+    if (n_cells == 0) return DF_OK;
+    DeviceScope dev(mech->device, who);
+    if (dev.st != DF_OK) return dev.st;
+    StepArgs a{n_cells, ld, dt, nullptr, p, T, Y, nullptr, nullptr, cell_status, n_steps, kernel_opts(o), DF_CELL_OK};
+    a.tape = static_cast<double *>(tape);
+    a.tape_cap = max_substeps;
+    return launch_chem_step(mech->dev, a, 1, nullptr, nullptr, static_cast<hipStream_t>(hip_stream));
+}
+
+extern "C" df_status df_chem_adjoint_workspace_size(const df_mech *mech, int64_t n_cells, size_t *bytes) {
+    using namespace df;
+    clear_error();
+    if (!mech || !bytes || n_cells < 0) return fail(DF_E_INVALID, "df_chem_adjoint_workspace_size: bad arguments");
+    *bytes = adj_ws_bytes(mech->host.K, mech->host.M, n_cells);
+    return DF_OK;
+}
+
+extern "C" df_status df_chem_adjoint(const df_mech *mech, int64_t n_cells, int64_t ld, const double *p,
+                                     const void *tape, size_t tape_size, int32_t max_substeps, const double *T_bar,
+                                     const double *Y_bar, double *T0_bar, double *Y0_bar, double *lnA_bar_cells,
+                                     double *lnA_bar, void *workspace, size_t ws_bytes, void *hip_stream) {
+    using namespace df;
+    clear_error();
+    const char *who = "df_chem_adjoint";
+    if (!mech) return fail(DF_E_INVALID, std::string(who) + ": null mechanism handle");
+    if (n_cells < 0 || ld < n_cells) return fail(DF_E_INVALID, std::string(who) + ": need 0 <= n_cells <= ld");
+    if (max_substeps < 1) return fail(DF_E_INVALID, std::string(who) + ": max_substeps must be >= 1");
+    if (n_cells > 0 && (!p || !tape || !T_bar || !Y_bar || !T0_bar || !Y0_bar || !workspace))
+        return fail(DF_E_INVALID, std::string(who) + ": null p, tape, seed, output or workspace");
+    if (n_cells > 0x7fffffff) return fail(DF_E_UNSUPPORTED, std::string(who) + ": more than 2^31-1 cells");
+    const int K = mech->host.K, M = mech->host.M;
+    if (n_cells > 0 && (tape_size < tape_bytes(K, n_cells, max_substeps) ||
+                        reinterpret_cast<uintptr_t>(tape) % 256 != 0))
+        return fail(DF_E_INVALID, std::string(who) + ": tape smaller than df_chem_tape_size or not 256-byte aligned");
+    if (n_cells > 0 && (ws_bytes < adj_ws_bytes(K, M, n_cells) || reinterpret_cast<uintptr_t>(workspace) % 256 != 0))
+        return fail(DF_E_INVALID,
+                    std::string(who) + ": workspace smaller than df_chem_adjoint_workspace_size or not 256-byte aligned");
+    if (!adjoint_supported(mech->dev))
+        return fail(DF_E_UNSUPPORTED, std::string(who) + ": no adjoint kernel for this mechanism");
+    if (n_cells == 0) {
+        if (lnA_bar && M > 0) {
+            DeviceScope dev(mech->device, who);
+            if (dev.st != DF_OK) return dev.st;
+            if (hipMemsetAsync(lnA_bar, 0, size_t(M) * 8, static_cast<hipStream_t>(hip_stream)) != hipSuccess)
+                return fail(DF_E_HIP, std::string(who) + ": clearing lnA_bar failed");
+        }
+        return DF_OK;
+    }
+    DeviceScope dev(mech->device, who);
+    if (dev.st != DF_OK) return dev.st;
+    auto s = static_cast<hipStream_t>(hip_stream);
+    const AdjArgs a{n_cells, ld,     p,      static_cast<const double *>(tape), max_substeps, T_bar, Y_bar,
+                    T0_bar,  Y0_bar, lnA_bar_cells, static_cast<double *>(workspace)};
+    df_status st = DF_OK;
+    switch (K) {
+#define DF_CASE(k)                                   \
+    case k:                                          \
+        st = launch_adjoint_k<k>(mech->dev, a, s);   \
+        break;
+        DF_ADJ_SPECIES_LIST(DF_CASE)
+#undef DF_CASE
+        default:
+            st = fail(DF_E_UNSUPPORTED, std::string(who) + ": no adjoint kernel for this mechanism");
+    }
+    if (st == DF_OK && lnA_bar && M > 0) {
+        const size_t N = size_t(K + 1);
+        const double *wth = static_cast<const double *>(workspace) + (12 * N + N * N + N) * size_t(n_cells);
+        hipLaunchKernelGGL(sum_cells_kernel, dim3(unsigned(M)), dim3(256), 256 * sizeof(double), s, wth, n_cells,
+                           mech->dev.src, lnA_bar);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) st = fail(DF_E_HIP, std::string(who) + ": reduction launch: " + hipGetErrorString(e));
+    }
+    return st;
+}

@@ -56,6 +56,7 @@ struct MechDev {
     const double *ceffw; // [MP][K] efficiencies divided by W_k
     const int *cli;      // [16][kCoopList] per-lane list: index into the per-cell rate array
     const double *clc;   // [16][kCoopList] per-lane list: coefficient
+    const int *src;      // [M] mechanism-file index of stored reaction j
 };
 
 struct HostMech {
@@ -95,7 +96,16 @@ struct StepArgs {
     int32_t *status, *nsteps;
     Opts o;
     int32_t status_ok;  // status written for cells that succeed (DF_CELL_OK or DF_CELL_DNN_FALLBACK)
+    // tape of the accepted sub-steps (one-cell-per-lane launch only; nullptr = none), for the
+    // adjoint: with S = tape_cap and N = K + 1, doubles [S][N][n] start states, then [S][n]
+    // step lengths, then int32 [n] sub-step counts (-1: no usable tape for the cell)
+    double *tape = nullptr;
+    int32_t tape_cap = 0;
 };
+
+inline size_t tape_bytes(int K, int64_t n, int32_t cap) {
+    return size_t(8) * size_t(cap) * size_t(K + 2) * size_t(n) + size_t(4) * size_t(n);
+}
 
 // Where the lanes (or 16-lane groups) of a launch get their cells.
 //   static: slot s (global lane or group index) takes cell cidx[s] (or s), for s < *dcount (or n);

@@ -369,7 +369,7 @@ df_status df_mech_load(const char *path, int32_t device, df_mech **out) {
                     {nu.data(), nu.size() * 4, 0},          {ct.cr.data(), ct.cr.size() * 8, 0},
                     {ct.ci.data(), ct.ci.size() * 4, 0},    {ct.ceff.data(), ct.ceff.size() * 8, 0},
                     {ct.ceffw.data(), ct.ceffw.size() * 8, 0}, {ct.cli.data(), ct.cli.size() * 4, 0},
-                    {ct.clc.data(), ct.clc.size() * 8, 0}};
+                    {ct.clc.data(), ct.clc.size() * 8, 0},  {order.data(), order.size() * 4, 0}};
     size_t total = 0;
     for (auto &q : parts) {
         q.off = total;
@@ -412,6 +412,7 @@ df_status df_mech_load(const char *path, int32_t device, df_mech **out) {
     m->dev.ceffw = D(8);
     m->dev.cli = I(9);
     m->dev.clc = D(10);
+    m->dev.src = I(11);
     *out = m;
     return DF_OK;
 }

@@ -71,3 +71,16 @@ def test_binding_refuses_cpu_tensors(L):
     import torch
     with pytest.raises(ValueError):
         df._ptr(torch.zeros(3, dtype=torch.float64), torch.float64, "T")
+
+
+def test_adjoint_host_checks(L):
+    o = df.chem_opts()
+    b = C.c_size_t()
+    assert L.df_chem_tape_size(None, 1, 10, C.byref(b)) == _lib.DF_E_INVALID
+    assert L.df_chem_adjoint_workspace_size(None, 1, C.byref(b)) == _lib.DF_E_INVALID
+    assert L.df_chem_step_taped(None, 1, 1, 1e-6, None, None, None, None, None, None, 0, 10, C.byref(o), None) \
+        == _lib.DF_E_INVALID
+    assert b"null mechanism" in L.df_last_error()
+    assert L.df_chem_adjoint(None, 1, 1, None, None, 0, 10, None, None, None, None, None, None, None, 0, None) \
+        == _lib.DF_E_INVALID
+    assert b"null mechanism" in L.df_last_error()

@@ -1,0 +1,235 @@
+"""GPU checks of the discrete adjoint of the chemistry step (df_chem_step_taped, df_chem_adjoint,
+chem_step_diff).
+
+The adjoint gives (dy/dy0)^T lam and (dy/dlnA)^T lam for the step with its accepted sub-step
+lengths frozen.  Its reference is the oracle's forward sensitivities of the same frozen sequence
+(complex-step differentiation of a replay, pinned to central differences and conservation in
+test_oracle_sensitivity): with unit seeds the adjoint returns rows of the sensitivity matrix.
+Both are exact up to rounding, so rows agree to 1e-9 of the row's largest entry on cells whose
+accept/reject sequence matches the oracle's (rounding may shift a sub-step length by an ulp, which
+moves the derivative by far less than the bar).  At the full size (4096 cells, dt = 1e-5 s)
+every cell is checked against the conservation laws the exact derivative obeys (total mass and
+each element, for every input) and a sample of cells against the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import sensitivity as sens
+from synth import fields
+
+pytestmark = pytest.mark.gpu
+
+DT = 1e-5
+CAP = 2048
+RTOL_ROW = 1e-9
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+def _taped(gm, f, dt=DT, cap=CAP):
+    torch = _torch()
+    n = f["T"].size
+    dev = "cuda:0"
+    T = torch.tensor(f["T"], dtype=torch.float64, device=dev)
+    p = torch.tensor(f["p"], dtype=torch.float64, device=dev)
+    Y = torch.tensor(np.ascontiguousarray(f["Y"]), dtype=torch.float64, device=dev)
+    st = torch.full((n,), -7, dtype=torch.int32, device=dev)
+    ns = torch.full((2 * n,), -7, dtype=torch.int32, device=dev)
+    tape = gm.chem_step_taped(T, p, Y, dt, max_substeps=cap, status=st, n_steps=ns)
+    return T, p, Y, tape, st, ns
+
+
+def _full_matrix(gm, p, tape, n, cap=CAP):
+    """Rows of d y(dt)/d(T0, Y0, lnA) for every cell, one adjoint sweep per output component."""
+    torch = _torch()
+    K, M = gm.n_species, gm.n_reactions
+    N = K + 1
+    G = np.zeros((n, N, N + M))
+    for r in range(N):
+        Tb = torch.zeros(n, dtype=torch.float64, device="cuda:0")
+        Yb = torch.zeros(K, n, dtype=torch.float64, device="cuda:0")
+        if r == 0:
+            Tb[:] = 1.0
+        else:
+            Yb[r - 1] = 1.0
+        T0b, Y0b, thc, ths = gm.chem_adjoint(p, tape, cap, Tb, Yb)
+        G[:, r, 0] = T0b.cpu().numpy()
+        G[:, r, 1:N] = Y0b.cpu().numpy().T
+        G[:, r, N:] = thc.cpu().numpy().T
+        # the summed ln A adjoint is the per-cell one summed (fixed-order reduction)
+        s = thc.sum(dim=1).cpu().numpy()
+        assert np.allclose(ths.cpu().numpy(), s, rtol=1e-12, atol=1e-300 + 1e-14 * np.abs(s).max())
+    return G
+
+
+def _oracle_rows(h2_mech, h2_oracle, f, i, dt=DT):
+    _, _, st, hs, nrej = h2_oracle.record(f["T"][i], f["p"][i], f["Y"][:, i], dt)
+    y0 = np.concatenate([[f["T"][i]], f["Y"][:, i]])
+    _, S = sens.sensitivities(sens.Kinetics(h2_mech), oracle.rodas4_tableau(), f["p"][i], y0, hs)
+    return S, st, hs.size, nrej
+
+
+def test_adjoint_rows_match_oracle_sensitivities(h2_path, h2_mech, h2_oracle):
+    import paper_2210_07094_amd as df
+    gm = df.Mechanism(h2_path)
+    f = fields.ignition_cells(h2_mech, n=5, seed=4)
+    n = 5
+    _, p, _, tape, st, ns = _taped(gm, f)
+    st, ns = st.cpu().numpy(), ns.cpu().numpy()
+    assert np.all(st == df.CELL_OK)
+    G = _full_matrix(gm, p, tape, n)
+    matched = 0
+    for i in range(n):
+        S, sto, nacc, nrej = _oracle_rows(h2_mech, h2_oracle, f, i)
+        assert sto == 0
+        if (nacc, nrej) != (ns[i], ns[n + i]):
+            continue
+        matched += 1
+        err = np.abs(G[i] - S) / np.abs(S).max(axis=1, keepdims=True)
+        assert err.max() <= RTOL_ROW, (i, err.max())
+    assert matched >= 4
+
+
+def test_adjoint_against_central_differences(h2_path, h2_mech):
+    """Central differences (relative step 1e-6) of the oracle's replay of the oracle's own
+    sub-step sequence, against the GPU adjoint on the same cell."""
+    import paper_2210_07094_amd as df
+    gm = df.Mechanism(h2_path)
+    om = oracle.Mech(h2_path)
+    f = fields.ignition_cells(h2_mech, n=2, seed=8)
+    _, p, _, tape, st, ns = _taped(gm, f)
+    G = _full_matrix(gm, p, tape, 2)
+    K, M = h2_mech.n_species, h2_mech.n_reactions
+    N = K + 1
+    for i in range(2):
+        _, _, sto, hs, nrej = om.record(f["T"][i], f["p"][i], f["Y"][:, i], DT)
+        y = np.concatenate([[f["T"][i]], f["Y"][:, i]])
+        pi = f["p"][i]
+        Sfd = np.zeros((N, N + M))
+        for c in range(N):
+            d = 1e-6 * max(abs(y[c]), 1e-3 if c else 1.0)
+            yp, ym = y.copy(), y.copy()
+            yp[c] += d
+            ym[c] -= d
+            Sfd[:, c] = (om.replay(pi, yp, hs) - om.replay(pi, ym, hs)) / (2 * d)
+        for j in range(M):
+            om.scale_A(j, np.exp(1e-6))
+            a = om.replay(pi, y, hs)
+            om.scale_A(j, np.exp(-2e-6))
+            b = om.replay(pi, y, hs)
+            om.scale_A(j, np.exp(1e-6))
+            Sfd[:, N + j] = (a - b) / 2e-6
+        err = np.abs(G[i] - Sfd) / np.abs(Sfd).max(axis=1, keepdims=True)
+        assert err.max() < 1e-5 and np.median(err) < 1e-9, (i, err.max(), np.median(err))
+
+
+def test_adjoint_full_size_conservation_and_sample(h2_path, h2_mech, h2_oracle):
+    """The differentiation workload: 4096 cells, T0 1000-1600 K, phi 0.5-2, dt = 1e-5 s."""
+    import paper_2210_07094_amd as df
+    torch = _torch()
+    gm = df.Mechanism(h2_path)
+    n = 4096
+    f = fields.ignition_cells(h2_mech, n=n, seed=2023)
+    T, p, Y, tape, st, ns = _taped(gm, f)
+    st = st.cpu().numpy()
+    assert np.all(st == df.CELL_OK), np.bincount(st)
+    K, M = h2_mech.n_species, h2_mech.n_reactions
+    W = np.asarray(h2_mech.molar_mass, dtype=float)
+    E = np.asarray(h2_mech.composition, dtype=float).T / W        # [E, K] element moles per gram
+    # seeds: total mass, then each element; the exact derivative is the seed itself on Y0 and
+    # zero on T0 and ln A, for every cell
+    seeds = [np.ones(K)] + [E[e] / np.abs(E[e]).max() for e in range(E.shape[0])]
+    for s in seeds:
+        Tb = torch.zeros(n, dtype=torch.float64, device="cuda:0")
+        Yb = torch.tensor(np.repeat(s[:, None], n, axis=1), dtype=torch.float64, device="cuda:0")
+        T0b, Y0b, thc, _ = gm.chem_adjoint(p, tape, CAP, Tb, Yb)
+        # scale of the terms that cancel: the seed against the adjoint of one species row
+        assert np.max(np.abs(Y0b.cpu().numpy() - s[:, None])) < 1e-9 * np.abs(s).max()
+        # dT: the rows being summed are O(1/K) per kelvin; dlnA: O(|Y|)
+        assert np.max(np.abs(T0b.cpu().numpy())) < 1e-10
+        assert np.max(np.abs(thc.cpu().numpy())) < 1e-10
+    # a sample against the oracle: one random seed per cell, compared with lam^T S
+    rng = np.random.default_rng(3)
+    idx = np.concatenate([[int(np.argmax(ns[:n].cpu().numpy()))], rng.choice(n, 3, replace=False)])
+    lam = rng.standard_normal((K + 1, n))
+    Tb = torch.tensor(lam[0], dtype=torch.float64, device="cuda:0")
+    Yb = torch.tensor(lam[1:], dtype=torch.float64, device="cuda:0")
+    T0b, Y0b, thc, _ = gm.chem_adjoint(p, tape, CAP, Tb, Yb)
+    T0b, Y0b, thc = T0b.cpu().numpy(), Y0b.cpu().numpy(), thc.cpu().numpy()
+    nsh = ns.cpu().numpy()
+    for i in idx:
+        S, sto, nacc, nrej = _oracle_rows(h2_mech, h2_oracle, f, i)
+        if (nacc, nrej) != (nsh[i], nsh[n + i]):
+            continue
+        want = lam[:, i] @ S
+        got = np.concatenate([[T0b[i]], Y0b[:, i], thc[:, i]])
+        scale = np.abs(lam[:, i][:, None] * S).max()
+        assert np.max(np.abs(got - want)) <= 1e-9 * scale, (i, np.max(np.abs(got - want)) / scale)
+
+
+def test_adjoint_edge_cases(h2_path, h2_mech):
+    """Tape overflow, unusable input, a ragged count, an empty call, and refused arguments."""
+    import paper_2210_07094_amd as df
+    torch = _torch()
+    gm = df.Mechanism(h2_path)
+    n = 67
+    f = fields.ignition_cells(h2_mech, n=n, seed=12)
+    f["T"][5] = np.nan
+    f["T"][9] = -1.0
+    T, p, Y, tape, st, ns = _taped(gm, f, cap=150)
+    st, nsh = st.cpu().numpy(), ns.cpu().numpy()
+    assert st[5] == df.CELL_NONFINITE and st[9] == df.CELL_NONFINITE
+    full = nsh[:n] > 150
+    assert full.any() and np.all(st[full] == df.CELL_TAPE_FULL)
+    ok = (st == df.CELL_OK)
+    assert ok.sum() > 10
+    Tb = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    Yb = torch.ones(h2_mech.n_species, n, dtype=torch.float64, device="cuda:0")
+    T0b, Y0b, thc, ths = gm.chem_adjoint(p, tape, 150, Tb, Yb)
+    T0b, Y0b, thc = T0b.cpu().numpy(), Y0b.cpu().numpy(), thc.cpu().numpy()
+    bad = ~ok
+    assert np.all(T0b[bad] == 0) and np.all(Y0b[:, bad] == 0) and np.all(thc[:, bad] == 0)
+    assert np.all(np.isfinite(T0b[ok])) and np.all(T0b[ok] != 0)
+    # a tape of a different capacity is refused when too small
+    with pytest.raises(df.DfError):
+        gm.chem_adjoint(p, tape[: tape.numel() // 2], 150, Tb, Yb)
+    # empty call: the summed adjoint is zero
+    e = torch.zeros(0, dtype=torch.float64, device="cuda:0")
+    _, _, _, ths0 = gm.chem_adjoint(e, tape, 150, e, torch.zeros(h2_mech.n_species, 0, dtype=torch.float64,
+                                                                  device="cuda:0"))
+    assert torch.all(ths0 == 0)
+
+
+def test_autograd_function(h2_path, h2_mech):
+    """chem_step_diff: the forward equals df_chem_step's result for fresh starts, and backward of a
+    linear loss equals the adjoint with that loss's weights as seeds."""
+    import paper_2210_07094_amd as df
+    torch = _torch()
+    gm = df.Mechanism(h2_path)
+    n = 128
+    f = fields.ignition_cells(h2_mech, n=n, seed=21)
+    dev = "cuda:0"
+    T0 = torch.tensor(f["T"], dtype=torch.float64, device=dev, requires_grad=True)
+    Y0 = torch.tensor(np.ascontiguousarray(f["Y"]), dtype=torch.float64, device=dev, requires_grad=True)
+    p = torch.tensor(f["p"], dtype=torch.float64, device=dev)
+    lnA = torch.zeros(h2_mech.n_reactions, dtype=torch.float64, device=dev, requires_grad=True)
+    T, Y = df.chem_step_diff(gm, T0, Y0, p, DT, lnA=lnA)
+    # forward as the per-lane integrator from a fresh start
+    T1 = T0.detach().clone()
+    Y1 = Y0.detach().clone()
+    gm.chem_step(T1, p, Y1, DT, h=torch.zeros(n, dtype=torch.float64, device=dev), opts=df.chem_opts(mapping=1))
+    assert torch.equal(T.detach(), T1) and torch.equal(Y.detach(), Y1)
+    rng = np.random.default_rng(1)
+    wT = torch.tensor(rng.standard_normal(n), dtype=torch.float64, device=dev)
+    wY = torch.tensor(rng.standard_normal((h2_mech.n_species, n)), dtype=torch.float64, device=dev)
+    loss = (wT * T).sum() + (wY * Y).sum()
+    loss.backward()
+    T2, Y2, tape = T0.detach().clone(), Y0.detach().clone(), None
+    tape = gm.chem_step_taped(T2, p, Y2, DT, max_substeps=2048)
+    T0b, Y0b, _, ths = gm.chem_adjoint(p, tape, 2048, wT, wY)
+    assert torch.equal(T0.grad, T0b) and torch.equal(Y0.grad, Y0b) and torch.equal(lnA.grad, ths)
