@@ -195,32 +195,33 @@ df_status df_chem_autotune(const df_mech *mech, int64_t n_cells, int64_t ld, dou
  * (the step-size controller's choices are not differentiated), so the gradient is the exact
  * derivative of the computed result, up to rounding.
  *
- * Bytes of tape (the adjoint's checkpoints: the start state and length of each accepted
- * sub-step) for n_cells and at most max_substeps accepted sub-steps per cell:
- * 8 max_substeps (K + 2) n_cells + 4 n_cells.
+ * Bytes of tape (the adjoint's checkpoints: for each accepted sub-step its start state, its
+ * length, the inverse of its iteration matrix and its six stage vectors) for n_cells and at
+ * most max_substeps accepted sub-steps per cell: 8 max_substeps (N^2 + 7N + 1) n_cells +
+ * 4 n_cells with N = K + 1.
  */
 df_status df_chem_tape_size(const df_mech *mech, int64_t n_cells, int32_t max_substeps, size_t *bytes);
 
 /*
- * df_chem_step (one cell per lane, each cell from a fresh start: no sub-step hint, no rr)
+ * df_chem_step (16 lanes per cell, each cell from a fresh start: no sub-step hint, no rr)
  * that also records the tape for df_chem_adjoint.
  *   p, T, Y, cell_status, n_steps, opts: as df_chem_step
  *   tape          device memory of df_chem_tape_size(mech, n_cells, max_substeps) bytes,
  *                 256-byte aligned, written; keep it (and p) unchanged until the adjoint ran.
- *                 Layout, with N = K + 1 and S = max_substeps: f64 [S][N][n_cells] start
- *                 states, f64 [S][n_cells] sub-step lengths, int32 [n_cells] sub-step counts
- *                 (-1: the cell has no tape).
+ *                 Layout, with N = K + 1, S = max_substeps and every array cell-minor (stride
+ *                 n_cells): f64 [S][N] start states, f64 [S] sub-step lengths, f64 [S][N*N]
+ *                 inverses of W = I/(gamma h) - J (row-major), f64 [S][6*N] stage vectors
+ *                 (stage-major), then int32 [n_cells] sub-step counts (-1: the cell has no tape).
  * A cell with more accepted sub-steps than max_substeps keeps its integrated state and gets
  * DF_CELL_TAPE_FULL (no tape); cells that fail as in df_chem_step get no tape either.
  * Errors: DF_E_INVALID (as df_chem_step; max_substeps < 1; tape null, too small or misaligned),
- * DF_E_UNSUPPORTED (no adjoint kernel for the species count, or its per-lane tables do not fit
- * in 64 KiB of LDS), DF_E_HIP.
+ * DF_E_UNSUPPORTED (no 16-lane integrator or adjoint kernel for the mechanism), DF_E_HIP.
  */
 df_status df_chem_step_taped(const df_mech *mech, int64_t n_cells, int64_t ld, double dt, const double *p,
                              double *T, double *Y, int32_t *cell_status, int32_t *n_steps, void *tape,
                              size_t tape_bytes, int32_t max_substeps, const df_chem_opts *opts, void *hip_stream);
 
-/* Bytes of device workspace df_chem_adjoint needs for n_cells: 8 n_cells (12 N + N^2 + N + M). */
+/* Bytes of device workspace df_chem_adjoint needs for n_cells: 8 M n_cells. */
 df_status df_chem_adjoint_workspace_size(const df_mech *mech, int64_t n_cells, size_t *bytes);
 
 /*

@@ -159,7 +159,7 @@ class Mechanism:
         check(lib().df_chem_tape_size(self._h, int(n_cells), int(max_substeps), C.byref(b)))
         return b.value
 
-    def chem_step_taped(self, T, p, Y, dt, max_substeps=2048, status=None, n_steps=None, opts=None, stream=None):
+    def chem_step_taped(self, T, p, Y, dt, max_substeps=1024, status=None, n_steps=None, opts=None, stream=None):
         """df_chem_step (each cell from a fresh start) that records the adjoint's tape; T, Y in
         place.  Returns the tape (uint8 device tensor) for chem_adjoint."""
         import torch
@@ -243,7 +243,7 @@ def _chem_step_function():
 _ChemStepFunction = None
 
 
-def chem_step_diff(mech: Mechanism, T0, Y0, p, dt, lnA=None, max_substeps=2048, opts=None):
+def chem_step_diff(mech: Mechanism, T0, Y0, p, dt, lnA=None, max_substeps=1024, opts=None):
     """Differentiable chemistry step: returns (T, Y) after dt, with gradients to T0 [n], Y0 [K, n]
     and, when lnA is given, to it.  lnA is a float64 device tensor [M] standing for the natural
     logs of the mechanism's pre-exponential factors (k_inf's for falloff rows) in the file's

@@ -291,151 +291,142 @@ struct AdjArgs {
     const double *Tb, *Yb;   // seeds, [n] and [K][ld]
     double *T0b, *Y0b;       // [n], [K][ld]
     double *thc;             // [M][ld] per-cell ln A adjoints in file order, or nullptr
-    double *ws;              // per-cell work: [6N] u, [6N] ubar, [N*N] LU, [N] pivots, [M] thbar (stride n)
+    double *wth;             // [M][n] per-cell ln A adjoints in stored order (for the sum)
 };
 
+constexpr int kAdjLanes = 8;                  // lanes per cell
+constexpr int kAdjCells = kWave / kAdjLanes;  // cells per block (one wave)
+
+// Per-block LDS of the sweep, in doubles: per lane the dual concentrations and their adjoints
+// (2 x N duals), the production-rate weights and rates (2 x 2K rows) and the ln A adjoints
+// (M); per cell the stage adjoints ubar (6N), the products' seeds rbar (6N), the chain's
+// state adjoint (N) and the second-order parts of the six stages (6N).
+template <int K>
+struct AdjLds {
+    static constexpr int N = K + 1;
+    static constexpr int kCell = 19 * N;
+    static size_t bytes(int M) { return size_t(8) * (size_t(kWave) * (8 * N + M) + size_t(kAdjCells) * kCell); }
+};
+
+// One cell per group of 8 lanes.  Per sub-step, last to first: lane 0 runs the chain of
+// transposed solves (products with W^-T from the tape's inverse) and first-order products
+// through the stages; then lanes 0..5 each take one stage's second-order term (the dual
+// product at y + eps u_i), and lane 0 adds them up.
 template <int K>
 __global__ __launch_bounds__(kWave) void adjoint_kernel(MechDev m, AdjArgs a) {
-    using C = Cell<K>;
     constexpr int N = K + 1;
-    // LDS per lane: Cell's arrays (5N slots: c, e, 1/e, H/RT, dq/dc), the dual concentrations
-    // and their adjoints (2N + 2N slots), ln A adjoints (M slots, dynamic)
     extern __shared__ double lds[];
-    double *sh = lds + threadIdx.x;
-    Dual *cs = reinterpret_cast<Dual *>(lds + 5 * N * kWave) + threadIdx.x;
+    const int lane = threadIdx.x, r = lane % kAdjLanes, g = lane / kAdjLanes;
+    Dual *cs = reinterpret_cast<Dual *>(lds) + lane;
     Dual *cb = cs + N * kWave;
-    // production-rate weights and rates of the products: in the Cell region, which is idle while
-    // the reverse phase runs (its neutral slots are set again before each forward recompute)
-    double *omr = sh, *wdr = sh + 2 * K * kWave;
-    static_assert(4 * K <= 5 * N, "product arrays must fit in the Cell region");
-    // the plain-number products use the value half of the same slots
+    double *omr = lds + 4 * N * kWave + lane, *wdr = omr + 2 * K * kWave;
+    double *th = lds + (4 * N + 4 * K) * kWave + lane;
     double *csd = reinterpret_cast<double *>(cs), *cbd = reinterpret_cast<double *>(cb);
-    double *th = lds + 9 * N * kWave + threadIdx.x;
-    const int64_t i = int64_t(blockIdx.x) * kWave + threadIdx.x;
-    if (i >= a.n) return;
-    const int64_t n = a.n, ld = a.ld;
-    const int32_t cnt = reinterpret_cast<const int32_t *>(a.tape + int64_t(a.cap) * (K + 2) * n)[i];
+    double *cell = lds + (4 * N + 4 * K + m.M) * kWave + g * AdjLds<K>::kCell;
+    double *ub = cell, *rbs = cell + 6 * N, *ybase = cell + 12 * N, *ybp = cell + 13 * N;
+    const int64_t i = int64_t(blockIdx.x) * kAdjCells + g;
+    if (i >= a.n) return;  // the lanes of a cell leave together
+    const int64_t ld = a.ld;
+    const Tape tp(K, a.n, a.cap);
+    const int32_t cnt = tp.count(a.tape)[i];
+    const double *T = a.tape + i;
     double lam[N];
     lam[0] = a.Tb[i];
 #pragma unroll
     for (int k = 0; k < K; ++k) lam[1 + k] = a.Yb[k * ld + i];
     for (int j = 0; j < m.M; ++j) at(th, j) = 0.0;
-    double *wu = a.ws + i, *wub = wu + 6 * N * n, *wlu = wub + 6 * N * n, *wpv = wlu + N * N * n;
-    double *wth = wpv + N * n;
     const double p = a.p[i];
-    for (int s = (cnt > 0 ? cnt : 0) - 1; s >= 0; --s) {
+    auto wave_sync = [] {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    for (int64_t s = int64_t(cnt > 0 ? cnt : 0) - 1; s >= 0; --s) {
         double y[N];
 #pragma unroll
-        for (int k = 0; k < N; ++k) y[k] = a.tape[(int64_t(s) * N + k) * n + i];
-        const double h = a.tape[int64_t(a.cap) * N * n + int64_t(s) * n + i];
-        // ---- forward: the sub-step's iteration matrix and stages, as the integrator took them
-        C::init_lds(sh);
-        {
-            double W[N][N], f0[N];
-            int piv[N];
-            C::jacobian(m, p, y, sh, W, f0);
-            const double ig = 1.0 / (Rodas4::g * h);
+        for (int k = 0; k < N; ++k) y[k] = T[tp.y(s, k)];
+        if (r == 0) {
+            const double ih = 1.0 / T[tp.h(s)];
+            double yb[N];
 #pragma unroll
-            for (int r = 0; r < N; ++r)
+            for (int k = 0; k < N; ++k) {
+                yb[k] = lam[k];
 #pragma unroll
-                for (int q = 0; q < N; ++q) W[r][q] = (r == q ? ig : 0.0) - W[r][q];
-            C::lu(W, piv);
-#pragma unroll
-            for (int r = 0; r < N; ++r) {
-                wpv[r * n] = double(piv[r]);
-#pragma unroll
-                for (int q = 0; q < N; ++q) wlu[(r * N + q) * n] = W[r][q];
+                for (int si = 0; si < 6; ++si) ub[si * N + k] = (si < 5 ? Rodas4::a[5][si] : 1.0) * lam[k];
             }
-            const double ih = 1.0 / h;
+#pragma unroll 1
+            for (int si = 5; si >= 0; --si) {
+                // rbar = W^-T ubar_i, streaming the rows of W^-1
+                double rb[N];
 #pragma unroll
-            for (int si = 0; si < 6; ++si) {
-                double v[N];
-                if (si == 0) {
+                for (int c = 0; c < N; ++c) rb[c] = 0.0;
 #pragma unroll
-                    for (int k = 0; k < N; ++k) v[k] = f0[k];
-                } else {
-                    double ys[N];
+                for (int q = 0; q < N; ++q) {
+                    const double uq = ub[si * N + q];
+#pragma unroll
+                    for (int c = 0; c < N; ++c) rb[c] = fma(T[tp.w(s, q * N + c)], uq, rb[c]);
+                }
+#pragma unroll
+                for (int c = 0; c < N; ++c) rbs[si * N + c] = rb[c];
+                if (si > 0) {
+                    double ys[N], v[N];
 #pragma unroll
                     for (int k = 0; k < N; ++k) {
                         double w = y[k];
-#pragma unroll
-                        for (int jj = 0; jj < si; ++jj) w = fma(Rodas4::a[si][jj], wu[(jj * N + k) * n], w);
+                        for (int jj = 0; jj < si; ++jj) w = fma(Rodas4::a[si][jj], T[tp.u(s, jj * N + k)], w);
                         ys[k] = w;
                     }
-                    C::rhs(m, p, ys, sh, v);
+                    vjp<K, double>(m, p, ys, rb, csd, cbd, omr, wdr, th, true, v);
 #pragma unroll
                     for (int k = 0; k < N; ++k) {
-                        double w = 0.0;
-#pragma unroll
-                        for (int jj = 0; jj < si; ++jj) w = fma(Rodas4::c[si][jj], wu[(jj * N + k) * n], w);
-                        v[k] = fma(w, ih, v[k]);
+                        yb[k] += v[k];
+                        for (int jj = 0; jj < si; ++jj)
+                            ub[jj * N + k] += Rodas4::a[si][jj] * v[k] + Rodas4::c[si][jj] * ih * rb[k];
                     }
                 }
-                C::solve(W, piv, v);
-#pragma unroll
-                for (int k = 0; k < N; ++k) wu[(si * N + k) * n] = v[k];
             }
+#pragma unroll
+            for (int k = 0; k < N; ++k) ybase[k] = yb[k];
         }
-        // ---- reverse
-        double yb[N];
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-            yb[k] = lam[k];
-#pragma unroll
-            for (int si = 0; si < 6; ++si) wub[(si * N + k) * n] = (si < 5 ? Rodas4::a[5][si] : 1.0) * lam[k];
-        }
-        const double ih = 1.0 / h;
-#pragma unroll 1
-        for (int si = 5; si >= 0; --si) {
-            double rb[N];
-            {
-                double A[N][N];
-                int piv[N];
-#pragma unroll
-                for (int r = 0; r < N; ++r) {
-                    piv[r] = int(wpv[r * n]);
-#pragma unroll
-                    for (int q = 0; q < N; ++q) A[r][q] = wlu[(r * N + q) * n];
-                }
-#pragma unroll
-                for (int k = 0; k < N; ++k) rb[k] = wub[(si * N + k) * n];
-                solve_T<N>(A, piv, rb);
-            }
-            if (si > 0) {
-                double ys[N], v[N];
-#pragma unroll
-                for (int k = 0; k < N; ++k) {
-                    double w = y[k];
-                    for (int jj = 0; jj < si; ++jj) w = fma(Rodas4::a[si][jj], wu[(jj * N + k) * n], w);
-                    ys[k] = w;
-                }
-                vjp<K, double>(m, p, ys, rb, csd, cbd, omr, wdr, th, true, v);
-#pragma unroll
-                for (int k = 0; k < N; ++k) {
-                    yb[k] += v[k];
-                    for (int jj = 0; jj < si; ++jj)
-                        wub[(jj * N + k) * n] += Rodas4::a[si][jj] * v[k] + Rodas4::c[si][jj] * ih * rb[k];
-                }
-            }
-            // derivative of W through J(y): the dual product at y + eps u_i (stage 0: also the
-            // first-order term J(y)^T rbar, the value part)
+        wave_sync();
+        // derivative of W through J(y): the dual product at y + eps u_i with seed rbar_i (stage 0
+        // also takes the first-order term J(y)^T rbar_0, the value part)
+        if (r < 6) {
             Dual yd[N], vd[N];
+            double rb[N];
 #pragma unroll
-            for (int k = 0; k < N; ++k) yd[k] = Dual{y[k], wu[(si * N + k) * n]};
-            vjp<K, Dual>(m, p, yd, rb, cs, cb, omr, wdr, th, si == 0, vd);
+            for (int k = 0; k < N; ++k) {
+                yd[k] = Dual{y[k], T[tp.u(s, r * N + k)]};
+                rb[k] = rbs[r * N + k];
+            }
+            vjp<K, Dual>(m, p, yd, rb, cs, cb, omr, wdr, th, r == 0, vd);
 #pragma unroll
-            for (int k = 0; k < N; ++k) yb[k] += (si == 0) ? vd[k].v + vd[k].d : vd[k].d;
+            for (int k = 0; k < N; ++k) ybp[r * N + k] = (r == 0) ? vd[k].v + vd[k].d : vd[k].d;
         }
+        wave_sync();
+        if (r == 0) {
 #pragma unroll
-        for (int k = 0; k < N; ++k) lam[k] = yb[k];
+            for (int k = 0; k < N; ++k) {
+                double v = ybase[k];
+#pragma unroll
+                for (int q = 0; q < 6; ++q) v += ybp[q * N + k];
+                lam[k] = v;
+            }
+        }
+        wave_sync();
     }
     const bool ok = cnt > 0;
-    a.T0b[i] = ok ? lam[0] : 0.0;
+    if (r == 0) {
+        a.T0b[i] = ok ? lam[0] : 0.0;
 #pragma unroll
-    for (int k = 0; k < K; ++k) a.Y0b[k * ld + i] = ok ? lam[1 + k] : 0.0;
-    for (int j = 0; j < m.M; ++j) {
-        const double v = ok ? at(th, j) : 0.0;
-        wth[j * n] = v;
+        for (int k = 0; k < K; ++k) a.Y0b[k * ld + i] = ok ? lam[1 + k] : 0.0;
+    }
+    // ln A adjoints: the six lanes' partial sums; lane r takes reactions r, r + 8, ...
+    for (int j = r; j < m.M; j += kAdjLanes) {
+        double v = 0.0;
+        for (int q = 0; q < 6; ++q) v += lds[(4 * N + 4 * K + j) * kWave + g * kAdjLanes + q];
+        v = ok ? v : 0.0;
+        a.wth[int64_t(j) * a.n + i] = v;
         if (a.thc) a.thc[int64_t(m.src[j]) * ld + i] = v;
     }
 }
@@ -457,18 +448,18 @@ __global__ __launch_bounds__(256) void sum_cells_kernel(const double *__restrict
     if (t == 0) out[src[j]] = part_sum[0];
 }
 
-size_t adj_ws_bytes(int K, int M, int64_t n) {
-    const size_t N = size_t(K + 1);
-    return size_t(8) * (12 * N + N * N + N + size_t(M)) * size_t(n);
-}
+size_t adj_ws_bytes(int, int M, int64_t n) { return size_t(8) * size_t(M) * size_t(n); }
 
-size_t adj_lds_bytes(int K, int M) { return size_t(8) * kWave * (9 * size_t(K + 1) + size_t(M)); }
+size_t adj_lds_bytes(int K, int M) {
+    const size_t N = size_t(K + 1);
+    return size_t(8) * (size_t(kWave) * (8 * N + size_t(M)) + size_t(kAdjCells) * 19 * N);
+}
 
 constexpr size_t kAdjLdsMax = 64 * 1024;
 
 template <int K>
 df_status launch_adjoint_k(const MechDev &m, const AdjArgs &a, hipStream_t s) {
-    const int64_t blocks = (a.n + kWave - 1) / kWave;
+    const int64_t blocks = (a.n + kAdjCells - 1) / kAdjCells;
     const size_t lds = adj_lds_bytes(K, m.M);
     hipLaunchKernelGGL(adjoint_kernel<K>, dim3(unsigned(blocks)), dim3(kWave), lds, s, m, a);
     const hipError_t e = hipGetLastError();
@@ -484,7 +475,7 @@ bool adjoint_supported(const MechDev &m) {
 #define DF_CASE(k) k_ok = k_ok || m.K == k;
     DF_ADJ_SPECIES_LIST(DF_CASE)
 #undef DF_CASE
-    return k_ok && adj_lds_bytes(m.K, m.M) <= kAdjLdsMax;
+    return k_ok && adj_lds_bytes(m.K, m.M) <= kAdjLdsMax && chem_coop_supported(m);
 }
 
 struct DeviceScope {
@@ -550,7 +541,8 @@ extern "C" df_status df_chem_step_taped(const df_mech *mech, int64_t n_cells, in
     StepArgs a{n_cells, ld, dt, nullptr, p, T, Y, nullptr, nullptr, cell_status, n_steps, kernel_opts(o), DF_CELL_OK};
     a.tape = static_cast<double *>(tape);
     a.tape_cap = max_substeps;
-    return launch_chem_step(mech->dev, a, 1, nullptr, nullptr, static_cast<hipStream_t>(hip_stream));
+    return launch_chem_coop(mech->dev, a, CellQueue{nullptr, nullptr, nullptr, nullptr, nullptr, 0},
+                            static_cast<hipStream_t>(hip_stream));
 }
 
 extern "C" df_status df_chem_adjoint_workspace_size(const df_mech *mech, int64_t n_cells, size_t *bytes) {
@@ -609,8 +601,7 @@ extern "C" df_status df_chem_adjoint(const df_mech *mech, int64_t n_cells, int64
             st = fail(DF_E_UNSUPPORTED, std::string(who) + ": no adjoint kernel for this mechanism");
     }
     if (st == DF_OK && lnA_bar && M > 0) {
-        const size_t N = size_t(K + 1);
-        const double *wth = static_cast<const double *>(workspace) + (12 * N + N * N + N) * size_t(n_cells);
+        const double *wth = static_cast<const double *>(workspace);
         hipLaunchKernelGGL(sum_cells_kernel, dim3(unsigned(M)), dim3(256), 256 * sizeof(double), s, wth, n_cells,
                            mech->dev.src, lnA_bar);
         const hipError_t e = hipGetLastError();

@@ -545,6 +545,7 @@ __device__ bool group_load(const StepArgs &a, const double *sp, int r, int64_t i
             }
         }
         if (a.rr && r >= 1 && r <= K) a.rr[(r - 1) * a.ld + i] = 0.0;
+        if (a.tape && r == 0) Tape(K, a.n, a.tape_cap).count(a.tape)[i] = -1;
         return false;
     }
     c.ip = 1.0 / c.p;
@@ -575,6 +576,11 @@ __device__ bool group_load(const StepArgs &a, const double *sp, int r, int64_t i
 template <int K>
 __device__ void group_finish(const StepArgs &a, int r, const GroupTask<K> &c, int st) {
     const int64_t i = c.i;
+    if (a.tape) {
+        // a cell whose accepted sub-steps did not all fit keeps its result but has no tape
+        if (st == DF_CELL_OK && c.acc > a.tape_cap) st = DF_CELL_TAPE_FULL;
+        if (r == 0) Tape(K, a.n, a.tape_cap).count(a.tape)[i] = (st == DF_CELL_OK) ? c.acc : -1;
+    }
     if (r == 0) {
         a.T[i] = c.y[0];
         if (a.h_io) a.h_io[i] = (st == DF_CELL_OK) ? c.h_final : c.h;
@@ -659,6 +665,18 @@ __device__ bool group_attempt(const StepArgs &a, const typename Coop<K, RPL>::Ta
         fac = fmin(fmx, fmax(0.2, 0.9 / sqrt(sqrt(err))));  // 0.9 err^(-1/4)
 
     if (isfinite(err) && err <= 1.0) {
+        if (a.tape && c.acc < a.tape_cap && r < N) {
+            // the accepted sub-step for the adjoint: lane r's component of the start state, its
+            // row of W^-1 and its components of the stage vectors
+            const Tape tp(K, a.n, a.tape_cap);
+            const int64_t s = c.acc;
+            a.tape[tp.y(s, r) + c.i] = c.yr;
+            if (r == 0) a.tape[tp.h(s) + c.i] = ht;
+#pragma unroll
+            for (int q = 0; q < N; ++q) a.tape[tp.w(s, r * N + q) + c.i] = winv[q];
+#pragma unroll
+            for (int si = 0; si < 6; ++si) a.tape[tp.u(s, si * N + r) + c.i] = u[si];
+        }
         ++c.acc;
         C::gather(sh + C::oVec, r, ynr, c.y);
         c.yr = (r < N) ? ynr : 0.0;

@@ -96,16 +96,36 @@ struct StepArgs {
     int32_t *status, *nsteps;
     Opts o;
     int32_t status_ok;  // status written for cells that succeed (DF_CELL_OK or DF_CELL_DNN_FALLBACK)
-    // tape of the accepted sub-steps (one-cell-per-lane launch only; nullptr = none), for the
-    // adjoint: with S = tape_cap and N = K + 1, doubles [S][N][n] start states, then [S][n]
-    // step lengths, then int32 [n] sub-step counts (-1: no usable tape for the cell)
+    // tape of the accepted sub-steps for the adjoint (16-lane launch only; nullptr = none),
+    // layout in Tape below
     double *tape = nullptr;
     int32_t tape_cap = 0;
 };
 
-inline size_t tape_bytes(int K, int64_t n, int32_t cap) {
-    return size_t(8) * size_t(cap) * size_t(K + 2) * size_t(n) + size_t(4) * size_t(n);
-}
+// Tape of a taped step: for each accepted sub-step s < cap of each of n cells, its start
+// state y (N = K + 1), its length h, the inverse of its iteration matrix W = I/(g h) - J(y)
+// (entry (r, c) at r N + c) and its six stage vectors (entry (i, k) at i N + k); then the
+// sub-step count of each cell (int32, -1 for a cell without a tape).  Every array is
+// cell-minor (stride n), so the lanes of a wave read and write it coalesced.
+struct Tape {
+    int N;
+    int64_t n, cap;
+    __host__ __device__ Tape(int K, int64_t n_, int64_t cap_) : N(K + 1), n(n_), cap(cap_) {}
+    __host__ __device__ int64_t y(int64_t s, int k) const { return (s * N + k) * n; }
+    __host__ __device__ int64_t h(int64_t s) const { return cap * N * n + s * n; }
+    __host__ __device__ int64_t w(int64_t s, int e) const { return cap * (N + 1) * n + (s * N * N + e) * n; }
+    __host__ __device__ int64_t u(int64_t s, int e) const {
+        return cap * (N + 1 + N * N) * n + (s * 6 * N + e) * n;
+    }
+    __host__ __device__ int64_t doubles() const { return cap * (7 * N + 1 + N * N) * n; }
+    __host__ __device__ int32_t *count(double *t) const { return reinterpret_cast<int32_t *>(t + doubles()); }
+    __host__ __device__ const int32_t *count(const double *t) const {
+        return reinterpret_cast<const int32_t *>(t + doubles());
+    }
+    size_t bytes() const { return size_t(8) * size_t(doubles()) + size_t(4) * size_t(n); }
+};
+
+inline size_t tape_bytes(int K, int64_t n, int32_t cap) { return Tape(K, n, cap).bytes(); }
 
 // Where the lanes (or 16-lane groups) of a launch get their cells.
 //   static: slot s (global lane or group index) takes cell cidx[s] (or s), for s < *dcount (or n);

@@ -346,23 +346,6 @@ struct LaneTask {
     bool prev_rej, fresh;
 };
 
-// Tape of the accepted sub-steps (layout in StepArgs): the start state and length of
-// accepted sub-step s of the lane's cell, and the cell's sub-step count.
-template <int K>
-__device__ __forceinline__ void tape_record(const StepArgs &a, const LaneTask<K> &c, double ht) {
-    constexpr int N = K + 1;
-    const int64_t n = a.n, s = c.acc;
-    double *ys = a.tape + s * N * n + c.i;
-#pragma unroll
-    for (int k = 0; k < N; ++k) ys[k * n] = c.y[k];
-    a.tape[int64_t(a.tape_cap) * N * n + s * n + c.i] = ht;
-}
-
-template <int K>
-__device__ __forceinline__ int32_t *tape_count(const StepArgs &a) {
-    return reinterpret_cast<int32_t *>(a.tape + int64_t(a.tape_cap) * (K + 2) * a.n);
-}
-
 // Load cell i.  A cell whose input is unusable (non-finite, p or T not positive, or a
 // step length that is not positive and finite) gets status DF_CELL_NONFINITE, zero
 // steps and zero rr, and false is returned.
@@ -386,7 +369,6 @@ __device__ bool lane_load(const StepArgs &a, int64_t i, LaneTask<K> &c) {
         }
         if (a.rr)
             for (int k = 0; k < K; ++k) a.rr[k * a.ld + i] = 0.0;
-        if (a.tape) tape_count<K>(a)[i] = -1;
         return false;
     }
     const double h_in = a.h_io ? a.h_io[i] : 0.0;
@@ -405,11 +387,6 @@ __device__ bool lane_load(const StepArgs &a, int64_t i, LaneTask<K> &c) {
 template <int K>
 __device__ void lane_finish(const MechDev &m, const StepArgs &a, const LaneTask<K> &c, int st) {
     const int64_t i = c.i;
-    if (a.tape) {
-        // a cell whose accepted sub-steps did not all fit keeps its result but has no tape
-        if (st == DF_CELL_OK && c.acc > a.tape_cap) st = DF_CELL_TAPE_FULL;
-        tape_count<K>(a)[i] = (st == DF_CELL_OK) ? c.acc : -1;
-    }
     if (a.rr) {
         // rr = rho0 (Y - Y0) / dt with rho0 the density of the input state, which is
         // still in memory: read it back instead of keeping it live through the loop
@@ -428,7 +405,7 @@ __device__ void lane_finish(const MechDev &m, const StepArgs &a, const LaneTask<
 #pragma unroll
     for (int k = 0; k < K; ++k) a.Y[k * a.ld + i] = c.y[1 + k];
     if (a.h_io) a.h_io[i] = (st == DF_CELL_OK) ? c.h_final : c.h;
-    if (a.status) a.status[i] = (st == DF_CELL_OK) ? a.status_ok : st;  // TAPE_FULL passes through
+    if (a.status) a.status[i] = (st == DF_CELL_OK) ? a.status_ok : st;
     if (a.nsteps) {
         a.nsteps[i] = c.acc;
         a.nsteps[a.n + i] = c.rej;
@@ -540,7 +517,6 @@ __device__ bool lane_attempt(const MechDev &m, const StepArgs &a, double *sh, La
         fac = fmin(fmx, fmax(0.2, 0.9 * pow(err, -0.25)));
 
     if (isfinite(err) && err <= 1.0) {
-        if (a.tape && c.acc < a.tape_cap) tape_record<K>(a, c, ht);
         ++c.acc;
 #pragma unroll
         for (int k = 0; k < N; ++k) c.y[k] = yn[k];
