@@ -171,6 +171,138 @@ def batching_study(gm, mech_h, dev):
             "cells_per_s_autotuned": n / (queue * 1e-3), "speedup_vs_naive": naive / queue}
 
 
+def adjoint_lane_ops(mech, ops):
+    """Algorithmic FP64 lane-ops of the reverse sweep per accepted sub-step: six products with
+    W^-T (N^2 each), five first-order vector-Jacobian products of f at the stage states, six
+    second-order products in dual-number arithmetic, and the stage-adjoint updates.  A
+    vector-Jacobian product is the right-hand side plus its reverse accumulation (per
+    reaction: the seed through the stoichiometry, the temperature and slot derivatives, the
+    third-body term, the falloff derivatives; per species: the mixture terms); dual numbers
+    cost 3 lane-ops per operation."""
+    K, M = mech.n_species, mech.n_reactions
+    N = K + 1
+    nu = mech.nu_prod - mech.nu_reac
+    nnz = (nu != 0).sum(axis=1)
+    n_tb = int(np.count_nonzero(mech.reaction_type != 0))
+    n_troe = int(np.count_nonzero(mech.reaction_type == 2))
+    reverse = int(np.sum(nnz + 25)) + n_tb * K + n_troe * (30 + 4 * DIVISION_OPS) + 20 * K
+    vjp = ops["rhs"] + reverse
+    per_substep = 6 * N * N + 5 * vjp + 6 * 3 * vjp + 30 * N
+    return {"per_substep": int(per_substep), "vjp": int(vjp)}
+
+
+def adjoint_study(gm, mech_h, dev, with_cpu, threads):
+    """Differentiation workload: 4096 cells, T0 1000-1600 K, phi 0.5-2, p = 1 atm, dt = 1e-5 s.
+    The taped step (16 lanes per cell, recording the stage tape), one reverse sweep (the
+    gradient of a scalar loss with respect to T0, Y0 and every ln A), and the full 10 x 34
+    Jacobian per cell (one sweep per output component); the oracle's forward sensitivities
+    (complex-step differentiation of its replay) on a sample of cells for the CPU rate."""
+    import torch
+    from synth import fields
+    n = 4096
+    dt = 1e-5
+    cap = 1024
+    f = fields.ignition_cells(mech_h, n=n, seed=2023)
+    K = mech_h.n_species
+    T0 = torch.tensor(f["T"], dtype=torch.float64, device=dev)
+    p = torch.tensor(f["p"], dtype=torch.float64, device=dev)
+    Y0 = torch.tensor(np.ascontiguousarray(f["Y"]), dtype=torch.float64, device=dev)
+    ns = torch.zeros(2 * n, dtype=torch.int32, device=dev)
+    st = torch.zeros(n, dtype=torch.int32, device=dev)
+    rng = np.random.default_rng(0)
+    Tb = torch.tensor(rng.standard_normal(n), dtype=torch.float64, device=dev)
+    Yb = torch.tensor(rng.standard_normal((K, n)), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    taped, sweep = [], []
+    for it in range(3):
+        T, Y = T0.clone(), Y0.clone()
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record(stream)
+        tape = gm.chem_step_taped(T, p, Y, dt, max_substeps=cap, status=st, n_steps=ns, stream=stream)
+        e[1].record(stream)
+        gm.chem_adjoint(p, tape, cap, Tb, Yb, stream=stream)
+        e[2].record(stream)
+        torch.cuda.synchronize()
+        if it > 0:
+            taped.append(e[0].elapsed_time(e[1]))
+            sweep.append(e[1].elapsed_time(e[2]))
+    t_tape, t_sweep = float(np.mean(taped)), float(np.mean(sweep))
+    nsh = ns.cpu().numpy()
+    acc = int(nsh[:n].sum())
+    aops = adjoint_lane_ops(mech_h, integrator_lane_ops(mech_h))
+    tflops = 2.0 * aops["per_substep"] * acc / (t_sweep * 1e-3) / 1e12
+    out = {"workload": "4096 ignition cells, T0 1000-1600 K, phi 0.5-2, p=1 atm, dt=1e-5 s; gradients of "
+                       "(T, Y) at dt w.r.t. T0, Y0 and 24 ln A on the frozen sub-step sequence",
+           "n_cells": n, "accepted_total": acc, "accepted_max": int(nsh[:n].max()),
+           "status_counts": np.bincount(st.cpu().numpy()).tolist(),
+           "taped_step_ms": t_tape, "reverse_sweep_ms": t_sweep,
+           "gradient_cells_per_s": n / ((t_tape + t_sweep) * 1e-3),
+           "full_jacobian_cells_per_s": n / ((t_tape + (K + 1) * t_sweep) * 1e-3),
+           "roofline": {"bound": "alu", "kernel": "adjoint_kernel<9> (FP64 VALU, 8 lanes per cell)",
+                        "achieved": tflops, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                        "frac": tflops / PEAK_FP64_TFLOPS, "traffic": None, "lane_ops": aops}}
+    if with_cpu:
+        import oracle
+        from oracle import sensitivity as sens
+        om = oracle.Mech(MECH)
+        kin = sens.Kinetics(mech_h)
+        tab = oracle.rodas4_tableau()
+        sample = [0, 1, 2]
+        t1 = time.perf_counter()
+        for i in sample:
+            _, _, _, hs, _ = om.record(f["T"][i], f["p"][i], f["Y"][:, i], dt)
+            sens.sensitivities(kin, tab, f["p"][i], np.concatenate([[f["T"][i]], f["Y"][:, i]]), hs)
+        t_cpu = time.perf_counter() - t1
+        out["cpu_oracle"] = {"value": len(sample) / t_cpu, "unit": "cells/s (full 10 x 34 Jacobian)", "cores": 1,
+                             "kind": "oracle", "sample": f"forward sensitivities of cells {sample} ({t_cpu:.1f} s)"}
+    return out
+
+
+def training_study(gm, dnn_path, mech_h, dev):
+    """One Adam step of the DNN on device-generated pairs: 8192 states (ignition cells and hotter
+    states) advanced by the integrator over the network's dt, turned into (input, target) rows,
+    then timed training steps (forward, loss, backward, Adam).  FLOPs of a step: the forward
+    products, and twice as many backward (data and weight gradients)."""
+    import torch
+    import paper_2210_07094_amd as df
+    from synth import fields
+    dnn = df.DNN(dnn_path, gm)
+    n = 8192
+    f = fields.ignition_cells(mech_h, n=n, seed=99)
+    f["T"][: n // 2] = np.random.default_rng(2).uniform(900.0, 2400.0, n // 2)
+    p = torch.tensor(f["p"], device=dev)
+    T0 = torch.tensor(f["T"], device=dev)
+    Y0 = torch.tensor(np.ascontiguousarray(f["Y"]), device=dev)
+    T1, Y1 = T0.clone(), Y0.clone()
+    gm.chem_step(T1, p, Y1, dnn.dt_train, h=torch.zeros(n, dtype=torch.float64, device=dev))
+    tr = df.Trainer(dnn, n)
+    x, t, v = tr.make_batch(p, T0, Y0, Y1)
+    keep = v.bool()
+    x, t = x[keep].contiguous(), t[keep].contiguous()
+    B = int(x.shape[0])
+    opts = df.adam_opts(lr=1e-4)
+    stream = torch.cuda.current_stream()
+    losses = []
+    for _ in range(3):
+        losses.append(float(tr.step(x, t, opts=opts).cpu()[0]))
+    reps = 10
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        last = tr.step(x, t, opts=opts)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    flops = 3.0 * mlp_flops(dnn.dims) * B
+    tflops = flops / (ms * 1e-3) / 1e12
+    return {"workload": "Adam steps of the 11-1600-800-400-9 network on pairs the integrator made from 8192 "
+                        "states (dt = network dt); batch = the states inside the training box",
+            "batch": B, "ms_per_step": ms, "samples_per_s": B / (ms * 1e-3),
+            "loss_first": losses[0], "loss_after_13_steps": float(last.cpu()[0]),
+            "roofline": {"bound": "mfma", "achieved": tflops, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                         "frac": tflops / PEAK_BF16_TFLOPS}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -178,6 +310,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing (cpu_baseline null)")
     ap.add_argument("--no-batching", action="store_true", help="skip the 1M-cell scheduling study")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the 4096-cell adjoint study")
+    ap.add_argument("--no-training", action="store_true", help="skip the DNN training study")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported (cells are independent, "
@@ -284,6 +418,9 @@ def main():
         err["integrator_max_rel_vs_oracle"] = float(max(relT.max(), relY.max()))
 
     batching = None if a.no_batching else batching_study(gm, mech_h, dev)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    adjoint = None if a.no_adjoint else adjoint_study(gm, mech_h, dev, not a.no_cpu, threads)
+    training = None if a.no_training else training_study(gm, DNN_W, mech_h, dev)
 
     out = {
         "metric": "cells/s per chemistry step: FP64 stiff integrator vs BF16 DNN at stated error",
@@ -317,6 +454,8 @@ def main():
                      "traffic": measured_traffic(), "lane_ops_per_attempt": ops},
         "dnn_error_vs_oracle_integrator": err,
         "batching_mixing_layer": batching,
+        "adjoint": adjoint,
+        "dnn_training": training,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -62,8 +62,9 @@ typedef int32_t df_status;
 #define DF_CELL_TAPE_FULL 5    /* taped step: more accepted sub-steps than the tape holds; state as
                                   integrated, no tape (the adjoint gives zero gradients) */
 
-typedef struct df_mech df_mech; /* opaque mechanism handle */
-typedef struct df_dnn df_dnn;   /* opaque DNN handle */
+typedef struct df_mech df_mech;       /* opaque mechanism handle */
+typedef struct df_dnn df_dnn;         /* opaque DNN handle */
+typedef struct df_trainer df_trainer; /* opaque DNN training state */
 
 /* Integrator options (see df_chem_default_opts for the defaults). */
 typedef struct {
@@ -280,6 +281,59 @@ df_status df_dnn_step(const df_dnn *dnn, const df_mech *mech, int64_t n_cells, i
                       const double *p, double *T, double *Y, double *rr, int32_t *cell_status, void *workspace,
                       size_t workspace_bytes, const df_dnn_opts *opts, const df_chem_opts *fallback_opts,
                       void *hip_stream);
+
+/*
+ * ---- Training the DNN on the device ----
+ * The network of the DNN form (Sec. "Chemistry Integration") fitted to pairs the integrator
+ * produces, with hand-written backward kernels: mean squared error of the z-scored outputs,
+ * L = 1/(B O) sum_b sum_o (u_bo - t_bo)^2, bf16 forward and backward products on the matrix
+ * cores with fp32 accumulation, fp32 gradients, Adam on fp32 master weights.  Training
+ * rewrites the DNN handle's weights, so df_dnn_step runs the trained network.
+ */
+typedef struct {
+    float lr, beta1, beta2, eps; /* defaults 1e-4, 0.9, 0.999, 1e-8 */
+} df_adam_opts;
+void df_adam_default_opts(df_adam_opts *opts);
+
+/* Training state for batches of up to max_batch rows: fp32 master copies of the weights, Adam
+   moments, transposed bf16 weights and activation buffers (device memory owned by the trainer;
+   about 2.2 kB per batch row plus 50 bytes per parameter for the 11-1600-800-400-9 network).
+   Errors: DF_E_INVALID, DF_E_UNSUPPORTED (output width other than 9), DF_E_HIP. */
+df_status df_dnn_trainer_create(df_dnn *dnn, int64_t max_batch, df_trainer **out);
+void df_dnn_trainer_free(df_trainer *trainer);
+
+/*
+ * Training rows from states before and after one integrator step of the network's dt_train:
+ *   p, T [n], Y0 [K*ld]   in   state before the step;  Y1 [K*ld] in  mass fractions after it
+ *   x [n][K+2] fp32       out  z-scored (T, p, Box-Cox(Y0)), the network's input
+ *   target [n][K] fp32    out  z-scored Box-Cox(Y1) - Box-Cox(Y0), the network's output
+ *   valid [n] int32       out  1 inside the network's training box, else 0 (nullable)
+ * Errors: DF_E_INVALID, DF_E_UNSUPPORTED (species count other than 9), DF_E_HIP.
+ */
+df_status df_dnn_make_batch(const df_dnn *dnn, int64_t n_cells, int64_t ld, const double *p, const double *T,
+                            const double *Y0, const double *Y1, float *x, float *target, int32_t *valid,
+                            void *hip_stream);
+
+/*
+ * One training step on `batch` rows (1 <= batch <= max_batch): forward, loss, gradients, and,
+ * when update != 0, one Adam step (opts nullable = defaults).  x [batch][K+2], target
+ * [batch][K] fp32 device arrays as df_dnn_make_batch writes them; loss (nullable) receives L,
+ * the loss before the update, as one fp32 on the device.  Asynchronous on hip_stream; the
+ * trainer's buffers are reused by the next call on it.
+ * Errors: DF_E_INVALID (null trainer/array, batch out of range, bad Adam options), DF_E_HIP.
+ */
+df_status df_dnn_train_step(df_trainer *trainer, int64_t batch, const float *x, const float *target,
+                            const df_adam_opts *opts, int32_t update, float *loss, void *hip_stream);
+
+/* Copy a trainer array of layer `layer` (0 .. n_layers-1) into dst (device, fp32):
+   what = 0 master weights [n_out][n_in], 1 master biases [n_out], 2 weight gradients of the
+   last step [n_out][n_in], 3 bias gradients [n_out].  Errors: DF_E_INVALID, DF_E_HIP. */
+df_status df_dnn_trainer_get(const df_trainer *trainer, int32_t layer, int32_t what, float *dst, void *hip_stream);
+
+/* Set the weights (what = 0, src [n_out][n_in]) or biases (what = 1, src [n_out]) of layer
+   `layer` from fp32 device memory: the trainer's master copy and the handle's weights (bf16)
+   both take them; the Adam moments are left as they are.  Errors: DF_E_INVALID, DF_E_HIP. */
+df_status df_dnn_trainer_set(df_trainer *trainer, int32_t layer, int32_t what, const float *src, void *hip_stream);
 
 #ifdef __cplusplus
 }

@@ -85,4 +85,4 @@ def make_batch(net, T, p, Y0, Y1):
     x = ((f.T - net["mu_in"]) / net["sig_in"])
     tgt = (((z1 - z0).T - net["mu_out"]) / net["sig_out"])
     valid = np.all((f.T >= net["box_lo"]) & (f.T <= net["box_hi"]), axis=1)
-    return x, tgt, valid
+    return np.ascontiguousarray(x), np.ascontiguousarray(tgt), valid

@@ -13,9 +13,9 @@ from __future__ import annotations
 import ctypes as C
 
 from ._lib import (CELL_DNN_FALLBACK, CELL_H_UNDERFLOW, CELL_MAX_STEPS, CELL_NONFINITE, CELL_OK,  # noqa
-                   CELL_TAPE_FULL, ChemOpts, DfError, DnnOpts, check, lib)
+                   CELL_TAPE_FULL, AdamOpts, ChemOpts, DfError, DnnOpts, check, lib)
 
-__all__ = ["Mechanism", "DNN", "chem_opts", "dnn_opts", "chem_step_diff", "DfError", "lib"]
+__all__ = ["Mechanism", "DNN", "Trainer", "chem_opts", "dnn_opts", "adam_opts", "chem_step_diff", "DfError", "lib"]
 
 
 def chem_opts(**kw) -> ChemOpts:
@@ -29,6 +29,14 @@ def chem_opts(**kw) -> ChemOpts:
 def dnn_opts(**kw) -> DnnOpts:
     o = DnnOpts()
     lib().df_dnn_default_opts(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def adam_opts(**kw) -> AdamOpts:
+    o = AdamOpts()
+    lib().df_adam_default_opts(C.byref(o))
     for k, v in kw.items():
         setattr(o, k, v)
     return o
@@ -278,6 +286,11 @@ class DNN:
         self.dims = [dims[i] for i in range(L.value + 1)]
         self.lam = lam.value
         self.dt_train = dtt.value
+        self.K = self.dims[-1]
+
+    @property
+    def handle(self):
+        return self._h
 
     def close(self):
         if getattr(self, "_h", None):
@@ -320,3 +333,76 @@ class DNN:
                 workspace.numel(), C.byref(opts) if opts is not None else None,
                 C.byref(fallback_opts) if fallback_opts is not None else None, _stream(stream))
         return check(lib().df_dnn_step(*args))
+
+
+class Trainer:
+    """Training state of a DNN handle on its device (df_dnn_trainer_create); each update rewrites
+    the handle's weights."""
+
+    def __init__(self, dnn: "DNN", max_batch: int):
+        self.dnn = dnn
+        self.max_batch = int(max_batch)
+        h = C.c_void_p()
+        check(lib().df_dnn_trainer_create(dnn.handle, self.max_batch, C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().df_dnn_trainer_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def make_batch(self, p, T, Y0, Y1, stream=None):
+        """(x [n, K+2], target [n, K], valid [n]) from states before (p, T, Y0) and after (Y1) an
+        integrator step of the network's dt (df_dnn_make_batch)."""
+        import torch
+        n = T.numel()
+        K = self.dnn.K
+        dev = self.dnn.device
+        ld = Y0.shape[1]
+        x = torch.empty(n, K + 2, dtype=torch.float32, device=f"cuda:{dev}")
+        t = torch.empty(n, K, dtype=torch.float32, device=f"cuda:{dev}")
+        v = torch.empty(n, dtype=torch.int32, device=f"cuda:{dev}")
+        check(lib().df_dnn_make_batch(self.dnn.handle, n, ld, _ptr(p, torch.float64, "p", n, dev),
+                                      _ptr(T, torch.float64, "T", n, dev), _ptr(Y0, torch.float64, "Y0", K * ld, dev),
+                                      _ptr(Y1, torch.float64, "Y1", K * ld, dev), _ptr(x, torch.float32, "x"),
+                                      _ptr(t, torch.float32, "target"), _ptr(v, torch.int32, "valid"),
+                                      _stream(stream)))
+        return x, t, v
+
+    def step(self, x, target, opts=None, update=True, stream=None):
+        """One training step on the rows of x [B, K+2], target [B, K] (fp32 device); returns the
+        loss before the update as a 1-element device tensor."""
+        import torch
+        dev = self.dnn.device
+        B = x.shape[0]
+        loss = torch.empty(1, dtype=torch.float32, device=f"cuda:{dev}")
+        check(lib().df_dnn_train_step(self._h, B, _ptr(x, torch.float32, "x", B * x.shape[1], dev),
+                                      _ptr(target, torch.float32, "target", B * target.shape[1], dev),
+                                      C.byref(opts) if opts is not None else None, 1 if update else 0,
+                                      _ptr(loss, torch.float32, "loss", 1, dev), _stream(stream)))
+        return loss
+
+    def get(self, layer: int, what: str, stream=None):
+        """'W', 'b', 'dW' or 'db' of layer `layer` (fp32 device tensor, unpadded)."""
+        import torch
+        code = {"W": 0, "b": 1, "dW": 2, "db": 3}[what]
+        dims = self.dnn.dims
+        shape = (dims[layer + 1], dims[layer]) if code in (0, 2) else (dims[layer + 1],)
+        out = torch.empty(*shape, dtype=torch.float32, device=f"cuda:{self.dnn.device}")
+        check(lib().df_dnn_trainer_get(self._h, int(layer), code, _ptr(out, torch.float32, what), _stream(stream)))
+        return out
+
+    def set(self, layer: int, what: str, value, stream=None):
+        """Set 'W' [n_out, n_in] or 'b' [n_out] of layer `layer` (fp32 device tensor)."""
+        import torch
+        code = {"W": 0, "b": 1}[what]
+        dims = self.dnn.dims
+        numel = dims[layer + 1] * dims[layer] if code == 0 else dims[layer + 1]
+        check(lib().df_dnn_trainer_set(self._h, int(layer), code,
+                                       _ptr(value, torch.float32, what, numel, self.dnn.device), _stream(stream)))

@@ -27,6 +27,10 @@ class ChemOpts(C.Structure):
                 ("max_steps", C.c_int32), ("mapping", C.c_int32), ("schedule", C.c_int32), ("coop_blocks", C.c_int32)]
 
 
+class AdamOpts(C.Structure):
+    _fields_ = [("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float)]
+
+
 class DnnOpts(C.Structure):
     _fields_ = [("renormalise", C.c_int32), ("fallback", C.c_int32), ("reserved0", C.c_int32),
                 ("reserved1", C.c_int32)]
@@ -82,6 +86,18 @@ def lib():
     L.df_chem_adjoint_workspace_size.argtypes = [vp, i64, C.POINTER(C.c_size_t)]
     L.df_chem_adjoint.restype = i32
     L.df_chem_adjoint.argtypes = [vp, i64, i64, vp, vp, C.c_size_t, i32, vp, vp, vp, vp, vp, vp, vp, C.c_size_t, vp]
+    L.df_adam_default_opts.argtypes = [C.POINTER(AdamOpts)]
+    L.df_dnn_trainer_create.restype = i32
+    L.df_dnn_trainer_create.argtypes = [vp, i64, C.POINTER(vp)]
+    L.df_dnn_trainer_free.argtypes = [vp]
+    L.df_dnn_make_batch.restype = i32
+    L.df_dnn_make_batch.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp]
+    L.df_dnn_train_step.restype = i32
+    L.df_dnn_train_step.argtypes = [vp, i64, vp, vp, C.POINTER(AdamOpts), i32, vp, vp]
+    L.df_dnn_trainer_get.restype = i32
+    L.df_dnn_trainer_get.argtypes = [vp, i32, i32, vp, vp]
+    L.df_dnn_trainer_set.restype = i32
+    L.df_dnn_trainer_set.argtypes = [vp, i32, i32, vp, vp]
     L.df_chem_step_cells.restype = i32
     L.df_chem_step_cells.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t,
                                      C.POINTER(ChemOpts), vp]

@@ -25,7 +25,7 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", os.path.j
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
 
-SOURCES = ["df_mech.cpp", "df_chem.hip", "df_chem_coop.hip", "df_dnn.hip", "df_mlp.hip", "df_adjoint.hip"]
+SOURCES = ["df_mech.cpp", "df_chem.hip", "df_chem_coop.hip", "df_dnn.hip", "df_mlp.hip", "df_adjoint.hip", "df_train.hip"]
 
 
 def _compile(src: str, verbose: bool) -> str:

@@ -82,6 +82,23 @@ template <class S>
 __device__ __forceinline__ S &slot(S *base, int k) {
     return base[k * kWave * int(sizeof(Dual) / sizeof(S))];
 }
+// Per-species arrays of the products: plain numbers stay in registers (compile-time indices
+// only); duals, whose registers the second-order products cannot spare, live in the lane's LDS
+// rows (see rget()).
+template <int K, class S>
+struct SpArr {
+    double v[K];
+    __device__ SpArr(double *) {}
+    __device__ double get(int k) const { return v[k]; }
+    __device__ void put(int k, double x) { v[k] = x; }
+};
+template <int K>
+struct SpArr<K, Dual> {
+    double *b;
+    __device__ SpArr(double *base) : b(base) {}
+    __device__ Dual get(int k) const;
+    __device__ void put(int k, Dual x);
+};
 // arrays in the Cell region keep its layout, one double per lane in each wave-wide row: a plain
 // number takes row k, a dual rows 2k (value) and 2k + 1 (derivative)
 __device__ __forceinline__ double rget(const double *b, int k, double) { return b[k * kWave]; }
@@ -90,6 +107,14 @@ __device__ __forceinline__ void rput(double *b, int k, double x) { b[k * kWave] 
 __device__ __forceinline__ void rput(double *b, int k, Dual x) {
     b[2 * k * kWave] = x.v;
     b[(2 * k + 1) * kWave] = x.d;
+}
+template <int K>
+__device__ __forceinline__ Dual SpArr<K, Dual>::get(int k) const {
+    return rget(b, k, Dual());
+}
+template <int K>
+__device__ __forceinline__ void SpArr<K, Dual>::put(int k, Dual x) {
+    rput(b, k, x);
 }
 
 // Reverse-mode product of lam with the Jacobian of f at y (the reactor right-hand side of
@@ -130,6 +155,7 @@ __device__ void vjp(const MechDev &m, double p, const S (&y)[K + 1], const doubl
     const S cfac = 1e-6 * rho;
     slot(cs, 0) = mk<S>(1.0);
     slot(cb, 0) = mk<S>(0.0);
+    SpArr<K, S> oms(om), wds(wd);
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const double *r = m.sp + k * kSpTab;
@@ -137,8 +163,8 @@ __device__ void vjp(const MechDev &m, double p, const S (&y)[K + 1], const doubl
         slot(cb, 1 + k) = mk<S>(0.0);
         // adjoint weight of wd_k: (lam_k - lam_T hm_k / cp) (1e6/rho) W_k, hm_k = h_k/RT * R T / W_k
         const S hm = hRT_of(r) * T * (kR * r[1]);
-        rput(om, k, (lam[1 + k] - lam[0] * hm * icp) * fy * r[0]);
-        rput(wd, k, mk<S>(0.0));
+        oms.put(k, (lam[1 + k] - lam[0] * hm * icp) * fy * r[0]);
+        wds.put(k, mk<S>(0.0));
     }
     S cbd[K];
 #pragma unroll
@@ -196,7 +222,7 @@ __device__ void vjp(const MechDev &m, double p, const S (&y)[K + 1], const doubl
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int nk = nuj[k];
-            if (nk != 0) Qb += double(nk) * rget(om, k, S());  // wave-uniform branch
+            if (nk != 0) Qb += double(nk) * oms.get(k);  // wave-uniform branch
         }
         const S kr = kf * iKc;
         const S c0 = slot(cs, r0), c1 = slot(cs, r1), c2 = slot(cs, r2);
@@ -208,7 +234,7 @@ __device__ void vjp(const MechDev &m, double p, const S (&y)[K + 1], const doubl
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int nk = nuj[k];
-            if (nk != 0) rput(wd, k, rget(wd, k, S()) + double(nk) * q);
+            if (nk != 0) wds.put(k, wds.get(k) + double(nk) * q);
         }
         // adjoint of q_j: T at fixed c, the concentrations of its slots, [M], ln A
         Tb += Qb * Mq * (fwd * dlnkf - rev * (dlnkf - dlnKc));
@@ -232,7 +258,7 @@ __device__ void vjp(const MechDev &m, double p, const S (&y)[K + 1], const doubl
     for (int k = 0; k < K; ++k) {
         const double *r = m.sp + k * kSpTab;
         const S hm = hRT_of(r) * T * (kR * r[1]);
-        const S wk = rget(wd, k, S());
+        const S wk = wds.get(k);
         H += hm * (fy * r[0] * wk);
         fyb += (lam[1 + k] - lam[0] * hm * icp) * r[0] * wk;
     }
@@ -246,7 +272,7 @@ __device__ void vjp(const MechDev &m, double p, const S (&y)[K + 1], const doubl
         const S cbk = slot(cb, 1 + k) + cbd[k];
         cbd[k] = cbk;
         rhob += cbk * slot(cs, 1 + k) * irho;
-        const S fk = fy * r[0] * rget(wd, k, S());
+        const S fk = fy * r[0] * wds.get(k);
         T_hm += (-lam[0] * fk * icp) * cpR_of(r) * (kR * r[1]);  // hm_k' = cp_k (mass)
     }
     yb[0] = Tb + T_hm + cpb * (kR * dcpm) - rhob * rho * iT;

@@ -199,6 +199,11 @@ struct DnnDevParams {   // kernel argument for the pre/post kernels
 // N % kGemmBN == 0, K % kGemmBK == 0, row strides in elements.
 df_status launch_gemm_bf16(const bf16_t *A, int lda, const bf16_t *B, int ldb, const float *bias, bf16_t *C, int ldc,
                            int64_t M, int N, int K, bool gelu, hipStream_t stream);
+// the same GEMM with the training epilogues: gelu_save also stores the pre-activation
+// (A B^T + bias) to P with C's layout; gelu_grad writes (A B^T) * GELU'(P) (no bias)
+enum class GemmEpi { gelu, linear, gelu_save, gelu_grad };
+df_status launch_gemm_bf16_epi(const bf16_t *A, int lda, const bf16_t *B, int ldb, const float *bias, bf16_t *C,
+                               int ldc, int64_t M, int N, int K, GemmEpi epi, bf16_t *P, hipStream_t stream);
 
 }  // namespace df
 

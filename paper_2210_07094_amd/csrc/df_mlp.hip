@@ -35,11 +35,22 @@ __device__ __forceinline__ bf16_t to_bf16(float x) {
 
 __device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
 
-template <bool GELU>
+// d GELU / dx = Phi(x) + x phi(x)
+__device__ __forceinline__ float gelu_grad(float x) {
+    return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * expf(-0.5f * x * x);
+}
+
+__device__ __forceinline__ float bf_to_f(bf16_t h) { return __uint_as_float(unsigned(h) << 16); }
+
+// Epilogues: inference (bias, GELU); training forward (bias, GELU, and the pre-activation
+// stored to P with C's layout); training backward (the product times GELU'(P), no bias).
+enum { kEpiGelu = 0, kEpiLinear = 1, kEpiGeluSave = 2, kEpiGeluGrad = 3 };
+
+template <int EPI>
 __global__ __launch_bounds__(kThreads) void gemm_kernel(const bf16_t *__restrict__ A, int lda,
                                                        const bf16_t *__restrict__ B, int ldb,
                                                        const float *__restrict__ bias, bf16_t *__restrict__ C,
-                                                       int ldc, int K, int n_tiles_n) {
+                                                       int ldc, int K, int n_tiles_n, bf16_t *__restrict__ P) {
     __shared__ __attribute__((aligned(16))) bf16_t As[BM * LDK];
     __shared__ __attribute__((aligned(16))) bf16_t Bs[BN * LDK];
 
@@ -122,14 +133,16 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(const bf16_t *__restrict
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
         const int col = col0 + wn * WN + j * 16 + fr;
-        const float bc = bias[col];
+        const float bc = (EPI == kEpiGeluGrad) ? 0.0f : bias[col];
 #pragma unroll
         for (int i = 0; i < TM; ++i) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int64_t row = row0 + wm * WM + i * 16 + (lane >> 4) * 4 + r;
                 float v = acc[i][j][r] + bc;
-                if (GELU) v = gelu(v);
+                if (EPI == kEpiGeluSave) P[row * ldc + col] = to_bf16(v);
+                if (EPI == kEpiGelu || EPI == kEpiGeluSave) v = gelu(v);
+                if (EPI == kEpiGeluGrad) v *= gelu_grad(bf_to_f(P[row * ldc + col]));
                 C[row * ldc + col] = to_bf16(v);
             }
         }
@@ -140,17 +153,34 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(const bf16_t *__restrict
 
 df_status launch_gemm_bf16(const bf16_t *A, int lda, const bf16_t *B, int ldb, const float *bias, bf16_t *C, int ldc,
                            int64_t M, int N, int K, bool gelu, hipStream_t stream) {
+    return launch_gemm_bf16_epi(A, lda, B, ldb, bias, C, ldc, M, N, K, gelu ? GemmEpi::gelu : GemmEpi::linear, nullptr,
+                                stream);
+}
+
+df_status launch_gemm_bf16_epi(const bf16_t *A, int lda, const bf16_t *B, int ldb, const float *bias, bf16_t *C,
+                               int ldc, int64_t M, int N, int K, GemmEpi epi, bf16_t *P, hipStream_t stream) {
     if (M % BM || N % BN || K % BK || lda % 8 || ldb % 8)
         return fail(DF_E_INVALID, "gemm: shapes must be multiples of the tile sizes");
+    if ((epi == GemmEpi::gelu_save || epi == GemmEpi::gelu_grad) && !P)
+        return fail(DF_E_INVALID, "gemm: the epilogue needs the pre-activation array");
     if (M == 0) return DF_OK;
     const int64_t tiles = (M / BM) * (N / BN);
     if (tiles > 0x7fffffff) return fail(DF_E_UNSUPPORTED, "gemm: too many tiles");
-    if (gelu)
-        hipLaunchKernelGGL(gemm_kernel<true>, dim3(unsigned(tiles)), dim3(kThreads), 0, stream, A, lda, B, ldb, bias,
-                           C, ldc, K, N / BN);
-    else
-        hipLaunchKernelGGL(gemm_kernel<false>, dim3(unsigned(tiles)), dim3(kThreads), 0, stream, A, lda, B, ldb, bias,
-                           C, ldc, K, N / BN);
+    const dim3 g = dim3(unsigned(tiles)), b = dim3(kThreads);
+    switch (epi) {
+        case GemmEpi::gelu:
+            hipLaunchKernelGGL(gemm_kernel<kEpiGelu>, g, b, 0, stream, A, lda, B, ldb, bias, C, ldc, K, N / BN, P);
+            break;
+        case GemmEpi::linear:
+            hipLaunchKernelGGL(gemm_kernel<kEpiLinear>, g, b, 0, stream, A, lda, B, ldb, bias, C, ldc, K, N / BN, P);
+            break;
+        case GemmEpi::gelu_save:
+            hipLaunchKernelGGL(gemm_kernel<kEpiGeluSave>, g, b, 0, stream, A, lda, B, ldb, bias, C, ldc, K, N / BN, P);
+            break;
+        case GemmEpi::gelu_grad:
+            hipLaunchKernelGGL(gemm_kernel<kEpiGeluGrad>, g, b, 0, stream, A, lda, B, ldb, bias, C, ldc, K, N / BN, P);
+            break;
+    }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(DF_E_HIP, std::string("gemm launch: ") + hipGetErrorString(e));
     return DF_OK;

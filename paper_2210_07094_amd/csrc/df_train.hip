@@ -1,0 +1,559 @@
+// Training the DNN chemistry integrator on the device: the MLP's backward pass and Adam.
+//
+// The network of the DNN form (Sec. "Chemistry Integration": z-scored (T, p, Box-Cox(Y)) in,
+// hidden GELU layers, z-scored Box-Cox increments out) is fitted to pairs the integrator
+// produces: df_dnn_make_batch turns states before and after an integrator step into
+// (input, target) rows; df_dnn_train_step takes one Adam step on the mean squared error
+//   L = 1/(B O) sum_b sum_o (u_bo - t_bo)^2 .
+// Forward in bf16 on the matrix cores with fp32 accumulation, as inference, keeping each hidden
+// layer's pre-activation a_l; backward:
+//   du = 2 (u - t) / (B O);   dh_last = du W_out;   da_l = dh_l * GELU'(a_l)
+//   dh_{l-1} = da_l W_l  (bf16 GEMM with the transposed weights, GELU' in the epilogue)
+//   dW_l = da_l^T in_l,  db_l = sum_b da_l      (fp32, reduction over the batch on MFMA)
+// Adam (Kingma and Ba, ICLR 2015) on fp32 master weights; each update rewrites the handle's
+// bf16 weights (so df_dnn_step runs the trained network) and the transposed bf16 copies.
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "df_internal.h"
+
+namespace df {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ bf16_t tbf(float x) {
+    unsigned u = __float_as_uint(x);
+    if ((u & 0x7f800000u) == 0x7f800000u) return bf16_t((u >> 16) | ((u & 0x007fffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return bf16_t(u >> 16);
+}
+__device__ __forceinline__ float fbf(bf16_t h) { return __uint_as_float(unsigned(h) << 16); }
+__device__ __forceinline__ float gelu_d(float x) {
+    return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * expf(-0.5f * x * x);
+}
+
+constexpr int kT = 256;
+
+// batch rows: x fp32 [B][n_in] -> bf16 [Bp][in_pad], zero beyond n_in and beyond B
+__global__ __launch_bounds__(kT) void load_x_kernel(const float *__restrict__ x, int64_t B, int64_t Bp, int n_in,
+                                                    int in_pad, bf16_t *__restrict__ xb) {
+    const int64_t e = int64_t(blockIdx.x) * kT + threadIdx.x;
+    if (e >= Bp * in_pad) return;
+    const int64_t b = e / in_pad;
+    const int c = int(e % in_pad);
+    xb[e] = (b < B && c < n_in) ? tbf(x[b * n_in + c]) : bf16_t(0);
+}
+
+// output layer and loss, one thread per batch row: u = W h + b (fp32 accumulation of bf16
+// operands, as inference), du = 2 (u - t)/(B O), row loss, and da of the last hidden layer
+template <int O>
+__global__ __launch_bounds__(kT) void out_loss_kernel(const bf16_t *__restrict__ h, const bf16_t *__restrict__ a,
+                                                      int hid, const bf16_t *__restrict__ W,
+                                                      const float *__restrict__ bias, const float *__restrict__ t,
+                                                      int64_t B, int64_t Bp, float *__restrict__ du,
+                                                      float *__restrict__ row_loss, bf16_t *__restrict__ da) {
+    const int64_t b = int64_t(blockIdx.x) * kT + threadIdx.x;
+    if (b >= Bp) return;
+    bf16_t *dar = da + b * hid;
+    if (b >= B) {
+        for (int i = 0; i < hid; ++i) dar[i] = 0;
+#pragma unroll
+        for (int o = 0; o < O; ++o) du[b * O + o] = 0.0f;
+        row_loss[b] = 0.0f;
+        return;
+    }
+    const bf16_t *hr = h + b * hid;
+    float u[O];
+#pragma unroll
+    for (int o = 0; o < O; ++o) u[o] = 0.0f;
+    for (int i = 0; i < hid; ++i) {
+        const float hv = fbf(hr[i]);
+#pragma unroll
+        for (int o = 0; o < O; ++o) u[o] = fmaf(fbf(W[o * hid + i]), hv, u[o]);
+    }
+    const float sc = 2.0f / float(B * O);
+    float g[O], l = 0.0f;
+#pragma unroll
+    for (int o = 0; o < O; ++o) {
+        const float e = u[o] + bias[o] - t[b * O + o];
+        l = fmaf(e, e, l);
+        g[o] = sc * e;
+        du[b * O + o] = g[o];
+    }
+    row_loss[b] = l;
+    const bf16_t *ar = a + b * hid;
+    for (int i = 0; i < hid; ++i) {
+        float s = 0.0f;
+#pragma unroll
+        for (int o = 0; o < O; ++o) s = fmaf(g[o], fbf(W[o * hid + i]), s);
+        dar[i] = tbf(s * gelu_d(fbf(ar[i])));
+    }
+}
+
+// loss = sum of row losses / (B O), fixed-order tree in one block
+__global__ __launch_bounds__(kT) void loss_sum_kernel(const float *__restrict__ row_loss, int64_t B, int O,
+                                                      float *__restrict__ loss) {
+    __shared__ double part[kT];
+    double s = 0.0;
+    for (int64_t b = threadIdx.x; b < B; b += kT) s += double(row_loss[b]);
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kT / 2; w > 0; w >>= 1) {
+        if (int(threadIdx.x) < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = float(part[0] / double(B * O));
+}
+
+// dW[M][N] (fp32) = sum_b A[b][M] X[b][N] over Bp rows (bf16 operands, MFMA 16x16x32 with fp32
+// accumulation): one wave per 32 x 32 tile of dW, four MFMA tiles, 32 batch rows per step.  A
+// lane supplies operand row (lane % 16) with the 8 batch rows 8 (lane / 16) .. + 7.
+__global__ __launch_bounds__(64) void wgrad_kernel(const bf16_t *__restrict__ A, int lda, const bf16_t *__restrict__ X,
+                                                   int ldx, int64_t Bp, float *__restrict__ dW, int ldw, int tiles_n) {
+    const int lane = threadIdx.x;
+    const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
+    const int m0 = tm * 32, n0 = tn * 32;
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
+    floatx4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int64_t b0 = 0; b0 < Bp; b0 += 32) {
+        bf16x8 af[2], xf[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            __bf16 va[8], vx[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int64_t b = b0 + fk + q;
+                const unsigned short ua = A[b * lda + m0 + i * 16 + fr];
+                const unsigned short ux = X[b * ldx + n0 + i * 16 + fr];
+                va[q] = __builtin_bit_cast(__bf16, ua);
+                vx[q] = __builtin_bit_cast(__bf16, ux);
+            }
+            af[i] = bf16x8{va[0], va[1], va[2], va[3], va[4], va[5], va[6], va[7]};
+            xf[i] = bf16x8{vx[0], vx[1], vx[2], vx[3], vx[4], vx[5], vx[6], vx[7]};
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], xf[j], acc[i][j], 0, 0, 0);
+    }
+    // lane holds column (lane % 16) and rows 4 (lane / 16) + r of each 16 x 16 tile
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                dW[int64_t(m0 + i * 16 + (lane >> 4) * 4 + r) * ldw + n0 + j * 16 + fr] = acc[i][j][r];
+}
+
+// output layer gradients: dW[o][i] = sum_b du[b][o] h[b][i], db[o] = sum_b du[b][o]
+template <int O>
+__global__ __launch_bounds__(kT) void wgrad_out_kernel(const float *__restrict__ du, const bf16_t *__restrict__ h,
+                                                       int hid, int64_t B, float *__restrict__ dW,
+                                                       float *__restrict__ db) {
+    const int e = blockIdx.x * kT + threadIdx.x;
+    if (e >= O * (hid + 1)) return;
+    const int o = e / (hid + 1), i = e % (hid + 1);
+    float s = 0.0f;
+    if (i < hid)
+        for (int64_t b = 0; b < B; ++b) s = fmaf(du[b * O + o], fbf(h[b * hid + i]), s);
+    else
+        for (int64_t b = 0; b < B; ++b) s += du[b * O + o];
+    if (i < hid)
+        dW[o * hid + i] = s;
+    else
+        db[o] = s;
+}
+
+// db[o] = sum_b da[b][o]
+__global__ __launch_bounds__(kT) void colsum_kernel(const bf16_t *__restrict__ da, int ld, int n, int64_t Bp,
+                                                    float *__restrict__ db) {
+    const int o = blockIdx.x * kT + threadIdx.x;
+    if (o >= n) return;
+    float s = 0.0f;
+    for (int64_t b = 0; b < Bp; ++b) s += fbf(da[b * ld + o]);
+    db[o] = s;
+}
+
+// Adam on one parameter block [rows][cols] (padded storage, real part rows_r x cols_r; padding
+// stays zero).  Writes the fp32 master, the bf16 copy (if Wb) and the transposed bf16 copy (if WT).
+__global__ __launch_bounds__(kT) void adam_kernel(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
+                                                  const float *__restrict__ g, int rows, int cols, int rows_r,
+                                                  int cols_r, float lr, float b1, float b2, float eps, float bc1,
+                                                  float bc2, bf16_t *__restrict__ Wb, bf16_t *__restrict__ WT,
+                                                  float *__restrict__ wf) {
+    const int64_t e = int64_t(blockIdx.x) * kT + threadIdx.x;
+    if (e >= int64_t(rows) * cols) return;
+    const int r = int(e / cols), c = int(e % cols);
+    if (r >= rows_r || c >= cols_r) return;
+    const float gi = g[e];
+    const float mi = b1 * m[e] + (1.0f - b1) * gi;
+    const float vi = b2 * v[e] + (1.0f - b2) * gi * gi;
+    m[e] = mi;
+    v[e] = vi;
+    const float wi = w[e] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    w[e] = wi;
+    if (Wb) Wb[e] = tbf(wi);
+    if (WT) WT[int64_t(c) * rows + r] = tbf(wi);
+    if (wf) wf[e] = wi;
+}
+
+// trainer set-up: fp32 master from the handle's bf16 weights, transposed bf16 copies
+__global__ __launch_bounds__(kT) void init_master_kernel(const bf16_t *__restrict__ Wb, int rows, int cols,
+                                                         float *__restrict__ w, bf16_t *__restrict__ WT) {
+    const int64_t e = int64_t(blockIdx.x) * kT + threadIdx.x;
+    if (e >= int64_t(rows) * cols) return;
+    w[e] = fbf(Wb[e]);
+    if (WT) WT[int64_t(e % cols) * rows + e / cols] = Wb[e];
+}
+
+// the bf16 copies of a layer from its fp32 master: the handle's weights and the transposed copy
+__global__ __launch_bounds__(kT) void refresh_bf16_kernel(const float *__restrict__ w, int rows, int cols,
+                                                          bf16_t *__restrict__ Wb, bf16_t *__restrict__ WT) {
+    const int64_t e = int64_t(blockIdx.x) * kT + threadIdx.x;
+    if (e >= int64_t(rows) * cols) return;
+    const bf16_t v = tbf(w[e]);
+    Wb[e] = v;
+    if (WT) WT[int64_t(e % cols) * rows + e / cols] = v;
+}
+
+// (input, target) rows from states before (T, p, Y0) and after (Y1) an integrator step of the
+// network's dt: x = z-score of (T, p, Box-Cox(Y0)), t = z-score of Box-Cox(Y1) - Box-Cox(Y0);
+// valid = 1 inside the training box (the rows of invalid cells are still written)
+template <int K>
+__global__ __launch_bounds__(kT) void make_batch_kernel(DnnDevParams prm, int64_t n, int64_t ld,
+                                                        const double *__restrict__ p, const double *__restrict__ T,
+                                                        const double *__restrict__ Y0, const double *__restrict__ Y1,
+                                                        float *__restrict__ x, float *__restrict__ t,
+                                                        int32_t *__restrict__ valid) {
+    const int64_t i = int64_t(blockIdx.x) * kT + threadIdx.x;
+    if (i >= n) return;
+    constexpr int NI = K + 2;
+    double f[NI];
+    f[0] = T[i];
+    f[1] = p[i];
+    bool ok = isfinite(f[0]) && f[0] > 0.0 && isfinite(f[1]) && f[1] > 0.0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const double y0 = Y0[k * ld + i], y1 = Y1[k * ld + i];
+        ok = ok && isfinite(y0) && isfinite(y1);
+        const double z0 = (pow(fmax(y0, 0.0), prm.lambda) - 1.0) / prm.lambda;
+        const double z1 = (pow(fmax(y1, 0.0), prm.lambda) - 1.0) / prm.lambda;
+        f[2 + k] = z0;
+        t[i * K + k] = float(((z1 - z0) - prm.mu_out[k]) / prm.sig_out[k]);
+    }
+#pragma unroll
+    for (int c = 0; c < NI; ++c) {
+        ok = ok && f[c] >= prm.lo[c] && f[c] <= prm.hi[c];
+        x[i * NI + c] = float((f[c] - prm.mu_in[c]) / prm.sig_in[c]);
+    }
+    if (valid) valid[i] = ok ? 1 : 0;
+}
+
+int64_t rup(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+
+}  // namespace
+}  // namespace df
+
+struct df_trainer {
+    df_dnn *dnn;
+    int64_t max_batch, bp;
+    int nh;  // hidden layers
+    void *blob;
+    std::vector<float *> W, b, mW, vW, mb, vb, gW, gb;  // per layer (hidden then output), padded
+    std::vector<df::bf16_t *> WT;                        // per hidden layer: [k_pad][n_pad], or null
+    df::bf16_t *x;
+    std::vector<df::bf16_t *> h, a, da;  // per hidden layer [bp][n_pad]
+    float *du, *row_loss, *loss;
+    int64_t step;
+};
+
+using namespace df;
+
+extern "C" {
+
+df_status df_dnn_trainer_create(df_dnn *d, int64_t max_batch, df_trainer **out) {
+    clear_error();
+    if (!d || !out || max_batch < 1) return fail(DF_E_INVALID, "df_dnn_trainer_create: bad arguments");
+    *out = nullptr;
+    const int L = int(d->layers.size()), nh = L - 1;
+    if (d->K != 9 || d->layers.back().n_out != 9)
+        return fail(DF_E_UNSUPPORTED, "df_dnn_trainer_create: the output layer kernels are compiled for 9 outputs");
+    // the weight-gradient kernel tiles every hidden layer's padded weights in 32 x 32 blocks, and
+    // the output layer reads its input width from the last hidden layer's padding
+    for (int l = 0; l < L - 1; ++l)
+        if (d->layers[l].n_pad % 32 || d->layers[l].k_pad % 32)
+            return fail(DF_E_UNSUPPORTED, "df_dnn_trainer_create: hidden widths must pad to multiples of 32");
+    if (L < 2 || d->layers.back().k_pad != d->layers[L - 2].n_pad)
+        return fail(DF_E_UNSUPPORTED, "df_dnn_trainer_create: unexpected layer padding");
+    auto *t = new df_trainer;
+    t->dnn = d;
+    t->max_batch = max_batch;
+    t->bp = rup(max_batch, kGemmBM);
+    t->nh = nh;
+    t->step = 0;
+    // one allocation: per layer 6 fp32 blocks of W's size (W, mW, vW, gW) and b's (b, mb, vb, gb),
+    // transposed bf16 copies, activations
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    size_t o = 0;
+    std::vector<size_t> oW(L), ob(L), oT(L, 0), oh(nh), oa(nh), oda(nh);
+    for (int l = 0; l < L; ++l) {
+        const size_t nw = size_t(d->layers[l].n_pad) * d->layers[l].k_pad, nb = size_t(d->layers[l].n_pad);
+        oW[l] = o;
+        o = al(o + 4 * nw * 4);
+        ob[l] = o;
+        o = al(o + 4 * nb * 4);
+        if (l >= 1 && l < nh) {
+            oT[l] = o;
+            o = al(o + nw * 2);
+        }
+    }
+    const size_t ox = o;
+    o = al(o + size_t(t->bp) * d->layers[0].k_pad * 2);
+    for (int l = 0; l < nh; ++l) {
+        const size_t na = size_t(t->bp) * d->layers[l].n_pad * 2;
+        oh[l] = o;
+        o = al(o + na);
+        oa[l] = o;
+        o = al(o + na);
+        oda[l] = o;
+        o = al(o + na);
+    }
+    const int O = d->layers.back().n_out;
+    const size_t odu = o;
+    o = al(o + size_t(t->bp) * O * 4);
+    const size_t orl = o;
+    o = al(o + size_t(t->bp) * 4);
+    const size_t ol = o;
+    o = al(o + 4);
+    int prev = 0;
+    if (hipGetDevice(&prev) != hipSuccess || hipSetDevice(d->device) != hipSuccess) {
+        delete t;
+        return fail(DF_E_HIP, "df_dnn_trainer_create: cannot select the network's device");
+    }
+    hipError_t e = hipMalloc(&t->blob, o);
+    if (e == hipSuccess) e = hipMemset(t->blob, 0, o);
+    if (e != hipSuccess) {
+        if (t->blob) (void)hipFree(t->blob);
+        (void)hipSetDevice(prev);
+        delete t;
+        return fail(DF_E_HIP, std::string("df_dnn_trainer_create: ") + hipGetErrorString(e));
+    }
+    auto *base = static_cast<unsigned char *>(t->blob);
+    for (int l = 0; l < L; ++l) {
+        const size_t nw = size_t(d->layers[l].n_pad) * d->layers[l].k_pad, nb = size_t(d->layers[l].n_pad);
+        auto *w = reinterpret_cast<float *>(base + oW[l]);
+        t->W.push_back(w);
+        t->mW.push_back(w + nw);
+        t->vW.push_back(w + 2 * nw);
+        t->gW.push_back(w + 3 * nw);
+        auto *bb = reinterpret_cast<float *>(base + ob[l]);
+        t->b.push_back(bb);
+        t->mb.push_back(bb + nb);
+        t->vb.push_back(bb + 2 * nb);
+        t->gb.push_back(bb + 3 * nb);
+        t->WT.push_back((l >= 1 && l < nh) ? reinterpret_cast<bf16_t *>(base + oT[l]) : nullptr);
+        hipLaunchKernelGGL(init_master_kernel, dim3(unsigned((nw + kT - 1) / kT)), dim3(kT), 0, 0, d->layers[l].W,
+                           d->layers[l].n_pad, d->layers[l].k_pad, w, t->WT.back());
+        (void)hipMemcpy(bb, d->layers[l].b, nb * 4, hipMemcpyDeviceToDevice);
+    }
+    t->x = reinterpret_cast<bf16_t *>(base + ox);
+    for (int l = 0; l < nh; ++l) {
+        t->h.push_back(reinterpret_cast<bf16_t *>(base + oh[l]));
+        t->a.push_back(reinterpret_cast<bf16_t *>(base + oa[l]));
+        t->da.push_back(reinterpret_cast<bf16_t *>(base + oda[l]));
+    }
+    t->du = reinterpret_cast<float *>(base + odu);
+    t->row_loss = reinterpret_cast<float *>(base + orl);
+    t->loss = reinterpret_cast<float *>(base + ol);
+    e = hipDeviceSynchronize();
+    if (e == hipSuccess) e = hipGetLastError();
+    (void)hipSetDevice(prev);
+    if (e != hipSuccess) {
+        (void)hipFree(t->blob);
+        delete t;
+        return fail(DF_E_HIP, std::string("df_dnn_trainer_create: ") + hipGetErrorString(e));
+    }
+    *out = t;
+    return DF_OK;
+}
+
+void df_dnn_trainer_free(df_trainer *t) {
+    if (!t) return;
+    int prev = 0;
+    if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(t->dnn->device) == hipSuccess) {
+        (void)hipFree(t->blob);
+        (void)hipSetDevice(prev);
+    }
+    delete t;
+}
+
+void df_adam_default_opts(df_adam_opts *o) {
+    if (!o) return;
+    o->lr = 1e-4f;
+    o->beta1 = 0.9f;
+    o->beta2 = 0.999f;
+    o->eps = 1e-8f;
+}
+
+df_status df_dnn_train_step(df_trainer *t, int64_t batch, const float *x, const float *target,
+                            const df_adam_opts *adam, int32_t update, float *loss, void *hip_stream) {
+    clear_error();
+    const char *who = "df_dnn_train_step";
+    if (!t) return fail(DF_E_INVALID, std::string(who) + ": null trainer");
+    if (batch < 1 || batch > t->max_batch) return fail(DF_E_INVALID, std::string(who) + ": need 1 <= batch <= max_batch");
+    if (!x || !target) return fail(DF_E_INVALID, std::string(who) + ": null x or target");
+    df_adam_opts ao;
+    df_adam_default_opts(&ao);
+    if (adam) ao = *adam;
+    if (!(ao.lr >= 0.0f) || !(ao.beta1 >= 0.0f && ao.beta1 < 1.0f) || !(ao.beta2 >= 0.0f && ao.beta2 < 1.0f) ||
+        !(ao.eps > 0.0f))
+        return fail(DF_E_INVALID, std::string(who) + ": bad Adam options");
+    df_dnn *d = t->dnn;
+    int prev = 0;
+    if (hipGetDevice(&prev) != hipSuccess) return fail(DF_E_HIP, std::string(who) + ": hipGetDevice failed");
+    if (prev != d->device && hipSetDevice(d->device) != hipSuccess)
+        return fail(DF_E_HIP, std::string(who) + ": cannot select the network's device");
+    auto s = static_cast<hipStream_t>(hip_stream);
+    const int nh = t->nh;
+    const int64_t B = batch, Bp = rup(batch, kGemmBM);
+    const DnnLayer &L0 = d->layers[0];
+    const DnnLayer &Lo = d->layers.back();
+    constexpr int O = 9;
+    df_status st = DF_OK;
+    auto chk = [&](const char *what) {
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess && st == DF_OK) st = fail(DF_E_HIP, std::string(who) + ": " + what + ": " + hipGetErrorString(e));
+    };
+    hipLaunchKernelGGL(load_x_kernel, dim3(unsigned((Bp * L0.k_pad + kT - 1) / kT)), dim3(kT), 0, s, x, B, Bp,
+                       L0.n_in, L0.k_pad, t->x);
+    chk("input");
+    // forward, keeping the pre-activations
+    const bf16_t *in = t->x;
+    int in_ld = L0.k_pad;
+    for (int l = 0; l < nh && st == DF_OK; ++l) {
+        const DnnLayer &Ly = d->layers[l];
+        st = launch_gemm_bf16_epi(in, in_ld, Ly.W, Ly.k_pad, Ly.b, t->h[l], Ly.n_pad, Bp, Ly.n_pad, Ly.k_pad,
+                                  GemmEpi::gelu_save, t->a[l], s);
+        in = t->h[l];
+        in_ld = Ly.n_pad;
+    }
+    const int hid = Lo.k_pad;
+    if (st == DF_OK) {
+        hipLaunchKernelGGL(out_loss_kernel<O>, dim3(unsigned((Bp + kT - 1) / kT)), dim3(kT), 0, s, t->h[nh - 1],
+                           t->a[nh - 1], hid, Lo.W, Lo.b, target, B, Bp, t->du, t->row_loss, t->da[nh - 1]);
+        chk("output layer");
+        hipLaunchKernelGGL(loss_sum_kernel, dim3(1), dim3(kT), 0, s, t->row_loss, B, O, t->loss);
+        chk("loss");
+        hipLaunchKernelGGL(wgrad_out_kernel<O>, dim3(unsigned((O * (hid + 1) + kT - 1) / kT)), dim3(kT), 0, s, t->du,
+                           t->h[nh - 1], hid, B, t->gW[nh], t->gb[nh]);
+        chk("output layer gradient");
+    }
+    // backward through the hidden layers
+    for (int l = nh - 1; l >= 0 && st == DF_OK; --l) {
+        const DnnLayer &Ly = d->layers[l];
+        const bf16_t *inl = (l == 0) ? t->x : t->h[l - 1];
+        const int inl_ld = Ly.k_pad;
+        const int tiles_n = Ly.k_pad / 32;
+        hipLaunchKernelGGL(wgrad_kernel, dim3(unsigned((Ly.n_pad / 32) * tiles_n)), dim3(64), 0, s, t->da[l], Ly.n_pad,
+                           inl, inl_ld, Bp, t->gW[l], Ly.k_pad, tiles_n);
+        chk("weight gradient");
+        hipLaunchKernelGGL(colsum_kernel, dim3(unsigned((Ly.n_pad + kT - 1) / kT)), dim3(kT), 0, s, t->da[l], Ly.n_pad,
+                           Ly.n_pad, Bp, t->gb[l]);
+        chk("bias gradient");
+        if (l > 0 && st == DF_OK)
+            st = launch_gemm_bf16_epi(t->da[l], Ly.n_pad, t->WT[l], Ly.n_pad, nullptr, t->da[l - 1], Ly.k_pad, Bp,
+                                      Ly.k_pad, Ly.n_pad, GemmEpi::gelu_grad, t->a[l - 1], s);
+    }
+    if (st == DF_OK && loss) {
+        if (hipMemcpyAsync(loss, t->loss, 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+            st = fail(DF_E_HIP, std::string(who) + ": copying the loss failed");
+    }
+    if (st == DF_OK && update) {
+        ++t->step;
+        const float bc1 = float(1.0 - std::pow(double(ao.beta1), double(t->step)));
+        const float bc2 = float(1.0 - std::pow(double(ao.beta2), double(t->step)));
+        for (int l = 0; l <= nh; ++l) {
+            DnnLayer &Ly = d->layers[l];
+            const int64_t nw = int64_t(Ly.n_pad) * Ly.k_pad;
+            hipLaunchKernelGGL(adam_kernel, dim3(unsigned((nw + kT - 1) / kT)), dim3(kT), 0, s, t->W[l], t->mW[l],
+                               t->vW[l], t->gW[l], Ly.n_pad, Ly.k_pad, Ly.n_out, Ly.n_in, ao.lr, ao.beta1, ao.beta2,
+                               ao.eps, bc1, bc2, Ly.W, t->WT[l], static_cast<float *>(nullptr));
+            hipLaunchKernelGGL(adam_kernel, dim3(unsigned((Ly.n_pad + kT - 1) / kT)), dim3(kT), 0, s, t->b[l],
+                               t->mb[l], t->vb[l], t->gb[l], Ly.n_pad, 1, Ly.n_out, 1, ao.lr, ao.beta1, ao.beta2,
+                               ao.eps, bc1, bc2, static_cast<bf16_t *>(nullptr), static_cast<bf16_t *>(nullptr),
+                               Ly.b);
+            chk("Adam");
+        }
+    }
+    if (prev != d->device) (void)hipSetDevice(prev);
+    return st;
+}
+
+df_status df_dnn_trainer_get(const df_trainer *t, int32_t layer, int32_t what, float *dst, void *hip_stream) {
+    clear_error();
+    if (!t || !dst || layer < 0 || layer > t->nh || what < 0 || what > 3)
+        return fail(DF_E_INVALID, "df_dnn_trainer_get: bad arguments");
+    const DnnLayer &Ly = t->dnn->layers[layer];
+    const float *src = (what == 0) ? t->W[layer] : (what == 1) ? t->b[layer] : (what == 2) ? t->gW[layer] : t->gb[layer];
+    const bool mat = (what == 0 || what == 2);
+    const hipError_t e =
+        mat ? hipMemcpy2DAsync(dst, size_t(Ly.n_in) * 4, src, size_t(Ly.k_pad) * 4, size_t(Ly.n_in) * 4, Ly.n_out,
+                               hipMemcpyDeviceToDevice, static_cast<hipStream_t>(hip_stream))
+            : hipMemcpyAsync(dst, src, size_t(Ly.n_out) * 4, hipMemcpyDeviceToDevice, static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return fail(DF_E_HIP, std::string("df_dnn_trainer_get: ") + hipGetErrorString(e));
+    return DF_OK;
+}
+
+df_status df_dnn_trainer_set(df_trainer *t, int32_t layer, int32_t what, const float *src, void *hip_stream) {
+    clear_error();
+    if (!t || !src || layer < 0 || layer > t->nh || what < 0 || what > 1)
+        return fail(DF_E_INVALID, "df_dnn_trainer_set: bad arguments");
+    DnnLayer &Ly = t->dnn->layers[layer];
+    auto s = static_cast<hipStream_t>(hip_stream);
+    hipError_t e;
+    if (what == 0) {
+        e = hipMemcpy2DAsync(t->W[layer], size_t(Ly.k_pad) * 4, src, size_t(Ly.n_in) * 4, size_t(Ly.n_in) * 4,
+                             Ly.n_out, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) {
+            const int64_t nw = int64_t(Ly.n_pad) * Ly.k_pad;
+            hipLaunchKernelGGL(refresh_bf16_kernel, dim3(unsigned((nw + kT - 1) / kT)), dim3(kT), 0, s, t->W[layer],
+                               Ly.n_pad, Ly.k_pad, Ly.W, t->WT[layer]);
+            e = hipGetLastError();
+        }
+    } else {
+        e = hipMemcpyAsync(t->b[layer], src, size_t(Ly.n_out) * 4, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(Ly.b, src, size_t(Ly.n_out) * 4, hipMemcpyDeviceToDevice, s);
+    }
+    if (e != hipSuccess) return fail(DF_E_HIP, std::string("df_dnn_trainer_set: ") + hipGetErrorString(e));
+    return DF_OK;
+}
+
+df_status df_dnn_make_batch(const df_dnn *d, int64_t n, int64_t ld, const double *p, const double *T, const double *Y0,
+                            const double *Y1, float *x, float *target, int32_t *valid, void *hip_stream) {
+    clear_error();
+    if (!d || n < 0 || ld < n) return fail(DF_E_INVALID, "df_dnn_make_batch: bad arguments");
+    if (n > 0 && (!p || !T || !Y0 || !Y1 || !x || !target))
+        return fail(DF_E_INVALID, "df_dnn_make_batch: null array");
+    if (d->K != 9) return fail(DF_E_UNSUPPORTED, "df_dnn_make_batch: compiled for 9 species");
+    if (n == 0) return DF_OK;
+    int prev = 0;
+    if (hipGetDevice(&prev) != hipSuccess) return fail(DF_E_HIP, "df_dnn_make_batch: hipGetDevice failed");
+    if (prev != d->device && hipSetDevice(d->device) != hipSuccess)
+        return fail(DF_E_HIP, "df_dnn_make_batch: cannot select the network's device");
+    hipLaunchKernelGGL(make_batch_kernel<9>, dim3(unsigned((n + kT - 1) / kT)), dim3(kT), 0,
+                       static_cast<hipStream_t>(hip_stream), d->prm, n, ld, p, T, Y0, Y1, x, target, valid);
+    const hipError_t e = hipGetLastError();
+    if (prev != d->device) (void)hipSetDevice(prev);
+    if (e != hipSuccess) return fail(DF_E_HIP, std::string("df_dnn_make_batch: ") + hipGetErrorString(e));
+    return DF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,174 @@
+"""GPU checks of the DNN training kernels (df_dnn_make_batch, df_dnn_train_step): training
+pairs, loss and gradients against the float64 oracle (oracle/mlp_train.py), one Adam step, and
+a short training run on states the integrator produced.
+
+Gradient bar: the device computes the products in bf16 with fp32 accumulation, rounding the
+input, every hidden activation, the saved pre-activations and every back-propagated da to bf16
+(unit roundoff u = 2^-9).  A gradient entry collects about six such roundings along each path,
+so each layer's gradient is held to a normwise relative error of 2e-2 (about 20 u), with its
+direction (cosine) within 1e-3 of the oracle's; the loss to 1e-2 relative.  This holds when the
+residuals u - t are large against the bf16 noise of u (a few 2^-9 |u|): the stored network
+already fits integrator pairs to residuals of that size, so the parity cases use the
+integrator's inputs with random targets.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp_train as mt
+from synth import fields
+from synth.dnnfile import read_dnn
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+DNN = os.path.join(ROOT, "paper_2210_07094_amd", "data", "h2_dnn_1600_800_400.dfdnn")
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+def _oracle_rows(h2_mech, h2_oracle, net, n, seed):
+    """Training rows from the oracle integrator (inputs of both sides)."""
+    f = fields.ignition_cells(h2_mech, n=n, seed=seed)
+    f["T"][: n // 3] = np.linspace(500.0, 2400.0, n // 3)
+    o = h2_oracle.chem_step(f["T"], f["p"], f["Y"], net["dt_train"], h_inout=np.zeros(n))
+    return f, o["Y"]
+
+
+def test_make_batch_matches_oracle(h2_path, h2_mech, h2_oracle):
+    import paper_2210_07094_amd as df
+    torch = _torch()
+    net = read_dnn(DNN)
+    gm = df.Mechanism(h2_path)
+    dnn = df.DNN(DNN, gm)
+    tr = df.Trainer(dnn, 256)
+    n = 200
+    f, Y1 = _oracle_rows(h2_mech, h2_oracle, net, n, 3)
+    d = "cuda:0"
+    x, t, v = tr.make_batch(torch.tensor(f["p"], device=d), torch.tensor(f["T"], device=d),
+                            torch.tensor(np.ascontiguousarray(f["Y"]), device=d),
+                            torch.tensor(np.ascontiguousarray(Y1), device=d))
+    xo, to, vo = mt.make_batch(net, f["T"], f["p"], f["Y"], Y1)
+    # fp64 arithmetic on both sides, rounded to fp32 at the end
+    assert np.allclose(x.cpu().numpy(), xo.astype(np.float32), rtol=2e-7, atol=1e-6)
+    assert np.allclose(t.cpu().numpy(), to.astype(np.float32), rtol=2e-7, atol=1e-6)
+    assert np.array_equal(v.cpu().numpy().astype(bool), vo)
+
+
+def _gpu_grads(tr, nl):
+    return ([tr.get(l, "dW").cpu().numpy().astype(np.float64) for l in range(nl)],
+            [tr.get(l, "db").cpu().numpy().astype(np.float64) for l in range(nl)])
+
+
+def test_loss_and_gradients_match_oracle(h2_path, h2_mech, h2_oracle):
+    import paper_2210_07094_amd as df
+    torch = _torch()
+    net = read_dnn(DNN)
+    gm = df.Mechanism(h2_path)
+    dnn = df.DNN(DNN, gm)
+    B = 300                       # not a multiple of the 128-row tile: padded rows must not count
+    tr = df.Trainer(dnn, B)
+    f, Y1 = _oracle_rows(h2_mech, h2_oracle, net, B, 5)
+    xo, _, _ = mt.make_batch(net, f["T"], f["p"], f["Y"], Y1)
+    x32 = xo.astype(np.float32)
+    t32 = np.random.default_rng(5).standard_normal((B, 9)).astype(np.float32)
+    loss = tr.step(torch.tensor(x32, device="cuda:0"), torch.tensor(t32, device="cuda:0"), update=False)
+    Ws = [w.astype(np.float64) for w in net["W"]]
+    bs = [b.astype(np.float64) for b in net["b"]]
+    L, dW, db = mt.loss_and_grads(Ws, bs, x32.astype(np.float64), t32.astype(np.float64))
+    assert abs(float(loss.cpu()[0]) - L) <= 1e-2 * L
+    gW, gb = _gpu_grads(tr, len(Ws))
+    for l in range(len(Ws)):
+        for g, o in ((gW[l], dW[l]), (gb[l], db[l])):
+            rel = np.linalg.norm(g - o) / np.linalg.norm(o)
+            cos = float(np.sum(g * o) / (np.linalg.norm(g) * np.linalg.norm(o)))
+            assert rel <= 2e-2 and cos >= 1 - 1e-3, (l, rel, cos)
+
+
+def test_adam_step_matches_oracle(h2_path, h2_mech, h2_oracle):
+    import paper_2210_07094_amd as df
+    torch = _torch()
+    net = read_dnn(DNN)
+    gm = df.Mechanism(h2_path)
+    dnn = df.DNN(DNN, gm)
+    B = 256
+    tr = df.Trainer(dnn, B)
+    f, Y1 = _oracle_rows(h2_mech, h2_oracle, net, B, 7)
+    xo, _, _ = mt.make_batch(net, f["T"], f["p"], f["Y"], Y1)
+    to = np.random.default_rng(7).standard_normal((B, 9)).astype(np.float32)
+    x = torch.tensor(xo.astype(np.float32), device="cuda:0")
+    t = torch.tensor(to, device="cuda:0")
+    W0 = [tr.get(l, "W").cpu().numpy().astype(np.float64) for l in range(len(net["W"]))]
+    lr = 1e-4
+    opts = df.adam_opts(lr=lr)
+    tr.step(x, t, opts=opts, update=True)
+    W1 = [tr.get(l, "W").cpu().numpy().astype(np.float64) for l in range(len(net["W"]))]
+    Ws = [w.astype(np.float64) for w in net["W"]]
+    bs = [b.astype(np.float64) for b in net["b"]]
+    _, dW, _ = mt.loss_and_grads(Ws, bs, xo.astype(np.float32).astype(np.float64), to.astype(np.float32).astype(np.float64))
+    for l in range(len(Ws)):
+        assert np.array_equal(W0[l], Ws[l])          # the master starts from the stored weights
+        wo, _, _ = mt.adam(Ws[l], dW[l], np.zeros_like(Ws[l]), np.zeros_like(Ws[l]), 1, lr, 0.9, 0.999, 1e-8)
+        # away from gradients near zero (where rounding may flip the sign), the first step is
+        # lr sign(g) on both sides
+        big = np.abs(dW[l]) > 0.05 * np.sqrt(np.mean(dW[l] ** 2))
+        d = np.abs((W1[l] - W0[l]) - (wo - Ws[l]))[big]
+        assert np.max(d) <= 1e-3 * lr + 1e-7 * np.abs(Ws[l]).max(), (l, np.max(d))
+        assert np.mean(big) > 0.2
+
+
+def test_training_on_integrator_states_reduces_the_error(h2_path, h2_mech):
+    """Pairs from the device integrator at the network's dt; with the output layer degraded
+    (weights halved), Adam steps on them bring the loss back down, and df_dnn_step then runs
+    the updated weights."""
+    import paper_2210_07094_amd as df
+    torch = _torch()
+    gm = df.Mechanism(h2_path)
+    dnn = df.DNN(DNN, gm)
+    net = read_dnn(DNN)
+    n = 4096
+    f = fields.ignition_cells(h2_mech, n=n, seed=17)
+    f["T"][: n // 2] = np.random.default_rng(1).uniform(900.0, 2400.0, n // 2)
+    d = "cuda:0"
+    p = torch.tensor(f["p"], device=d)
+    T0 = torch.tensor(f["T"], device=d)
+    Y0 = torch.tensor(np.ascontiguousarray(f["Y"]), device=d)
+    T1, Y1 = T0.clone(), Y0.clone()
+    gm.chem_step(T1, p, Y1, net["dt_train"], h=torch.zeros(n, dtype=torch.float64, device=d))
+    tr = df.Trainer(dnn, n)
+    x, t, v = tr.make_batch(p, T0, Y0, Y1)
+    keep = v.bool()
+    x, t = x[keep].contiguous(), t[keep].contiguous()
+    assert x.shape[0] > n // 2
+    L = len(net["W"]) - 1
+    tr.set(L, "W", 0.5 * tr.get(L, "W"))
+    losses = [float(tr.step(x, t, opts=df.adam_opts(lr=2e-4)).cpu()[0]) for _ in range(40)]
+    assert all(np.isfinite(losses))
+    assert np.mean(losses[-5:]) < 0.5 * losses[0], losses
+    # the handle now runs the trained network
+    Ta, Ya = T0.clone(), Y0.clone()
+    dnn.step(Ta, p, Ya, net["dt_train"], workspace=dnn.workspace(n))
+    dnn2 = df.DNN(DNN, gm)
+    Tb, Yb = T0.clone(), Y0.clone()
+    dnn2.step(Tb, p, Yb, net["dt_train"], workspace=dnn2.workspace(n))
+    assert not torch.equal(Ya, Yb)
+
+
+def test_trainer_argument_checks(h2_path):
+    import paper_2210_07094_amd as df
+    torch = _torch()
+    gm = df.Mechanism(h2_path)
+    dnn = df.DNN(DNN, gm)
+    tr = df.Trainer(dnn, 128)
+    x = torch.zeros(129, 11, dtype=torch.float32, device="cuda:0")
+    t = torch.zeros(129, 9, dtype=torch.float32, device="cuda:0")
+    with pytest.raises(df.DfError):
+        tr.step(x, t)                                  # batch above max_batch
+    with pytest.raises(df.DfError):
+        tr.step(x[:8], t[:8], opts=df.adam_opts(beta1=1.0))
