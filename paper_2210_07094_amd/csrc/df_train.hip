@@ -9,7 +9,7 @@
 // layer's pre-activation a_l; backward:
 //   du = 2 (u - t) / (B O);   dh_last = du W_out;   da_l = dh_l * GELU'(a_l)
 //   dh_{l-1} = da_l W_l  (bf16 GEMM with the transposed weights, GELU' in the epilogue)
-//   dW_l = da_l^T in_l,  db_l = sum_b da_l      (fp32, reduction over the batch on MFMA)
+//   dW_l = da_l^T in_l,  db_l = sum_b da_l      (fp32, reductions over the batch; dW on MFMA)
 // Adam (Kingma and Ba, ICLR 2015) on fp32 master weights; each update rewrites the handle's
 // bf16 weights (so df_dnn_step runs the trained network) and the transposed bf16 copies.
 #include <cmath>
@@ -111,12 +111,15 @@ __global__ __launch_bounds__(kT) void loss_sum_kernel(const float *__restrict__ 
 // dW[M][N] (fp32) = sum_b A[b][M] X[b][N] over Bp rows (bf16 operands, MFMA 16x16x32 with fp32
 // accumulation): one wave per 32 x 32 tile of dW, four MFMA tiles, 32 batch rows per step.  A
 // lane supplies operand row (lane % 16) with the 8 batch rows 8 (lane / 16) .. + 7.
+// The blocks of the first column of tiles also sum A over the batch (the bias gradient db).
 __global__ __launch_bounds__(64) void wgrad_kernel(const bf16_t *__restrict__ A, int lda, const bf16_t *__restrict__ X,
-                                                   int ldx, int64_t Bp, float *__restrict__ dW, int ldw, int tiles_n) {
+                                                   int ldx, int64_t Bp, float *__restrict__ dW, int ldw, int tiles_n,
+                                                   float *__restrict__ db) {
     const int lane = threadIdx.x;
     const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
     const int m0 = tm * 32, n0 = tn * 32;
     const int fr = lane & 15, fk = (lane >> 4) * 8;
+    float cs[2] = {0.0f, 0.0f};
     floatx4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -134,6 +137,7 @@ __global__ __launch_bounds__(64) void wgrad_kernel(const bf16_t *__restrict__ A,
                 const unsigned short ux = X[b * ldx + n0 + i * 16 + fr];
                 va[q] = __builtin_bit_cast(__bf16, ua);
                 vx[q] = __builtin_bit_cast(__bf16, ux);
+                cs[i] += fbf(ua);
             }
             af[i] = bf16x8{va[0], va[1], va[2], va[3], va[4], va[5], va[6], va[7]};
             xf[i] = bf16x8{vx[0], vx[1], vx[2], vx[3], vx[4], vx[5], vx[6], vx[7]};
@@ -151,35 +155,50 @@ __global__ __launch_bounds__(64) void wgrad_kernel(const bf16_t *__restrict__ A,
 #pragma unroll
             for (int r = 0; r < 4; ++r)
                 dW[int64_t(m0 + i * 16 + (lane >> 4) * 4 + r) * ldw + n0 + j * 16 + fr] = acc[i][j][r];
+    if (tn == 0) {
+        // lanes l, l + 16, l + 32, l + 48 hold the four batch quarters of row m0 + i 16 + l
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            float v = cs[i];
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            if (lane < 16) db[m0 + i * 16 + lane] = v;
+        }
+    }
 }
 
-// output layer gradients: dW[o][i] = sum_b du[b][o] h[b][i], db[o] = sum_b du[b][o]
+// output layer gradients: dW[o][i] = sum_b du[b][o] h[b][i], db[o] = sum_b du[b][o]; one
+// block per input column i (column hid: the bias), the batch spread over the threads and the
+// partial sums added in a fixed-order tree
 template <int O>
 __global__ __launch_bounds__(kT) void wgrad_out_kernel(const float *__restrict__ du, const bf16_t *__restrict__ h,
                                                        int hid, int64_t B, float *__restrict__ dW,
                                                        float *__restrict__ db) {
-    const int e = blockIdx.x * kT + threadIdx.x;
-    if (e >= O * (hid + 1)) return;
-    const int o = e / (hid + 1), i = e % (hid + 1);
-    float s = 0.0f;
-    if (i < hid)
-        for (int64_t b = 0; b < B; ++b) s = fmaf(du[b * O + o], fbf(h[b * hid + i]), s);
-    else
-        for (int64_t b = 0; b < B; ++b) s += du[b * O + o];
-    if (i < hid)
-        dW[o * hid + i] = s;
-    else
-        db[o] = s;
-}
-
-// db[o] = sum_b da[b][o]
-__global__ __launch_bounds__(kT) void colsum_kernel(const bf16_t *__restrict__ da, int ld, int n, int64_t Bp,
-                                                    float *__restrict__ db) {
-    const int o = blockIdx.x * kT + threadIdx.x;
-    if (o >= n) return;
-    float s = 0.0f;
-    for (int64_t b = 0; b < Bp; ++b) s += fbf(da[b * ld + o]);
-    db[o] = s;
+    __shared__ float part[O][kT];
+    const int i = blockIdx.x, t = threadIdx.x;
+    float s[O];
+#pragma unroll
+    for (int o = 0; o < O; ++o) s[o] = 0.0f;
+    for (int64_t b = t; b < B; b += kT) {
+        const float hv = (i < hid) ? fbf(h[b * hid + i]) : 1.0f;
+#pragma unroll
+        for (int o = 0; o < O; ++o) s[o] = fmaf(du[b * O + o], hv, s[o]);
+    }
+#pragma unroll
+    for (int o = 0; o < O; ++o) part[o][t] = s[o];
+    __syncthreads();
+    for (int w = kT / 2; w > 0; w >>= 1) {
+        if (t < w)
+#pragma unroll
+            for (int o = 0; o < O; ++o) part[o][t] += part[o][t + w];
+        __syncthreads();
+    }
+    if (t < O) {
+        if (i < hid)
+            dW[t * hid + i] = part[t][0];
+        else
+            db[t] = part[t][0];
+    }
 }
 
 // Adam on one parameter block [rows][cols] (padded storage, real part rows_r x cols_r; padding
@@ -452,8 +471,8 @@ df_status df_dnn_train_step(df_trainer *t, int64_t batch, const float *x, const 
         chk("output layer");
         hipLaunchKernelGGL(loss_sum_kernel, dim3(1), dim3(kT), 0, s, t->row_loss, B, O, t->loss);
         chk("loss");
-        hipLaunchKernelGGL(wgrad_out_kernel<O>, dim3(unsigned((O * (hid + 1) + kT - 1) / kT)), dim3(kT), 0, s, t->du,
-                           t->h[nh - 1], hid, B, t->gW[nh], t->gb[nh]);
+        hipLaunchKernelGGL(wgrad_out_kernel<O>, dim3(unsigned(hid + 1)), dim3(kT), 0, s, t->du, t->h[nh - 1], hid, B,
+                           t->gW[nh], t->gb[nh]);
         chk("output layer gradient");
     }
     // backward through the hidden layers
@@ -463,11 +482,8 @@ df_status df_dnn_train_step(df_trainer *t, int64_t batch, const float *x, const 
         const int inl_ld = Ly.k_pad;
         const int tiles_n = Ly.k_pad / 32;
         hipLaunchKernelGGL(wgrad_kernel, dim3(unsigned((Ly.n_pad / 32) * tiles_n)), dim3(64), 0, s, t->da[l], Ly.n_pad,
-                           inl, inl_ld, Bp, t->gW[l], Ly.k_pad, tiles_n);
+                           inl, inl_ld, Bp, t->gW[l], Ly.k_pad, tiles_n, t->gb[l]);
         chk("weight gradient");
-        hipLaunchKernelGGL(colsum_kernel, dim3(unsigned((Ly.n_pad + kT - 1) / kT)), dim3(kT), 0, s, t->da[l], Ly.n_pad,
-                           Ly.n_pad, Bp, t->gb[l]);
-        chk("bias gradient");
         if (l > 0 && st == DF_OK)
             st = launch_gemm_bf16_epi(t->da[l], Ly.n_pad, t->WT[l], Ly.n_pad, nullptr, t->da[l - 1], Ly.k_pad, Bp,
                                       Ly.k_pad, Ly.n_pad, GemmEpi::gelu_grad, t->a[l - 1], s);
