@@ -73,6 +73,11 @@ def lib():
     L.orc_chem_step_dt.restype = C.c_int
     L.orc_chem_step_dt.argtypes = [vp, C.c_int64, C.c_int64, C.c_double, dp, dp, dp, dp, dp, dp, ip, ip, ip,
                                    C.POINTER(_Opts), C.c_int]
+    L.orc_rhs_v.argtypes = [vp, C.c_double, dp, dp]
+    L.orc_jacobian_v.argtypes = [vp, C.c_double, dp, dp]
+    L.orc_chem_step_v.restype = C.c_int
+    L.orc_chem_step_v.argtypes = [vp, C.c_int64, C.c_int64, C.c_double, dp, dp, dp, dp, ip, ip, ip,
+                                  C.POINTER(_Opts), C.c_int]
     L.orc_chem_cell_record.restype = C.c_int
     L.orc_chem_cell_record.argtypes = [vp, C.c_double, C.c_double, dp, C.POINTER(_Opts), dp, C.c_int32, ip, ip]
     L.orc_chem_replay.argtypes = [vp, C.c_double, dp, dp, C.c_int32]
@@ -188,6 +193,37 @@ class Mech:
         if ret < 0:
             raise ValueError("oracle chem_step: bad arguments")
         return {"T": T, "Y": Y, "h": h, "rr": rr, "status": st, "n_acc": na, "n_rej": nr}
+
+    def rhs_v(self, rho, y):
+        """Right-hand side of the constant-volume reactor at density rho."""
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        f = np.zeros(self.K + 1)
+        lib().orc_rhs_v(self._h, float(rho), _dp(y), _dp(f))
+        return f
+
+    def jacobian_v(self, rho, y):
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        N = self.K + 1
+        J = np.zeros((N, N))
+        lib().orc_jacobian_v(self._h, float(rho), _dp(y), _dp(J))
+        return J
+
+    def chem_step_v(self, T, rho, Y, dt, h_inout=None, opts=None, nthreads=0):
+        """Constant-volume step of every cell: rho [n] fixed; returns dict like chem_step."""
+        T = np.array(T, dtype=np.float64, copy=True)
+        rho = np.ascontiguousarray(rho, dtype=np.float64)
+        Y = np.array(Y, dtype=np.float64, copy=True, order="C")
+        n = T.size
+        h = None if h_inout is None else np.array(h_inout, dtype=np.float64, copy=True)
+        st = np.zeros(n, dtype=np.int32)
+        na = np.zeros(n, dtype=np.int32)
+        nr = np.zeros(n, dtype=np.int32)
+        o = opts if opts is not None else default_opts()
+        ret = lib().orc_chem_step_v(self._h, n, n, float(dt), _dp(rho), _dp(T), _dp(Y), _dp(h), _ip(st), _ip(na),
+                                    _ip(nr), C.byref(o), int(nthreads))
+        if ret < 0:
+            raise ValueError("oracle chem_step_v: bad arguments")
+        return {"T": T, "Y": Y, "h": h, "status": st, "n_acc": na, "n_rej": nr}
 
     def record(self, T, p, Y, dt, opts=None, cap=100000):
         """Integrate one cell (T, Y[K]) over dt from a fresh start; returns (T, Y, status, h_list, n_rej)

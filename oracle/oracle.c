@@ -429,6 +429,109 @@ void orc_jacobian(const orc_mech *m, double p, const double *y, double *J) {
     free(dw);
 }
 
+/*
+ * Constant-volume adiabatic reactor (the df0DFoam constant-volume case): the
+ * density is fixed and the pressure follows, p = rho R T / Wbar;
+ *   dY_k/dt = W_k wdot_k / rho
+ *   dT/dt   = -sum_k U_k wdot_k / (rho cv),  U_k = H_k - R T,  cv = cp - R / Wbar
+ * (the species line as at constant pressure; the energy line keeps the mixture
+ * internal energy constant at fixed volume).
+ */
+static double pressure_at(const orc_mech *m, double rho, double T, const double *Y) {
+    double s = 0;
+    for (int k = 0; k < m->K; ++k) s += Y[k] / m->W[k];
+    return rho * R_GAS * T * s;
+}
+
+void orc_rhs_v(const orc_mech *m, double rho, const double *y, double *f) {
+    int K = m->K;
+    double T = y[0];
+    const double *Y = y + 1;
+    double p = pressure_at(m, rho, T, Y);
+    double wdot[ORC_MAX_SPECIES], h_RT[ORC_MAX_SPECIES], cp_R[ORC_MAX_SPECIES];
+    orc_rates(m, T, p, Y, NULL, NULL, NULL, wdot);
+    orc_species_thermo(m, T, cp_R, h_RT, NULL, NULL);
+    double S = 0, cv = 0;
+    for (int k = 0; k < K; ++k) {
+        f[1 + k] = m->W[k] * wdot[k] / rho;
+        S += (h_RT[k] - 1.0) * R_GAS * T * wdot[k];
+        cv += Y[k] * (cp_R[k] - 1.0) * R_GAS / m->W[k];
+    }
+    f[0] = -S / (rho * cv);
+}
+
+/* analytic Jacobian of the constant-volume reactor: the chain rule through
+ * q_j(T, c) with c_m = 1e-6 rho Y_m / W_m independent of T */
+void orc_jacobian_v(const orc_mech *m, double rho, const double *y, double *J) {
+    int K = m->K, M = m->M, N = K + 1;
+    double T = y[0];
+    const double *Y = y + 1;
+    double c[ORC_MAX_SPECIES], cp_R[ORC_MAX_SPECIES], h_RT[ORC_MAX_SPECIES], g_RT[ORC_MAX_SPECIES];
+    for (int k = 0; k < K; ++k) c[k] = 1e-6 * rho * Y[k] / m->W[k];
+    orc_species_thermo(m, T, cp_R, h_RT, NULL, g_RT);
+    double wdot[ORC_MAX_SPECIES];
+    double *dw = (double *)calloc((size_t)K * N, sizeof(double)); /* dw[k*N + l] */
+    double dqdc[ORC_MAX_SPECIES];
+    for (int k = 0; k < K; ++k) wdot[k] = 0;
+    for (int j = 0; j < M; ++j) {
+        const int *nr = &m->nu_r[K * j];
+        const int *np = &m->nu_p[K * j];
+        double Mc = (m->type[j] != 0) ? third_body(m, j, c) : 0.0;
+        double kf, dlnkf, dkfdM, Kc, dlnKc;
+        forward_rate(m, j, T, Mc, &kf, &dlnkf, &dkfdM);
+        equilibrium_constant(m, j, T, h_RT, g_RT, &Kc, &dlnKc);
+        double kr = kf / Kc;
+        double Pf = mass_action(c, nr, K), Pb = mass_action(c, np, K);
+        double fwd = kf * Pf, rev = kr * Pb;
+        double X = fwd - rev;
+        double dXdT = fwd * dlnkf - rev * (dlnkf - dlnKc);
+        double q, dqdT;
+        for (int mm = 0; mm < K; ++mm) dqdc[mm] = kf * d_mass_action(c, nr, K, mm) - kr * d_mass_action(c, np, K, mm);
+        if (m->type[j] == 0) {
+            q = X;
+            dqdT = dXdT;
+        } else if (m->type[j] == 1) {
+            q = Mc * X;
+            dqdT = Mc * dXdT;
+            for (int mm = 0; mm < K; ++mm) dqdc[mm] = Mc * dqdc[mm] + m->eff[K * j + mm] * X;
+        } else {
+            q = X;
+            dqdT = dXdT;
+            for (int mm = 0; mm < K; ++mm) dqdc[mm] += dkfdM * m->eff[K * j + mm] * (Pf - Pb / Kc);
+        }
+        for (int k = 0; k < K; ++k) {
+            int nu = np[k] - nr[k];
+            if (nu == 0) continue;
+            wdot[k] += 1e6 * nu * q;
+            dw[k * N + 0] += 1e6 * nu * dqdT;
+            for (int l = 0; l < K; ++l) dw[k * N + 1 + l] += 1e6 * nu * dqdc[l] * 1e-6 * rho / m->W[l];
+        }
+    }
+    for (int k = 0; k < K; ++k)
+        for (int l = 0; l < N; ++l) J[(1 + k) * N + l] = m->W[k] * dw[k * N + l] / rho;
+    /* temperature row: f_T = -S / D, S = sum U_k wdot_k, D = rho cv */
+    double S = 0, cv = 0, dcv_dT = 0;
+    for (int k = 0; k < K; ++k) {
+        S += (h_RT[k] - 1.0) * R_GAS * T * wdot[k];
+        cv += Y[k] * (cp_R[k] - 1.0) * R_GAS / m->W[k];
+        dcv_dT += Y[k] * R_GAS * dcpR_dT(m, k, T) / m->W[k];
+    }
+    double D = rho * cv;
+    for (int l = 0; l < N; ++l) {
+        double dS = 0;
+        for (int k = 0; k < K; ++k) dS += (h_RT[k] - 1.0) * R_GAS * T * dw[k * N + l];
+        double dD;
+        if (l == 0) {
+            for (int k = 0; k < K; ++k) dS += (cp_R[k] - 1.0) * R_GAS * wdot[k]; /* dU_k/dT = cv_k */
+            dD = rho * dcv_dT;
+        } else {
+            dD = rho * (cp_R[l - 1] - 1.0) * R_GAS / m->W[l - 1];
+        }
+        J[l] = -dS / D + S * dD / (D * D);
+    }
+    free(dw);
+}
+
 /* ------------------------------------------------------------------------- */
 /* dense LU with partial pivoting (ties -> lowest row index)                  */
 /* ------------------------------------------------------------------------- */
@@ -724,16 +827,23 @@ void orc_linear_fixed_step(int n, const double *A, double *y, double h, double *
 }
 
 /* ---- chemistry ---- */
-typedef struct { const orc_mech *m; double p; } chem_ctx;
+/* p is the pressure (constant-pressure reactor) or the density (constant-volume, cv != 0) */
+typedef struct { const orc_mech *m; double p; int cv; } chem_ctx;
 
 static void chem_rhs(void *ctx, const double *y, double *f) {
     chem_ctx *c = (chem_ctx *)ctx;
-    orc_rhs(c->m, c->p, y, f);
+    if (c->cv)
+        orc_rhs_v(c->m, c->p, y, f);
+    else
+        orc_rhs(c->m, c->p, y, f);
 }
 
 static void chem_jac(void *ctx, const double *y, double *J) {
     chem_ctx *c = (chem_ctx *)ctx;
-    orc_jacobian(c->m, c->p, y, J);
+    if (c->cv)
+        orc_jacobian_v(c->m, c->p, y, J);
+    else
+        orc_jacobian(c->m, c->p, y, J);
 }
 
 static orc_opts default_opts(const orc_opts *o) {
@@ -743,7 +853,7 @@ static orc_opts default_opts(const orc_opts *o) {
 
 /* integrate one cell in place; returns status */
 static int chem_cell(const orc_mech *m, double dt, double p, double *y, double *h_io, const orc_opts *o,
-                     int *acc, int *rej) {
+                     int *acc, int *rej, int cv) {
     int K = m->K, N = K + 1;
     int finite = isfinite(p) && p > 0 && isfinite(y[0]) && y[0] > 0;
     for (int k = 0; k < K; ++k) finite = finite && isfinite(y[1 + k]);
@@ -753,7 +863,7 @@ static int chem_cell(const orc_mech *m, double dt, double p, double *y, double *
     double atol[ORC_MAX_SPECIES + 1];
     atol[0] = o->atol_T;
     for (int k = 0; k < K; ++k) atol[1 + k] = o->atol_Y;
-    chem_ctx c = {m, p};
+    chem_ctx c = {m, p, cv};
     double h_in = h_io ? *h_io : 0.0, h_next = 0.0;
     int st = ros_integrate(N, y, dt, h_in, atol, o->rtol, o->h_min, o->max_steps, chem_rhs, chem_jac, &c, &h_next,
                            acc, rej, NULL, 0);
@@ -792,13 +902,46 @@ int orc_chem_step_dt(const orc_mech *m, int64_t n, int64_t ld, double dt, const 
         if (rr) orc_mixture(m, T[i], p[i], Y0, NULL, &rho0, NULL, NULL);
         int acc, rej;
         const double dti = dt_cells ? dt_cells[i] : dt;
-        int st = chem_cell(m, dti, p[i], y, h_inout ? &h_inout[i] : NULL, &o, &acc, &rej);
+        int st = chem_cell(m, dti, p[i], y, h_inout ? &h_inout[i] : NULL, &o, &acc, &rej, 0);
         if (st != ORC_NONFINITE) {
             T[i] = y[0];
             for (int k = 0; k < K; ++k) Y[k * ld + i] = y[1 + k];
         }
         if (rr)
             for (int k = 0; k < K; ++k) rr[k * ld + i] = rho0 * (Y[k * ld + i] - Y0[k]) / dti;
+        if (status) status[i] = st;
+        if (n_acc) n_acc[i] = acc;
+        if (n_rej) n_rej[i] = rej;
+        if (st != ORC_OK) fails += 1;
+    }
+    return fails;
+}
+
+/* constant-volume step of n cells: rho [n] fixed, T and Y advanced in place
+ * (same controller, tolerances and statuses as orc_chem_step) */
+int orc_chem_step_v(const orc_mech *m, int64_t n, int64_t ld, double dt, const double *rho, double *T, double *Y,
+                    double *h_inout, int32_t *status, int32_t *n_acc, int32_t *n_rej, const orc_opts *opts,
+                    int nthreads) {
+    if (!m || n < 0 || ld < n || !rho || !T || !Y || !(dt > 0)) return -1;
+    orc_opts o = default_opts(opts);
+    int K = m->K;
+    int fails = 0;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : fails)
+    for (int64_t i = 0; i < n; ++i) {
+        double y[ORC_MAX_SPECIES + 1];
+        y[0] = T[i];
+        for (int k = 0; k < K; ++k) y[1 + k] = Y[k * ld + i];
+        int acc, rej;
+        int st = chem_cell(m, dt, rho[i], y, h_inout ? &h_inout[i] : NULL, &o, &acc, &rej, 1);
+        if (st != ORC_NONFINITE) {
+            T[i] = y[0];
+            for (int k = 0; k < K; ++k) Y[k * ld + i] = y[1 + k];
+        }
         if (status) status[i] = st;
         if (n_acc) n_acc[i] = acc;
         if (n_rej) n_rej[i] = rej;
@@ -823,7 +966,7 @@ int orc_chem_cell_record(const orc_mech *m, double dt, double p, double *y, cons
     double atol[ORC_MAX_SPECIES + 1];
     atol[0] = o.atol_T;
     for (int k = 0; k < K; ++k) atol[1 + k] = o.atol_Y;
-    chem_ctx c = {m, p};
+    chem_ctx c = {m, p, 0};
     int a = 0, r = 0;
     int st = ros_integrate(N, y, dt, 0.0, atol, o.rtol, o.h_min, o.max_steps, chem_rhs, chem_jac, &c, NULL, &a, &r,
                            h_rec, rec_cap);
@@ -834,7 +977,7 @@ int orc_chem_cell_record(const orc_mech *m, double dt, double p, double *y, cons
 
 void orc_chem_replay(const orc_mech *m, double p, double *y, const double *hs, int32_t nh) {
     int N = m->K + 1;
-    chem_ctx c = {m, p};
+    chem_ctx c = {m, p, 0};
     double J[(ORC_MAX_SPECIES + 1) * (ORC_MAX_SPECIES + 1)], Wm[(ORC_MAX_SPECIES + 1) * (ORC_MAX_SPECIES + 1)];
     double u[NS * (ORC_MAX_SPECIES + 1)], f0[ORC_MAX_SPECIES + 1], ys[ORC_MAX_SPECIES + 1], fs[ORC_MAX_SPECIES + 1];
     double yn[ORC_MAX_SPECIES + 1], ev[ORC_MAX_SPECIES + 1];
@@ -1055,7 +1198,7 @@ int orc_dnn_step(const orc_dnn *d, const orc_mech *m, int64_t n, int64_t ld, dou
                 y[0] = T0;
                 for (int k = 0; k < K; ++k) y[1 + k] = Y0[k];
                 int acc, rej;
-                st = chem_cell(m, dt, p[i], y, NULL, &o, &acc, &rej);
+                st = chem_cell(m, dt, p[i], y, NULL, &o, &acc, &rej, 0);
                 T[i] = y[0];
                 for (int k = 0; k < K; ++k) Y[k * ld + i] = y[1 + k];
                 st = (st == ORC_OK) ? ORC_DNN_FALLBACK : st;

@@ -75,6 +75,14 @@ void orc_rhs(const orc_mech *m, double p, const double *y, double *f);
 /* analytic Jacobian J[i*N + j] = d f_i / d y_j, N = K + 1 */
 void orc_jacobian(const orc_mech *m, double p, const double *y, double *J);
 
+/* constant-volume reactor (rho fixed, p = rho R T / Wbar): right-hand side, analytic Jacobian,
+ * and the step of n cells with density rho [n] (arguments otherwise as orc_chem_step) */
+void orc_rhs_v(const orc_mech *m, double rho, const double *y, double *f);
+void orc_jacobian_v(const orc_mech *m, double rho, const double *y, double *J);
+int orc_chem_step_v(const orc_mech *m, int64_t n, int64_t ld, double dt, const double *rho, double *T, double *Y,
+                    double *h_inout, int32_t *status, int32_t *n_acc, int32_t *n_rej, const orc_opts *opts,
+                    int nthreads);
+
 /* RODAS4 coefficients in transformed form: gamma, a[6*6], c[6*6], m[6], mhat[6] */
 void orc_rodas4_tableau(double *gamma, double *a, double *c, double *mm, double *mhat);
 

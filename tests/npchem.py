@@ -98,6 +98,31 @@ class NpChem:
         dT = -np.sum(self.h_RT(T) * R * T * w) / (rho * self.cp_mass(T, Y))
         return np.concatenate([[dT], dY])
 
+    def rhs_v(self, rho, y):
+        """Constant-volume reactor: rho fixed, p = rho R T / Wbar; the energy equation keeps
+        u = sum_k Y_k (H_k - R T)/W_k constant."""
+        T = y[0]
+        Y = y[1:]
+        p = rho * R * T * np.sum(Y / self.W)
+        w, _ = self.wdot(T, p, Y)
+        dY = self.W * w / rho
+        cv = np.sum(Y * (self.cp_R(T) - 1.0) * R / self.W)
+        dT = -np.sum((self.h_RT(T) - 1.0) * R * T * w) / (rho * cv)
+        return np.concatenate([[dT], dY])
+
+    def u_mass(self, T, Y):
+        return np.sum(Y * (self.h_RT(T) - 1.0) * R * T / self.W)
+
+    def jac_v_complex_step(self, rho, y, h=1e-30):
+        N = len(y)
+        J = np.zeros((N, N))
+        for l in range(N):
+            yc = np.array(y, dtype=complex)
+            step = h * max(abs(y[l]), 1e-3 if l else 1.0)
+            yc[l] += 1j * step
+            J[:, l] = np.imag(self.rhs_v(rho, yc)) / step
+        return J
+
     def jac_complex_step(self, p, y, h=1e-30):
         N = len(y)
         J = np.zeros((N, N))
