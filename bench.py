@@ -308,6 +308,74 @@ def training_study(gm, dnn_path, mech_h, dev):
                          "frac": tflops / PEAK_BF16_TFLOPS}}
 
 
+def rollout_study(gm, dnn, mech_h, dev):
+    """The paper's 0-D checks on the synthetic mechanism, as device rollouts of 1 us steps:
+    the ignition delay (largest dT/dt) against T0 for stoichiometric H2/air at 1 atm from the
+    integrator and from the DNN; the constant-volume case (phi = 1, 1000 K, 0.5 atm) with the
+    integrator; and the time per rollout step of the constant-pressure case (phi = 1, 1400 K,
+    1 atm) at several reactor counts, the paper's 0-D timing over grid sizes."""
+    import torch
+    from synth import fields
+    R = 8.31446261815324
+    Yphi = fields.premixed_h2_air(mech_h, 1.0).reshape(-1)
+    W = np.asarray(mech_h.molar_mass) * 1e-3
+
+    def cells(T0):
+        n = T0.size
+        Y = torch.tensor(np.ascontiguousarray(np.repeat(Yphi[:, None], n, axis=1)), device=dev)
+        return torch.tensor(T0, device=dev), Y
+
+    T0 = np.linspace(1000.0, 1500.0, 21)
+    p = torch.full((T0.size,), 101325.0, dtype=torch.float64, device=dev)
+    steps = 2000
+    T, Y = cells(T0)
+    idt_i, _ = gm.rollout(T, p, Y, 1e-6, steps)
+    T, Y = cells(T0)
+    idt_d, _ = gm.rollout(T, p, Y, 1e-6, steps, dnn=dnn)
+    ii, dd = idt_i.cpu().numpy(), idt_d.cpu().numpy()
+    both = np.isfinite(ii) & np.isfinite(dd)
+    rel = np.abs(dd[both] - ii[both]) / ii[both]
+    # constant volume: phi = 1, 1000 K, 0.5 atm
+    rho = 0.5 * 101325.0 / (R * 1000.0 * np.sum(Yphi / W))
+    T, Y = cells(np.array([1000.0]))
+    idt_v, traj_v = gm.rollout(T, torch.tensor([rho], device=dev), Y, 1e-6, 2500, trajectory=True,
+                               constant_volume=True)
+    Yv = Y.cpu().numpy()[:, 0]
+    Tv_end = float(T.cpu()[0])
+    p_end = rho * R * Tv_end * np.sum(Yv / W)
+    # time per rollout step of the 1400 K constant-pressure reactor, n copies
+    timing = []
+    stream = torch.cuda.current_stream()
+    for n in (1, 1024, 65536):
+        row = {"reactors": n}
+        for name, net in (("integrator", None), ("dnn", dnn)):
+            pn = torch.full((n,), 101325.0, dtype=torch.float64, device=dev)
+            T, Y = cells(np.full(n, 1400.0))
+            gm.rollout(T, pn, Y, 1e-6, 5, dnn=net)
+            T, Y = cells(np.full(n, 1400.0))
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            gm.rollout(T, pn, Y, 1e-6, 100, dnn=net)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            row[f"{name}_ms_per_step"] = e0.elapsed_time(e1) / 100
+        row["dnn_speedup"] = row["integrator_ms_per_step"] / row["dnn_ms_per_step"]
+        timing.append(row)
+    return {"workload": "0-D H2/air rollouts, 1 us steps: delay curve phi=1 1 atm T0 1000-1500 K (21 reactors, "
+                        "2 ms); constant volume phi=1 1000 K 0.5 atm (2.5 ms); time per step of the 1400 K "
+                        "reactor (100 steps) at 1, 1024, 65536 copies",
+            "idt_curve": {"T0_K": T0.tolist(), "integrator_s": [None if not np.isfinite(v) else float(v) for v in ii],
+                          "dnn_s": [None if not np.isfinite(v) else float(v) for v in dd]},
+            "dnn_idt_rel_err": {"median": float(np.median(rel)) if rel.size else None,
+                                "max": float(rel.max()) if rel.size else None,
+                                "within_10pct": int(np.sum(rel <= 0.1)), "compared": int(both.sum()),
+                                "dnn_no_ignition": int(np.sum(np.isfinite(ii) & ~np.isfinite(dd)))},
+            "constant_volume": {"idt_s": float(idt_v.cpu()[0]), "T_end_K": Tv_end,
+                                "T_max_rise_K": float((traj_v[:, 0] - traj_v[0, 0]).max().cpu()),
+                                "p_end_over_p0": p_end / (0.5 * 101325.0)},
+            "time_per_step": timing}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -317,6 +385,7 @@ def main():
     ap.add_argument("--no-batching", action="store_true", help="skip the 1M-cell scheduling study")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the 4096-cell adjoint study")
     ap.add_argument("--no-training", action="store_true", help="skip the DNN training study")
+    ap.add_argument("--no-rollout", action="store_true", help="skip the 0-D rollout study")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported (cells are independent, "
@@ -426,6 +495,7 @@ def main():
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     adjoint = None if a.no_adjoint else adjoint_study(gm, mech_h, dev, not a.no_cpu, threads)
     training = None if a.no_training else training_study(gm, DNN_W, mech_h, dev)
+    rollouts = None if a.no_rollout else rollout_study(gm, dnn, mech_h, dev)
 
     out = {
         "metric": "cells/s per chemistry step: FP64 stiff integrator vs BF16 DNN at stated error",
@@ -461,6 +531,7 @@ def main():
         "batching_mixing_layer": batching,
         "adjoint": adjoint,
         "dnn_training": training,
+        "rollouts_0d": rollouts,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -166,6 +166,50 @@ df_status df_chem_step_cells(const df_mech *mech, int64_t n_cells, int64_t ld, c
                              int32_t *n_steps, void *workspace, size_t workspace_bytes, const df_chem_opts *opts,
                              void *hip_stream);
 
+/*
+ * The constant-volume reactor (df0DFoam's constant-volume case): density fixed per cell,
+ * pressure following from the state (p = rho R T / Wbar),
+ *   dY_k/dt = W_k wdot_k / rho,  dT/dt = -sum_k U_k wdot_k / (rho cv),
+ * U_k = H_k - R T, cv = cp - R / Wbar; the mixture internal energy is conserved.
+ *   rho         [n]      in      density per cell [kg/m^3]
+ *   T, Y, h_inout, cell_status, n_steps, opts: as df_chem_step (one cell per lane; opts.mapping
+ *               and opts.schedule are ignored)
+ * A cell whose rho or T is not positive and finite, or whose Y is not finite, is left untouched
+ * with DF_CELL_NONFINITE.  Errors: DF_E_INVALID, DF_E_UNSUPPORTED, DF_E_HIP.
+ */
+df_status df_chem_step_const_volume(const df_mech *mech, int64_t n_cells, int64_t ld, double dt, const double *rho,
+                                    double *T, double *Y, double *h_inout, int32_t *cell_status, int32_t *n_steps,
+                                    const df_chem_opts *opts, void *hip_stream);
+
+/* reactors of df_rollout */
+#define DF_REACTOR_CONST_P 0
+#define DF_REACTOR_CONST_V 1
+
+/*
+ * 0-D rollouts (the paper's 0-D autoignition cases and ignition-delay curves, Sec. "df0DFoam-
+ * solver"; the delay is taken at the largest dT/dt): n_steps consecutive chemistry steps of
+ * length dt of the DNN form (dnn != NULL, df_dnn_step with its fallback) or of the integrator
+ * (dnn == NULL: df_chem_step, or df_chem_step_const_volume for DF_REACTOR_CONST_V, carrying each
+ * cell's sub-step hint), on (T, Y) in place, tracking each cell's ignition delay: the time of the
+ * largest temperature rate, r_k = (T_{k+1} - T_k)/dt at t_k = (k + 1/2) dt, refined by the vertex
+ * of the parabola through the rates of the steps around it.
+ *   reactor                in      DF_REACTOR_CONST_P, or DF_REACTOR_CONST_V (integrator only)
+ *   p [n]                  in      pressure [Pa]; the density [kg/m^3] for DF_REACTOR_CONST_V
+ *   T [n], Y [K*ld]        in/out  state (after n_steps steps on return)
+ *   idt [n]                out     ignition delay [s]; NaN when the largest rate falls on the
+ *                                  first or last step
+ *   T_traj [(n_steps+1)*n] out     temperature after each step, row 0 the initial one (nullable)
+ *   workspace             device memory of df_rollout_workspace_size bytes (enough for either
+ *                         reactor), 256-byte aligned
+ *   opts                  integrator options (also the DNN's fallback), nullable
+ * Errors: DF_E_INVALID (also a DNN with DF_REACTOR_CONST_V), those of df_chem_step /
+ * df_chem_step_const_volume / df_dnn_step, DF_E_HIP.
+ */
+df_status df_rollout_workspace_size(const df_mech *mech, const df_dnn *dnn, int64_t n_cells, size_t *bytes);
+df_status df_rollout(const df_mech *mech, const df_dnn *dnn, int64_t n_cells, int64_t ld, double dt, int32_t n_steps,
+                     int32_t reactor, const double *p, double *T, double *Y, double *idt, double *T_traj, void *workspace,
+                     size_t workspace_bytes, const df_chem_opts *opts, void *hip_stream);
+
 /* Bytes of device workspace df_chem_autotune needs for n_cells. */
 df_status df_chem_autotune_workspace_size(const df_mech *mech, int64_t n_cells, size_t *bytes);
 

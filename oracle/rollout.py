@@ -28,13 +28,15 @@ def ignition_delay(T_traj, dt):
     return out
 
 
-def integrator_rollout(om, T, p, Y, dt, n_steps, nthreads=0):
+def integrator_rollout(om, T, p, Y, dt, n_steps, nthreads=0, constant_volume=False):
+    """Constant pressure p, or with constant_volume the constant-volume reactor at density p."""
     T = np.array(T, dtype=np.float64, copy=True)
     Y = np.array(Y, dtype=np.float64, copy=True)
     h = np.zeros(T.size)
     traj = [T.copy()]
+    step = om.chem_step_v if constant_volume else om.chem_step
     for _ in range(n_steps):
-        r = om.chem_step(T, p, Y, dt, h_inout=h, nthreads=nthreads)
+        r = step(T, p, Y, dt, h_inout=h, nthreads=nthreads)
         T, Y, h = r["T"], r["Y"], r["h"]
         traj.append(T.copy())
     traj = np.array(traj)

@@ -134,6 +134,49 @@ class Mechanism:
         return check(lib().df_chem_step_cells(*args) if per_cell else lib().df_chem_step(*args))
 
 
+    def chem_step_const_volume(self, T, rho, Y, dt, h=None, status=None, n_steps=None, opts=None, stream=None):
+        """Advance every cell by dt at constant volume, in place (df_chem_step_const_volume):
+        rho float64 [n] densities, other arguments as chem_step."""
+        import torch
+        n = T.numel()
+        K = self.n_species
+        if Y.dim() != 2 or Y.shape[0] != K:
+            raise ValueError(f"Y must have shape [{K}, ld]")
+        ld = Y.shape[1]
+        dev = self.device
+        return check(lib().df_chem_step_const_volume(
+            self._h, n, ld, float(dt), _ptr(rho, torch.float64, "rho", n, dev), _ptr(T, torch.float64, "T", n, dev),
+            _ptr(Y, torch.float64, "Y", K * ld, dev), _ptr(h, torch.float64, "h", n, dev),
+            _ptr(status, torch.int32, "status", n, dev), _ptr(n_steps, torch.int32, "n_steps", 2 * n, dev),
+            C.byref(opts) if opts is not None else None, _stream(stream)))
+
+    def rollout(self, T, p, Y, dt, n_steps, dnn=None, trajectory=False, constant_volume=False, opts=None,
+                stream=None):
+        """n_steps consecutive steps of the DNN (dnn given) or of the integrator on (T, Y) in place,
+        with each cell's ignition delay (df_rollout).  With constant_volume the integrator steps the
+        constant-volume reactor and p holds the density.  Returns (idt [n], T_traj [n_steps+1, n]
+        or None)."""
+        import torch
+        n = T.numel()
+        K = self.n_species
+        if Y.dim() != 2 or Y.shape[0] != K:
+            raise ValueError(f"Y must have shape [{K}, ld]")
+        ld = Y.shape[1]
+        dev = self.device
+        dh = dnn.handle if dnn is not None else None
+        b = C.c_size_t()
+        check(lib().df_rollout_workspace_size(self._h, dh, n, C.byref(b)))
+        ws = torch.empty(max(b.value, 1), dtype=torch.uint8, device=f"cuda:{dev}")
+        idt = torch.empty(n, dtype=torch.float64, device=f"cuda:{dev}")
+        traj = torch.empty(int(n_steps) + 1, n, dtype=torch.float64, device=f"cuda:{dev}") if trajectory else None
+        check(lib().df_rollout(self._h, dh, n, ld, float(dt), int(n_steps), 1 if constant_volume else 0,
+                               _ptr(p, torch.float64, "p", n, dev),
+                               _ptr(T, torch.float64, "T", n, dev), _ptr(Y, torch.float64, "Y", K * ld, dev),
+                               _ptr(idt, torch.float64, "idt", n, dev),
+                               _ptr(traj, torch.float64, "T_traj", None, dev), _ptr(ws, torch.uint8, "ws", None, dev),
+                               ws.numel(), C.byref(opts) if opts is not None else None, _stream(stream)))
+        return idt, traj
+
     def autotune(self, T, p, Y, dt, opts=None, stream=None) -> ChemOpts:
         """Schedule for this workload (df_chem_autotune): times the candidates on copies of
         (T, Y) and returns `opts` (or the defaults) with schedule and coop_blocks set."""

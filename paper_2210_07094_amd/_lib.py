@@ -98,6 +98,12 @@ def lib():
     L.df_dnn_trainer_get.argtypes = [vp, i32, i32, vp, vp]
     L.df_dnn_trainer_set.restype = i32
     L.df_dnn_trainer_set.argtypes = [vp, i32, i32, vp, vp]
+    L.df_rollout_workspace_size.restype = i32
+    L.df_rollout_workspace_size.argtypes = [vp, vp, i64, C.POINTER(C.c_size_t)]
+    L.df_rollout.restype = i32
+    L.df_rollout.argtypes = [vp, vp, i64, i64, d, i32, i32, vp, vp, vp, vp, vp, vp, C.c_size_t, C.POINTER(ChemOpts), vp]
+    L.df_chem_step_const_volume.restype = i32
+    L.df_chem_step_const_volume.argtypes = [vp, i64, i64, d, vp, vp, vp, vp, vp, vp, C.POINTER(ChemOpts), vp]
     L.df_chem_step_cells.restype = i32
     L.df_chem_step_cells.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t,
                                      C.POINTER(ChemOpts), vp]

@@ -51,9 +51,6 @@ static df_status launch_k(const MechDev &m, const StepArgs &a, const int32_t *ci
     return DF_OK;
 }
 
-// species counts with a compiled per-lane kernel
-#define DF_CHEM_SPECIES_LIST(X) X(2) X(4) X(9)
-
 df_status launch_chem_step(const MechDev &m, const StepArgs &a, int mapping, const int32_t *cidx,
                            const int32_t *dcount, hipStream_t stream) {
     if (a.n == 0) return DF_OK;

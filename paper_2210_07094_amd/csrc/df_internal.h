@@ -144,6 +144,9 @@ struct CellQueue {
     int32_t head_blocks;
 };
 
+// species counts with a compiled one-cell-per-lane kernel
+#define DF_CHEM_SPECIES_LIST(X) X(2) X(4) X(9)
+
 inline Opts kernel_opts(const df_chem_opts &o) { return Opts{o.rtol, o.atol_T, o.atol_Y, o.h_min, o.max_steps}; }
 
 // integrator launch with the static schedule (df_chem.hip); arrays already validated.

@@ -29,7 +29,10 @@ namespace {
 // over registers.  Slot 0 of each array is the neutral element.
 constexpr int kWave = 64;
 
-template <int K>
+// CV: the constant-volume reactor (the df0DFoam constant-volume case): the density is an input
+// (passed where the pressure is otherwise), dT/dt = -sum_k U_k wdot_k / (rho cv) with
+// U_k = H_k - R T and cv = cp - R / Wbar, and the concentrations do not depend on T or Wbar.
+template <int K, bool CV = false>
 struct Cell {
     static constexpr int N = K + 1;
     // LDS slot offsets (in units of one wave-wide row of doubles).  The Jacobian-only
@@ -48,7 +51,7 @@ struct Cell {
 
     struct Mix {
         double T, iT, lT;
-        double rho, Wbar, cp;  // kg/m^3, kg/mol, J/kg/K
+        double rho, Wbar, cp;  // kg/m^3, kg/mol, J/kg/K (cv for the constant-volume reactor)
         double cref, icref;    // p0/(RT) in mol/cm^3 and its inverse
     };
 
@@ -76,8 +79,8 @@ struct Cell {
             cpm += y[1 + k] * cp * r[1];
         }
         s.Wbar = 1.0 / sYW;
-        s.rho = p * s.Wbar * s.iT * (1.0 / kR);
-        s.cp = cpm * kR;
+        s.rho = CV ? p : p * s.Wbar * s.iT * (1.0 / kR);
+        s.cp = CV ? (cpm - sYW) * kR : cpm * kR;
         const double cfac = 1e-6 * s.rho;
 #pragma unroll
         for (int k = 0; k < K; ++k) at(sh, kC + 1 + k) = cfac * y[1 + k] * m.sp[k * kSpTab + 1];
@@ -143,7 +146,7 @@ struct Cell {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             f[1 + k] = fy * m.sp[k * kSpTab] * wd[1 + k];
-            hsum = fma(hRT[1 + k], wd[1 + k], hsum);
+            hsum = fma(CV ? hRT[1 + k] - 1.0 : hRT[1 + k], wd[1 + k], hsum);  // U/RT = H/RT - 1
         }
         f[0] = -hsum * (1e6 * kR) * s.T / (s.rho * s.cp);
     }
@@ -239,22 +242,24 @@ struct Cell {
             const double Wk = r[0];
             const int row = 1 + k;
             const double coef = fy * Wk;
-            const double gk = coef * s.Wbar * (wd[row] - sq[row]);
-            J[row][0] = coef * (dt[row] + (wd[row] - sq[row]) * s.iT);
+            // at constant pressure c depends on T and Wbar (dc_m/dT = -c_m/T, and the Wbar term);
+            // at constant volume it does not
+            const double gk = CV ? 0.0 : coef * s.Wbar * (wd[row] - sq[row]);
+            J[row][0] = CV ? coef * dt[row] : coef * (dt[row] + (wd[row] - sq[row]) * s.iT);
 #pragma unroll
             for (int l = 0; l < K; ++l) {
                 const double iWl = m.sp[l * kSpTab + 1];
                 J[row][1 + l] = (Wk * J[row][1 + l] + gk) * iWl;
             }
             f[row] = coef * wd[row];
-            hm[row] = hRT[row] * kR * s.T * r[1];  // J/kg
-            cpm[row] = cpR[row] * kR * r[1];              // J/kg/K
+            hm[row] = (CV ? hRT[row] - 1.0 : hRT[row]) * kR * s.T * r[1];  // J/kg: h_k, or u_k
+            cpm[row] = (CV ? cpR[row] - 1.0 : cpR[row]) * kR * r[1];       // J/kg/K: cp_k, or cv_k
             dcpdT += y[row] * (r[3] + s.T * (r[16] + s.T * (r[17] + s.T * r[18]))) * kR * r[1];
             hf += hm[row] * f[row];
         }
         const double icp = 1.0 / s.cp;
         f[0] = -hf * icp;
-        // temperature row: f_T = -sum_k h_k f_k / cp
+        // temperature row: f_T = -sum_k h_k f_k / cp (u_k and cv at constant volume)
 #pragma unroll
         for (int l = 0; l < N; ++l) {
             double acc = 0.0;
@@ -415,9 +420,9 @@ __device__ void lane_finish(const MechDev &m, const StepArgs &a, const LaneTask<
 // One RODAS4 attempt of the lane's cell (the first attempt of a cell without a step
 // hint also picks the initial step from f(y0)).  Returns true when the cell is done and
 // its results have been written.
-template <int K>
+template <int K, bool CV = false>
 __device__ bool lane_attempt(const MechDev &m, const StepArgs &a, double *sh, LaneTask<K> &c) {
-    using C = Cell<K>;
+    using C = Cell<K, CV>;
     constexpr int N = K + 1;
     const Opts &o = a.o;
     if (c.acc + c.rej >= o.max_steps) {

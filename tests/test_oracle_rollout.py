@@ -27,3 +27,32 @@ def test_integrator_rollout_delays(h2_mech, h2_oracle):
     assert traj.shape == (801, 2)
     assert np.all(np.isfinite(idt)) and idt[1] < idt[0]
     assert 1e-4 < idt[0] < 8e-4
+
+
+def test_constant_volume_rollout_conserves_internal_energy(h2_mech, h2_oracle, npchem):
+    """The paper's constant-volume case (phi = 1, 1000 K, 0.5 atm): along the whole trajectory the
+    mixture internal energy stays at its initial value, the mass fractions keep their sum, and the
+    pressure rho R T / Wbar rises through ignition; the delay is finite."""
+    R = 8.31446261815324
+    Y0 = fields.premixed_h2_air(h2_mech, 1.0).reshape(-1)
+    T0, p0 = 1000.0, 0.5 * 101325.0
+    rho = p0 / (R * T0 * np.sum(Y0 / npchem.W))
+    u0 = npchem.u_mass(T0, Y0)
+    T, Y = np.array([T0]), Y0[:, None].copy()
+    h = np.zeros(1)
+    traj = [T0]
+    pmax = p0
+    for _ in range(2500):
+        r = h2_oracle.chem_step_v(T, np.array([rho]), Y, 1e-6, h_inout=h)
+        T, Y, h = r["T"], r["Y"], r["h"]
+        assert r["status"][0] == 0
+        traj.append(T[0])
+        cv = np.sum(Y[:, 0] * (npchem.cp_R(T[0]) - 1.0) * R / npchem.W)
+        assert abs(npchem.u_mass(T[0], Y[:, 0]) - u0) <= 20 * 1e-8 * cv * T[0]
+        pmax = max(pmax, rho * R * T[0] * np.sum(Y[:, 0] / npchem.W))
+    assert abs(Y.sum() - Y0.sum()) < 1e-12
+    assert traj[-1] - T0 > 150.0 and pmax > 1.1 * p0
+    traj2, _, idt = ro.integrator_rollout(h2_oracle, np.array([T0]), np.array([rho]), Y0[:, None], 1e-6, 2500,
+                                          constant_volume=True)
+    assert np.array_equal(traj2[:, 0], np.array(traj))
+    assert np.isfinite(idt[0]) and 1e-4 < idt[0] < 2.5e-3
