@@ -22,6 +22,13 @@ All fields are returned as float64 structure-of-arrays: ``T[n]`` (K),
   is used up); T = 300 + 2200 c + N(0, 50^2) clipped to [300, 2500] K;
   p = 1 atm; per-cell dt log-uniform in [1e-7, 1e-5] s.  It stands in for the
   paper's uneven chemistry load across a flame (its DLB motivation).
+* ``premixed_ch4_air(phi)``: CH4/air, air O2:N2:AR = 1:3.72:0.0446 by moles
+  (21 % O2, 1 % AR), phi = (n_CH4 / n_O2) * 2.
+* ``hydrocarbon_field`` (262,144 cells, the 53-species mechanism): T ~ U(300, 2400) K,
+  p ~ U(1, 10) atm; composition the blend (1 - c) unburnt + c products of CH4/air at
+  phi ~ U(0.5, 1.5) with progress c ~ U(0, 1) (products: CH4 + 2 O2 -> CO2 + 2 H2O until
+  the deficient reactant is used up), plus every other species at a mass fraction
+  log-uniform in [1e-12, 1e-3], renormalised; dt = 1e-6 s.
 """
 from __future__ import annotations
 
@@ -113,3 +120,49 @@ def mixing_layer_3d(mech, n_side=100, seed=FIELD_SEED_3, delta=10.0, z_noise=0.0
     dt = np.exp(rng.uniform(np.log(dt_range[0]), np.log(dt_range[1]), size=n))
     return {"T": T, "p": np.full(n, float(p)), "Y": np.ascontiguousarray(Y), "dt": dt, "Z": Z, "c": c,
             "z_st": z_st, "shape": (n_side, n_side, n_side)}
+
+
+FIELD_SEED_5 = 5005
+
+
+def premixed_ch4_air(mech, phi):
+    """Mass fractions [K, n] of CH4/air at equivalence ratio phi (array or scalar)."""
+    phi = np.atleast_1d(np.asarray(phi, dtype=np.float64))
+    W = np.asarray(mech.molar_mass, dtype=np.float64)
+    n = np.zeros((mech.n_species, phi.size))
+    n[mech.index("CH4")] = 0.5 * phi
+    n[mech.index("O2")] = 1.0
+    n[mech.index("N2")] = 3.72
+    n[mech.index("AR")] = 0.0446
+    m = n * W[:, None]
+    return m / m.sum(axis=0, keepdims=True)
+
+
+def hydrocarbon_field(mech, n=262144, seed=FIELD_SEED_5, T_range=(300.0, 2400.0), p_range=(1.0, 10.0),
+                      phi_range=(0.5, 1.5), minor=(1e-12, 1e-3)):
+    rng = np.random.default_rng(seed)
+    K = mech.n_species
+    W = np.asarray(mech.molar_mass, dtype=np.float64)
+    T = rng.uniform(*T_range, size=n)
+    p = rng.uniform(*p_range, size=n) * P_ATM
+    phi = rng.uniform(*phi_range, size=n)
+    c = rng.uniform(0.0, 1.0, size=n)
+    iF, iO, iC, iW = mech.index("CH4"), mech.index("O2"), mech.index("CO2"), mech.index("H2O")
+    Yu = premixed_ch4_air(mech, phi)
+    # complete combustion of the unburnt mixture, per unit mass
+    nu = Yu / W[:, None]
+    burn = np.minimum(nu[iF], nu[iO] / 2.0)
+    nb = nu.copy()
+    nb[iF] -= burn
+    nb[iO] -= 2.0 * burn
+    nb[iC] += burn
+    nb[iW] += 2.0 * burn
+    Yb = nb * W[:, None]
+    Y = (1.0 - c) * Yu + c * Yb
+    major = np.zeros(K, dtype=bool)
+    major[[iF, iO, iC, iW, mech.index("N2"), mech.index("AR")]] = True
+    lo, hi = np.log(minor[0]), np.log(minor[1])
+    Y[~major] = np.exp(rng.uniform(lo, hi, size=(int((~major).sum()), n)))
+    Y /= Y.sum(axis=0, keepdims=True)
+    return {"T": T, "p": p, "Y": np.ascontiguousarray(Y), "phi": phi, "c": c}
+
