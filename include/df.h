@@ -74,7 +74,9 @@ typedef struct {
     double h_min;      /* smallest sub-step [s], default 1e-20 */
     int32_t max_steps; /* attempted sub-steps per cell and call, default 100000 */
     int32_t mapping;   /* work mapping of the static schedule: 0 (default) automatic, 1 one cell
-                          per lane, 2 sixteen lanes per cell (species count <= 15) */
+                          per lane, 2 sixteen lanes per cell (species count <= 15), 3 one
+                          wavefront (64 lanes) per cell (species count <= 63); automatic takes
+                          16 lanes where compiled, else one cell per lane, else a wavefront */
     int32_t schedule;  /* 0 (default) or 1: static, one launch that gives each lane (or group of
                           16 lanes) one cell; 2: persistent work queue (needs the workspace):
                           cells sorted by estimated cost (temperature, then step length) are

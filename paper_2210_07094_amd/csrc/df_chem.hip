@@ -56,6 +56,7 @@ df_status launch_chem_step(const MechDev &m, const StepArgs &a, int mapping, con
     if (a.n == 0) return DF_OK;
     // mapping 0 picks 16 lanes per cell whenever a kernel is compiled for K: one sub-step
     // then takes a fraction of the latency, which bounds a stiff cell's step time
+    if (mapping == 3) return launch_chem_wave(m, a, cidx, dcount, stream);
     if (mapping == 2 || (mapping == 0 && chem_coop_supported(m)))
         return launch_chem_coop(m, a, CellQueue{cidx, dcount, nullptr, nullptr, nullptr, 0}, stream);
     if (a.n > int64_t(64) * 0x7fffffff) return fail(DF_E_UNSUPPORTED, "df_chem_step: too many cells for one launch");
@@ -66,6 +67,7 @@ df_status launch_chem_step(const MechDev &m, const StepArgs &a, int mapping, con
         DF_CHEM_SPECIES_LIST(DF_CASE)
 #undef DF_CASE
         default:
+            if (mapping == 0 && chem_wave_supported(m)) return launch_chem_wave(m, a, cidx, dcount, stream);
             return fail(DF_E_UNSUPPORTED, "df_chem_step: no compiled kernel for " + std::to_string(m.K) + " species");
     }
 }

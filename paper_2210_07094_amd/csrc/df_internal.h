@@ -57,6 +57,11 @@ struct MechDev {
     const int *cli;      // [16][kCoopList] per-lane list: index into the per-cell rate array
     const double *clc;   // [16][kCoopList] per-lane list: coefficient
     const int *src;      // [M] mechanism-file index of stored reaction j
+    // per-species reaction lists of the one-wave-per-cell kernel (CSR over the coop rows):
+    // species k takes part in rows wlj[e] with net coefficient wlc[e], wlo[k] <= e < wlo[k + 1]
+    const int *wlo;      // [K + 1]
+    const int *wlj;      // [nnz]
+    const double *wlc;   // [nnz]
 };
 
 struct HostMech {
@@ -155,6 +160,12 @@ df_status launch_chem_step(const MechDev &m, const StepArgs &a, int mapping, con
                            const int32_t *dcount, hipStream_t stream);
 
 df_status validate_chem_opts(const df_chem_opts &o);
+
+// one-wave-per-cell integrator (df_chem_wave.hip): mechanisms of up to 63 species with a
+// compiled instantiation; cidx/dcount as launch_chem_step
+bool chem_wave_supported(const MechDev &m);
+df_status launch_chem_wave(const MechDev &m, const StepArgs &a, const int32_t *cidx, const int32_t *dcount,
+                           hipStream_t stream);
 
 // cooperative integrator (df_chem_coop.hip): 16 lanes per cell, for the species counts and
 // table sizes it is instantiated for

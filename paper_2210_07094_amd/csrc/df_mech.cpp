@@ -208,8 +208,8 @@ static void pack_tables(const HostMech &m, const std::vector<int> &order, std::v
 // ln k_r = ln k_f + ln(1/K_c) is one dot product, and so is sum_k nu_k H_k/(R T).
 struct CoopTables {
     int RPL = 1, MP = 16, lmax = 0;
-    std::vector<double> cr, ceff, ceffw, clc;
-    std::vector<int> ci, cli;
+    std::vector<double> cr, ceff, ceffw, clc, wlc;
+    std::vector<int> ci, cli, wlo, wlj;
 };
 
 static void pack_coop_tables(const HostMech &m, const std::vector<int> &order, CoopTables &t) {
@@ -294,6 +294,21 @@ static void pack_coop_tables(const HostMech &m, const std::vector<int> &order, C
     // species lanes 1..K sum nu q over their reactions, lane 0 sums the 16 partial enthalpy sums
     t.lmax = 0;
     for (auto &l : lists) t.lmax = std::max<int>(t.lmax, int(l.size()));
+    // the same lists as CSR for the one-wave-per-cell kernel
+    t.wlo.assign(size_t(K) + 1, 0);
+    t.wlj.clear();
+    t.wlc.clear();
+    for (int k = 0; k < K; ++k) {
+        for (auto &e : lists[k]) {
+            t.wlj.push_back(e.first);
+            t.wlc.push_back(double(e.second));
+        }
+        t.wlo[size_t(k) + 1] = int(t.wlj.size());
+    }
+    if (t.wlj.empty()) {  // keep every table part non-empty
+        t.wlj.push_back(0);
+        t.wlc.push_back(0.0);
+    }
     t.cli.assign(size_t(kCoopLanes) * kCoopList, MP);
     t.clc.assign(size_t(kCoopLanes) * kCoopList, 0.0);
     for (int e = 0; e < kCoopList; ++e) {
@@ -309,10 +324,10 @@ static void pack_coop_tables(const HostMech &m, const std::vector<int> &order, C
 
 df_status validate_chem_opts(const df_chem_opts &o) {
     if (!(o.rtol > 0 && o.rtol < 1) || !(o.atol_T > 0) || !(o.atol_Y > 0) || !(o.h_min > 0) || o.max_steps < 1 ||
-        o.mapping < 0 || o.mapping > 2 || o.schedule < 0 || o.schedule > 2 || o.coop_blocks < -1 ||
+        o.mapping < 0 || o.mapping > 3 || o.schedule < 0 || o.schedule > 2 || o.coop_blocks < -1 ||
         !std::isfinite(o.atol_T) || !std::isfinite(o.atol_Y) || !std::isfinite(o.h_min))
         return fail(DF_E_INVALID, "df_chem_opts: need 0 < rtol < 1, atol_T, atol_Y, h_min > 0 and finite, "
-                                  "max_steps >= 1, mapping in {0, 1, 2}, schedule in {0, 1, 2}, coop_blocks >= -1");
+                                  "max_steps >= 1, mapping in {0, 1, 2, 3}, schedule in {0, 1, 2}, coop_blocks >= -1");
     return DF_OK;
 }
 
@@ -369,7 +384,9 @@ df_status df_mech_load(const char *path, int32_t device, df_mech **out) {
                     {nu.data(), nu.size() * 4, 0},          {ct.cr.data(), ct.cr.size() * 8, 0},
                     {ct.ci.data(), ct.ci.size() * 4, 0},    {ct.ceff.data(), ct.ceff.size() * 8, 0},
                     {ct.ceffw.data(), ct.ceffw.size() * 8, 0}, {ct.cli.data(), ct.cli.size() * 4, 0},
-                    {ct.clc.data(), ct.clc.size() * 8, 0},  {order.data(), order.size() * 4, 0}};
+                    {ct.clc.data(), ct.clc.size() * 8, 0},  {order.data(), order.size() * 4, 0},
+                    {ct.wlo.data(), ct.wlo.size() * 4, 0},  {ct.wlj.data(), ct.wlj.size() * 4, 0},
+                    {ct.wlc.data(), ct.wlc.size() * 8, 0}};
     size_t total = 0;
     for (auto &q : parts) {
         q.off = total;
@@ -413,6 +430,9 @@ df_status df_mech_load(const char *path, int32_t device, df_mech **out) {
     m->dev.cli = I(9);
     m->dev.clc = D(10);
     m->dev.src = I(11);
+    m->dev.wlo = I(12);
+    m->dev.wlj = I(13);
+    m->dev.wlc = D(14);
     *out = m;
     return DF_OK;
 }
