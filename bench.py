@@ -27,6 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 MECH = os.path.join(ROOT, "synth", "data", "h2_synth_9sp_24r.mech")
+HC_MECH = os.path.join(ROOT, "synth", "data", "hc_synth_53sp_325r.mech")
 DNN_W = os.path.join(ROOT, "paper_2210_07094_amd", "data", "h2_dnn_1600_800_400.dfdnn")
 DT = 1e-6
 
@@ -308,6 +309,59 @@ def training_study(gm, dnn_path, mech_h, dev):
                          "frac": tflops / PEAK_BF16_TFLOPS}}
 
 
+def large_mechanism_study(dev, with_cpu, threads, n=65536):
+    """The 53-species / 325-reaction hydrocarbon mechanism on one wavefront per cell: one
+    chemistry step (dt = 1 us) of n cells of the hydrocarbon field recipe (T 300-2400 K,
+    p 1-10 atm, CH4/air unburnt/product blend with log-uniform minor species).  FLOPs are the
+    method's algorithmic lane-ops per attempt for this mechanism times the attempts the step
+    made (an FMA counts 2).  The oracle is timed on 16 cells spread over the temperature range."""
+    import torch
+    import synth
+    import paper_2210_07094_amd as df
+    from synth import fields
+    mech = synth.read_mech(HC_MECH)
+    gm = df.Mechanism(HC_MECH)
+    f = fields.hydrocarbon_field(mech, n=n)
+    T0 = torch.tensor(f["T"], device=dev)
+    p = torch.tensor(f["p"], device=dev)
+    Y0 = torch.tensor(f["Y"], device=dev)
+    st = torch.zeros(n, dtype=torch.int32, device=dev)
+    ns = torch.zeros(2 * n, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    w = 2048
+    gm.chem_step(T0[:w].clone(), p[:w], Y0[:, :w].clone(), DT)   # first launch
+    T, Y = T0.clone(), Y0.clone()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    gm.chem_step(T, p, Y, DT, status=st, n_steps=ns, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    nsn = ns.cpu().numpy()
+    attempts = int(nsn.sum())
+    ops = integrator_lane_ops(mech)
+    tflops = 2.0 * ops["per_attempt"] * attempts / (ms * 1e-3) / 1e12
+    out = {"workload": f"hydrocarbon field recipe, {n} cells, 53 species / 325 reactions (seeded), dt = 1 us, "
+                       "one wavefront per cell",
+           "n_cells": n, "ms": ms, "cells_per_s": n / (ms * 1e-3), "attempts": attempts,
+           "attempts_per_s": attempts / (ms * 1e-3), "accepted_mean": float(nsn[:n].mean()),
+           "accepted_max": int(nsn[:n].max()), "status_counts": np.bincount(st.cpu().numpy()).tolist(),
+           "roofline": {"bound": "alu", "kernel": "chem_wave_kernel<53> (FP64 VALU, one wavefront per cell)",
+                        "achieved": tflops, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                        "frac": tflops / PEAK_FP64_TFLOPS, "lane_ops_per_attempt": ops}}
+    if with_cpu:
+        import oracle
+        om = oracle.Mech(HC_MECH)
+        idx = np.argsort(f["T"])[np.linspace(0, n - 1, 16).astype(int)]
+        t1 = time.perf_counter()
+        om.chem_step(f["T"][idx], f["p"][idx], np.ascontiguousarray(f["Y"][:, idx]), DT, nthreads=threads)
+        t_cpu = time.perf_counter() - t1
+        out["cpu_oracle"] = {"value": idx.size / t_cpu, "unit": "cells/s", "cores": min(threads, idx.size),
+                             "kind": "oracle", "sample": f"16 cells spread over the temperature range ({t_cpu:.1f} s)"}
+    return out
+
+
 def rollout_study(gm, dnn, mech_h, dev):
     """The paper's 0-D checks on the synthetic mechanism, as device rollouts of 1 us steps:
     the ignition delay (largest dT/dt) against T0 for stoichiometric H2/air at 1 atm from the
@@ -386,6 +440,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the 4096-cell adjoint study")
     ap.add_argument("--no-training", action="store_true", help="skip the DNN training study")
     ap.add_argument("--no-rollout", action="store_true", help="skip the 0-D rollout study")
+    ap.add_argument("--no-large", action="store_true", help="skip the 53-species mechanism study")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported (cells are independent, "
@@ -496,6 +551,7 @@ def main():
     adjoint = None if a.no_adjoint else adjoint_study(gm, mech_h, dev, not a.no_cpu, threads)
     training = None if a.no_training else training_study(gm, DNN_W, mech_h, dev)
     rollouts = None if a.no_rollout else rollout_study(gm, dnn, mech_h, dev)
+    large = None if a.no_large else large_mechanism_study(dev, not a.no_cpu, threads)
 
     out = {
         "metric": "cells/s per chemistry step: FP64 stiff integrator vs BF16 DNN at stated error",
@@ -532,6 +588,7 @@ def main():
         "adjoint": adjoint,
         "dnn_training": training,
         "rollouts_0d": rollouts,
+        "large_mechanism": large,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

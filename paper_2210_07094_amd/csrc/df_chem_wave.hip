@@ -7,24 +7,28 @@
 // and its step-size controller are those of the one-cell-per-lane and 16-lane kernels.  What
 // changes is how one cell occupies the 64 lanes of a wave:
 //  * rates: lane t evaluates reactions t, t + 64, ... (ln k_f and ln k_r as coefficient rows
-//    over functions of T, third-body sums, Troe falloff) into per-reaction LDS arrays;
+//    over functions of T, third-body sums, Troe falloff; the tables are column-major, so the
+//    lanes' loads are contiguous) into per-reaction LDS arrays, with the Jacobian the
+//    derivative of each rate of progress with respect to the concentration in each slot;
 //  * production rates: lane 1 + k gathers species k's reactions from its list;
-//  * Jacobian: for each reaction in turn (a wave-uniform loop) the lanes take the distinct
-//    (species, species) pairs of the reaction and add its concentration derivatives to an
-//    LDS-staged N x N matrix; third-body and falloff rows add their dense efficiency terms
-//    one species row at a time; then the map to the (T, Y) variables;
+//  * Jacobian: the sparse entries are grouped by target on the host, so each lane sums whole
+//    entries of an LDS-staged N x N matrix (no two lanes write one entry); third-body and
+//    falloff rows add their dense efficiency terms one species row at a time, together with
+//    the map to the (T, Y) variables;
 //  * factorisation: lane r holds row r of W = I/(g h) - J in registers.  Gaussian elimination
 //    with partial pivoting takes the pivot row by a wave-wide arg-max and never moves a row:
 //    the pivot row is broadcast to the other lanes by readlane, and each lane remembers the
 //    step at which its row was the pivot;
 //  * solves: forward and back substitution in pivot order, one readlane broadcast per step;
 //    component k of the solution ends in lane k.
-// Wave-wide sums are butterflies over the 64 lanes: each pairing adds the same two numbers in
-// either order, so every lane ends with the same bits and the control flow stays uniform.
-// Between the LDS phases of one cell the block's barrier orders the accesses; inside the
-// per-reaction Jacobian loop, where successive updates of different lanes may add to one
-// entry, the wave's LDS operations complete in program order and a wave barrier keeps the
-// compiler from reordering them.
+// Wave-wide sums and maxima give every lane the same bits, so the control flow stays uniform.
+// The block's barrier orders the LDS phases of one cell.
+//
+// This file is compiled with the AMDGPU scheduler's max-memory-clause strategy: -O2 and -O3
+// builds of the 53-species instantiation with the default strategy returned garbage states on
+// gfx950 (every attempt rejected), while -O1, -O3 with the scheduler off or with the max-ILP or
+// max-memory-clause strategy, and a CPU build of the same source under AddressSanitizer
+// reproduced the oracle's sub-step sequences exactly.
 #include <cmath>
 
 #include "df_internal.h"
@@ -35,18 +39,6 @@ namespace {
 
 constexpr int kW = 64;
 
-__device__ __forceinline__ double wsum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kW);
-    return v;
-}
-
-__device__ __forceinline__ double wmax(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kW));
-    return v;
-}
-
 // value of v in lane l (l wave-uniform)
 __device__ __forceinline__ double rdlane(double v, int l) {
     const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
@@ -55,7 +47,40 @@ __device__ __forceinline__ double rdlane(double v, int l) {
     return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
 }
 
-__device__ __forceinline__ int popc3(int m) { return (m & 1) + ((m >> 1) & 1) + ((m >> 2) & 1); }
+// v of another lane of the same row of 16 by a DPP control (quad_perm, row_mirror, ...)
+template <int CTRL>
+__device__ __forceinline__ double dppd(double v) {
+    const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b & 0xffffffffull), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, 0xf, 0xf, false);
+    return __longlong_as_double(
+        static_cast<long long>((static_cast<unsigned long long>(static_cast<unsigned>(hi)) << 32) | static_cast<unsigned>(lo)));
+}
+
+// Wave-wide sum and maximum: within each row of 16 lanes exchange with the lane at xor 1, xor 2,
+// the mirrored lane of the half row and of the row (each pairing combines the same two numbers
+// in either order, so all 16 lanes of a row end with the same bits), then combine the four rows'
+// values read from lanes 0, 16, 32 and 48; every lane gets the same result.
+__device__ __forceinline__ double wsum(double v) {
+    v += dppd<0xb1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dppd<0x4e>(v);   // quad_perm [2, 3, 0, 1]
+    v += dppd<0x141>(v);  // row_half_mirror
+    v += dppd<0x140>(v);  // row_mirror
+    return (rdlane(v, 0) + rdlane(v, 16)) + (rdlane(v, 32) + rdlane(v, 48));
+}
+
+__device__ __forceinline__ double wmax(double v) {
+    v = fmax(v, dppd<0xb1>(v));
+    v = fmax(v, dppd<0x4e>(v));
+    v = fmax(v, dppd<0x141>(v));
+    v = fmax(v, dppd<0x140>(v));
+    return fmax(fmax(rdlane(v, 0), rdlane(v, 16)), fmax(rdlane(v, 32), rdlane(v, 48)));
+}
+
+// packed table entries: index | (coefficient + 8) << 20
+constexpr int kPad = 8 << 20;  // index 0, coefficient 0
+__device__ __forceinline__ int ent_idx(int v) { return v & 0xfffff; }
+__device__ __forceinline__ int ent_nu(int v) { return (v >> 20) - 8; }
 
 template <int K>
 struct Wave {
@@ -63,23 +88,25 @@ struct Wave {
     static_assert(N <= kW, "one wavefront holds a cell of at most 63 species");
     static constexpr int LDJ = N + 1;  // row stride of the staged Jacobian (doubles)
 
-    // LDS of one cell (doubles): staged J [N * LDJ]; concentrations [kW] (slot 0 = 1, slot
-    // 1 + k = species k, mol/cm^3); per reaction row: q, Mq kf, Mq kr, G (coefficient of the
-    // dense third-body term), S (sum_m c_m dq/dc_m), dq/dT at fixed c.
+    // LDS of one cell (doubles): area A [max(N LDJ, 3 M)] holding the staged J, or before the
+    // matrix is formed q, S (sum_m c_m dq/dc_m) and dq/dT of every reaction (q alone in f(y));
+    // concentrations [kW] (slot 0 = 1, slot 1 + k = species k, mol/cm^3); D [6 M], the
+    // derivative of q with respect to the concentration in each slot; G [M], the coefficient of
+    // a reaction's dense third-body term.
     struct Lds {
-        double *J, *c, *q, *kf, *kr, *G, *S, *dT;
+        double *J, *q, *S, *dT, *c, *D, *G;
     };
-    static size_t lds_doubles(int M) { return size_t(N) * LDJ + kW + 6 * size_t(M); }
+    __host__ __device__ static size_t area(int M) { return size_t(N) * LDJ > 3 * size_t(M) ? size_t(N) * LDJ : 3 * size_t(M); }
+    static size_t lds_doubles(int M) { return area(M) + kW + 7 * size_t(M); }
     __device__ static Lds layout(double *base, int M) {
         Lds L;
         L.J = base;
-        L.c = L.J + N * LDJ;
-        L.q = L.c + kW;
-        L.kf = L.q + M;
-        L.kr = L.kf + M;
-        L.G = L.kr + M;
-        L.S = L.G + M;
-        L.dT = L.S + M;
+        L.q = base;
+        L.S = base + M;
+        L.dT = base + 2 * M;
+        L.c = base + area(M);
+        L.D = L.c + kW;
+        L.G = L.D + 6 * M;
         return L;
     }
 
@@ -118,39 +145,42 @@ struct Wave {
     }
 
     struct Rate {
-        double q, kfM, krM, G, S, dqdT;
+        double q, G, S, dqdT, D[6];
     };
 
-    // reaction row jd at the concentrations in LDS; with D the derivative terms
-    template <bool D>
+    // reaction jd at the concentrations in LDS; with DER the derivative terms
+    template <bool DER>
     __device__ static void rate(const MechDev &m, const Lds &L, const Mix &s, int jd, Rate &o) {
-        const double *cr = m.cr + jd * kCrDbl;
-        const int *ci = m.ci + jd * kCiInt;
+        const int M = m.M;
+        const double *cr = m.wcr + jd;
+        const int *ci = m.wci + jd;
         const int type = ci[0];
-        double lf = fma(cr[1], s.lT, fma(cr[2], s.iT, cr[0]));
-        double lr = fma(cr[4], s.lT, fma(cr[5], s.iT, cr[3]));
-        lr = fma(cr[6], s.T, lr);
-        lr = fma(cr[7], s.T2, lr);
-        lr = fma(cr[8], s.T3, lr);
-        lr = fma(cr[9], s.T4, lr);
+        double lf = fma(cr[M], s.lT, fma(cr[2 * M], s.iT, cr[0]));
+        double lr = fma(cr[4 * M], s.lT, fma(cr[5 * M], s.iT, cr[3 * M]));
+        lr = fma(cr[6 * M], s.T, lr);
+        lr = fma(cr[7 * M], s.T2, lr);
+        lr = fma(cr[8 * M], s.T3, lr);
+        lr = fma(cr[9 * M], s.T4, lr);
         double Mc = 0.0;
         if (type != 0) {  // third-body concentration sum_k eff_k c_k
-            const double *ef = m.ceff + size_t(jd) * (K + 4);
+            const double *ef = m.weff + jd;
             double m0 = 0.0, m1 = 0.0;
+#pragma unroll 8
             for (int k = 0; k + 1 < K; k += 2) {
-                m0 = fma(ef[k], L.c[1 + k], m0);
-                m1 = fma(ef[k + 1], L.c[2 + k], m1);
+                m0 = fma(ef[k * M], L.c[1 + k], m0);
+                m1 = fma(ef[(k + 1) * M], L.c[2 + k], m1);
             }
-            if (K & 1) m0 = fma(ef[K - 1], L.c[K], m0);
+            if (K & 1) m0 = fma(ef[(K - 1) * M], L.c[K], m0);
             Mc = m0 + m1;
         }
         double phi = 1.0, dphiM = 0.0, dlphi = 0.0;
         if (type == 2) {
             // Lindemann form times the Troe broadening factor F (ln F folded into both
             // exponentials), phi = Pr/(1 + Pr)
-            const double e3 = exp(cr[20] * s.T), e1 = exp(cr[21] * s.T), e2 = exp(cr[22] * s.iT);
-            const double ek0 = exp(fma(cr[17], s.lT, fma(cr[18], s.iT, cr[16])));  // k0 / k_inf
-            const double al = cr[19];
+            const double c20 = cr[20 * M], c21 = cr[21 * M], c22 = cr[22 * M];
+            const double e3 = exp(c20 * s.T), e1 = exp(c21 * s.T), e2 = exp(c22 * s.iT);
+            const double ek0 = exp(fma(cr[17 * M], s.lT, fma(cr[18 * M], s.iT, cr[16 * M])));  // k0 / k_inf
+            const double al = cr[19 * M];
             const double Fc = fma(1.0 - al, e3, fma(al, e1, e2));
             const double Pr = ek0 * Mc;
             const double lFc = dlog(Fc) * kInvLn10;
@@ -166,32 +196,40 @@ struct Wave {
             lf = fma(kLn10, lF, lf);
             lr = fma(kLn10, lF, lr);
             phi = Pr * iPr1;
-            if (D) {
+            if (DER) {
                 const double gq = 2.0 * f1 * q1 * q1;
                 const double dlF_dlPr = -lFc * gq * nn * iden * iden;
                 const double dlF_dlFc = q1 - lFc * gq * (1.27 * x - 0.67 * nn) * iden * iden;
-                const double dFc = (1.0 - al) * cr[20] * e3 + al * cr[21] * e1 - cr[22] * s.iT * s.iT * e2;
-                const double dlnPr = (cr[17] - cr[18] * s.iT) * s.iT;
+                const double dFc = (1.0 - al) * c20 * e3 + al * c21 * e1 - c22 * s.iT * s.iT * e2;
+                const double dlnPr = (cr[17 * M] - cr[18 * M] * s.iT) * s.iT;
                 dlphi = (iPr1 + dlF_dlPr) * dlnPr + dlF_dlFc * fdiv(dFc, Fc);
                 dphiM = ek0 * iPr1 * (iPr1 + dlF_dlPr);
             }
         }
         const double Ef = exp(lf), Er = exp(lr);
         const double kf = Ef * phi, kr = Er * phi;
-        const double Pf = L.c[ci[1]] * L.c[ci[2]] * L.c[ci[3]];
-        const double Pb = L.c[ci[4]] * L.c[ci[5]] * L.c[ci[6]];
+        const double c0 = L.c[ci[M]], c1 = L.c[ci[2 * M]], c2 = L.c[ci[3 * M]];
+        const double d0 = L.c[ci[4 * M]], d1 = L.c[ci[5 * M]], d2 = L.c[ci[6 * M]];
+        const double Pf = c0 * c1 * c2, Pb = d0 * d1 * d2;
         const double fwd = kf * Pf, rev = kr * Pb, X = fwd - rev;
         const double Mq = (type == 1) ? Mc : 1.0;
         o.q = Mq * X;
-        if (D) {
-            const double dlf = (cr[1] - cr[2] * s.iT) * s.iT + dlphi;
-            const double dlr = (cr[4] - cr[5] * s.iT) * s.iT +
-                               fma(s.T, fma(s.T, fma(4.0 * cr[9], s.T, 3.0 * cr[8]), 2.0 * cr[7]), cr[6]) + dlphi;
+        if (DER) {
+            const double dlf = (cr[M] - cr[2 * M] * s.iT) * s.iT + dlphi;
+            const double dlr = (cr[4 * M] - cr[5 * M] * s.iT) * s.iT +
+                               fma(s.T, fma(s.T, fma(4.0 * cr[9 * M], s.T, 3.0 * cr[8 * M]), 2.0 * cr[7 * M]),
+                                   cr[6 * M]) +
+                               dlphi;
             o.dqdT = Mq * (fwd * dlf - rev * dlr);
             o.G = (type == 1) ? X : ((type == 2) ? (Ef * dphiM) * Pf - (Er * dphiM) * Pb : 0.0);
-            o.S = Mq * (cr[23] * fwd - cr[24] * rev) + Mc * o.G;
-            o.kfM = Mq * kf;
-            o.krM = Mq * kr;
+            o.S = Mq * (cr[23 * M] * fwd - cr[24 * M] * rev) + Mc * o.G;
+            const double kfM = Mq * kf, krM = Mq * kr;
+            o.D[0] = kfM * c1 * c2;
+            o.D[1] = kfM * c0 * c2;
+            o.D[2] = kfM * c0 * c1;
+            o.D[3] = -krM * d1 * d2;
+            o.D[4] = -krM * d0 * d2;
+            o.D[5] = -krM * d0 * d1;
         }
     }
 
@@ -209,7 +247,14 @@ struct Wave {
         double wd = 0.0;
         if (s.spl) {
             const int k = lane - 1;
-            for (int e = m.wlo[k]; e < m.wlo[k + 1]; ++e) wd = fma(m.wlc[e], L.q[m.wlj[e]], wd);
+            const int e1 = m.wlo2[k + 1];
+            for (int e = m.wlo2[k]; e < e1; e += 4) {
+                int v[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) v[i] = (e + i < e1) ? m.wlp[e + i] : kPad;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) wd = fma(double(ent_nu(v[i])), L.q[ent_idx(v[i])], wd);
+            }
         }
         const double rho = s.rho;
         const double hs = wsum(s.spl ? s.hRT * wd : 0.0);
@@ -220,86 +265,59 @@ struct Wave {
 
     // J = df/dy staged in LDS (row-major, stride LDJ) and f(y) in lane order
     __device__ static double jacobian(const MechDev &m, const Lds &L, double p, double y, int lane) {
+        const int M = m.M;
         Mix s;
         state(m, L, p, y, lane, s);
-        for (int e = lane; e < N * LDJ; e += kW) L.J[e] = 0.0;
         __syncthreads();
-        for (int jd = lane; jd < m.M; jd += kW) {
+        for (int jd = lane; jd < M; jd += kW) {
             Rate o;
             rate<true>(m, L, s, jd, o);
             L.q[jd] = o.q;
-            L.kf[jd] = o.kfM;
-            L.kr[jd] = o.krM;
-            L.G[jd] = o.G;
             L.S[jd] = o.S;
             L.dT[jd] = o.dqdT;
-        }
-        __syncthreads();
-        // concentration-space derivatives A_kl = sum_j nu_kj dq_j/dc_l, one reaction at a time
-        for (int jd = 0; jd < m.M; ++jd) {
-            const int *ci = m.ci + jd * kCiInt;
-            const int type = ci[0];
-            int col[kCoopEnt], msk[kCoopEnt], ne = 0;
+            L.G[jd] = o.G;
 #pragma unroll
-            for (int e = 0; e < kCoopEnt; ++e) {
-                col[e] = ci[7 + 2 * e];
-                msk[e] = ci[8 + 2 * e];
-                ne += (col[e] < K) ? 1 : 0;
-            }
-            const double kfM = L.kf[jd], krM = L.kr[jd];
-            const double c0 = L.c[ci[1]], c1 = L.c[ci[2]], c2 = L.c[ci[3]];
-            const double d0 = L.c[ci[4]], d1 = L.c[ci[5]], d2 = L.c[ci[6]];
-            // derivative of q with respect to the concentration in each slot
-            const double D0 = kfM * c1 * c2, D1 = kfM * c0 * c2, D2 = kfM * c0 * c1;
-            const double D3 = -krM * d1 * d2, D4 = -krM * d0 * d2, D5 = -krM * d0 * d1;
-            if (lane < ne * ne) {
-                const int ia = lane / ne, ib = lane - ia * ne;
-                int ck = col[0], mk = msk[0], cl = col[0], ml = msk[0];
-#pragma unroll
-                for (int e = 1; e < kCoopEnt; ++e) {
-                    ck = (ia == e) ? col[e] : ck;
-                    mk = (ia == e) ? msk[e] : mk;
-                    cl = (ib == e) ? col[e] : cl;
-                    ml = (ib == e) ? msk[e] : ml;
-                }
-                const double nuk = double(popc3(mk >> 3) - popc3(mk));
-                double v = (ml & 1) ? D0 : 0.0;
-                v += (ml & 2) ? D1 : 0.0;
-                v += (ml & 4) ? D2 : 0.0;
-                v += (ml & 8) ? D3 : 0.0;
-                v += (ml & 16) ? D4 : 0.0;
-                v += (ml & 32) ? D5 : 0.0;
-                double &Jkl = L.J[(1 + ck) * LDJ + 1 + cl];
-                Jkl = fma(nuk, v, Jkl);
-            }
-            // lanes of the next update may add to the entries just written: keep the order
-            __builtin_amdgcn_wave_barrier();
-            if (type != 0) {
-                // dense term: dq/dc_l gains eff_l G
-                const double el = (lane < K) ? L.G[jd] * m.ceff[size_t(jd) * (K + 4) + lane] : 0.0;
-                for (int e = 0; e < ne; ++e) {
-                    const double nua = double(popc3(msk[e] >> 3) - popc3(msk[e]));
-                    if (lane < K) {
-                        double &Jal = L.J[(1 + col[e]) * LDJ + 1 + lane];
-                        Jal = fma(nua, el, Jal);
-                    }
-                    __builtin_amdgcn_wave_barrier();
-                }
-            }
+            for (int i = 0; i < 6; ++i) L.D[i * M + jd] = o.D[i];
         }
         __syncthreads();
         // per species: production rate, sum_m c_m dq/dc_m and dq/dT at fixed c
         double wd = 0.0, sq = 0.0, dt = 0.0;
         if (s.spl) {
             const int k = lane - 1;
-            for (int e = m.wlo[k]; e < m.wlo[k + 1]; ++e) {
-                const int j = m.wlj[e];
-                const double nu = m.wlc[e];
-                wd = fma(nu, L.q[j], wd);
-                sq = fma(nu, L.S[j], sq);
-                dt = fma(nu, L.dT[j], dt);
+            const int e1 = m.wlo2[k + 1];
+            for (int e = m.wlo2[k]; e < e1; e += 4) {
+                int v[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) v[i] = (e + i < e1) ? m.wlp[e + i] : kPad;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int j = ent_idx(v[i]);
+                    const double nu = double(ent_nu(v[i]));
+                    wd = fma(nu, L.q[j], wd);
+                    sq = fma(nu, L.S[j], sq);
+                    dt = fma(nu, L.dT[j], dt);
+                }
             }
         }
+        __syncthreads();
+        for (int e = lane; e < N * LDJ; e += kW) L.J[e] = 0.0;
+        __syncthreads();
+        // concentration-space derivatives A_kl = sum_j nu_kj dq_j/dc_l: whole entries per lane
+        for (int r = 0; r < m.wnr; ++r) {
+            const int t = r * kW + lane;
+            const int *ep = m.well + m.wrb[r] + lane;
+            const int cm = m.wrc[r];
+            double acc = 0.0;
+            for (int e0 = 0; e0 < cm; e0 += 8) {
+                int v[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) v[i] = (e0 + i < cm) ? ep[(e0 + i) * kW] : kPad;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) acc = fma(double(ent_nu(v[i])), L.D[ent_idx(v[i])], acc);
+            }
+            if (t < m.wnt) L.J[m.wtk[t]] = acc;
+        }
+        __syncthreads();
         const double T = s.T;
         const double coef = (1e6 / s.rho) * s.W;
         const double gk = coef * s.Wbar * (wd - sq);
@@ -312,15 +330,29 @@ struct Wave {
         const double icp = 1.0 / s.cp;
         const double fT = -wsum(hm * fk) * icp;
         const double cf = wsum(cpm * fk);
-        // species rows in (T, Y): dc_m/dY_l = 1e-6 rho delta_ml / W_m - c_m Wbar / W_l and
-        // dc_m/dT = -c_m / T at constant pressure
+        // species rows: the dense third-body terms (dq/dc_l gains eff_l G), then the map to (T, Y)
+        // with dc_m/dY_l = 1e-6 rho delta_ml / W_m - c_m Wbar / W_l and dc_m/dT = -c_m / T at
+        // constant pressure
         const double iWl = (lane < K) ? m.sp[lane * kSpTab + 1] : 0.0;
+        const double *effl = m.ceff + ((lane < K) ? lane : 0);
         for (int k = 0; k < K; ++k) {
             const double Wk = m.sp[k * kSpTab];
             const double g = rdlane(gk, 1 + k);
             if (lane < K) {
                 double &Jkl = L.J[(1 + k) * LDJ + 1 + lane];
-                Jkl = (Wk * Jkl + g) * iWl;
+                double acc = Jkl;
+                const int e1 = m.wdo[k + 1];
+                for (int e = m.wdo[k]; e < e1; e += 4) {
+                    int v[4];
+                    double ef[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) v[i] = (e + i < e1) ? m.wdp[e + i] : kPad;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) ef[i] = effl[size_t(ent_idx(v[i])) * (K + 4)];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) acc = fma(double(ent_nu(v[i])) * L.G[ent_idx(v[i])], ef[i], acc);
+                }
+                Jkl = (Wk * acc + g) * iWl;
             }
         }
         if (s.spl) L.J[lane * LDJ] = coef * (dt + (wd - sq) * s.iT);

@@ -62,6 +62,27 @@ struct MechDev {
     const int *wlo;      // [K + 1]
     const int *wlj;      // [nnz]
     const double *wlc;   // [nnz]
+    // column-major copies for the one-wave-per-cell kernel (field f of stored reaction j at f M + j)
+    const double *wcr;   // [kCrDbl][M]
+    const int *wci;      // [7][M] type, slots
+    const double *weff;  // [K][M] third-body efficiencies (zero for plain rows)
+    // its Jacobian's sparse entries: target t (LDS offset wtk[t] = (1 + k)(K + 2) + 1 + l) is the
+    // sum over its entries of nu D[idx], D[s M + j] the derivative of q_j with respect to the
+    // concentration in slot s; targets go in rounds of 64, one per lane, and entry e of the lane
+    // of target 64 r + l is well[wrb[r] + 64 e + l], e < wrc[r] (padding has nu = 0).  Entries
+    // are packed idx | (nu + 8) << 20.
+    int wnt, wnr;
+    const int *wtk;      // [wnt]
+    const int *well;
+    const int *wrb;      // [wnr]
+    const int *wrc;      // [wnr]
+    // the per-species reaction lists packed (j, nu), species k at wlo2[k] <= e < wlo2[k + 1]
+    const int *wlo2;     // [K + 1]
+    const int *wlp;
+    // the dense third-body terms: row k gains sum over wdo[k] <= e < wdo[k + 1] of
+    // nu G_j eff_jl, (j, nu) packed in wdp[e]
+    const int *wdo;      // [K + 1]
+    const int *wdp;
 };
 
 struct HostMech {

@@ -322,6 +322,109 @@ static void pack_coop_tables(const HostMech &m, const std::vector<int> &order, C
         }
 }
 
+// Tables of the one-wave-per-cell kernel (layout in df_internal.h), from the coop rows of the
+// first M stored reactions: column-major copies (lane t reads field f of reaction t at f M + t,
+// so a wave's loads are contiguous), the Jacobian's sparse entries grouped by target in rounds
+// of 64 targets, the per-species reaction lists and the third-body reactions of each species row,
+// each entry packed into one int.
+struct WaveTables {
+    std::vector<double> cr, eff;
+    std::vector<int> ci, tk, ell, rb, rc, lo, lp, dof, dp;
+};
+
+// an entry (index < 2^20, small signed coefficient) packed into one int
+static int pack_entry(int idx, int nu) { return idx | ((nu + 8) << 20); }
+
+static void pack_wave_tables(const HostMech &m, const CoopTables &ct, WaveTables &w) {
+    const int K = m.K, M = m.M, KE = K + 4, LDJ = K + 2;
+    w.cr.assign(size_t(kCrDbl) * M, 0.0);
+    w.ci.assign(size_t(7) * M, 0);
+    w.eff.assign(size_t(K) * M, 0.0);
+    for (int jd = 0; jd < M; ++jd) {
+        for (int f = 0; f < kCrDbl; ++f) w.cr[size_t(f) * M + jd] = ct.cr[size_t(jd) * kCrDbl + f];
+        for (int f = 0; f < 7; ++f) w.ci[size_t(f) * M + jd] = ct.ci[size_t(jd) * kCiInt + f];
+        for (int k = 0; k < K; ++k) w.eff[size_t(k) * M + jd] = ct.ceff[size_t(jd) * KE + k];
+    }
+    // sparse part: J(1 + k, 1 + l) = sum over reactions jd containing k and l of
+    // nu_k(jd) * (derivative of q_jd with respect to the concentration in each slot holding l)
+    std::vector<std::vector<std::pair<int, int>>> ent(size_t(K) * K);
+    for (int jd = 0; jd < M; ++jd) {
+        const int *ri = &ct.ci[size_t(jd) * kCiInt];
+        for (int a = 0; a < kCoopEnt; ++a) {
+            const int k = ri[7 + 2 * a];
+            if (k >= K) continue;
+            const int mk = ri[8 + 2 * a];
+            int nuk = 0;
+            for (int s = 0; s < 6; ++s)
+                if (mk & (1 << s)) nuk += (s < 3) ? -1 : 1;
+            for (int b = 0; b < kCoopEnt; ++b) {
+                const int l = ri[7 + 2 * b];
+                if (l >= K) continue;
+                const int ml = ri[8 + 2 * b];
+                for (int s = 0; s < 6; ++s)
+                    if (ml & (1 << s)) ent[size_t(k) * K + l].push_back({s * M + jd, nuk});
+            }
+        }
+    }
+    // targets in rounds of 64 (one per lane); a round's entries column-major (entry e of lane l
+    // at rb[r] + 64 e + l), padded with coefficient-0 entries to the round's longest list rc[r]
+    std::vector<const std::vector<std::pair<int, int>> *> lt;
+    w.tk.clear();
+    for (int k = 0; k < K; ++k)
+        for (int l = 0; l < K; ++l) {
+            const auto &e = ent[size_t(k) * K + l];
+            if (e.empty()) continue;
+            w.tk.push_back((1 + k) * LDJ + 1 + l);
+            lt.push_back(&e);
+        }
+    const int NT = int(w.tk.size());
+    w.ell.clear();
+    w.rb.clear();
+    w.rc.clear();
+    for (int r = 0; r * 64 < NT; ++r) {
+        int cm = 0;
+        for (int l = 0; l < 64 && r * 64 + l < NT; ++l) cm = std::max<int>(cm, int(lt[r * 64 + l]->size()));
+        w.rb.push_back(int(w.ell.size()));
+        w.rc.push_back(cm);
+        for (int e = 0; e < cm; ++e)
+            for (int l = 0; l < 64; ++l) {
+                const int t = r * 64 + l;
+                const bool has = t < NT && e < int(lt[t]->size());
+                w.ell.push_back(has ? pack_entry((*lt[t])[e].first, (*lt[t])[e].second) : pack_entry(0, 0));
+            }
+    }
+    // the per-species reaction lists, packed (reaction, nu)
+    w.lo = ct.wlo;
+    w.lp.clear();
+    for (size_t e = 0; e < ct.wlj.size(); ++e) w.lp.push_back(pack_entry(ct.wlj[e], int(ct.wlc[e])));
+    // dense third-body part, per species row k: the third-body and falloff reactions with nu_k != 0
+    w.dof.assign(size_t(K) + 1, 0);
+    w.dp.clear();
+    for (int k = 0; k < K; ++k) {
+        for (int jd = 0; jd < M; ++jd) {
+            const int *ri = &ct.ci[size_t(jd) * kCiInt];
+            if (ri[0] == 0) continue;
+            int nuk = 0;
+            for (int s = 0; s < 6; ++s)
+                if (ri[1 + s] == 1 + k) nuk += (s < 3) ? -1 : 1;
+            if (nuk != 0) w.dp.push_back(pack_entry(jd, nuk));
+        }
+        w.dof[size_t(k) + 1] = int(w.dp.size());
+    }
+    // keep every table part non-empty
+    if (w.cr.empty()) w.cr.push_back(0.0);
+    if (w.ci.empty()) w.ci.push_back(0);
+    if (w.eff.empty()) w.eff.push_back(0.0);
+    if (w.tk.empty()) w.tk.push_back(0);
+    if (w.ell.empty()) w.ell.push_back(pack_entry(0, 0));
+    if (w.rb.empty()) {
+        w.rb.push_back(0);
+        w.rc.push_back(0);
+    }
+    if (w.lp.empty()) w.lp.push_back(pack_entry(0, 0));
+    if (w.dp.empty()) w.dp.push_back(pack_entry(0, 0));
+}
+
 df_status validate_chem_opts(const df_chem_opts &o) {
     if (!(o.rtol > 0 && o.rtol < 1) || !(o.atol_T > 0) || !(o.atol_Y > 0) || !(o.h_min > 0) || o.max_steps < 1 ||
         o.mapping < 0 || o.mapping > 3 || o.schedule < 0 || o.schedule > 2 || o.coop_blocks < -1 ||
@@ -374,6 +477,8 @@ df_status df_mech_load(const char *path, int32_t device, df_mech **out) {
     pack_tables(hm, order, sp, rx, rk, eff, nu);
     CoopTables ct;
     pack_coop_tables(hm, order, ct);
+    WaveTables wt;
+    pack_wave_tables(hm, ct, wt);
     // one allocation holding every table, each part 256-byte aligned
     struct Part {
         const void *src;
@@ -386,7 +491,12 @@ df_status df_mech_load(const char *path, int32_t device, df_mech **out) {
                     {ct.ceffw.data(), ct.ceffw.size() * 8, 0}, {ct.cli.data(), ct.cli.size() * 4, 0},
                     {ct.clc.data(), ct.clc.size() * 8, 0},  {order.data(), order.size() * 4, 0},
                     {ct.wlo.data(), ct.wlo.size() * 4, 0},  {ct.wlj.data(), ct.wlj.size() * 4, 0},
-                    {ct.wlc.data(), ct.wlc.size() * 8, 0}};
+                    {ct.wlc.data(), ct.wlc.size() * 8, 0},  {wt.cr.data(), wt.cr.size() * 8, 0},
+                    {wt.ci.data(), wt.ci.size() * 4, 0},    {wt.eff.data(), wt.eff.size() * 8, 0},
+                    {wt.tk.data(), wt.tk.size() * 4, 0},    {wt.ell.data(), wt.ell.size() * 4, 0},
+                    {wt.rb.data(), wt.rb.size() * 4, 0},    {wt.rc.data(), wt.rc.size() * 4, 0},
+                    {wt.lo.data(), wt.lo.size() * 4, 0},    {wt.lp.data(), wt.lp.size() * 4, 0},
+                    {wt.dof.data(), wt.dof.size() * 4, 0},  {wt.dp.data(), wt.dp.size() * 4, 0}};
     size_t total = 0;
     for (auto &q : parts) {
         q.off = total;
@@ -433,6 +543,19 @@ df_status df_mech_load(const char *path, int32_t device, df_mech **out) {
     m->dev.wlo = I(12);
     m->dev.wlj = I(13);
     m->dev.wlc = D(14);
+    m->dev.wcr = D(15);
+    m->dev.wci = I(16);
+    m->dev.weff = D(17);
+    m->dev.wtk = I(18);
+    m->dev.well = I(19);
+    m->dev.wrb = I(20);
+    m->dev.wrc = I(21);
+    m->dev.wlo2 = I(22);
+    m->dev.wlp = I(23);
+    m->dev.wdo = I(24);
+    m->dev.wdp = I(25);
+    m->dev.wnr = int(wt.rb.size());
+    m->dev.wnt = m->dev.wnr > 0 && wt.rc[0] > 0 ? int(wt.tk.size()) : 0;
     *out = m;
     return DF_OK;
 }
