@@ -350,6 +350,33 @@ def large_mechanism_study(dev, with_cpu, threads, n=65536):
            "roofline": {"bound": "alu", "kernel": "chem_wave_kernel<53> (FP64 VALU, one wavefront per cell)",
                         "achieved": tflops, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                         "frac": tflops / PEAK_FP64_TFLOPS, "lane_ops_per_attempt": ops}}
+    # the DNN form at this size: a 55-3200-1600-800-53 BF16 network with seeded weights (no
+    # trained network exists for this mechanism), its training box around the field
+    import tempfile
+    from synth import dnnfile
+    with tempfile.TemporaryDirectory() as tmp:
+        path = os.path.join(tmp, "hc.dfdnn")
+        dnnfile.write_seeded_network(path, mech.n_species, f["T"], f["p"], f["Y"], (3200, 1600, 800), seed=3)
+        dnn = df.DNN(path, gm)
+    ws = dnn.workspace(n)
+    std = torch.zeros(n, dtype=torch.int32, device=dev)
+    T, Y = T0.clone(), Y0.clone()
+    dnn.step(T, p, Y, DT, status=std, workspace=ws, stream=stream)
+    reps = 5
+    e0.record(stream)
+    for _ in range(reps):
+        T.copy_(T0)
+        Y.copy_(Y0)
+        dnn.step(T, p, Y, DT, status=std, workspace=ws, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_dnn = e0.elapsed_time(e1) / reps
+    dflops = mlp_flops(dnn.dims) * n
+    dt_ = dflops / (ms_dnn * 1e-3) / 1e12
+    out["bf16_dnn"] = {"network": "55-3200-1600-800-53, seeded weights", "ms": ms_dnn,
+                       "cells_per_s": n / (ms_dnn * 1e-3), "tflops": dt_, "mfma_frac": dt_ / PEAK_BF16_TFLOPS,
+                       "fallback_frac": float((std == 4).float().mean()),
+                       "speedup_vs_fp64_integrator": ms / ms_dnn}
     if with_cpu:
         import oracle
         om = oracle.Mech(HC_MECH)

@@ -399,7 +399,7 @@ df_status df_dnn_workspace_size(const df_dnn *d, int64_t n_cells, size_t *bytes)
     return DF_OK;
 }
 
-#define DF_DNN_SPECIES_LIST(X) X(2) X(4) X(9)
+#define DF_DNN_SPECIES_LIST(X) X(2) X(4) X(9) X(53)
 
 df_status df_dnn_step(const df_dnn *d, const df_mech *m, int64_t n, int64_t ld, double dt, const double *p, double *T,
                       double *Y, double *rr, int32_t *status, void *ws, size_t ws_bytes, const df_dnn_opts *opts,

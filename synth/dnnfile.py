@@ -87,3 +87,24 @@ def read_dnn(path):
         off += 4 * dims[l + 1]
     out["W"], out["b"] = Ws, bs
     return out
+
+
+def write_seeded_network(path, K, T, p, Y, hidden, seed=0, lam=0.1, dt_train=1e-6, out_scale=0.02):
+    """A DFDNN01 network with seeded random weights (no training): inputs normalised by the mean
+    and standard deviation of (T, p, BoxCox(Y)) over the given cells, He-scaled hidden layers,
+    an output layer scaled down so the increments stay small, output scale out_scale in z, and
+    a training box wide enough that every given cell is inside it.  For throughput and parity
+    work where no trained weights exist."""
+    rng = np.random.default_rng(seed)
+    z = (np.maximum(np.asarray(Y), 0.0) ** lam - 1.0) / lam
+    X = np.vstack([np.asarray(T)[None, :], np.asarray(p)[None, :], z])
+    mu_in = X.mean(axis=1)
+    sig_in = np.maximum(X.std(axis=1), 1e-6 * np.maximum(np.abs(mu_in), 1.0))
+    dims = [K + 2, *hidden, K]
+    W = [rng.normal(0, np.sqrt(2.0 / dims[l]), (dims[l + 1], dims[l])).astype(np.float32)
+         for l in range(len(dims) - 1)]
+    W[-1] *= 0.1
+    b = [rng.normal(0, 0.05, dims[l + 1]).astype(np.float32) for l in range(len(dims) - 1)]
+    lo = X.min(axis=1) - 1.0 * sig_in
+    hi = X.max(axis=1) + 1.0 * sig_in
+    write_dnn(path, W, b, K, lam, dt_train, mu_in, sig_in, np.zeros(K), np.full(K, out_scale), lo, hi)
