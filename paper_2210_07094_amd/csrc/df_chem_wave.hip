@@ -233,15 +233,46 @@ struct Wave {
         }
     }
 
+    // rate of progress of a plain (type 0) reaction: the arithmetic of rate<false> for such a row,
+    // without its branches, so that two of them can be interleaved
+    __device__ __forceinline__ static double q_plain(const MechDev &m, const Lds &L, const Mix &s, int jd) {
+        const int M = m.M;
+        const double *cr = m.wcr + jd;
+        const int *ci = m.wci + jd;
+        const double lf = fma(cr[M], s.lT, fma(cr[2 * M], s.iT, cr[0]));
+        double lr = fma(cr[4 * M], s.lT, fma(cr[5 * M], s.iT, cr[3 * M]));
+        lr = fma(cr[6 * M], s.T, lr);
+        lr = fma(cr[7 * M], s.T2, lr);
+        lr = fma(cr[8 * M], s.T3, lr);
+        lr = fma(cr[9 * M], s.T4, lr);
+        const double kf = exp(lf), kr = exp(lr);
+        const double Pf = L.c[ci[M]] * L.c[ci[2 * M]] * L.c[ci[3 * M]];
+        const double Pb = L.c[ci[4 * M]] * L.c[ci[5 * M]] * L.c[ci[6 * M]];
+        return kf * Pf - kr * Pb;
+    }
+
     // component `lane` of f(y)
     __device__ static double rhs(const MechDev &m, const Lds &L, double p, double y, int lane) {
         Mix s;
         state(m, L, p, y, lane, s);
         __syncthreads();
-        for (int jd = lane; jd < m.M; jd += kW) {
-            Rate o;
-            rate<false>(m, L, s, jd, o);
-            L.q[jd] = o.q;
+        // reactions are stored third-body and falloff rows first: once a round starts with a plain
+        // row, it and every later round are plain, and two rounds go through at once
+        const int M = m.M;
+        for (int r0 = 0; r0 < M; r0 += kW) {
+            if (r0 + kW < M && m.wci[r0] == 0) {
+                const int j0 = r0 + lane, j1 = r0 + kW + lane;
+                const int j1c = j1 < M ? j1 : M - 1;
+                const double q0 = q_plain(m, L, s, j0);
+                const double q1 = q_plain(m, L, s, j1c);
+                L.q[j0] = q0;
+                if (j1 < M) L.q[j1] = q1;
+                r0 += kW;
+            } else if (r0 + lane < M) {
+                Rate o;
+                rate<false>(m, L, s, r0 + lane, o);
+                L.q[r0 + lane] = o.q;
+            }
         }
         __syncthreads();
         double wd = 0.0;
@@ -330,29 +361,39 @@ struct Wave {
         const double icp = 1.0 / s.cp;
         const double fT = -wsum(hm * fk) * icp;
         const double cf = wsum(cpm * fk);
-        // species rows: the dense third-body terms (dq/dc_l gains eff_l G), then the map to (T, Y)
-        // with dc_m/dY_l = 1e-6 rho delta_ml / W_m - c_m Wbar / W_l and dc_m/dT = -c_m / T at
+        // species rows: the dense third-body terms (dq/dc_l gains eff_l G), over the flat list of
+        // (row, reaction) pairs in batches, the row of entry e being the number of rows 1..K-1
+        // starting at or before e; then the map to (T, Y) with
+        // dc_m/dY_l = 1e-6 rho delta_ml / W_m - c_m Wbar / W_l and dc_m/dT = -c_m / T at
         // constant pressure
         const double iWl = (lane < K) ? m.sp[lane * kSpTab + 1] : 0.0;
         const double *effl = m.ceff + ((lane < K) ? lane : 0);
+        const int row_start = (lane >= 1 && lane < K) ? m.wdo[lane] : 0x7fffffff;
+        const int nd = m.wdo[K];
+        for (int e0 = 0; e0 < nd; e0 += 8) {
+            int v[8], kr[8];
+            double ef[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int e = e0 + i;
+                v[i] = (e < nd) ? m.wdp[e] : kPad;
+                kr[i] = __popcll(__ballot(row_start <= e));
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) ef[i] = effl[size_t(ent_idx(v[i])) * (K + 4)];
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+                if (lane < K) {
+                    double &Jkl = L.J[(1 + kr[i]) * LDJ + 1 + lane];
+                    Jkl = fma(double(ent_nu(v[i])) * L.G[ent_idx(v[i])], ef[i], Jkl);
+                }
+        }
         for (int k = 0; k < K; ++k) {
             const double Wk = m.sp[k * kSpTab];
             const double g = rdlane(gk, 1 + k);
             if (lane < K) {
                 double &Jkl = L.J[(1 + k) * LDJ + 1 + lane];
-                double acc = Jkl;
-                const int e1 = m.wdo[k + 1];
-                for (int e = m.wdo[k]; e < e1; e += 4) {
-                    int v[4];
-                    double ef[4];
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) v[i] = (e + i < e1) ? m.wdp[e + i] : kPad;
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) ef[i] = effl[size_t(ent_idx(v[i])) * (K + 4)];
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) acc = fma(double(ent_nu(v[i])) * L.G[ent_idx(v[i])], ef[i], acc);
-                }
-                Jkl = (Wk * acc + g) * iWl;
+                Jkl = (Wk * Jkl + g) * iWl;
             }
         }
         if (s.spl) L.J[lane * LDJ] = coef * (dt + (wd - sq) * s.iT);
