@@ -321,7 +321,8 @@ df_status df_dnn_workspace_size(const df_dnn *dnn, int64_t n_cells, size_t *byte
  * df_chem_step; `workspace` is caller-owned device memory of at least
  * df_dnn_workspace_size bytes, 256-byte aligned.
  * Errors: DF_E_INVALID, DF_E_UNSUPPORTED (dt != the network's dt_train,
- * relative difference above 1e-12), DF_E_HIP.
+ * relative difference above 1e-12, or a species count without compiled
+ * pre- and post-processing kernels: 2, 4, 9 and 53 are compiled), DF_E_HIP.
  */
 df_status df_dnn_step(const df_dnn *dnn, const df_mech *mech, int64_t n_cells, int64_t ld, double dt,
                       const double *p, double *T, double *Y, double *rr, int32_t *cell_status, void *workspace,
