@@ -233,46 +233,15 @@ struct Wave {
         }
     }
 
-    // rate of progress of a plain (type 0) reaction: the arithmetic of rate<false> for such a row,
-    // without its branches, so that two of them can be interleaved
-    __device__ __forceinline__ static double q_plain(const MechDev &m, const Lds &L, const Mix &s, int jd) {
-        const int M = m.M;
-        const double *cr = m.wcr + jd;
-        const int *ci = m.wci + jd;
-        const double lf = fma(cr[M], s.lT, fma(cr[2 * M], s.iT, cr[0]));
-        double lr = fma(cr[4 * M], s.lT, fma(cr[5 * M], s.iT, cr[3 * M]));
-        lr = fma(cr[6 * M], s.T, lr);
-        lr = fma(cr[7 * M], s.T2, lr);
-        lr = fma(cr[8 * M], s.T3, lr);
-        lr = fma(cr[9 * M], s.T4, lr);
-        const double kf = exp(lf), kr = exp(lr);
-        const double Pf = L.c[ci[M]] * L.c[ci[2 * M]] * L.c[ci[3 * M]];
-        const double Pb = L.c[ci[4 * M]] * L.c[ci[5 * M]] * L.c[ci[6 * M]];
-        return kf * Pf - kr * Pb;
-    }
-
     // component `lane` of f(y)
     __device__ static double rhs(const MechDev &m, const Lds &L, double p, double y, int lane) {
         Mix s;
         state(m, L, p, y, lane, s);
         __syncthreads();
-        // reactions are stored third-body and falloff rows first: once a round starts with a plain
-        // row, it and every later round are plain, and two rounds go through at once
-        const int M = m.M;
-        for (int r0 = 0; r0 < M; r0 += kW) {
-            if (r0 + kW < M && m.wci[r0] == 0) {
-                const int j0 = r0 + lane, j1 = r0 + kW + lane;
-                const int j1c = j1 < M ? j1 : M - 1;
-                const double q0 = q_plain(m, L, s, j0);
-                const double q1 = q_plain(m, L, s, j1c);
-                L.q[j0] = q0;
-                if (j1 < M) L.q[j1] = q1;
-                r0 += kW;
-            } else if (r0 + lane < M) {
-                Rate o;
-                rate<false>(m, L, s, r0 + lane, o);
-                L.q[r0 + lane] = o.q;
-            }
+        for (int jd = lane; jd < m.M; jd += kW) {
+            Rate o;
+            rate<false>(m, L, s, jd, o);
+            L.q[jd] = o.q;
         }
         __syncthreads();
         double wd = 0.0;
