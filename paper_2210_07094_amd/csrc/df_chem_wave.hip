@@ -149,18 +149,38 @@ struct Wave {
     };
 
     // reaction jd at the concentrations in LDS; with DER the derivative terms
+    // the table fields every reaction needs, loaded ahead of the arithmetic
+    struct Pre {
+        double a[10];
+        int type, sl[6];
+    };
+    __device__ __forceinline__ static void pre_load(const MechDev &m, int jd, Pre &pr) {
+        const int M = m.M;
+#pragma unroll
+        for (int f = 0; f < 10; ++f) pr.a[f] = m.wcr[f * M + jd];
+        pr.type = m.wci[jd];
+#pragma unroll
+        for (int f = 0; f < 6; ++f) pr.sl[f] = m.wci[(1 + f) * M + jd];
+    }
+
     template <bool DER>
     __device__ static void rate(const MechDev &m, const Lds &L, const Mix &s, int jd, Rate &o) {
+        Pre pr;
+        pre_load(m, jd, pr);
+        rate_from<DER>(m, L, s, jd, pr, o);
+    }
+
+    template <bool DER>
+    __device__ static void rate_from(const MechDev &m, const Lds &L, const Mix &s, int jd, const Pre &pr, Rate &o) {
         const int M = m.M;
         const double *cr = m.wcr + jd;
-        const int *ci = m.wci + jd;
-        const int type = ci[0];
-        double lf = fma(cr[M], s.lT, fma(cr[2 * M], s.iT, cr[0]));
-        double lr = fma(cr[4 * M], s.lT, fma(cr[5 * M], s.iT, cr[3 * M]));
-        lr = fma(cr[6 * M], s.T, lr);
-        lr = fma(cr[7 * M], s.T2, lr);
-        lr = fma(cr[8 * M], s.T3, lr);
-        lr = fma(cr[9 * M], s.T4, lr);
+        const int type = pr.type;
+        double lf = fma(pr.a[1], s.lT, fma(pr.a[2], s.iT, pr.a[0]));
+        double lr = fma(pr.a[4], s.lT, fma(pr.a[5], s.iT, pr.a[3]));
+        lr = fma(pr.a[6], s.T, lr);
+        lr = fma(pr.a[7], s.T2, lr);
+        lr = fma(pr.a[8], s.T3, lr);
+        lr = fma(pr.a[9], s.T4, lr);
         double Mc = 0.0;
         if (type != 0) {  // third-body concentration sum_k eff_k c_k
             const double *ef = m.weff + jd;
@@ -208,17 +228,16 @@ struct Wave {
         }
         const double Ef = exp(lf), Er = exp(lr);
         const double kf = Ef * phi, kr = Er * phi;
-        const double c0 = L.c[ci[M]], c1 = L.c[ci[2 * M]], c2 = L.c[ci[3 * M]];
-        const double d0 = L.c[ci[4 * M]], d1 = L.c[ci[5 * M]], d2 = L.c[ci[6 * M]];
+        const double c0 = L.c[pr.sl[0]], c1 = L.c[pr.sl[1]], c2 = L.c[pr.sl[2]];
+        const double d0 = L.c[pr.sl[3]], d1 = L.c[pr.sl[4]], d2 = L.c[pr.sl[5]];
         const double Pf = c0 * c1 * c2, Pb = d0 * d1 * d2;
         const double fwd = kf * Pf, rev = kr * Pb, X = fwd - rev;
         const double Mq = (type == 1) ? Mc : 1.0;
         o.q = Mq * X;
         if (DER) {
-            const double dlf = (cr[M] - cr[2 * M] * s.iT) * s.iT + dlphi;
-            const double dlr = (cr[4 * M] - cr[5 * M] * s.iT) * s.iT +
-                               fma(s.T, fma(s.T, fma(4.0 * cr[9 * M], s.T, 3.0 * cr[8 * M]), 2.0 * cr[7 * M]),
-                                   cr[6 * M]) +
+            const double dlf = (pr.a[1] - pr.a[2] * s.iT) * s.iT + dlphi;
+            const double dlr = (pr.a[4] - pr.a[5] * s.iT) * s.iT +
+                               fma(s.T, fma(s.T, fma(4.0 * pr.a[9], s.T, 3.0 * pr.a[8]), 2.0 * pr.a[7]), pr.a[6]) +
                                dlphi;
             o.dqdT = Mq * (fwd * dlf - rev * dlr);
             o.G = (type == 1) ? X : ((type == 2) ? (Ef * dphiM) * Pf - (Er * dphiM) * Pb : 0.0);
@@ -238,10 +257,19 @@ struct Wave {
         Mix s;
         state(m, L, p, y, lane, s);
         __syncthreads();
-        for (int jd = lane; jd < m.M; jd += kW) {
-            Rate o;
-            rate<false>(m, L, s, jd, o);
-            L.q[jd] = o.q;
+        // the next round's table fields are loaded before this round's arithmetic
+        {
+            const int M = m.M;
+            Pre cur, nxt;
+            pre_load(m, lane < M ? lane : M - 1, cur);
+            for (int jd = lane; jd < M; jd += kW) {
+                const int jn = jd + kW;
+                pre_load(m, jn < M ? jn : M - 1, nxt);
+                Rate o;
+                rate_from<false>(m, L, s, jd, cur, o);
+                L.q[jd] = o.q;
+                cur = nxt;
+            }
         }
         __syncthreads();
         double wd = 0.0;
