@@ -96,26 +96,37 @@ __global__ __launch_bounds__(kPreThreads) void post_kernel(DnnDevParams prm, Mec
                                                            int32_t *__restrict__ status, int renormalise) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n || flag[i] != 1) return;
-    // ---- output layer: u = W h + b, fp32 accumulation
+    // ---- output layer: u = W h + b, fp32 accumulation, each output summed over the inputs in
+    // order; the outputs go in blocks of 8 so that their accumulators stay in registers
+    constexpr int KB = 8;
     float u[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) u[k] = 0.0f;
     const bf16_t *hr = h + i * int64_t(h_ld);
-    for (int j = 0; j < k_in; j += 8) {
-        const uint4 v = *reinterpret_cast<const uint4 *>(hr + j);
-        const unsigned w4[4] = {v.x, v.y, v.z, v.w};
-        float a[8];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            a[2 * q] = __uint_as_float(w4[q] << 16);
-            a[2 * q + 1] = __uint_as_float(w4[q] & 0xffff0000u);
+    for (int k0 = 0; k0 < K; k0 += KB) {
+        float acc[KB];
+#pragma unroll
+        for (int kk = 0; kk < KB; ++kk) acc[kk] = 0.0f;
+        for (int j = 0; j < k_in; j += 8) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(hr + j);
+            const unsigned w4[4] = {v.x, v.y, v.z, v.w};
+            float a[8];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                a[2 * q] = __uint_as_float(w4[q] << 16);
+                a[2 * q + 1] = __uint_as_float(w4[q] & 0xffff0000u);
+            }
+#pragma unroll
+            for (int kk = 0; kk < KB; ++kk) {
+                if (k0 + kk < K) {
+                    const bf16_t *wr = W + int64_t(k0 + kk) * k_in + j;
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) acc[kk] = fmaf(bf2f(wr[q]), a[q], acc[kk]);
+                }
+            }
         }
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const bf16_t *wr = W + int64_t(k) * k_in + j;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) u[k] = fmaf(bf2f(wr[q]), a[q], u[k]);
-        }
+        for (int kk = 0; kk < KB; ++kk)
+            if (k0 + kk < K) u[k0 + kk] = acc[kk];
     }
     // ---- stage 3, FP64
     const double T0 = T[i];
