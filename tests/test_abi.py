@@ -84,3 +84,15 @@ def test_adjoint_host_checks(L):
     assert L.df_chem_adjoint(None, 1, 1, None, None, 0, 10, None, None, None, None, None, None, None, 0, None) \
         == _lib.DF_E_INVALID
     assert b"null mechanism" in L.df_last_error()
+
+
+def test_const_volume_and_rollout_host_checks(L):
+    o = df.chem_opts()
+    assert L.df_chem_step_const_volume(None, 1, 1, 1e-6, None, None, None, None, None, None, C.byref(o), None) \
+        == _lib.DF_E_INVALID
+    assert b"null mechanism" in L.df_last_error()
+    b = C.c_size_t()
+    assert L.df_rollout_workspace_size(None, None, 1, C.byref(b)) == _lib.DF_E_INVALID
+    assert L.df_rollout(None, None, 1, 1, 1e-6, 10, 0, None, None, None, None, None, None, 0, None, None) \
+        == _lib.DF_E_INVALID
+    assert b"null mechanism" in L.df_last_error()
