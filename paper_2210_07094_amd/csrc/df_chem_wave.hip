@@ -275,8 +275,8 @@ struct Wave {
         double wd = 0.0;
         if (s.spl) {
             const int k = lane - 1;
-            const int e1 = m.wlo2[k + 1];
-            for (int e = m.wlo2[k]; e < e1; e += 4) {
+            const int e1 = m.wlo[k + 1];
+            for (int e = m.wlo[k]; e < e1; e += 4) {
                 int v[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) v[i] = (e + i < e1) ? m.wlp[e + i] : kPad;
@@ -312,8 +312,8 @@ struct Wave {
         double wd = 0.0, sq = 0.0, dt = 0.0;
         if (s.spl) {
             const int k = lane - 1;
-            const int e1 = m.wlo2[k + 1];
-            for (int e = m.wlo2[k]; e < e1; e += 4) {
+            const int e1 = m.wlo[k + 1];
+            for (int e = m.wlo[k]; e < e1; e += 4) {
                 int v[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) v[i] = (e + i < e1) ? m.wlp[e + i] : kPad;

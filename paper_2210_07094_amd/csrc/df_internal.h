@@ -57,11 +57,6 @@ struct MechDev {
     const int *cli;      // [16][kCoopList] per-lane list: index into the per-cell rate array
     const double *clc;   // [16][kCoopList] per-lane list: coefficient
     const int *src;      // [M] mechanism-file index of stored reaction j
-    // per-species reaction lists of the one-wave-per-cell kernel (CSR over the coop rows):
-    // species k takes part in rows wlj[e] with net coefficient wlc[e], wlo[k] <= e < wlo[k + 1]
-    const int *wlo;      // [K + 1]
-    const int *wlj;      // [nnz]
-    const double *wlc;   // [nnz]
     // column-major copies for the one-wave-per-cell kernel (field f of stored reaction j at f M + j)
     const double *wcr;   // [kCrDbl][M]
     const int *wci;      // [7][M] type, slots
@@ -76,8 +71,8 @@ struct MechDev {
     const int *well;
     const int *wrb;      // [wnr]
     const int *wrc;      // [wnr]
-    // the per-species reaction lists packed (j, nu), species k at wlo2[k] <= e < wlo2[k + 1]
-    const int *wlo2;     // [K + 1]
+    // the per-species reaction lists packed (j, nu), species k at wlo[k] <= e < wlo[k + 1]
+    const int *wlo;     // [K + 1]
     const int *wlp;
     // the dense third-body terms: row k gains sum over wdo[k] <= e < wdo[k + 1] of
     // nu G_j eff_jl, (j, nu) packed in wdp[e]

@@ -294,7 +294,7 @@ static void pack_coop_tables(const HostMech &m, const std::vector<int> &order, C
     // species lanes 1..K sum nu q over their reactions, lane 0 sums the 16 partial enthalpy sums
     t.lmax = 0;
     for (auto &l : lists) t.lmax = std::max<int>(t.lmax, int(l.size()));
-    // the same lists as CSR for the one-wave-per-cell kernel
+    // the same lists as CSR (packed for the one-wave-per-cell kernel by pack_wave_tables)
     t.wlo.assign(size_t(K) + 1, 0);
     t.wlj.clear();
     t.wlc.clear();
@@ -505,8 +505,7 @@ df_status df_mech_load(const char *path, int32_t device, df_mech **out) {
                     {ct.ci.data(), ct.ci.size() * 4, 0},    {ct.ceff.data(), ct.ceff.size() * 8, 0},
                     {ct.ceffw.data(), ct.ceffw.size() * 8, 0}, {ct.cli.data(), ct.cli.size() * 4, 0},
                     {ct.clc.data(), ct.clc.size() * 8, 0},  {order.data(), order.size() * 4, 0},
-                    {ct.wlo.data(), ct.wlo.size() * 4, 0},  {ct.wlj.data(), ct.wlj.size() * 4, 0},
-                    {ct.wlc.data(), ct.wlc.size() * 8, 0},  {wt.cr.data(), wt.cr.size() * 8, 0},
+                    {wt.cr.data(), wt.cr.size() * 8, 0},
                     {wt.ci.data(), wt.ci.size() * 4, 0},    {wt.eff.data(), wt.eff.size() * 8, 0},
                     {wt.tk.data(), wt.tk.size() * 4, 0},    {wt.ell.data(), wt.ell.size() * 4, 0},
                     {wt.rb.data(), wt.rb.size() * 4, 0},    {wt.rc.data(), wt.rc.size() * 4, 0},
@@ -555,20 +554,17 @@ df_status df_mech_load(const char *path, int32_t device, df_mech **out) {
     m->dev.cli = I(9);
     m->dev.clc = D(10);
     m->dev.src = I(11);
-    m->dev.wlo = I(12);
-    m->dev.wlj = I(13);
-    m->dev.wlc = D(14);
-    m->dev.wcr = D(15);
-    m->dev.wci = I(16);
-    m->dev.weff = D(17);
-    m->dev.wtk = I(18);
-    m->dev.well = I(19);
-    m->dev.wrb = I(20);
-    m->dev.wrc = I(21);
-    m->dev.wlo2 = I(22);
-    m->dev.wlp = I(23);
-    m->dev.wdo = I(24);
-    m->dev.wdp = I(25);
+    m->dev.wcr = D(12);
+    m->dev.wci = I(13);
+    m->dev.weff = D(14);
+    m->dev.wtk = I(15);
+    m->dev.well = I(16);
+    m->dev.wrb = I(17);
+    m->dev.wrc = I(18);
+    m->dev.wlo = I(19);
+    m->dev.wlp = I(20);
+    m->dev.wdo = I(21);
+    m->dev.wdp = I(22);
     m->dev.wnr = int(wt.rb.size());
     m->dev.wnt = m->dev.wnr > 0 && wt.rc[0] > 0 ? int(wt.tk.size()) : 0;
     *out = m;
