@@ -90,15 +90,18 @@ struct Wave {
 
     // LDS of one cell (doubles): area A [max(N LDJ, 3 M)] holding the staged J, or before the
     // matrix is formed q, S (sum_m c_m dq/dc_m) and dq/dT of every reaction (q alone in f(y));
-    // concentrations [kW] (slot 0 = 1, slot 1 + k = species k, mol/cm^3); D [6 M], the
-    // derivative of q with respect to the concentration in each slot; G [M], the coefficient of
-    // a reaction's dense third-body term.
+    // concentrations [kW] (slot 0 = 1, slot 1 + k = species k, mol/cm^3); D [(wsr + wsp) M], the
+    // derivative of q with respect to the concentration in each slot in use; G [M], the
+    // coefficient of a reaction's dense third-body term.
     struct Lds {
         double *J, *q, *S, *dT, *c, *D, *G;
     };
     __host__ __device__ static size_t area(int M) { return size_t(N) * LDJ > 3 * size_t(M) ? size_t(N) * LDJ : 3 * size_t(M); }
-    static size_t lds_doubles(int M) { return area(M) + kW + 7 * size_t(M); }
-    __device__ static Lds layout(double *base, int M) {
+    static size_t lds_doubles(const MechDev &m) {
+        return area(m.M) + kW + size_t(m.wsr + m.wsp + 1) * size_t(m.M);
+    }
+    __device__ static Lds layout(double *base, const MechDev &m) {
+        const int M = m.M;
         Lds L;
         L.J = base;
         L.q = base;
@@ -106,7 +109,7 @@ struct Wave {
         L.dT = base + 2 * M;
         L.c = base + area(M);
         L.D = L.c + kW;
-        L.G = L.D + 6 * M;
+        L.G = L.D + (m.wsr + m.wsp) * M;
         return L;
     }
 
@@ -304,8 +307,13 @@ struct Wave {
             L.S[jd] = o.S;
             L.dT[jd] = o.dqdT;
             L.G[jd] = o.G;
+            // the slot derivatives of the slots in use
 #pragma unroll
-            for (int i = 0; i < 6; ++i) L.D[i * M + jd] = o.D[i];
+            for (int i = 0; i < 3; ++i)
+                if (i < m.wsr) L.D[i * M + jd] = o.D[i];
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                if (i < m.wsp) L.D[(m.wsr + i) * M + jd] = o.D[3 + i];
         }
         __syncthreads();
         // per species: production rate, sum_m c_m dq/dc_m and dq/dT at fixed c
@@ -473,7 +481,7 @@ __global__ __launch_bounds__(kW) void chem_wave_kernel(MechDev m, StepArgs a, co
     const int64_t limit = dcount ? int64_t(*dcount) : a.n;
     if (slot >= limit) return;
     const int64_t i = cidx ? int64_t(cidx[slot]) : slot;
-    const typename Wv::Lds L = Wv::layout(lds, m.M);
+    const typename Wv::Lds L = Wv::layout(lds, m);
     const Opts &o = a.o;
 
     const double p = a.p[i];
@@ -597,7 +605,7 @@ __global__ __launch_bounds__(kW) void chem_wave_kernel(MechDev m, StepArgs a, co
 
 template <int K>
 size_t wave_lds_bytes(const MechDev &m) {
-    return 8 * Wave<K>::lds_doubles(m.M);
+    return 8 * Wave<K>::lds_doubles(m);
 }
 
 template <int K>

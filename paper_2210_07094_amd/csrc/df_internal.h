@@ -62,11 +62,14 @@ struct MechDev {
     const int *wci;      // [7][M] type, slots
     const double *weff;  // [K][M] third-body efficiencies (zero for plain rows)
     // its Jacobian's sparse entries: target t (LDS offset wtk[t] = (1 + k)(K + 2) + 1 + l) is the
-    // sum over its entries of nu D[idx], D[s M + j] the derivative of q_j with respect to the
-    // concentration in slot s; targets go in rounds of 64, one per lane, and entry e of the lane
+    // sum over its entries of nu D[idx], D[r M + j] the derivative of q_j with respect to the
+    // concentration in the slot of D row r; targets go in rounds of 64, one per lane, and entry e of the lane
     // of target 64 r + l is well[wrb[r] + 64 e + l], e < wrc[r] (padding has nu = 0).  Entries
     // are packed idx | (nu + 8) << 20.
     int wnt, wnr;
+    // slots in use: reactant slots 0..wsr-1 and product slots 3..3+wsp-1 (the slot derivatives
+    // D hold wsr + wsp rows: slot s < 3 in row s, slot 3 + s in row wsr + s)
+    int wsr, wsp;
     const int *wtk;      // [wnt]
     const int *well;
     const int *wrb;      // [wnr]

@@ -330,6 +330,7 @@ static void pack_coop_tables(const HostMech &m, const std::vector<int> &order, C
 struct WaveTables {
     std::vector<double> cr, eff;
     std::vector<int> ci, tk, ell, rb, rc, lo, lp, dof, dp;
+    int sr = 0, sp = 0;  // reactant and product slots in use
 };
 
 // an entry (index < 2^20, small signed coefficient) packed into one int
@@ -347,6 +348,15 @@ static void pack_wave_tables(const HostMech &m, const CoopTables &ct, WaveTables
     }
     // sparse part: J(1 + k, 1 + l) = sum over reactions jd containing k and l of
     // nu_k(jd) * (derivative of q_jd with respect to the concentration in each slot holding l)
+    // slots in use (reactant slots fill 0, 1, 2 and product slots 3, 4, 5 in order); the slot
+    // derivatives keep one row per slot in use
+    w.sr = w.sp = 0;
+    for (int jd = 0; jd < M; ++jd)
+        for (int s = 0; s < 3; ++s) {
+            if (ct.ci[size_t(jd) * kCiInt + 1 + s] != 0) w.sr = std::max(w.sr, s + 1);
+            if (ct.ci[size_t(jd) * kCiInt + 4 + s] != 0) w.sp = std::max(w.sp, s + 1);
+        }
+    auto drow = [&](int s) { return s < 3 ? s : w.sr + (s - 3); };
     std::vector<std::vector<std::pair<int, int>>> ent(size_t(K) * K);
     for (int jd = 0; jd < M; ++jd) {
         const int *ri = &ct.ci[size_t(jd) * kCiInt];
@@ -362,7 +372,7 @@ static void pack_wave_tables(const HostMech &m, const CoopTables &ct, WaveTables
                 if (l >= K) continue;
                 const int ml = ri[8 + 2 * b];
                 for (int s = 0; s < 6; ++s)
-                    if (ml & (1 << s)) ent[size_t(k) * K + l].push_back({s * M + jd, nuk});
+                    if (ml & (1 << s)) ent[size_t(k) * K + l].push_back({drow(s) * M + jd, nuk});
             }
         }
     }
@@ -566,6 +576,8 @@ df_status df_mech_load(const char *path, int32_t device, df_mech **out) {
     m->dev.wdo = I(21);
     m->dev.wdp = I(22);
     m->dev.wnr = int(wt.rb.size());
+    m->dev.wsr = wt.sr;
+    m->dev.wsp = wt.sp;
     m->dev.wnt = m->dev.wnr > 0 && wt.rc[0] > 0 ? int(wt.tk.size()) : 0;
     *out = m;
     return DF_OK;
