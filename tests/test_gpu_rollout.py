@@ -127,3 +127,26 @@ def test_rollout_edges(h2_path, h2_mech):
     e = torch.zeros(0, dtype=torch.float64, device=d)
     idt0, _ = gm.rollout(e, e, torch.zeros(h2_mech.n_species, 0, dtype=torch.float64, device=d), DT, 5)
     assert idt0.numel() == 0
+
+
+def test_rollout_large_mechanism():
+    """df_rollout through the one-wavefront-per-cell integrator (53 species, sub-step hints carried
+    from step to step) against the oracle's rollout: 6 hydrocarbon cells, 20 steps of 1 us."""
+    import synth
+    import paper_2210_07094_amd as df
+    torch = _torch()
+    path = os.path.join(ROOT, "synth", "data", "hc_synth_53sp_325r.mech")
+    mech = synth.read_mech(path)
+    om = oracle.Mech(path)
+    gm = df.Mechanism(path)
+    f = fields.hydrocarbon_field(mech, n=256)
+    idx = np.argsort(f["T"])[np.linspace(0, 200, 6).astype(int)]
+    T0, p0, Y0 = f["T"][idx], f["p"][idx], np.ascontiguousarray(f["Y"][:, idx])
+    d = "cuda:0"
+    T, Y = torch.tensor(T0, device=d), torch.tensor(Y0, device=d)
+    steps = 20
+    _, traj = gm.rollout(T, torch.tensor(p0, device=d), Y, DT, steps, trajectory=True)
+    traj_o, Y_o, _ = ro.integrator_rollout(om, T0, p0, Y0, DT, steps, nthreads=6)
+    assert np.max(np.abs(traj.cpu().numpy() - traj_o) / traj_o) < 1e-7
+    mask = Y_o > 1e-10
+    assert np.max(np.abs(Y.cpu().numpy() - Y_o)[mask] / Y_o[mask]) < 1e-6
