@@ -174,8 +174,9 @@ df_status df_chem_step_cells(const df_mech *mech, int64_t n_cells, int64_t ld, c
  *   dY_k/dt = W_k wdot_k / rho,  dT/dt = -sum_k U_k wdot_k / (rho cv),
  * U_k = H_k - R T, cv = cp - R / Wbar; the mixture internal energy is conserved.
  *   rho         [n]      in      density per cell [kg/m^3]
- *   T, Y, h_inout, cell_status, n_steps, opts: as df_chem_step (one cell per lane; opts.mapping
- *               and opts.schedule are ignored)
+ *   T, Y, h_inout, cell_status, n_steps, opts: as df_chem_step (one cell per lane for the
+ *               species counts with that kernel, else one wavefront per cell for up to 63
+ *               species; opts.mapping and opts.schedule are ignored)
  * A cell whose rho or T is not positive and finite, or whose Y is not finite, is left untouched
  * with DF_CELL_NONFINITE.  Errors: DF_E_INVALID, DF_E_UNSUPPORTED, DF_E_HIP.
  */

@@ -4,7 +4,8 @@
 //   dY_k/dt = W_k wdot_k / rho,  dT/dt = -sum_k U_k wdot_k / (rho cv),
 // with U_k = H_k - R T the molar internal energy and cv = cp - R / Wbar; the pressure follows
 // the state (p = rho R T / Wbar).  The per-lane RODAS4 solver is the constant-pressure one with
-// its constant-volume thermodynamics (Cell<K, true>).
+// its constant-volume thermodynamics (Cell<K, true>); species counts without a per-lane kernel
+// go to the one-wavefront-per-cell kernel's constant-volume instantiation (df_chem_wave.hip).
 //
 // This file is compiled on its own, with the machine instruction scheduler off: optimised
 // builds of this instantiation with the scheduler on produced wrong sub-steps on gfx950
@@ -18,6 +19,11 @@
 #include "df_lane.h"
 
 namespace df {
+// the constant-volume reactor on one wavefront per cell (df_chem_wave.hip), for species counts
+// without a one-cell-per-lane kernel; a.p holds the density
+bool chem_wave_supported(const MechDev &m);
+df_status launch_chem_wave_cv(const MechDev &m, const StepArgs &a, hipStream_t stream);
+
 namespace {
 
 template <int K>
@@ -79,8 +85,11 @@ extern "C" df_status df_chem_step_const_volume(const df_mech *mech, int64_t n_ce
         DF_CHEM_SPECIES_LIST(DF_CASE)
 #undef DF_CASE
         default:
-            st = fail(DF_E_UNSUPPORTED,
-                      std::string(who) + ": no compiled kernel for " + std::to_string(mech->dev.K) + " species");
+            if (chem_wave_supported(mech->dev))
+                st = launch_chem_wave_cv(mech->dev, a, s);
+            else
+                st = fail(DF_E_UNSUPPORTED,
+                          std::string(who) + ": no compiled kernel for " + std::to_string(mech->dev.K) + " species");
     }
     if (prev != mech->device) (void)hipSetDevice(prev);
     return st;

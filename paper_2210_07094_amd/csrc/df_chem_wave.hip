@@ -82,7 +82,9 @@ constexpr int kPad = 8 << 20;  // index 0, coefficient 0
 __device__ __forceinline__ int ent_idx(int v) { return v & 0xfffff; }
 __device__ __forceinline__ int ent_nu(int v) { return (v >> 20) - 8; }
 
-template <int K>
+// CV: the constant-volume reactor (density given where the pressure is otherwise, internal
+// energies and cv in the energy equation, concentrations independent of T and Wbar)
+template <int K, bool CV = false>
 struct Wave {
     static constexpr int N = K + 1;
     static_assert(N <= kW, "one wavefront holds a cell of at most 63 species");
@@ -142,8 +144,8 @@ struct Wave {
         const double sYW = wsum(s.Yk * s.iW);
         const double cpm = wsum(s.Yk * s.cpR * s.iW);
         s.Wbar = 1.0 / sYW;
-        s.rho = p * s.Wbar * s.iT * (1.0 / kR);
-        s.cp = cpm * kR;
+        s.rho = CV ? p : p * s.Wbar * s.iT * (1.0 / kR);
+        s.cp = CV ? (cpm - sYW) * kR : cpm * kR;
         L.c[lane] = (lane == 0) ? 1.0 : 1e-6 * s.rho * s.Yk * s.iW;
     }
 
@@ -288,7 +290,7 @@ struct Wave {
             }
         }
         const double rho = s.rho;
-        const double hs = wsum(s.spl ? s.hRT * wd : 0.0);
+        const double hs = wsum(s.spl ? (CV ? s.hRT - 1.0 : s.hRT) * wd : 0.0);  // U/RT = H/RT - 1
         __syncthreads();
         if (lane == 0) return -hs * (1e6 * kR) * s.T / (rho * s.cp);
         return s.spl ? (1e6 / rho) * s.W * wd : 0.0;
@@ -356,10 +358,11 @@ struct Wave {
         __syncthreads();
         const double T = s.T;
         const double coef = (1e6 / s.rho) * s.W;
-        const double gk = coef * s.Wbar * (wd - sq);
+        // at constant pressure c depends on T and Wbar; at constant volume it does not
+        const double gk = CV ? 0.0 : coef * s.Wbar * (wd - sq);
         const double fk = s.spl ? coef * wd : 0.0;
-        const double hm = s.spl ? s.hRT * kR * T * s.iW : 0.0;   // J/kg
-        const double cpm = s.spl ? s.cpR * kR * s.iW : 0.0;      // J/kg/K
+        const double hm = s.spl ? (CV ? s.hRT - 1.0 : s.hRT) * kR * T * s.iW : 0.0;  // J/kg: h_k, or u_k
+        const double cpm = s.spl ? (CV ? s.cpR - 1.0 : s.cpR) * kR * s.iW : 0.0;     // J/kg/K: cp_k, or cv_k
         const double *r = s.sr;
         const double dcpR = r[3] + T * (r[16] + T * (r[17] + T * r[18]));
         const double dcpdT = wsum(s.spl ? s.Yk * dcpR * kR * s.iW : 0.0);
@@ -401,7 +404,7 @@ struct Wave {
                 Jkl = (Wk * Jkl + g) * iWl;
             }
         }
-        if (s.spl) L.J[lane * LDJ] = coef * (dt + (wd - sq) * s.iT);
+        if (s.spl) L.J[lane * LDJ] = CV ? coef * dt : coef * (dt + (wd - sq) * s.iT);
         __syncthreads();
         // temperature row: f_T = -sum_k h_k f_k / cp
         double acc = 0.0;
@@ -470,10 +473,10 @@ struct Wave {
     }
 };
 
-template <int K>
+template <int K, bool CV>
 __global__ __launch_bounds__(kW) void chem_wave_kernel(MechDev m, StepArgs a, const int32_t *__restrict__ cidx,
                                                        const int32_t *__restrict__ dcount) {
-    using Wv = Wave<K>;
+    using Wv = Wave<K, CV>;
     constexpr int N = K + 1;
     extern __shared__ double lds[];
     const int lane = threadIdx.x;
@@ -588,7 +591,7 @@ __global__ __launch_bounds__(kW) void chem_wave_kernel(MechDev m, StepArgs a, co
         const double T0 = rdlane(y0, 0);
         const int k = (lane >= 1 && lane <= K) ? lane - 1 : 0;
         const double sYW = wsum((lane >= 1 && lane <= K) ? y0 * m.sp[k * kSpTab + 1] : 0.0);
-        const double rdt = p / (sYW * kR * T0) / dtc;
+        const double rdt = (CV ? p : p / (sYW * kR * T0)) / dtc;  // the density is given at constant volume
         if (lane >= 1 && lane <= K) a.rr[(lane - 1) * a.ld + i] = rdt * (y - y0);
     }
     if (lane == 0) a.T[i] = y;
@@ -608,11 +611,11 @@ size_t wave_lds_bytes(const MechDev &m) {
     return 8 * Wave<K>::lds_doubles(m);
 }
 
-template <int K>
+template <int K, bool CV = false>
 df_status launch_wave_k(const MechDev &m, const StepArgs &a, const int32_t *cidx, const int32_t *dcount,
                         hipStream_t stream) {
     const size_t lds = wave_lds_bytes<K>(m);
-    auto kernel = chem_wave_kernel<K>;
+    auto kernel = chem_wave_kernel<K, CV>;
     if (lds > 65536 &&
         hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
                             int(lds)) != hipSuccess)
@@ -656,6 +659,24 @@ df_status launch_chem_wave(const MechDev &m, const StepArgs &a, const int32_t *c
 #undef DF_CASE
         default:
             return fail(DF_E_UNSUPPORTED, "df_chem_step: no one-wave-per-cell kernel for " + std::to_string(m.K));
+    }
+}
+
+// the constant-volume reactor on one wavefront per cell (df_chem_step_const_volume for species
+// counts without a one-cell-per-lane kernel); a.p holds the density
+df_status launch_chem_wave_cv(const MechDev &m, const StepArgs &a, hipStream_t stream) {
+    if (a.n == 0) return DF_OK;
+    if (a.n > 0x7fffffff) return fail(DF_E_UNSUPPORTED, "df_chem_step_const_volume: too many cells for one launch");
+    if (!chem_wave_supported(m))
+        return fail(DF_E_UNSUPPORTED, "df_chem_step_const_volume: no kernel for " + std::to_string(m.K) + " species");
+    switch (m.K) {
+#define DF_CASE(k) \
+    case k:        \
+        return launch_wave_k<k, true>(m, a, nullptr, nullptr, stream);
+        DF_WAVE_SPECIES_LIST(DF_CASE)
+#undef DF_CASE
+        default:
+            return fail(DF_E_UNSUPPORTED, "df_chem_step_const_volume: no kernel for " + std::to_string(m.K));
     }
 }
 

@@ -95,3 +95,33 @@ def test_internal_energy_conserved_full_field(h2_path, h2_mech, h2_oracle, npche
     gs = {k: (v[:, sample] if v.ndim == 2 else v[sample]) for k, v in g.items()}
     worst, flipped, tol_err = compare(gs, o)
     assert worst <= 1e-8 and flipped <= 3 and tol_err <= 10.0
+
+
+def test_parity_large_mechanism():
+    """The 53-species mechanism at constant volume (one wavefront per cell): 48 cells of the
+    hydrocarbon field spread over the temperature range, at the parity bar, and the mixture
+    internal energy conserved on every cell."""
+    import os
+    import oracle
+    import synth
+    import paper_2210_07094_amd as df
+    from npchem import NpChem
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    path = os.path.join(root, "synth", "data", "hc_synth_53sp_325r.mech")
+    mech, om, gm = synth.read_mech(path), oracle.Mech(path), df.Mechanism(path)
+    npc = NpChem(mech)
+    g = fields.hydrocarbon_field(mech, n=512)
+    idx = np.argsort(g["T"])[np.linspace(0, 511, 48).astype(int)]
+    f = {"T": g["T"][idx].copy(), "p": g["p"][idx].copy(), "Y": np.ascontiguousarray(g["Y"][:, idx])}
+    W = np.asarray(mech.molar_mass) * 1e-3
+    rho = f["p"] / (R * f["T"] * np.sum(f["Y"] / W[:, None], axis=0))
+    out = _run(gm, f, rho, 1e-6, ld=50)
+    o = om.chem_step_v(f["T"], rho, f["Y"], 1e-6, h_inout=np.zeros(48), nthreads=16)
+    assert np.all(o["status"] == 0) and np.array_equal(out["status"], o["status"])
+    worst, flipped, tol_err = compare(out, o)
+    assert worst <= 1e-8 and flipped <= 3 and tol_err <= 10.0, (worst, flipped, tol_err)
+    for i in range(48):
+        u0 = npc.u_mass(f["T"][i], f["Y"][:, i])
+        u1 = npc.u_mass(out["T"][i], out["Y"][:, i])
+        cv = np.sum(out["Y"][:, i] * (npc.cp_R(out["T"][i]) - 1.0) * R / npc.W)
+        assert abs(u1 - u0) <= 10 * 1e-8 * cv * out["T"][i]
