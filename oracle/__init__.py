@@ -93,6 +93,11 @@ def lib():
     L.orc_bf16_round.restype = C.c_float
     L.orc_bf16_round.argtypes = [C.c_float]
     L.orc_mlp_forward.argtypes = [vp, dp, dp, C.c_int]
+    L.orc_fp8_e4m3_round.restype = C.c_double
+    L.orc_fp8_e4m3_round.argtypes = [C.c_double]
+    L.orc_fp8_scale_exp.restype = C.c_int
+    L.orc_fp8_scale_exp.argtypes = [C.c_double]
+    L.orc_mlp_forward_fp8.argtypes = [vp, C.c_int64, dp, dp]
     L.orc_T_from_h.restype = C.c_int
     L.orc_T_from_h.argtypes = [vp, C.c_double, dp, C.c_double, dp]
     L.orc_dnn_step.restype = C.c_int
@@ -289,6 +294,16 @@ def bf16_round(x):
     return lib().orc_bf16_round(float(x))
 
 
+def fp8_e4m3_round(x):
+    """Nearest OCP E4M3FN value (ties to even); NaN where that exceeds 448."""
+    return lib().orc_fp8_e4m3_round(float(x))
+
+
+def fp8_scale_exp(amax):
+    """Smallest e with amax <= 448 * 2**e (0 for amax 0)."""
+    return lib().orc_fp8_scale_exp(float(amax))
+
+
 class DNN:
     def __init__(self, path):
         self.path = str(path)
@@ -317,6 +332,13 @@ class DNN:
         u = np.zeros(self.dims[-1])
         lib().orc_mlp_forward(self._h, _dp(x), _dp(u), int(mode))
         return u
+
+    def mlp_fp8(self, X_norm):
+        """Batched forward with FP8 hidden-to-hidden layers; X_norm is n x n_in."""
+        X = np.ascontiguousarray(X_norm, dtype=np.float64)
+        U = np.zeros((X.shape[0], self.dims[-1]))
+        lib().orc_mlp_forward_fp8(self._h, X.shape[0], _dp(X), _dp(U))
+        return U
 
     def step(self, mech: Mech, T, p, Y, dt, renormalise=True, mode=1, fallback=True, want_rr=False, opts=None,
              nthreads=0):

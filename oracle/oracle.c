@@ -1142,6 +1142,98 @@ void orc_mlp_forward(const orc_dnn *d, const double *x_norm, double *u, int mode
     free(z);
 }
 
+/* ---- FP8 inference (OCP 8-bit floating point, E4M3FN variant) ----------------
+ * E4M3FN: 1 sign bit, 4 exponent bits with bias 7, 3 mantissa bits, no infinities;
+ * the largest finite magnitude is 1.75 * 2^8 = 448, normal numbers start at 2^-6
+ * and the subnormal spacing is 2^-9.  Rounding is to nearest, ties to even. */
+double orc_fp8_e4m3_round(double x) {
+    if (!isfinite(x)) return NAN;
+    double a = fabs(x);
+    if (a == 0.0) return x;
+    int e2;
+    frexp(a, &e2);             /* a = f * 2^e2, f in [0.5, 1): floor(log2 a) = e2 - 1 */
+    int E = e2 - 1;
+    if (E < -6) E = -6;        /* below the normal range the spacing stays 2^-9 */
+    double q = ldexp(1.0, E - 3);
+    double r = nearbyint(a / q) * q; /* a / q is exact; nearbyint rounds ties to even */
+    if (r > 448.0) return NAN; /* rounds beyond the format (not reached for scaled values) */
+    return copysign(r, x);
+}
+
+/* smallest e with amax <= 448 * 2^e, so that amax * 2^-e lies in the E4M3FN range; 0 for amax 0 */
+int orc_fp8_scale_exp(double amax) {
+    if (!(amax > 0.0)) return 0;
+    int e = 0;
+    while (amax > ldexp(448.0, e)) ++e;
+    while (amax <= ldexp(448.0, e - 1)) --e;
+    return e;
+}
+
+/* Batched forward with the hidden-to-hidden layers in FP8: layer l (1 <= l <= L-2) quantises its
+ * input activations with one power-of-two scale for the whole batch (from the largest magnitude
+ * over all n rows) and each weight row with its own power-of-two scale, sums the exact products of
+ * the quantised values, and undoes both scales before the bias and GELU.  The first layer and the
+ * output layer are those of mode 1 (bf16 values, fp32 sums); every hidden activation is rounded
+ * to bf16.  xn: n x n_in (a zero row for a cell the network does not predict); u: n x n_out. */
+void orc_mlp_forward_fp8(const orc_dnn *d, int64_t n, const double *xn, double *u) {
+    int maxw = 0;
+    for (int l = 0; l <= d->L; ++l) if (d->dims[l] > maxw) maxw = d->dims[l];
+    double *A = malloc(sizeof(double) * (size_t)n * maxw), *B = malloc(sizeof(double) * (size_t)n * maxw);
+    for (int64_t i = 0; i < n; ++i)
+        for (int c = 0; c < d->n_in; ++c) A[i * d->n_in + c] = (double)orc_bf16_round((float)xn[i * d->n_in + c]);
+    for (int l = 0; l < d->L; ++l) {
+        const int ni = d->dims[l], no = d->dims[l + 1];
+        const int fp8 = (l >= 1 && l <= d->L - 2);
+        int ea = 0;
+        double *wq = NULL;
+        int *ew = NULL;
+        if (fp8) {
+            double amax = 0.0;
+            for (int64_t j = 0; j < n * ni; ++j) amax = fmax(amax, fabs(A[j]));
+            ea = orc_fp8_scale_exp(amax);
+            for (int64_t j = 0; j < n * ni; ++j) A[j] = orc_fp8_e4m3_round(ldexp(A[j], -ea));
+            wq = malloc(sizeof(double) * (size_t)no * ni);
+            ew = malloc(sizeof(int) * no);
+            for (int o = 0; o < no; ++o) {
+                const double *w = &d->W[l][(size_t)o * ni];
+                double wmax = 0.0;
+                for (int c = 0; c < ni; ++c) wmax = fmax(wmax, fabs(w[c]));
+                ew[o] = orc_fp8_scale_exp(wmax);
+                for (int c = 0; c < ni; ++c) wq[(size_t)o * ni + c] = orc_fp8_e4m3_round(ldexp(w[c], -ew[o]));
+            }
+        }
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            const double *a = &A[i * ni];
+            for (int o = 0; o < no; ++o) {
+                double z;
+                if (fp8) {
+                    double acc = 0.0;
+                    for (int c = 0; c < ni; ++c) acc += a[c] * wq[(size_t)o * ni + c];
+                    z = ldexp(acc, ea + ew[o]) + d->b[l][o];
+                } else {
+                    const double *w = &d->W[l][(size_t)o * ni];
+                    float acc = 0.0f;
+                    for (int c = 0; c < ni; ++c) acc = acc + (float)w[c] * (float)a[c];
+                    acc = acc + (float)d->b[l][o];
+                    z = acc;
+                }
+                if (l < d->L - 1)
+                    B[i * no + o] = (double)orc_bf16_round((float)gelu(z));
+                else
+                    u[i * no + o] = z;
+            }
+        }
+        free(wq);
+        free(ew);
+        double *t = A;
+        A = B;
+        B = t;
+    }
+    free(A);
+    free(B);
+}
+
 /* Newton on T -> h(T, Y) - h_target with dh/dT = cp */
 int orc_T_from_h(const orc_mech *m, double h_target, const double *Y, double T_guess, double *T_out) {
     double T = T_guess;
@@ -1169,6 +1261,27 @@ int orc_dnn_step(const orc_dnn *d, const orc_mech *m, int64_t n, int64_t ld, dou
 #else
     (void)nthreads;
 #endif
+    /* mode 2: the network runs on the whole batch first (its activation scales are batch-wide) */
+    double *U = NULL;
+    if (mode == 2) {
+        double *X = calloc((size_t)n * d->n_in, sizeof(double));
+        U = calloc((size_t)n * d->n_out, sizeof(double));
+        for (int64_t i = 0; i < n; ++i) {
+            double x[ORC_MAX_SPECIES + 2];
+            int ok = isfinite(T[i]) && T[i] > 0 && isfinite(p[i]) && p[i] > 0;
+            x[0] = T[i];
+            x[1] = p[i];
+            for (int k = 0; k < K; ++k) {
+                ok = ok && isfinite(Y[k * ld + i]);
+                x[2 + k] = orc_bct(Y[k * ld + i], d->lambda);
+            }
+            for (int j = 0; ok && j < d->n_in; ++j) ok = (x[j] >= d->lo[j]) && (x[j] <= d->hi[j]);
+            if (ok)
+                for (int j = 0; j < d->n_in; ++j) X[i * d->n_in + j] = (x[j] - d->mu_in[j]) / d->sig_in[j];
+        }
+        orc_mlp_forward_fp8(d, n, X, U);
+        free(X);
+    }
 #pragma omp parallel for schedule(dynamic, 16) reduction(+ : fails)
     for (int64_t i = 0; i < n; ++i) {
         double Y0[ORC_MAX_SPECIES], x[ORC_MAX_SPECIES + 2], xn[ORC_MAX_SPECIES + 2], u[ORC_MAX_SPECIES];
@@ -1208,7 +1321,10 @@ int orc_dnn_step(const orc_dnn *d, const orc_mech *m, int64_t n, int64_t ld, dou
         } else {
             for (int j = 0; j < d->n_in; ++j) xn[j] = (x[j] - d->mu_in[j]) / d->sig_in[j];
             /* stage 2: the network */
-            orc_mlp_forward(d, xn, u, mode);
+            if (mode == 2)
+                memcpy(u, &U[i * d->n_out], sizeof(double) * d->n_out);
+            else
+                orc_mlp_forward(d, xn, u, mode);
             /* stage 3: undo the normalisation and the transform, recover T from h */
             double sum = 0.0;
             for (int k = 0; k < K; ++k) {
@@ -1229,5 +1345,6 @@ int orc_dnn_step(const orc_dnn *d, const orc_mech *m, int64_t n, int64_t ld, dou
         if (status) status[i] = st;
         if (st != ORC_OK && st != ORC_DNN_FALLBACK) fails += 1;
     }
+    free(U);
     return fails;
 }

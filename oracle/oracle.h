@@ -124,10 +124,19 @@ double orc_bct_inv(double z, double lambda);
 float orc_bf16_round(float x);
 /* MLP forward on one normalised input vector; mode 0 = FP64, 1 = BF16-emulated (fp32 accumulate) */
 void orc_mlp_forward(const orc_dnn *d, const double *x_norm, double *u, int mode);
+/* nearest OCP E4M3FN value of x (ties to even); NaN where the rounded magnitude exceeds 448 or x is not finite */
+double orc_fp8_e4m3_round(double x);
+/* smallest e with amax <= 448 * 2^e (0 for amax 0): the power-of-two scale of an FP8 tensor */
+int orc_fp8_scale_exp(double amax);
+/* batched forward with the hidden-to-hidden layers in FP8 (per-batch power-of-two activation
+   scale, per-row power-of-two weight scales, exact sums); first and output layers as mode 1.
+   xn: n x n_in normalised inputs (zero rows for cells the network does not predict); u: n x n_out */
+void orc_mlp_forward_fp8(const orc_dnn *d, int64_t n, const double *xn, double *u);
 /* T from enthalpy at fixed p and composition: Newton from T_guess; returns iterations or -1 */
 int orc_T_from_h(const orc_mech *m, double h_target, const double *Y, double T_guess, double *T_out);
 /* DNN chemistry step over n cells; cells outside the training box fall back to orc_chem_step.
-   renormalise: 1 = rescale sum Y to 1; mode as orc_mlp_forward; fallback: 1 = integrate, 0 = leave. */
+   renormalise: 1 = rescale sum Y to 1; mode as orc_mlp_forward, or 2 = orc_mlp_forward_fp8 over the
+   batch; fallback: 1 = integrate, 0 = leave. */
 int orc_dnn_step(const orc_dnn *d, const orc_mech *m, int64_t n, int64_t ld, double dt, const double *p,
                  double *T, double *Y, double *rr, int32_t *status, int renormalise, int mode, int fallback,
                  const orc_opts *o, int nthreads);
