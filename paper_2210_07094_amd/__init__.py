@@ -29,7 +29,10 @@ def chem_opts(**kw) -> ChemOpts:
 def dnn_opts(**kw) -> DnnOpts:
     o = DnnOpts()
     lib().df_dnn_default_opts(C.byref(o))
+    names = {f[0] for f in DnnOpts._fields_}
     for k, v in kw.items():
+        if k not in names:
+            raise TypeError(f"dnn_opts: unknown option {k!r}")
         setattr(o, k, v)
     return o
 

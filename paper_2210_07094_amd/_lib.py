@@ -32,7 +32,7 @@ class AdamOpts(C.Structure):
 
 
 class DnnOpts(C.Structure):
-    _fields_ = [("renormalise", C.c_int32), ("fallback", C.c_int32), ("reserved0", C.c_int32),
+    _fields_ = [("renormalise", C.c_int32), ("fallback", C.c_int32), ("precision", C.c_int32),
                 ("reserved1", C.c_int32)]
 
 

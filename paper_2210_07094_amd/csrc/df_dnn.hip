@@ -3,7 +3,8 @@
 // "Chemistry Integration"):
 //   1. pre   : x = (T, p, BoxCox(Y)), training-range test, z-score, bf16
 //   2. layers: hidden layers as bf16 MFMA GEMMs with GELU (df_mlp.hip), output
-//              layer in fp32 inside the post kernel
+//              layer in fp32 inside the post kernel; with FP8 precision the layers between
+//              two hidden layers run on E4M3FN operands (df_fp8.h)
 //   3. post  : inverse normalisation and Box-Cox, optional renormalisation of Y,
 //              T from enthalpy conservation at fixed p (FP64 Newton), rr
 // Cells outside the training range are compacted into an index list and
@@ -13,6 +14,7 @@
 #include <cstring>
 #include <fstream>
 
+#include "df_fp8.h"
 #include "df_internal.h"
 
 namespace df {
@@ -31,7 +33,11 @@ __device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float(unsigne
 
 __device__ __forceinline__ double boxcox(double Y, double lam) { return (pow(fmax(Y, 0.0), lam) - 1.0) / lam; }
 
-__global__ void zero_counter(int32_t *c) { *c = 0; }
+// the fallback counter and the FP8 activation maxima that follow it
+constexpr int kMaxLayers = 15;
+__global__ void zero_words(uint32_t *w, int n) {
+    if (int(threadIdx.x) < n) w[threadIdx.x] = 0u;
+}
 
 // flags: 1 = network, 0 = fallback (out of training range), 2 = non-finite input
 template <int K>
@@ -218,6 +224,58 @@ WsLayout workspace_layout(const df_dnn *d, int64_t n) {
     return w;
 }
 
+// Device blob of a network: per layer the bf16 weights [n_pad][k_pad] and fp32 biases [n_pad],
+// the normalisation parameters, then per layer between two hidden layers the E4M3FN weights
+// [n_pad][k_pad] and their row exponents [n_pad] (int32).  Offsets follow from the widths alone.
+struct BlobLayout {
+    std::vector<size_t> W, b, w8, e8;
+    size_t prm = 0, total = 0;
+};
+
+BlobLayout blob_layout(const std::vector<DnnLayer> &layers, int n_in) {
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    const int L = int(layers.size());
+    BlobLayout bl;
+    bl.W.assign(L, 0);
+    bl.b.assign(L, 0);
+    bl.w8.assign(L, 0);
+    bl.e8.assign(L, 0);
+    size_t o = 0;
+    for (int l = 0; l < L; ++l) {
+        bl.W[l] = o;
+        o = al(o + size_t(layers[l].n_pad) * layers[l].k_pad * 2);
+        bl.b[l] = o;
+        o = al(o + size_t(layers[l].n_pad) * 4);
+    }
+    bl.prm = o;
+    o = al(o + size_t(6) * n_in * 8);
+    for (int l = 1; l + 1 < L; ++l) {
+        bl.w8[l] = o;
+        o = al(o + size_t(layers[l].n_pad) * layers[l].k_pad);
+        bl.e8[l] = o;
+        o = al(o + size_t(layers[l].n_pad) * 4);
+    }
+    bl.total = o;
+    return bl;
+}
+
+// E4M3FN byte of v, |v| <= 448: round to nearest, ties to even
+uint8_t e4m3_byte(float v) {
+    const uint8_t sgn = std::signbit(v) ? 0x80 : 0x00;
+    const float a = std::fabs(v);
+    if (!(a > 0.0f)) return sgn;
+    int k = 0;
+    (void)std::frexp(a, &k);               // a = f 2^k, f in [0.5, 1): floor(log2 a) = k - 1
+    int E = std::max(k - 1, -6);           // below 2^-6 the spacing stays 2^-9
+    int m = int(std::nearbyint(std::ldexp(a, 3 - E)));  // a / 2^(E-3), exact before rounding
+    if (E == -6 && m < 8) return uint8_t(sgn | m);     // subnormal
+    if (m == 16) {
+        m = 8;
+        ++E;
+    }
+    return uint8_t(sgn | ((E + 7) << 3) | (m - 8));
+}
+
 template <int K>
 df_status launch_dnn_k(const df_dnn *d, const df_mech *m, int64_t n, int64_t ld, double dt, const double *p,
                        double *T, double *Y, double *rr, int32_t *status, void *ws, const df_dnn_opts &o,
@@ -230,7 +288,8 @@ df_status launch_dnn_k(const df_dnn *d, const df_mech *m, int64_t n, int64_t ld,
     auto *flag = reinterpret_cast<int8_t *>(base + w.o_flag);
     auto *idx = reinterpret_cast<int32_t *>(base + w.o_idx);
     auto *cnt = reinterpret_cast<int32_t *>(base + w.o_cnt);
-    hipLaunchKernelGGL(zero_counter, dim3(1), dim3(1), 0, s, cnt);
+    auto *amax = reinterpret_cast<uint32_t *>(cnt) + 1;  // amax[l]: max |output| of hidden layer l
+    hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t *>(cnt), 1 + kMaxLayers);
     const int in_pad = d->layers[0].k_pad;
     hipLaunchKernelGGL(pre_kernel<K>, dim3(unsigned((w.n_pad + kPreThreads - 1) / kPreThreads)), dim3(kPreThreads), 0,
                        s, d->prm, n, w.n_pad, ld, p, T, Y, xb, in_pad, flag, idx, cnt, status, rr, o.fallback);
@@ -240,11 +299,27 @@ df_status launch_dnn_k(const df_dnn *d, const df_mech *m, int64_t n, int64_t ld,
     const bf16_t *in = xb;
     int in_ld = in_pad;
     const int nh = int(d->layers.size()) - 1;
+    const bool fp8 = (o.precision == 1);
+    const BlobLayout bl = fp8 ? blob_layout(d->layers, d->prm.n_in) : BlobLayout{};
+    auto *blob = static_cast<unsigned char *>(d->dev_blob);
     for (int l = 0; l < nh; ++l) {
         const DnnLayer &L = d->layers[l];
         bf16_t *out = (l % 2 == 0) ? ba : bb;
         const int out_ld = (l % 2 == 0) ? w.wa : w.wb;
-        df_status st = launch_gemm_bf16(in, in_ld, L.W, L.k_pad, L.b, out, out_ld, w.n_pad, L.n_pad, L.k_pad, true, s);
+        // layers 1..nh-1 (between two hidden layers) in FP8; the layer before one of them
+        // reduces the amax of its output
+        const bool q = fp8 && l >= 1;
+        uint32_t *amax_out = (fp8 && l + 1 < nh) ? amax + l : nullptr;
+        df_status st;
+        if (q)
+            st = launch_gemm_fp8(in, in_ld, amax + (l - 1), blob + bl.w8[l], L.k_pad,
+                                 reinterpret_cast<const int32_t *>(blob + bl.e8[l]), L.b, out, out_ld, w.n_pad,
+                                 L.n_pad, L.k_pad, amax_out, n, s);
+        else if (amax_out)
+            st = launch_gemm_bf16_amax(in, in_ld, L.W, L.k_pad, L.b, out, out_ld, w.n_pad, L.n_pad, L.k_pad, amax_out,
+                                       n, s);
+        else
+            st = launch_gemm_bf16(in, in_ld, L.W, L.k_pad, L.b, out, out_ld, w.n_pad, L.n_pad, L.k_pad, true, s);
         if (st != DF_OK) return st;
         in = out;
         in_ld = out_ld;
@@ -337,17 +412,9 @@ df_status df_dnn_load(const char *path, const df_mech *mech, int32_t device, df_
         prev_pad = Ly.n_pad;
     }
     // one device allocation
-    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
-    std::vector<size_t> offW(L), offb(L);
-    size_t o = 0;
-    for (int l = 0; l < L; ++l) {
-        offW[l] = o;
-        o = al(o + Wh[l].size() * 2);
-        offb[l] = o;
-        o = al(o + bh[l].size() * 4);
-    }
-    const size_t offP = o;
-    o = al(o + prm_h.size() * 8);
+    const BlobLayout bl = blob_layout(d->layers, ni);
+    const std::vector<size_t> &offW = bl.W, &offb = bl.b;
+    const size_t offP = bl.prm, o = bl.total;
     int prev = 0;
     if (hipGetDevice(&prev) != hipSuccess || hipSetDevice(device) != hipSuccess) {
         delete d;
@@ -362,6 +429,26 @@ df_status df_dnn_load(const char *path, const df_mech *mech, int32_t device, df_
             std::memcpy(h.data() + offb[l], bh[l].data(), bh[l].size() * 4);
         }
         std::memcpy(h.data() + offP, prm_h.data(), prm_h.size() * 8);
+        // E4M3FN copies of the weights between two hidden layers, one power-of-two scale per row
+        for (int l = 1; l + 1 < L; ++l) {
+            const DnnLayer &Ly = d->layers[l];
+            auto *e8 = reinterpret_cast<int32_t *>(h.data() + bl.e8[l]);
+            for (int r = 0; r < Ly.n_pad; ++r) {
+                const bf16_t *wr = &Wh[l][size_t(r) * Ly.k_pad];
+                auto bf = [](bf16_t x) {
+                    uint32_t u = uint32_t(x) << 16;
+                    float f;
+                    std::memcpy(&f, &u, 4);
+                    return f;
+                };
+                float wmax = 0.0f;
+                for (int c = 0; c < Ly.k_pad; ++c) wmax = std::max(wmax, std::fabs(bf(wr[c])));
+                const int e = fp8_scale_exp(wmax);
+                e8[r] = e;
+                uint8_t *q = h.data() + bl.w8[l] + size_t(r) * Ly.k_pad;
+                for (int c = 0; c < Ly.k_pad; ++c) q[c] = e4m3_byte(std::ldexp(bf(wr[c]), -e));
+            }
+        }
         e = hipMemcpy(blob, h.data(), o, hipMemcpyHostToDevice);
     }
     (void)hipSetDevice(prev);
@@ -428,9 +515,9 @@ df_status df_dnn_step(const df_dnn *d, const df_mech *m, int64_t n, int64_t ld, 
     df_dnn_opts o;
     df_dnn_default_opts(&o);
     if (opts) o = *opts;
-    if ((o.renormalise != 0 && o.renormalise != 1) || (o.fallback != 0 && o.fallback != 1) || o.reserved0 ||
-        o.reserved1)
-        return fail(DF_E_INVALID, "df_dnn_opts: renormalise and fallback must be 0 or 1, reserved 0");
+    if ((o.renormalise != 0 && o.renormalise != 1) || (o.fallback != 0 && o.fallback != 1) ||
+        (o.precision != 0 && o.precision != 1) || o.reserved1)
+        return fail(DF_E_INVALID, "df_dnn_opts: renormalise, fallback and precision must be 0 or 1, reserved 0");
     df_chem_opts fo;
     df_chem_default_opts(&fo);
     if (fallback_opts) fo = *fallback_opts;

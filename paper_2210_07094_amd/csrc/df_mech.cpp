@@ -485,7 +485,7 @@ void df_dnn_default_opts(df_dnn_opts *o) {
     if (!o) return;
     o->renormalise = 1;
     o->fallback = 1;
-    o->reserved0 = 0;
+    o->precision = 0;
     o->reserved1 = 0;
 }
 

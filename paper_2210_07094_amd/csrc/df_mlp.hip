@@ -10,6 +10,7 @@
 // A panel is fetched into that XCD's L2 once.
 #include <cmath>
 
+#include "df_fp8.h"
 #include "df_internal.h"
 
 namespace df {
@@ -42,6 +43,14 @@ __device__ __forceinline__ float gelu_grad(float x) {
 
 __device__ __forceinline__ float bf_to_f(bf16_t h) { return __uint_as_float(unsigned(h) << 16); }
 
+// wave-wide max of a non-negative float, combined into *amax (float bits; non-negative floats
+// order as their bit patterns) by one lane; all 64 lanes take part
+__device__ __forceinline__ void amax_combine(float m, uint32_t *amax) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) atomicMax(amax, __float_as_uint(m));
+}
+
 // Epilogues: inference (bias, GELU); training forward (bias, GELU, and the pre-activation
 // stored to P with C's layout); training backward (the product times GELU'(P), no bias).
 enum { kEpiGelu = 0, kEpiLinear = 1, kEpiGeluSave = 2, kEpiGeluGrad = 3 };
@@ -50,7 +59,8 @@ template <int EPI>
 __global__ __launch_bounds__(kThreads) void gemm_kernel(const bf16_t *__restrict__ A, int lda,
                                                        const bf16_t *__restrict__ B, int ldb,
                                                        const float *__restrict__ bias, bf16_t *__restrict__ C,
-                                                       int ldc, int K, int n_tiles_n, bf16_t *__restrict__ P) {
+                                                       int ldc, int K, int n_tiles_n, bf16_t *__restrict__ P,
+                                                       uint32_t *__restrict__ amax, int64_t m_valid) {
     __shared__ __attribute__((aligned(16))) bf16_t As[BM * LDK];
     __shared__ __attribute__((aligned(16))) bf16_t Bs[BN * LDK];
 
@@ -130,6 +140,7 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(const bf16_t *__restrict
     }
 
     // epilogue: lane l holds column (l % 16) and rows 4 * (l / 16) + r of each 16 x 16 tile
+    float m = 0.0f;
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
         const int col = col0 + wn * WN + j * 16 + fr;
@@ -143,10 +154,144 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(const bf16_t *__restrict
                 if (EPI == kEpiGeluSave) P[row * ldc + col] = to_bf16(v);
                 if (EPI == kEpiGelu || EPI == kEpiGeluSave) v = gelu(v);
                 if (EPI == kEpiGeluGrad) v *= gelu_grad(bf_to_f(P[row * ldc + col]));
-                C[row * ldc + col] = to_bf16(v);
+                const bf16_t h = to_bf16(v);
+                C[row * ldc + col] = h;
+                if (row < m_valid) m = fmaxf(m, fabsf(bf_to_f(h)));
             }
         }
     }
+    if (amax) amax_combine(m, amax);
+}
+
+// E4M3FN bytes of four floats (round to nearest even), clamped to the format's range first
+__device__ __forceinline__ uint32_t to_fp8x4(float a, float b, float c, float d) {
+    a = fminf(fmaxf(a, -448.0f), 448.0f);
+    b = fminf(fmaxf(b, -448.0f), 448.0f);
+    c = fminf(fmaxf(c, -448.0f), 448.0f);
+    d = fminf(fmaxf(d, -448.0f), 448.0f);
+    int v = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);  // bytes 0, 1
+    v = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, v, true);       // bytes 2, 3
+    return uint32_t(v);
+}
+
+// FP8 layer: the tiling of gemm_kernel with E4M3FN operands.  A is read as bf16 and quantised
+// while it is staged (scale 2^-e_a), the weights are E4M3FN bytes already; each 16x16x32 MFMA
+// takes 8 bytes of a row of A and of W per lane, in the lane layout of the bf16 instruction.
+constexpr int LDK8 = BK + 8;  // LDS row stride in bytes
+__global__ __launch_bounds__(kThreads) void gemm_fp8_kernel(const bf16_t *__restrict__ A, int lda,
+                                                           const uint32_t *__restrict__ amax_in,
+                                                           const uint8_t *__restrict__ W8, int ldb,
+                                                           const int32_t *__restrict__ wexp,
+                                                           const float *__restrict__ bias, bf16_t *__restrict__ C,
+                                                           int ldc, int K, int n_tiles_n,
+                                                           uint32_t *__restrict__ amax_out, int64_t m_valid) {
+    __shared__ __attribute__((aligned(16))) uint8_t As[BM * LDK8];
+    __shared__ __attribute__((aligned(16))) uint8_t Bs[BN * LDK8];
+
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int logical = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+    const int tile_m = logical / n_tiles_n, tile_n = logical % n_tiles_n;
+    const int64_t row0 = int64_t(tile_m) * BM;
+    const int col0 = tile_n * BN;
+
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    const int ea = fp8_scale_exp(__uint_as_float(*amax_in));
+    const float sa = ldexpf(1.0f, -ea);
+
+    // A: BM*BK/8 = 512 chunks of 8 bf16 (two per thread); W: BN*BK/16 = 320 chunks of 16 bytes
+    constexpr int kAChunks = BM * BK / 8, kBChunks = BN * BK / 16;
+    constexpr int kAPer = kAChunks / kThreads;
+    constexpr int kBPer = (kBChunks + kThreads - 1) / kThreads;
+    u32x4 ra[kAPer], rb[kBPer];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < kAPer; ++i) {
+            const int c = t + i * kThreads, r = c / (BK / 8), kc = c % (BK / 8);
+            ra[i] = *reinterpret_cast<const u32x4 *>(A + (row0 + r) * lda + k0 + kc * 8);
+        }
+#pragma unroll
+        for (int i = 0; i < kBPer; ++i) {
+            const int c = t + i * kThreads;
+            if (c < kBChunks) {
+                const int r = c / (BK / 16), kc = c % (BK / 16);
+                rb[i] = *reinterpret_cast<const u32x4 *>(W8 + int64_t(col0 + r) * ldb + k0 + kc * 16);
+            }
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int i = 0; i < kAPer; ++i) {
+            const int c = t + i * kThreads, r = c / (BK / 8), kc = c % (BK / 8);
+            float f[8];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                f[2 * q] = __uint_as_float(ra[i][q] << 16) * sa;
+                f[2 * q + 1] = __uint_as_float(ra[i][q] & 0xffff0000u) * sa;
+            }
+            uint2 v;
+            v.x = to_fp8x4(f[0], f[1], f[2], f[3]);
+            v.y = to_fp8x4(f[4], f[5], f[6], f[7]);
+            *reinterpret_cast<uint2 *>(As + r * LDK8 + kc * 8) = v;
+        }
+#pragma unroll
+        for (int i = 0; i < kBPer; ++i) {
+            const int c = t + i * kThreads;
+            if (c < kBChunks) {
+                const int r = c / (BK / 16), kc = c % (BK / 16);
+                uint2 lo, hi;
+                lo.x = rb[i][0];
+                lo.y = rb[i][1];
+                hi.x = rb[i][2];
+                hi.y = rb[i][3];
+                *reinterpret_cast<uint2 *>(Bs + r * LDK8 + kc * 16) = lo;
+                *reinterpret_cast<uint2 *>(Bs + r * LDK8 + kc * 16 + 8) = hi;
+            }
+        }
+    };
+
+    floatx4 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
+    load(0);
+    for (int k0 = 0; k0 < K; k0 += BK) {
+        __syncthreads();
+        store();
+        __syncthreads();
+        if (k0 + BK < K) load(k0 + BK);
+        long af[TM], bfr[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) af[i] = *reinterpret_cast<const long *>(As + (wm * WM + i * 16 + fr) * LDK8 + fk);
+#pragma unroll
+        for (int j = 0; j < TN; ++j) bfr[j] = *reinterpret_cast<const long *>(Bs + (wn * WN + j * 16 + fr) * LDK8 + fk);
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    }
+
+    float m = 0.0f;
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+        const int col = col0 + wn * WN + j * 16 + fr;
+        const float sc = ldexpf(1.0f, ea + wexp[col]), bc = bias[col];
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = row0 + wm * WM + i * 16 + (lane >> 4) * 4 + r;
+                const bf16_t h = to_bf16(gelu(acc[i][j][r] * sc + bc));
+                C[row * ldc + col] = h;
+                if (row < m_valid) m = fmaxf(m, fabsf(bf_to_f(h)));
+            }
+        }
+    }
+    if (amax_out) amax_combine(m, amax_out);
 }
 
 }  // namespace
@@ -169,20 +314,50 @@ df_status launch_gemm_bf16_epi(const bf16_t *A, int lda, const bf16_t *B, int ld
     const dim3 g = dim3(unsigned(tiles)), b = dim3(kThreads);
     switch (epi) {
         case GemmEpi::gelu:
-            hipLaunchKernelGGL(gemm_kernel<kEpiGelu>, g, b, 0, stream, A, lda, B, ldb, bias, C, ldc, K, N / BN, P);
+            hipLaunchKernelGGL(gemm_kernel<kEpiGelu>, g, b, 0, stream, A, lda, B, ldb, bias, C, ldc, K, N / BN, P, nullptr, int64_t(0));
             break;
         case GemmEpi::linear:
-            hipLaunchKernelGGL(gemm_kernel<kEpiLinear>, g, b, 0, stream, A, lda, B, ldb, bias, C, ldc, K, N / BN, P);
+            hipLaunchKernelGGL(gemm_kernel<kEpiLinear>, g, b, 0, stream, A, lda, B, ldb, bias, C, ldc, K, N / BN, P, nullptr, int64_t(0));
             break;
         case GemmEpi::gelu_save:
-            hipLaunchKernelGGL(gemm_kernel<kEpiGeluSave>, g, b, 0, stream, A, lda, B, ldb, bias, C, ldc, K, N / BN, P);
+            hipLaunchKernelGGL(gemm_kernel<kEpiGeluSave>, g, b, 0, stream, A, lda, B, ldb, bias, C, ldc, K, N / BN, P, nullptr, int64_t(0));
             break;
         case GemmEpi::gelu_grad:
-            hipLaunchKernelGGL(gemm_kernel<kEpiGeluGrad>, g, b, 0, stream, A, lda, B, ldb, bias, C, ldc, K, N / BN, P);
+            hipLaunchKernelGGL(gemm_kernel<kEpiGeluGrad>, g, b, 0, stream, A, lda, B, ldb, bias, C, ldc, K, N / BN, P, nullptr, int64_t(0));
             break;
     }
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(DF_E_HIP, std::string("gemm launch: ") + hipGetErrorString(e));
+    return DF_OK;
+}
+
+df_status launch_gemm_bf16_amax(const bf16_t *A, int lda, const bf16_t *B, int ldb, const float *bias, bf16_t *C,
+                                int ldc, int64_t M, int N, int K, uint32_t *amax, int64_t m_valid,
+                                hipStream_t stream) {
+    if (M % BM || N % BN || K % BK || lda % 8 || ldb % 8 || !amax)
+        return fail(DF_E_INVALID, "gemm: shapes must be multiples of the tile sizes");
+    if (M == 0) return DF_OK;
+    const int64_t tiles = (M / BM) * (N / BN);
+    if (tiles > 0x7fffffff) return fail(DF_E_UNSUPPORTED, "gemm: too many tiles");
+    hipLaunchKernelGGL(gemm_kernel<kEpiGelu>, dim3(unsigned(tiles)), dim3(kThreads), 0, stream, A, lda, B, ldb, bias,
+                       C, ldc, K, N / BN, static_cast<bf16_t *>(nullptr), amax, m_valid);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(DF_E_HIP, std::string("gemm launch: ") + hipGetErrorString(e));
+    return DF_OK;
+}
+
+df_status launch_gemm_fp8(const bf16_t *A, int lda, const uint32_t *amax_in, const uint8_t *W8, int ldb,
+                          const int32_t *wexp, const float *bias, bf16_t *C, int ldc, int64_t M, int N, int K,
+                          uint32_t *amax_out, int64_t m_valid, hipStream_t stream) {
+    if (M % BM || N % BN || K % BK || lda % 8 || ldb % 16 || ldb < K || !amax_in || !W8 || !wexp)
+        return fail(DF_E_INVALID, "gemm fp8: shapes must be multiples of the tile sizes");
+    if (M == 0) return DF_OK;
+    const int64_t tiles = (M / BM) * (N / BN);
+    if (tiles > 0x7fffffff) return fail(DF_E_UNSUPPORTED, "gemm fp8: too many tiles");
+    hipLaunchKernelGGL(gemm_fp8_kernel, dim3(unsigned(tiles)), dim3(kThreads), 0, stream, A, lda, amax_in, W8, ldb,
+                       wexp, bias, C, ldc, K, N / BN, amax_out, m_valid);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(DF_E_HIP, std::string("gemm fp8 launch: ") + hipGetErrorString(e));
     return DF_OK;
 }
 
