@@ -377,6 +377,25 @@ def large_mechanism_study(dev, with_cpu, threads, n=65536):
                        "cells_per_s": n / (ms_dnn * 1e-3), "tflops": dt_, "mfma_frac": dt_ / PEAK_BF16_TFLOPS,
                        "fallback_frac": float((std == 4).float().mean()),
                        "speedup_vs_fp64_integrator": ms / ms_dnn}
+    # the same network with its hidden-to-hidden layers in FP8
+    fp8_opts = df.dnn_opts(precision=1)
+    Tb, Yb = T.clone(), Y.clone()
+    T.copy_(T0)
+    Y.copy_(Y0)
+    dnn.step(T, p, Y, DT, status=std, workspace=ws, stream=stream, opts=fp8_opts)
+    torch.cuda.synchronize()
+    dY = float((Y - Yb).abs().max())
+    e0.record(stream)
+    for _ in range(reps):
+        T.copy_(T0)
+        Y.copy_(Y0)
+        dnn.step(T, p, Y, DT, status=std, workspace=ws, stream=stream, opts=fp8_opts)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_fp8 = e0.elapsed_time(e1) / reps
+    out["fp8_dnn"] = {"network": "55-3200-1600-800-53, 1600x3200 and 800x1600 layers in E4M3FN", "ms": ms_fp8,
+                      "cells_per_s": n / (ms_fp8 * 1e-3), "tflops": dflops / (ms_fp8 * 1e-3) / 1e12,
+                      "speedup_vs_bf16_dnn": ms_dnn / ms_fp8, "max_abs_dY_vs_bf16_dnn": dY}
     if with_cpu:
         import oracle
         om = oracle.Mech(HC_MECH)
@@ -551,6 +570,9 @@ def main():
 
     chem_alone = alone(lambda: gm.chem_step(Ta, p, Ya, DT, workspace=chem_ws, stream=stream), a.steps)
     dnn_alone = alone(lambda: dnn.step(Ta, p, Ya, DT, workspace=ws, stream=stream), a.steps)
+    # the FP8 variant of the DNN step (hidden-to-hidden layers in E4M3FN), alone
+    fp8_opts = df.dnn_opts(precision=1)
+    fp8_alone = alone(lambda: dnn.step(Ta, p, Ya, DT, workspace=ws, stream=stream, opts=fp8_opts), a.steps)
 
     # work actually done by the integrator (useful attempts per cell)
     ns = nsteps.cpu().numpy()
@@ -567,6 +589,9 @@ def main():
     Td2, Yd2 = T_in.clone(), Y_in.clone()
     st2 = torch.zeros(n, dtype=torch.int32, device=dev)
     dnn.step(Td2, p, Yd2, DT, status=st2, workspace=ws, opts=df.dnn_opts(renormalise=0))
+    Td3, Yd3 = T_in.clone(), Y_in.clone()
+    st3 = torch.zeros(n, dtype=torch.int32, device=dev)
+    dnn.step(Td3, p, Yd3, DT, status=st3, workspace=ws, opts=fp8_opts)
     torch.cuda.synchronize()
 
     cpu = None
@@ -591,7 +616,9 @@ def main():
                "integrator_cells_per_s": n / t_int, "dnn_cells_per_s": n / t_dnn}
         err = {"renormalised": dnn_error(f["T"], f["Y"], T_d, Y_d, ro["T"], ro["Y"], std),
                "not_renormalised": dnn_error(f["T"], f["Y"], Td2.cpu().numpy(), Yd2.cpu().numpy(), ro["T"], ro["Y"],
-                                             st2.cpu().numpy())}
+                                             st2.cpu().numpy()),
+               "fp8_renormalised": dnn_error(f["T"], f["Y"], Td3.cpu().numpy(), Yd3.cpu().numpy(), ro["T"], ro["Y"],
+                                             st3.cpu().numpy())}
         # the integrator result itself against the oracle (sampled parity at full size)
         relT = np.abs(T_c - ro["T"]) / ro["T"]
         mask = ro["Y"] > 1e-10
@@ -632,6 +659,11 @@ def main():
                          "ms_alone": dnn_alone, "mfma_frac_alone": dnn_flops / (dnn_alone * 1e-3) / 1e12 / PEAK_BF16_TFLOPS,
                          "tflops": dnn_tflops, "mfma_frac": dnn_tflops / PEAK_BF16_TFLOPS,
                          "fallback_frac": float(np.mean(std == 4)), "status_counts": np.bincount(std).tolist()},
+            "fp8_dnn": {"layers": "800x1600 and 400x800 in E4M3FN (power-of-two scales), first hidden and output "
+                                  "layer as bf16_dnn", "ms_alone": fp8_alone,
+                        "cells_per_s_alone": n / (fp8_alone * 1e-3),
+                        "tflops_alone": dnn_flops / (fp8_alone * 1e-3) / 1e12,
+                        "status_counts": np.bincount(st3.cpu().numpy()).tolist()},
         },
         "roofline": {"bound": "alu", "kernel": "chem_coop_kernel<9, 2> (FP64 VALU, 16 lanes per cell)",
                      "achieved": chem_tflops,

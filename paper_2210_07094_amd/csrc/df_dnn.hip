@@ -33,10 +33,12 @@ __device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float(unsigne
 
 __device__ __forceinline__ double boxcox(double Y, double lam) { return (pow(fmax(Y, 0.0), lam) - 1.0) / lam; }
 
-// the fallback counter and the FP8 activation maxima that follow it
+// the fallback counter and the FP8 activation maxima (kAmaxSlots words per hidden layer)
 constexpr int kMaxLayers = 15;
-__global__ void zero_words(uint32_t *w, int n) {
-    if (int(threadIdx.x) < n) w[threadIdx.x] = 0u;
+constexpr int kAmaxWords = kMaxLayers * kAmaxSlots;
+__global__ void zero_words(uint32_t *cnt, uint32_t *amax) {
+    if (threadIdx.x == 0) *cnt = 0u;
+    for (int i = int(threadIdx.x); i < kAmaxWords; i += int(blockDim.x)) amax[i] = 0u;
 }
 
 // flags: 1 = network, 0 = fallback (out of training range), 2 = non-finite input
@@ -191,7 +193,7 @@ int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
 struct WsLayout {
     int64_t n_pad;
-    size_t o_x, o_a, o_b, o_flag, o_idx, o_cnt, total;
+    size_t o_x, o_a, o_b, o_flag, o_idx, o_cnt, o_amax, total;
     int wa, wb;  // widths of the two activation buffers
 };
 
@@ -220,6 +222,8 @@ WsLayout workspace_layout(const df_dnn *d, int64_t n) {
     o = al(o + size_t(w.n_pad) * 4);
     w.o_cnt = o;
     o = al(o + 4);
+    w.o_amax = o;
+    o = al(o + size_t(kAmaxWords) * 4);
     w.total = o;
     return w;
 }
@@ -288,8 +292,9 @@ df_status launch_dnn_k(const df_dnn *d, const df_mech *m, int64_t n, int64_t ld,
     auto *flag = reinterpret_cast<int8_t *>(base + w.o_flag);
     auto *idx = reinterpret_cast<int32_t *>(base + w.o_idx);
     auto *cnt = reinterpret_cast<int32_t *>(base + w.o_cnt);
-    auto *amax = reinterpret_cast<uint32_t *>(cnt) + 1;  // amax[l]: max |output| of hidden layer l
-    hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t *>(cnt), 1 + kMaxLayers);
+    // amax + kAmaxSlots l: the max |output| of hidden layer l
+    auto *amax = reinterpret_cast<uint32_t *>(base + w.o_amax);
+    hipLaunchKernelGGL(zero_words, dim3(1), dim3(256), 0, s, reinterpret_cast<uint32_t *>(cnt), amax);
     const int in_pad = d->layers[0].k_pad;
     hipLaunchKernelGGL(pre_kernel<K>, dim3(unsigned((w.n_pad + kPreThreads - 1) / kPreThreads)), dim3(kPreThreads), 0,
                        s, d->prm, n, w.n_pad, ld, p, T, Y, xb, in_pad, flag, idx, cnt, status, rr, o.fallback);
@@ -309,10 +314,10 @@ df_status launch_dnn_k(const df_dnn *d, const df_mech *m, int64_t n, int64_t ld,
         // layers 1..nh-1 (between two hidden layers) in FP8; the layer before one of them
         // reduces the amax of its output
         const bool q = fp8 && l >= 1;
-        uint32_t *amax_out = (fp8 && l + 1 < nh) ? amax + l : nullptr;
+        uint32_t *amax_out = (fp8 && l + 1 < nh) ? amax + size_t(l) * kAmaxSlots : nullptr;
         df_status st;
         if (q)
-            st = launch_gemm_fp8(in, in_ld, amax + (l - 1), blob + bl.w8[l], L.k_pad,
+            st = launch_gemm_fp8(in, in_ld, amax + size_t(l - 1) * kAmaxSlots, blob + bl.w8[l], L.k_pad,
                                  reinterpret_cast<const int32_t *>(blob + bl.e8[l]), L.b, out, out_ld, w.n_pad,
                                  L.n_pad, L.k_pad, amax_out, n, s);
         else if (amax_out)

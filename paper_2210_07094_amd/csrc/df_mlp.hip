@@ -43,12 +43,20 @@ __device__ __forceinline__ float gelu_grad(float x) {
 
 __device__ __forceinline__ float bf_to_f(bf16_t h) { return __uint_as_float(unsigned(h) << 16); }
 
-// wave-wide max of a non-negative float, combined into *amax (float bits; non-negative floats
-// order as their bit patterns) by one lane; all 64 lanes take part
+// wave-wide max of a non-negative float, combined into one of the kAmaxSlots words of amax
+// (float bits; non-negative floats order as their bit patterns) by one lane; all 64 lanes take part
 __device__ __forceinline__ void amax_combine(float m, uint32_t *amax) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
-    if ((threadIdx.x & 63) == 0) atomicMax(amax, __float_as_uint(m));
+    const unsigned slot = (blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6)) % kAmaxSlots;
+    if ((threadIdx.x & 63) == 0) atomicMax(amax + slot, __float_as_uint(m));
+}
+
+__device__ __forceinline__ float amax_read(const uint32_t *amax) {
+    uint32_t u = 0;
+#pragma unroll
+    for (int i = 0; i < kAmaxSlots; ++i) u = max(u, amax[i]);
+    return __uint_as_float(u);
 }
 
 // Epilogues: inference (bias, GELU); training forward (bias, GELU, and the pre-activation
@@ -196,7 +204,7 @@ __global__ __launch_bounds__(kThreads) void gemm_fp8_kernel(const bf16_t *__rest
 
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wm = w >> 1, wn = w & 1;
-    const int ea = fp8_scale_exp(__uint_as_float(*amax_in));
+    const int ea = fp8_scale_exp(amax_read(amax_in));
     const float sa = ldexpf(1.0f, -ea);
 
     // A: BM*BK/8 = 512 chunks of 8 bf16 (two per thread); W: BN*BK/16 = 320 chunks of 16 bytes
