@@ -105,8 +105,9 @@ __global__ __launch_bounds__(kPreThreads) void post_kernel(DnnDevParams prm, Mec
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n || flag[i] != 1) return;
     // ---- output layer: u = W h + b, fp32 accumulation, each output summed over the inputs in
-    // order; the outputs go in blocks of 8 so that their accumulators stay in registers
-    constexpr int KB = 8;
+    // order; the outputs go in blocks of up to 16 so that their accumulators stay in registers
+    // (each block reads the cell's activations once)
+    constexpr int KB = K < 16 ? K : 16;
     float u[K];
     const bf16_t *hr = h + i * int64_t(h_ld);
 #pragma unroll
