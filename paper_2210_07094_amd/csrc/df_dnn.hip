@@ -33,6 +33,17 @@ __device__ __forceinline__ float bf2f(bf16_t h) { return __uint_as_float(unsigne
 
 __device__ __forceinline__ double boxcox(double Y, double lam) { return (pow(fmax(Y, 0.0), lam) - 1.0) / lam; }
 
+// x^n for 1 <= n by repeated squaring (the inverse Box-Cox power when 1/lambda is an integer)
+__device__ __forceinline__ double ipow(double x, int n) {
+    double r = 1.0;
+    while (n) {
+        if (n & 1) r *= x;
+        x *= x;
+        n >>= 1;
+    }
+    return r;
+}
+
 // the fallback counter and the FP8 activation maxima (kAmaxSlots words per hidden layer)
 constexpr int kMaxLayers = 15;
 constexpr int kAmaxWords = kMaxLayers * kAmaxSlots;
@@ -138,7 +149,11 @@ __global__ __launch_bounds__(kPreThreads) void post_kernel(DnnDevParams prm, Mec
             if (k0 + kk < K) u[k0 + kk] = acc[kk];
     }
     // ---- stage 3, FP64
-    const double T0 = T[i];
+    const double T0 = T[i], iT0 = 1.0 / T0;
+    // 1/lambda as an exact small integer (lambda = 0.1 gives 10): the power by squaring
+    const int n_inv = (prm.inv_lambda == rint(prm.inv_lambda) && prm.inv_lambda >= 1.0 && prm.inv_lambda <= 64.0)
+                          ? int(prm.inv_lambda)
+                          : 0;
     double Y0[K], Yn[K];
     double sYW = 0.0, h0 = 0.0, sum = 0.0;
 #pragma unroll
@@ -146,10 +161,11 @@ __global__ __launch_bounds__(kPreThreads) void post_kernel(DnnDevParams prm, Mec
         Y0[k] = Y[k * ld + i];
         const double *r = m.sp + k * kSpTab;
         sYW += Y0[k] * r[1];
-        const double hRT = r[2] + T0 * (r[9] + T0 * (r[10] + T0 * (r[11] + T0 * r[12]))) + r[7] / T0;
+        const double hRT = r[2] + T0 * (r[9] + T0 * (r[10] + T0 * (r[11] + T0 * r[12]))) + r[7] * iT0;
         h0 += Y0[k] * hRT * r[1];
         const double z1 = boxcox(Y0[k], prm.lambda) + (double(u[k] + b[k]) * prm.sig_out[k] + prm.mu_out[k]);
-        Yn[k] = pow(fmax(1.0 + prm.lambda * z1, 0.0), prm.inv_lambda);
+        const double base = fmax(1.0 + prm.lambda * z1, 0.0);
+        Yn[k] = n_inv ? ipow(base, n_inv) : pow(base, prm.inv_lambda);
         sum += Yn[k];
     }
     h0 *= kR * T0;
@@ -163,11 +179,12 @@ __global__ __launch_bounds__(kPreThreads) void post_kernel(DnnDevParams prm, Mec
     bool conv = false;
     for (int it = 0; it < 20; ++it) {
         double hm = 0.0, cp = 0.0;
+        const double iTn = 1.0 / Tn;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const double *r = m.sp + k * kSpTab;
             const double cpR = r[2] + Tn * (r[3] + Tn * (r[4] + Tn * (r[5] + Tn * r[6])));
-            const double hRT = r[2] + Tn * (r[9] + Tn * (r[10] + Tn * (r[11] + Tn * r[12]))) + r[7] / Tn;
+            const double hRT = r[2] + Tn * (r[9] + Tn * (r[10] + Tn * (r[11] + Tn * r[12]))) + r[7] * iTn;
             hm += Yn[k] * hRT * r[1];
             cp += Yn[k] * cpR * r[1];
         }
