@@ -1162,7 +1162,7 @@ double orc_fp8_e4m3_round(double x) {
 
 /* smallest e with amax <= 448 * 2^e, so that amax * 2^-e lies in the E4M3FN range; 0 for amax 0 */
 int orc_fp8_scale_exp(double amax) {
-    if (!(amax > 0.0)) return 0;
+    if (!(amax > 0.0) || !isfinite(amax)) return 0; /* no finite scale covers it: the values decide */
     int e = 0;
     while (amax > ldexp(448.0, e)) ++e;
     while (amax <= ldexp(448.0, e - 1)) --e;

@@ -281,9 +281,11 @@ BlobLayout blob_layout(const std::vector<DnnLayer> &layers, int n_in) {
     return bl;
 }
 
-// E4M3FN byte of v, |v| <= 448: round to nearest, ties to even
+// E4M3FN byte of v, |v| <= 448: round to nearest, ties to even; a non-finite v gives the
+// format's NaN (the format has no infinity), so that it propagates as in the bf16 path
 uint8_t e4m3_byte(float v) {
     const uint8_t sgn = std::signbit(v) ? 0x80 : 0x00;
+    if (!std::isfinite(v)) return uint8_t(sgn | 0x7f);
     const float a = std::fabs(v);
     if (!(a > 0.0f)) return sgn;
     int k = 0;

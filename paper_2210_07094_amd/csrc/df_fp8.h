@@ -21,9 +21,9 @@ namespace df {
 
 constexpr int kAmaxSlots = 32;  // words of one activation maximum
 
-// smallest e with amax <= 448 * 2^e for the float amax (0 for amax 0); exact
+// smallest e with amax <= 448 * 2^e for the float amax (0 for amax 0 or not finite); exact
 __host__ __device__ inline int fp8_scale_exp(float amax) {
-    if (!(amax > 0.0f)) return 0;
+    if (!(amax > 0.0f) || !(amax <= 3.40282347e38f)) return 0;  // zero, NaN or infinite
     int k = 0;
     const float f = frexpf(amax, &k);  // amax = f * 2^k, f in [0.5, 1); 448 = 0.875 * 2^9
     return (f <= 0.875f) ? k - 9 : k - 8;

@@ -342,8 +342,9 @@ df_status launch_gemm_bf16_epi(const bf16_t *A, int lda, const bf16_t *B, int ld
 df_status launch_gemm_bf16_amax(const bf16_t *A, int lda, const bf16_t *B, int ldb, const float *bias, bf16_t *C,
                                 int ldc, int64_t M, int N, int K, uint32_t *amax, int64_t m_valid,
                                 hipStream_t stream) {
-    if (M % BM || N % BN || K % BK || lda % 8 || ldb % 8 || !amax)
+    if (M % BM || N % BN || K % BK || lda % 8 || ldb % 8)
         return fail(DF_E_INVALID, "gemm: shapes must be multiples of the tile sizes");
+    if (!amax) return fail(DF_E_INVALID, "gemm: null activation-maximum words");
     if (M == 0) return DF_OK;
     const int64_t tiles = (M / BM) * (N / BN);
     if (tiles > 0x7fffffff) return fail(DF_E_UNSUPPORTED, "gemm: too many tiles");
@@ -357,8 +358,9 @@ df_status launch_gemm_bf16_amax(const bf16_t *A, int lda, const bf16_t *B, int l
 df_status launch_gemm_fp8(const bf16_t *A, int lda, const uint32_t *amax_in, const uint8_t *W8, int ldb,
                           const int32_t *wexp, const float *bias, bf16_t *C, int ldc, int64_t M, int N, int K,
                           uint32_t *amax_out, int64_t m_valid, hipStream_t stream) {
-    if (M % BM || N % BN || K % BK || lda % 8 || ldb % 16 || ldb < K || !amax_in || !W8 || !wexp)
-        return fail(DF_E_INVALID, "gemm fp8: shapes must be multiples of the tile sizes");
+    if (M % BM || N % BN || K % BK || lda % 8 || ldb % 16 || ldb < K)
+        return fail(DF_E_INVALID, "gemm fp8: shapes must be multiples of the tile sizes (weight rows of 16 bytes)");
+    if (!amax_in || !W8 || !wexp) return fail(DF_E_INVALID, "gemm fp8: null maximum, weight or exponent array");
     if (M == 0) return DF_OK;
     const int64_t tiles = (M / BM) * (N / BN);
     if (tiles > 0x7fffffff) return fail(DF_E_UNSUPPORTED, "gemm fp8: too many tiles");

@@ -50,6 +50,7 @@ def test_scale_exponent():
     assert s(448.0) == 0 and s(448.0 * (1 + 1e-15)) == 1
     assert s(1.0) == -8 and s(1.75) == -8 and s(1.76) == -7
     assert s(0.0) == 0 and s(896.0) == 1 and s(896.1) == 2
+    assert s(float("inf")) == 0 and s(float("nan")) == 0   # no finite scale: left to the values
     rng = np.random.default_rng(2)
     for a in np.exp(rng.uniform(-40, 40, 500)):
         e = s(a)
