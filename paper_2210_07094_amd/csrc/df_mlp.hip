@@ -21,7 +21,7 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int BM = kGemmBM, BN = kGemmBN, BK = kGemmBK;
-constexpr int LDK = BK + 8;  // LDS row stride in bf16 (80 bytes) to spread rows over banks
+constexpr int LDK = BK + 16;  // LDS row stride in bf16 (96 bytes) to spread rows over banks
 constexpr int kThreads = 256;
 constexpr int WM = 64, WN = 80;          // per-wave sub-tile
 constexpr int TM = WM / 16, TN = WN / 16;  // MFMA tiles per wave
