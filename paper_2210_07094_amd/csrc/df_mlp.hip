@@ -5,8 +5,8 @@
 // with v_mfma_f32_16x16x32_bf16, exact-erf GELU epilogue, bf16 output.
 // Block tile 128 x 160 with four wave64s in a 2 x 2 arrangement, each wave
 // owning a 64 x 80 sub-tile (4 x 5 MFMA tiles); operands are staged through
-// LDS with the next tile's global loads issued before the current tile's
-// MFMAs.  Tiles sharing the same rows of A are mapped to the same XCD so the
+// LDS 32 or 64 deep in K (64 where K allows it) with the next stage's global
+// loads issued before the current stage's MFMAs.  Tiles sharing the same rows of A are mapped to the same XCD so the
 // A panel is fetched into that XCD's L2 once.
 #include <cmath>
 
@@ -21,7 +21,6 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int BM = kGemmBM, BN = kGemmBN, BK = kGemmBK;
-constexpr int LDK = BK + 16;  // LDS row stride in bf16 (96 bytes) to spread rows over banks
 constexpr int kThreads = 256;
 constexpr int WM = 64, WN = 80;          // per-wave sub-tile
 constexpr int TM = WM / 16, TN = WN / 16;  // MFMA tiles per wave
@@ -63,14 +62,16 @@ __device__ __forceinline__ float amax_read(const uint32_t *amax) {
 // stored to P with C's layout); training backward (the product times GELU'(P), no bias).
 enum { kEpiGelu = 0, kEpiLinear = 1, kEpiGeluSave = 2, kEpiGeluGrad = 3 };
 
-template <int EPI>
+// KD: reduction depth staged per barrier pair (32, or 64 where K allows it)
+template <int EPI, int KD>
 __global__ __launch_bounds__(kThreads) void gemm_kernel(const bf16_t *__restrict__ A, int lda,
                                                        const bf16_t *__restrict__ B, int ldb,
                                                        const float *__restrict__ bias, bf16_t *__restrict__ C,
                                                        int ldc, int K, int n_tiles_n, bf16_t *__restrict__ P,
                                                        uint32_t *__restrict__ amax, int64_t m_valid) {
-    __shared__ __attribute__((aligned(16))) bf16_t As[BM * LDK];
-    __shared__ __attribute__((aligned(16))) bf16_t Bs[BN * LDK];
+    constexpr int LDKD = KD + 16;  // LDS row stride in bf16 (96 bytes at KD = 32)
+    __shared__ __attribute__((aligned(16))) bf16_t As[BM * LDKD];
+    __shared__ __attribute__((aligned(16))) bf16_t Bs[BN * LDKD];
 
     // XCD-aware tile order: workgroups are dispatched round-robin over the 8 XCDs, so
     // block b runs on XCD b % 8; give each XCD a contiguous range of logical tiles.
@@ -83,22 +84,22 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(const bf16_t *__restrict
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wm = w >> 1, wn = w & 1;
 
-    // global -> register staging: A has BM*BK/8 = 512 16-byte chunks, B has 640
-    constexpr int kAChunks = BM * BK / 8, kBChunks = BN * BK / 8;
-    constexpr int kAPer = kAChunks / kThreads;                      // 2
-    constexpr int kBPer = (kBChunks + kThreads - 1) / kThreads;     // 3
+    // global -> register staging: A has BM*KD/8 16-byte chunks (512 at KD = 32), B has BN*KD/8 (640)
+    constexpr int kAChunks = BM * KD / 8, kBChunks = BN * KD / 8;
+    constexpr int kAPer = kAChunks / kThreads;
+    constexpr int kBPer = (kBChunks + kThreads - 1) / kThreads;
     u32x4 ra[kAPer], rb[kBPer];
     auto load = [&](int k0) {
 #pragma unroll
         for (int i = 0; i < kAPer; ++i) {
-            const int c = t + i * kThreads, r = c / (BK / 8), kc = c % (BK / 8);
+            const int c = t + i * kThreads, r = c / (KD / 8), kc = c % (KD / 8);
             ra[i] = *reinterpret_cast<const u32x4 *>(A + (row0 + r) * lda + k0 + kc * 8);
         }
 #pragma unroll
         for (int i = 0; i < kBPer; ++i) {
             const int c = t + i * kThreads;
             if (c < kBChunks) {
-                const int r = c / (BK / 8), kc = c % (BK / 8);
+                const int r = c / (KD / 8), kc = c % (KD / 8);
                 rb[i] = *reinterpret_cast<const u32x4 *>(B + int64_t(col0 + r) * ldb + k0 + kc * 8);
             }
         }
@@ -106,15 +107,15 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(const bf16_t *__restrict
     auto store = [&]() {
 #pragma unroll
         for (int i = 0; i < kAPer; ++i) {
-            const int c = t + i * kThreads, r = c / (BK / 8), kc = c % (BK / 8);
-            *reinterpret_cast<u32x4 *>(As + r * LDK + kc * 8) = ra[i];
+            const int c = t + i * kThreads, r = c / (KD / 8), kc = c % (KD / 8);
+            *reinterpret_cast<u32x4 *>(As + r * LDKD + kc * 8) = ra[i];
         }
 #pragma unroll
         for (int i = 0; i < kBPer; ++i) {
             const int c = t + i * kThreads;
             if (c < kBChunks) {
-                const int r = c / (BK / 8), kc = c % (BK / 8);
-                *reinterpret_cast<u32x4 *>(Bs + r * LDK + kc * 8) = rb[i];
+                const int r = c / (KD / 8), kc = c % (KD / 8);
+                *reinterpret_cast<u32x4 *>(Bs + r * LDKD + kc * 8) = rb[i];
             }
         }
     };
@@ -129,22 +130,27 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(const bf16_t *__restrict
     // the B tile, with 8 consecutive k values starting at 8 * (l / 16)
     const int fr = lane & 15, fk = (lane >> 4) * 8;
     load(0);
-    for (int k0 = 0; k0 < K; k0 += BK) {
+    for (int k0 = 0; k0 < K; k0 += KD) {
         __syncthreads();
         store();
         __syncthreads();
-        if (k0 + BK < K) load(k0 + BK);
-        bf16x8 af[TM], bfr[TN];
+        if (k0 + KD < K) load(k0 + KD);
+        // the staged depth in 32-deep MFMA steps, in k order (the sums are those of KD = 32)
 #pragma unroll
-        for (int i = 0; i < TM; ++i)
-            af[i] = *reinterpret_cast<const bf16x8 *>(As + (wm * WM + i * 16 + fr) * LDK + fk);
+        for (int kk = 0; kk < KD; kk += 32) {
+            bf16x8 af[TM], bfr[TN];
 #pragma unroll
-        for (int j = 0; j < TN; ++j)
-            bfr[j] = *reinterpret_cast<const bf16x8 *>(Bs + (wn * WN + j * 16 + fr) * LDK + fk);
+            for (int i = 0; i < TM; ++i)
+                af[i] = *reinterpret_cast<const bf16x8 *>(As + (wm * WM + i * 16 + fr) * LDKD + kk + fk);
 #pragma unroll
-        for (int i = 0; i < TM; ++i)
+            for (int j = 0; j < TN; ++j)
+                bfr[j] = *reinterpret_cast<const bf16x8 *>(Bs + (wn * WN + j * 16 + fr) * LDKD + kk + fk);
 #pragma unroll
-            for (int j = 0; j < TN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        }
     }
 
     // epilogue: lane l holds column (l % 16) and rows 4 * (l / 16) + r of each 16 x 16 tile
@@ -320,20 +326,29 @@ df_status launch_gemm_bf16_epi(const bf16_t *A, int lda, const bf16_t *B, int ld
     const int64_t tiles = (M / BM) * (N / BN);
     if (tiles > 0x7fffffff) return fail(DF_E_UNSUPPORTED, "gemm: too many tiles");
     const dim3 g = dim3(unsigned(tiles)), b = dim3(kThreads);
+    const bool deep = K % 64 == 0;
+#define DF_GEMM(E)                                                                                              \
+    if (deep)                                                                                                   \
+        hipLaunchKernelGGL((gemm_kernel<E, 64>), g, b, 0, stream, A, lda, B, ldb, bias, C, ldc, K, N / BN, P,   \
+                           nullptr, int64_t(0));                                                                \
+    else                                                                                                        \
+        hipLaunchKernelGGL((gemm_kernel<E, 32>), g, b, 0, stream, A, lda, B, ldb, bias, C, ldc, K, N / BN, P,   \
+                           nullptr, int64_t(0));
     switch (epi) {
         case GemmEpi::gelu:
-            hipLaunchKernelGGL(gemm_kernel<kEpiGelu>, g, b, 0, stream, A, lda, B, ldb, bias, C, ldc, K, N / BN, P, nullptr, int64_t(0));
+            DF_GEMM(kEpiGelu)
             break;
         case GemmEpi::linear:
-            hipLaunchKernelGGL(gemm_kernel<kEpiLinear>, g, b, 0, stream, A, lda, B, ldb, bias, C, ldc, K, N / BN, P, nullptr, int64_t(0));
+            DF_GEMM(kEpiLinear)
             break;
         case GemmEpi::gelu_save:
-            hipLaunchKernelGGL(gemm_kernel<kEpiGeluSave>, g, b, 0, stream, A, lda, B, ldb, bias, C, ldc, K, N / BN, P, nullptr, int64_t(0));
+            DF_GEMM(kEpiGeluSave)
             break;
         case GemmEpi::gelu_grad:
-            hipLaunchKernelGGL(gemm_kernel<kEpiGeluGrad>, g, b, 0, stream, A, lda, B, ldb, bias, C, ldc, K, N / BN, P, nullptr, int64_t(0));
+            DF_GEMM(kEpiGeluGrad)
             break;
     }
+#undef DF_GEMM
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(DF_E_HIP, std::string("gemm launch: ") + hipGetErrorString(e));
     return DF_OK;
@@ -348,8 +363,12 @@ df_status launch_gemm_bf16_amax(const bf16_t *A, int lda, const bf16_t *B, int l
     if (M == 0) return DF_OK;
     const int64_t tiles = (M / BM) * (N / BN);
     if (tiles > 0x7fffffff) return fail(DF_E_UNSUPPORTED, "gemm: too many tiles");
-    hipLaunchKernelGGL(gemm_kernel<kEpiGelu>, dim3(unsigned(tiles)), dim3(kThreads), 0, stream, A, lda, B, ldb, bias,
-                       C, ldc, K, N / BN, static_cast<bf16_t *>(nullptr), amax, m_valid);
+    if (K % 64 == 0)
+        hipLaunchKernelGGL((gemm_kernel<kEpiGelu, 64>), dim3(unsigned(tiles)), dim3(kThreads), 0, stream, A, lda, B,
+                           ldb, bias, C, ldc, K, N / BN, static_cast<bf16_t *>(nullptr), amax, m_valid);
+    else
+        hipLaunchKernelGGL((gemm_kernel<kEpiGelu, 32>), dim3(unsigned(tiles)), dim3(kThreads), 0, stream, A, lda, B,
+                           ldb, bias, C, ldc, K, N / BN, static_cast<bf16_t *>(nullptr), amax, m_valid);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(DF_E_HIP, std::string("gemm launch: ") + hipGetErrorString(e));
     return DF_OK;
