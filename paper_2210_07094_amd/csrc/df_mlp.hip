@@ -6,8 +6,9 @@
 // Block tile 128 x 160 with four wave64s in a 2 x 2 arrangement, each wave
 // owning a 64 x 80 sub-tile (4 x 5 MFMA tiles); operands are staged through
 // LDS 32 or 64 deep in K (64 where K allows it) with the next stage's global
-// loads issued before the current stage's MFMAs.  Tiles sharing the same rows of A are mapped to the same XCD so the
-// A panel is fetched into that XCD's L2 once.
+// loads issued before the current stage's MFMAs.  Tiles sharing the same rows
+// of A are mapped to the same XCD so the A panel is fetched into that XCD's L2
+// once.
 #include <cmath>
 
 #include "df_fp8.h"
