@@ -192,7 +192,8 @@ __device__ __forceinline__ uint32_t to_fp8x4(float a, float b, float c, float d)
 // FP8 layer: the tiling of gemm_kernel with E4M3FN operands.  A is read as bf16 and quantised
 // while it is staged (scale 2^-e_a), the weights are E4M3FN bytes already; each 16x16x32 MFMA
 // takes 8 bytes of a row of A and of W per lane, in the lane layout of the bf16 instruction.
-constexpr int LDK8 = BK + 8;  // LDS row stride in bytes
+// KD: reduction depth staged per barrier pair (32, or 64 where K allows it)
+template <int KD>
 __global__ __launch_bounds__(kThreads) void gemm_fp8_kernel(const bf16_t *__restrict__ A, int lda,
                                                            const uint32_t *__restrict__ amax_in,
                                                            const uint8_t *__restrict__ W8, int ldb,
@@ -200,6 +201,7 @@ __global__ __launch_bounds__(kThreads) void gemm_fp8_kernel(const bf16_t *__rest
                                                            const float *__restrict__ bias, bf16_t *__restrict__ C,
                                                            int ldc, int K, int n_tiles_n,
                                                            uint32_t *__restrict__ amax_out, int64_t m_valid) {
+    constexpr int LDK8 = KD + 8;  // LDS row stride in bytes
     __shared__ __attribute__((aligned(16))) uint8_t As[BM * LDK8];
     __shared__ __attribute__((aligned(16))) uint8_t Bs[BN * LDK8];
 
@@ -214,22 +216,22 @@ __global__ __launch_bounds__(kThreads) void gemm_fp8_kernel(const bf16_t *__rest
     const int ea = fp8_scale_exp(amax_read(amax_in));
     const float sa = ldexpf(1.0f, -ea);
 
-    // A: BM*BK/8 = 512 chunks of 8 bf16 (two per thread); W: BN*BK/16 = 320 chunks of 16 bytes
-    constexpr int kAChunks = BM * BK / 8, kBChunks = BN * BK / 16;
+    // A: BM*KD/8 chunks of 8 bf16; W: BN*KD/16 chunks of 16 bytes
+    constexpr int kAChunks = BM * KD / 8, kBChunks = BN * KD / 16;
     constexpr int kAPer = kAChunks / kThreads;
     constexpr int kBPer = (kBChunks + kThreads - 1) / kThreads;
     u32x4 ra[kAPer], rb[kBPer];
     auto load = [&](int k0) {
 #pragma unroll
         for (int i = 0; i < kAPer; ++i) {
-            const int c = t + i * kThreads, r = c / (BK / 8), kc = c % (BK / 8);
+            const int c = t + i * kThreads, r = c / (KD / 8), kc = c % (KD / 8);
             ra[i] = *reinterpret_cast<const u32x4 *>(A + (row0 + r) * lda + k0 + kc * 8);
         }
 #pragma unroll
         for (int i = 0; i < kBPer; ++i) {
             const int c = t + i * kThreads;
             if (c < kBChunks) {
-                const int r = c / (BK / 16), kc = c % (BK / 16);
+                const int r = c / (KD / 16), kc = c % (KD / 16);
                 rb[i] = *reinterpret_cast<const u32x4 *>(W8 + int64_t(col0 + r) * ldb + k0 + kc * 16);
             }
         }
@@ -237,7 +239,7 @@ __global__ __launch_bounds__(kThreads) void gemm_fp8_kernel(const bf16_t *__rest
     auto store = [&]() {
 #pragma unroll
         for (int i = 0; i < kAPer; ++i) {
-            const int c = t + i * kThreads, r = c / (BK / 8), kc = c % (BK / 8);
+            const int c = t + i * kThreads, r = c / (KD / 8), kc = c % (KD / 8);
             float f[8];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -253,7 +255,7 @@ __global__ __launch_bounds__(kThreads) void gemm_fp8_kernel(const bf16_t *__rest
         for (int i = 0; i < kBPer; ++i) {
             const int c = t + i * kThreads;
             if (c < kBChunks) {
-                const int r = c / (BK / 16), kc = c % (BK / 16);
+                const int r = c / (KD / 16), kc = c % (KD / 16);
                 uint2 lo, hi;
                 lo.x = rb[i][0];
                 lo.y = rb[i][1];
@@ -273,21 +275,26 @@ __global__ __launch_bounds__(kThreads) void gemm_fp8_kernel(const bf16_t *__rest
 
     const int fr = lane & 15, fk = (lane >> 4) * 8;
     load(0);
-    for (int k0 = 0; k0 < K; k0 += BK) {
+    for (int k0 = 0; k0 < K; k0 += KD) {
         __syncthreads();
         store();
         __syncthreads();
-        if (k0 + BK < K) load(k0 + BK);
-        long af[TM], bfr[TN];
+        if (k0 + KD < K) load(k0 + KD);
 #pragma unroll
-        for (int i = 0; i < TM; ++i) af[i] = *reinterpret_cast<const long *>(As + (wm * WM + i * 16 + fr) * LDK8 + fk);
+        for (int kk = 0; kk < KD; kk += 32) {
+            long af[TM], bfr[TN];
 #pragma unroll
-        for (int j = 0; j < TN; ++j) bfr[j] = *reinterpret_cast<const long *>(Bs + (wn * WN + j * 16 + fr) * LDK8 + fk);
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
+            for (int i = 0; i < TM; ++i)
+                af[i] = *reinterpret_cast<const long *>(As + (wm * WM + i * 16 + fr) * LDK8 + kk + fk);
 #pragma unroll
             for (int j = 0; j < TN; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(af[i], bfr[j], acc[i][j], 0, 0, 0);
+                bfr[j] = *reinterpret_cast<const long *>(Bs + (wn * WN + j * 16 + fr) * LDK8 + kk + fk);
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        }
     }
 
     float m = 0.0f;
@@ -384,8 +391,12 @@ df_status launch_gemm_fp8(const bf16_t *A, int lda, const uint32_t *amax_in, con
     if (M == 0) return DF_OK;
     const int64_t tiles = (M / BM) * (N / BN);
     if (tiles > 0x7fffffff) return fail(DF_E_UNSUPPORTED, "gemm fp8: too many tiles");
-    hipLaunchKernelGGL(gemm_fp8_kernel, dim3(unsigned(tiles)), dim3(kThreads), 0, stream, A, lda, amax_in, W8, ldb,
-                       wexp, bias, C, ldc, K, N / BN, amax_out, m_valid);
+    if (K % 64 == 0)
+        hipLaunchKernelGGL(gemm_fp8_kernel<64>, dim3(unsigned(tiles)), dim3(kThreads), 0, stream, A, lda, amax_in, W8,
+                           ldb, wexp, bias, C, ldc, K, N / BN, amax_out, m_valid);
+    else
+        hipLaunchKernelGGL(gemm_fp8_kernel<32>, dim3(unsigned(tiles)), dim3(kThreads), 0, stream, A, lda, amax_in, W8,
+                           ldb, wexp, bias, C, ldc, K, N / BN, amax_out, m_valid);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(DF_E_HIP, std::string("gemm fp8 launch: ") + hipGetErrorString(e));
     return DF_OK;
