@@ -50,6 +50,8 @@ typedef int32_t df_status;
 #define DF_E_HIP (-3)         /* HIP runtime error (allocation, copy, launch) */
 #define DF_E_IO (-4)          /* file cannot be opened or read */
 #define DF_E_FORMAT (-5)      /* file content malformed */
+#define DF_CELL_FAILURES 1    /* df_step_stats only: the step ran, and at least one cell failed
+                                 (status MAX_STEPS, H_UNDERFLOW, NONFINITE or TAPE_FULL) */
 
 /* per-cell status codes */
 #define DF_CELL_OK 0
@@ -129,6 +131,39 @@ void df_dnn_default_opts(df_dnn_opts *opts);
 df_status df_mech_load(const char *path, int32_t device, df_mech **out);
 void df_mech_free(df_mech *mech);
 df_status df_mech_info(const df_mech *mech, int32_t *n_species, int32_t *n_reactions, int32_t *n_elements);
+
+/*
+ * Summary of a finished step (the outcome of dfChemistryModel::solve() over the whole mesh,
+ * Sec. "Description of the new classes"), reduced on the device from the per-cell outputs that
+ * df_chem_step, df_chem_step_cells, df_chem_step_const_volume or df_dnn_step wrote.
+ */
+typedef struct {
+    int64_t n_cells;
+    int64_t count[8];     /* cells per status code DF_CELL_OK .. 7 (needs cell_status, else 0) */
+    int64_t failed;       /* cells with MAX_STEPS, H_UNDERFLOW, NONFINITE or TAPE_FULL */
+    int64_t accepted;     /* accepted sub-steps summed over the cells (needs n_steps, else 0) */
+    int64_t rejected;     /* rejected sub-steps summed over the cells */
+    int32_t max_attempts; /* largest accepted + rejected of one cell (0 without n_steps) */
+    int32_t max_cell;     /* the lowest-index cell with that count (-1 without n_steps or cells) */
+    double min_Y;         /* smallest mass fraction over the cells, NaN ignored (+inf without Y);
+                             the integrator never clips negative mass fractions */
+} df_stats;
+
+/*
+ * Reduce the outputs of a step into *stats_dev, asynchronously on hip_stream, ordered after the
+ * step when launched on its stream.
+ *   cell_status [n], n_steps [2n] (accepted at [i], rejected at [n + i]), Y [n_species * ld]:
+ *               device arrays as the step wrote them, each nullable (its fields stay 0)
+ *   stats_dev   device memory for one df_stats, 8-byte aligned, caller-owned, written
+ *   stats_host  host memory for one df_stats, or NULL.  When given, the call waits for
+ *               hip_stream, copies the summary there and returns DF_CELL_FAILURES (> 0) if any
+ *               cell failed, DF_OK otherwise.  When NULL, nothing waits and DF_OK is returned.
+ * Runs on the current device.  Errors: DF_E_INVALID (null or misaligned stats_dev, n_cells < 0
+ * or >= 2^31, Y without n_species >= 1 and ld >= n_cells), DF_E_HIP.
+ */
+df_status df_step_stats(int64_t n_cells, int64_t ld, int32_t n_species, const int32_t *cell_status,
+                        const int32_t *n_steps, const double *Y, df_stats *stats_dev, df_stats *stats_host,
+                        void *hip_stream);
 
 /* Bytes of device workspace df_chem_step / df_chem_step_cells can use for n_cells (see their
    `workspace`). */

@@ -13,9 +13,10 @@ from __future__ import annotations
 import ctypes as C
 
 from ._lib import (CELL_DNN_FALLBACK, CELL_H_UNDERFLOW, CELL_MAX_STEPS, CELL_NONFINITE, CELL_OK,  # noqa
-                   CELL_TAPE_FULL, AdamOpts, ChemOpts, DfError, DnnOpts, check, lib)
+                   CELL_TAPE_FULL, DF_CELL_FAILURES, AdamOpts, ChemOpts, DfError, DnnOpts, Stats, check, lib)
 
-__all__ = ["Mechanism", "DNN", "Trainer", "chem_opts", "dnn_opts", "adam_opts", "chem_step_diff", "DfError", "lib"]
+__all__ = ["Mechanism", "DNN", "Trainer", "chem_opts", "dnn_opts", "adam_opts", "chem_step_diff", "step_stats",
+           "DfError", "lib"]
 
 
 def chem_opts(**kw) -> ChemOpts:
@@ -69,6 +70,31 @@ def _stream(stream):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
     return C.c_void_p(s.cuda_stream)
+
+
+def step_stats(n_cells, status=None, n_steps=None, Y=None, stats_dev=None, stream=None):
+    """Summary of a finished step (df_step_stats) from its per-cell outputs: status int32 [n],
+    n_steps int32 [2n], Y float64 [K, ld] device tensors (each optional).  Waits for the stream and
+    returns (failures, summary): failures is True when df_step_stats returned DF_CELL_FAILURES,
+    summary a dict of the df_stats fields (count as a list per status code).  stats_dev: a device
+    uint8 tensor of at least sizeof(df_stats) bytes to hold the device copy (allocated if None)."""
+    import torch
+    n = int(n_cells)
+    size = C.sizeof(Stats)
+    if stats_dev is None:
+        dev = next((t.device for t in (status, n_steps, Y) if t is not None), torch.device("cuda"))
+        stats_dev = torch.empty(size, dtype=torch.uint8, device=dev)
+    if stats_dev.dtype != torch.uint8 or stats_dev.numel() < size:
+        raise ValueError(f"stats_dev: needs a uint8 device tensor of at least {size} bytes")
+    K, ld = (0, n) if Y is None else (int(Y.shape[0]), int(Y.shape[1]))
+    host = Stats()
+    code = check(lib().df_step_stats(n, ld, K, _ptr(status, torch.int32, "status", n),
+                                     _ptr(n_steps, torch.int32, "n_steps", 2 * n),
+                                     _ptr(Y, torch.float64, "Y", K * ld), C.c_void_p(stats_dev.data_ptr()),
+                                     C.byref(host), _stream(stream)))
+    out = {f[0]: getattr(host, f[0]) for f in Stats._fields_}
+    out["count"] = list(host.count)
+    return code == DF_CELL_FAILURES, out
 
 
 class Mechanism:

@@ -13,6 +13,7 @@ DF_E_UNSUPPORTED = -2
 DF_E_HIP = -3
 DF_E_IO = -4
 DF_E_FORMAT = -5
+DF_CELL_FAILURES = 1
 
 CELL_OK = 0
 CELL_MAX_STEPS = 1
@@ -34,6 +35,11 @@ class AdamOpts(C.Structure):
 class DnnOpts(C.Structure):
     _fields_ = [("renormalise", C.c_int32), ("fallback", C.c_int32), ("precision", C.c_int32),
                 ("reserved1", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_cells", C.c_int64), ("count", C.c_int64 * 8), ("failed", C.c_int64), ("accepted", C.c_int64),
+                ("rejected", C.c_int64), ("max_attempts", C.c_int32), ("max_cell", C.c_int32), ("min_Y", C.c_double)]
 
 
 class DfError(RuntimeError):
@@ -107,6 +113,8 @@ def lib():
     L.df_chem_step_cells.restype = i32
     L.df_chem_step_cells.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t,
                                      C.POINTER(ChemOpts), vp]
+    L.df_step_stats.restype = i32
+    L.df_step_stats.argtypes = [i64, i64, i32, vp, vp, vp, vp, C.POINTER(Stats), vp]
     if hasattr(L, "df_dnn_load"):
         L.df_dnn_load.restype = i32
         L.df_dnn_load.argtypes = [C.c_char_p, vp, i32, C.POINTER(vp)]

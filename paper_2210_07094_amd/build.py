@@ -25,7 +25,7 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", os.path.j
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
 
-SOURCES = ["df_mech.cpp", "df_chem.hip", "df_chem_cv.hip", "df_chem_wave.hip", "df_chem_coop.hip", "df_dnn.hip", "df_mlp.hip", "df_adjoint.hip", "df_train.hip", "df_rollout.hip"]
+SOURCES = ["df_mech.cpp", "df_chem.hip", "df_chem_cv.hip", "df_chem_wave.hip", "df_chem_coop.hip", "df_dnn.hip", "df_mlp.hip", "df_adjoint.hip", "df_train.hip", "df_rollout.hip", "df_stats.hip"]
 
 # per-source additions: the constant-volume kernel is built with the machine instruction
 # scheduler off and the one-wavefront-per-cell kernel with the scheduler's max-memory-clause

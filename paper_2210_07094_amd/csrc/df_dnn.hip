@@ -164,7 +164,10 @@ __global__ __launch_bounds__(kPreThreads) void post_kernel(DnnDevParams prm, Mec
         const double hRT = r[2] + T0 * (r[9] + T0 * (r[10] + T0 * (r[11] + T0 * r[12]))) + r[7] * iT0;
         h0 += Y0[k] * hRT * r[1];
         const double z1 = boxcox(Y0[k], prm.lambda) + (double(u[k] + b[k]) * prm.sig_out[k] + prm.mu_out[k]);
-        const double base = fmax(1.0 + prm.lambda * z1, 0.0);
+        // the base clamped at 0 from below; a NaN (a non-finite network output) stays NaN, so
+        // that the cell's temperature recovery fails and it is flagged non-finite
+        const double b1 = 1.0 + prm.lambda * z1;
+        const double base = (b1 < 0.0) ? 0.0 : b1;
         Yn[k] = n_inv ? ipow(base, n_inv) : pow(base, prm.inv_lambda);
         sum += Yn[k];
     }

@@ -178,12 +178,22 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(const bf16_t *__restrict
     if (amax) amax_combine(m, amax);
 }
 
-// E4M3FN bytes of four floats (round to nearest even), clamped to the format's range first
+// A value the E4M3FN conversion takes as is: |x| <= 448 unchanged; 448 < |x| <= 464 rounds to
+// 448 (ties to even) and is passed as 448; a value that would round beyond 448, an infinity or a
+// NaN becomes NaN, the format's only non-finite value, so that it propagates to the cell's
+// status as in the bf16 path.  The per-call scale keeps every finite scaled value within 448;
+// the other cases arise only when the activation maximum itself is not finite.
+__device__ __forceinline__ float fp8_in_range(float x) {
+    const float a = fabsf(x);
+    return (a <= 448.0f) ? x : ((a <= 464.0f) ? copysignf(448.0f, x) : __builtin_nanf(""));
+}
+
+// E4M3FN bytes of four floats (round to nearest even)
 __device__ __forceinline__ uint32_t to_fp8x4(float a, float b, float c, float d) {
-    a = fminf(fmaxf(a, -448.0f), 448.0f);
-    b = fminf(fmaxf(b, -448.0f), 448.0f);
-    c = fminf(fmaxf(c, -448.0f), 448.0f);
-    d = fminf(fmaxf(d, -448.0f), 448.0f);
+    a = fp8_in_range(a);
+    b = fp8_in_range(b);
+    c = fp8_in_range(c);
+    d = fp8_in_range(d);
     int v = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);  // bytes 0, 1
     v = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, v, true);       // bytes 2, 3
     return uint32_t(v);

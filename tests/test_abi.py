@@ -96,3 +96,17 @@ def test_const_volume_and_rollout_host_checks(L):
     assert L.df_rollout(None, None, 1, 1, 1e-6, 10, 0, None, None, None, None, None, None, 0, None, None) \
         == _lib.DF_E_INVALID
     assert b"null mechanism" in L.df_last_error()
+
+
+def test_step_stats_host_checks(L):
+    s = _lib.Stats()
+    # null device summary, negative cell count, Y without species count: refused before any launch
+    assert L.df_step_stats(4, 4, 0, None, None, None, None, C.byref(s), None) == _lib.DF_E_INVALID
+    assert b"null stats_dev" in L.df_last_error()
+    fake = C.c_void_p(4096)   # never dereferenced: the argument checks come first
+    assert L.df_step_stats(-1, 4, 0, None, None, None, fake, C.byref(s), None) == _lib.DF_E_INVALID
+    assert L.df_step_stats(4, 4, 0, None, None, fake, fake, C.byref(s), None) == _lib.DF_E_INVALID
+    assert L.df_step_stats(4, 2, 9, None, None, fake, fake, C.byref(s), None) == _lib.DF_E_INVALID
+    assert L.df_step_stats(4, 4, 0, None, None, None, C.c_void_p(4097), C.byref(s), None) == _lib.DF_E_INVALID
+    assert b"aligned" in L.df_last_error()
+    assert C.sizeof(_lib.Stats) == 8 * 12 + 8 + 8

@@ -133,3 +133,74 @@ def test_fallback_cells_use_the_integrator(tmp_path, h2_oracle, h2_mech):
     np.testing.assert_array_equal(r["Y"][:, cold], ref["Y"])
     r0 = d.step(h2_oracle, f["T"], f["p"], f["Y"], 1e-6, fallback=False)
     np.testing.assert_array_equal(r0["T"][cold], f["T"][cold])
+
+
+def _stage3_reference(npc, T0, p, Y0, u, mu_out, sig_out, lam, dt, renormalise):
+    """Stage 3 of the DNN step written out from its definition with NumPy: the increment of
+    z = BoxCox(Y) is u sig_out + mu_out; Y' = max(1 + lam z', 0)^(1/lam); optionally Y' / sum Y';
+    T' solves h(T', Y') = h(T0, Y0) (bisection on the independent NumPy enthalpy, no Newton);
+    rr = rho0 (Y' - Y0) / dt with rho0 = p Wbar0 / (R T0)."""
+    from npchem import R
+    z0 = (np.maximum(Y0, 0.0) ** lam - 1.0) / lam
+    z1 = z0 + (u * sig_out + mu_out)
+    Y1 = np.maximum(1.0 + lam * z1, 0.0) ** (1.0 / lam)
+    if renormalise:
+        Y1 = Y1 / Y1.sum()
+    h0 = npc.h_mass(T0, Y0)
+    lo, hi = 200.0, 4000.0
+    assert npc.h_mass(lo, Y1) < h0 < npc.h_mass(hi, Y1)
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if npc.h_mass(mid, Y1) < h0:
+            lo = mid
+        else:
+            hi = mid
+        if hi - lo <= 1e-13 * mid:
+            break
+    T1 = 0.5 * (lo + hi)
+    Wbar0 = 1.0 / np.sum(Y0 / npc.W)
+    rho0 = p * Wbar0 / (R * T0)
+    return T1, Y1, rho0 * (Y1 - Y0) / dt
+
+
+@pytest.mark.parametrize("renormalise", [True, False])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_stage3_against_definition(tmp_path, h2_oracle, h2_mech, npchem, renormalise, mode):
+    """Stage 3 of the DNN step (inverse normalisation, inverse Box-Cox, renormalisation, T from
+    the enthalpy, rr), Sec. "Description of the new classes": the output layer has zero weights
+    and a chosen bias, so u equals the bias exactly in either precision, and the mean and scale
+    of the outputs differ per species and from each other.  Swapping sig_out and mu_out, a sign
+    of the increment, a missing renormalisation, the clamp of the inverse transform or a wrong
+    density in rr each change the result far beyond the bar."""
+    K = 9
+    path = tmp_path / "s3.dfdnn"
+    rng = np.random.default_rng(17)
+    dims = [K + 2, 24, 16, 12, K]
+    W = [rng.normal(0, 0.3, (dims[l + 1], dims[l])).astype(np.float32) for l in range(4)]
+    b = [rng.normal(0, 0.05, dims[l + 1]).astype(np.float32) for l in range(4)]
+    W[-1][:] = 0.0
+    # output bias in float32; species 6 (HO2) gets an increment below -1/lambda - z0, so the
+    # inverse transform clamps it to zero
+    b[-1] = np.array([0.75, -1.25, 0.5, 2.0, -0.5, 1.5, -60.0, 0.25, -0.75], np.float32)
+    mu_out = np.array([0.011, -0.023, 0.017, 0.05, -0.031, 0.029, 0.0, -0.013, 0.002])
+    sig_out = np.array([0.04, 0.09, 0.06, 0.5, 0.3, 0.2, 1.0, 0.7, 0.01])
+    mu_in = np.concatenate([[1300.0, 101325.0], np.full(K, -5.0)])
+    sig_in = np.concatenate([[300.0, 1.0], np.full(K, 3.0)])
+    dnnfile.write_dnn(path, W, b, K, LAM, 1e-6, mu_in, sig_in, mu_out, sig_out,
+                      np.full(K + 2, -1e300), np.full(K + 2, 1e300))
+    d = oracle.DNN(path)
+    f = fields.ignition_cells(h2_mech, n=24, seed=29)
+    Y = f["Y"] + rng.uniform(0, 1, f["Y"].shape) ** 4 * 1e-3
+    f["Y"] = Y / Y.sum(axis=0, keepdims=True)
+    r = d.step(h2_oracle, f["T"], f["p"], f["Y"], 1e-6, renormalise=renormalise, mode=mode, want_rr=True)
+    assert np.all(r["status"] == 0)
+    u = b[-1].astype(np.float64)
+    for i in range(f["T"].size):
+        T1, Y1, rr = _stage3_reference(npchem, f["T"][i], f["p"][i], f["Y"][:, i], u, mu_out, sig_out, LAM,
+                                       1e-6, renormalise)
+        assert Y1[6] == 0.0 and r["Y"][6, i] == 0.0
+        np.testing.assert_allclose(r["Y"][:, i], Y1, rtol=1e-12, atol=0)
+        assert abs(r["T"][i] - T1) <= 1e-10 * T1
+        np.testing.assert_allclose(r["rr"][:, i], rr, rtol=1e-9, atol=1e-9 * np.abs(rr).max())
+        if not renormalise:
+            assert abs(Y1.sum() - 1.0) > 1e-3   # the case really tests the switch
