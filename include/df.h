@@ -212,6 +212,20 @@ df_status df_chem_step_cells(const df_mech *mech, int64_t n_cells, int64_t ld, c
                              void *hip_stream);
 
 /*
+ * df_chem_step for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the cost-ordering and queue workspace
+ * is the library's own static device array instead of a caller workspace, so the call allocates
+ * nothing.  Arguments, schedules, results and errors as df_chem_step with a workspace, for at most
+ * 1,048,576 cells per call (more: DF_E_UNSUPPORTED before anything is launched).  The array
+ * (about 4.2 MB on each device the library runs on) is held until the process ends and is shared
+ * by every call on that device: calls that overlap on one device (several streams or host
+ * threads at once) race on it and must not be issued.  Each call clears what it needs itself.
+ */
+df_status df_chem_step_noalloc(const df_mech *mech, int64_t n_cells, int64_t ld, double dt, const double *p, double *T,
+                               double *Y, double *h_inout, double *rr, int32_t *cell_status, int32_t *n_steps,
+                               const df_chem_opts *opts, void *hip_stream);
+
+/*
  * The constant-volume reactor (df0DFoam's constant-volume case): density fixed per cell,
  * pressure following from the state (p = rho R T / Wbar),
  *   dY_k/dt = W_k wdot_k / rho,  dT/dt = -sum_k U_k wdot_k / (rho cv),

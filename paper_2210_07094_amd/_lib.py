@@ -113,6 +113,8 @@ def lib():
     L.df_chem_step_cells.restype = i32
     L.df_chem_step_cells.argtypes = [vp, i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t,
                                      C.POINTER(ChemOpts), vp]
+    L.df_chem_step_noalloc.restype = i32
+    L.df_chem_step_noalloc.argtypes = [vp, i64, i64, d, vp, vp, vp, vp, vp, vp, vp, C.POINTER(ChemOpts), vp]
     L.df_step_stats.restype = i32
     L.df_step_stats.argtypes = [i64, i64, i32, vp, vp, vp, vp, C.POINTER(Stats), vp]
     if hasattr(L, "df_dnn_load"):

@@ -13,6 +13,7 @@
 // element, so a reaction side with fewer than three molecules needs no
 // branch.
 #include <cmath>
+#include <mutex>
 
 #include "df_internal.h"
 #include "df_kinetics.h"
@@ -165,11 +166,11 @@ __global__ __launch_bounds__(kOrdThreads) void order_scatter(const double *__res
     if (i < n) idx[base[b] + rank] = int32_t(i);
 }
 
-size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+constexpr size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // workspace: bucket counts and offsets | queue counter | cell order
 constexpr size_t kCntBytes = size_t(2 * kBuckets + 64) * 4;
-size_t order_bytes(int64_t n) { return al256(kCntBytes) + 256 + al256(size_t(n) * 4); }
+constexpr size_t order_bytes(int64_t n) { return al256(kCntBytes) + 256 + al256(size_t(n) * 4); }
 
 struct Work {
     int32_t *cnt;
@@ -272,6 +273,66 @@ extern "C" df_status df_chem_step_cells(const df_mech *mech, int64_t n_cells, in
     if (n_cells > 0 && !dt) return df::fail(DF_E_INVALID, "df_chem_step_cells: null dt");
     return df::chem_step_impl("df_chem_step_cells", mech, n_cells, ld, 0.0, dt, p, T, Y, h_inout, rr, cell_status,
                               n_steps, workspace, ws_bytes, opts, hip_stream);
+}
+
+// ---- the step without a caller workspace: the cost-ordering scratch in a static device array ----
+namespace df {
+namespace {
+
+// Cells one call of df_chem_step_noalloc takes at most; its scratch holds the bucket counts, the
+// queue counter and the cell order of that many cells (4 bytes a cell, 4.2 MB in all), in every
+// device's copy of the code object until the process ends.
+constexpr int64_t kNoAllocMaxCells = int64_t(1) << 20;
+constexpr size_t kNoAllocBytes = order_bytes(kNoAllocMaxCells);
+
+__device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+// the device address of each device's copy of `scratch`, taken once per device with that device
+// current (the array's name is not a device address in host code)
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+df_status scratch_on(int device, void **out) {
+    if (device < 0 || device >= kMaxDevices) return fail(DF_E_UNSUPPORTED, "df_chem_step_noalloc: device index beyond 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(DF_E_HIP, std::string("df_chem_step_noalloc: hipGetSymbolAddress: ") + hipGetErrorString(e));
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return DF_OK;
+}
+
+}  // namespace
+}  // namespace df
+
+extern "C" df_status df_chem_step_noalloc(const df_mech *mech, int64_t n_cells, int64_t ld, double dt,
+                                          const double *p, double *T, double *Y, double *h_inout, double *rr,
+                                          int32_t *cell_status, int32_t *n_steps, const df_chem_opts *opts,
+                                          void *hip_stream) {
+    using namespace df;
+    clear_error();
+    const char *who = "df_chem_step_noalloc";
+    if (!mech) return fail(DF_E_INVALID, std::string(who) + ": null mechanism handle");
+    if (n_cells > kNoAllocMaxCells)
+        return fail(DF_E_UNSUPPORTED, std::string(who) + ": " + std::to_string(n_cells) + " cells, at most " +
+                                          std::to_string(kNoAllocMaxCells) + " per call");
+    if (n_cells <= 0) return chem_step_impl(who, mech, n_cells, ld, dt, nullptr, p, T, Y, h_inout, rr, cell_status,
+                                            n_steps, nullptr, 0, opts, hip_stream);
+    int prev = 0;
+    if (hipGetDevice(&prev) != hipSuccess) return fail(DF_E_HIP, std::string(who) + ": hipGetDevice failed");
+    if (prev != mech->device && hipSetDevice(mech->device) != hipSuccess)
+        return fail(DF_E_HIP, std::string(who) + ": cannot select the mechanism's device");
+    void *ws = nullptr;
+    df_status st = scratch_on(mech->device, &ws);
+    if (prev != mech->device) (void)hipSetDevice(prev);
+    if (st != DF_OK) return st;
+    return chem_step_impl(who, mech, n_cells, ld, dt, nullptr, p, T, Y, h_inout, rr, cell_status, n_steps, ws,
+                          order_bytes(n_cells), opts, hip_stream);
 }
 
 // ---- schedule autotuning ----
