@@ -29,9 +29,10 @@ SOURCES = ["df_mech.cpp", "df_chem.hip", "df_chem_cv.hip", "df_chem_wave.hip", "
 
 # per-source additions: the constant-volume kernel is built with the machine instruction
 # scheduler off and the one-wavefront-per-cell kernel with the scheduler's max-memory-clause
-# strategy (-O2 and -O3 builds with the default scheduling gave wrong results on gfx950 where
-# these builds, -O1 and a CPU build of the same source agreed with the oracle; their parity
-# tests check these builds)
+# strategy.  -O2 and -O3 builds with the default scheduling gave wrong results on gfx950, while
+# these builds, -O1 and the CPU build of the same sources under sanitizers (tests/test_cpu_emu.py)
+# agree with the oracle; the optimised IR of both files carries no undefined value into the
+# arithmetic, so the difference arises in code generation.  Their parity tests check these builds.
 EXTRA = {"df_chem_cv.hip": ["-mllvm", "-enable-misched=0"],
          "df_chem_wave.hip": ["-mllvm", "-amdgpu-sched-strategy=max-memory-clause"]}
 

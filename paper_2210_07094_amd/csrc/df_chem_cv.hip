@@ -10,8 +10,11 @@
 // This file is compiled on its own, with the machine instruction scheduler off: optimised
 // builds of this instantiation with the scheduler on produced wrong sub-steps on gfx950
 // (every attempt after the first rejected, the step length driven to 1e-17 s) while the same
-// source built without optimisation, built with FP contraction off, or run on the CPU gave the
-// oracle's sub-step sequence.  The parity tests of the constant-volume step check this build.
+// source built without optimisation, built with FP contraction off, or run on the CPU under
+// sanitizers (tests/test_cpu_emu.py) gave the oracle's sub-step sequence; the constant-pressure
+// instantiation of the same solver is correct with the scheduler on, and the optimised IR of
+// this file carries no undefined value into the arithmetic.  The parity tests of the
+// constant-volume step check this build.
 #include <cmath>
 
 #include "df_internal.h"

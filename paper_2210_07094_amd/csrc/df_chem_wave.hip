@@ -27,8 +27,10 @@
 // This file is compiled with the AMDGPU scheduler's max-memory-clause strategy: -O2 and -O3
 // builds of the 53-species instantiation with the default strategy returned garbage states on
 // gfx950 (every attempt rejected), while -O1, -O3 with the scheduler off or with the max-ILP or
-// max-memory-clause strategy, and a CPU build of the same source under AddressSanitizer
-// reproduced the oracle's sub-step sequences exactly.
+// max-memory-clause strategy, and the CPU build of the same source under AddressSanitizer and
+// UndefinedBehaviorSanitizer (tests/test_cpu_emu.py, which also fails a cross-lane operation in
+// divergent code) reproduced the oracle's sub-step sequences exactly.  The optimised IR of this
+// file holds no undefined value, so the difference arises in code generation, not in the source.
 #include <cmath>
 
 #include "df_internal.h"
