@@ -18,6 +18,7 @@ import argparse
 import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -35,6 +36,7 @@ DT = 1e-6
 # dense BF16 MFMA 2.5 PFLOP/s
 PEAK_FP64_TFLOPS = 78.6
 PEAK_BF16_TFLOPS = 2500.0
+PEAK_FP8_TFLOPS = 5000.0
 
 # cost of operations without a native FP64 instruction, in FP64 lane-ops (an FMA is one lane-op)
 TRANSCENDENTAL_OPS = 25
@@ -476,6 +478,70 @@ def rollout_study(gm, dnn, mech_h, dev):
             "time_per_step": timing}
 
 
+def cpu_model():
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return None
+
+
+def cpu_leg(out_path, threads):
+    """The oracle timed on the host (run in a child process with the -O3 -march=native build): the
+    integrator on every cell of snapshots 0 and S and of the 1,024 ignition cells with all threads,
+    the BF16-emulated DNN step on every 16th cell of each snapshot, and one thread on every 64th
+    cell (integrator) and every 256th cell (DNN) of snapshot 0.  Its results are also the reference
+    of the DNN error statement.  Writes the oracle states to out_path, returns the timings."""
+    import oracle
+    import synth
+    from synth import fields
+    om = oracle.Mech(MECH)
+    od = oracle.DNN(DNN_W)
+    mech_h = synth.read_mech(MECH)
+    res, tim = {}, {}
+    for name, f in (("s0", fields.hot_kernel_field_2d(mech_h)), ("sS", fields.snapshot_s()),
+                    ("c1", fields.ignition_cells(mech_h))):
+        t1 = time.perf_counter()
+        ro = om.chem_step(f["T"], f["p"], f["Y"], DT, nthreads=threads)
+        tim[f"{name}_integrator_s"] = time.perf_counter() - t1
+        res[f"{name}_T"], res[f"{name}_Y"] = ro["T"], ro["Y"]
+        if name != "c1":
+            smp = np.arange(0, f["T"].size, 16)
+            t1 = time.perf_counter()
+            od.step(om, f["T"][smp], f["p"][smp], f["Y"][:, smp], DT, mode=1, nthreads=threads)
+            tim[f"{name}_dnn_s"] = time.perf_counter() - t1
+            tim[f"{name}_dnn_cells"] = int(smp.size)
+        tim[f"{name}_cells"] = int(f["T"].size)
+        if name == "s0":
+            smp = np.arange(0, f["T"].size, 64)
+            t1 = time.perf_counter()
+            om.chem_step(f["T"][smp], f["p"][smp], f["Y"][:, smp], DT, nthreads=1)
+            tim["s0_integrator_1core_s"], tim["s0_integrator_1core_cells"] = time.perf_counter() - t1, int(smp.size)
+            smp = np.arange(0, f["T"].size, 256)
+            t1 = time.perf_counter()
+            od.step(om, f["T"][smp], f["p"][smp], f["Y"][:, smp], DT, mode=1, nthreads=1)
+            tim["s0_dnn_1core_s"], tim["s0_dnn_1core_cells"] = time.perf_counter() - t1, int(smp.size)
+    np.savez(out_path, **res)
+    return tim
+
+
+def run_cpu_leg(threads):
+    import tempfile
+    with tempfile.TemporaryDirectory() as tmp:
+        path = os.path.join(tmp, "oracle_states.npz")
+        env = dict(os.environ, DF_ORACLE_NATIVE="1", OMP_NUM_THREADS=str(threads))
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-leg", path, "--threads", str(threads)],
+                           capture_output=True, text=True, env=env, timeout=1200)
+        if r.returncode != 0:
+            raise RuntimeError(f"cpu leg failed:\n{r.stderr[-3000:]}")
+        tim = json.loads(r.stdout.strip().splitlines()[-1])
+        z = np.load(path)
+        return tim, {k: z[k].copy() for k in z.files}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -487,7 +553,12 @@ def main():
     ap.add_argument("--no-training", action="store_true", help="skip the DNN training study")
     ap.add_argument("--no-rollout", action="store_true", help="skip the 0-D rollout study")
     ap.add_argument("--no-large", action="store_true", help="skip the 53-species mechanism study")
+    ap.add_argument("--cpu-leg", default=None, help=argparse.SUPPRESS)
+    ap.add_argument("--threads", type=int, default=1, help=argparse.SUPPRESS)
     a = ap.parse_args()
+    if a.cpu_leg:
+        print(json.dumps(cpu_leg(a.cpu_leg, a.threads)), flush=True)
+        return
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported (cells are independent, "
               "so N GPUs would each run this benchmark on their own shard)", file=sys.stderr)
@@ -506,6 +577,8 @@ def main():
     K = mech_h.n_species
     gm = df.Mechanism(MECH)
     dnn = df.DNN(DNN_W, gm)
+    ops = integrator_lane_ops(mech_h)
+    dnn_cell_flops = mlp_flops(dnn.dims)
 
     T_in = torch.tensor(f["T"], dtype=torch.float64, device=dev)
     p = torch.tensor(f["p"], dtype=torch.float64, device=dev)
@@ -551,87 +624,130 @@ def main():
     chem_ms = np.array([e[0].elapsed_time(e[1]) for e in events])
     dnn_ms = np.array([e[2].elapsed_time(e[3]) for e in events])
     ms_step = wall * 1e3 / a.steps
-
-    # each form alone (outside the timed region), for the kernels' own efficiency
-    Ta, Ya = T_in.clone(), Y_in.clone()
-
-    def alone(fn, reps):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        out = []
-        for _ in range(reps):
-            Ta.copy_(T_in)
-            Ya.copy_(Y_in)
-            e0.record(stream)
-            fn()
-            e1.record(stream)
-            torch.cuda.synchronize()
-            out.append(e0.elapsed_time(e1))
-        return float(np.mean(out))
-
-    chem_alone = alone(lambda: gm.chem_step(Ta, p, Ya, DT, workspace=chem_ws, stream=stream), a.steps)
-    dnn_alone = alone(lambda: dnn.step(Ta, p, Ya, DT, workspace=ws, stream=stream), a.steps)
-    # the FP8 variant of the DNN step (hidden-to-hidden layers in E4M3FN), alone
-    fp8_opts = df.dnn_opts(precision=1)
-    fp8_alone = alone(lambda: dnn.step(Ta, p, Ya, DT, workspace=ws, stream=stream, opts=fp8_opts), a.steps)
-
-    # work actually done by the integrator (useful attempts per cell)
     ns = nsteps.cpu().numpy()
     attempts = int(ns.sum())
-    ops = integrator_lane_ops(mech_h)
-    chem_flops = 2.0 * ops["per_attempt"] * attempts        # an FMA lane-op is 2 FLOP
-    chem_tflops = chem_flops / (chem_ms.mean() * 1e-3) / 1e12
-    dnn_flops = mlp_flops(dnn.dims) * n
-    dnn_tflops = dnn_flops / (dnn_ms.mean() * 1e-3) / 1e12
-
-    # DNN error against the oracle integrator (renormalisation on, as timed, and off)
+    chem_tflops = 2.0 * ops["per_attempt"] * attempts / (chem_ms.mean() * 1e-3) / 1e12
     T_c, Y_c, stc = Tc.cpu().numpy(), Yc.cpu().numpy(), st_c.cpu().numpy()
     T_d, Y_d, std = Td.cpu().numpy(), Yd.cpu().numpy(), st_d.cpu().numpy()
-    Td2, Yd2 = T_in.clone(), Y_in.clone()
-    st2 = torch.zeros(n, dtype=torch.int32, device=dev)
-    dnn.step(Td2, p, Yd2, DT, status=st2, workspace=ws, opts=df.dnn_opts(renormalise=0))
-    Td3, Yd3 = T_in.clone(), Y_in.clone()
-    st3 = torch.zeros(n, dtype=torch.int32, device=dev)
-    dnn.step(Td3, p, Yd3, DT, status=st3, workspace=ws, opts=fp8_opts)
-    torch.cuda.synchronize()
 
-    cpu = None
-    err = None
+    # each form alone on a workload (outside the timed region): the kernels' own efficiency
+    fp8_opts = df.dnn_opts(precision=1)
+
+    def forms_alone(fld, reps):
+        m = fld["T"].size
+        T0 = torch.tensor(fld["T"], dtype=torch.float64, device=dev)
+        p0 = torch.tensor(fld["p"], dtype=torch.float64, device=dev)
+        Y0 = torch.tensor(np.ascontiguousarray(fld["Y"]), dtype=torch.float64, device=dev)
+        Ta, Ya = T0.clone(), Y0.clone()
+        sta = torch.zeros(m, dtype=torch.int32, device=dev)
+        nsa = torch.zeros(2 * m, dtype=torch.int32, device=dev)
+        wsa = dnn.workspace(m)
+        cwa = gm.workspace(m)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+        def timed(fn):
+            out = []
+            for _ in range(reps + 1):
+                Ta.copy_(T0)
+                Ya.copy_(Y0)
+                e0.record(stream)
+                fn()
+                e1.record(stream)
+                torch.cuda.synchronize()
+                out.append(e0.elapsed_time(e1))
+            return float(np.mean(out[1:]))
+
+        res = {"n_cells": m}
+        ms = timed(lambda: gm.chem_step(Ta, p0, Ya, DT, status=sta, n_steps=nsa, workspace=cwa, stream=stream))
+        at = int(nsa.cpu().numpy().sum())
+        tf = 2.0 * ops["per_attempt"] * at / (ms * 1e-3) / 1e12
+        res["integrator"] = {"ms": ms, "cells_per_s": m / (ms * 1e-3), "attempts": at, "tflops": tf,
+                             "fp64_frac": tf / PEAK_FP64_TFLOPS,
+                             "status_counts": np.bincount(sta.cpu().numpy(), minlength=5).tolist()}
+        res["states_integrator"] = (Ta.cpu().numpy(), Ya.cpu().numpy())
+        for key, opts in (("dnn_bf16", None), ("dnn_fp8", fp8_opts)):
+            ms = timed(lambda: dnn.step(Ta, p0, Ya, DT, status=sta, workspace=wsa, stream=stream, opts=opts))
+            tf = dnn_cell_flops * m / (ms * 1e-3) / 1e12
+            res[key] = {"ms": ms, "cells_per_s": m / (ms * 1e-3), "tflops": tf,
+                        "mfma_frac": tf / (PEAK_BF16_TFLOPS if key == "dnn_bf16" else PEAK_FP8_TFLOPS),
+                        "fallback_frac": float((sta == 4).float().mean())}
+            res[f"states_{key}"] = (Ta.cpu().numpy(), Ya.cpu().numpy(), sta.cpu().numpy())
+        # the DNN without renormalisation, for the error statement
+        Ta.copy_(T0)
+        Ya.copy_(Y0)
+        dnn.step(Ta, p0, Ya, DT, status=sta, workspace=wsa, stream=stream, opts=df.dnn_opts(renormalise=0))
+        torch.cuda.synchronize()
+        res["states_dnn_bf16_norenorm"] = (Ta.cpu().numpy(), Ya.cpu().numpy(), sta.cpu().numpy())
+        return res
+
+    fS = fields.snapshot_s()
+    f1 = fields.ignition_cells(mech_h)
+    alone = {"snapshot_0": forms_alone(f, a.steps), "snapshot_s": forms_alone(fS, a.steps),
+             "ignition_1024": forms_alone(f1, a.steps)}
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cpu, err = None, None
     if not a.no_cpu:
-        import oracle
-        om = oracle.Mech(MECH)
-        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        t1 = time.perf_counter()
-        ro = om.chem_step(f["T"], f["p"], f["Y"], DT, nthreads=threads)
-        t_int = time.perf_counter() - t1
-        # the oracle's DNN step (bf16-emulated network) on a strided sample of the field
-        od = oracle.DNN(DNN_W)
-        sample = np.arange(0, n, 16)
-        t1 = time.perf_counter()
-        od.step(om, f["T"][sample], f["p"][sample], f["Y"][:, sample], DT, mode=1, nthreads=threads)
-        t_dnn_s = time.perf_counter() - t1
-        t_dnn = t_dnn_s * n / sample.size
+        tim, ora = run_cpu_leg(threads)
+        t_int, t_dnn = tim["s0_integrator_s"], tim["s0_dnn_s"] * n / tim["s0_dnn_cells"]
+        t_int1 = tim["s0_integrator_1core_s"] * n / tim["s0_integrator_1core_cells"]
+        t_dnn1 = tim["s0_dnn_1core_s"] * n / tim["s0_dnn_1core_cells"]
         cpu = {"value": n / (t_int + t_dnn), "unit": "cells/s", "cores": threads, "kind": "oracle",
-               "sample": f"integrator on all {n} cells ({t_int:.2f} s) + DNN step on every 16th cell "
-                         f"({sample.size} cells, {t_dnn_s:.2f} s, scaled to {n})",
-               "integrator_cells_per_s": n / t_int, "dnn_cells_per_s": n / t_dnn}
-        err = {"renormalised": dnn_error(f["T"], f["Y"], T_d, Y_d, ro["T"], ro["Y"], std),
-               "not_renormalised": dnn_error(f["T"], f["Y"], Td2.cpu().numpy(), Yd2.cpu().numpy(), ro["T"], ro["Y"],
-                                             st2.cpu().numpy()),
-               "fp8_renormalised": dnn_error(f["T"], f["Y"], Td3.cpu().numpy(), Yd3.cpu().numpy(), ro["T"], ro["Y"],
-                                             st3.cpu().numpy())}
-        # the integrator result itself against the oracle (sampled parity at full size)
-        relT = np.abs(T_c - ro["T"]) / ro["T"]
-        mask = ro["Y"] > 1e-10
-        relY = np.where(mask, np.abs(Y_c - ro["Y"]) / np.where(mask, ro["Y"], 1.0), 0.0)
-        err["integrator_max_rel_vs_oracle"] = float(max(relT.max(), relY.max()))
+               "sample": f"snapshot 0: integrator on all {n} cells ({t_int:.2f} s) + BF16-emulated DNN step on every "
+                         f"16th cell ({tim['s0_dnn_cells']} cells, {tim['s0_dnn_s']:.2f} s, scaled to {n}); 1 core: "
+                         f"every 64th / 256th cell, scaled",
+               "build": "gcc -O3 -march=native, OpenMP over cells", "cpu_model": cpu_model(),
+               "integrator_cells_per_s": n / t_int, "dnn_cells_per_s": n / t_dnn,
+               "integrator_cells_per_s_1core": n / t_int1, "dnn_cells_per_s_1core": n / t_dnn1,
+               "snapshot_s_integrator_cells_per_s": tim["sS_cells"] / tim["sS_integrator_s"],
+               "ignition_1024_integrator_cells_per_s": tim["c1_cells"] / tim["c1_integrator_s"]}
+        err = {}
+        for key, fld, tag in (("snapshot_0", f, "s0"), ("snapshot_s", fS, "sS")):
+            To, Yo = ora[f"{tag}_T"], ora[f"{tag}_Y"]
+            al = alone[key]
+            err[key] = {
+                "renormalised": dnn_error(fld["T"], fld["Y"], al["states_dnn_bf16"][0], al["states_dnn_bf16"][1],
+                                          To, Yo, al["states_dnn_bf16"][2]),
+                "not_renormalised": dnn_error(fld["T"], fld["Y"], al["states_dnn_bf16_norenorm"][0],
+                                              al["states_dnn_bf16_norenorm"][1], To, Yo,
+                                              al["states_dnn_bf16_norenorm"][2]),
+                "fp8_renormalised": dnn_error(fld["T"], fld["Y"], al["states_dnn_fp8"][0], al["states_dnn_fp8"][1],
+                                              To, Yo, al["states_dnn_fp8"][2])}
+            Tg, Yg = al["states_integrator"]
+            relT = np.abs(Tg - To) / To
+            mask = Yo > 1e-10
+            relY = np.where(mask, np.abs(Yg - Yo) / np.where(mask, Yo, 1.0), 0.0)
+            err[key]["integrator_max_rel_vs_oracle"] = float(max(relT.max(), relY.max()))
+        To, Yo = ora["c1_T"], ora["c1_Y"]
+        Tg, Yg = alone["ignition_1024"]["states_integrator"]
+        err["ignition_1024_integrator_max_rel_vs_oracle"] = float(max(
+            (np.abs(Tg - To) / To).max(),
+            np.where(Yo > 1e-10, np.abs(Yg - Yo) / np.where(Yo > 1e-10, Yo, 1.0), 0.0).max()))
+    for v in alone.values():
+        for k in [k for k in v if k.startswith("states_")]:
+            del v[k]
 
     batching = None if a.no_batching else batching_study(gm, mech_h, dev)
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     adjoint = None if a.no_adjoint else adjoint_study(gm, mech_h, dev, not a.no_cpu, threads)
     training = None if a.no_training else training_study(gm, DNN_W, mech_h, dev)
     rollouts = None if a.no_rollout else rollout_study(gm, dnn, mech_h, dev)
-    large = None if a.no_large else large_mechanism_study(dev, not a.no_cpu, threads)
+    large = None if a.no_large else large_mechanism_study(dev, not a.no_cpu, threads, n=262144)
 
+    s0 = alone["snapshot_0"]
+    summary = {
+        "value_is": "cells/s of one step = the 65,536-cell field through both forms (integrator and DNN "
+                    "overlapped on two streams)",
+        "integrator_cells_per_s": n / (chem_ms.mean() * 1e-3), "integrator_fp64_frac": chem_tflops / PEAK_FP64_TFLOPS,
+        "integrator_alone_cells_per_s": s0["integrator"]["cells_per_s"],
+        "dnn_bf16_alone_cells_per_s": s0["dnn_bf16"]["cells_per_s"], "dnn_bf16_mfma_frac": s0["dnn_bf16"]["mfma_frac"],
+        "dnn_fp8_alone_cells_per_s": s0["dnn_fp8"]["cells_per_s"], "dnn_fp8_mfma_frac": s0["dnn_fp8"]["mfma_frac"],
+        "snapshot_s_integrator_cells_per_s": alone["snapshot_s"]["integrator"]["cells_per_s"],
+        "snapshot_s_dnn_bf16_cells_per_s": alone["snapshot_s"]["dnn_bf16"]["cells_per_s"],
+        "ignition_1024_integrator_cells_per_s": alone["ignition_1024"]["integrator"]["cells_per_s"],
+        "ignition_1024_dnn_bf16_cells_per_s": alone["ignition_1024"]["dnn_bf16"]["cells_per_s"],
+        "dnn_max_abs_dT_K": None if err is None else {k: err[k]["renormalised"]["max_abs_dT_K"]
+                                                      for k in ("snapshot_0", "snapshot_s")},
+    }
     out = {
         "metric": "cells/s per chemistry step: FP64 stiff integrator vs BF16 DNN at stated error",
         "value": n / (ms_step * 1e-3),
@@ -643,39 +759,40 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64+bf16",
         "data": "synthetic",
-        "config": {"workload": "hot-kernel field 256x256=65536 cells, H2/air phi=1, 9 species/24 reactions "
-                               "(seeded), p=1 atm, dt=1e-6 s; step = FP64 RODAS4 integrator + BF16 DNN "
-                               "11-1600-800-400-9 with FP64 fallback",
+        "config": {"workload": "both forms per step: FP64 RODAS4 integrator + BF16 DNN 11-1600-800-400-9 (FP64 "
+                               "fallback), overlapped on 2 streams; hot-kernel field 256x256=65536 cells, snapshot 0, "
+                               "H2/air phi=1, 9 species/24 reactions (seeded), p=1 atm, dt=1e-6 s",
                    "n_cells": n, "dt": DT, "rtol": 1e-8, "mechanism": os.path.basename(MECH),
-                   "dnn": os.path.basename(DNN_W)},
-        "forms": {
-            "fp64_integrator": {"cells_per_s": n / (chem_ms.mean() * 1e-3), "ms": float(chem_ms.mean()),
-                                "ms_alone": chem_alone, "overlap": "the DNN step runs on a second stream beside it",
-                                "attempts_total": attempts, "attempts_per_cell_mean": attempts / n,
-                                "accepted_max": int(ns[:n].max()), "status_counts": np.bincount(stc).tolist()},
-            "bf16_dnn": {"cells_per_s": n / (dnn_ms.mean() * 1e-3), "ms": float(dnn_ms.mean()),
-                         "ms_alone": dnn_alone, "mfma_frac_alone": dnn_flops / (dnn_alone * 1e-3) / 1e12 / PEAK_BF16_TFLOPS,
-                         "tflops": dnn_tflops, "mfma_frac": dnn_tflops / PEAK_BF16_TFLOPS,
-                         "fallback_frac": float(np.mean(std == 4)), "status_counts": np.bincount(std).tolist()},
-            "fp8_dnn": {"layers": "800x1600 and 400x800 in E4M3FN (power-of-two scales), first hidden and output "
-                                  "layer as bf16_dnn", "ms_alone": fp8_alone,
-                        "cells_per_s_alone": n / (fp8_alone * 1e-3),
-                        "tflops_alone": dnn_flops / (fp8_alone * 1e-3) / 1e12,
-                        "status_counts": np.bincount(st3.cpu().numpy()).tolist()},
-        },
+                   "dnn": os.path.basename(DNN_W), "snapshot": "0 (as generated)"},
         "roofline": {"bound": "alu", "kernel": "chem_coop_kernel<9, 2> (FP64 VALU, 16 lanes per cell)",
                      "achieved": chem_tflops,
                      "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": chem_tflops / PEAK_FP64_TFLOPS,
-                     "traffic": measured_traffic(), "lane_ops_per_attempt": ops},
+                     "traffic": measured_traffic(), "lane_ops_per_attempt": ops["per_attempt"],
+                     "forms": {"integrator_in_step": {"ms": float(chem_ms.mean()),
+                                                      "cells_per_s": n / (chem_ms.mean() * 1e-3),
+                                                      "fp64_frac": chem_tflops / PEAK_FP64_TFLOPS,
+                                                      "attempts": attempts},
+                               "dnn_bf16_in_step": {"ms": float(dnn_ms.mean()),
+                                                    "cells_per_s": n / (dnn_ms.mean() * 1e-3),
+                                                    "mfma_frac": dnn_cell_flops * n / (dnn_ms.mean() * 1e-3) / 1e12 /
+                                                    PEAK_BF16_TFLOPS},
+                               **{k: {f: {kk: (round(vv, 6) if isinstance(vv, float) else vv)
+                                          for kk, vv in v[f].items() if kk != "status_counts"}
+                                      for f in ("integrator", "dnn_bf16", "dnn_fp8")}
+                                  for k, v in alone.items()}}},
+        "cpu_baseline": cpu,
         "dnn_error_vs_oracle_integrator": err,
+        "step_status_counts": {"integrator": np.bincount(stc, minlength=5).tolist(),
+                               "dnn_bf16": np.bincount(std, minlength=5).tolist()},
+        "forms_alone": alone,
         "batching_mixing_layer": batching,
         "adjoint": adjoint,
         "dnn_training": training,
         "rollouts_0d": rollouts,
         "large_mechanism": large,
-        "cpu_baseline": cpu,
+        "summary": summary,
     }
     print(json.dumps(out), flush=True)
 

@@ -32,6 +32,8 @@ All fields are returned as float64 structure-of-arrays: ``T[n]`` (K),
 """
 from __future__ import annotations
 
+import os
+
 import numpy as np
 
 P_ATM = 101325.0
@@ -166,3 +168,16 @@ def hydrocarbon_field(mech, n=262144, seed=FIELD_SEED_5, T_range=(300.0, 2400.0)
     Y /= Y.sum(axis=0, keepdims=True)
     return {"T": T, "p": p, "Y": np.ascontiguousarray(Y), "phi": phi, "c": c}
 
+
+
+SNAPSHOT_S = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "h2_field_snapshot_s.npz")
+
+
+def snapshot_s(path=SNAPSHOT_S):
+    """Snapshot S of the 256 x 256 hot-kernel field: the stored state of the field after the oracle
+    integrator advanced it until its hottest cell rose by 500 K (written by
+    oracle/make_snapshot_s.py; this only reads it).  Keys as hot_kernel_field_2d, plus h (each
+    cell's sub-step hint after the last advancing call) and steps/dt of the advance."""
+    z = np.load(path)
+    return {"T": z["T"].copy(), "p": z["p"].copy(), "Y": np.ascontiguousarray(z["Y"]), "h": z["h"].copy(),
+            "shape": tuple(int(v) for v in z["shape"]), "steps": int(z["steps"]), "dt": float(z["dt"])}

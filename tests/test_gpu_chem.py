@@ -106,12 +106,19 @@ def test_parity_ignition_cells(gmech, h2_oracle, h2_mech, mapping):
     assert np.abs(g["rr"][:, same] - o["rr"][:, same]).max() <= 1e-6 * scale
 
 
-@pytest.mark.parametrize("mapping,ordered", [(1, False), (2, False), (2, True)])
-def test_parity_hot_kernel_field(gmech, h2_oracle, h2_mech, mapping, ordered):
-    f = fields.hot_kernel_field_2d(h2_mech)
-    print(f"case: 65536-cell hot-kernel field, dt=1e-6, mapping {mapping}, hottest-first {ordered}", flush=True)
-    g = _gpu_step(gmech, f, 1e-6, opts=_opts(mapping), ordered=ordered)
-    o = h2_oracle.chem_step(f["T"], f["p"], f["Y"], 1e-6, nthreads=0)
+@pytest.mark.parametrize("snapshot,mapping,ordered,hint", [("0", 1, False, False), ("0", 2, False, False),
+                                                            ("0", 2, True, False), ("S", 2, True, False),
+                                                            ("S", 2, True, True), ("S", 1, False, True)])
+def test_parity_hot_kernel_field(gmech, h2_oracle, h2_mech, snapshot, mapping, ordered, hint):
+    """The 65,536-cell field as generated (snapshot 0) and after the oracle advanced it until the
+    hottest cell rose by 500 K (snapshot S: igniting kernels with radicals), every cell compared;
+    with `hint` each cell starts from the sub-step hint the advance left."""
+    f = fields.hot_kernel_field_2d(h2_mech) if snapshot == "0" else fields.snapshot_s()
+    print(f"case: 65536-cell hot-kernel field, snapshot {snapshot}, dt=1e-6, mapping {mapping}, hottest-first "
+          f"{ordered}, hints {hint}", flush=True)
+    h = f["h"] if hint else None
+    g = _gpu_step(gmech, f, 1e-6, h=h, opts=_opts(mapping), ordered=ordered)
+    o = h2_oracle.chem_step(f["T"], f["p"], f["Y"], 1e-6, h_inout=h, nthreads=0)
     assert np.all(g["status"] == 0)
     worst, nflip, tol_err = compare(g, o)
     print(f"max rel err (same step sequence) {worst:.3e}; flipped cells {nflip}; flipped tol-scaled err {tol_err:.3f}")

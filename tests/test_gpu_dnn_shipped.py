@@ -20,8 +20,8 @@ separately, because they differ in what the two sides may disagree on:
   * rr = rho0 (Y' - Y0)/dt: on the GPU from its own Y' to rounding, and against the oracle's
     within rho0 |dY'| / dt.
 Cells outside the network's training box are integrated (fallback) and held to the integrator's
-1e-8.  The field case runs the whole 65,536-cell field in one call, as the benchmark does, and
-compares every 16th cell.
+1e-8.  The field cases run the whole 65,536-cell field (snapshots 0 and S) in one call, as the
+benchmark does, and compare every 16th cell.
 """
 import os
 
@@ -163,6 +163,17 @@ def test_shipped_network_field(gpu_dnn, h2_oracle, h2_mech):
     """The 256 x 256 hot-kernel field in one call; every 16th cell compared."""
     f = fields.hot_kernel_field_2d(h2_mech)
     print("case: shipped network, 65,536-cell field, renormalise 0 and 1", flush=True)
+    g0 = _run_gpu(gpu_dnn, f, 0)
+    g1 = _run_gpu(gpu_dnn, f, 1)
+    idx = np.arange(0, f["T"].size, 16)
+    _check(h2_oracle, h2_mech, f, idx, _take(g0, idx), _take(g1, idx))
+
+
+def test_shipped_network_snapshot_s(gpu_dnn, h2_oracle, h2_mech):
+    """Snapshot S of the field (igniting kernels with radicals) in one call; every 16th cell
+    compared."""
+    f = fields.snapshot_s()
+    print("case: shipped network, snapshot S of the 65,536-cell field, renormalise 0 and 1", flush=True)
     g0 = _run_gpu(gpu_dnn, f, 0)
     g1 = _run_gpu(gpu_dnn, f, 1)
     idx = np.arange(0, f["T"].size, 16)
