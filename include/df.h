@@ -77,8 +77,12 @@ typedef struct {
     int32_t max_steps; /* attempted sub-steps per cell and call, default 100000 */
     int32_t mapping;   /* work mapping of the static schedule: 0 (default) automatic, 1 one cell
                           per lane, 2 sixteen lanes per cell (species count <= 15), 3 one
-                          wavefront (64 lanes) per cell (species count <= 63); automatic takes
-                          16 lanes where compiled, else one cell per lane, else a wavefront */
+                          wavefront (64 lanes) per cell (species count <= 63), 4 thirty-two
+                          lanes per cell (as 2, the second 16 lanes taking half of the rate
+                          constants: a shorter sub-step for stiff cells, half the cells per wave;
+                          16 lanes where the reaction slots do not divide in two); automatic takes
+                          16 lanes where compiled, else one cell per lane, else a wavefront.
+                          Mappings 2 and 4 give the same bits */
     int32_t schedule;  /* 0 (default) or 1: static, one launch that gives each lane (or group of
                           16 lanes) one cell; 2: persistent work queue (needs the workspace):
                           cells sorted by estimated cost (temperature, then step length) are
@@ -275,11 +279,13 @@ df_status df_chem_autotune_workspace_size(const df_mech *mech, int64_t n_cells, 
 
 /*
  * Pick the schedule of df_chem_step / df_chem_step_cells for a workload (the cells-per-wave
- * choice of uneven stiffness: one cell per 16 lanes, or one cell per lane for the cold cells
- * first): time one step of each candidate -- static schedule with the cost order; queue
+ * choice of uneven stiffness: one cell per 16 or 32 lanes, or one cell per lane for the cold
+ * cells first): time one step of each candidate -- static schedule with the cost order, with
+ * the given mapping and (for the automatic or 16-lane mapping) with 32 lanes per cell; queue
  * schedule with every wave as 16-lane groups; queue schedule with a half or a quarter of the
  * waves as 16-lane groups from the start -- on copies of the input, and write the fastest into
- * opts->schedule and opts->coop_blocks (the other fields are kept and used for the trials).
+ * opts->schedule, opts->coop_blocks and opts->mapping (the other fields are kept and used for
+ * the trials).
  *   dt, dt_cells  step length of every cell, or per cell (dt_cells [n] device, nullable)
  *   p, T, Y       the workload, device memory, layouts as df_chem_step; not modified
  *   workspace     device memory of df_chem_autotune_workspace_size bytes, 256-byte aligned

@@ -58,8 +58,9 @@ df_status launch_chem_step(const MechDev &m, const StepArgs &a, int mapping, con
     // mapping 0 picks 16 lanes per cell whenever a kernel is compiled for K: one sub-step
     // then takes a fraction of the latency, which bounds a stiff cell's step time
     if (mapping == 3) return launch_chem_wave(m, a, cidx, dcount, stream);
-    if (mapping == 2 || (mapping == 0 && chem_coop_supported(m)))
-        return launch_chem_coop(m, a, CellQueue{cidx, dcount, nullptr, nullptr, nullptr, 0}, stream);
+    if (mapping == 2 || mapping == 4 || (mapping == 0 && chem_coop_supported(m)))
+        return launch_chem_coop(m, a, CellQueue{cidx, dcount, nullptr, nullptr, nullptr, 0}, stream,
+                                mapping == 4 ? 2 : 1);
     if (a.n > int64_t(64) * 0x7fffffff) return fail(DF_E_UNSUPPORTED, "df_chem_step: too many cells for one launch");
     switch (m.K) {
 #define DF_CASE(k) \
@@ -383,13 +384,15 @@ extern "C" df_status df_chem_autotune(const df_mech *mech, int64_t n_cells, int6
     auto *Yc = reinterpret_cast<double *>(base + order_bytes(n_cells) + al256(size_t(n_cells) * 8));
     const int32_t cap = chem_queue_capacity(mech->dev);
     struct Cand {
-        int32_t schedule, coop_blocks;
+        int32_t schedule, coop_blocks, mapping;
     };
-    std::vector<Cand> cands = {{1, 0}};
+    std::vector<Cand> cands = {{1, 0, opts->mapping}};
+    if (chem_coop_supported(mech->dev) && mech->dev.RPL % 2 == 0 && (opts->mapping == 0 || opts->mapping == 2))
+        cands.push_back({1, 0, 4});
     if (cap > 0) {
-        cands.push_back({2, 0});
-        cands.push_back({2, cap / 2});
-        cands.push_back({2, (3 * cap) / 4});
+        cands.push_back({2, 0, opts->mapping});
+        cands.push_back({2, cap / 2, opts->mapping});
+        cands.push_back({2, (3 * cap) / 4, opts->mapping});
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     float best_ms = -1.0f;
@@ -400,6 +403,7 @@ extern "C" df_status df_chem_autotune(const df_mech *mech, int64_t n_cells, int6
         df_chem_opts o = *opts;
         o.schedule = cands[c].schedule;
         o.coop_blocks = cands[c].coop_blocks;
+        o.mapping = cands[c].mapping;
         for (int rep = 0; rep < 2 && he == hipSuccess && st == DF_OK; ++rep) {
             he = hipMemcpyAsync(Tc, T, size_t(n_cells) * 8, hipMemcpyDeviceToDevice, s);
             if (he == hipSuccess)
@@ -427,5 +431,6 @@ extern "C" df_status df_chem_autotune(const df_mech *mech, int64_t n_cells, int6
     if (he != hipSuccess) return fail(DF_E_HIP, std::string(who) + ": " + hipGetErrorString(he));
     opts->schedule = best.schedule;
     opts->coop_blocks = best.coop_blocks;
+    opts->mapping = best.mapping;
     return DF_OK;
 }

@@ -24,6 +24,11 @@
 // control flow (error norm, step size, accept/reject) is computed from the same
 // LDS data in the same order by all 16 lanes, so a cell's lanes never diverge.
 // Cells of a wave communicate only through their own LDS region.
+// With two halves per cell (H = 2: 32 lanes, two cells per wave) the second 16 lanes take
+// the second slot of reactions, so each lane evaluates half as many rate constants in the
+// rate phases that dominate an attempt; every other phase runs replicated in both halves.
+// Each reaction's arithmetic and every sum's order are those of the 16-lane layout, so the
+// two layouts give the same bits.
 #include <cmath>
 
 #include "df_internal.h"
@@ -33,8 +38,8 @@
 namespace df {
 namespace {
 
-constexpr int G = kCoopLanes;       // lanes per cell
-constexpr int kCellsPerBlock = 4;   // one wave64 per block
+constexpr int G = kCoopLanes;       // lanes of a cell that hold the rows (the cell's first half)
+constexpr int kCellsPerBlock = 4;   // one wave64 per block, 16-lane cells
 constexpr int kMaxRPL = 4;          // reaction slots per lane instantiated (M <= 64)
 
 // Order LDS accesses of the lanes of a wave: the wave executes in lockstep and LDS
@@ -51,9 +56,15 @@ __device__ __forceinline__ void wave_sync() {
 __host__ __device__ constexpr int odd(int x) { return x | 1; }
 constexpr int kSpS = kSpTab + 1;  // 21 doubles per species row
 
-template <int K, int RPL>
+// H: halves (of 16 lanes) per cell; the lanes of half h evaluate reaction slots h, h + H, ...
+template <int K, int RPL, int H = 1>
 struct Coop {
+    static_assert(H == 1 || H == 2, "one or two halves per cell");
+    static_assert(RPL % H == 0, "the reaction slots divide between the halves");
     static constexpr int N = K + 1;
+    static constexpr int GL = G * H;       // lanes per cell
+    static constexpr int RL = RPL / H;     // reaction slots per lane
+    static constexpr int CPB = kCellsPerBlock / H;  // cells per block
     static constexpr int MP = G * RPL;     // stored reactions incl. inert padding
     static constexpr int RS = odd(K + 4);  // record: dq/dc_0..K-1, q, dq/dT, S, scratch
     static constexpr int EFS = odd(K + 4);
@@ -74,7 +85,8 @@ struct Coop {
     static constexpr int oVec2 = oVec + N;
     static constexpr int oRed = oVec2 + N;
     static constexpr int oClaim = oRed + 3 * N;  // a claimed cell index (int64), broadcast to the group
-    static constexpr int kEnd = oClaim + 1;
+    static constexpr int oDH = oClaim + 1;       // reaction enthalpies dH_j/(R T) (two halves only)
+    static constexpr int kEnd = oDH + (H > 1 ? MP : 0);
     // cells of a wave start 10 doubles (20 banks) apart modulo the 64 banks
     static constexpr int kStride = kEnd + ((10 - kEnd % 32) + 32) % 32;
 
@@ -85,7 +97,7 @@ struct Coop {
     static constexpr int tEw = tEff + MP * EFS * 8;
     static constexpr int tCi = tEw + MP * EWS * 8;
     static constexpr int tBytes = (tCi + MP * kCiInt * 4 + 15) & ~15;
-    static constexpr size_t lds_bytes() { return size_t(tBytes) + size_t(kStride) * kCellsPerBlock * 8; }
+    static constexpr size_t lds_bytes() { return size_t(tBytes) + size_t(kStride) * CPB * 8; }
 
     struct Tab {
         const double *sp, *cr, *eff, *ew;
@@ -194,9 +206,9 @@ struct Coop {
         }
     }
 
-    // component r of f(y) in lane r (r < N); yo = y[r]
-    __device__ static double rhs(const Tab &tb, double *sh, int r, double p, double ip, const double (&y)[N], double yo,
-                                 const int (&li)[LM], const double (&lc)[LM]) {
+    // component r of f(y) in lane r (r < N); yo = y[r]; rl is the lane within the cell
+    __device__ static double rhs(const Tab &tb, double *sh, int r, int rl, double p, double ip, const double (&y)[N],
+                                 double yo, const int (&li)[LM], const double (&lc)[LM]) {
         St s;
         state(tb, p, ip, y, s);
         const bool spl = (r >= 1 && r <= K);
@@ -206,21 +218,29 @@ struct Coop {
             sh[oC + r] = s.c6 * yo * sp[1];
             sh[oCpt + r] = yo * cpR * sp[1];
         }
-        Rate rt[RPL];
+        Rate rt[RL];
 #pragma unroll
-        for (int q = 0; q < RPL; ++q) rate<false>(tb, r + G * q, s, y, rt[q]);
+        for (int q = 0; q < RL; ++q) rate<false>(tb, rl + GL * q, s, y, rt[q]);
         wave_sync();
         double hs = 0.0;
 #pragma unroll
-        for (int q = 0; q < RPL; ++q) {
-            const int jd = r + G * q;
+        for (int q = 0; q < RL; ++q) {
+            const int jd = rl + GL * q;
             const int *sl = rt[q].sl;
             const double Pf = sh[oC + sl[0]] * sh[oC + sl[1]] * sh[oC + sl[2]];
             const double Pb = sh[oC + sl[3]] * sh[oC + sl[4]] * sh[oC + sl[5]];
             double X = rt[q].kf * Pf - rt[q].kr * Pb;
             X = (rt[q].type == 1) ? X * rt[q].Mc : X;
-            hs = fma(X, rt[q].dH, hs);
+            if (H == 1) hs = fma(X, rt[q].dH, hs);
             sh[oQ + jd] = X;
+            if (H > 1) sh[oDH + jd] = rt[q].dH;
+        }
+        if (H > 1) {
+            // the partial sum of lane r over its reactions r, r + 16, ... in slot order, as the
+            // 16-lane layout forms it in registers
+            wave_sync();
+#pragma unroll
+            for (int q = 0; q < RPL; ++q) hs = fma(sh[oQ + r + G * q], sh[oDH + r + G * q], hs);
         }
         sh[oQ + MP + 1 + r] = hs;
         double c0 = 0.0, c1 = 0.0;
@@ -244,8 +264,8 @@ struct Coop {
     // the analytic Jacobian J = d f/d y, row-major in LDS (rows), and f_r.  Derivatives are
     // taken in concentration space and mapped to (T, Y); species lane k writes row k, lane c
     // then adds the T-row entry of column c from f_T = -sum_k h_k f_k / cp.
-    __device__ static double jacobian(const Tab &tb, double *sh, int r, double p, double ip, const double (&y)[N],
-                                      double yo, const int (&li)[LM], const double (&lc)[LM]) {
+    __device__ static double jacobian(const Tab &tb, double *sh, int r, int rl, double p, double ip,
+                                      const double (&y)[N], double yo, const int (&li)[LM], const double (&lc)[LM]) {
         St s;
         state(tb, p, ip, y, s);
         const bool spl = (r >= 1 && r <= K);
@@ -262,12 +282,12 @@ struct Coop {
             sh[oHm + r] = hm;
             sh[oDcp + r] = yo * dcpR * kR * sp[1];
         }
-        Rate rt[RPL];
-        int ecol[RPL][kCoopEnt], emsk[RPL][kCoopEnt];
-        double eeff[RPL][kCoopEnt], nrp[RPL][2], effr[RPL][K];
+        Rate rt[RL];
+        int ecol[RL][kCoopEnt], emsk[RL][kCoopEnt];
+        double eeff[RL][kCoopEnt], nrp[RL][2], effr[RL][K];
 #pragma unroll
-        for (int q = 0; q < RPL; ++q) {
-            const int jd = r + G * q;
+        for (int q = 0; q < RL; ++q) {
+            const int jd = rl + GL * q;
             rate<true>(tb, jd, s, y, rt[q]);
             const int *ci = tb.ci + jd * kCiInt;
             const double *ef = tb.eff + jd * EFS;
@@ -284,8 +304,8 @@ struct Coop {
         }
         wave_sync();
 #pragma unroll
-        for (int q = 0; q < RPL; ++q) {
-            const int jd = r + G * q;
+        for (int q = 0; q < RL; ++q) {
+            const int jd = rl + GL * q;
             const Rate &k = rt[q];
             const int *sl = k.sl;
             const double c0 = sh[oC + sl[0]], c1 = sh[oC + sl[1]], c2 = sh[oC + sl[2]];
@@ -456,9 +476,9 @@ struct Coop {
 
 // Tables staged in LDS once per block (read by all cells of the block), and the constant
 // slots of the cell regions.
-template <int K, int RPL>
-__device__ typename Coop<K, RPL>::Tab stage_tables(const MechDev &mg, double *lds, int lane) {
-    using C = Coop<K, RPL>;
+template <int K, int RPL, int H = 1>
+__device__ typename Coop<K, RPL, H>::Tab stage_tables(const MechDev &mg, double *lds, int lane) {
+    using C = Coop<K, RPL, H>;
     constexpr int MP = C::MP;
     auto *dst = reinterpret_cast<unsigned char *>(lds);
     // copy rows x cols from a dense table to an LDS table with row stride `st`
@@ -494,9 +514,9 @@ __device__ __forceinline__ void load_lists(const MechDev &mg, int r, int (&li)[k
     }
 }
 
-template <int K, int RPL>
+template <int K, int RPL, int H = 1>
 __device__ void init_cell_region(double *sh, int r) {
-    using C = Coop<K, RPL>;
+    using C = Coop<K, RPL, H>;
     if (r == 0) {
         sh[C::oC] = 1.0;
         sh[C::oCpt] = 0.0;
@@ -598,17 +618,17 @@ __device__ void group_finish(const StepArgs &a, int r, const GroupTask<K> &c, in
 // One RODAS4 attempt of the group's cell (the first attempt of a cell without a step hint
 // also picks the initial step from f(y0)).  Returns true when the cell is done and its
 // results have been written.
-template <int K, int RPL>
-__device__ bool group_attempt(const StepArgs &a, const typename Coop<K, RPL>::Tab &tb, double *sh, int r,
+template <int K, int RPL, int H = 1>
+__device__ bool group_attempt(const StepArgs &a, const typename Coop<K, RPL, H>::Tab &tb, double *sh, int r, int rl,
                               const int (&li)[kCoopList], const double (&lc)[kCoopList], GroupTask<K> &c) {
-    using C = Coop<K, RPL>;
+    using C = Coop<K, RPL, H>;
     constexpr int N = K + 1;
     const Opts &o = a.o;
     if (c.acc + c.rej >= o.max_steps) {
         group_finish<K>(a, r, c, DF_CELL_MAX_STEPS);
         return true;
     }
-    const double f0 = C::jacobian(tb, sh, r, c.p, c.ip, c.y, c.yr, li, lc);
+    const double f0 = C::jacobian(tb, sh, r, rl, c.p, c.ip, c.y, c.yr, li, lc);
     if (c.fresh) {
         // initial sub-step from the weighted norms of y0 and f(y0)
         const double sc = c.atol + o.rtol * fabs(c.yr);
@@ -637,7 +657,7 @@ __device__ bool group_attempt(const StepArgs &a, const typename Coop<K, RPL>::Ta
             for (int j = 0; j < s; ++j) ysr = fma(Rodas4::a[s][j], u[j], ysr);
             double ys[N];
             C::gather(sh + C::oVec, r, ysr, ys);
-            fs = C::rhs(tb, sh, r, c.p, c.ip, ys, ysr, li, lc);
+            fs = C::rhs(tb, sh, r, rl, c.p, c.ip, ys, ysr, li, lc);
         }
         double cu = 0.0;
 #pragma unroll
@@ -700,26 +720,28 @@ __device__ bool group_attempt(const StepArgs &a, const typename Coop<K, RPL>::Ta
     return false;
 }
 
-// Static schedule: group s of the launch (four per block) integrates cell cidx[s] (or s).
-template <int K, int RPL>
+// Static schedule: cell s of the launch (four 16-lane or two 32-lane cells per block) is cell
+// cidx[s] (or s).
+template <int K, int RPL, int H>
 __global__ __launch_bounds__(64) void chem_coop_kernel(MechDev mg, StepArgs a, CellQueue q) {
-    using C = Coop<K, RPL>;
+    using C = Coop<K, RPL, H>;
     extern __shared__ double lds[];
     const int lane = threadIdx.x;
-    const int r = lane & (G - 1);
+    const int r = lane & (G - 1);        // row of the cell held by the lane (both halves)
+    const int rl = lane & (C::GL - 1);   // lane within the cell
     const int64_t limit = q.dcount ? int64_t(*q.dcount) : a.n;
-    if (int64_t(blockIdx.x) * kCellsPerBlock >= limit) return;  // whole block idle (e.g. no fallback cells)
-    const typename C::Tab tb = stage_tables<K, RPL>(mg, lds, lane);
-    double *sh = lds + C::tBytes / 8 + (lane / G) * C::kStride;
-    const int64_t slot = int64_t(blockIdx.x) * kCellsPerBlock + lane / G;
-    if (slot >= limit) return;  // the 16 lanes of a cell leave together
-    init_cell_region<K, RPL>(sh, r);
+    if (int64_t(blockIdx.x) * C::CPB >= limit) return;  // whole block idle (e.g. no fallback cells)
+    const typename C::Tab tb = stage_tables<K, RPL, H>(mg, lds, lane);
+    double *sh = lds + C::tBytes / 8 + (lane / C::GL) * C::kStride;
+    const int64_t slot = int64_t(blockIdx.x) * C::CPB + lane / C::GL;
+    if (slot >= limit) return;  // the lanes of a cell leave together
+    init_cell_region<K, RPL, H>(sh, r);
     int li[kCoopList];
     double lc[kCoopList];
     load_lists(mg, r, li, lc);
     GroupTask<K> c;
     bool have = group_load<K>(a, tb.sp, r, q.cidx ? int64_t(q.cidx[slot]) : slot, c);
-    while (have) have = !group_attempt<K, RPL>(a, tb, sh, r, li, lc, c);
+    while (have) have = !group_attempt<K, RPL, H>(a, tb, sh, r, rl, li, lc, c);
 }
 
 // Queue schedule: a persistent grid.  Blocks [0, head_blocks) run four 16-lane groups that
@@ -771,7 +793,7 @@ __global__ __launch_bounds__(64) void chem_queue_kernel(MechDev mg, StepArgs a, 
     };
     bool have = next();
     while (have)
-        if (group_attempt<K, RPL>(a, tb, sh, r, li, lc, c)) have = next();
+        if (group_attempt<K, RPL>(a, tb, sh, r, r, li, lc, c)) have = next();
 }
 
 }  // namespace
@@ -809,15 +831,27 @@ bool chem_coop_supported(const MechDev &m) {
     return b > 0 && b <= kCoopMaxLds;
 }
 
-template <int K, int RPL>
-static df_status launch_coop_k(const MechDev &m, const StepArgs &a, const CellQueue &q, hipStream_t stream) {
-    const int64_t blocks = (a.n + kCellsPerBlock - 1) / kCellsPerBlock;
+template <int K, int RPL, int H>
+static df_status launch_coop_kh(const MechDev &m, const StepArgs &a, const CellQueue &q, hipStream_t stream) {
+    constexpr int cpb = Coop<K, RPL, H>::CPB;
+    const int64_t blocks = (a.n + cpb - 1) / cpb;
     if (blocks > 0x7fffffff) return fail(DF_E_UNSUPPORTED, "chem_step: too many cells for one launch");
-    const size_t lds = Coop<K, RPL>::lds_bytes();
-    hipLaunchKernelGGL((chem_coop_kernel<K, RPL>), dim3(unsigned(blocks)), dim3(64), lds, stream, m, a, q);
+    const size_t lds = Coop<K, RPL, H>::lds_bytes();
+    hipLaunchKernelGGL((chem_coop_kernel<K, RPL, H>), dim3(unsigned(blocks)), dim3(64), lds, stream, m, a, q);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(DF_E_HIP, std::string("chem_step launch: ") + hipGetErrorString(e));
     return DF_OK;
+}
+
+// 32-lane cells when asked for and the reaction slots divide between two halves (the taped
+// step keeps the 16-lane layout of the adjoint's tape writer)
+template <int K, int RPL>
+static df_status launch_coop_k(const MechDev &m, const StepArgs &a, const CellQueue &q, hipStream_t stream,
+                               int halves) {
+    if constexpr (RPL % 2 == 0) {
+        if (halves == 2 && !a.tape) return launch_coop_kh<K, RPL, 2>(m, a, q, stream);
+    }
+    return launch_coop_kh<K, RPL, 1>(m, a, q, stream);
 }
 
 // LDS of the persistent kernel: the larger of the two bodies
@@ -867,13 +901,14 @@ static df_status launch_queue_k(const MechDev &m, const StepArgs &a, const CellQ
         default: return CALL(k, 4);            \
     }
 
-df_status launch_chem_coop(const MechDev &m, const StepArgs &a, const CellQueue &q, hipStream_t stream) {
+df_status launch_chem_coop(const MechDev &m, const StepArgs &a, const CellQueue &q, hipStream_t stream,
+                           int halves) {
     if (a.n == 0) return DF_OK;
     if (!chem_coop_supported(m))
         return fail(DF_E_UNSUPPORTED, "chem_step: no cooperative kernel for " + std::to_string(m.K) + " species, " +
                                           std::to_string(m.M) + " reactions (needs K in {2, 4, 9}, M <= 64, at most " +
                                           std::to_string(kCoopList) + " reactions per species)");
-#define DF_CALL(k, rpl) launch_coop_k<k, rpl>(m, a, q, stream)
+#define DF_CALL(k, rpl) launch_coop_k<k, rpl>(m, a, q, stream, halves)
     switch (m.K) {
 #define DF_CASE(k)              \
     case k:                     \

@@ -186,10 +186,12 @@ bool chem_wave_supported(const MechDev &m);
 df_status launch_chem_wave(const MechDev &m, const StepArgs &a, const int32_t *cidx, const int32_t *dcount,
                            hipStream_t stream);
 
-// cooperative integrator (df_chem_coop.hip): 16 lanes per cell, for the species counts and
-// table sizes it is instantiated for
+// cooperative integrator (df_chem_coop.hip): 16 lanes per cell (halves = 1), or 32 (halves = 2, where
+// the reaction slots divide between two halves and no tape is written), for the species counts
+// and table sizes it is instantiated for
 bool chem_coop_supported(const MechDev &m);
-df_status launch_chem_coop(const MechDev &m, const StepArgs &a, const CellQueue &q, hipStream_t stream);
+df_status launch_chem_coop(const MechDev &m, const StepArgs &a, const CellQueue &q, hipStream_t stream,
+                           int halves = 1);
 // persistent work-queue launch mixing the 16-lane and the one-cell-per-lane bodies
 // (df_chem_coop.hip): blocks resident at once on the current device, and the launch
 int32_t chem_queue_capacity(const MechDev &m);

@@ -26,7 +26,7 @@ def _torch():
     return torch
 
 
-MAPPINGS = [1, 2]   # one cell per lane; sixteen lanes per cell
+MAPPINGS = [1, 2, 4]   # one cell per lane; sixteen lanes per cell; thirty-two lanes per cell
 
 
 def _opts(mapping, **kw):
@@ -107,7 +107,8 @@ def test_parity_ignition_cells(gmech, h2_oracle, h2_mech, mapping):
 
 
 @pytest.mark.parametrize("snapshot,mapping,ordered,hint", [("0", 1, False, False), ("0", 2, False, False),
-                                                            ("0", 2, True, False), ("S", 2, True, False),
+                                                            ("0", 2, True, False), ("0", 4, True, False),
+                                                            ("S", 2, True, False), ("S", 4, True, True),
                                                             ("S", 2, True, True), ("S", 1, False, True)])
 def test_parity_hot_kernel_field(gmech, h2_oracle, h2_mech, snapshot, mapping, ordered, hint):
     """The 65,536-cell field as generated (snapshot 0) and after the oracle advanced it until the

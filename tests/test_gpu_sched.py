@@ -61,6 +61,7 @@ def _run(gm, f, opts, ld=None, rr=False, dt=None):
 SCHEDULES = [
     ("static, one cell per lane", dict(schedule=1, mapping=1)),
     ("static, 16 lanes per cell", dict(schedule=1, mapping=2)),
+    ("static, 32 lanes per cell", dict(schedule=1, mapping=4)),
     ("queue, all waves 16-lane groups", dict(schedule=2, coop_blocks=0)),
     ("queue, 8 waves 16-lane groups from the start", dict(schedule=2, coop_blocks=8)),
     ("queue, every wave first takes cold cells per lane", dict(schedule=2, coop_blocks=-1)),
@@ -101,7 +102,9 @@ def test_unusable_step_lengths(h2_path, h2_mech):
 
 
 def test_queue_equals_static_bitwise(h2_path, h2_mech):
-    """The 16-lane body does the same arithmetic for a cell whichever group takes it."""
+    """The 16-lane body does the same arithmetic for a cell whichever group takes it, and the
+    32-lane layout (the second 16 lanes taking half the rate constants) the same as the 16-lane
+    one."""
     import paper_2210_07094_amd as df
     gm = df.Mechanism(h2_path)
     f = fields.hot_kernel_field_2d(h2_mech, nx=64, ny=64)
@@ -109,8 +112,10 @@ def test_queue_equals_static_bitwise(h2_path, h2_mech):
     a = _run(gm, f, df.chem_opts(schedule=1, mapping=2))
     b = _run(gm, f, df.chem_opts(schedule=2, coop_blocks=0))
     c = _run(gm, f, df.chem_opts(schedule=2, coop_blocks=5))
+    d = _run(gm, f, df.chem_opts(schedule=1, mapping=4))
     for k in ("status", "n_acc", "n_rej", "T", "Y"):
         assert np.array_equal(a[k], b[k]), k
+        assert np.array_equal(a[k], d[k]), k
     # with five group waves the cold cells go one per lane first (rounding may differ there);
     # the hot cells go to 16-lane groups in every schedule: bitwise equal results
     assert np.array_equal(a["status"], c["status"])
@@ -163,7 +168,7 @@ def test_autotune_picks_a_valid_schedule(h2_path, h2_mech, h2_oracle):
     dt = torch.tensor(f["dt"], device=dev)
     o = gm.autotune(T, p, Y, dt)
     torch.cuda.synchronize()
-    assert o.schedule in (1, 2) and o.coop_blocks >= -1
+    assert o.schedule in (1, 2) and o.coop_blocks >= -1 and o.mapping in (0, 4)
     # inputs untouched
     assert np.array_equal(T.cpu().numpy(), f["T"]) and np.array_equal(Y.cpu().numpy(), f["Y"])
     g = _run(gm, f, o)
