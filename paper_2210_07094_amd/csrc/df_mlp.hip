@@ -2,13 +2,15 @@
 //
 // C[M][N] = act(A[M][K] . B[N][K]^T + bias[N]), A = activations (one row per
 // cell), B = weights (out x in, row-major), bf16 inputs, fp32 accumulation
-// with v_mfma_f32_16x16x32_bf16, exact-erf GELU epilogue, bf16 output.
+// with v_mfma_f32_16x16x32_bf16, GELU epilogue, bf16 output.
 // Block tile 128 x 160 with four wave64s in a 2 x 2 arrangement, each wave
 // owning a 64 x 80 sub-tile (4 x 5 MFMA tiles); operands are staged through
 // LDS 32 or 64 deep in K (64 where K allows it) with the next stage's global
-// loads issued before the current stage's MFMAs.  Tiles sharing the same rows
-// of A are mapped to the same XCD so the A panel is fetched into that XCD's L2
-// once.
+// loads issued before the current stage's MFMAs.  The MFMAs take the weight
+// fragment as their first operand, so that each lane ends with four consecutive
+// outputs of one row: the epilogue converts them with one packed bf16 conversion
+// pair and writes them with one 8-byte store.  Tiles sharing the same rows of A
+// are mapped to the same XCD so the A panel is fetched into that XCD's L2 once.
 #include <cmath>
 
 #include "df_fp8.h"
@@ -26,22 +28,42 @@ constexpr int kThreads = 256;
 constexpr int WM = 64, WN = 80;          // per-wave sub-tile
 constexpr int TM = WM / 16, TN = WN / 16;  // MFMA tiles per wave
 
-// float -> bf16, round to nearest even (NaN kept quiet)
-__device__ __forceinline__ bf16_t to_bf16(float x) {
-    unsigned u = __float_as_uint(x);
-    if ((u & 0x7f800000u) == 0x7f800000u) return bf16_t((u >> 16) | ((u & 0x007fffffu) ? 0x40u : 0u));
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return bf16_t(u >> 16);
-}
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+
+// GELU(x) = x Phi(x) of the inference epilogue without branches: Phi(x) = erfc(-x/sqrt 2) / 2,
+// with erfc(a) for a >= 0 from the Chebyshev fit erfcc of Press et al., Numerical Recipes
+// (Sec. 6.2), erfc(a) = t exp(-a^2 + P(t)), t = 1 / (1 + a/2), fractional error below 1.2e-7
+// for every a >= 0; for x >= 0, Phi = 1 - erfc(x/sqrt 2) / 2.  Its error is far below the bf16
+// rounding that follows.  NaN stays NaN; GELU(+inf) = +inf, GELU(-inf) = NaN as x Phi(x) gives.
+__device__ __forceinline__ float gelu_erfc(float x) {
+    const float z = x * 0.70710678118654752f;
+    const float a = fabsf(z);
+    const float t = __builtin_amdgcn_rcpf(1.0f + 0.5f * a);
+    float q = 0.17087277f;
+    q = fmaf(q, t, -0.82215223f);
+    q = fmaf(q, t, 1.48851587f);
+    q = fmaf(q, t, -1.13520398f);
+    q = fmaf(q, t, 0.27886807f);
+    q = fmaf(q, t, -0.18628806f);
+    q = fmaf(q, t, 0.09678418f);
+    q = fmaf(q, t, 0.37409196f);
+    q = fmaf(q, t, 1.00002368f);
+    q = fmaf(q, t, -1.26551223f);
+    const float h = 0.5f * t * __expf(fmaf(-a, a, q));  // erfc(a) / 2
+    return x * ((z >= 0.0f) ? 1.0f - h : h);
+}
+
+// four floats to bf16 with two packed conversions (v_cvt_pk_bf16_f32): round to nearest even and
+// NaN kept, except that fp32 subnormal inputs (|x| < 2^-126) are rounded toward zero, at most one
+// bf16 subnormal unit (2^-133) from the nearest-even result
+__device__ __forceinline__ bf16x4 to_bf16x4(floatx4 v) { return __builtin_convertvector(v, bf16x4); }
 
 // d GELU / dx = Phi(x) + x phi(x)
 __device__ __forceinline__ float gelu_grad(float x) {
     return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * expf(-0.5f * x * x);
 }
-
-__device__ __forceinline__ float bf_to_f(bf16_t h) { return __uint_as_float(unsigned(h) << 16); }
 
 // wave-wide max of a non-negative float, combined into one of the kAmaxSlots words of amax
 // (float bits; non-negative floats order as their bit patterns) by one lane; all 64 lanes take part
@@ -150,29 +172,42 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(const bf16_t *__restrict
             for (int i = 0; i < TM; ++i)
 #pragma unroll
                 for (int j = 0; j < TN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[j], af[i], acc[i][j], 0, 0, 0);
         }
     }
 
-    // epilogue: lane l holds column (l % 16) and rows 4 * (l / 16) + r of each 16 x 16 tile
+    // epilogue: with the weights as the first MFMA operand, lane l holds row (l % 16) and the four
+    // columns 4 * (l / 16) + r of each 16 x 16 tile
     float m = 0.0f;
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
-        const int col = col0 + wn * WN + j * 16 + fr;
-        const float bc = (EPI == kEpiGeluGrad) ? 0.0f : bias[col];
+        const int col = col0 + wn * WN + j * 16 + (lane >> 4) * 4;
+        const floatx4 bc = (EPI == kEpiGeluGrad) ? floatx4{0.f, 0.f, 0.f, 0.f}
+                                                 : *reinterpret_cast<const floatx4 *>(bias + col);
 #pragma unroll
         for (int i = 0; i < TM; ++i) {
+            const int64_t row = row0 + wm * WM + i * 16 + fr;
+            const int64_t off = row * ldc + col;
+            floatx4 v = acc[i][j] + bc;
+            if (EPI == kEpiGeluSave) *reinterpret_cast<bf16x4 *>(P + off) = to_bf16x4(v);
+            if (EPI == kEpiGelu) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t row = row0 + wm * WM + i * 16 + (lane >> 4) * 4 + r;
-                float v = acc[i][j][r] + bc;
-                if (EPI == kEpiGeluSave) P[row * ldc + col] = to_bf16(v);
-                if (EPI == kEpiGelu || EPI == kEpiGeluSave) v = gelu(v);
-                if (EPI == kEpiGeluGrad) v *= gelu_grad(bf_to_f(P[row * ldc + col]));
-                const bf16_t h = to_bf16(v);
-                C[row * ldc + col] = h;
-                if (row < m_valid) m = fmaxf(m, fabsf(bf_to_f(h)));
+                for (int r = 0; r < 4; ++r) v[r] = gelu_erfc(v[r]);
             }
+            if (EPI == kEpiGeluSave) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) v[r] = gelu(v[r]);
+            }
+            if (EPI == kEpiGeluGrad) {
+                const bf16x4 pv = *reinterpret_cast<const bf16x4 *>(P + off);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) v[r] *= gelu_grad(float(pv[r]));
+            }
+            const bf16x4 h = to_bf16x4(v);
+            *reinterpret_cast<bf16x4 *>(C + off) = h;
+            if (amax && row < m_valid)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) m = fmaxf(m, fabsf(float(h[r])));
         }
     }
     if (amax) amax_combine(m, amax);
@@ -303,24 +338,29 @@ __global__ __launch_bounds__(kThreads) void gemm_fp8_kernel(const bf16_t *__rest
             for (int i = 0; i < TM; ++i)
 #pragma unroll
                 for (int j = 0; j < TN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(af[i], bfr[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(bfr[j], af[i], acc[i][j], 0, 0, 0);
         }
     }
 
     float m = 0.0f;
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
-        const int col = col0 + wn * WN + j * 16 + fr;
-        const float sc = ldexpf(1.0f, ea + wexp[col]), bc = bias[col];
+        const int col = col0 + wn * WN + j * 16 + (lane >> 4) * 4;
+        const floatx4 bc = *reinterpret_cast<const floatx4 *>(bias + col);
+        floatx4 sc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sc[r] = ldexpf(1.0f, ea + wexp[col + r]);
 #pragma unroll
         for (int i = 0; i < TM; ++i) {
+            const int64_t row = row0 + wm * WM + i * 16 + fr;
+            floatx4 v;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t row = row0 + wm * WM + i * 16 + (lane >> 4) * 4 + r;
-                const bf16_t h = to_bf16(gelu(acc[i][j][r] * sc + bc));
-                C[row * ldc + col] = h;
-                if (row < m_valid) m = fmaxf(m, fabsf(bf_to_f(h)));
-            }
+            for (int r = 0; r < 4; ++r) v[r] = gelu_erfc(acc[i][j][r] * sc[r] + bc[r]);
+            const bf16x4 h = to_bf16x4(v);
+            *reinterpret_cast<bf16x4 *>(C + row * ldc + col) = h;
+            if (amax_out && row < m_valid)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) m = fmaxf(m, fabsf(float(h[r])));
         }
     }
     if (amax_out) amax_combine(m, amax_out);
