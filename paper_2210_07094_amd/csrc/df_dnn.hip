@@ -104,50 +104,71 @@ __global__ __launch_bounds__(kPreThreads) void pre_kernel(DnnDevParams prm, int6
     }
 }
 
-// output layer (fp32, bf16 weights) + stage 3
+// output layer + stage 3.  Each wavefront takes 64 consecutive cells: the output layer
+// u = W h (bf16 operands, fp32 sums) runs on the matrix cores as 16 x 16 x 32 MFMAs with the
+// weight rows (zero beyond the K outputs) as the first operand, so that lane l ends with outputs
+// 4 (l / 16) + r of cell l % 16 of each 16-cell tile; the products go through LDS to one lane per
+// cell, which then runs stage 3 in FP64.  The activation rows are read as 16-byte fragments, 16
+// rows x 64 contiguous bytes per load.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+constexpr int kPostThreads = 256;
+
 template <int K>
-__global__ __launch_bounds__(kPreThreads) void post_kernel(DnnDevParams prm, MechDev m, int64_t n, int64_t ld,
-                                                           double dt, const bf16_t *__restrict__ h, int h_ld,
-                                                           const bf16_t *__restrict__ W, const float *__restrict__ b,
-                                                           int k_in, const int8_t *__restrict__ flag,
-                                                           const double *__restrict__ p, double *__restrict__ T,
-                                                           double *__restrict__ Y, double *__restrict__ rr,
-                                                           int32_t *__restrict__ status, int renormalise) {
-    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n || flag[i] != 1) return;
-    // ---- output layer: u = W h + b, fp32 accumulation, each output summed over the inputs in
-    // order; the outputs go in blocks of up to 16 so that their accumulators stay in registers
-    // (each block reads the cell's activations once)
-    constexpr int KB = K < 16 ? K : 16;
-    float u[K];
-    const bf16_t *hr = h + i * int64_t(h_ld);
+__global__ __launch_bounds__(kPostThreads) void post_kernel(DnnDevParams prm, MechDev m, int64_t n, int64_t ld,
+                                                            double dt, const bf16_t *__restrict__ h, int h_ld,
+                                                            const bf16_t *__restrict__ W, const float *__restrict__ b,
+                                                            int k_in, const int8_t *__restrict__ flag,
+                                                            const double *__restrict__ p, double *__restrict__ T,
+                                                            double *__restrict__ Y, double *__restrict__ rr,
+                                                            int32_t *__restrict__ status, int renormalise) {
+    constexpr int NT = (K + 15) / 16;          // 16-output tiles
+    constexpr int NP = (K % 2) ? K : K + 1;    // LDS row stride in floats (odd: conflict-free reads)
+    __shared__ float su[kPostThreads / 64][64 * NP];
+    const int lane = int(threadIdx.x) & 63, wv = int(threadIdx.x) >> 6;
+    const int fr = lane & 15, fg = lane >> 4;
+    const int64_t cell0 = int64_t(blockIdx.x) * kPostThreads + int64_t(wv) * 64;
+    {
+        floatx4 acc[4][NT];
 #pragma unroll
-    for (int k0 = 0; k0 < K; k0 += KB) {
-        float acc[KB];
+        for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-        for (int kk = 0; kk < KB; ++kk) acc[kk] = 0.0f;
-        for (int j = 0; j < k_in; j += 8) {
-            const uint4 v = *reinterpret_cast<const uint4 *>(hr + j);
-            const unsigned w4[4] = {v.x, v.y, v.z, v.w};
-            float a[8];
+            for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
+        const bf16x8 zero = {};
+        for (int k0 = 0; k0 < k_in; k0 += 32) {
+            bf16x8 wf[NT], hf[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                a[2 * q] = __uint_as_float(w4[q] << 16);
-                a[2 * q + 1] = __uint_as_float(w4[q] & 0xffff0000u);
+            for (int nt = 0; nt < NT; ++nt) {
+                const int o = nt * 16 + fr;
+                wf[nt] = (o < K) ? *reinterpret_cast<const bf16x8 *>(W + int64_t(o) * k_in + k0 + fg * 8) : zero;
             }
 #pragma unroll
-            for (int kk = 0; kk < KB; ++kk) {
-                if (k0 + kk < K) {
-                    const bf16_t *wr = W + int64_t(k0 + kk) * k_in + j;
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) acc[kk] = fmaf(bf2f(wr[q]), a[q], acc[kk]);
-                }
+            for (int mt = 0; mt < 4; ++mt) {
+                const int64_t c = cell0 + mt * 16 + fr;
+                hf[mt] = (c < n) ? *reinterpret_cast<const bf16x8 *>(h + c * h_ld + k0 + fg * 8) : zero;
             }
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[nt], hf[mt], acc[mt][nt], 0, 0, 0);
         }
 #pragma unroll
-        for (int kk = 0; kk < KB; ++kk)
-            if (k0 + kk < K) u[k0 + kk] = acc[kk];
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int o = nt * 16 + fg * 4 + r;
+                    if (o < K) su[wv][(mt * 16 + fr) * NP + o] = acc[mt][nt][r];
+                }
     }
+    __syncthreads();
+    const int64_t i = cell0 + lane;
+    if (i >= n || flag[i] != 1) return;
+    float u[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) u[k] = su[wv][lane * NP + k];
     // ---- stage 3, FP64
     const double T0 = T[i], iT0 = 1.0 / T0;
     // 1/lambda as an exact small integer (lambda = 0.1 gives 10): the power by squaring
@@ -353,7 +374,7 @@ df_status launch_dnn_k(const df_dnn *d, const df_mech *m, int64_t n, int64_t ld,
         in_ld = out_ld;
     }
     const DnnLayer &Lo = d->layers.back();
-    hipLaunchKernelGGL(post_kernel<K>, dim3(unsigned((n + kPreThreads - 1) / kPreThreads)), dim3(kPreThreads), 0, s,
+    hipLaunchKernelGGL(post_kernel<K>, dim3(unsigned((n + kPostThreads - 1) / kPostThreads)), dim3(kPostThreads), 0, s,
                        d->prm, m->dev, n, ld, dt, in, in_ld, Lo.W, Lo.b, Lo.k_pad, flag, p, T, Y, rr, status,
                        o.renormalise);
     e = hipGetLastError();

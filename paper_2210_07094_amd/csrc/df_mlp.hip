@@ -11,6 +11,7 @@
 // outputs of one row: the epilogue converts them with one packed bf16 conversion
 // pair and writes them with one 8-byte store.  Tiles sharing the same rows of A
 // are mapped to the same XCD so the A panel is fetched into that XCD's L2 once.
+#include <algorithm>
 #include <cmath>
 
 #include "df_fp8.h"
@@ -213,6 +214,89 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(const bf16_t *__restrict
     if (amax) amax_combine(m, amax);
 }
 
+// Inference layer with a shallow reduction (K = KD <= 64, the first hidden layer: the network's
+// inputs padded to 32 or 64): no K loop to pipeline, so the time is the GELU epilogue and the
+// stores of the M x N outputs.  Each block keeps one 160-column weight panel in registers as MFMA
+// fragments and walks down the row tiles tile_m = g, g + G, ... (G = gridDim.x / n_tiles_n),
+// loading each tile's activation fragments straight from global memory (16 rows x 64 contiguous
+// bytes per load) one tile ahead, so that the loads of the next tile are in flight during the
+// epilogue of the current one; no LDS and no barriers.  Same tile shape, operand order and
+// epilogue (bias, GELU, bf16, optional max |C| over rows < m_valid) as gemm_kernel.
+template <int KD>
+__global__ __launch_bounds__(kThreads) void gemm_shallow_kernel(const bf16_t *__restrict__ A, int lda,
+                                                                const bf16_t *__restrict__ B, int ldb,
+                                                                const float *__restrict__ bias,
+                                                                bf16_t *__restrict__ C, int ldc, int n_tiles_m,
+                                                                int n_tiles_n, uint32_t *__restrict__ amax,
+                                                                int64_t m_valid) {
+    constexpr int KS = KD / 32;  // 32-deep MFMA steps
+    const int tile_n = int(blockIdx.x) % n_tiles_n, g0 = int(blockIdx.x) / n_tiles_n;
+    const int G = int(gridDim.x) / n_tiles_n;
+    const int col0 = tile_n * BN;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
+
+    bf16x8 bfr[KS][TN];
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+            bfr[s][j] = *reinterpret_cast<const bf16x8 *>(B + int64_t(col0 + wn * WN + j * 16 + fr) * ldb + s * 32 + fk);
+    floatx4 bc[TN];
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+        bc[j] = *reinterpret_cast<const floatx4 *>(bias + col0 + wn * WN + j * 16 + (lane >> 4) * 4);
+
+    auto load_a = [&](int tm, bf16x8 (&af)[KS][TM]) {
+        const int64_t r0 = int64_t(tm) * BM + wm * WM + fr;
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+                af[s][i] = *reinterpret_cast<const bf16x8 *>(A + (r0 + i * 16) * lda + s * 32 + fk);
+    };
+    float m = 0.0f;
+    bf16x8 an[KS][TM];
+    if (g0 < n_tiles_m) load_a(g0, an);
+    for (int tm = g0; tm < n_tiles_m; tm += G) {
+        bf16x8 af[KS][TM];
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+#pragma unroll
+            for (int i = 0; i < TM; ++i) af[s][i] = an[s][i];
+        if (tm + G < n_tiles_m) load_a(tm + G, an);
+        floatx4 acc[TM][TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int s = 0; s < KS; ++s)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[s][j], af[s][i], acc[i][j], 0, 0, 0);
+            }
+        const int64_t row0 = int64_t(tm) * BM + wm * WM + fr;
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const int col = col0 + wn * WN + j * 16 + (lane >> 4) * 4;
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                const int64_t row = row0 + i * 16;
+                floatx4 v = acc[i][j] + bc[j];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) v[r] = gelu_erfc(v[r]);
+                const bf16x4 h = to_bf16x4(v);
+                *reinterpret_cast<bf16x4 *>(C + row * ldc + col) = h;
+                if (amax && row < m_valid)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) m = fmaxf(m, fabsf(float(h[r])));
+            }
+        }
+    }
+    if (amax) amax_combine(m, amax);
+}
+
 // A value the E4M3FN conversion takes as is: |x| <= 448 unchanged; 448 < |x| <= 464 rounds to
 // 448 (ties to even) and is passed as 448; a value that would round beyond 448, an infinity or a
 // NaN becomes NaN, the format's only non-finite value, so that it propagates to the cell's
@@ -366,6 +450,26 @@ __global__ __launch_bounds__(kThreads) void gemm_fp8_kernel(const bf16_t *__rest
     if (amax_out) amax_combine(m, amax_out);
 }
 
+// the shallow-reduction layer (K = 32 or 64, shapes checked by the caller): about two blocks per
+// CU, each on one 160-column panel and every G-th row tile
+df_status launch_shallow(const bf16_t *A, int lda, const bf16_t *B, int ldb, const float *bias, bf16_t *C, int ldc,
+                         int64_t M, int N, int K, uint32_t *amax, int64_t m_valid, hipStream_t stream) {
+    const int64_t tm = M / BM;
+    const int tn = N / BN;
+    if (tm > 0x7fffffff) return fail(DF_E_UNSUPPORTED, "gemm: too many row tiles");
+    const int G = int(std::max<int64_t>(1, std::min<int64_t>(tm, std::max(1, 512 / tn))));
+    const dim3 g = dim3(unsigned(int64_t(G) * tn)), b = dim3(kThreads);
+    if (K == 32)
+        hipLaunchKernelGGL(gemm_shallow_kernel<32>, g, b, 0, stream, A, lda, B, ldb, bias, C, ldc, int(tm), tn, amax,
+                           m_valid);
+    else
+        hipLaunchKernelGGL(gemm_shallow_kernel<64>, g, b, 0, stream, A, lda, B, ldb, bias, C, ldc, int(tm), tn, amax,
+                           m_valid);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(DF_E_HIP, std::string("gemm launch: ") + hipGetErrorString(e));
+    return DF_OK;
+}
+
 }  // namespace
 
 df_status launch_gemm_bf16(const bf16_t *A, int lda, const bf16_t *B, int ldb, const float *bias, bf16_t *C, int ldc,
@@ -383,6 +487,8 @@ df_status launch_gemm_bf16_epi(const bf16_t *A, int lda, const bf16_t *B, int ld
     if (M == 0) return DF_OK;
     const int64_t tiles = (M / BM) * (N / BN);
     if (tiles > 0x7fffffff) return fail(DF_E_UNSUPPORTED, "gemm: too many tiles");
+    if (epi == GemmEpi::gelu && (K == 32 || K == 64)) return launch_shallow(A, lda, B, ldb, bias, C, ldc, M, N, K,
+                                                                             nullptr, 0, stream);
     const dim3 g = dim3(unsigned(tiles)), b = dim3(kThreads);
     const bool deep = K % 64 == 0;
 #define DF_GEMM(E)                                                                                              \
@@ -421,6 +527,7 @@ df_status launch_gemm_bf16_amax(const bf16_t *A, int lda, const bf16_t *B, int l
     if (M == 0) return DF_OK;
     const int64_t tiles = (M / BM) * (N / BN);
     if (tiles > 0x7fffffff) return fail(DF_E_UNSUPPORTED, "gemm: too many tiles");
+    if (K == 32 || K == 64) return launch_shallow(A, lda, B, ldb, bias, C, ldc, M, N, K, amax, m_valid, stream);
     if (K % 64 == 0)
         hipLaunchKernelGGL((gemm_kernel<kEpiGelu, 64>), dim3(unsigned(tiles)), dim3(kThreads), 0, stream, A, lda, B,
                            ldb, bias, C, ldc, K, N / BN, static_cast<bf16_t *>(nullptr), amax, m_valid);

@@ -11,9 +11,11 @@ separately, because they differ in what the two sides may disagree on:
     scale s_k = max over cells of sum_j |W_kj h_j| (a float64 forward of the same weights, computed
     here for the bar only), not with max|u_k|: in the trained network the N2, H2 and O2 outputs
     are near-cancellations (s_k is 890, 85 and 33 times max|u_k|), where a single flip is a large
-    fraction of the output.  Per output feature: max |du| <= 2^-8 s_k, 99th percentile
-    <= 2^-12 s_k, median <= 1e-5 max|u| (measured on MI355X: 5.5e-4 s_k, 4.5e-5 s_k and
-    2e-7 max|u| at most);
+    fraction of the output.  The output layer itself sums its fp32 products in another order on
+    the two sides (the GPU's runs on the matrix cores), so most outputs differ by a few fp32
+    rounding units of the same term scale.  Per output feature: max |du| <= 2^-8 s_k,
+    99th percentile <= 2^-12 s_k, median <= 2^-20 s_k (measured on MI355X: 5.5e-4 s_k,
+    4.6e-5 s_k and 1.6e-8 s_k at most);
   * renormalisation, a property of each side on its own: Y'(on) = Y'(off) / sum Y'(off);
   * T from the enthalpy: |T_gpu - T_oracle| within the bound the difference in Y' implies,
     2 sum_k |h_k| |dY_k| / cp (factor 2 for the Newton stopping rule), plus 1e-8 K;
@@ -110,15 +112,14 @@ def _check(om, mech, f, idx, g0, g1):
     u_o = (z(o0["Y"]) - z(Y0) - mu) / sig
     u_g = (z(g0["Y"]) - z(Y0) - mu) / sig
     du = np.where(ok, np.abs(u_g - u_o), 0.0)
-    umax = np.abs(np.where(ok, u_o, 0.0)).max(axis=1)
     sk = _term_scale(net, f, idx[nc])
     sel = du[:, nc]
     print("per output: max |du| / s_k", np.array2string(sel.max(axis=1) / sk, precision=2),
           "p99 / s_k", np.array2string(np.percentile(sel, 99, axis=1) / sk, precision=2),
-          "median / max|u|", np.array2string(np.median(sel, axis=1) / umax, precision=2), flush=True)
+          "median / s_k", np.array2string(np.median(sel, axis=1) / sk, precision=2), flush=True)
     assert np.all(sel.max(axis=1) <= 2.0 ** -8 * sk)
     assert np.all(np.percentile(sel, 99, axis=1) <= 2.0 ** -12 * sk)
-    assert np.all(np.median(sel, axis=1) <= 1e-5 * umax)
+    assert np.all(np.median(sel, axis=1) <= 2.0 ** -20 * sk)
     # renormalisation on each side on its own
     for a, b in ((g0, g1), (o0, o1)):
         s = a["Y"][:, nc].sum(axis=0)
