@@ -1160,19 +1160,23 @@ double orc_fp8_e4m3_round(double x) {
     return copysign(r, x);
 }
 
-/* smallest e with amax <= 448 * 2^e, so that amax * 2^-e lies in the E4M3FN range; 0 for amax 0 */
+/* smallest e with amax <= 448 * 2^e, so that amax * 2^-e lies in the E4M3FN range; 0 for amax 0;
+ * at least -127, the smallest power of two an E8M0 block scale holds (a block whose largest
+ * magnitude is below 448 * 2^-127 keeps the scale 2^-127 and its values round at the FP8 grid) */
 int orc_fp8_scale_exp(double amax) {
     if (!(amax > 0.0) || !isfinite(amax)) return 0; /* no finite scale covers it: the values decide */
     int e = 0;
     while (amax > ldexp(448.0, e)) ++e;
     while (amax <= ldexp(448.0, e - 1)) --e;
-    return e;
+    return e < -127 ? -127 : e;
 }
 
-/* Batched forward with the hidden-to-hidden layers in FP8: layer l (1 <= l <= L-2) quantises its
- * input activations with one power-of-two scale for the whole batch (from the largest magnitude
- * over all n rows) and each weight row with its own power-of-two scale, sums the exact products of
- * the quantised values, and undoes both scales before the bias and GELU.  The first layer and the
+/* Batched forward with the hidden-to-hidden layers in FP8: layer l (1 <= l <= L-2) quantises each
+ * row of its input activations in blocks of 32 consecutive values, block q of row i with its own
+ * power-of-two scale 2^e_iq (from the block's largest magnitude; a last block shorter than 32
+ * takes the values there are), and each weight row with its own power-of-two scale; it sums the
+ * exact products of the quantised values over each block, undoes the block's scale, sums the
+ * blocks, and undoes the weight row's scale before the bias and GELU.  The first layer and the
  * output layer are those of mode 1 (bf16 values, fp32 sums); every hidden activation is rounded
  * to bf16.  xn: n x n_in (a zero row for a cell the network does not predict); u: n x n_out. */
 void orc_mlp_forward_fp8(const orc_dnn *d, int64_t n, const double *xn, double *u) {
@@ -1184,14 +1188,22 @@ void orc_mlp_forward_fp8(const orc_dnn *d, int64_t n, const double *xn, double *
     for (int l = 0; l < d->L; ++l) {
         const int ni = d->dims[l], no = d->dims[l + 1];
         const int fp8 = (l >= 1 && l <= d->L - 2);
-        int ea = 0;
+        const int nb = (ni + 31) / 32;
+        int *ea = NULL;
         double *wq = NULL;
         int *ew = NULL;
         if (fp8) {
-            double amax = 0.0;
-            for (int64_t j = 0; j < n * ni; ++j) amax = fmax(amax, fabs(A[j]));
-            ea = orc_fp8_scale_exp(amax);
-            for (int64_t j = 0; j < n * ni; ++j) A[j] = orc_fp8_e4m3_round(ldexp(A[j], -ea));
+            ea = malloc(sizeof(int) * (size_t)n * nb);
+            for (int64_t i = 0; i < n; ++i)
+                for (int q = 0; q < nb; ++q) {
+                    double *a = &A[i * ni];
+                    const int c1 = (32 * q + 32 < ni) ? 32 * q + 32 : ni;
+                    double amax = 0.0;
+                    for (int c = 32 * q; c < c1; ++c) amax = fmax(amax, fabs(a[c]));
+                    const int e = orc_fp8_scale_exp(amax);
+                    ea[i * nb + q] = e;
+                    for (int c = 32 * q; c < c1; ++c) a[c] = orc_fp8_e4m3_round(ldexp(a[c], -e));
+                }
             wq = malloc(sizeof(double) * (size_t)no * ni);
             ew = malloc(sizeof(int) * no);
             for (int o = 0; o < no; ++o) {
@@ -1209,8 +1221,13 @@ void orc_mlp_forward_fp8(const orc_dnn *d, int64_t n, const double *xn, double *
                 double z;
                 if (fp8) {
                     double acc = 0.0;
-                    for (int c = 0; c < ni; ++c) acc += a[c] * wq[(size_t)o * ni + c];
-                    z = ldexp(acc, ea + ew[o]) + d->b[l][o];
+                    for (int q = 0; q < nb; ++q) {
+                        const int c1 = (32 * q + 32 < ni) ? 32 * q + 32 : ni;
+                        double s = 0.0;
+                        for (int c = 32 * q; c < c1; ++c) s += a[c] * wq[(size_t)o * ni + c];
+                        acc += ldexp(s, ea[i * nb + q]);
+                    }
+                    z = ldexp(acc, ew[o]) + d->b[l][o];
                 } else {
                     const double *w = &d->W[l][(size_t)o * ni];
                     float acc = 0.0f;
@@ -1226,6 +1243,7 @@ void orc_mlp_forward_fp8(const orc_dnn *d, int64_t n, const double *xn, double *
         }
         free(wq);
         free(ew);
+        free(ea);
         double *t = A;
         A = B;
         B = t;

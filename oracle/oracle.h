@@ -126,10 +126,12 @@ float orc_bf16_round(float x);
 void orc_mlp_forward(const orc_dnn *d, const double *x_norm, double *u, int mode);
 /* nearest OCP E4M3FN value of x (ties to even); NaN where the rounded magnitude exceeds 448 or x is not finite */
 double orc_fp8_e4m3_round(double x);
-/* smallest e with amax <= 448 * 2^e (0 for amax 0 or not finite): the power-of-two scale of an FP8 tensor */
+/* smallest e with amax <= 448 * 2^e (0 for amax 0 or not finite, at least -127): the power-of-two
+   scale of an FP8 block */
 int orc_fp8_scale_exp(double amax);
-/* batched forward with the hidden-to-hidden layers in FP8 (per-batch power-of-two activation
-   scale, per-row power-of-two weight scales, exact sums); first and output layers as mode 1.
+/* batched forward with the hidden-to-hidden layers in FP8 (a power-of-two activation scale per
+   row and block of 32 inputs, per-row power-of-two weight scales, exact sums); first and output
+   layers as mode 1.
    xn: n x n_in normalised inputs (zero rows for cells the network does not predict); u: n x n_out */
 void orc_mlp_forward_fp8(const orc_dnn *d, int64_t n, const double *xn, double *u);
 /* T from enthalpy at fixed p and composition: Newton from T_guess; returns iterations or -1 */

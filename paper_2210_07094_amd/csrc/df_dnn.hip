@@ -3,8 +3,8 @@
 // "Chemistry Integration"):
 //   1. pre   : x = (T, p, BoxCox(Y)), training-range test, z-score, bf16
 //   2. layers: hidden layers as bf16 MFMA GEMMs with GELU (df_mlp.hip), output
-//              layer in fp32 inside the post kernel; with FP8 precision the layers between
-//              two hidden layers run on E4M3FN operands (df_fp8.h)
+//              layer on the matrix cores inside the post kernel; with FP8 precision the
+//              layers between two hidden layers run on block-scaled E4M3FN operands (df_fp8.h)
 //   3. post  : inverse normalisation and Box-Cox, optional renormalisation of Y,
 //              T from enthalpy conservation at fixed p (FP64 Newton), rr
 // Cells outside the training range are compacted into an index list and
@@ -44,12 +44,9 @@ __device__ __forceinline__ double ipow(double x, int n) {
     return r;
 }
 
-// the fallback counter and the FP8 activation maxima (kAmaxSlots words per hidden layer)
-constexpr int kMaxLayers = 15;
-constexpr int kAmaxWords = kMaxLayers * kAmaxSlots;
-__global__ void zero_words(uint32_t *cnt, uint32_t *amax) {
+// zero the fallback counter
+__global__ void zero_count(uint32_t *cnt) {
     if (threadIdx.x == 0) *cnt = 0u;
-    for (int i = int(threadIdx.x); i < kAmaxWords; i += int(blockDim.x)) amax[i] = 0u;
 }
 
 // flags: 1 = network, 0 = fallback (out of training range), 2 = non-finite input
@@ -235,7 +232,8 @@ int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
 struct WsLayout {
     int64_t n_pad;
-    size_t o_x, o_a, o_b, o_flag, o_idx, o_cnt, o_amax, total;
+    size_t o_x, o_a, o_b, o_flag, o_idx, o_cnt, o_q, o_s, total;
+    int sst;  // scale bytes per row of the FP8 activation copy
     int wa, wb;  // widths of the two activation buffers
 };
 
@@ -264,8 +262,13 @@ WsLayout workspace_layout(const df_dnn *d, int64_t n) {
     o = al(o + size_t(w.n_pad) * 4);
     w.o_cnt = o;
     o = al(o + 4);
-    w.o_amax = o;
-    o = al(o + size_t(kAmaxWords) * 4);
+    // FP8 copy of a hidden layer's output (E4M3FN bytes and block scales), for FP8 inference
+    const int wq = std::max(w.wa, w.wb);
+    w.sst = fp8_scale_stride(wq);
+    w.o_q = o;
+    o = al(o + size_t(w.n_pad) * wq);
+    w.o_s = o;
+    o = al(o + size_t(w.n_pad) * w.sst);
     w.total = o;
     return w;
 }
@@ -336,9 +339,9 @@ df_status launch_dnn_k(const df_dnn *d, const df_mech *m, int64_t n, int64_t ld,
     auto *flag = reinterpret_cast<int8_t *>(base + w.o_flag);
     auto *idx = reinterpret_cast<int32_t *>(base + w.o_idx);
     auto *cnt = reinterpret_cast<int32_t *>(base + w.o_cnt);
-    // amax + kAmaxSlots l: the max |output| of hidden layer l
-    auto *amax = reinterpret_cast<uint32_t *>(base + w.o_amax);
-    hipLaunchKernelGGL(zero_words, dim3(1), dim3(256), 0, s, reinterpret_cast<uint32_t *>(cnt), amax);
+    auto *q8 = base + w.o_q;
+    auto *s8 = base + w.o_s;
+    hipLaunchKernelGGL(zero_count, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t *>(cnt));
     const int in_pad = d->layers[0].k_pad;
     hipLaunchKernelGGL(pre_kernel<K>, dim3(unsigned((w.n_pad + kPreThreads - 1) / kPreThreads)), dim3(kPreThreads), 0,
                        s, d->prm, n, w.n_pad, ld, p, T, Y, xb, in_pad, flag, idx, cnt, status, rr, o.fallback);
@@ -355,20 +358,18 @@ df_status launch_dnn_k(const df_dnn *d, const df_mech *m, int64_t n, int64_t ld,
         const DnnLayer &L = d->layers[l];
         bf16_t *out = (l % 2 == 0) ? ba : bb;
         const int out_ld = (l % 2 == 0) ? w.wa : w.wb;
-        // layers 1..nh-1 (between two hidden layers) in FP8; the layer before one of them
-        // reduces the amax of its output
-        const bool q = fp8 && l >= 1;
-        uint32_t *amax_out = (fp8 && l + 1 < nh) ? amax + size_t(l) * kAmaxSlots : nullptr;
+        // layers 1..nh-1 (between two hidden layers) in FP8: each reads the E4M3FN copy of its
+        // input (bytes and block scales), quantised from the previous layer's bf16 output
         df_status st;
-        if (q)
-            st = launch_gemm_fp8(in, in_ld, amax + size_t(l - 1) * kAmaxSlots, blob + bl.w8[l], L.k_pad,
-                                 reinterpret_cast<const int32_t *>(blob + bl.e8[l]), L.b, out, out_ld, w.n_pad,
-                                 L.n_pad, L.k_pad, amax_out, n, s);
-        else if (amax_out)
-            st = launch_gemm_bf16_amax(in, in_ld, L.W, L.k_pad, L.b, out, out_ld, w.n_pad, L.n_pad, L.k_pad, amax_out,
-                                       n, s);
-        else
+        if (fp8 && l >= 1) {
+            st = launch_quant_fp8(in, in_ld, w.n_pad, q8, s8, w.sst, s);
+            if (st == DF_OK)
+                st = launch_gemm_fp8(q8, in_ld, s8, w.sst, blob + bl.w8[l], L.k_pad,
+                                     reinterpret_cast<const int32_t *>(blob + bl.e8[l]), L.b, out, out_ld, w.n_pad,
+                                     L.n_pad, L.k_pad, s);
+        } else {
             st = launch_gemm_bf16(in, in_ld, L.W, L.k_pad, L.b, out, out_ld, w.n_pad, L.n_pad, L.k_pad, true, s);
+        }
         if (st != DF_OK) return st;
         in = out;
         in_ld = out_ld;

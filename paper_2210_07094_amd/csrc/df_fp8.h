@@ -1,16 +1,16 @@
 // FP8 inference of the DNN form: the layers between two hidden layers run on the E4M3FN
 // matrix cores of gfx950 (OCP 8-bit floating point: 4 exponent bits with bias 7, 3 mantissa
-// bits, largest magnitude 448, no infinities).
+// bits, largest magnitude 448, no infinities), as block-scaled products
+// (v_mfma_scale_f32_16x16x128_f8f6f4).
 //
 // Scales are powers of two, so that applying and removing them is exact:
-//  * activations: one scale 2^e per layer input over the whole call, e the smallest integer with
-//    amax <= 448 * 2^e, where amax is the largest |value| over the rows of the call's cells
-//    (the producing layer's epilogue reduces it into kAmaxSlots 32-bit words holding float bits,
-//    wave w of block b into word (4 b + w) % kAmaxSlots, so that the atomics of a launch do not
-//    queue on one address; the reading layer takes the max of the words);
+//  * activations: each row of a layer's input in blocks of 32 consecutive values, block q of row
+//    i with the scale 2^e, e the smallest integer with max |block| <= 448 * 2^e (0 for a block of
+//    zeros or one holding a non-finite value's maximum, at least -127); the bf16 activations are
+//    quantised once per layer into E4M3FN bytes [M][ld] and E8M0 scale bytes (127 + e) [M][sst];
 //  * weights: one scale per output row, by the same rule over the row, quantised once at load.
-// The products of the quantised values are summed in fp32 by the MFMA; the epilogue multiplies
-// by 2^(e_a + e_w[col]), adds the bias, applies GELU and rounds to bf16.
+// The matrix cores take both scales with each 128-deep product and sum in fp32; the epilogue
+// adds the bias, applies GELU and rounds to bf16.
 #pragma once
 
 #include <cstdint>
@@ -19,30 +19,33 @@
 
 namespace df {
 
-constexpr int kAmaxSlots = 32;  // words of one activation maximum
+constexpr int kFp8Block = 32;  // activations per block scale
 
-// smallest e with amax <= 448 * 2^e for the float amax (0 for amax 0 or not finite); exact
+// smallest e with amax <= 448 * 2^e for the float amax (0 for amax 0 or not finite), at least
+// -127 (the smallest E8M0 scale); exact
 __host__ __device__ inline int fp8_scale_exp(float amax) {
     if (!(amax > 0.0f) || !(amax <= 3.40282347e38f)) return 0;  // zero, NaN or infinite
     int k = 0;
     const float f = frexpf(amax, &k);  // amax = f * 2^k, f in [0.5, 1); 448 = 0.875 * 2^9
-    return (f <= 0.875f) ? k - 9 : k - 8;
+    const int e = (f <= 0.875f) ? k - 9 : k - 8;
+    return e < -127 ? -127 : e;
 }
 
-// The inference GEMM of launch_gemm_bf16 (GELU epilogue) that also reduces max |C| over rows
-// < m_valid into amax[0..kAmaxSlots) (float bits, combined with atomicMax; the words must start
-// at 0).
-df_status launch_gemm_bf16_amax(const bf16_t *A, int lda, const bf16_t *B, int ldb, const float *bias, bf16_t *C,
-                                int ldc, int64_t M, int N, int K, uint32_t *amax, int64_t m_valid,
-                                hipStream_t stream);
+// bytes per row of the scale array of an FP8 activation buffer of width ld (16-byte rows)
+inline int fp8_scale_stride(int ld) { return (ld / kFp8Block + 15) / 16 * 16; }
 
-// C[M][N] = GELU(2^(e_a + wexp[n]) * (Q(A 2^-e_a) . W8^T)[m][n] + bias[n]) in bf16, e_a from the
-// max of amax_in[0..kAmaxSlots) (the scale rule above), Q the E4M3FN rounding (ties to even) of
-// the bf16 activations.
-// W8: [N][K] E4M3FN bytes (row stride ldb bytes), wexp: [N] row exponents.  amax_out (nullable):
-// max |C| over rows < m_valid for the next FP8 layer.  Shapes as launch_gemm_bf16, ldb % 16 == 0.
-df_status launch_gemm_fp8(const bf16_t *A, int lda, const uint32_t *amax_in, const uint8_t *W8, int ldb,
+// Q[M][ld] E4M3FN bytes and S[M][sst] E8M0 bytes (127 + e, blocks 0 .. ld/32 - 1 of each row;
+// bytes from ld/32 on are not written) from the bf16 activations A[M][ld] (ld % 32 == 0), by the
+// block rule above.
+df_status launch_quant_fp8(const bf16_t *A, int ld, int64_t M, uint8_t *Q, uint8_t *S, int sst, hipStream_t stream);
+
+// C[M][N] = GELU(sum_q 2^(e_a[m][q] + wexp[n]) (Q_a . W8^T over block q)[m][n] + bias[n]) in bf16,
+// over the K (% 32 == 0) inputs in 128-deep steps (inputs from K to the next multiple of 128 read
+// as zeros).  Q_a: [M][lda] E4M3FN bytes, S_a: [M][sst] E8M0 block scales (as launch_quant_fp8);
+// W8: [N][ldb] E4M3FN bytes, wexp: [N] row exponents (-127 .. 127).  M % 128 == 0, N % 160 == 0,
+// lda, ldb multiples of 16, sst of 16.
+df_status launch_gemm_fp8(const uint8_t *A8, int lda, const uint8_t *S, int sst, const uint8_t *W8, int ldb,
                           const int32_t *wexp, const float *bias, bf16_t *C, int ldc, int64_t M, int N, int K,
-                          uint32_t *amax_out, int64_t m_valid, hipStream_t stream);
+                          hipStream_t stream);
 
 }  // namespace df

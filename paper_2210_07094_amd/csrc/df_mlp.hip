@@ -66,22 +66,6 @@ __device__ __forceinline__ float gelu_grad(float x) {
     return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * expf(-0.5f * x * x);
 }
 
-// wave-wide max of a non-negative float, combined into one of the kAmaxSlots words of amax
-// (float bits; non-negative floats order as their bit patterns) by one lane; all 64 lanes take part
-__device__ __forceinline__ void amax_combine(float m, uint32_t *amax) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
-    const unsigned slot = (blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6)) % kAmaxSlots;
-    if ((threadIdx.x & 63) == 0) atomicMax(amax + slot, __float_as_uint(m));
-}
-
-__device__ __forceinline__ float amax_read(const uint32_t *amax) {
-    uint32_t u = 0;
-#pragma unroll
-    for (int i = 0; i < kAmaxSlots; ++i) u = max(u, amax[i]);
-    return __uint_as_float(u);
-}
-
 // Epilogues: inference (bias, GELU); training forward (bias, GELU, and the pre-activation
 // stored to P with C's layout); training backward (the product times GELU'(P), no bias).
 enum { kEpiGelu = 0, kEpiLinear = 1, kEpiGeluSave = 2, kEpiGeluGrad = 3 };
@@ -91,8 +75,7 @@ template <int EPI, int KD>
 __global__ __launch_bounds__(kThreads) void gemm_kernel(const bf16_t *__restrict__ A, int lda,
                                                        const bf16_t *__restrict__ B, int ldb,
                                                        const float *__restrict__ bias, bf16_t *__restrict__ C,
-                                                       int ldc, int K, int n_tiles_n, bf16_t *__restrict__ P,
-                                                       uint32_t *__restrict__ amax, int64_t m_valid) {
+                                                       int ldc, int K, int n_tiles_n, bf16_t *__restrict__ P) {
     constexpr int LDKD = KD + 16;  // LDS row stride in bf16 (96 bytes at KD = 32)
     __shared__ __attribute__((aligned(16))) bf16_t As[BM * LDKD];
     __shared__ __attribute__((aligned(16))) bf16_t Bs[BN * LDKD];
@@ -179,7 +162,6 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(const bf16_t *__restrict
 
     // epilogue: with the weights as the first MFMA operand, lane l holds row (l % 16) and the four
     // columns 4 * (l / 16) + r of each 16 x 16 tile
-    float m = 0.0f;
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
         const int col = col0 + wn * WN + j * 16 + (lane >> 4) * 4;
@@ -204,14 +186,9 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(const bf16_t *__restrict
 #pragma unroll
                 for (int r = 0; r < 4; ++r) v[r] *= gelu_grad(float(pv[r]));
             }
-            const bf16x4 h = to_bf16x4(v);
-            *reinterpret_cast<bf16x4 *>(C + off) = h;
-            if (amax && row < m_valid)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) m = fmaxf(m, fabsf(float(h[r])));
+            *reinterpret_cast<bf16x4 *>(C + off) = to_bf16x4(v);
         }
     }
-    if (amax) amax_combine(m, amax);
 }
 
 // Inference layer with a shallow reduction (K = KD <= 64, the first hidden layer: the network's
@@ -221,14 +198,13 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(const bf16_t *__restrict
 // loading each tile's activation fragments straight from global memory (16 rows x 64 contiguous
 // bytes per load) one tile ahead, so that the loads of the next tile are in flight during the
 // epilogue of the current one; no LDS and no barriers.  Same tile shape, operand order and
-// epilogue (bias, GELU, bf16, optional max |C| over rows < m_valid) as gemm_kernel.
+// epilogue (bias, GELU, bf16) as gemm_kernel.
 template <int KD>
 __global__ __launch_bounds__(kThreads) void gemm_shallow_kernel(const bf16_t *__restrict__ A, int lda,
                                                                 const bf16_t *__restrict__ B, int ldb,
                                                                 const float *__restrict__ bias,
                                                                 bf16_t *__restrict__ C, int ldc, int n_tiles_m,
-                                                                int n_tiles_n, uint32_t *__restrict__ amax,
-                                                                int64_t m_valid) {
+                                                                int n_tiles_n) {
     constexpr int KS = KD / 32;  // 32-deep MFMA steps
     const int tile_n = int(blockIdx.x) % n_tiles_n, g0 = int(blockIdx.x) / n_tiles_n;
     const int G = int(gridDim.x) / n_tiles_n;
@@ -256,7 +232,6 @@ __global__ __launch_bounds__(kThreads) void gemm_shallow_kernel(const bf16_t *__
             for (int i = 0; i < TM; ++i)
                 af[s][i] = *reinterpret_cast<const bf16x8 *>(A + (r0 + i * 16) * lda + s * 32 + fk);
     };
-    float m = 0.0f;
     bf16x8 an[KS][TM];
     if (g0 < n_tiles_m) load_a(g0, an);
     for (int tm = g0; tm < n_tiles_m; tm += G) {
@@ -286,22 +261,17 @@ __global__ __launch_bounds__(kThreads) void gemm_shallow_kernel(const bf16_t *__
                 floatx4 v = acc[i][j] + bc[j];
 #pragma unroll
                 for (int r = 0; r < 4; ++r) v[r] = gelu_erfc(v[r]);
-                const bf16x4 h = to_bf16x4(v);
-                *reinterpret_cast<bf16x4 *>(C + row * ldc + col) = h;
-                if (amax && row < m_valid)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) m = fmaxf(m, fabsf(float(h[r])));
+                *reinterpret_cast<bf16x4 *>(C + row * ldc + col) = to_bf16x4(v);
             }
         }
     }
-    if (amax) amax_combine(m, amax);
 }
 
 // A value the E4M3FN conversion takes as is: |x| <= 448 unchanged; 448 < |x| <= 464 rounds to
 // 448 (ties to even) and is passed as 448; a value that would round beyond 448, an infinity or a
 // NaN becomes NaN, the format's only non-finite value, so that it propagates to the cell's
-// status as in the bf16 path.  The per-call scale keeps every finite scaled value within 448;
-// the other cases arise only when the activation maximum itself is not finite.
+// status as in the bf16 path.  The block scale keeps every finite scaled value within 448; the
+// other cases arise only when the block's maximum itself is not finite.
 __device__ __forceinline__ float fp8_in_range(float x) {
     const float a = fabsf(x);
     return (a <= 448.0f) ? x : ((a <= 464.0f) ? copysignf(448.0f, x) : __builtin_nanf(""));
@@ -318,153 +288,180 @@ __device__ __forceinline__ uint32_t to_fp8x4(float a, float b, float c, float d)
     return uint32_t(v);
 }
 
-// FP8 layer: the tiling of gemm_kernel with E4M3FN operands.  A is read as bf16 and quantised
-// while it is staged (scale 2^-e_a), the weights are E4M3FN bytes already; each 16x16x32 MFMA
-// takes 8 bytes of a row of A and of W per lane, in the lane layout of the bf16 instruction.
-// KD: reduction depth staged per barrier pair (32, or 64 where K allows it)
-template <int KD>
-__global__ __launch_bounds__(kThreads) void gemm_fp8_kernel(const bf16_t *__restrict__ A, int lda,
-                                                           const uint32_t *__restrict__ amax_in,
+// one thread per block of 32 activations of a row: the block's largest magnitude (NaN ignored),
+// its scale exponent, the 32 E4M3FN bytes and the E8M0 scale byte
+constexpr int kQuantThreads = 256;
+__global__ __launch_bounds__(kQuantThreads) void quant_fp8_kernel(const bf16_t *__restrict__ A, int ld, int64_t n_blk,
+                                                                  uint8_t *__restrict__ Q, uint8_t *__restrict__ S,
+                                                                  int sst) {
+    const int64_t id = int64_t(blockIdx.x) * kQuantThreads + threadIdx.x;
+    if (id >= n_blk) return;
+    const int nb = ld / kFp8Block;
+    const int64_t row = id / nb;
+    const int q = int(id % nb);
+    const u32x4 *src = reinterpret_cast<const u32x4 *>(A + row * ld + q * kFp8Block);
+    float v[kFp8Block];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const u32x4 x = src[c];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            v[8 * c + 2 * w] = __uint_as_float(x[w] << 16);
+            v[8 * c + 2 * w + 1] = __uint_as_float(x[w] & 0xffff0000u);
+        }
+    }
+    float amax = 0.0f;
+#pragma unroll
+    for (int c = 0; c < kFp8Block; ++c) amax = fmaxf(amax, fabsf(v[c]));
+    const int e = fp8_scale_exp(amax);
+    const float sc = ldexpf(1.0f, -e);
+    u32x4 o[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const float *f = v + 16 * h + 4 * w;
+            o[h][w] = to_fp8x4(f[0] * sc, f[1] * sc, f[2] * sc, f[3] * sc);
+        }
+    u32x4 *dst = reinterpret_cast<u32x4 *>(Q + row * ld + q * kFp8Block);
+    dst[0] = o[0];
+    dst[1] = o[1];
+    S[row * sst + q] = uint8_t(127 + e);
+}
+
+// FP8 layer on the block-scaled matrix cores: the tiling of gemm_kernel (128 x 160 block tile,
+// 2 x 2 waves of 64 x 80) with 128-deep stages of E4M3FN bytes.  In a 16x16x128 product with
+// 8-bit operands, lane l supplies row l % 16 of its operand at the stage's inputs 16 g .. 16 g + 15
+// (bytes 0-15) and 64 + 16 g .. 64 + 16 g + 15 (bytes 16-31), g = l / 16, and the E8M0 scale of
+// the inputs 32 g .. 32 g + 31 of that row: its two halves lie with lanes g' = 2 (g % 2) and
+// 2 (g % 2) + 1 (measured on gfx950 with one-hot data and per-lane scales).  So each lane reads
+// the two 16-byte pieces of its row at 16 g and 64 + 16 g, and passes the scale of activation
+// block g of the stage (the weight row's scale, 127 + wexp, is the same for all blocks).  Inputs
+// at or beyond K (the last stage of a K that is not a multiple of 128) are zeros with scale 2^0.
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+constexpr int KD8 = 128, LDK8 = KD8 + 16;  // stage depth and LDS row stride in bytes
+
+__global__ __launch_bounds__(kThreads) void gemm_fp8_kernel(const uint8_t *__restrict__ A8, int lda,
+                                                           const uint8_t *__restrict__ SA, int sst,
                                                            const uint8_t *__restrict__ W8, int ldb,
                                                            const int32_t *__restrict__ wexp,
                                                            const float *__restrict__ bias, bf16_t *__restrict__ C,
-                                                           int ldc, int K, int n_tiles_n,
-                                                           uint32_t *__restrict__ amax_out, int64_t m_valid) {
-    constexpr int LDK8 = KD + 8;  // LDS row stride in bytes
+                                                           int ldc, int K, int n_tiles_n) {
     __shared__ __attribute__((aligned(16))) uint8_t As[BM * LDK8];
     __shared__ __attribute__((aligned(16))) uint8_t Bs[BN * LDK8];
+    __shared__ uint32_t Ss[BM];
 
     const int nb = gridDim.x, b = blockIdx.x;
     const int logical = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
     const int tile_m = logical / n_tiles_n, tile_n = logical % n_tiles_n;
     const int64_t row0 = int64_t(tile_m) * BM;
     const int col0 = tile_n * BN;
-
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wm = w >> 1, wn = w & 1;
-    const int ea = fp8_scale_exp(amax_read(amax_in));
-    const float sa = ldexpf(1.0f, -ea);
+    const int fr = lane & 15, fg = lane >> 4;
 
-    // A: BM*KD/8 chunks of 8 bf16; W: BN*KD/16 chunks of 16 bytes
-    constexpr int kAChunks = BM * KD / 8, kBChunks = BN * KD / 16;
-    constexpr int kAPer = kAChunks / kThreads;
-    constexpr int kBPer = (kBChunks + kThreads - 1) / kThreads;
+    // 16-byte chunks: A BM*KD8/16 = 1024 (4 per thread), W BN*KD8/16 = 1280 (5 per thread)
+    constexpr int kCh = KD8 / 16;
+    constexpr int kAPer = BM * kCh / kThreads, kBPer = BN * kCh / kThreads;
     u32x4 ra[kAPer], rb[kBPer];
+    uint32_t rs = 0;
+    const u32x4 z4 = {0u, 0u, 0u, 0u};
     auto load = [&](int k0) {
 #pragma unroll
         for (int i = 0; i < kAPer; ++i) {
-            const int c = t + i * kThreads, r = c / (KD / 8), kc = c % (KD / 8);
-            ra[i] = *reinterpret_cast<const u32x4 *>(A + (row0 + r) * lda + k0 + kc * 8);
+            const int c = t + i * kThreads, r = c / kCh, k = k0 + (c % kCh) * 16;
+            ra[i] = (k < K) ? *reinterpret_cast<const u32x4 *>(A8 + (row0 + r) * lda + k) : z4;
         }
 #pragma unroll
         for (int i = 0; i < kBPer; ++i) {
-            const int c = t + i * kThreads;
-            if (c < kBChunks) {
-                const int r = c / (KD / 16), kc = c % (KD / 16);
-                rb[i] = *reinterpret_cast<const u32x4 *>(W8 + int64_t(col0 + r) * ldb + k0 + kc * 16);
-            }
+            const int c = t + i * kThreads, r = c / kCh, k = k0 + (c % kCh) * 16;
+            rb[i] = (k < K) ? *reinterpret_cast<const u32x4 *>(W8 + int64_t(col0 + r) * ldb + k) : z4;
+        }
+        // the four block scales of a row for this stage; 127 (2^0) for blocks at or beyond K
+        if (t < BM) {
+            const uint8_t *sp = SA + (row0 + t) * sst + k0 / kFp8Block;
+            uint32_t v = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) v |= uint32_t((k0 + q * kFp8Block < K) ? sp[q] : 127) << (8 * q);
+            rs = v;
         }
     };
     auto store = [&]() {
 #pragma unroll
         for (int i = 0; i < kAPer; ++i) {
-            const int c = t + i * kThreads, r = c / (KD / 8), kc = c % (KD / 8);
-            float f[8];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                f[2 * q] = __uint_as_float(ra[i][q] << 16) * sa;
-                f[2 * q + 1] = __uint_as_float(ra[i][q] & 0xffff0000u) * sa;
-            }
-            uint2 v;
-            v.x = to_fp8x4(f[0], f[1], f[2], f[3]);
-            v.y = to_fp8x4(f[4], f[5], f[6], f[7]);
-            *reinterpret_cast<uint2 *>(As + r * LDK8 + kc * 8) = v;
+            const int c = t + i * kThreads;
+            *reinterpret_cast<u32x4 *>(As + (c / kCh) * LDK8 + (c % kCh) * 16) = ra[i];
         }
 #pragma unroll
         for (int i = 0; i < kBPer; ++i) {
             const int c = t + i * kThreads;
-            if (c < kBChunks) {
-                const int r = c / (KD / 16), kc = c % (KD / 16);
-                uint2 lo, hi;
-                lo.x = rb[i][0];
-                lo.y = rb[i][1];
-                hi.x = rb[i][2];
-                hi.y = rb[i][3];
-                *reinterpret_cast<uint2 *>(Bs + r * LDK8 + kc * 16) = lo;
-                *reinterpret_cast<uint2 *>(Bs + r * LDK8 + kc * 16 + 8) = hi;
-            }
+            *reinterpret_cast<u32x4 *>(Bs + (c / kCh) * LDK8 + (c % kCh) * 16) = rb[i];
         }
+        if (t < BM) Ss[t] = rs;
     };
 
+    int sw[TN];  // E8M0 scale of the weight row each lane supplies
+#pragma unroll
+    for (int j = 0; j < TN; ++j) sw[j] = 127 + wexp[col0 + wn * WN + j * 16 + fr];
     floatx4 acc[TM][TN];
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-    const int fr = lane & 15, fk = (lane >> 4) * 8;
     load(0);
-    for (int k0 = 0; k0 < K; k0 += KD) {
+    for (int k0 = 0; k0 < K; k0 += KD8) {
         __syncthreads();
         store();
         __syncthreads();
-        if (k0 + KD < K) load(k0 + KD);
+        if (k0 + KD8 < K) load(k0 + KD8);
+        auto frag = [&](const uint8_t *row) {
+            const u32x4 lo = *reinterpret_cast<const u32x4 *>(row + fg * 16);
+            const u32x4 hi = *reinterpret_cast<const u32x4 *>(row + 64 + fg * 16);
+            return i32x8{int(lo[0]), int(lo[1]), int(lo[2]), int(lo[3]), int(hi[0]), int(hi[1]), int(hi[2]), int(hi[3])};
+        };
+        i32x8 wf[TN];
 #pragma unroll
-        for (int kk = 0; kk < KD; kk += 32) {
-            long af[TM], bfr[TN];
+        for (int j = 0; j < TN; ++j) wf[j] = frag(Bs + (wn * WN + j * 16 + fr) * LDK8);
 #pragma unroll
-            for (int i = 0; i < TM; ++i)
-                af[i] = *reinterpret_cast<const long *>(As + (wm * WM + i * 16 + fr) * LDK8 + kk + fk);
+        for (int i = 0; i < TM; ++i) {
+            const int r = wm * WM + i * 16 + fr;
+            const i32x8 af = frag(As + r * LDK8);
+            const int sa = int((Ss[r] >> (8 * fg)) & 0xffu);
 #pragma unroll
             for (int j = 0; j < TN; ++j)
-                bfr[j] = *reinterpret_cast<const long *>(Bs + (wn * WN + j * 16 + fr) * LDK8 + kk + fk);
-#pragma unroll
-            for (int i = 0; i < TM; ++i)
-#pragma unroll
-                for (int j = 0; j < TN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(bfr[j], af[i], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(wf[j], af, acc[i][j], 0, 0, 0, sw[j], 0, sa);
         }
     }
 
-    float m = 0.0f;
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
-        const int col = col0 + wn * WN + j * 16 + (lane >> 4) * 4;
+        const int col = col0 + wn * WN + j * 16 + fg * 4;
         const floatx4 bc = *reinterpret_cast<const floatx4 *>(bias + col);
-        floatx4 sc;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) sc[r] = ldexpf(1.0f, ea + wexp[col + r]);
 #pragma unroll
         for (int i = 0; i < TM; ++i) {
             const int64_t row = row0 + wm * WM + i * 16 + fr;
-            floatx4 v;
+            floatx4 v = acc[i][j] + bc;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) v[r] = gelu_erfc(acc[i][j][r] * sc[r] + bc[r]);
-            const bf16x4 h = to_bf16x4(v);
-            *reinterpret_cast<bf16x4 *>(C + row * ldc + col) = h;
-            if (amax_out && row < m_valid)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) m = fmaxf(m, fabsf(float(h[r])));
+            for (int r = 0; r < 4; ++r) v[r] = gelu_erfc(v[r]);
+            *reinterpret_cast<bf16x4 *>(C + row * ldc + col) = to_bf16x4(v);
         }
     }
-    if (amax_out) amax_combine(m, amax_out);
 }
 
 // the shallow-reduction layer (K = 32 or 64, shapes checked by the caller): about two blocks per
 // CU, each on one 160-column panel and every G-th row tile
 df_status launch_shallow(const bf16_t *A, int lda, const bf16_t *B, int ldb, const float *bias, bf16_t *C, int ldc,
-                         int64_t M, int N, int K, uint32_t *amax, int64_t m_valid, hipStream_t stream) {
+                         int64_t M, int N, int K, hipStream_t stream) {
     const int64_t tm = M / BM;
     const int tn = N / BN;
     if (tm > 0x7fffffff) return fail(DF_E_UNSUPPORTED, "gemm: too many row tiles");
     const int G = int(std::max<int64_t>(1, std::min<int64_t>(tm, std::max(1, 512 / tn))));
     const dim3 g = dim3(unsigned(int64_t(G) * tn)), b = dim3(kThreads);
     if (K == 32)
-        hipLaunchKernelGGL(gemm_shallow_kernel<32>, g, b, 0, stream, A, lda, B, ldb, bias, C, ldc, int(tm), tn, amax,
-                           m_valid);
+        hipLaunchKernelGGL(gemm_shallow_kernel<32>, g, b, 0, stream, A, lda, B, ldb, bias, C, ldc, int(tm), tn);
     else
-        hipLaunchKernelGGL(gemm_shallow_kernel<64>, g, b, 0, stream, A, lda, B, ldb, bias, C, ldc, int(tm), tn, amax,
-                           m_valid);
+        hipLaunchKernelGGL(gemm_shallow_kernel<64>, g, b, 0, stream, A, lda, B, ldb, bias, C, ldc, int(tm), tn);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(DF_E_HIP, std::string("gemm launch: ") + hipGetErrorString(e));
     return DF_OK;
@@ -487,17 +484,14 @@ df_status launch_gemm_bf16_epi(const bf16_t *A, int lda, const bf16_t *B, int ld
     if (M == 0) return DF_OK;
     const int64_t tiles = (M / BM) * (N / BN);
     if (tiles > 0x7fffffff) return fail(DF_E_UNSUPPORTED, "gemm: too many tiles");
-    if (epi == GemmEpi::gelu && (K == 32 || K == 64)) return launch_shallow(A, lda, B, ldb, bias, C, ldc, M, N, K,
-                                                                             nullptr, 0, stream);
+    if (epi == GemmEpi::gelu && (K == 32 || K == 64)) return launch_shallow(A, lda, B, ldb, bias, C, ldc, M, N, K, stream);
     const dim3 g = dim3(unsigned(tiles)), b = dim3(kThreads);
     const bool deep = K % 64 == 0;
 #define DF_GEMM(E)                                                                                              \
     if (deep)                                                                                                   \
-        hipLaunchKernelGGL((gemm_kernel<E, 64>), g, b, 0, stream, A, lda, B, ldb, bias, C, ldc, K, N / BN, P,   \
-                           nullptr, int64_t(0));                                                                \
+        hipLaunchKernelGGL((gemm_kernel<E, 64>), g, b, 0, stream, A, lda, B, ldb, bias, C, ldc, K, N / BN, P);  \
     else                                                                                                        \
-        hipLaunchKernelGGL((gemm_kernel<E, 32>), g, b, 0, stream, A, lda, B, ldb, bias, C, ldc, K, N / BN, P,   \
-                           nullptr, int64_t(0));
+        hipLaunchKernelGGL((gemm_kernel<E, 32>), g, b, 0, stream, A, lda, B, ldb, bias, C, ldc, K, N / BN, P);
     switch (epi) {
         case GemmEpi::gelu:
             DF_GEMM(kEpiGelu)
@@ -518,42 +512,31 @@ df_status launch_gemm_bf16_epi(const bf16_t *A, int lda, const bf16_t *B, int ld
     return DF_OK;
 }
 
-df_status launch_gemm_bf16_amax(const bf16_t *A, int lda, const bf16_t *B, int ldb, const float *bias, bf16_t *C,
-                                int ldc, int64_t M, int N, int K, uint32_t *amax, int64_t m_valid,
-                                hipStream_t stream) {
-    if (M % BM || N % BN || K % BK || lda % 8 || ldb % 8)
-        return fail(DF_E_INVALID, "gemm: shapes must be multiples of the tile sizes");
-    if (!amax) return fail(DF_E_INVALID, "gemm: null activation-maximum words");
-    if (M == 0) return DF_OK;
-    const int64_t tiles = (M / BM) * (N / BN);
-    if (tiles > 0x7fffffff) return fail(DF_E_UNSUPPORTED, "gemm: too many tiles");
-    if (K == 32 || K == 64) return launch_shallow(A, lda, B, ldb, bias, C, ldc, M, N, K, amax, m_valid, stream);
-    if (K % 64 == 0)
-        hipLaunchKernelGGL((gemm_kernel<kEpiGelu, 64>), dim3(unsigned(tiles)), dim3(kThreads), 0, stream, A, lda, B,
-                           ldb, bias, C, ldc, K, N / BN, static_cast<bf16_t *>(nullptr), amax, m_valid);
-    else
-        hipLaunchKernelGGL((gemm_kernel<kEpiGelu, 32>), dim3(unsigned(tiles)), dim3(kThreads), 0, stream, A, lda, B,
-                           ldb, bias, C, ldc, K, N / BN, static_cast<bf16_t *>(nullptr), amax, m_valid);
+df_status launch_quant_fp8(const bf16_t *A, int ld, int64_t M, uint8_t *Q, uint8_t *S, int sst, hipStream_t stream) {
+    if (ld % kFp8Block || sst % 16 || sst < ld / kFp8Block || M < 0)
+        return fail(DF_E_INVALID, "fp8 quantisation: width must be a multiple of 32 and the scale rows hold its blocks");
+    const int64_t n_blk = M * (ld / kFp8Block);
+    if (n_blk == 0) return DF_OK;
+    if ((n_blk + kQuantThreads - 1) / kQuantThreads > 0x7fffffff) return fail(DF_E_UNSUPPORTED, "fp8 quantisation: too many blocks");
+    hipLaunchKernelGGL(quant_fp8_kernel, dim3(unsigned((n_blk + kQuantThreads - 1) / kQuantThreads)),
+                       dim3(kQuantThreads), 0, stream, A, ld, n_blk, Q, S, sst);
     const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return fail(DF_E_HIP, std::string("gemm launch: ") + hipGetErrorString(e));
+    if (e != hipSuccess) return fail(DF_E_HIP, std::string("fp8 quantisation launch: ") + hipGetErrorString(e));
     return DF_OK;
 }
 
-df_status launch_gemm_fp8(const bf16_t *A, int lda, const uint32_t *amax_in, const uint8_t *W8, int ldb,
+df_status launch_gemm_fp8(const uint8_t *A8, int lda, const uint8_t *S, int sst, const uint8_t *W8, int ldb,
                           const int32_t *wexp, const float *bias, bf16_t *C, int ldc, int64_t M, int N, int K,
-                          uint32_t *amax_out, int64_t m_valid, hipStream_t stream) {
-    if (M % BM || N % BN || K % BK || lda % 8 || ldb % 16 || ldb < K)
-        return fail(DF_E_INVALID, "gemm fp8: shapes must be multiples of the tile sizes (weight rows of 16 bytes)");
-    if (!amax_in || !W8 || !wexp) return fail(DF_E_INVALID, "gemm fp8: null maximum, weight or exponent array");
+                          hipStream_t stream) {
+    if (M % BM || N % BN || K % kFp8Block || lda % 16 || ldb % 16 || sst % 16 || lda < K || ldb < K ||
+        sst < K / kFp8Block)
+        return fail(DF_E_INVALID, "gemm fp8: shapes must be multiples of the tile sizes (rows of 16 bytes)");
+    if (!A8 || !S || !W8 || !wexp) return fail(DF_E_INVALID, "gemm fp8: null activation, scale, weight or exponent array");
     if (M == 0) return DF_OK;
     const int64_t tiles = (M / BM) * (N / BN);
     if (tiles > 0x7fffffff) return fail(DF_E_UNSUPPORTED, "gemm fp8: too many tiles");
-    if (K % 64 == 0)
-        hipLaunchKernelGGL(gemm_fp8_kernel<64>, dim3(unsigned(tiles)), dim3(kThreads), 0, stream, A, lda, amax_in, W8,
-                           ldb, wexp, bias, C, ldc, K, N / BN, amax_out, m_valid);
-    else
-        hipLaunchKernelGGL(gemm_fp8_kernel<32>, dim3(unsigned(tiles)), dim3(kThreads), 0, stream, A, lda, amax_in, W8,
-                           ldb, wexp, bias, C, ldc, K, N / BN, amax_out, m_valid);
+    hipLaunchKernelGGL(gemm_fp8_kernel, dim3(unsigned(tiles)), dim3(kThreads), 0, stream, A8, lda, S, sst, W8, ldb,
+                       wexp, bias, C, ldc, K, N / BN);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(DF_E_HIP, std::string("gemm fp8 launch: ") + hipGetErrorString(e));
     return DF_OK;

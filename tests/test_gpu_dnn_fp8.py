@@ -1,7 +1,7 @@
 """GPU parity of the DNN step with FP8 hidden-to-hidden layers (df_dnn_opts.precision = 1)
 against the oracle's FP8 forward (mode 2): E4M3FN quantisation with power-of-two scales (one per
-call for the activations, one per row for the weights), exact sums on the oracle's side, fp32
-MFMA sums on the GPU's.
+row and block of 32 for the activations, one per row for the weights), exact sums on the oracle's
+side, fp32 sums of the block-scaled MFMAs on the GPU's.
 
 The bar.  Both sides quantise bf16 activations to E4M3FN with the same rule, but the two sum the
 products differently: the oracle exactly, the MFMA with an internal accumulation that differs

@@ -1,8 +1,8 @@
 """Pins of the oracle's FP8 inference (OCP E4M3FN, power-of-two scales) against what the format
 and the mathematics fix: the rounding against torch's own float8_e4m3fn conversion (a library
 routine) and against hand-worked ties and subnormals; the scale rule against hand cases; the
-batched FP8 forward against a brute-force recomputation (quantisation by torch, products summed
-by numpy) on a small network; and the special case of a network with one hidden layer, which has
+batched FP8 forward (a scale per row and block of 32 activations) against a brute-force
+recomputation (quantisation by torch, products summed by numpy) on a small network; and the special case of a network with one hidden layer, which has
 no hidden-to-hidden layer and must give the BF16-emulated forward exactly."""
 import math
 
@@ -51,6 +51,7 @@ def test_scale_exponent():
     assert s(1.0) == -8 and s(1.75) == -8 and s(1.76) == -7
     assert s(0.0) == 0 and s(896.0) == 1 and s(896.1) == 2
     assert s(float("inf")) == 0 and s(float("nan")) == 0   # no finite scale: left to the values
+    assert s(448.0 * 2.0 ** -127) == -127 and s(448.0 * 2.0 ** -128) == -127 and s(1e-300) == -127  # E8M0 floor
     rng = np.random.default_rng(2)
     for a in np.exp(rng.uniform(-40, 40, 500)):
         e = s(a)
@@ -75,11 +76,15 @@ def _brute_force(net, X):
     a = _bf16(X)
     for l in range(L):
         if 1 <= l <= L - 2:
-            ea = oracle.fp8_scale_exp(np.abs(a).max())
-            aq = _q(np.ldexp(a, -ea))
             ew = np.array([oracle.fp8_scale_exp(np.abs(w).max()) for w in W[l]])
             wq = _q(np.ldexp(W[l].astype(np.float64), -ew[:, None]))
-            z = np.ldexp(aq @ wq.T, ea + ew[None, :]) + b[l].astype(np.float64)[None, :]
+            acc = np.zeros((a.shape[0], W[l].shape[0]))
+            for c0 in range(0, a.shape[1], 32):      # blocks of 32 inputs of each row
+                blk = a[:, c0:c0 + 32]
+                ea = np.array([oracle.fp8_scale_exp(np.abs(r).max()) for r in blk])
+                aq = _q(np.ldexp(blk, -ea[:, None]))
+                acc += np.ldexp(aq @ wq[:, c0:c0 + 32].T, ea[:, None])
+            z = np.ldexp(acc, ew[None, :]) + b[l].astype(np.float64)[None, :]
         else:
             # fp32 products and running fp32 sums, in input order
             acc = np.zeros((a.shape[0], W[l].shape[0]), dtype=np.float32)
@@ -97,7 +102,7 @@ def test_fp8_forward_brute_force(tmp_path):
     p = np.full(64, 101325.0)
     Y = rng.dirichlet(np.ones(K), 64).T
     path = tmp_path / "net.dfdnn"
-    dnnfile.write_seeded_network(path, K, T, p, Y, (48, 40, 32), seed=5)
+    dnnfile.write_seeded_network(path, K, T, p, Y, (48, 40, 32), seed=5)   # 48 and 40 inputs: a short last block
     net = dnnfile.read_dnn(path)
     X = rng.standard_normal((200, K + 2))
     X[7] = 0.0                         # a cell the network does not predict
