@@ -354,23 +354,47 @@ df_status launch_dnn_k(const df_dnn *d, const df_mech *m, int64_t n, int64_t ld,
     const bool fp8 = (o.precision == 1);
     const BlobLayout bl = fp8 ? blob_layout(d->layers, d->prm.n_in) : BlobLayout{};
     auto *blob = static_cast<unsigned char *>(d->dev_blob);
+    // FP8 input of the current layer (E4M3FN bytes and block scales), when its producer wrote one
+    const uint8_t *a8 = nullptr, *a8s = nullptr;
+    int a8_sst = 0;
     for (int l = 0; l < nh; ++l) {
         const DnnLayer &L = d->layers[l];
         bf16_t *out = (l % 2 == 0) ? ba : bb;
         const int out_ld = (l % 2 == 0) ? w.wa : w.wb;
         // layers 1..nh-1 (between two hidden layers) in FP8: each reads the E4M3FN copy of its
-        // input (bytes and block scales), quantised from the previous layer's bf16 output
+        // input (bytes and block scales), written by the layer before it where that layer can
+        // (the first layer with K = 32 or 64, an FP8 layer), else quantised from its bf16 output.
+        // An FP8 copy fills the layer's activation buffer as bytes [n_pad][out_ld] followed by
+        // the scales [n_pad][sst].
+        const bool q_next = fp8 && l + 1 < nh;
+        auto *o8 = reinterpret_cast<uint8_t *>(out);
+        uint8_t *o8s = o8 + size_t(w.n_pad) * out_ld;
+        const int o8_sst = fp8_scale_stride(out_ld);
         df_status st;
+        bool wrote8 = false;
         if (fp8 && l >= 1) {
-            st = launch_quant_fp8(in, in_ld, w.n_pad, q8, s8, w.sst, s);
-            if (st == DF_OK)
-                st = launch_gemm_fp8(q8, in_ld, s8, w.sst, blob + bl.w8[l], L.k_pad,
-                                     reinterpret_cast<const int32_t *>(blob + bl.e8[l]), L.b, out, out_ld, w.n_pad,
-                                     L.n_pad, L.k_pad, s);
+            if (!a8) {
+                st = launch_quant_fp8(in, in_ld, w.n_pad, q8, s8, w.sst, s);
+                if (st != DF_OK) return st;
+                a8 = q8;
+                a8s = s8;
+                a8_sst = w.sst;
+            }
+            st = launch_gemm_fp8(a8, in_ld, a8s, a8_sst, blob + bl.w8[l], L.k_pad,
+                                 reinterpret_cast<const int32_t *>(blob + bl.e8[l]), L.b, out, out_ld,
+                                 q_next ? o8s : nullptr, o8_sst, w.n_pad, L.n_pad, L.k_pad, s);
+            wrote8 = q_next;
+        } else if (q_next && (L.k_pad == 32 || L.k_pad == 64)) {
+            st = launch_gemm_bf16_fp8out(in, in_ld, L.W, L.k_pad, L.b, o8, out_ld, o8s, o8_sst, w.n_pad, L.n_pad,
+                                         L.k_pad, s);
+            wrote8 = true;
         } else {
             st = launch_gemm_bf16(in, in_ld, L.W, L.k_pad, L.b, out, out_ld, w.n_pad, L.n_pad, L.k_pad, true, s);
         }
         if (st != DF_OK) return st;
+        a8 = wrote8 ? o8 : nullptr;
+        a8s = wrote8 ? o8s : nullptr;
+        a8_sst = o8_sst;
         in = out;
         in_ld = out_ld;
     }

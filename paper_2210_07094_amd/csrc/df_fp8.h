@@ -43,9 +43,17 @@ df_status launch_quant_fp8(const bf16_t *A, int ld, int64_t M, uint8_t *Q, uint8
 // over the K (% 32 == 0) inputs in 128-deep steps (inputs from K to the next multiple of 128 read
 // as zeros).  Q_a: [M][lda] E4M3FN bytes, S_a: [M][sst] E8M0 block scales (as launch_quant_fp8);
 // W8: [N][ldb] E4M3FN bytes, wexp: [N] row exponents (-127 .. 127).  M % 128 == 0, N % 160 == 0,
-// lda, ldb multiples of 16, sst of 16.
+// lda, ldb multiples of 16, sst of 16.  With SC != nullptr the output is instead the FP8 copy the
+// next FP8 layer reads: C holds E4M3FN bytes (row stride ldc bytes) and SC the block scales (row
+// stride sstc), each value rounded to bf16 before it is quantised.
 df_status launch_gemm_fp8(const uint8_t *A8, int lda, const uint8_t *S, int sst, const uint8_t *W8, int ldb,
-                          const int32_t *wexp, const float *bias, bf16_t *C, int ldc, int64_t M, int N, int K,
-                          hipStream_t stream);
+                          const int32_t *wexp, const float *bias, bf16_t *C, int ldc, uint8_t *SC, int sstc,
+                          int64_t M, int N, int K, hipStream_t stream);
+
+// The first layer with an FP8 output: GELU(A . B^T + bias) as launch_gemm_bf16 for K = 32 or 64
+// (DF_E_UNSUPPORTED otherwise), written as the FP8 copy (E4M3FN bytes Q[M][ldq], block scales
+// S[M][sst]) of the bf16 values.
+df_status launch_gemm_bf16_fp8out(const bf16_t *A, int lda, const bf16_t *B, int ldb, const float *bias, uint8_t *Q,
+                                  int ldq, uint8_t *S, int sst, int64_t M, int N, int K, hipStream_t stream);
 
 }  // namespace df

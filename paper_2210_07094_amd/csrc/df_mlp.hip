@@ -191,82 +191,6 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(const bf16_t *__restrict
     }
 }
 
-// Inference layer with a shallow reduction (K = KD <= 64, the first hidden layer: the network's
-// inputs padded to 32 or 64): no K loop to pipeline, so the time is the GELU epilogue and the
-// stores of the M x N outputs.  Each block keeps one 160-column weight panel in registers as MFMA
-// fragments and walks down the row tiles tile_m = g, g + G, ... (G = gridDim.x / n_tiles_n),
-// loading each tile's activation fragments straight from global memory (16 rows x 64 contiguous
-// bytes per load) one tile ahead, so that the loads of the next tile are in flight during the
-// epilogue of the current one; no LDS and no barriers.  Same tile shape, operand order and
-// epilogue (bias, GELU, bf16) as gemm_kernel.
-template <int KD>
-__global__ __launch_bounds__(kThreads) void gemm_shallow_kernel(const bf16_t *__restrict__ A, int lda,
-                                                                const bf16_t *__restrict__ B, int ldb,
-                                                                const float *__restrict__ bias,
-                                                                bf16_t *__restrict__ C, int ldc, int n_tiles_m,
-                                                                int n_tiles_n) {
-    constexpr int KS = KD / 32;  // 32-deep MFMA steps
-    const int tile_n = int(blockIdx.x) % n_tiles_n, g0 = int(blockIdx.x) / n_tiles_n;
-    const int G = int(gridDim.x) / n_tiles_n;
-    const int col0 = tile_n * BN;
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int wm = w >> 1, wn = w & 1;
-    const int fr = lane & 15, fk = (lane >> 4) * 8;
-
-    bf16x8 bfr[KS][TN];
-#pragma unroll
-    for (int s = 0; s < KS; ++s)
-#pragma unroll
-        for (int j = 0; j < TN; ++j)
-            bfr[s][j] = *reinterpret_cast<const bf16x8 *>(B + int64_t(col0 + wn * WN + j * 16 + fr) * ldb + s * 32 + fk);
-    floatx4 bc[TN];
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-        bc[j] = *reinterpret_cast<const floatx4 *>(bias + col0 + wn * WN + j * 16 + (lane >> 4) * 4);
-
-    auto load_a = [&](int tm, bf16x8 (&af)[KS][TM]) {
-        const int64_t r0 = int64_t(tm) * BM + wm * WM + fr;
-#pragma unroll
-        for (int s = 0; s < KS; ++s)
-#pragma unroll
-            for (int i = 0; i < TM; ++i)
-                af[s][i] = *reinterpret_cast<const bf16x8 *>(A + (r0 + i * 16) * lda + s * 32 + fk);
-    };
-    bf16x8 an[KS][TM];
-    if (g0 < n_tiles_m) load_a(g0, an);
-    for (int tm = g0; tm < n_tiles_m; tm += G) {
-        bf16x8 af[KS][TM];
-#pragma unroll
-        for (int s = 0; s < KS; ++s)
-#pragma unroll
-            for (int i = 0; i < TM; ++i) af[s][i] = an[s][i];
-        if (tm + G < n_tiles_m) load_a(tm + G, an);
-        floatx4 acc[TM][TN];
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-            for (int j = 0; j < TN; ++j) {
-                acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                for (int s = 0; s < KS; ++s)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[s][j], af[s][i], acc[i][j], 0, 0, 0);
-            }
-        const int64_t row0 = int64_t(tm) * BM + wm * WM + fr;
-#pragma unroll
-        for (int j = 0; j < TN; ++j) {
-            const int col = col0 + wn * WN + j * 16 + (lane >> 4) * 4;
-#pragma unroll
-            for (int i = 0; i < TM; ++i) {
-                const int64_t row = row0 + i * 16;
-                floatx4 v = acc[i][j] + bc[j];
-#pragma unroll
-                for (int r = 0; r < 4; ++r) v[r] = gelu_erfc(v[r]);
-                *reinterpret_cast<bf16x4 *>(C + row * ldc + col) = to_bf16x4(v);
-            }
-        }
-    }
-}
-
 // A value the E4M3FN conversion takes as is: |x| <= 448 unchanged; 448 < |x| <= 464 rounds to
 // 448 (ties to even) and is passed as 448; a value that would round beyond 448, an infinity or a
 // NaN becomes NaN, the format's only non-finite value, so that it propagates to the cell's
@@ -286,6 +210,132 @@ __device__ __forceinline__ uint32_t to_fp8x4(float a, float b, float c, float d)
     int v = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);  // bytes 0, 1
     v = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, v, true);       // bytes 2, 3
     return uint32_t(v);
+}
+
+// FP8 output of a layer whose result feeds an FP8 layer, for a wave that owns whole 32-column
+// blocks: v0 and v1 are the GELU outputs of the 16 x 16 tiles 2q and 2q + 1 of a 16-row tile
+// (lane l: row l % 16, columns 4 (l / 16) + r of each), so a block's 32 values of a row lie with
+// the four lanes l % 16 + 16 g'.  Each value is rounded to bf16 first (the hidden activations are
+// bf16 values in every precision), the block's largest magnitude is combined over the four lanes
+// (NaN ignored), and the values are quantised with the block's scale: E4M3FN bytes to
+// Q[row][c0 .. c0 + 32) and the E8M0 scale byte to S[row][c0 / 32].
+__device__ __forceinline__ void store_fp8_block(floatx4 v0, floatx4 v1, uint8_t *__restrict__ Q,
+                                                uint8_t *__restrict__ S, int64_t row, int ldq, int sst, int c0,
+                                                int g) {
+    const bf16x4 h0 = to_bf16x4(v0), h1 = to_bf16x4(v1);
+    float f[8];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        f[r] = float(h0[r]);
+        f[4 + r] = float(h1[r]);
+    }
+    float m = 0.0f;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) m = fmaxf(m, fabsf(f[r]));
+    m = fmaxf(m, __shfl_xor(m, 16));
+    m = fmaxf(m, __shfl_xor(m, 32));
+    const int e = fp8_scale_exp(m);
+    const float sc = ldexpf(1.0f, -e);
+    uint8_t *q = Q + row * ldq + c0 + 4 * g;
+    *reinterpret_cast<uint32_t *>(q) = to_fp8x4(f[0] * sc, f[1] * sc, f[2] * sc, f[3] * sc);
+    *reinterpret_cast<uint32_t *>(q + 16) = to_fp8x4(f[4] * sc, f[5] * sc, f[6] * sc, f[7] * sc);
+    if (g == 0) S[row * sst + c0 / kFp8Block] = uint8_t(127 + e);
+}
+
+// Inference layer with a shallow reduction (K = KD <= 64, the first hidden layer: the network's
+// inputs padded to 32 or 64): no K loop to pipeline, so the time is the GELU epilogue and the
+// stores of the M x N outputs.  Each block keeps one 160-column weight panel in registers as MFMA
+// fragments and walks down the row tiles tile_m = g, g + G, ... (G = gridDim.x / n_tiles_n),
+// loading each tile's activation fragments straight from global memory (16 rows x 64 contiguous
+// bytes per load) one tile ahead, so that the loads of the next tile are in flight during the
+// epilogue of the current one; no LDS and no barriers.  Same tile shape, operand order and
+// epilogue (bias, GELU, bf16) as gemm_kernel; with Q8 the output is the FP8 copy the next layer
+// reads (store_fp8_block), and the four waves take 32 rows x 160 columns each so that every
+// wave owns whole 32-column blocks.
+template <int KD, bool Q8>
+__global__ __launch_bounds__(kThreads, 2) void gemm_shallow_kernel(const bf16_t *__restrict__ A, int lda,
+                                                                const bf16_t *__restrict__ B, int ldb,
+                                                                const float *__restrict__ bias,
+                                                                bf16_t *__restrict__ C, int ldc,
+                                                                uint8_t *__restrict__ S, int sst, int n_tiles_m,
+                                                                int n_tiles_n) {
+    constexpr int KS = KD / 32;  // 32-deep MFMA steps
+    constexpr int WMq = Q8 ? 32 : WM, WNq = Q8 ? 160 : WN, TMq = WMq / 16, TNq = WNq / 16;
+    const int tile_n = int(blockIdx.x) % n_tiles_n, g0 = int(blockIdx.x) / n_tiles_n;
+    const int G = int(gridDim.x) / n_tiles_n;
+    const int col0 = tile_n * BN;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int wm = Q8 ? w : w >> 1, wn = Q8 ? 0 : w & 1;
+    const int fr = lane & 15, fg = lane >> 4, fk = fg * 8;
+
+    bf16x8 bfr[KS][TNq];
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+        for (int j = 0; j < TNq; ++j)
+            bfr[s][j] = *reinterpret_cast<const bf16x8 *>(B + int64_t(col0 + wn * WNq + j * 16 + fr) * ldb + s * 32 + fk);
+    floatx4 bc[TNq];
+#pragma unroll
+    for (int j = 0; j < TNq; ++j)
+        bc[j] = *reinterpret_cast<const floatx4 *>(bias + col0 + wn * WNq + j * 16 + fg * 4);
+
+    auto load_a = [&](int tm, bf16x8 (&af)[KS][TMq]) {
+        const int64_t r0 = int64_t(tm) * BM + wm * WMq + fr;
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+#pragma unroll
+            for (int i = 0; i < TMq; ++i)
+                af[s][i] = *reinterpret_cast<const bf16x8 *>(A + (r0 + i * 16) * lda + s * 32 + fk);
+    };
+    bf16x8 an[KS][TMq];
+    if (g0 < n_tiles_m) load_a(g0, an);
+    for (int tm = g0; tm < n_tiles_m; tm += G) {
+        bf16x8 af[KS][TMq];
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+#pragma unroll
+            for (int i = 0; i < TMq; ++i) af[s][i] = an[s][i];
+        if (tm + G < n_tiles_m) load_a(tm + G, an);
+        floatx4 acc[TMq][TNq];
+#pragma unroll
+        for (int i = 0; i < TMq; ++i)
+#pragma unroll
+            for (int j = 0; j < TNq; ++j) {
+                acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int s = 0; s < KS; ++s)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[s][j], af[s][i], acc[i][j], 0, 0, 0);
+            }
+        const int64_t row0 = int64_t(tm) * BM + wm * WMq + fr;
+        if constexpr (Q8) {
+#pragma unroll
+            for (int i = 0; i < TMq; ++i)
+#pragma unroll
+                for (int q = 0; q < TNq / 2; ++q) {
+                    floatx4 v0 = acc[i][2 * q] + bc[2 * q], v1 = acc[i][2 * q + 1] + bc[2 * q + 1];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        v0[r] = gelu_erfc(v0[r]);
+                        v1[r] = gelu_erfc(v1[r]);
+                    }
+                    store_fp8_block(v0, v1, reinterpret_cast<uint8_t *>(C), S, row0 + i * 16, ldc, sst,
+                                    col0 + 32 * q, fg);
+                }
+        } else {
+#pragma unroll
+            for (int j = 0; j < TNq; ++j) {
+                const int col = col0 + wn * WNq + j * 16 + fg * 4;
+#pragma unroll
+                for (int i = 0; i < TMq; ++i) {
+                    const int64_t row = row0 + i * 16;
+                    floatx4 v = acc[i][j] + bc[j];
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) v[r] = gelu_erfc(v[r]);
+                    *reinterpret_cast<bf16x4 *>(C + row * ldc + col) = to_bf16x4(v);
+                }
+            }
+        }
+    }
 }
 
 // one thread per block of 32 activations of a row: the block's largest magnitude (NaN ignored),
@@ -341,12 +391,15 @@ __global__ __launch_bounds__(kQuantThreads) void quant_fp8_kernel(const bf16_t *
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 constexpr int KD8 = 128, LDK8 = KD8 + 16;  // stage depth and LDS row stride in bytes
 
-__global__ __launch_bounds__(kThreads) void gemm_fp8_kernel(const uint8_t *__restrict__ A8, int lda,
+template <bool Q8>
+__global__ __launch_bounds__(kThreads, 2) void gemm_fp8_kernel(const uint8_t *__restrict__ A8, int lda,
                                                            const uint8_t *__restrict__ SA, int sst,
                                                            const uint8_t *__restrict__ W8, int ldb,
                                                            const int32_t *__restrict__ wexp,
                                                            const float *__restrict__ bias, bf16_t *__restrict__ C,
-                                                           int ldc, int K, int n_tiles_n) {
+                                                           int ldc, uint8_t *__restrict__ SC, int sstc, int K,
+                                                           int n_tiles_n) {
+    constexpr int WMq = Q8 ? 32 : WM, WNq = Q8 ? 160 : WN, TMq = WMq / 16, TNq = WNq / 16;
     __shared__ __attribute__((aligned(16))) uint8_t As[BM * LDK8];
     __shared__ __attribute__((aligned(16))) uint8_t Bs[BN * LDK8];
     __shared__ uint32_t Ss[BM];
@@ -357,7 +410,7 @@ __global__ __launch_bounds__(kThreads) void gemm_fp8_kernel(const uint8_t *__res
     const int64_t row0 = int64_t(tile_m) * BM;
     const int col0 = tile_n * BN;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const int wm = w >> 1, wn = w & 1;
+    const int wm = Q8 ? w : w >> 1, wn = Q8 ? 0 : w & 1;
     const int fr = lane & 15, fg = lane >> 4;
 
     // 16-byte chunks: A BM*KD8/16 = 1024 (4 per thread), W BN*KD8/16 = 1280 (5 per thread)
@@ -400,14 +453,14 @@ __global__ __launch_bounds__(kThreads) void gemm_fp8_kernel(const uint8_t *__res
         if (t < BM) Ss[t] = rs;
     };
 
-    int sw[TN];  // E8M0 scale of the weight row each lane supplies
+    int sw[TNq];  // E8M0 scale of the weight row each lane supplies
 #pragma unroll
-    for (int j = 0; j < TN; ++j) sw[j] = 127 + wexp[col0 + wn * WN + j * 16 + fr];
-    floatx4 acc[TM][TN];
+    for (int j = 0; j < TNq; ++j) sw[j] = 127 + wexp[col0 + wn * WNq + j * 16 + fr];
+    floatx4 acc[TMq][TNq];
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+    for (int i = 0; i < TMq; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < TNq; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
     load(0);
     for (int k0 = 0; k0 < K; k0 += KD8) {
@@ -420,48 +473,83 @@ __global__ __launch_bounds__(kThreads) void gemm_fp8_kernel(const uint8_t *__res
             const u32x4 hi = *reinterpret_cast<const u32x4 *>(row + 64 + fg * 16);
             return i32x8{int(lo[0]), int(lo[1]), int(lo[2]), int(lo[3]), int(hi[0]), int(hi[1]), int(hi[2]), int(hi[3])};
         };
-        i32x8 wf[TN];
+        // the activation fragments (fewer than the weight ones) held, the weight fragments one at a time
+        i32x8 af[TMq];
+        int sa[TMq];
 #pragma unroll
-        for (int j = 0; j < TN; ++j) wf[j] = frag(Bs + (wn * WN + j * 16 + fr) * LDK8);
+        for (int i = 0; i < TMq; ++i) {
+            const int r = wm * WMq + i * 16 + fr;
+            af[i] = frag(As + r * LDK8);
+            sa[i] = int((Ss[r] >> (8 * fg)) & 0xffu);
+        }
 #pragma unroll
-        for (int i = 0; i < TM; ++i) {
-            const int r = wm * WM + i * 16 + fr;
-            const i32x8 af = frag(As + r * LDK8);
-            const int sa = int((Ss[r] >> (8 * fg)) & 0xffu);
+        for (int j = 0; j < TNq; ++j) {
+            const i32x8 wf = frag(Bs + (wn * WNq + j * 16 + fr) * LDK8);
 #pragma unroll
-            for (int j = 0; j < TN; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(wf[j], af, acc[i][j], 0, 0, 0, sw[j], 0, sa);
+            for (int i = 0; i < TMq; ++i)
+                acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(wf, af[i], acc[i][j], 0, 0, 0, sw[j], 0, sa[i]);
         }
     }
 
+    if constexpr (Q8) {
 #pragma unroll
-    for (int j = 0; j < TN; ++j) {
-        const int col = col0 + wn * WN + j * 16 + fg * 4;
-        const floatx4 bc = *reinterpret_cast<const floatx4 *>(bias + col);
+        for (int q = 0; q < TNq / 2; ++q) {
+            const floatx4 b0 = *reinterpret_cast<const floatx4 *>(bias + col0 + 32 * q + fg * 4);
+            const floatx4 b1 = *reinterpret_cast<const floatx4 *>(bias + col0 + 32 * q + 16 + fg * 4);
 #pragma unroll
-        for (int i = 0; i < TM; ++i) {
-            const int64_t row = row0 + wm * WM + i * 16 + fr;
-            floatx4 v = acc[i][j] + bc;
+            for (int i = 0; i < TMq; ++i) {
+                floatx4 v0 = acc[i][2 * q] + b0, v1 = acc[i][2 * q + 1] + b1;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) v[r] = gelu_erfc(v[r]);
-            *reinterpret_cast<bf16x4 *>(C + row * ldc + col) = to_bf16x4(v);
+                for (int r = 0; r < 4; ++r) {
+                    v0[r] = gelu_erfc(v0[r]);
+                    v1[r] = gelu_erfc(v1[r]);
+                }
+                store_fp8_block(v0, v1, reinterpret_cast<uint8_t *>(C), SC, row0 + wm * WMq + i * 16 + fr, ldc, sstc,
+                                col0 + 32 * q, fg);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < TNq; ++j) {
+            const int col = col0 + wn * WNq + j * 16 + fg * 4;
+            const floatx4 bc = *reinterpret_cast<const floatx4 *>(bias + col);
+#pragma unroll
+            for (int i = 0; i < TMq; ++i) {
+                const int64_t row = row0 + wm * WMq + i * 16 + fr;
+                floatx4 v = acc[i][j] + bc;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) v[r] = gelu_erfc(v[r]);
+                *reinterpret_cast<bf16x4 *>(C + row * ldc + col) = to_bf16x4(v);
+            }
         }
     }
 }
 
 // the shallow-reduction layer (K = 32 or 64, shapes checked by the caller): about two blocks per
-// CU, each on one 160-column panel and every G-th row tile
+// CU, each on one 160-column panel and every G-th row tile; S != nullptr: FP8 output (C holds the
+// E4M3FN bytes with row stride ldc, S the block scales with row stride sst)
 df_status launch_shallow(const bf16_t *A, int lda, const bf16_t *B, int ldb, const float *bias, bf16_t *C, int ldc,
-                         int64_t M, int N, int K, hipStream_t stream) {
+                         uint8_t *S, int sst, int64_t M, int N, int K, hipStream_t stream) {
     const int64_t tm = M / BM;
     const int tn = N / BN;
     if (tm > 0x7fffffff) return fail(DF_E_UNSUPPORTED, "gemm: too many row tiles");
     const int G = int(std::max<int64_t>(1, std::min<int64_t>(tm, std::max(1, 512 / tn))));
     const dim3 g = dim3(unsigned(int64_t(G) * tn)), b = dim3(kThreads);
-    if (K == 32)
-        hipLaunchKernelGGL(gemm_shallow_kernel<32>, g, b, 0, stream, A, lda, B, ldb, bias, C, ldc, int(tm), tn);
-    else
-        hipLaunchKernelGGL(gemm_shallow_kernel<64>, g, b, 0, stream, A, lda, B, ldb, bias, C, ldc, int(tm), tn);
+#define DF_SHALLOW(KD, Q)                                                                                        \
+    hipLaunchKernelGGL((gemm_shallow_kernel<KD, Q>), g, b, 0, stream, A, lda, B, ldb, bias, C, ldc, S, sst, int(tm), \
+                       tn)
+    if (K == 32) {
+        if (S)
+            DF_SHALLOW(32, true);
+        else
+            DF_SHALLOW(32, false);
+    } else {
+        if (S)
+            DF_SHALLOW(64, true);
+        else
+            DF_SHALLOW(64, false);
+    }
+#undef DF_SHALLOW
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(DF_E_HIP, std::string("gemm launch: ") + hipGetErrorString(e));
     return DF_OK;
@@ -484,7 +572,8 @@ df_status launch_gemm_bf16_epi(const bf16_t *A, int lda, const bf16_t *B, int ld
     if (M == 0) return DF_OK;
     const int64_t tiles = (M / BM) * (N / BN);
     if (tiles > 0x7fffffff) return fail(DF_E_UNSUPPORTED, "gemm: too many tiles");
-    if (epi == GemmEpi::gelu && (K == 32 || K == 64)) return launch_shallow(A, lda, B, ldb, bias, C, ldc, M, N, K, stream);
+    if (epi == GemmEpi::gelu && (K == 32 || K == 64))
+        return launch_shallow(A, lda, B, ldb, bias, C, ldc, nullptr, 0, M, N, K, stream);
     const dim3 g = dim3(unsigned(tiles)), b = dim3(kThreads);
     const bool deep = K % 64 == 0;
 #define DF_GEMM(E)                                                                                              \
@@ -525,18 +614,31 @@ df_status launch_quant_fp8(const bf16_t *A, int ld, int64_t M, uint8_t *Q, uint8
     return DF_OK;
 }
 
+df_status launch_gemm_bf16_fp8out(const bf16_t *A, int lda, const bf16_t *B, int ldb, const float *bias, uint8_t *Q,
+                                  int ldq, uint8_t *S, int sst, int64_t M, int N, int K, hipStream_t stream) {
+    if (M % BM || N % BN || lda % 8 || ldb % 8 || ldq % 16 || sst % 16 || sst < N / kFp8Block || !Q || !S)
+        return fail(DF_E_INVALID, "gemm: shapes must be multiples of the tile sizes");
+    if (K != 32 && K != 64) return fail(DF_E_UNSUPPORTED, "gemm with FP8 output: only a reduction depth of 32 or 64");
+    if (M == 0) return DF_OK;
+    return launch_shallow(A, lda, B, ldb, bias, reinterpret_cast<bf16_t *>(Q), ldq, S, sst, M, N, K, stream);
+}
+
 df_status launch_gemm_fp8(const uint8_t *A8, int lda, const uint8_t *S, int sst, const uint8_t *W8, int ldb,
-                          const int32_t *wexp, const float *bias, bf16_t *C, int ldc, int64_t M, int N, int K,
-                          hipStream_t stream) {
+                          const int32_t *wexp, const float *bias, bf16_t *C, int ldc, uint8_t *SC, int sstc,
+                          int64_t M, int N, int K, hipStream_t stream) {
     if (M % BM || N % BN || K % kFp8Block || lda % 16 || ldb % 16 || sst % 16 || lda < K || ldb < K ||
-        sst < K / kFp8Block)
+        sst < K / kFp8Block || (SC && (ldc % 16 || sstc % 16 || sstc < N / kFp8Block)))
         return fail(DF_E_INVALID, "gemm fp8: shapes must be multiples of the tile sizes (rows of 16 bytes)");
     if (!A8 || !S || !W8 || !wexp) return fail(DF_E_INVALID, "gemm fp8: null activation, scale, weight or exponent array");
     if (M == 0) return DF_OK;
     const int64_t tiles = (M / BM) * (N / BN);
     if (tiles > 0x7fffffff) return fail(DF_E_UNSUPPORTED, "gemm fp8: too many tiles");
-    hipLaunchKernelGGL(gemm_fp8_kernel, dim3(unsigned(tiles)), dim3(kThreads), 0, stream, A8, lda, S, sst, W8, ldb,
-                       wexp, bias, C, ldc, K, N / BN);
+    if (SC)
+        hipLaunchKernelGGL(gemm_fp8_kernel<true>, dim3(unsigned(tiles)), dim3(kThreads), 0, stream, A8, lda, S, sst, W8,
+                           ldb, wexp, bias, C, ldc, SC, sstc, K, N / BN);
+    else
+        hipLaunchKernelGGL(gemm_fp8_kernel<false>, dim3(unsigned(tiles)), dim3(kThreads), 0, stream, A8, lda, S, sst,
+                           W8, ldb, wexp, bias, C, ldc, SC, sstc, K, N / BN);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(DF_E_HIP, std::string("gemm fp8 launch: ") + hipGetErrorString(e));
     return DF_OK;
