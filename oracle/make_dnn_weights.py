@@ -3,11 +3,17 @@
 Test infrastructure: the labels come from the CPU oracle's integrator only.
 
 1. Seeded 0-D constant-pressure trajectories of H2/air (T0 ~ U(300, 2500) K,
-   phi ~ U(0.3, 3), p = 1 atm) are integrated by the oracle and sampled at
-   log-spaced times up to 5 ms.
-2. Training states are drawn from those trajectories and perturbed in
-   Box-Cox space (z_k += U(-0.3, 0.3) for species present, T += N(0, 20 K)),
-   then renormalised.
+   phi ~ U(0.3, 3), p = 1 atm) are integrated by the oracle out to 10 ms and
+   sampled as densely as the state moves (at most 10 K and 0.25 in any
+   Box-Cox component between samples; see trajectories()), so that the slow
+   heat release and the late in-flame states are covered as well as the
+   early radical build-up.
+2. Training states: every sampled state as it is; unreacted premixed states
+   (T ~ U(300, 2500) K, phi ~ U(0.3, 3), no radicals), where the first step
+   creates the radical pool; copies with small
+   perturbations (z_k += U(-0.05, 0.05) for the species present,
+   T += N(0, 5 K)), the states a flow step leaves near the trajectories; and
+   copies with large ones (U(-0.3, 0.3), N(0, 20 K)); all renormalised.
 3. Each state is advanced by the oracle over dt = 1 us; the label is the
    increment of z = BoxCox(Y) with lambda = 0.1 (the paper's DNN maps
    (T, P, BCT(Y)) to the change of its input over a 1 us step).
@@ -16,8 +22,7 @@ Test infrastructure: the labels come from the CPU oracle's integrator only.
    cosine learning-rate decay) and written as a DFDNN01 file with bf16
    weights; the training box is the per-feature min/max of the raw inputs.
 
-    python oracle/make_dnn_weights.py --samples 2000000 --epochs 12 \
-        --out paper_2210_07094_amd/data/h2_dnn_1600_800_400.dfdnn
+    python oracle/make_dnn_weights.py --out paper_2210_07094_amd/data/h2_dnn_1600_800_400.dfdnn
 """
 from __future__ import annotations
 
@@ -48,37 +53,59 @@ def bct_inv(z):
     return np.maximum(1.0 + LAM * z, 0.0) ** (1.0 / LAM)
 
 
-def trajectories(om, mech, n_traj, rng, t_end=5e-3, n_times=40):
+def trajectories(om, mech, n_traj, rng, t_end=1e-2, dT_max=10.0, dz_max=0.25, tau0=1e-8, tau_max=2e-4):
+    """States along seeded 0-D constant-pressure trajectories, spaced by state change.
+
+    Each trajectory is advanced by the oracle in intervals tau that adapt to the change they
+    produce: an interval whose temperature change exceeds dT_max or whose largest Box-Cox change
+    exceeds dz_max is taken again at half the length (down to 1 us, which is always accepted);
+    an accepted interval stores its end state and doubles tau (up to tau_max).  So the fast
+    early radical build-up, the slow heat release over milliseconds and the late near-equilibrium
+    evolution are sampled as densely as the state moves, not as densely as time passes."""
     T0 = rng.uniform(300.0, 2500.0, n_traj)
     phi = rng.uniform(0.3, 3.0, n_traj)
     Y = fields.premixed_h2_air(mech, phi)
     T = T0.copy()
     p = np.full(n_traj, P_ATM)
-    times = np.concatenate([[0.0], np.logspace(-8, np.log10(t_end), n_times)])
     h = np.zeros(n_traj)
+    t = np.zeros(n_traj)
+    tau = np.full(n_traj, tau0)
     states_T, states_Y = [T.copy()], [Y.copy()]
     o = oracle.default_opts(rtol=1e-7, atol_Y=1e-14, max_steps=200000)
-    for a, b in zip(times[:-1], times[1:]):
-        r = om.chem_step(T, p, Y, b - a, h_inout=h, opts=o)
-        ok = r["status"] == 0
-        T = np.where(ok, r["T"], T)
-        Y = np.where(ok[None, :], r["Y"], Y)
-        h = r["h"]
-        states_T.append(T.copy())
-        states_Y.append(Y.copy())
+    live = np.arange(n_traj)
+    while live.size:
+        step = np.minimum(tau[live], t_end - t[live])
+        r = om.chem_step(T[live], p[live], Y[:, live], step, h_inout=h[live], opts=o)
+        dT = np.abs(r["T"] - T[live])
+        dz = np.abs(bct(r["Y"]) - bct(Y[:, live])).max(axis=0)
+        ok = (r["status"] == 0) & (((dT <= dT_max) & (dz <= dz_max)) | (step <= DT))
+        acc, rej = live[ok], live[~ok]
+        T[acc], Y[:, acc], h[acc] = r["T"][ok], r["Y"][:, ok], r["h"][ok]
+        t[acc] += step[ok]
+        tau[acc] = np.minimum(2.0 * tau[acc], tau_max)
+        tau[rej] = np.maximum(0.5 * tau[rej], DT)
+        states_T.append(T[acc].copy())
+        states_Y.append(Y[:, acc].copy())
+        live = live[t[live] < t_end * (1.0 - 1e-12)]
     return np.concatenate(states_T), np.concatenate(states_Y, axis=1)
 
 
-def make_samples(om, mech, n, rng, pool_T, pool_Y, chunk=100000):
-    K = mech.n_species
+def perturb(pool_T, pool_Y, n, rng, dz, sT):
+    """n states drawn from the pool with z_k += U(-dz, dz) for the species present and
+    T += N(0, sT), renormalised."""
     idx = rng.integers(0, pool_T.size, n)
-    T = pool_T[idx] + rng.normal(0.0, 20.0, n)
-    T = np.clip(T, 280.0, 2900.0)
+    T = np.clip(pool_T[idx] + rng.normal(0.0, sT, n), 280.0, 2900.0)
     z = bct(pool_Y[:, idx])
     present = z > -9.99
-    z = z + np.where(present, rng.uniform(-0.3, 0.3, z.shape), 0.0)
-    Y = bct_inv(z)
+    Y = bct_inv(z + np.where(present, rng.uniform(-dz, dz, z.shape), 0.0))
     Y /= Y.sum(axis=0, keepdims=True)
+    return T, Y
+
+
+def make_samples(om, mech, T, Y, chunk=100000):
+    """Rows (T, p, BCT(Y)) and labels BCT(Y(t + dt)) - BCT(Y) from one oracle step of dt."""
+    K = mech.n_species
+    n = T.size
     p = np.full(n, P_ATM)
     T1 = np.empty(n)
     Y1 = np.empty((K, n))
@@ -139,9 +166,11 @@ def train(x, y, epochs, seed, batch=4096, lr=1e-3, widths=(1600, 800, 400)):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--mech", default=os.path.join(os.path.dirname(HERE), "synth", "data", "h2_synth_9sp_24r.mech"))
-    ap.add_argument("--samples", type=int, default=2_000_000)
-    ap.add_argument("--trajectories", type=int, default=4000)
-    ap.add_argument("--epochs", type=int, default=12)
+    ap.add_argument("--trajectories", type=int, default=8000)
+    ap.add_argument("--near", type=int, default=700_000, help="states with small perturbations")
+    ap.add_argument("--far", type=int, default=600_000, help="states with large perturbations")
+    ap.add_argument("--fresh", type=int, default=400_000, help="unreacted premixed states")
+    ap.add_argument("--epochs", type=int, default=16)
     ap.add_argument("--seed", type=int, default=2210)
     ap.add_argument("--out", default=os.path.join(os.path.dirname(HERE), "paper_2210_07094_amd", "data",
                                                   "h2_dnn_1600_800_400.dfdnn"))
@@ -152,7 +181,11 @@ def main():
     t0 = time.time()
     pool_T, pool_Y = trajectories(om, mech, a.trajectories, rng)
     print(f"trajectory pool: {pool_T.size} states ({time.time() - t0:.0f} s)", flush=True)
-    x, dz = make_samples(om, mech, a.samples, rng, pool_T, pool_Y)
+    Tn, Yn = perturb(pool_T, pool_Y, a.near, rng, 0.05, 5.0)
+    Tf, Yf = perturb(pool_T, pool_Y, a.far, rng, 0.3, 20.0)
+    T0 = rng.uniform(300.0, 2500.0, a.fresh)
+    Y0 = fields.premixed_h2_air(mech, rng.uniform(0.3, 3.0, a.fresh))
+    x, dz = make_samples(om, mech, np.concatenate([pool_T, Tn, Tf, T0]), np.concatenate([pool_Y, Yn, Yf, Y0], axis=1))
     print(f"samples: {x.shape[0]} ({time.time() - t0:.0f} s)", flush=True)
     W, b, mu_in, sig_in, mu_out, sig_out = train(x, dz, a.epochs, a.seed)
     os.makedirs(os.path.dirname(a.out), exist_ok=True)

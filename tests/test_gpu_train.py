@@ -116,11 +116,14 @@ def test_adam_step_matches_oracle(h2_path, h2_mech, h2_oracle):
         assert np.array_equal(W0[l], Ws[l])          # the master starts from the stored weights
         wo, _, _ = mt.adam(Ws[l], dW[l], np.zeros_like(Ws[l]), np.zeros_like(Ws[l]), 1, lr, 0.9, 0.999, 1e-8)
         # away from gradients near zero (where rounding may flip the sign), the first step is
-        # lr sign(g) on both sides
-        big = np.abs(dW[l]) > 0.05 * np.sqrt(np.mean(dW[l] ** 2))
+        # lr sign(g) on both sides.  The bf16 gradients differ from the oracle's by at most 2e-2
+        # of the norm (test above), about 2e-2 of the RMS per element; over the 1.28M weights of
+        # the 1600 -> 800 layer the largest such error reaches 5 sigma, so "away from zero" is
+        # 0.25 RMS, over 12 sigma
+        big = np.abs(dW[l]) > 0.25 * np.sqrt(np.mean(dW[l] ** 2))
         d = np.abs((W1[l] - W0[l]) - (wo - Ws[l]))[big]
         assert np.max(d) <= 1e-3 * lr + 1e-7 * np.abs(Ws[l]).max(), (l, np.max(d))
-        assert np.mean(big) > 0.2
+        assert np.mean(big) > 0.05     # a share of every layer takes part (12 % of the largest)
 
 
 def test_training_on_integrator_states_reduces_the_error(h2_path, h2_mech):
