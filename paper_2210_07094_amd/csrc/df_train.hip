@@ -47,33 +47,40 @@ __global__ __launch_bounds__(kT) void load_x_kernel(const float *__restrict__ x,
     xb[e] = (b < B && c < n_in) ? tbf(x[b * n_in + c]) : bf16_t(0);
 }
 
-// output layer and loss, one thread per batch row: u = W h + b (fp32 accumulation of bf16
-// operands, as inference), du = 2 (u - t)/(B O), row loss, and da of the last hidden layer
+// output layer and loss, one wavefront per batch row (the 64 lanes split the hidden units,
+// lane i taking units i, i + 64, ...): u = W h + b (bf16 operands, fp32 partial sums per lane,
+// combined by a fixed butterfly, so every lane holds u), du = 2 (u - t)/(B O), the row loss, and
+// da of the last hidden layer, each lane writing its own units
 template <int O>
 __global__ __launch_bounds__(kT) void out_loss_kernel(const bf16_t *__restrict__ h, const bf16_t *__restrict__ a,
                                                       int hid, const bf16_t *__restrict__ W,
                                                       const float *__restrict__ bias, const float *__restrict__ t,
                                                       int64_t B, int64_t Bp, float *__restrict__ du,
                                                       float *__restrict__ row_loss, bf16_t *__restrict__ da) {
-    const int64_t b = int64_t(blockIdx.x) * kT + threadIdx.x;
+    static_assert(O <= 64, "one lane per output writes du");
+    const int lane = int(threadIdx.x) & 63;
+    const int64_t b = int64_t(blockIdx.x) * (kT / 64) + (threadIdx.x >> 6);
     if (b >= Bp) return;
     bf16_t *dar = da + b * hid;
     if (b >= B) {
-        for (int i = 0; i < hid; ++i) dar[i] = 0;
-#pragma unroll
-        for (int o = 0; o < O; ++o) du[b * O + o] = 0.0f;
-        row_loss[b] = 0.0f;
+        for (int i = lane; i < hid; i += 64) dar[i] = 0;
+        if (lane < O) du[b * O + lane] = 0.0f;
+        if (lane == 0) row_loss[b] = 0.0f;
         return;
     }
     const bf16_t *hr = h + b * hid;
     float u[O];
 #pragma unroll
     for (int o = 0; o < O; ++o) u[o] = 0.0f;
-    for (int i = 0; i < hid; ++i) {
+    for (int i = lane; i < hid; i += 64) {
         const float hv = fbf(hr[i]);
 #pragma unroll
         for (int o = 0; o < O; ++o) u[o] = fmaf(fbf(W[o * hid + i]), hv, u[o]);
     }
+#pragma unroll
+    for (int o = 0; o < O; ++o)
+#pragma unroll
+        for (int m = 32; m > 0; m >>= 1) u[o] += __shfl_xor(u[o], m);
     const float sc = 2.0f / float(B * O);
     float g[O], l = 0.0f;
 #pragma unroll
@@ -81,11 +88,11 @@ __global__ __launch_bounds__(kT) void out_loss_kernel(const bf16_t *__restrict__
         const float e = u[o] + bias[o] - t[b * O + o];
         l = fmaf(e, e, l);
         g[o] = sc * e;
-        du[b * O + o] = g[o];
+        if (lane == o) du[b * O + o] = g[o];
     }
-    row_loss[b] = l;
+    if (lane == 0) row_loss[b] = l;
     const bf16_t *ar = a + b * hid;
-    for (int i = 0; i < hid; ++i) {
+    for (int i = lane; i < hid; i += 64) {
         float s = 0.0f;
 #pragma unroll
         for (int o = 0; o < O; ++o) s = fmaf(g[o], fbf(W[o * hid + i]), s);
@@ -466,7 +473,7 @@ df_status df_dnn_train_step(df_trainer *t, int64_t batch, const float *x, const 
     }
     const int hid = Lo.k_pad;
     if (st == DF_OK) {
-        hipLaunchKernelGGL(out_loss_kernel<O>, dim3(unsigned((Bp + kT - 1) / kT)), dim3(kT), 0, s, t->h[nh - 1],
+        hipLaunchKernelGGL(out_loss_kernel<O>, dim3(unsigned((Bp + kT / 64 - 1) / (kT / 64))), dim3(kT), 0, s, t->h[nh - 1],
                            t->a[nh - 1], hid, Lo.W, Lo.b, target, B, Bp, t->du, t->row_loss, t->da[nh - 1]);
         chk("output layer");
         hipLaunchKernelGGL(loss_sum_kernel, dim3(1), dim3(kT), 0, s, t->row_loss, B, O, t->loss);
