@@ -12,6 +12,7 @@
 //   dW_l = da_l^T in_l,  db_l = sum_b da_l      (fp32, reductions over the batch; dW on MFMA)
 // Adam (Kingma and Ba, ICLR 2015) on fp32 master weights; each update rewrites the handle's
 // bf16 weights (so df_dnn_step runs the trained network) and the transposed bf16 copies.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -23,6 +24,7 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ bf16_t tbf(float x) {
     unsigned u = __float_as_uint(x);
@@ -115,15 +117,31 @@ __global__ __launch_bounds__(kT) void loss_sum_kernel(const float *__restrict__ 
     if (threadIdx.x == 0) *loss = float(part[0] / double(B * O));
 }
 
-// dW[M][N] (fp32) = sum_b A[b][M] X[b][N] over Bp rows (bf16 operands, MFMA 16x16x32 with fp32
-// accumulation): one wave per 32 x 32 tile of dW, four MFMA tiles, 32 batch rows per step.  A
-// lane supplies operand row (lane % 16) with the 8 batch rows 8 (lane / 16) .. + 7.
-// The blocks of the first column of tiles also sum A over the batch (the bias gradient db).
+// dW[M][N] (fp32) = sum_b A[b][M] X[b][N] over the batch rows (bf16 operands, MFMA 16x16x32 with
+// fp32 accumulation): one wave per 32 x 32 tile of dW and slice of the batch (S slices of whole
+// 32-row steps; block (tile, s) takes steps s, s + S, ...), four MFMA tiles, 32 batch rows per
+// step.  The batch is the reduction dimension, so each step's 32 x 32 slices of A and X are read
+// as 16-byte row pieces and written to LDS transposed ([m][b]); a lane then reads operand row
+// (lane % 16) with the 8 batch rows 8 (lane / 16) .. + 7 as one 16-byte fragment.  The blocks of
+// the first column of tiles also sum A over their batch rows (the bias gradient db).  With S = 1
+// the sums go to dW and db, else to the slice's partial arrays P[s][M][N] and Pb[s][M], which
+// wgrad_reduce_kernel adds in slice order: the result does not depend on the launch.
+constexpr int kWgT = 32 + 8;  // LDS row stride of the transposed slices (bf16)
+
+// orders the LDS writes and reads of the lanes of one wavefront (the workgroup is one wave, so a
+// workgroup barrier would not order them)
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 __global__ __launch_bounds__(64) void wgrad_kernel(const bf16_t *__restrict__ A, int lda, const bf16_t *__restrict__ X,
-                                                   int ldx, int64_t Bp, float *__restrict__ dW, int ldw, int tiles_n,
-                                                   float *__restrict__ db) {
+                                                   int ldx, int64_t Bp, int S, float *__restrict__ dW, int ldw,
+                                                   int tiles_n, float *__restrict__ db) {
+    __shared__ __attribute__((aligned(16))) bf16_t At[32 * kWgT], Xt[32 * kWgT];
     const int lane = threadIdx.x;
-    const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
+    const int tile = int(blockIdx.x) / S, sl = int(blockIdx.x) % S;
+    const int tm = tile / tiles_n, tn = tile % tiles_n;
     const int m0 = tm * 32, n0 = tn * 32;
     const int fr = lane & 15, fk = (lane >> 4) * 8;
     float cs[2] = {0.0f, 0.0f};
@@ -132,28 +150,38 @@ __global__ __launch_bounds__(64) void wgrad_kernel(const bf16_t *__restrict__ A,
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (int64_t b0 = 0; b0 < Bp; b0 += 32) {
+    // this lane's two 16-byte pieces of each slice: batch row c / 4, columns 8 (c % 4) .. + 7
+    const int c0 = lane, c1 = lane + 64;
+    for (int64_t b0 = int64_t(sl) * 32; b0 < Bp; b0 += int64_t(S) * 32) {
+        const u32x4 a0 = *reinterpret_cast<const u32x4 *>(A + (b0 + c0 / 4) * lda + m0 + 8 * (c0 % 4));
+        const u32x4 a1 = *reinterpret_cast<const u32x4 *>(A + (b0 + c1 / 4) * lda + m0 + 8 * (c1 % 4));
+        const u32x4 x0 = *reinterpret_cast<const u32x4 *>(X + (b0 + c0 / 4) * ldx + n0 + 8 * (c0 % 4));
+        const u32x4 x1 = *reinterpret_cast<const u32x4 *>(X + (b0 + c1 / 4) * ldx + n0 + 8 * (c1 % 4));
+        wave_lds_sync();  // the previous step's fragment reads are done
+        // value q of a 16-byte piece is the low (q even) or high (q odd) half of word q / 2
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int sh = 16 * (q & 1);
+            At[(8 * (c0 % 4) + q) * kWgT + c0 / 4] = bf16_t(a0[q / 2] >> sh);
+            At[(8 * (c1 % 4) + q) * kWgT + c1 / 4] = bf16_t(a1[q / 2] >> sh);
+            Xt[(8 * (c0 % 4) + q) * kWgT + c0 / 4] = bf16_t(x0[q / 2] >> sh);
+            Xt[(8 * (c1 % 4) + q) * kWgT + c1 / 4] = bf16_t(x1[q / 2] >> sh);
+        }
+        wave_lds_sync();
         bf16x8 af[2], xf[2];
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
-            __bf16 va[8], vx[8];
+            af[i] = *reinterpret_cast<const bf16x8 *>(At + (i * 16 + fr) * kWgT + fk);
+            xf[i] = *reinterpret_cast<const bf16x8 *>(Xt + (i * 16 + fr) * kWgT + fk);
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int64_t b = b0 + fk + q;
-                const unsigned short ua = A[b * lda + m0 + i * 16 + fr];
-                const unsigned short ux = X[b * ldx + n0 + i * 16 + fr];
-                va[q] = __builtin_bit_cast(__bf16, ua);
-                vx[q] = __builtin_bit_cast(__bf16, ux);
-                cs[i] += fbf(ua);
-            }
-            af[i] = bf16x8{va[0], va[1], va[2], va[3], va[4], va[5], va[6], va[7]};
-            xf[i] = bf16x8{vx[0], vx[1], vx[2], vx[3], vx[4], vx[5], vx[6], vx[7]};
+            for (int q = 0; q < 8; ++q) cs[i] += float(af[i][q]);
         }
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], xf[j], acc[i][j], 0, 0, 0);
     }
+    float *out = (S == 1) ? dW : dW + size_t(sl) * size_t(gridDim.x / S / tiles_n * 32) * ldw;
     // lane holds column (lane % 16) and rows 4 (lane / 16) + r of each 16 x 16 tile
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -161,17 +189,44 @@ __global__ __launch_bounds__(64) void wgrad_kernel(const bf16_t *__restrict__ A,
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                dW[int64_t(m0 + i * 16 + (lane >> 4) * 4 + r) * ldw + n0 + j * 16 + fr] = acc[i][j][r];
+                out[int64_t(m0 + i * 16 + (lane >> 4) * 4 + r) * ldw + n0 + j * 16 + fr] = acc[i][j][r];
     if (tn == 0) {
         // lanes l, l + 16, l + 32, l + 48 hold the four batch quarters of row m0 + i 16 + l
+        float *outb = (S == 1) ? db : db + size_t(sl) * size_t(gridDim.x / S / tiles_n * 32);
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
             float v = cs[i];
             v += __shfl_xor(v, 16);
             v += __shfl_xor(v, 32);
-            if (lane < 16) db[m0 + i * 16 + lane] = v;
+            if (lane < 16) outb[m0 + i * 16 + lane] = v;
         }
     }
+}
+
+// dW = sum over the S slices of P[s] (in slice order), db likewise from Pb
+__global__ __launch_bounds__(kT) void wgrad_reduce_kernel(const float *__restrict__ P, const float *__restrict__ Pb,
+                                                          int S, int64_t nw, int nb, float *__restrict__ dW,
+                                                          float *__restrict__ db) {
+    const int64_t e = int64_t(blockIdx.x) * kT + threadIdx.x;
+    if (e < nw) {
+        float v = 0.0f;
+        for (int k = 0; k < S; ++k) v += P[size_t(k) * nw + e];
+        dW[e] = v;
+    } else if (e < nw + nb) {
+        const int64_t c = e - nw;
+        float v = 0.0f;
+        for (int k = 0; k < S; ++k) v += Pb[size_t(k) * nb + c];
+        db[c] = v;
+    }
+}
+
+// batch slices of the weight gradient of a layer with `tiles` 32 x 32 tiles: enough blocks to
+// fill the chip (about 2048 waves), at most 32 and at most one per 32-row step
+int wgrad_slices(int64_t tiles, int64_t Bp) {
+    int64_t S = (2048 + tiles - 1) / tiles;
+    S = std::min<int64_t>(S, 32);
+    S = std::min<int64_t>(S, std::max<int64_t>(1, Bp / 32));
+    return int(std::max<int64_t>(S, 1));
 }
 
 // output layer gradients: dW[o][i] = sum_b du[b][o] h[b][i], db[o] = sum_b du[b][o]; one
@@ -298,6 +353,7 @@ struct df_trainer {
     df::bf16_t *x;
     std::vector<df::bf16_t *> h, a, da;  // per hidden layer [bp][n_pad]
     float *du, *row_loss, *loss;
+    float *part, *part_b;  // weight-gradient partial sums over batch slices
     int64_t step;
 };
 
@@ -359,6 +415,20 @@ df_status df_dnn_trainer_create(df_dnn *d, int64_t max_batch, df_trainer **out) 
     o = al(o + size_t(t->bp) * 4);
     const size_t ol = o;
     o = al(o + 4);
+    // partial weight gradients of the hidden layers, for the largest slice count of any of them
+    size_t part = 0, part_b = 0;
+    for (int l = 0; l < nh; ++l) {
+        const DnnLayer &Ly = d->layers[l];
+        const int S = wgrad_slices(int64_t(Ly.n_pad / 32) * (Ly.k_pad / 32), t->bp);
+        if (S > 1) {
+            part = std::max(part, size_t(S) * Ly.n_pad * Ly.k_pad);
+            part_b = std::max(part_b, size_t(S) * Ly.n_pad);
+        }
+    }
+    const size_t opart = o;
+    o = al(o + part * 4);
+    const size_t opb = o;
+    o = al(o + part_b * 4);
     int prev = 0;
     if (hipGetDevice(&prev) != hipSuccess || hipSetDevice(d->device) != hipSuccess) {
         delete t;
@@ -399,6 +469,8 @@ df_status df_dnn_trainer_create(df_dnn *d, int64_t max_batch, df_trainer **out) 
     t->du = reinterpret_cast<float *>(base + odu);
     t->row_loss = reinterpret_cast<float *>(base + orl);
     t->loss = reinterpret_cast<float *>(base + ol);
+    t->part = reinterpret_cast<float *>(base + opart);
+    t->part_b = reinterpret_cast<float *>(base + opb);
     e = hipDeviceSynchronize();
     if (e == hipSuccess) e = hipGetLastError();
     (void)hipSetDevice(prev);
@@ -488,9 +560,17 @@ df_status df_dnn_train_step(df_trainer *t, int64_t batch, const float *x, const 
         const bf16_t *inl = (l == 0) ? t->x : t->h[l - 1];
         const int inl_ld = Ly.k_pad;
         const int tiles_n = Ly.k_pad / 32;
-        hipLaunchKernelGGL(wgrad_kernel, dim3(unsigned((Ly.n_pad / 32) * tiles_n)), dim3(64), 0, s, t->da[l], Ly.n_pad,
-                           inl, inl_ld, Bp, t->gW[l], Ly.k_pad, tiles_n, t->gb[l]);
+        const int64_t tiles = int64_t(Ly.n_pad / 32) * tiles_n;
+        const int S = wgrad_slices(tiles, Bp);
+        hipLaunchKernelGGL(wgrad_kernel, dim3(unsigned(tiles * S)), dim3(64), 0, s, t->da[l], Ly.n_pad, inl, inl_ld,
+                           Bp, S, S > 1 ? t->part : t->gW[l], Ly.k_pad, tiles_n, S > 1 ? t->part_b : t->gb[l]);
         chk("weight gradient");
+        if (S > 1) {
+            const int64_t nw = int64_t(Ly.n_pad) * Ly.k_pad;
+            hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(unsigned((nw + Ly.n_pad + kT - 1) / kT)), dim3(kT), 0, s,
+                               t->part, t->part_b, S, nw, Ly.n_pad, t->gW[l], t->gb[l]);
+            chk("weight gradient sum");
+        }
         if (l > 0 && st == DF_OK)
             st = launch_gemm_bf16_epi(t->da[l], Ly.n_pad, t->WT[l], Ly.n_pad, nullptr, t->da[l - 1], Ly.k_pad, Bp,
                                       Ly.k_pad, Ly.n_pad, GemmEpi::gelu_grad, t->a[l - 1], s);
