@@ -101,13 +101,15 @@ typedef struct {
     int32_t fallback;    /* 1 (default): integrate cells outside the training range;
                             0: leave them unchanged and flag DF_CELL_DNN_FALLBACK */
     int32_t precision;   /* 0 (default): every hidden layer in bf16 (fp32 sums);
-                            1: the layers between two hidden layers in FP8 (OCP E4M3FN, fp32
-                            sums), an inference variant the paper's BF16 network does not fix:
-                            activations take one power-of-two scale per call (from the largest
-                            |value| over the call's cells, a cell the network does not predict
-                            counting with a zero input), weights one power-of-two scale per row,
-                            quantised at load; round to nearest even.  The first hidden layer
-                            and the output layer stay as with 0 */
+                            1: the layers between two hidden layers in FP8 (OCP E4M3FN on the
+                            block-scaled matrix cores, fp32 sums), an inference variant the
+                            paper's BF16 network does not fix: each row of a layer's input
+                            activations takes one power-of-two scale per block of 32 values
+                            (from the block's largest |value|, at least 2^-127), weights one
+                            power-of-two scale per row, quantised at load; round to nearest
+                            even.  The first hidden layer and the output layer stay as with 0;
+                            a first layer with more than 64 padded inputs is refused
+                            (DF_E_UNSUPPORTED) */
     int32_t reserved1;   /* must be 0 */
 } df_dnn_opts;
 

@@ -232,8 +232,7 @@ int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 
 struct WsLayout {
     int64_t n_pad;
-    size_t o_x, o_a, o_b, o_flag, o_idx, o_cnt, o_q, o_s, total;
-    int sst;  // scale bytes per row of the FP8 activation copy
+    size_t o_x, o_a, o_b, o_flag, o_idx, o_cnt, total;
     int wa, wb;  // widths of the two activation buffers
 };
 
@@ -262,13 +261,6 @@ WsLayout workspace_layout(const df_dnn *d, int64_t n) {
     o = al(o + size_t(w.n_pad) * 4);
     w.o_cnt = o;
     o = al(o + 4);
-    // FP8 copy of a hidden layer's output (E4M3FN bytes and block scales), for FP8 inference
-    const int wq = std::max(w.wa, w.wb);
-    w.sst = fp8_scale_stride(wq);
-    w.o_q = o;
-    o = al(o + size_t(w.n_pad) * wq);
-    w.o_s = o;
-    o = al(o + size_t(w.n_pad) * w.sst);
     w.total = o;
     return w;
 }
@@ -339,8 +331,6 @@ df_status launch_dnn_k(const df_dnn *d, const df_mech *m, int64_t n, int64_t ld,
     auto *flag = reinterpret_cast<int8_t *>(base + w.o_flag);
     auto *idx = reinterpret_cast<int32_t *>(base + w.o_idx);
     auto *cnt = reinterpret_cast<int32_t *>(base + w.o_cnt);
-    auto *q8 = base + w.o_q;
-    auto *s8 = base + w.o_s;
     hipLaunchKernelGGL(zero_count, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t *>(cnt));
     const int in_pad = d->layers[0].k_pad;
     hipLaunchKernelGGL(pre_kernel<K>, dim3(unsigned((w.n_pad + kPreThreads - 1) / kPreThreads)), dim3(kPreThreads), 0,
@@ -362,10 +352,10 @@ df_status launch_dnn_k(const df_dnn *d, const df_mech *m, int64_t n, int64_t ld,
         bf16_t *out = (l % 2 == 0) ? ba : bb;
         const int out_ld = (l % 2 == 0) ? w.wa : w.wb;
         // layers 1..nh-1 (between two hidden layers) in FP8: each reads the E4M3FN copy of its
-        // input (bytes and block scales), written by the layer before it where that layer can
-        // (the first layer with K = 32 or 64, an FP8 layer), else quantised from its bf16 output.
-        // An FP8 copy fills the layer's activation buffer as bytes [n_pad][out_ld] followed by
-        // the scales [n_pad][sst].
+        // input (bytes and block scales), written by the layer before it (the first layer, whose
+        // K is 32 or 64 for every compiled species count, or an FP8 layer).  An FP8 copy fills
+        // the layer's activation buffer as bytes [n_pad][out_ld] followed by the scales
+        // [n_pad][sst].
         const bool q_next = fp8 && l + 1 < nh;
         auto *o8 = reinterpret_cast<uint8_t *>(out);
         uint8_t *o8s = o8 + size_t(w.n_pad) * out_ld;
@@ -373,18 +363,12 @@ df_status launch_dnn_k(const df_dnn *d, const df_mech *m, int64_t n, int64_t ld,
         df_status st;
         bool wrote8 = false;
         if (fp8 && l >= 1) {
-            if (!a8) {
-                st = launch_quant_fp8(in, in_ld, w.n_pad, q8, s8, w.sst, s);
-                if (st != DF_OK) return st;
-                a8 = q8;
-                a8s = s8;
-                a8_sst = w.sst;
-            }
+            if (!a8) return fail(DF_E_UNSUPPORTED, "dnn step: FP8 needs a first layer with 32 or 64 padded inputs");
             st = launch_gemm_fp8(a8, in_ld, a8s, a8_sst, blob + bl.w8[l], L.k_pad,
                                  reinterpret_cast<const int32_t *>(blob + bl.e8[l]), L.b, out, out_ld,
                                  q_next ? o8s : nullptr, o8_sst, w.n_pad, L.n_pad, L.k_pad, s);
             wrote8 = q_next;
-        } else if (q_next && (L.k_pad == 32 || L.k_pad == 64)) {
+        } else if (q_next) {
             st = launch_gemm_bf16_fp8out(in, in_ld, L.W, L.k_pad, L.b, o8, out_ld, o8s, o8_sst, w.n_pad, L.n_pad,
                                          L.k_pad, s);
             wrote8 = true;

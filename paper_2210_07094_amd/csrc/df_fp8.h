@@ -6,8 +6,9 @@
 // Scales are powers of two, so that applying and removing them is exact:
 //  * activations: each row of a layer's input in blocks of 32 consecutive values, block q of row
 //    i with the scale 2^e, e the smallest integer with max |block| <= 448 * 2^e (0 for a block of
-//    zeros or one holding a non-finite value's maximum, at least -127); the bf16 activations are
-//    quantised once per layer into E4M3FN bytes [M][ld] and E8M0 scale bytes (127 + e) [M][sst];
+//    zeros or one holding a non-finite value's maximum, at least -127), applied by the layer that
+//    produces the activations to their bf16 values, which it writes as E4M3FN bytes [M][ld] and
+//    E8M0 scale bytes (127 + e) [M][sst];
 //  * weights: one scale per output row, by the same rule over the row, quantised once at load.
 // The matrix cores take both scales with each 128-deep product and sum in fp32; the epilogue
 // adds the bias, applies GELU and rounds to bf16.
@@ -34,14 +35,9 @@ __host__ __device__ inline int fp8_scale_exp(float amax) {
 // bytes per row of the scale array of an FP8 activation buffer of width ld (16-byte rows)
 inline int fp8_scale_stride(int ld) { return (ld / kFp8Block + 15) / 16 * 16; }
 
-// Q[M][ld] E4M3FN bytes and S[M][sst] E8M0 bytes (127 + e, blocks 0 .. ld/32 - 1 of each row;
-// bytes from ld/32 on are not written) from the bf16 activations A[M][ld] (ld % 32 == 0), by the
-// block rule above.
-df_status launch_quant_fp8(const bf16_t *A, int ld, int64_t M, uint8_t *Q, uint8_t *S, int sst, hipStream_t stream);
-
 // C[M][N] = GELU(sum_q 2^(e_a[m][q] + wexp[n]) (Q_a . W8^T over block q)[m][n] + bias[n]) in bf16,
 // over the K (% 32 == 0) inputs in 128-deep steps (inputs from K to the next multiple of 128 read
-// as zeros).  Q_a: [M][lda] E4M3FN bytes, S_a: [M][sst] E8M0 block scales (as launch_quant_fp8);
+// as zeros).  Q_a: [M][lda] E4M3FN bytes, S_a: [M][sst] E8M0 block scales of blocks 0 .. K/32 - 1;
 // W8: [N][ldb] E4M3FN bytes, wexp: [N] row exponents (-127 .. 127).  M % 128 == 0, N % 160 == 0,
 // lda, ldb multiples of 16, sst of 16.  With SC != nullptr the output is instead the FP8 copy the
 // next FP8 layer reads: C holds E4M3FN bytes (row stride ldc bytes) and SC the block scales (row

@@ -338,47 +338,6 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_shallow_kernel(const bf16_t 
     }
 }
 
-// one thread per block of 32 activations of a row: the block's largest magnitude (NaN ignored),
-// its scale exponent, the 32 E4M3FN bytes and the E8M0 scale byte
-constexpr int kQuantThreads = 256;
-__global__ __launch_bounds__(kQuantThreads) void quant_fp8_kernel(const bf16_t *__restrict__ A, int ld, int64_t n_blk,
-                                                                  uint8_t *__restrict__ Q, uint8_t *__restrict__ S,
-                                                                  int sst) {
-    const int64_t id = int64_t(blockIdx.x) * kQuantThreads + threadIdx.x;
-    if (id >= n_blk) return;
-    const int nb = ld / kFp8Block;
-    const int64_t row = id / nb;
-    const int q = int(id % nb);
-    const u32x4 *src = reinterpret_cast<const u32x4 *>(A + row * ld + q * kFp8Block);
-    float v[kFp8Block];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        const u32x4 x = src[c];
-#pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            v[8 * c + 2 * w] = __uint_as_float(x[w] << 16);
-            v[8 * c + 2 * w + 1] = __uint_as_float(x[w] & 0xffff0000u);
-        }
-    }
-    float amax = 0.0f;
-#pragma unroll
-    for (int c = 0; c < kFp8Block; ++c) amax = fmaxf(amax, fabsf(v[c]));
-    const int e = fp8_scale_exp(amax);
-    const float sc = ldexpf(1.0f, -e);
-    u32x4 o[2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-        for (int w = 0; w < 4; ++w) {
-            const float *f = v + 16 * h + 4 * w;
-            o[h][w] = to_fp8x4(f[0] * sc, f[1] * sc, f[2] * sc, f[3] * sc);
-        }
-    u32x4 *dst = reinterpret_cast<u32x4 *>(Q + row * ld + q * kFp8Block);
-    dst[0] = o[0];
-    dst[1] = o[1];
-    S[row * sst + q] = uint8_t(127 + e);
-}
-
 // FP8 layer on the block-scaled matrix cores: the tiling of gemm_kernel (128 x 160 block tile,
 // 2 x 2 waves of 64 x 80) with 128-deep stages of E4M3FN bytes.  In a 16x16x128 product with
 // 8-bit operands, lane l supplies row l % 16 of its operand at the stage's inputs 16 g .. 16 g + 15
@@ -598,19 +557,6 @@ df_status launch_gemm_bf16_epi(const bf16_t *A, int lda, const bf16_t *B, int ld
 #undef DF_GEMM
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(DF_E_HIP, std::string("gemm launch: ") + hipGetErrorString(e));
-    return DF_OK;
-}
-
-df_status launch_quant_fp8(const bf16_t *A, int ld, int64_t M, uint8_t *Q, uint8_t *S, int sst, hipStream_t stream) {
-    if (ld % kFp8Block || sst % 16 || sst < ld / kFp8Block || M < 0)
-        return fail(DF_E_INVALID, "fp8 quantisation: width must be a multiple of 32 and the scale rows hold its blocks");
-    const int64_t n_blk = M * (ld / kFp8Block);
-    if (n_blk == 0) return DF_OK;
-    if ((n_blk + kQuantThreads - 1) / kQuantThreads > 0x7fffffff) return fail(DF_E_UNSUPPORTED, "fp8 quantisation: too many blocks");
-    hipLaunchKernelGGL(quant_fp8_kernel, dim3(unsigned((n_blk + kQuantThreads - 1) / kQuantThreads)),
-                       dim3(kQuantThreads), 0, stream, A, ld, n_blk, Q, S, sst);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return fail(DF_E_HIP, std::string("fp8 quantisation launch: ") + hipGetErrorString(e));
     return DF_OK;
 }
 
