@@ -389,6 +389,20 @@ extern "C" df_status df_chem_autotune(const df_mech *mech, int64_t n_cells, int6
     std::vector<Cand> cands = {{1, 0, opts->mapping}};
     if (chem_coop_supported(mech->dev) && mech->dev.RPL % 2 == 0 && (opts->mapping == 0 || opts->mapping == 2))
         cands.push_back({1, 0, 4});
+    // one cell per lane: 64 cells per wave, for fields where the total work, not one cell's chain
+    // of sub-steps, sets the time
+    bool lane_kernel = false;
+    switch (K) {
+#define DF_CASE(k)         \
+    case k:                \
+        lane_kernel = true; \
+        break;
+        DF_CHEM_SPECIES_LIST(DF_CASE)
+#undef DF_CASE
+        default:
+            break;
+    }
+    if (lane_kernel && (opts->mapping == 0 || opts->mapping == 2)) cands.push_back({1, 0, 1});
     if (cap > 0) {
         cands.push_back({2, 0, opts->mapping});
         cands.push_back({2, cap / 2, opts->mapping});
