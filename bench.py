@@ -175,8 +175,10 @@ def batching_study(gm, mech_h, dev):
 
 
 def adjoint_lane_ops(mech, ops):
-    """Algorithmic FP64 lane-ops of the reverse sweep per accepted sub-step: six products with
-    W^-T (N^2 each), five first-order vector-Jacobian products of f at the stage states, six
+    """Algorithmic FP64 lane-ops of the reverse sweep per accepted sub-step: the five stage
+    states and the analytic Jacobian at each, six products with W^-T and five with J^T (N^2
+    each), the first-order ln A terms of five stages (per species the production-rate weight,
+    per reaction the seed through the stoichiometry and the factor of d q / d ln A), six
     second-order products in dual-number arithmetic, and the stage-adjoint updates.  A
     vector-Jacobian product is the right-hand side plus its reverse accumulation (per
     reaction: the seed through the stoichiometry, the temperature and slot derivatives, the
@@ -190,7 +192,8 @@ def adjoint_lane_ops(mech, ops):
     n_troe = int(np.count_nonzero(mech.reaction_type == 2))
     reverse = int(np.sum(nnz + 25)) + n_tb * K + n_troe * (30 + 4 * DIVISION_OPS) + 20 * K
     vjp = ops["rhs"] + reverse
-    per_substep = 6 * N * N + 5 * vjp + 6 * 3 * vjp + 30 * N
+    lna = 3 * K + int(np.sum(nnz + 1))
+    per_substep = 5 * (5 * N + ops["jacobian"] + lna) + 11 * N * N + 6 * 3 * vjp + 30 * N
     return {"per_substep": int(per_substep), "vjp": int(vjp)}
 
 

@@ -21,6 +21,7 @@
 // dual-number arithmetic at y + eps u_i, whose eps part is the directional derivative
 // (a Hessian-vector product of <rbar, f>).  ln A is the natural log of the pre-exponential
 // factor of each reaction, k_inf's for falloff rows.
+#include <algorithm>
 #include <cmath>
 
 #include "df_internal.h"
@@ -82,15 +83,15 @@ template <class S>
 __device__ __forceinline__ S &slot(S *base, int k) {
     return base[k * kWave * int(sizeof(Dual) / sizeof(S))];
 }
-// Per-species arrays of the products: plain numbers stay in registers (compile-time indices
-// only); duals, whose registers the second-order products cannot spare, live in the lane's LDS
-// rows (see rget()).
+// Per-species arrays of the products (the adjoint weights and the production rates) live in the
+// lane's LDS rows (see rget()), plain numbers and duals alike: the registers go to the reaction
+// loop's temporaries (in registers, both arrays spilled to scratch memory in the chain).
 template <int K, class S>
 struct SpArr {
-    double v[K];
-    __device__ SpArr(double *) {}
-    __device__ double get(int k) const { return v[k]; }
-    __device__ void put(int k, double x) { v[k] = x; }
+    double *b;
+    __device__ SpArr(double *base) : b(base) {}
+    __device__ double get(int k) const { return b[k * kWave]; }
+    __device__ void put(int k, double x) { b[k * kWave] = x; }
 };
 template <int K>
 struct SpArr<K, Dual> {
@@ -170,6 +171,9 @@ __device__ void vjp(const MechDev &m, double p, const S (&y)[K + 1], const doubl
 #pragma unroll
     for (int k = 0; k < K; ++k) cbd[k] = mk<S>(0.0);
     S Tb = mk<S>(0.0);
+    // the species table entries read above are read again after the reaction loop rather than
+    // kept live across it (compiler barrier)
+    __asm__ volatile("" ::: "memory");
     for (int j = 0; j < m.M; ++j) {
         const int *ri = m.rx + j * kRxInt;
         const double *rd = m.rk + j * kRxDbl;
@@ -252,6 +256,7 @@ __device__ void vjp(const MechDev &m, double p, const S (&y)[K + 1], const doubl
         }
         at(th, j) += part(Qb * q * rA, with_value);
     }
+    __asm__ volatile("" ::: "memory");
     // mixture: f_k, f_T and the adjoints of fy, hm_k, cp, rho
     S fyb = mk<S>(0.0), H = mk<S>(0.0);
 #pragma unroll
@@ -323,33 +328,48 @@ struct AdjArgs {
 constexpr int kAdjLanes = 8;                  // lanes per cell
 constexpr int kAdjCells = kWave / kAdjLanes;  // cells per block (one wave)
 
-// Per-block LDS of the sweep, in doubles: per lane the dual concentrations and their adjoints
-// (2 x N duals), the production-rate weights and rates (2 x 2K rows) and the ln A adjoints
-// (M); per cell the stage adjoints ubar (6N), the products' seeds rbar (6N), the chain's
-// state adjoint (N) and the second-order parts of the six stages (6N).
+// Per-block LDS of the sweep, in doubles.  Per lane, rows of one double per lane (element k at
+// base[k * kWave]): a work area of P = max(4N + 4K, 5N + M) rows, then the ln A adjoints (M).
+// The work area holds, at different times of a sub-step, the analytic Jacobian's thermo and
+// scatter rows (5N) with the per-reaction ln A factors after them (M), and the products' dual
+// concentrations and their adjoints (4N) with the production-rate weights and rates (4K).  Per
+// cell: the stage adjoints ubar (6N), the transposed products' results rbar (6N), the state
+// adjoint (N), the second-order parts of the six stages (6N), the product J^T rbar (N) and the
+// sub-step's tape record (N^2 + 7N).
 template <int K>
 struct AdjLds {
     static constexpr int N = K + 1;
-    static constexpr int kCell = 19 * N;
-    static size_t bytes(int M) { return size_t(8) * (size_t(kWave) * (8 * N + M) + size_t(kAdjCells) * kCell); }
+    static constexpr int kTapeRec = N * N + 7 * N;  // a sub-step's W^-1, y and six stage vectors
+    static constexpr int kCell = 20 * N + kTapeRec;
+    __host__ __device__ static int work_rows(int M) { return 4 * N + 4 * K > 5 * N + M ? 4 * N + 4 * K : 5 * N + M; }
 };
 
-// One cell per group of 8 lanes.  Per sub-step, last to first: lane 0 runs the chain of
-// transposed solves (products with W^-T from the tape's inverse) and first-order products
-// through the stages; then lanes 0..5 each take one stage's second-order term (the dual
-// product at y + eps u_i), and lane 0 adds them up.
+// One cell per group of 8 lanes.  Per sub-step, last to first:
+//  1. the lanes stage the sub-step's tape record in LDS;
+//  2. lanes 0..4 form J(Y_i) of stages i = 1..5 with the analytic Jacobian (lane i - 1 keeps its
+//     stage's Jacobian in registers), with the factors of df/dlnA;
+//  3. the chain, stage 5 to 0: rbar_i = W^-T ubar_i with the eight lanes taking the columns,
+//     v = J(Y_i)^T rbar_i on the lane that holds J(Y_i), and the ubar and ybar updates with the
+//     lanes taking the species;
+//  4. lanes 0..4 add (df/dlnA)(Y_i)^T rbar_i to the ln A adjoints;
+//  5. lanes 0..5 each take one stage's second-order term (the dual product at y + eps u_i);
+//     every lane adds them up into the new lam.
 template <int K>
 __global__ __launch_bounds__(kWave) void adjoint_kernel(MechDev m, AdjArgs a) {
     constexpr int N = K + 1;
     extern __shared__ double lds[];
     const int lane = threadIdx.x, r = lane % kAdjLanes, g = lane / kAdjLanes;
+    const int P = AdjLds<K>::work_rows(m.M);
     Dual *cs = reinterpret_cast<Dual *>(lds) + lane;
     Dual *cb = cs + N * kWave;
     double *omr = lds + 4 * N * kWave + lane, *wdr = omr + 2 * K * kWave;
-    double *th = lds + (4 * N + 4 * K) * kWave + lane;
+    double *shr = lds + lane;                 // the Jacobian's rows
+    double *lnar = lds + 5 * N * kWave + lane;  // its ln A factors
+    double *th = lds + P * kWave + lane;
     double *csd = reinterpret_cast<double *>(cs), *cbd = reinterpret_cast<double *>(cb);
-    double *cell = lds + (4 * N + 4 * K + m.M) * kWave + g * AdjLds<K>::kCell;
-    double *ub = cell, *rbs = cell + 6 * N, *ybase = cell + 12 * N, *ybp = cell + 13 * N;
+    double *cell = lds + (P + m.M) * kWave + g * AdjLds<K>::kCell;
+    double *ub = cell, *rbs = cell + 6 * N, *yba = cell + 12 * N, *ybp = cell + 13 * N, *vt = cell + 19 * N;
+    double *tw = cell + 20 * N, *ty = tw + N * N, *tu = ty + N;  // the sub-step's tape record
     const int64_t i = int64_t(blockIdx.x) * kAdjCells + g;
     if (i >= a.n) return;  // the lanes of a cell leave together
     const int64_t ld = a.ld;
@@ -367,62 +387,130 @@ __global__ __launch_bounds__(kWave) void adjoint_kernel(MechDev m, AdjArgs a) {
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     };
+    // the species (or columns) of the lane in the spread phases: r and r + 8
+    constexpr int kSpread = (N + kAdjLanes - 1) / kAdjLanes;
+    constexpr int kRec = AdjLds<K>::kTapeRec, kPer = (kRec + kAdjLanes - 1) / kAdjLanes;
     for (int64_t s = int64_t(cnt > 0 ? cnt : 0) - 1; s >= 0; --s) {
+        // 1. the cell's 8 lanes stage the sub-step's tape record with all loads in flight together
+        {
+            double v[kPer];
+#pragma unroll
+            for (int t = 0; t < kPer; ++t) {
+                const int e = r + kAdjLanes * t;
+                v[t] = (e < N * N) ? T[tp.w(s, e)] : (e < N * N + N) ? T[tp.y(s, e - N * N)]
+                                                   : (e < kRec) ? T[tp.u(s, e - N * N - N)] : 0.0;
+            }
+#pragma unroll
+            for (int t = 0; t < kPer; ++t) {
+                const int e = r + kAdjLanes * t;
+                if (e < kRec) tw[e] = v[t];
+            }
+        }
+        const double ih = 1.0 / T[tp.h(s)];
+        wave_sync();
         double y[N];
 #pragma unroll
-        for (int k = 0; k < N; ++k) y[k] = T[tp.y(s, k)];
-        if (r == 0) {
-            const double ih = 1.0 / T[tp.h(s)];
-            double yb[N];
+        for (int k = 0; k < N; ++k) y[k] = ty[k];
+        // 2. lane r < 5: J at the state of stage r + 1, Y = y + sum_{j < r+1} a_{r+1,j} u_j
+        double J[N][N], wf[K], wh[K];
+        if (r < 5) {
+            const int si = r + 1;
+            double ys[N], f[N];
 #pragma unroll
             for (int k = 0; k < N; ++k) {
-                yb[k] = lam[k];
+                double w = y[k];
 #pragma unroll
-                for (int si = 0; si < 6; ++si) ub[si * N + k] = (si < 5 ? Rodas4::a[5][si] : 1.0) * lam[k];
+                for (int jj = 0; jj < 5; ++jj) w = fma(Rodas4::a[si][jj], tu[jj * N + k], w);  // a_ij = 0 for j >= i
+                ys[k] = w;
             }
-#pragma unroll 1
-            for (int si = 5; si >= 0; --si) {
-                // rbar = W^-T ubar_i, streaming the rows of W^-1
-                double rb[N];
+            Cell<K>::init_lds(shr);
+            Cell<K>::template jacobian<true>(m, p, ys, shr, J, f, lnar, wf, wh);
+        }
+        // ubar_i = b_i lam, ybar = lam (the lanes take species r, r + 8)
 #pragma unroll
-                for (int c = 0; c < N; ++c) rb[c] = 0.0;
+        for (int t = 0; t < kSpread; ++t) {
+            const int k = r + kAdjLanes * t;
+            if (k < N) {
+                double lk = lam[0];
 #pragma unroll
-                for (int q = 0; q < N; ++q) {
-                    const double uq = ub[si * N + q];
+                for (int kk = 1; kk < N; ++kk) lk = (k == kk) ? lam[kk] : lk;
+                yba[k] = lk;
 #pragma unroll
-                    for (int c = 0; c < N; ++c) rb[c] = fma(T[tp.w(s, q * N + c)], uq, rb[c]);
-                }
-#pragma unroll
-                for (int c = 0; c < N; ++c) rbs[si * N + c] = rb[c];
-                if (si > 0) {
-                    double ys[N], v[N];
-#pragma unroll
-                    for (int k = 0; k < N; ++k) {
-                        double w = y[k];
-                        for (int jj = 0; jj < si; ++jj) w = fma(Rodas4::a[si][jj], T[tp.u(s, jj * N + k)], w);
-                        ys[k] = w;
-                    }
-                    vjp<K, double>(m, p, ys, rb, csd, cbd, omr, wdr, th, true, v);
-#pragma unroll
-                    for (int k = 0; k < N; ++k) {
-                        yb[k] += v[k];
-                        for (int jj = 0; jj < si; ++jj)
-                            ub[jj * N + k] += Rodas4::a[si][jj] * v[k] + Rodas4::c[si][jj] * ih * rb[k];
-                    }
-                }
+                for (int si = 0; si < 6; ++si) ub[si * N + k] = (si < 5 ? Rodas4::a[5][si] : 1.0) * lk;
             }
-#pragma unroll
-            for (int k = 0; k < N; ++k) ybase[k] = yb[k];
         }
         wave_sync();
-        // derivative of W through J(y): the dual product at y + eps u_i with seed rbar_i (stage 0
-        // also takes the first-order term J(y)^T rbar_0, the value part)
+        // 3. the chain
+#pragma unroll 1
+        for (int si = 5; si >= 0; --si) {
+            // rbar = W^-T ubar_i: lane r takes columns r, r + 8
+#pragma unroll
+            for (int t = 0; t < kSpread; ++t) {
+                const int c = r + kAdjLanes * t;
+                if (c < N) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int q = 0; q < N; ++q) acc = fma(tw[q * N + c], ub[si * N + q], acc);
+                    rbs[si * N + c] = acc;
+                }
+            }
+            wave_sync();
+            if (si > 0) {
+                // v = J(Y_i)^T rbar on lane i - 1
+                if (r == si - 1) {
+                    double rb[N];
+#pragma unroll
+                    for (int k = 0; k < N; ++k) rb[k] = rbs[si * N + k];
+#pragma unroll
+                    for (int l = 0; l < N; ++l) {
+                        double acc = 0.0;
+#pragma unroll
+                        for (int k = 0; k < N; ++k) acc = fma(J[k][l], rb[k], acc);
+                        vt[l] = acc;
+                    }
+                }
+                wave_sync();
+                // ybar += v;  ubar_j += a_ij v + (c_ij / h) rbar  (j < i)
+#pragma unroll
+                for (int t = 0; t < kSpread; ++t) {
+                    const int k = r + kAdjLanes * t;
+                    if (k < N) {
+                        const double vk = vt[k], rk = rbs[si * N + k];
+                        yba[k] += vk;
+                        for (int jj = 0; jj < si; ++jj)
+                            ub[jj * N + k] += Rodas4::a[si][jj] * vk + Rodas4::c[si][jj] * ih * rk;
+                    }
+                }
+                wave_sync();
+            }
+        }
+        // 4. lane r < 5: the first-order ln A terms of stage r + 1, lnA_bar_j += Qb_j q_j dlnkf_j/dlnA_j
+        //    with Qb_j = sum_k nu_kj (fy W_k (rbar_k - rbar_T h_k / cp))
+        if (r < 5) {
+            const int si = r + 1;
+            double om[K];
+            const double rT = rbs[si * N];
+#pragma unroll
+            for (int k = 0; k < K; ++k) om[k] = wf[k] * rbs[si * N + 1 + k] - wh[k] * rT;
+            for (int j = 0; j < m.M; ++j) {
+                const int *nuj = m.nu + j * K;
+                double Qb = 0.0;
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const int nk = nuj[k];
+                    if (nk != 0) Qb = fma(double(nk), om[k], Qb);  // wave-uniform branch
+                }
+                at(th, j) = fma(Qb, at(lnar, j), at(th, j));
+            }
+        }
+        // 5. derivative of W through J(y): the dual product at y + eps u_i with seed rbar_i (stage 0
+        //    also takes the first-order term J(y)^T rbar_0, the value part)
         if (r < 6) {
             Dual yd[N], vd[N];
             double rb[N];
 #pragma unroll
             for (int k = 0; k < N; ++k) {
-                yd[k] = Dual{y[k], T[tp.u(s, r * N + k)]};
+                yd[k] = Dual{y[k], tu[r * N + k]};
                 rb[k] = rbs[r * N + k];
             }
             vjp<K, Dual>(m, p, yd, rb, cs, cb, omr, wdr, th, r == 0, vd);
@@ -430,14 +518,12 @@ __global__ __launch_bounds__(kWave) void adjoint_kernel(MechDev m, AdjArgs a) {
             for (int k = 0; k < N; ++k) ybp[r * N + k] = (r == 0) ? vd[k].v + vd[k].d : vd[k].d;
         }
         wave_sync();
-        if (r == 0) {
 #pragma unroll
-            for (int k = 0; k < N; ++k) {
-                double v = ybase[k];
+        for (int k = 0; k < N; ++k) {
+            double v = yba[k];
 #pragma unroll
-                for (int q = 0; q < 6; ++q) v += ybp[q * N + k];
-                lam[k] = v;
-            }
+            for (int q = 0; q < 6; ++q) v += ybp[q * N + k];
+            lam[k] = v;
         }
         wave_sync();
     }
@@ -450,7 +536,7 @@ __global__ __launch_bounds__(kWave) void adjoint_kernel(MechDev m, AdjArgs a) {
     // ln A adjoints: the six lanes' partial sums; lane r takes reactions r, r + 8, ...
     for (int j = r; j < m.M; j += kAdjLanes) {
         double v = 0.0;
-        for (int q = 0; q < 6; ++q) v += lds[(4 * N + 4 * K + j) * kWave + g * kAdjLanes + q];
+        for (int q = 0; q < 6; ++q) v += lds[(P + j) * kWave + g * kAdjLanes + q];
         v = ok ? v : 0.0;
         a.wth[int64_t(j) * a.n + i] = v;
         if (a.thc) a.thc[int64_t(m.src[j]) * ld + i] = v;
@@ -478,15 +564,22 @@ size_t adj_ws_bytes(int, int M, int64_t n) { return size_t(8) * size_t(M) * size
 
 size_t adj_lds_bytes(int K, int M) {
     const size_t N = size_t(K + 1);
-    return size_t(8) * (size_t(kWave) * (8 * N + size_t(M)) + size_t(kAdjCells) * 19 * N);
+    const size_t P = std::max(4 * N + 4 * size_t(K), 5 * N + size_t(M));
+    return size_t(8) * (size_t(kWave) * (P + size_t(M)) + size_t(kAdjCells) * (27 * N + N * N));
 }
 
-constexpr size_t kAdjLdsMax = 64 * 1024;
+constexpr size_t kAdjLdsMax = 80 * 1024;  // two blocks (waves) per CU
 
 template <int K>
 df_status launch_adjoint_k(const MechDev &m, const AdjArgs &a, hipStream_t s) {
     const int64_t blocks = (a.n + kAdjCells - 1) / kAdjCells;
     const size_t lds = adj_lds_bytes(K, m.M);
+    if (lds > 64 * 1024) {
+        const hipError_t ea = hipFuncSetAttribute(reinterpret_cast<const void *>(adjoint_kernel<K>),
+                                                  hipFuncAttributeMaxDynamicSharedMemorySize, int(lds));
+        if (ea != hipSuccess)
+            return fail(DF_E_HIP, std::string("df_chem_adjoint: LDS size: ") + hipGetErrorString(ea));
+    }
     hipLaunchKernelGGL(adjoint_kernel<K>, dim3(unsigned(blocks)), dim3(kWave), lds, s, m, a);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(DF_E_HIP, std::string("df_chem_adjoint launch: ") + hipGetErrorString(e));

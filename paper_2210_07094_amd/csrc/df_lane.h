@@ -158,8 +158,14 @@ struct Cell {
     // A is accumulated in the species block of J (row/column 1 + k) by rows with
     // compile-time indices and wave-uniform stoichiometric coefficients, so J stays in
     // registers; the T row and column are filled afterwards.
+    // With kLnA (the adjoint's products with df/dlnA) it also writes, per reaction j,
+    // q_j d ln kf_j / d ln A_j to lna[j * kWave] (for a falloff row the part of q_j that goes
+    // through Pr = k0 [M] / k_inf, G_j [M], is taken off), and per species the weights of wd_k in
+    // f_k and f_T: wf[k] = fy W_k, wh[k] = fy W_k h_k / cp.
+    template <bool kLnA = false>
     __device__ __forceinline__ static void jacobian(const MechDev &m, double p, const double (&y)[N], double *sh,
-                                                    double (&J)[N][N], double (&f)[N]) {
+                                                    double (&J)[N][N], double (&f)[N], double *lna = nullptr,
+                                                    double *wf = nullptr, double *wh = nullptr) {
         Mix s;
         double cpR[N], hRT[N];
         state(m, p, y, sh, s, cpR, hRT);
@@ -204,6 +210,7 @@ struct Cell {
                 G = dkfdM * (Pf - Pb * iKc);
                 S += G * Mc;
             }
+            if constexpr (kLnA) lna[j * kWave] = (type == 2) ? q - G * Mc : q;
             // dq/dc: the slot terms (each slot's derivative is the product of the other slots)
             // are scattered into LDS, the dense third-body term is added on the way out;
             // slot 0 collects the empty slots
@@ -259,6 +266,13 @@ struct Cell {
         }
         const double icp = 1.0 / s.cp;
         f[0] = -hf * icp;
+        if constexpr (kLnA) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                wf[k] = fy * m.sp[k * kSpTab];
+                wh[k] = wf[k] * hm[1 + k] * icp;
+            }
+        }
         // temperature row: f_T = -sum_k h_k f_k / cp (u_k and cv at constant volume)
 #pragma unroll
         for (int l = 0; l < N; ++l) {
