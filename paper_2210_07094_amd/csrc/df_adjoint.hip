@@ -1,4 +1,4 @@
-// Discrete adjoint of the detailed-chemistry step on gfx950: one cell per lane, FP64.
+// Discrete adjoint of the detailed-chemistry step on gfx950: eight lanes per cell, FP64.
 //
 // The step y0 = (T0, Y0) -> y(dt) is the sequence of accepted RODAS4 sub-steps of the taped
 // forward integration (df_chem_step_taped), with the step lengths held fixed: the
@@ -6,9 +6,9 @@
 // from y with length h is
 //   W = I/(g h) - J(y),   Y_i = y + sum_{j<i} a_ij u_j,
 //   W u_i = f(Y_i) + (1/h) sum_{j<i} c_ij u_j,   y_new = y + sum_i b_i u_i
-// (b_i = a_5i for i < 5, b_5 = 1: the new state is the stage-6 state plus u_5).  Given the
-// adjoint lam of y_new, the reverse sweep over the sub-steps, last to first, recomputes the
-// stages from the checkpointed start state and sets
+// (b_i = a_5i for i < 5, b_5 = 1: the new state is the stage-6 state plus u_5).  The tape
+// holds, per accepted sub-step, y, h, W^-1 and the six stage vectors u_i.  Given the adjoint
+// lam of y_new, the reverse sweep over the sub-steps, last to first, sets
 //   ubar_i = b_i lam,  ybar = lam;  for i = 5 .. 0:
 //     rbar = W^-T ubar_i
 //     v = J(Y_i)^T rbar:  ybar += v,  ubar_j += a_ij v + (c_ij / h) rbar   (j < i)
@@ -16,11 +16,12 @@
 //     ybar += grad_y <rbar, J(y) u_i>,  thbar += grad_lnA <rbar, J(y) u_i>
 //   lam = ybar
 // The last line is the derivative of the iteration matrix: W depends on y through J.  The
-// products with J^T are vector-Jacobian products of f written out in reverse mode (no
-// Jacobian is formed), and the second-order terms are the same products evaluated in
-// dual-number arithmetic at y + eps u_i, whose eps part is the directional derivative
-// (a Hessian-vector product of <rbar, f>).  ln A is the natural log of the pre-exponential
-// factor of each reaction, k_inf's for falloff rows.
+// first-order products use the analytic Jacobian at the five stage states (formed in parallel,
+// one stage per lane), so the sequential chain is a string of small matrix products.  The
+// second-order terms are a vector-Jacobian product of f written out in reverse mode and
+// evaluated in dual-number arithmetic at y + eps u_i, whose eps part is the directional
+// derivative (a Hessian-vector product of <rbar, f>).  ln A is the natural log of the
+// pre-exponential factor of each reaction, k_inf's for falloff rows.
 #include <algorithm>
 #include <cmath>
 
@@ -30,6 +31,9 @@
 
 namespace df {
 namespace {
+
+// columns of the equilibrium-constant rows the products read (the sweep's LDS copy keeps these)
+constexpr int kAdjCr = 16;
 
 // ---- dual numbers: value v and derivative d along one direction
 struct Dual {
@@ -177,7 +181,7 @@ __device__ void vjp(const MechDev &m, double p, const S (&y)[K + 1], const doubl
     for (int j = 0; j < m.M; ++j) {
         const int *ri = m.rx + j * kRxInt;
         const double *rd = m.rk + j * kRxDbl;
-        const double *cr = m.cr + j * kCrDbl;
+        const double *cr = m.cr + j * kAdjCr;
         const int type = ri[0];
         const int r0 = ri[1], r1 = ri[2], r2 = ri[3], p0 = ri[4], p1 = ri[5], p2 = ri[6], dnu = ri[7];
         const double *ef = m.eff + j * K;
@@ -333,15 +337,22 @@ constexpr int kAdjCells = kWave / kAdjLanes;  // cells per block (one wave)
 // The work area holds, at different times of a sub-step, the analytic Jacobian's thermo and
 // scatter rows (5N) with the per-reaction ln A factors after them (M), and the products' dual
 // concentrations and their adjoints (4N) with the production-rate weights and rates (4K).  Per
-// cell: the stage adjoints ubar (6N), the transposed products' results rbar (6N), the state
-// adjoint (N), the second-order parts of the six stages (6N), the product J^T rbar (N) and the
-// sub-step's tape record (N^2 + 7N).
+// cell: the stage adjoints ubar (6N; after the chain, the second-order parts of the six
+// stages), the transposed products' results rbar (6N), the state adjoint (N), the product
+// J^T rbar (N) and the sub-step's tape record (N^2 + 7N).  Then a copy of the mechanism tables
+// the reaction loops read (species rows, reaction rows, third-body efficiencies, the first
+// kAdjCr columns of the equilibrium rows, stoichiometry): read with wave-uniform addresses,
+// they are broadcast LDS reads instead of memory loads on the loops' dependency chains.
 template <int K>
 struct AdjLds {
     static constexpr int N = K + 1;
     static constexpr int kTapeRec = N * N + 7 * N;  // a sub-step's W^-1, y and six stage vectors
-    static constexpr int kCell = 20 * N + kTapeRec;
+    static constexpr int kCell = 14 * N + kTapeRec;
     __host__ __device__ static int work_rows(int M) { return 4 * N + 4 * K > 5 * N + M ? 4 * N + 4 * K : 5 * N + M; }
+    // doubles of the per-lane rows and the cell regions, then of the mechanism copy
+    __host__ __device__ static int front(int M) { return kWave * (work_rows(M) + M) + kAdjCells * kCell; }
+    __host__ __device__ static int mech_dbl(int M) { return K * kSpTab + M * (kRxDbl + K + kAdjCr); }
+    __host__ __device__ static int mech_int(int M) { return M * (kRxInt + K); }
 };
 
 // One cell per group of 8 lanes.  Per sub-step, last to first:
@@ -368,8 +379,31 @@ __global__ __launch_bounds__(kWave) void adjoint_kernel(MechDev m, AdjArgs a) {
     double *th = lds + P * kWave + lane;
     double *csd = reinterpret_cast<double *>(cs), *cbd = reinterpret_cast<double *>(cb);
     double *cell = lds + (P + m.M) * kWave + g * AdjLds<K>::kCell;
-    double *ub = cell, *rbs = cell + 6 * N, *yba = cell + 12 * N, *ybp = cell + 13 * N, *vt = cell + 19 * N;
-    double *tw = cell + 20 * N, *ty = tw + N * N, *tu = ty + N;  // the sub-step's tape record
+    double *ub = cell, *rbs = cell + 6 * N, *yba = cell + 12 * N, *vt = cell + 13 * N;
+    double *ybp = ub;  // the stage adjoints are dead once the chain is done
+    double *tw = cell + 14 * N, *ty = tw + N * N, *tu = ty + N;  // the sub-step's tape record
+    // the mechanism copy: doubles (species, reaction rows, efficiencies, equilibrium rows), then ints
+    MechDev ml = m;
+    {
+        double *md = lds + AdjLds<K>::front(m.M);
+        double *lsp = md, *lrk = lsp + K * kSpTab, *leff = lrk + m.M * kRxDbl, *lcr = leff + m.M * K;
+        int *lrx = reinterpret_cast<int *>(lcr + m.M * kAdjCr), *lnu = lrx + m.M * kRxInt;
+        for (int e = lane; e < K * kSpTab; e += kWave) lsp[e] = m.sp[e];
+        for (int e = lane; e < m.M * kRxDbl; e += kWave) lrk[e] = m.rk[e];
+        for (int e = lane; e < m.M * K; e += kWave) leff[e] = m.eff[e];
+        for (int e = lane; e < m.M * kAdjCr; e += kWave) lcr[e] = m.cr[(e / kAdjCr) * kCrDbl + e % kAdjCr];
+        for (int e = lane; e < m.M * kRxInt; e += kWave) lrx[e] = m.rx[e];
+        for (int e = lane; e < m.M * K; e += kWave) lnu[e] = m.nu[e];
+        ml.sp = lsp;
+        ml.rk = lrk;
+        ml.eff = leff;
+        ml.cr = lcr;
+        ml.rx = lrx;
+        ml.nu = lnu;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
     const int64_t i = int64_t(blockIdx.x) * kAdjCells + g;
     if (i >= a.n) return;  // the lanes of a cell leave together
     const int64_t ld = a.ld;
@@ -424,7 +458,7 @@ __global__ __launch_bounds__(kWave) void adjoint_kernel(MechDev m, AdjArgs a) {
                 ys[k] = w;
             }
             Cell<K>::init_lds(shr);
-            Cell<K>::template jacobian<true>(m, p, ys, shr, J, f, lnar, wf, wh);
+            Cell<K>::template jacobian<true>(ml, p, ys, shr, J, f, lnar, wf, wh);
         }
         // ubar_i = b_i lam, ybar = lam (the lanes take species r, r + 8)
 #pragma unroll
@@ -493,7 +527,7 @@ __global__ __launch_bounds__(kWave) void adjoint_kernel(MechDev m, AdjArgs a) {
 #pragma unroll
             for (int k = 0; k < K; ++k) om[k] = wf[k] * rbs[si * N + 1 + k] - wh[k] * rT;
             for (int j = 0; j < m.M; ++j) {
-                const int *nuj = m.nu + j * K;
+                const int *nuj = ml.nu + j * K;
                 double Qb = 0.0;
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
@@ -513,7 +547,7 @@ __global__ __launch_bounds__(kWave) void adjoint_kernel(MechDev m, AdjArgs a) {
                 yd[k] = Dual{y[k], tu[r * N + k]};
                 rb[k] = rbs[r * N + k];
             }
-            vjp<K, Dual>(m, p, yd, rb, cs, cb, omr, wdr, th, r == 0, vd);
+            vjp<K, Dual>(ml, p, yd, rb, cs, cb, omr, wdr, th, r == 0, vd);
 #pragma unroll
             for (int k = 0; k < N; ++k) ybp[r * N + k] = (r == 0) ? vd[k].v + vd[k].d : vd[k].d;
         }
@@ -563,9 +597,11 @@ __global__ __launch_bounds__(256) void sum_cells_kernel(const double *__restrict
 size_t adj_ws_bytes(int, int M, int64_t n) { return size_t(8) * size_t(M) * size_t(n); }
 
 size_t adj_lds_bytes(int K, int M) {
-    const size_t N = size_t(K + 1);
-    const size_t P = std::max(4 * N + 4 * size_t(K), 5 * N + size_t(M));
-    return size_t(8) * (size_t(kWave) * (P + size_t(M)) + size_t(kAdjCells) * (27 * N + N * N));
+    const size_t N = size_t(K + 1), Ms = size_t(M), Ks = size_t(K);
+    const size_t P = std::max(4 * N + 4 * Ks, 5 * N + Ms);
+    const size_t front = size_t(kWave) * (P + Ms) + size_t(kAdjCells) * (21 * N + N * N);
+    const size_t mech_dbl = Ks * kSpTab + Ms * (kRxDbl + Ks + kAdjCr), mech_int = Ms * (kRxInt + Ks);
+    return size_t(8) * (front + mech_dbl) + size_t(4) * mech_int;
 }
 
 constexpr size_t kAdjLdsMax = 80 * 1024;  // two blocks (waves) per CU
