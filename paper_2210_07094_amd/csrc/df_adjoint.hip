@@ -442,25 +442,8 @@ __global__ __launch_bounds__(kWave) void adjoint_kernel(MechDev m, AdjArgs a) {
         }
         const double ih = 1.0 / T[tp.h(s)];
         wave_sync();
-        double y[N];
-#pragma unroll
-        for (int k = 0; k < N; ++k) y[k] = ty[k];
-        // 2. lane r < 5: J at the state of stage r + 1, Y = y + sum_{j < r+1} a_{r+1,j} u_j
-        double J[N][N], wf[K], wh[K];
-        if (r < 5) {
-            const int si = r + 1;
-            double ys[N], f[N];
-#pragma unroll
-            for (int k = 0; k < N; ++k) {
-                double w = y[k];
-#pragma unroll
-                for (int jj = 0; jj < 5; ++jj) w = fma(Rodas4::a[si][jj], tu[jj * N + k], w);  // a_ij = 0 for j >= i
-                ys[k] = w;
-            }
-            Cell<K>::init_lds(shr);
-            Cell<K>::template jacobian<true>(ml, p, ys, shr, J, f, lnar, wf, wh);
-        }
-        // ubar_i = b_i lam, ybar = lam (the lanes take species r, r + 8)
+        // ubar_i = b_i lam, ybar = lam (the lanes take species r, r + 8); lam is dead from here
+        // until the sub-step's end, while the stage Jacobians take the registers
 #pragma unroll
         for (int t = 0; t < kSpread; ++t) {
             const int k = r + kAdjLanes * t;
@@ -472,6 +455,22 @@ __global__ __launch_bounds__(kWave) void adjoint_kernel(MechDev m, AdjArgs a) {
 #pragma unroll
                 for (int si = 0; si < 6; ++si) ub[si * N + k] = (si < 5 ? Rodas4::a[5][si] : 1.0) * lk;
             }
+        }
+        // 2. lane r < 5: J at the state of stage r + 1, Y = y + sum_{j < r+1} a_{r+1,j} u_j (y and
+        //    the u_j read from the staged record)
+        double J[N][N], mix[2];
+        if (r < 5) {
+            const int si = r + 1;
+            double ys[N], f[N];
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                double w = ty[k];
+#pragma unroll
+                for (int jj = 0; jj < 5; ++jj) w = fma(Rodas4::a[si][jj], tu[jj * N + k], w);  // a_ij = 0 for j >= i
+                ys[k] = w;
+            }
+            Cell<K>::init_lds(shr);
+            Cell<K>::template jacobian<true>(ml, p, ys, shr, J, f, lnar, mix);
         }
         wave_sync();
         // 3. the chain
@@ -519,13 +518,15 @@ __global__ __launch_bounds__(kWave) void adjoint_kernel(MechDev m, AdjArgs a) {
             }
         }
         // 4. lane r < 5: the first-order ln A terms of stage r + 1, lnA_bar_j += Qb_j q_j dlnkf_j/dlnA_j
-        //    with Qb_j = sum_k nu_kj (fy W_k (rbar_k - rbar_T h_k / cp))
+        //    with Qb_j = sum_k nu_kj om_k, om_k = fy W_k rbar_k - (fy R T / cp) (H_k/RT) rbar_T (the
+        //    H/RT rows of the stage state are still in the lane's Jacobian rows)
         if (r < 5) {
             const int si = r + 1;
             double om[K];
-            const double rT = rbs[si * N];
+            const double rT = rbs[si * N] * mix[1];
 #pragma unroll
-            for (int k = 0; k < K; ++k) om[k] = wf[k] * rbs[si * N + 1 + k] - wh[k] * rT;
+            for (int k = 0; k < K; ++k)
+                om[k] = mix[0] * ml.sp[k * kSpTab] * rbs[si * N + 1 + k] - rT * at(shr, Cell<K>::kH + 1 + k);
             for (int j = 0; j < m.M; ++j) {
                 const int *nuj = ml.nu + j * K;
                 double Qb = 0.0;
@@ -544,7 +545,7 @@ __global__ __launch_bounds__(kWave) void adjoint_kernel(MechDev m, AdjArgs a) {
             double rb[N];
 #pragma unroll
             for (int k = 0; k < N; ++k) {
-                yd[k] = Dual{y[k], tu[r * N + k]};
+                yd[k] = Dual{ty[k], tu[r * N + k]};
                 rb[k] = rbs[r * N + k];
             }
             vjp<K, Dual>(ml, p, yd, rb, cs, cb, omr, wdr, th, r == 0, vd);

@@ -160,12 +160,13 @@ struct Cell {
     // registers; the T row and column are filled afterwards.
     // With kLnA (the adjoint's products with df/dlnA) it also writes, per reaction j,
     // q_j d ln kf_j / d ln A_j to lna[j * kWave] (for a falloff row the part of q_j that goes
-    // through Pr = k0 [M] / k_inf, G_j [M], is taken off), and per species the weights of wd_k in
-    // f_k and f_T: wf[k] = fy W_k, wh[k] = fy W_k h_k / cp.
+    // through Pr = k0 [M] / k_inf, G_j [M], is taken off), and the two mixture factors of the
+    // weights of wd_k in f_k and f_T: mix[0] = fy = 1e6 / rho and mix[1] = fy R T / cp, so that
+    // f_k weighs wd_k by fy W_k and f_T by -mix[1] H_k/RT (the H/RT rows stay in sh).
     template <bool kLnA = false>
     __device__ __forceinline__ static void jacobian(const MechDev &m, double p, const double (&y)[N], double *sh,
                                                     double (&J)[N][N], double (&f)[N], double *lna = nullptr,
-                                                    double *wf = nullptr, double *wh = nullptr) {
+                                                    double *mix = nullptr) {
         Mix s;
         double cpR[N], hRT[N];
         state(m, p, y, sh, s, cpR, hRT);
@@ -267,11 +268,8 @@ struct Cell {
         const double icp = 1.0 / s.cp;
         f[0] = -hf * icp;
         if constexpr (kLnA) {
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                wf[k] = fy * m.sp[k * kSpTab];
-                wh[k] = wf[k] * hm[1 + k] * icp;
-            }
+            mix[0] = fy;
+            mix[1] = fy * kR * s.T * icp;
         }
         // temperature row: f_T = -sum_k h_k f_k / cp (u_k and cv at constant volume)
 #pragma unroll
