@@ -15,8 +15,9 @@ import numpy as np
 import pytest
 
 import oracle
+import synth
 from oracle import sensitivity as sens
-from synth import fields
+from synth import fields, testmechs
 
 pytestmark = pytest.mark.gpu
 
@@ -93,6 +94,70 @@ def test_adjoint_rows_match_oracle_sensitivities(h2_path, h2_mech, h2_oracle):
         err = np.abs(G[i] - S) / np.abs(S).max(axis=1, keepdims=True)
         assert err.max() <= RTOL_ROW, (i, err.max())
     assert matched >= 4
+
+
+def test_adjoint_small_mechanisms(tmp_path):
+    """The sweeps compiled for 2 and 4 species.
+
+    K = 2, A <-> B with rate constants independent of T and equal enthalpies: T stays constant
+    and Y(t) is linear in Y0, Y_A(t) = q (Y_A0 + Y_B0) + (Y_A0 - q (Y_A0 + Y_B0)) e^{-s} with
+    s = (kf + kr) t and q = kr / (kf + kr), and s proportional to A.  The adjoint's rows are the
+    derivatives of the computed step, which the closed forms match to the integrator's accuracy
+    (the oracle's own sensitivities: 2e-9 on the Y block, 2e-8 on ln A); the map of the computed
+    step is itself linear in Y0 (a Rosenbrock step of a linear system with its step lengths
+    fixed), so the rows applied to Y0 give the computed Y(dt) to rounding.
+    K = 4, P2 + Q2 + M <-> 2 PQ + M with heat release: rows against the oracle's forward
+    sensitivities, as for the hydrogen mechanism."""
+    import paper_2210_07094_amd as df
+    m = testmechs.isomerisation()
+    path = tmp_path / "iso.mech"
+    synth.write_mech(path, m)
+    gm = df.Mechanism(path)
+    n = 70
+    YA0 = np.linspace(0.05, 0.95, n)
+    f = {"T": np.full(n, 900.0), "p": np.full(n, 101325.0), "Y": np.vstack([YA0, 1 - YA0])}
+    print("case: adjoint, isomerisation K=2, 70 cells", flush=True)
+    _, p, Y, tape, st, ns = _taped(gm, f)
+    assert np.all(st.cpu().numpy() == df.CELL_OK)
+    G = _full_matrix(gm, p, tape, n)
+    kf = m.arrhenius[0, 0]
+    kr = kf / np.exp(m.nasa7[1, 6] - m.nasa7[0, 6])
+    s, q = (kf + kr) * DT, kr / (kf + kr)
+    e = np.exp(-s)
+    Jx = np.array([[q + (1 - q) * e, q * (1 - e)], [(1 - q) * (1 - e), (1 - q) + q * e]])
+    assert np.abs(G[:, 1:, 1:3] - Jx).max() <= 1e-7
+    np.testing.assert_allclose(G[:, 0, :], np.tile([1.0, 0.0, 0.0, 0.0], (n, 1)), rtol=0, atol=1e-12)
+    assert np.abs(G[:, 1:, 0]).max() <= 1e-12
+    lnA = -(YA0 - q) * s * e
+    np.testing.assert_allclose(G[:, 1, 3], lnA, rtol=1e-6, atol=1e-9)
+    np.testing.assert_allclose(G[:, 2, 3], -lnA, rtol=1e-6, atol=1e-9)
+    Yn = Y.cpu().numpy()
+    lin = np.einsum("nrc,cn->rn", G[:, 1:, 1:3], f["Y"])
+    assert np.abs(lin - Yn).max() <= 1e-13
+
+    mb = testmechs.bimolecular(k=3.0e15, third_body=True)
+    pb = tmp_path / "bi.mech"
+    synth.write_mech(pb, mb)
+    gb = df.Mechanism(pb)
+    ob = oracle.Mech(str(pb))
+    nb = 6
+    Yc = np.array([[0.05], [0.08], [0.0], [0.87]]) + np.outer([0.01, -0.01, 0.0, 0.0], np.linspace(0, 1, nb))
+    fb = {"T": np.linspace(950.0, 1150.0, nb), "p": np.full(nb, 101325.0), "Y": Yc}
+    print("case: adjoint, bimolecular + M K=4, 6 cells", flush=True)
+    _, pbt, _, tape_b, stb, nsb = _taped(gb, fb, dt=2e-5)
+    stb, nsb = stb.cpu().numpy(), nsb.cpu().numpy()
+    assert np.all(stb == df.CELL_OK)
+    Gb = _full_matrix(gb, pbt, tape_b, nb)
+    matched = 0
+    for i in range(nb):
+        S, sto, nacc, nrej = _oracle_rows(mb, ob, fb, i, dt=2e-5)
+        assert sto == 0
+        if (nacc, nrej) != (nsb[i], nsb[nb + i]):
+            continue
+        matched += 1
+        err = np.abs(Gb[i] - S) / np.abs(S).max(axis=1, keepdims=True)
+        assert err.max() <= RTOL_ROW, (i, err.max())
+    assert matched >= nb - 1
 
 
 def test_adjoint_against_central_differences(h2_path, h2_mech):
