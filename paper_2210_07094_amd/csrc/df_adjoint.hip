@@ -292,32 +292,6 @@ __device__ void vjp(const MechDev &m, double p, const S (&y)[K + 1], const doubl
     }
 }
 
-// A^T x = b with the LU of Cell<K>::lu (P A = L U, unit L below the diagonal, 1/U_kk on it,
-// row exchanges piv applied in order): U^T w = b, L^T z = w, x = P^T z.
-template <int N>
-__device__ __forceinline__ void solve_T(const double (&A)[N][N], const int (&piv)[N], double (&b)[N]) {
-#pragma unroll
-    for (int i = 0; i < N; ++i) {
-#pragma unroll
-        for (int j = 0; j < i; ++j) b[i] = fma(-A[j][i], b[j], b[i]);
-        b[i] *= A[i][i];
-    }
-#pragma unroll
-    for (int i = N - 1; i >= 0; --i)
-#pragma unroll
-        for (int j = i + 1; j < N; ++j) b[i] = fma(-A[j][i], b[j], b[i]);
-#pragma unroll
-    for (int k = N - 2; k >= 0; --k) {
-#pragma unroll
-        for (int r = N - 1; r > k; --r) {
-            const bool sw = (piv[k] == r);
-            const double x = b[k], y = b[r];
-            b[k] = sw ? y : x;
-            b[r] = sw ? x : y;
-        }
-    }
-}
-
 struct AdjArgs {
     int64_t n, ld;
     const double *p;
@@ -377,7 +351,6 @@ __global__ __launch_bounds__(kWave) void adjoint_kernel(MechDev m, AdjArgs a) {
     double *shr = lds + lane;                 // the Jacobian's rows
     double *lnar = lds + 5 * N * kWave + lane;  // its ln A factors
     double *th = lds + P * kWave + lane;
-    double *csd = reinterpret_cast<double *>(cs), *cbd = reinterpret_cast<double *>(cb);
     double *cell = lds + (P + m.M) * kWave + g * AdjLds<K>::kCell;
     double *ub = cell, *rbs = cell + 6 * N, *yba = cell + 12 * N, *vt = cell + 13 * N;
     double *ybp = ub;  // the stage adjoints are dead once the chain is done
