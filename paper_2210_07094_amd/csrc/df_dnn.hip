@@ -44,25 +44,26 @@ __device__ __forceinline__ double ipow(double x, int n) {
     return r;
 }
 
-// zero the fallback counter
-__global__ void zero_count(uint32_t *cnt) {
-    if (threadIdx.x == 0) *cnt = 0u;
-}
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-// flags: 1 = network, 0 = fallback (out of training range), 2 = non-finite input
+// Normalised network inputs and flags: 1 = network, 0 = fallback (out of training range),
+// 2 = non-finite input.  Cell i's row of in_pad bf16 inputs (zero beyond the K + 2 features, and
+// for the padding rows i >= n) is written as 16-byte pieces.  The thread of cell 0 also clears
+// the fallback counter, which the output kernel (a later launch) advances.
 template <int K>
 __global__ __launch_bounds__(kPreThreads) void pre_kernel(DnnDevParams prm, int64_t n, int64_t n_pad, int64_t ld,
                                                           const double *__restrict__ p, const double *__restrict__ T,
                                                           const double *__restrict__ Y, bf16_t *__restrict__ xb,
                                                           int in_pad, int8_t *__restrict__ flag,
-                                                          int32_t *__restrict__ idx, int32_t *__restrict__ count,
+                                                          int32_t *__restrict__ count,
                                                           int32_t *__restrict__ status, double *__restrict__ rr,
                                                           int fallback) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n_pad) return;
-    bf16_t *row = xb + i * in_pad;
+    if (i == 0) *count = 0;
+    u32x4 *row = reinterpret_cast<u32x4 *>(xb + i * in_pad);
     if (i >= n) {
-        for (int c = 0; c < in_pad; ++c) row[c] = 0;
+        for (int c = 0; c < in_pad / 8; ++c) row[c] = u32x4{0u, 0u, 0u, 0u};
         return;
     }
     constexpr int NI = K + 2;
@@ -85,15 +86,28 @@ __global__ __launch_bounds__(kPreThreads) void pre_kernel(DnnDevParams prm, int6
             if (!(x[c] >= prm.lo[c] && x[c] <= prm.hi[c])) f = 0;
     }
     flag[i] = int8_t(f);
+    unsigned xr[(NI + 1) / 2];
 #pragma unroll
-    for (int c = 0; c < NI; ++c) {
-        const double xn = (x[c] - prm.mu_in[c]) / prm.sig_in[c];
-        row[c] = (f == 1) ? f2bf(float(xn)) : bf16_t(0);
+    for (int c = 0; c < NI; c += 2) {
+        const double x0 = (x[c] - prm.mu_in[c]) / prm.sig_in[c];
+        const unsigned b0 = (f == 1) ? unsigned(f2bf(float(x0))) : 0u;
+        unsigned b1 = 0u;
+        if (c + 1 < NI) {
+            const double x1 = (x[c + 1] - prm.mu_in[c + 1]) / prm.sig_in[c + 1];
+            b1 = (f == 1) ? unsigned(f2bf(float(x1))) : 0u;
+        }
+        xr[c / 2] = b0 | (b1 << 16);
     }
-    for (int c = NI; c < in_pad; ++c) row[c] = 0;
-    if (f == 0 && fallback) {
-        idx[atomicAdd(count, 1)] = int32_t(i);
-    } else if (f != 1) {
+    constexpr int NQ = (NI + 7) / 8;  // 16-byte pieces holding features
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        u32x4 v;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) v[e] = (4 * q + e < (NI + 1) / 2) ? xr[4 * q + e] : 0u;
+        row[q] = v;
+    }
+    for (int q = NQ; q < in_pad / 8; ++q) row[q] = u32x4{0u, 0u, 0u, 0u};
+    if (f != 1 && !(f == 0 && fallback)) {
         // non-finite input, or out of range with the fallback switched off: state left as is
         if (status) status[i] = (f == 2) ? DF_CELL_NONFINITE : DF_CELL_DNN_FALLBACK;
         if (rr)
@@ -118,7 +132,9 @@ __global__ __launch_bounds__(kPostThreads) void post_kernel(DnnDevParams prm, Me
                                                             int k_in, const int8_t *__restrict__ flag,
                                                             const double *__restrict__ p, double *__restrict__ T,
                                                             double *__restrict__ Y, double *__restrict__ rr,
-                                                            int32_t *__restrict__ status, int renormalise) {
+                                                            int32_t *__restrict__ status, int renormalise,
+                                                            int32_t *__restrict__ idx, int32_t *__restrict__ count,
+                                                            int fallback) {
     constexpr int NT = (K + 15) / 16;          // 16-output tiles
     constexpr int NP = (K % 2) ? K : K + 1;    // LDS row stride in floats (odd: conflict-free reads)
     __shared__ float su[kPostThreads / 64][64 * NP];
@@ -162,7 +178,13 @@ __global__ __launch_bounds__(kPostThreads) void post_kernel(DnnDevParams prm, Me
     }
     __syncthreads();
     const int64_t i = cell0 + lane;
-    if (i >= n || flag[i] != 1) return;
+    if (i >= n) return;
+    const int fl = flag[i];
+    if (fl != 1) {
+        // the fallback list for the integrator's launch (its order does not change any cell's result)
+        if (fl == 0 && fallback) idx[atomicAdd(count, 1)] = int32_t(i);
+        return;
+    }
     float u[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) u[k] = su[wv][lane * NP + k];
@@ -331,10 +353,9 @@ df_status launch_dnn_k(const df_dnn *d, const df_mech *m, int64_t n, int64_t ld,
     auto *flag = reinterpret_cast<int8_t *>(base + w.o_flag);
     auto *idx = reinterpret_cast<int32_t *>(base + w.o_idx);
     auto *cnt = reinterpret_cast<int32_t *>(base + w.o_cnt);
-    hipLaunchKernelGGL(zero_count, dim3(1), dim3(64), 0, s, reinterpret_cast<uint32_t *>(cnt));
     const int in_pad = d->layers[0].k_pad;
     hipLaunchKernelGGL(pre_kernel<K>, dim3(unsigned((w.n_pad + kPreThreads - 1) / kPreThreads)), dim3(kPreThreads), 0,
-                       s, d->prm, n, w.n_pad, ld, p, T, Y, xb, in_pad, flag, idx, cnt, status, rr, o.fallback);
+                       s, d->prm, n, w.n_pad, ld, p, T, Y, xb, in_pad, flag, cnt, status, rr, o.fallback);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(DF_E_HIP, std::string("dnn pre launch: ") + hipGetErrorString(e));
     // hidden layers
@@ -385,7 +406,7 @@ df_status launch_dnn_k(const df_dnn *d, const df_mech *m, int64_t n, int64_t ld,
     const DnnLayer &Lo = d->layers.back();
     hipLaunchKernelGGL(post_kernel<K>, dim3(unsigned((n + kPostThreads - 1) / kPostThreads)), dim3(kPostThreads), 0, s,
                        d->prm, m->dev, n, ld, dt, in, in_ld, Lo.W, Lo.b, Lo.k_pad, flag, p, T, Y, rr, status,
-                       o.renormalise);
+                       o.renormalise, idx, cnt, o.fallback);
     e = hipGetLastError();
     if (e != hipSuccess) return fail(DF_E_HIP, std::string("dnn post launch: ") + hipGetErrorString(e));
     if (o.fallback) {
