@@ -197,8 +197,10 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(const bf16_t *__restrict
 // status as in the bf16 path.  The block scale keeps every finite scaled value within 448; the
 // other cases arise only when the block's maximum itself is not finite.
 __device__ __forceinline__ float fp8_in_range(float x) {
-    const float a = fabsf(x);
-    return (a <= 448.0f) ? x : ((a <= 464.0f) ? copysignf(448.0f, x) : __builtin_nanf(""));
+    // without branches: clamp to [-448, 448] (leaves |x| <= 448 and -0 as they are), then NaN
+    // where |x| > 464 or x is NaN (the comparison is false for NaN)
+    const float c = __builtin_amdgcn_fmed3f(x, -448.0f, 448.0f);
+    return (fabsf(x) <= 464.0f) ? c : __builtin_nanf("");
 }
 
 // E4M3FN bytes of four floats (round to nearest even)
@@ -237,8 +239,20 @@ __device__ __forceinline__ void store_fp8_block(floatx4 v0, floatx4 v1, uint8_t 
     const int e = fp8_scale_exp(m);
     const float sc = ldexpf(1.0f, -e);
     uint8_t *q = Q + row * ldq + c0 + 4 * g;
-    *reinterpret_cast<uint32_t *>(q) = to_fp8x4(f[0] * sc, f[1] * sc, f[2] * sc, f[3] * sc);
-    *reinterpret_cast<uint32_t *>(q + 16) = to_fp8x4(f[4] * sc, f[5] * sc, f[6] * sc, f[7] * sc);
+    uint32_t w0, w1;
+    if (m <= 3.40282347e38f) {
+        // a finite block maximum: the scale keeps every scaled value within 448 (a NaN value
+        // stays NaN through the conversion), so the range rule has nothing to do
+        int v = __builtin_amdgcn_cvt_pk_fp8_f32(f[0] * sc, f[1] * sc, 0, false);
+        w0 = uint32_t(__builtin_amdgcn_cvt_pk_fp8_f32(f[2] * sc, f[3] * sc, v, true));
+        v = __builtin_amdgcn_cvt_pk_fp8_f32(f[4] * sc, f[5] * sc, 0, false);
+        w1 = uint32_t(__builtin_amdgcn_cvt_pk_fp8_f32(f[6] * sc, f[7] * sc, v, true));
+    } else {
+        w0 = to_fp8x4(f[0] * sc, f[1] * sc, f[2] * sc, f[3] * sc);
+        w1 = to_fp8x4(f[4] * sc, f[5] * sc, f[6] * sc, f[7] * sc);
+    }
+    *reinterpret_cast<uint32_t *>(q) = w0;
+    *reinterpret_cast<uint32_t *>(q + 16) = w1;
     if (g == 0) S[row * sst + c0 / kFp8Block] = uint8_t(127 + e);
 }
 
