@@ -203,6 +203,109 @@ __global__ __launch_bounds__(64) void wgrad_kernel(const bf16_t *__restrict__ A,
     }
 }
 
+// Weight gradient of a layer whose padded widths are multiples of 160, dW[m][n] = sum over the
+// batch slice of A[b][m] X[b][n] (A: the gradient at the layer's output [Bp][lda], X: its input
+// [Bp][ldx]), and with tn == 0 the bias gradient sum_b A[b][m]: one 160 x 160 tile and one batch
+// slice per block of five waves.  Per 64-row step of the slice, each of the 320 threads loads one
+// 8 x 8 piece (eight batch rows of 16 bytes) of A (threads 0..159) or X (160..319), transposes it
+// in registers and writes it as eight 16-byte rows of the transposed tile in LDS, so that the
+// MFMA fragments (eight consecutive batch rows of one m or n) are single 16-byte reads.  Wave w
+// owns rows 32 w .. 32 w + 31 of the tile and its 160 columns (2 x 10 MFMA tiles).  The slice's
+// steps are 64-row steps sl, sl + S, ...; the partial sums of slice sl go to dW + sl rows_total ldw
+// (and db + sl rows_total) when S > 1.
+constexpr int kWbT = 160, kWbK = 64, kWbLd = kWbK + 8;  // tile side, batch rows per step, LDS row stride
+constexpr int kWbThreads = 320;
+__global__ __launch_bounds__(kWbThreads) void wgrad_big_kernel(const bf16_t *__restrict__ A, int lda,
+                                                               const bf16_t *__restrict__ X, int ldx, int64_t Bp,
+                                                               int S, float *__restrict__ dW, int ldw, int tiles_n,
+                                                               int rows_total, float *__restrict__ db) {
+    __shared__ __attribute__((aligned(16))) bf16_t At[kWbT * kWbLd], Xt[kWbT * kWbLd];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int tile = int(blockIdx.x) / S, sl = int(blockIdx.x) % S;
+    const int tm = tile / tiles_n, tn = tile % tiles_n;
+    const int m0 = tm * kWbT, n0 = tn * kWbT;
+    // this thread's piece: batch group bg (rows 8 bg .. 8 bg + 7 of the step), column group cg
+    const bool isA = t < kWbT;
+    const int u = isA ? t : t - kWbT;
+    const int bg = u & 7, cg = u >> 3;
+    const bf16_t *src = isA ? A + (m0 + 8 * cg) : X + (n0 + 8 * cg);
+    const int64_t ld = isA ? lda : ldx;
+    bf16_t *dst = (isA ? At : Xt) + (8 * cg) * kWbLd + 8 * bg;
+    u32x4 r[8];
+    auto load = [&](int64_t b0) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) r[j] = *reinterpret_cast<const u32x4 *>(src + (b0 + 8 * bg + j) * ld);
+    };
+    auto store = [&]() {
+        // column c of the piece holds the values of batch rows 0..7, two to a word (row 2p low)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            u32x4 v;
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const unsigned lo = r[2 * p][c >> 1], hi = r[2 * p + 1][c >> 1];
+                v[p] = (c & 1) ? ((lo >> 16) | (hi & 0xffff0000u)) : ((lo & 0xffffu) | (hi << 16));
+            }
+            *reinterpret_cast<u32x4 *>(dst + c * kWbLd) = v;
+        }
+    };
+    floatx4 acc[2][10];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 10; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    float cs[2] = {0.0f, 0.0f};
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
+    const int64_t step = int64_t(S) * kWbK;
+    int64_t b0 = int64_t(sl) * kWbK;
+    if (b0 < Bp) load(b0);
+    for (; b0 < Bp; b0 += step) {
+        __syncthreads();  // the previous step's fragment reads are done
+        store();
+        __syncthreads();
+        if (b0 + step < Bp) load(b0 + step);
+#pragma unroll
+        for (int kk = 0; kk < kWbK; kk += 32) {
+            bf16x8 af[2], xf[10];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                af[i] = *reinterpret_cast<const bf16x8 *>(At + (w * 32 + i * 16 + fr) * kWbLd + kk + fk);
+                if (tn == 0) {
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) cs[i] += float(af[i][q]);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 10; ++j) xf[j] = *reinterpret_cast<const bf16x8 *>(Xt + (j * 16 + fr) * kWbLd + kk + fk);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 10; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], xf[j], acc[i][j], 0, 0, 0);
+        }
+    }
+    float *out = (S == 1) ? dW : dW + size_t(sl) * size_t(rows_total) * size_t(ldw);
+    // lane holds column (lane % 16) and rows 4 (lane / 16) + r of each 16 x 16 tile
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 10; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                out[int64_t(m0 + w * 32 + i * 16 + (lane >> 4) * 4 + q) * ldw + n0 + j * 16 + fr] = acc[i][j][q];
+    if (tn == 0) {
+        // lanes l, l + 16, l + 32, l + 48 hold the four batch quarters of row w 32 + i 16 + l
+        float *outb = (S == 1) ? db : db + size_t(sl) * size_t(rows_total);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            float v = cs[i];
+            v += __shfl_xor(v, 16);
+            v += __shfl_xor(v, 32);
+            if (lane < 16) outb[m0 + w * 32 + i * 16 + lane] = v;
+        }
+    }
+}
+
 // dW = sum over the S slices of P[s] (in slice order), db likewise from Pb
 __global__ __launch_bounds__(kT) void wgrad_reduce_kernel(const float *__restrict__ P, const float *__restrict__ Pb,
                                                           int S, int64_t nw, int nb, float *__restrict__ dW,
@@ -227,6 +330,33 @@ int wgrad_slices(int64_t tiles, int64_t Bp) {
     S = std::min<int64_t>(S, 32);
     S = std::min<int64_t>(S, std::max<int64_t>(1, Bp / 32));
     return int(std::max<int64_t>(S, 1));
+}
+
+// How a hidden layer's weight gradient is computed: 160 x 160 tiles (wgrad_big_kernel) where both
+// padded widths are multiples of 160 and the padded batch of 64, else 32 x 32 tiles; S batch
+// slices, enough for about 400 blocks (2000 waves) of the large tiles.
+struct WgradPlan {
+    bool big;
+    int S;
+    int64_t tiles;
+    int tiles_n;
+};
+WgradPlan wgrad_plan(const DnnLayer &Ly, int64_t Bp) {
+    WgradPlan p{};
+    p.big = Ly.n_pad % kWbT == 0 && Ly.k_pad % kWbT == 0 && Bp % kWbK == 0;
+    if (p.big) {
+        p.tiles_n = Ly.k_pad / kWbT;
+        p.tiles = int64_t(Ly.n_pad / kWbT) * p.tiles_n;
+        int64_t S = (400 + p.tiles - 1) / p.tiles;
+        S = std::min<int64_t>(S, 32);
+        S = std::min<int64_t>(S, std::max<int64_t>(1, Bp / kWbK));
+        p.S = int(std::max<int64_t>(S, 1));
+    } else {
+        p.tiles_n = Ly.k_pad / 32;
+        p.tiles = int64_t(Ly.n_pad / 32) * p.tiles_n;
+        p.S = wgrad_slices(p.tiles, Bp);
+    }
+    return p;
 }
 
 // output layer gradients: dW[o][i] = sum_b du[b][o] h[b][i], db[o] = sum_b du[b][o]; one
@@ -419,7 +549,7 @@ df_status df_dnn_trainer_create(df_dnn *d, int64_t max_batch, df_trainer **out) 
     size_t part = 0, part_b = 0;
     for (int l = 0; l < nh; ++l) {
         const DnnLayer &Ly = d->layers[l];
-        const int S = wgrad_slices(int64_t(Ly.n_pad / 32) * (Ly.k_pad / 32), t->bp);
+        const int S = wgrad_plan(Ly, t->bp).S;
         if (S > 1) {
             part = std::max(part, size_t(S) * Ly.n_pad * Ly.k_pad);
             part_b = std::max(part_b, size_t(S) * Ly.n_pad);
@@ -559,11 +689,16 @@ df_status df_dnn_train_step(df_trainer *t, int64_t batch, const float *x, const 
         const DnnLayer &Ly = d->layers[l];
         const bf16_t *inl = (l == 0) ? t->x : t->h[l - 1];
         const int inl_ld = Ly.k_pad;
-        const int tiles_n = Ly.k_pad / 32;
-        const int64_t tiles = int64_t(Ly.n_pad / 32) * tiles_n;
-        const int S = wgrad_slices(tiles, Bp);
-        hipLaunchKernelGGL(wgrad_kernel, dim3(unsigned(tiles * S)), dim3(64), 0, s, t->da[l], Ly.n_pad, inl, inl_ld,
-                           Bp, S, S > 1 ? t->part : t->gW[l], Ly.k_pad, tiles_n, S > 1 ? t->part_b : t->gb[l]);
+        const WgradPlan wp = wgrad_plan(Ly, Bp);
+        const int S = wp.S;
+        if (wp.big)
+            hipLaunchKernelGGL(wgrad_big_kernel, dim3(unsigned(wp.tiles * S)), dim3(kWbThreads), 0, s, t->da[l],
+                               Ly.n_pad, inl, inl_ld, Bp, S, S > 1 ? t->part : t->gW[l], Ly.k_pad, wp.tiles_n,
+                               Ly.n_pad, S > 1 ? t->part_b : t->gb[l]);
+        else
+            hipLaunchKernelGGL(wgrad_kernel, dim3(unsigned(wp.tiles * S)), dim3(64), 0, s, t->da[l], Ly.n_pad, inl,
+                               inl_ld, Bp, S, S > 1 ? t->part : t->gW[l], Ly.k_pad, wp.tiles_n,
+                               S > 1 ? t->part_b : t->gb[l]);
         chk("weight gradient");
         if (S > 1) {
             const int64_t nw = int64_t(Ly.n_pad) * Ly.k_pad;
