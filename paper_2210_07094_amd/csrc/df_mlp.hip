@@ -31,14 +31,12 @@ constexpr int TM = WM / 16, TN = WN / 16;  // MFMA tiles per wave
 
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
-
-// GELU(x) = x Phi(x) of the inference epilogue without branches: Phi(x) = erfc(-x/sqrt 2) / 2,
+// GELU(x) = x Phi(x) of the inference and training epilogues without branches: Phi(x) = erfc(-x/sqrt 2) / 2,
 // with erfc(a) for a >= 0 from the Chebyshev fit erfcc of Press et al., Numerical Recipes
 // (Sec. 6.2), erfc(a) = t exp(-a^2 + P(t)), t = 1 / (1 + a/2), fractional error below 1.2e-7
 // for every a >= 0; for x >= 0, Phi = 1 - erfc(x/sqrt 2) / 2.  Its error is far below the bf16
 // rounding that follows.  NaN stays NaN; GELU(+inf) = +inf, GELU(-inf) = NaN as x Phi(x) gives.
-__device__ __forceinline__ float gelu_erfc(float x) {
+__device__ __forceinline__ float phi_erfc(float x) {
     const float z = x * 0.70710678118654752f;
     const float a = fabsf(z);
     const float t = __builtin_amdgcn_rcpf(1.0f + 0.5f * a);
@@ -53,17 +51,18 @@ __device__ __forceinline__ float gelu_erfc(float x) {
     q = fmaf(q, t, 1.00002368f);
     q = fmaf(q, t, -1.26551223f);
     const float h = 0.5f * t * __expf(fmaf(-a, a, q));  // erfc(a) / 2
-    return x * ((z >= 0.0f) ? 1.0f - h : h);
+    return (z >= 0.0f) ? 1.0f - h : h;
 }
+__device__ __forceinline__ float gelu_erfc(float x) { return x * phi_erfc(x); }
 
 // four floats to bf16 with two packed conversions (v_cvt_pk_bf16_f32): round to nearest even and
 // NaN kept, except that fp32 subnormal inputs (|x| < 2^-126) are rounded toward zero, at most one
 // bf16 subnormal unit (2^-133) from the nearest-even result
 __device__ __forceinline__ bf16x4 to_bf16x4(floatx4 v) { return __builtin_convertvector(v, bf16x4); }
 
-// d GELU / dx = Phi(x) + x phi(x)
+// d GELU / dx = Phi(x) + x phi(x), Phi as in gelu_erfc (no branches)
 __device__ __forceinline__ float gelu_grad(float x) {
-    return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * expf(-0.5f * x * x);
+    return fmaf(x * 0.39894228040143268f, __expf(-0.5f * x * x), phi_erfc(x));
 }
 
 // Epilogues: inference (bias, GELU); training forward (bias, GELU, and the pre-activation
@@ -179,7 +178,7 @@ __global__ __launch_bounds__(kThreads) void gemm_kernel(const bf16_t *__restrict
             }
             if (EPI == kEpiGeluSave) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) v[r] = gelu(v[r]);
+                for (int r = 0; r < 4; ++r) v[r] = gelu_erfc(v[r]);
             }
             if (EPI == kEpiGeluGrad) {
                 const bf16x4 pv = *reinterpret_cast<const bf16x4 *>(P + off);
