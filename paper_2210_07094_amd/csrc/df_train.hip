@@ -393,27 +393,43 @@ __global__ __launch_bounds__(kT) void wgrad_out_kernel(const float *__restrict__
     }
 }
 
-// Adam on one parameter block [rows][cols] (padded storage, real part rows_r x cols_r; padding
-// stays zero).  Writes the fp32 master, the bf16 copy (if Wb) and the transposed bf16 copy (if WT).
-__global__ __launch_bounds__(kT) void adam_kernel(float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
-                                                  const float *__restrict__ g, int rows, int cols, int rows_r,
-                                                  int cols_r, float lr, float b1, float b2, float eps, float bc1,
-                                                  float bc2, bf16_t *__restrict__ Wb, bf16_t *__restrict__ WT,
-                                                  float *__restrict__ wf) {
-    const int64_t e = int64_t(blockIdx.x) * kT + threadIdx.x;
-    if (e >= int64_t(rows) * cols) return;
-    const int r = int(e / cols), c = int(e % cols);
-    if (r >= rows_r || c >= cols_r) return;
-    const float gi = g[e];
-    const float mi = b1 * m[e] + (1.0f - b1) * gi;
-    const float vi = b2 * v[e] + (1.0f - b2) * gi * gi;
-    m[e] = mi;
-    v[e] = vi;
-    const float wi = w[e] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
-    w[e] = wi;
-    if (Wb) Wb[e] = tbf(wi);
-    if (WT) WT[int64_t(c) * rows + r] = tbf(wi);
-    if (wf) wf[e] = wi;
+// Adam over every parameter block of the network in one launch.  Segment q is one parameter
+// block [rows][cols] (padded storage, real part rows_r x cols_r; padding stays zero), taken by the
+// thread blocks first[q] .. first[q + 1] - 1; it writes the fp32 master, the bf16 copy (if Wb), the
+// transposed bf16 copy (if WT) and an fp32 copy (if wf).
+constexpr int kAdamSegs = 32;
+struct AdamSeg {
+    float *w, *m, *v;
+    const float *g;
+    bf16_t *Wb, *WT;
+    float *wf;
+    int rows, cols, rows_r, cols_r;
+};
+struct AdamSegs {
+    AdamSeg seg[kAdamSegs];
+    int64_t first[kAdamSegs + 1];
+    int n;
+};
+__global__ __launch_bounds__(kT) void adam_all_kernel(AdamSegs sg, float lr, float b1, float b2, float eps, float bc1,
+                                                      float bc2) {
+    const int64_t blk = blockIdx.x;
+    int q = 0;
+    while (q + 1 < sg.n && blk >= sg.first[q + 1]) ++q;  // block-uniform
+    const AdamSeg &a = sg.seg[q];
+    const int64_t e = (blk - sg.first[q]) * kT + threadIdx.x;
+    if (e >= int64_t(a.rows) * a.cols) return;
+    const int r = int(e / a.cols), c = int(e % a.cols);
+    if (r >= a.rows_r || c >= a.cols_r) return;
+    const float gi = a.g[e];
+    const float mi = b1 * a.m[e] + (1.0f - b1) * gi;
+    const float vi = b2 * a.v[e] + (1.0f - b2) * gi * gi;
+    a.m[e] = mi;
+    a.v[e] = vi;
+    const float wi = a.w[e] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    a.w[e] = wi;
+    if (a.Wb) a.Wb[e] = tbf(wi);
+    if (a.WT) a.WT[int64_t(c) * a.rows + r] = tbf(wi);
+    if (a.wf) a.wf[e] = wi;
 }
 
 // trainer set-up: fp32 master from the handle's bf16 weights, transposed bf16 copies
@@ -718,16 +734,26 @@ df_status df_dnn_train_step(df_trainer *t, int64_t batch, const float *x, const 
         ++t->step;
         const float bc1 = float(1.0 - std::pow(double(ao.beta1), double(t->step)));
         const float bc2 = float(1.0 - std::pow(double(ao.beta2), double(t->step)));
-        for (int l = 0; l <= nh; ++l) {
+        // every layer's weights and biases in one launch
+        AdamSegs sg{};
+        int64_t blocks = 0;
+        for (int l = 0; l <= nh && sg.n + 2 <= kAdamSegs; ++l) {
             DnnLayer &Ly = d->layers[l];
-            const int64_t nw = int64_t(Ly.n_pad) * Ly.k_pad;
-            hipLaunchKernelGGL(adam_kernel, dim3(unsigned((nw + kT - 1) / kT)), dim3(kT), 0, s, t->W[l], t->mW[l],
-                               t->vW[l], t->gW[l], Ly.n_pad, Ly.k_pad, Ly.n_out, Ly.n_in, ao.lr, ao.beta1, ao.beta2,
-                               ao.eps, bc1, bc2, Ly.W, t->WT[l], static_cast<float *>(nullptr));
-            hipLaunchKernelGGL(adam_kernel, dim3(unsigned((Ly.n_pad + kT - 1) / kT)), dim3(kT), 0, s, t->b[l],
-                               t->mb[l], t->vb[l], t->gb[l], Ly.n_pad, 1, Ly.n_out, 1, ao.lr, ao.beta1, ao.beta2,
-                               ao.eps, bc1, bc2, static_cast<bf16_t *>(nullptr), static_cast<bf16_t *>(nullptr),
-                               Ly.b);
+            sg.seg[sg.n] = AdamSeg{t->W[l], t->mW[l], t->vW[l], t->gW[l], Ly.W, t->WT[l], nullptr,
+                                   Ly.n_pad, Ly.k_pad, Ly.n_out, Ly.n_in};
+            sg.first[sg.n++] = blocks;
+            blocks += (int64_t(Ly.n_pad) * Ly.k_pad + kT - 1) / kT;
+            sg.seg[sg.n] = AdamSeg{t->b[l], t->mb[l], t->vb[l], t->gb[l], nullptr, nullptr, Ly.b,
+                                   Ly.n_pad, 1, Ly.n_out, 1};
+            sg.first[sg.n++] = blocks;
+            blocks += (int64_t(Ly.n_pad) + kT - 1) / kT;
+        }
+        sg.first[sg.n] = blocks;
+        if (sg.n != 2 * (nh + 1)) {
+            st = fail(DF_E_UNSUPPORTED, std::string(who) + ": too many layers for one Adam launch");
+        } else {
+            hipLaunchKernelGGL(adam_all_kernel, dim3(unsigned(blocks)), dim3(kT), 0, s, sg, ao.lr, ao.beta1,
+                               ao.beta2, ao.eps, bc1, bc2);
             chk("Adam");
         }
     }
