@@ -323,10 +323,8 @@ struct AdjLds {
     static constexpr int kTapeRec = N * N + 7 * N;  // a sub-step's W^-1, y and six stage vectors
     static constexpr int kCell = 14 * N + kTapeRec;
     __host__ __device__ static int work_rows(int M) { return 4 * N + 4 * K > 5 * N + M ? 4 * N + 4 * K : 5 * N + M; }
-    // doubles of the per-lane rows and the cell regions, then of the mechanism copy
+    // doubles of the per-lane rows and the cell regions (the mechanism copy follows them)
     __host__ __device__ static int front(int M) { return kWave * (work_rows(M) + M) + kAdjCells * kCell; }
-    __host__ __device__ static int mech_dbl(int M) { return K * kSpTab + M * (kRxDbl + K + kAdjCr); }
-    __host__ __device__ static int mech_int(int M) { return M * (kRxInt + K); }
 };
 
 // One cell per group of 8 lanes.  Per sub-step, last to first:
