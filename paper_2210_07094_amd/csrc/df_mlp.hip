@@ -16,6 +16,7 @@
 
 #include "df_fp8.h"
 #include "df_internal.h"
+#include "df_phi_table.h"
 
 namespace df {
 namespace {
@@ -65,6 +66,36 @@ __device__ __forceinline__ float gelu_grad(float x) {
     return fmaf(x * 0.39894228040143268f, __expf(-0.5f * x * x), phi_erfc(x));
 }
 
+// GELU of the inference epilogues, GELU(x) = x Phi(x), with Phi from the table of one cubic per
+// interval of 12/256 on [-6, 6] (kPhiTable, from erfc in double), which the block keeps in LDS.
+// Interpolation error 1.5e-9; the position s = x 256/12 is rounded relative to x, so with the
+// float32 evaluation the result is within about 1e-7 of x Phi(x), as close as gelu_erfc, so that
+// the bf16 rounding that follows differs from that of the exact value as rarely.  Beyond the table
+// Phi is 0 (x < -6 - 12/256, where the exact value is below 7e-10) or 1 (x >= 6).  NaN stays NaN;
+// GELU(+inf) = +inf and GELU(-inf) = NaN, as x Phi(x) gives.  About 10 VALU instructions and one
+// 16-byte LDS read per value, against about 28 instruction slots for gelu_erfc (reciprocal and
+// exponential at a quarter of the rate).
+constexpr int kPhiLdsFloats = 4 * kPhiEntries;  // 4,128 bytes of LDS per block
+
+__device__ __forceinline__ float gelu_tab(float x, const float *__restrict__ tab) {
+    constexpr float kScale = float(kPhiIntervals) / 12.0f, kHalf = 0.5f * float(kPhiIntervals);
+    // position in intervals from 0, clamped to the table: entry 0 (zeros) below -6, entries
+    // 1 .. kPhiIntervals the cubics, entry kPhiIntervals + 1 from 6 on; fmaxf maps NaN to entry 0
+    const float s = fminf(fmaxf(x * kScale, -kHalf - 1.0f), kHalf);
+    const int k = int(floorf(s)) + int(kHalf) + 1;  // 0 .. kPhiIntervals + 1
+    const float u = __builtin_amdgcn_fractf(s);
+    const floatx4 c = *reinterpret_cast<const floatx4 *>(tab + 4 * k);
+    return x * fmaf(fmaf(fmaf(c[3], u, c[2]), u, c[1]), u, c[0]);
+}
+
+// copies the table into the block's LDS copy in 16-byte pieces; a barrier must follow before the
+// first gelu_tab
+__device__ __forceinline__ void copy_phi_table(float *__restrict__ lds, int t) {
+    const u32x4 *src = reinterpret_cast<const u32x4 *>(kPhiTable);
+    u32x4 *dst = reinterpret_cast<u32x4 *>(lds);
+    for (int i = t; i < kPhiLdsFloats / 4; i += kThreads) dst[i] = src[i];
+}
+
 // Epilogues: inference (bias, GELU); training forward (bias, GELU, and the pre-activation
 // stored to P with C's layout); training backward (the product times GELU'(P), no bias).
 enum { kEpiGelu = 0, kEpiLinear = 1, kEpiGeluSave = 2, kEpiGeluGrad = 3 };
@@ -80,6 +111,7 @@ __global__ __launch_bounds__(kThreads, KD == 32 ? 3 : 1) void gemm_kernel(const 
     constexpr int LDKD = KD + 16;  // LDS row stride in bf16 (96 bytes at KD = 32)
     __shared__ __attribute__((aligned(16))) bf16_t As[BM * LDKD];
     __shared__ __attribute__((aligned(16))) bf16_t Bs[BN * LDKD];
+    __shared__ __attribute__((aligned(16))) float Ptab[EPI == kEpiGelu ? kPhiLdsFloats : 4];
 
     // XCD-aware tile order: workgroups are dispatched round-robin over the 8 XCDs, so
     // block b runs on XCD b % 8; give each XCD a contiguous range of logical tiles.
@@ -138,6 +170,7 @@ __global__ __launch_bounds__(kThreads, KD == 32 ? 3 : 1) void gemm_kernel(const 
     // the B tile, with 8 consecutive k values starting at 8 * (l / 16)
     const int fr = lane & 15, fk = (lane >> 4) * 8;
     load(0);
+    if (EPI == kEpiGelu) copy_phi_table(Ptab, t);  // visible after the stage loop's first barrier
     for (int k0 = 0; k0 < K; k0 += KD) {
         __syncthreads();
         store();
@@ -176,7 +209,7 @@ __global__ __launch_bounds__(kThreads, KD == 32 ? 3 : 1) void gemm_kernel(const 
             if (EPI == kEpiGeluSave) *reinterpret_cast<bf16x4 *>(P + off) = to_bf16x4(v);
             if (EPI == kEpiGelu) {
 #pragma unroll
-                for (int r = 0; r < 4; ++r) v[r] = gelu_erfc(v[r]);
+                for (int r = 0; r < 4; ++r) v[r] = gelu_tab(v[r], Ptab);
             }
             if (EPI == kEpiGeluSave) {
 #pragma unroll
@@ -263,7 +296,7 @@ __device__ __forceinline__ void store_fp8_block(floatx4 v0, floatx4 v1, uint8_t 
 // fragments and walks down the row tiles tile_m = g, g + G, ... (G = gridDim.x / n_tiles_n),
 // loading each tile's activation fragments straight from global memory (16 rows x 64 contiguous
 // bytes per load) one tile ahead, so that the loads of the next tile are in flight during the
-// epilogue of the current one; no LDS and no barriers.  Same tile shape, operand order and
+// epilogue of the current one; LDS holds only the GELU table (one barrier, at the start).  Same tile shape, operand order and
 // epilogue (bias, GELU, bf16) as gemm_kernel; with Q8 the output is the FP8 copy the next layer
 // reads (store_fp8_block), and the four waves take 32 rows x 160 columns each so that every
 // wave owns whole 32-column blocks.
@@ -282,6 +315,8 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_shallow_kernel(const bf16_t 
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const int wm = Q8 ? w : w >> 1, wn = Q8 ? 0 : w & 1;
     const int fr = lane & 15, fg = lane >> 4, fk = fg * 8;
+    __shared__ __attribute__((aligned(16))) float Ptab[kPhiLdsFloats];
+    copy_phi_table(Ptab, t);
 
     bf16x8 bfr[KS][TNq];
 #pragma unroll
@@ -304,6 +339,7 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_shallow_kernel(const bf16_t 
     };
     bf16x8 an[KS][TMq];
     if (g0 < n_tiles_m) load_a(g0, an);
+    __syncthreads();  // the table is in LDS
     for (int tm = g0; tm < n_tiles_m; tm += G) {
         bf16x8 af[KS][TMq];
 #pragma unroll
@@ -330,8 +366,8 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_shallow_kernel(const bf16_t 
                     floatx4 v0 = acc[i][2 * q] + bc[2 * q], v1 = acc[i][2 * q + 1] + bc[2 * q + 1];
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        v0[r] = gelu_erfc(v0[r]);
-                        v1[r] = gelu_erfc(v1[r]);
+                        v0[r] = gelu_tab(v0[r], Ptab);
+                        v1[r] = gelu_tab(v1[r], Ptab);
                     }
                     store_fp8_block(v0, v1, reinterpret_cast<uint8_t *>(C), S, row0 + i * 16, ldc, sst,
                                     col0 + 32 * q, fg);
@@ -345,7 +381,7 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_shallow_kernel(const bf16_t 
                     const int64_t row = row0 + i * 16;
                     floatx4 v = acc[i][j] + bc[j];
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) v[r] = gelu_erfc(v[r]);
+                    for (int r = 0; r < 4; ++r) v[r] = gelu_tab(v[r], Ptab);
                     *reinterpret_cast<bf16x4 *>(C + row * ldc + col) = to_bf16x4(v);
                 }
             }
@@ -377,6 +413,7 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_fp8_kernel(const uint8_t *__
     __shared__ __attribute__((aligned(16))) uint8_t As[BM * LDK8];
     __shared__ __attribute__((aligned(16))) uint8_t Bs[BN * LDK8];
     __shared__ uint32_t Ss[BM];
+    __shared__ __attribute__((aligned(16))) float Ptab[kPhiLdsFloats];
 
     const int nb = gridDim.x, b = blockIdx.x;
     const int logical = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
@@ -437,6 +474,7 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_fp8_kernel(const uint8_t *__
         for (int j = 0; j < TNq; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
     load(0);
+    copy_phi_table(Ptab, t);  // visible after the stage loop's first barrier
     for (int k0 = 0; k0 < K; k0 += KD8) {
         __syncthreads();
         store();
@@ -475,8 +513,8 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_fp8_kernel(const uint8_t *__
                 floatx4 v0 = acc[i][2 * q] + b0, v1 = acc[i][2 * q + 1] + b1;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
-                    v0[r] = gelu_erfc(v0[r]);
-                    v1[r] = gelu_erfc(v1[r]);
+                    v0[r] = gelu_tab(v0[r], Ptab);
+                    v1[r] = gelu_tab(v1[r], Ptab);
                 }
                 store_fp8_block(v0, v1, reinterpret_cast<uint8_t *>(C), SC, row0 + wm * WMq + i * 16 + fr, ldc, sstc,
                                 col0 + 32 * q, fg);
@@ -492,7 +530,7 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_fp8_kernel(const uint8_t *__
                 const int64_t row = row0 + wm * WMq + i * 16 + fr;
                 floatx4 v = acc[i][j] + bc;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) v[r] = gelu_erfc(v[r]);
+                for (int r = 0; r < 4; ++r) v[r] = gelu_tab(v[r], Ptab);
                 *reinterpret_cast<bf16x4 *>(C + row * ldc + col) = to_bf16x4(v);
             }
         }
@@ -539,7 +577,7 @@ df_status launch_gemm_bf16(const bf16_t *A, int lda, const bf16_t *B, int ldb, c
 
 df_status launch_gemm_bf16_epi(const bf16_t *A, int lda, const bf16_t *B, int ldb, const float *bias, bf16_t *C,
                                int ldc, int64_t M, int N, int K, GemmEpi epi, bf16_t *P, hipStream_t stream) {
-    if (M % BM || N % BN || K % BK || lda % 8 || ldb % 8)
+    if (M % BM || N % BN || K % BK || K <= 0 || lda % 8 || ldb % 8)
         return fail(DF_E_INVALID, "gemm: shapes must be multiples of the tile sizes");
     if ((epi == GemmEpi::gelu_save || epi == GemmEpi::gelu_grad) && !P)
         return fail(DF_E_INVALID, "gemm: the epilogue needs the pre-activation array");
@@ -587,7 +625,7 @@ df_status launch_gemm_bf16_fp8out(const bf16_t *A, int lda, const bf16_t *B, int
 df_status launch_gemm_fp8(const uint8_t *A8, int lda, const uint8_t *S, int sst, const uint8_t *W8, int ldb,
                           const int32_t *wexp, const float *bias, bf16_t *C, int ldc, uint8_t *SC, int sstc,
                           int64_t M, int N, int K, hipStream_t stream) {
-    if (M % BM || N % BN || K % kFp8Block || lda % 16 || ldb % 16 || sst % 16 || lda < K || ldb < K ||
+    if (M % BM || N % BN || K % kFp8Block || K <= 0 || lda % 16 || ldb % 16 || sst % 16 || lda < K || ldb < K ||
         sst < K / kFp8Block || (SC && (ldc % 16 || sstc % 16 || sstc < N / kFp8Block)))
         return fail(DF_E_INVALID, "gemm fp8: shapes must be multiples of the tile sizes (rows of 16 bytes)");
     if (!A8 || !S || !W8 || !wexp) return fail(DF_E_INVALID, "gemm fp8: null activation, scale, weight or exponent array");
