@@ -253,11 +253,11 @@ __device__ __forceinline__ uint32_t to_fp8x4(float a, float b, float c, float d)
 // (lane l: row l % 16, columns 4 (l / 16) + r of each), so a block's 32 values of a row lie with
 // the four lanes l % 16 + 16 g'.  Each value is rounded to bf16 first (the hidden activations are
 // bf16 values in every precision), the block's largest magnitude is combined over the four lanes
-// (NaN ignored), and the values are quantised with the block's scale: E4M3FN bytes to
-// Q[row][c0 .. c0 + 32) and the E8M0 scale byte to S[row][c0 / 32].
-__device__ __forceinline__ void store_fp8_block(floatx4 v0, floatx4 v1, uint8_t *__restrict__ Q,
-                                                uint8_t *__restrict__ S, int64_t row, int ldq, int sst, int c0,
-                                                int g) {
+// (NaN ignored), and the values are quantised with the block's scale: the lane's E4M3FN bytes of
+// Q[row][c0 .. c0 + 32) as two words (bytes 4 g .. 4 g + 3 and 16 + 4 g .. 16 + 4 g + 3), and the
+// E8M0 scale byte to S[row][c0 / 32].
+__device__ __forceinline__ void quant_fp8_block(floatx4 v0, floatx4 v1, uint8_t *__restrict__ S, int64_t row,
+                                                int sst, int c0, int g, uint32_t &w0, uint32_t &w1) {
     const bf16x4 h0 = to_bf16x4(v0), h1 = to_bf16x4(v1);
     float f[8];
 #pragma unroll
@@ -272,8 +272,6 @@ __device__ __forceinline__ void store_fp8_block(floatx4 v0, floatx4 v1, uint8_t 
     m = fmaxf(m, __shfl_xor(m, 32));
     const int e = fp8_scale_exp(m);
     const float sc = ldexpf(1.0f, -e);
-    uint8_t *q = Q + row * ldq + c0 + 4 * g;
-    uint32_t w0, w1;
     if (m <= 3.40282347e38f) {
         // a finite block maximum: the scale keeps every scaled value within 448 (a NaN value
         // stays NaN through the conversion), so the range rule has nothing to do
@@ -285,9 +283,18 @@ __device__ __forceinline__ void store_fp8_block(floatx4 v0, floatx4 v1, uint8_t 
         w0 = to_fp8x4(f[0] * sc, f[1] * sc, f[2] * sc, f[3] * sc);
         w1 = to_fp8x4(f[4] * sc, f[5] * sc, f[6] * sc, f[7] * sc);
     }
+    if (g == 0) S[row * sst + c0 / kFp8Block] = uint8_t(127 + e);
+}
+
+// the same, with the lane's two words stored to Q[row][c0 + 4 g] and Q[row][c0 + 16 + 4 g]
+__device__ __forceinline__ void store_fp8_block(floatx4 v0, floatx4 v1, uint8_t *__restrict__ Q,
+                                                uint8_t *__restrict__ S, int64_t row, int ldq, int sst, int c0,
+                                                int g) {
+    uint32_t w0, w1;
+    quant_fp8_block(v0, v1, S, row, sst, c0, g, w0, w1);
+    uint8_t *q = Q + row * ldq + c0 + 4 * g;
     *reinterpret_cast<uint32_t *>(q) = w0;
     *reinterpret_cast<uint32_t *>(q + 16) = w1;
-    if (g == 0) S[row * sst + c0 / kFp8Block] = uint8_t(127 + e);
 }
 
 // Inference layer with a shallow reduction (K = KD <= 64, the first hidden layer: the network's
@@ -298,8 +305,13 @@ __device__ __forceinline__ void store_fp8_block(floatx4 v0, floatx4 v1, uint8_t 
 // bytes per load) one tile ahead, so that the loads of the next tile are in flight during the
 // epilogue of the current one; LDS holds only the GELU table (one barrier, at the start).  Same tile shape, operand order and
 // epilogue (bias, GELU, bf16) as gemm_kernel; with Q8 the output is the FP8 copy the next layer
-// reads (store_fp8_block), and the four waves take 32 rows x 160 columns each so that every
-// wave owns whole 32-column blocks.
+// reads (quant_fp8_block), and the four waves take 32 rows x 160 columns each so that every
+// wave owns whole 32-column blocks.  Each wave writes its outputs (160 bytes per row either way)
+// to its own LDS region first and then to memory as 16-byte pieces, consecutive lanes along a
+// row: the MFMA layout would give 16 rows x 32 bytes (bf16) or 16 bytes (FP8) per store, which
+// measured about 1.7 times slower than row pieces for these outputs.  The exception is the FP8
+// copy at KD = 64, whose 160-column weight panel leaves no registers for the staging (it spilled
+// and ran 14 % slower): it stores in the MFMA layout.
 template <int KD, bool Q8>
 __global__ __launch_bounds__(kThreads, 2) void gemm_shallow_kernel(const bf16_t *__restrict__ A, int lda,
                                                                 const bf16_t *__restrict__ B, int ldb,
@@ -317,6 +329,15 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_shallow_kernel(const bf16_t 
     const int fr = lane & 15, fg = lane >> 4, fk = fg * 8;
     __shared__ __attribute__((aligned(16))) float Ptab[kPhiLdsFloats];
     copy_phi_table(Ptab, t);
+    // the wave's staging rows: 160 bytes of outputs, stride 176 (16-byte aligned)
+    constexpr bool kStage = !(Q8 && KD == 64);
+    constexpr int kRowB = 160, kStrideB = kRowB + 16, kPieces = WMq * kRowB / 16;
+    static_assert((Q8 ? WNq : 2 * WNq) == kRowB && kPieces % 64 == 0, "staging layout");
+    __shared__ __attribute__((aligned(16))) uint8_t Stage[kStage ? 4 * WMq * kStrideB : 16];
+    uint8_t *stg = Stage + w * (WMq * kStrideB);
+    uint8_t *const Cb = reinterpret_cast<uint8_t *>(C);
+    const int col0b = Q8 ? col0 : 2 * (col0 + wn * WNq);  // byte column of the wave's sub-tile
+    const int64_t ldcb = Q8 ? ldc : 2 * int64_t(ldc);
 
     bf16x8 bfr[KS][TNq];
 #pragma unroll
@@ -357,7 +378,7 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_shallow_kernel(const bf16_t 
                 for (int s = 0; s < KS; ++s)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bfr[s][j], af[s][i], acc[i][j], 0, 0, 0);
             }
-        const int64_t row0 = int64_t(tm) * BM + wm * WMq + fr;
+        const int64_t rowt = int64_t(tm) * BM + wm * WMq;  // first row of the wave's sub-tile
         if constexpr (Q8) {
 #pragma unroll
             for (int i = 0; i < TMq; ++i)
@@ -369,22 +390,45 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_shallow_kernel(const bf16_t 
                         v0[r] = gelu_tab(v0[r], Ptab);
                         v1[r] = gelu_tab(v1[r], Ptab);
                     }
-                    store_fp8_block(v0, v1, reinterpret_cast<uint8_t *>(C), S, row0 + i * 16, ldc, sst,
-                                    col0 + 32 * q, fg);
+                    if constexpr (kStage) {
+                        uint32_t w0, w1;
+                        quant_fp8_block(v0, v1, S, rowt + i * 16 + fr, sst, col0 + 32 * q, fg, w0, w1);
+                        uint8_t *p = stg + (i * 16 + fr) * kStrideB + 32 * q + 4 * fg;
+                        *reinterpret_cast<uint32_t *>(p) = w0;
+                        *reinterpret_cast<uint32_t *>(p + 16) = w1;
+                    } else {
+                        store_fp8_block(v0, v1, Cb, S, rowt + i * 16 + fr, ldc, sst, col0 + 32 * q, fg);
+                    }
                 }
         } else {
 #pragma unroll
             for (int j = 0; j < TNq; ++j) {
-                const int col = col0 + wn * WNq + j * 16 + fg * 4;
 #pragma unroll
                 for (int i = 0; i < TMq; ++i) {
-                    const int64_t row = row0 + i * 16;
                     floatx4 v = acc[i][j] + bc[j];
 #pragma unroll
                     for (int r = 0; r < 4; ++r) v[r] = gelu_tab(v[r], Ptab);
-                    *reinterpret_cast<bf16x4 *>(C + row * ldc + col) = to_bf16x4(v);
+                    *reinterpret_cast<bf16x4 *>(stg + (i * 16 + fr) * kStrideB + 2 * (j * 16 + fg * 4)) =
+                        to_bf16x4(v);
                 }
             }
+        }
+        if constexpr (kStage) {
+            // the wave's own LDS region: its LDS operations execute in order, so the reads below
+            // see the writes above, and the next tile's writes follow these reads; the fences keep
+            // the compiler from moving LDS accesses across
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+            for (int p0 = 0; p0 < kPieces; p0 += 64) {
+                const int c = p0 + lane, r = c / (kRowB / 16), ch = c % (kRowB / 16);
+                const u32x4 v = *reinterpret_cast<const u32x4 *>(stg + r * kStrideB + ch * 16);
+                *reinterpret_cast<u32x4 *>(Cb + (rowt + r) * ldcb + col0b + ch * 16) = v;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         }
     }
 }
@@ -545,6 +589,9 @@ df_status launch_shallow(const bf16_t *A, int lda, const bf16_t *B, int ldb, con
     const int64_t tm = M / BM;
     const int tn = N / BN;
     if (tm > 0x7fffffff) return fail(DF_E_UNSUPPORTED, "gemm: too many row tiles");
+    // the outputs are written as 16-byte row pieces
+    if ((reinterpret_cast<uintptr_t>(C) & 15) || (S ? ldc % 16 : ldc % 8))
+        return fail(DF_E_INVALID, "gemm: the output rows must be 16-byte aligned");
     const int G = int(std::max<int64_t>(1, std::min<int64_t>(tm, std::max(1, 512 / tn))));
     const dim3 g = dim3(unsigned(int64_t(G) * tn)), b = dim3(kThreads);
 #define DF_SHALLOW(KD, Q)                                                                                        \
