@@ -309,9 +309,9 @@ __device__ __forceinline__ void store_fp8_block(floatx4 v0, floatx4 v1, uint8_t 
 // wave owns whole 32-column blocks.  Each wave writes its outputs (160 bytes per row either way)
 // to its own LDS region first and then to memory as 16-byte pieces, consecutive lanes along a
 // row: the MFMA layout would give 16 rows x 32 bytes (bf16) or 16 bytes (FP8) per store, which
-// measured about 1.7 times slower than row pieces for these outputs.  The exception is the FP8
-// copy at KD = 64, whose 160-column weight panel leaves no registers for the staging (it spilled
-// and ran 14 % slower): it stores in the MFMA layout.
+// measured about 1.7 times slower than row pieces for these outputs.  In the FP8 copy the bias
+// row is read from LDS in the epilogue: held in registers (40 of them next to a 160-column weight
+// panel) it left none for the staging at KD = 64, which then spilled and ran 14 % slower.
 template <int KD, bool Q8>
 __global__ __launch_bounds__(kThreads, 2) void gemm_shallow_kernel(const bf16_t *__restrict__ A, int lda,
                                                                 const bf16_t *__restrict__ B, int ldb,
@@ -330,10 +330,12 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_shallow_kernel(const bf16_t 
     __shared__ __attribute__((aligned(16))) float Ptab[kPhiLdsFloats];
     copy_phi_table(Ptab, t);
     // the wave's staging rows: 160 bytes of outputs, stride 176 (16-byte aligned)
-    constexpr bool kStage = !(Q8 && KD == 64);
     constexpr int kRowB = 160, kStrideB = kRowB + 16, kPieces = WMq * kRowB / 16;
     static_assert((Q8 ? WNq : 2 * WNq) == kRowB && kPieces % 64 == 0, "staging layout");
-    __shared__ __attribute__((aligned(16))) uint8_t Stage[kStage ? 4 * WMq * kStrideB : 16];
+    __shared__ __attribute__((aligned(16))) uint8_t Stage[4 * WMq * kStrideB];
+    __shared__ __attribute__((aligned(16))) float Bias[Q8 ? BN : 4];
+    if (Q8 && t < BN / 4)
+        reinterpret_cast<floatx4 *>(Bias)[t] = reinterpret_cast<const floatx4 *>(bias + col0)[t];
     uint8_t *stg = Stage + w * (WMq * kStrideB);
     uint8_t *const Cb = reinterpret_cast<uint8_t *>(C);
     const int col0b = Q8 ? col0 : 2 * (col0 + wn * WNq);  // byte column of the wave's sub-tile
@@ -345,10 +347,12 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_shallow_kernel(const bf16_t 
 #pragma unroll
         for (int j = 0; j < TNq; ++j)
             bfr[s][j] = *reinterpret_cast<const bf16x8 *>(B + int64_t(col0 + wn * WNq + j * 16 + fr) * ldb + s * 32 + fk);
-    floatx4 bc[TNq];
+    floatx4 bc[Q8 ? 1 : TNq];  // the bf16 path holds its 80-column bias slice in registers
+    if constexpr (!Q8) {
 #pragma unroll
-    for (int j = 0; j < TNq; ++j)
-        bc[j] = *reinterpret_cast<const floatx4 *>(bias + col0 + wn * WNq + j * 16 + fg * 4);
+        for (int j = 0; j < TNq; ++j)
+            bc[j] = *reinterpret_cast<const floatx4 *>(bias + col0 + wn * WNq + j * 16 + fg * 4);
+    }
 
     auto load_a = [&](int tm, bf16x8 (&af)[KS][TMq]) {
         const int64_t r0 = int64_t(tm) * BM + wm * WMq + fr;
@@ -384,21 +388,18 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_shallow_kernel(const bf16_t 
             for (int i = 0; i < TMq; ++i)
 #pragma unroll
                 for (int q = 0; q < TNq / 2; ++q) {
-                    floatx4 v0 = acc[i][2 * q] + bc[2 * q], v1 = acc[i][2 * q + 1] + bc[2 * q + 1];
+                    const floatx4 *bl = reinterpret_cast<const floatx4 *>(Bias + 32 * q + fg * 4);
+                    floatx4 v0 = acc[i][2 * q] + bl[0], v1 = acc[i][2 * q + 1] + bl[4];
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         v0[r] = gelu_tab(v0[r], Ptab);
                         v1[r] = gelu_tab(v1[r], Ptab);
                     }
-                    if constexpr (kStage) {
-                        uint32_t w0, w1;
-                        quant_fp8_block(v0, v1, S, rowt + i * 16 + fr, sst, col0 + 32 * q, fg, w0, w1);
-                        uint8_t *p = stg + (i * 16 + fr) * kStrideB + 32 * q + 4 * fg;
-                        *reinterpret_cast<uint32_t *>(p) = w0;
-                        *reinterpret_cast<uint32_t *>(p + 16) = w1;
-                    } else {
-                        store_fp8_block(v0, v1, Cb, S, rowt + i * 16 + fr, ldc, sst, col0 + 32 * q, fg);
-                    }
+                    uint32_t w0, w1;
+                    quant_fp8_block(v0, v1, S, rowt + i * 16 + fr, sst, col0 + 32 * q, fg, w0, w1);
+                    uint8_t *p = stg + (i * 16 + fr) * kStrideB + 32 * q + 4 * fg;
+                    *reinterpret_cast<uint32_t *>(p) = w0;
+                    *reinterpret_cast<uint32_t *>(p + 16) = w1;
                 }
         } else {
 #pragma unroll
@@ -413,23 +414,21 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_shallow_kernel(const bf16_t 
                 }
             }
         }
-        if constexpr (kStage) {
-            // the wave's own LDS region: its LDS operations execute in order, so the reads below
-            // see the writes above, and the next tile's writes follow these reads; the fences keep
-            // the compiler from moving LDS accesses across
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        // the wave's own LDS region: its LDS operations execute in order, so the reads below see
+        // the writes above, and the next tile's writes follow these reads; the fences keep the
+        // compiler from moving LDS accesses across
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-            for (int p0 = 0; p0 < kPieces; p0 += 64) {
-                const int c = p0 + lane, r = c / (kRowB / 16), ch = c % (kRowB / 16);
-                const u32x4 v = *reinterpret_cast<const u32x4 *>(stg + r * kStrideB + ch * 16);
-                *reinterpret_cast<u32x4 *>(Cb + (rowt + r) * ldcb + col0b + ch * 16) = v;
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int p0 = 0; p0 < kPieces; p0 += 64) {
+            const int c = p0 + lane, r = c / (kRowB / 16), ch = c % (kRowB / 16);
+            const u32x4 v = *reinterpret_cast<const u32x4 *>(stg + r * kStrideB + ch * 16);
+            *reinterpret_cast<u32x4 *>(Cb + (rowt + r) * ldcb + col0b + ch * 16) = v;
         }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
 }
 
