@@ -115,15 +115,24 @@ __global__ __launch_bounds__(kPreThreads) void pre_kernel(DnnDevParams prm, int6
     }
 }
 
-// output layer + stage 3.  Each wavefront takes 64 consecutive cells: the output layer
-// u = W h (bf16 operands, fp32 sums) runs on the matrix cores as 16 x 16 x 32 MFMAs with the
-// weight rows (zero beyond the K outputs) as the first operand, so that lane l ends with outputs
-// 4 (l / 16) + r of cell l % 16 of each 16-cell tile; the products go through LDS to one lane per
-// cell, which then runs stage 3 in FP64.  The activation rows are read as 16-byte fragments, 16
-// rows x 64 contiguous bytes per load.
+// output layer + stage 3.  The output layer u = W h (bf16 operands, fp32 sums) runs on the matrix
+// cores as 16 x 16 x 32 MFMAs over groups of 64 consecutive cells, with the weight rows (zero
+// beyond the K outputs) as the first operand, so that lane l ends with outputs 4 (l / 16) + r of
+// cell l % 16 of each 16-cell tile; the products go through LDS to one lane per cell, which then
+// runs stage 3 in FP64.  The activation rows are read as 16-byte fragments, 16 rows x 64
+// contiguous bytes per load.  With at most 16 outputs (one output tile) the four waves of a block
+// share one group of 64 cells and split the reduction, wave w taking the 32-deep steps w, w + 4,
+// ...; their partial sums meet in LDS and are added in wave order, and wave 0 runs stage 3.  The
+// chain of dependent load-and-product steps of a wave is then a quarter as long, and a launch has
+// four times as many waves (65,536 cells: 4,096 instead of 1,024).  With more outputs each wave
+// takes its own 64 cells: there stage 3 holds the most registers and the longest chain.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 constexpr int kPostThreads = 256;
+template <int K>
+constexpr int post_ksplit() { return (K + 15) / 16 == 1 ? 4 : 1; }
+template <int K>
+constexpr int post_cells_per_block() { return kPostThreads / post_ksplit<K>(); }
 
 template <int K>
 __global__ __launch_bounds__(kPostThreads) void post_kernel(DnnDevParams prm, MechDev m, int64_t n, int64_t ld,
@@ -137,10 +146,11 @@ __global__ __launch_bounds__(kPostThreads) void post_kernel(DnnDevParams prm, Me
                                                             int fallback) {
     constexpr int NT = (K + 15) / 16;          // 16-output tiles
     constexpr int NP = (K % 2) ? K : K + 1;    // LDS row stride in floats (odd: conflict-free reads)
+    constexpr int KS = post_ksplit<K>();       // waves sharing a group of 64 cells
     __shared__ float su[kPostThreads / 64][64 * NP];
     const int lane = int(threadIdx.x) & 63, wv = int(threadIdx.x) >> 6;
     const int fr = lane & 15, fg = lane >> 4;
-    const int64_t cell0 = int64_t(blockIdx.x) * kPostThreads + int64_t(wv) * 64;
+    const int64_t cell0 = int64_t(blockIdx.x) * post_cells_per_block<K>() + (KS == 1 ? int64_t(wv) * 64 : 0);
     {
         floatx4 acc[4][NT];
 #pragma unroll
@@ -148,7 +158,7 @@ __global__ __launch_bounds__(kPostThreads) void post_kernel(DnnDevParams prm, Me
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = floatx4{0.f, 0.f, 0.f, 0.f};
         const bf16x8 zero = {};
-        for (int k0 = 0; k0 < k_in; k0 += 32) {
+        for (int k0 = (KS == 1 ? 0 : 32 * wv); k0 < k_in; k0 += 32 * KS) {
             bf16x8 wf[NT], hf[4];
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
@@ -177,6 +187,7 @@ __global__ __launch_bounds__(kPostThreads) void post_kernel(DnnDevParams prm, Me
                 }
     }
     __syncthreads();
+    if (KS > 1 && wv > 0) return;  // wave 0 finishes the shared group
     const int64_t i = cell0 + lane;
     if (i >= n) return;
     const int fl = flag[i];
@@ -187,7 +198,11 @@ __global__ __launch_bounds__(kPostThreads) void post_kernel(DnnDevParams prm, Me
     }
     float u[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) u[k] = su[wv][lane * NP + k];
+    for (int k = 0; k < K; ++k) {
+        u[k] = su[wv][lane * NP + k];
+#pragma unroll
+        for (int w = 1; w < KS; ++w) u[k] += su[w][lane * NP + k];
+    }
     // ---- stage 3, FP64
     const double T0 = T[i], iT0 = 1.0 / T0;
     // 1/lambda as an exact small integer (lambda = 0.1 gives 10): the power by squaring
@@ -404,7 +419,8 @@ df_status launch_dnn_k(const df_dnn *d, const df_mech *m, int64_t n, int64_t ld,
         in_ld = out_ld;
     }
     const DnnLayer &Lo = d->layers.back();
-    hipLaunchKernelGGL(post_kernel<K>, dim3(unsigned((n + kPostThreads - 1) / kPostThreads)), dim3(kPostThreads), 0, s,
+    constexpr int kCpb = post_cells_per_block<K>();
+    hipLaunchKernelGGL(post_kernel<K>, dim3(unsigned((n + kCpb - 1) / kCpb)), dim3(kPostThreads), 0, s,
                        d->prm, m->dev, n, ld, dt, in, in_ld, Lo.W, Lo.b, Lo.k_pad, flag, p, T, Y, rr, status,
                        o.renormalise, idx, cnt, o.fallback);
     e = hipGetLastError();
