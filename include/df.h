@@ -80,9 +80,13 @@ typedef struct {
                           wavefront (64 lanes) per cell (species count <= 63), 4 thirty-two
                           lanes per cell (as 2, the second 16 lanes taking half of the rate
                           constants: a shorter sub-step for stiff cells, half the cells per wave;
-                          16 lanes where the reaction slots do not divide in two); automatic takes
-                          16 lanes where compiled, else one cell per lane, else a wavefront.
-                          Mappings 2 and 4 give the same bits */
+                          16 lanes where the reaction slots do not divide in two), 5 thirty-two
+                          lanes for the 512 cells at the head of the cost order (the stiffest,
+                          whose sub-step chains set the launch's time) and sixteen for the rest
+                          (needs the workspace, which holds the order; as 2 without it);
+                          automatic takes 5 where the reaction slots divide in two, else 16 lanes,
+                          where compiled, else one cell per lane, else a wavefront.  Mappings 2, 4
+                          and 5 give the same bits */
     int32_t schedule;  /* 0 (default) or 1: static, one launch that gives each lane (or group of
                           16 lanes) one cell; 2: persistent work queue (needs the workspace):
                           cells sorted by estimated cost (temperature, then step length) are

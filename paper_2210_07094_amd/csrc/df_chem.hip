@@ -56,11 +56,13 @@ df_status launch_chem_step(const MechDev &m, const StepArgs &a, int mapping, con
                            const int32_t *dcount, hipStream_t stream) {
     if (a.n == 0) return DF_OK;
     // mapping 0 picks 16 lanes per cell whenever a kernel is compiled for K: one sub-step
-    // then takes a fraction of the latency, which bounds a stiff cell's step time
+    // then takes a fraction of the latency, which bounds a stiff cell's step time; with the cost
+    // order (and reaction slots that divide in two) the head of the order takes 32 lanes, the
+    // head variant (mapping 5), whose stiffest cells then finish sooner
     if (mapping == 3) return launch_chem_wave(m, a, cidx, dcount, stream);
-    if (mapping == 2 || mapping == 4 || (mapping == 0 && chem_coop_supported(m)))
+    if (mapping == 2 || mapping == 4 || mapping == 5 || (mapping == 0 && chem_coop_supported(m)))
         return launch_chem_coop(m, a, CellQueue{cidx, dcount, nullptr, nullptr, nullptr, 0}, stream,
-                                mapping == 4 ? 2 : 1);
+                                mapping == 4 ? 2 : (mapping == 5 || mapping == 0 ? 3 : 1));
     if (a.n > int64_t(64) * 0x7fffffff) return fail(DF_E_UNSUPPORTED, "df_chem_step: too many cells for one launch");
     switch (m.K) {
 #define DF_CASE(k) \

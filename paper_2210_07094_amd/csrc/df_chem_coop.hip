@@ -720,20 +720,20 @@ __device__ bool group_attempt(const StepArgs &a, const typename Coop<K, RPL, H>:
     return false;
 }
 
-// Static schedule: cell s of the launch (four 16-lane or two 32-lane cells per block) is cell
-// cidx[s] (or s).
+// Static schedule: the block's cells are the slots slot0, slot0 + 1, ... (four 16-lane or two
+// 32-lane cells per block), and slot s is cell cidx[s] (or s).
 template <int K, int RPL, int H>
-__global__ __launch_bounds__(64) void chem_coop_kernel(MechDev mg, StepArgs a, CellQueue q) {
+__device__ __forceinline__ void coop_static_block(const MechDev &mg, const StepArgs &a, const CellQueue &q,
+                                                  int64_t slot0, double *lds) {
     using C = Coop<K, RPL, H>;
-    extern __shared__ double lds[];
     const int lane = threadIdx.x;
     const int r = lane & (G - 1);        // row of the cell held by the lane (both halves)
     const int rl = lane & (C::GL - 1);   // lane within the cell
     const int64_t limit = q.dcount ? int64_t(*q.dcount) : a.n;
-    if (int64_t(blockIdx.x) * C::CPB >= limit) return;  // whole block idle (e.g. no fallback cells)
+    if (slot0 >= limit) return;  // whole block idle (e.g. no fallback cells)
     const typename C::Tab tb = stage_tables<K, RPL, H>(mg, lds, lane);
     double *sh = lds + C::tBytes / 8 + (lane / C::GL) * C::kStride;
-    const int64_t slot = int64_t(blockIdx.x) * C::CPB + lane / C::GL;
+    const int64_t slot = slot0 + lane / C::GL;
     if (slot >= limit) return;  // the lanes of a cell leave together
     init_cell_region<K, RPL, H>(sh, r);
     int li[kCoopList];
@@ -742,6 +742,28 @@ __global__ __launch_bounds__(64) void chem_coop_kernel(MechDev mg, StepArgs a, C
     GroupTask<K> c;
     bool have = group_load<K>(a, tb.sp, r, q.cidx ? int64_t(q.cidx[slot]) : slot, c);
     while (have) have = !group_attempt<K, RPL, H>(a, tb, sh, r, rl, li, lc, c);
+}
+
+template <int K, int RPL, int H>
+__global__ __launch_bounds__(64) void chem_coop_kernel(MechDev mg, StepArgs a, CellQueue q) {
+    extern __shared__ double lds[];
+    coop_static_block<K, RPL, H>(mg, a, q, int64_t(blockIdx.x) * Coop<K, RPL, H>::CPB, lds);
+}
+
+// Static schedule with a 32-lane head: blocks [0, head_blocks) take the first 2 head_blocks slots of
+// the cost order as 32-lane cells, the other blocks the rest as 16-lane cells.  The head of the
+// order holds the stiffest cells, whose chains of sub-steps set the launch's time; an attempt
+// costs less at 32 lanes, while the bulk keeps the layout that needs half as many waves.  The
+// two layouts give the same results bit for bit.
+template <int K, int RPL>
+__global__ __launch_bounds__(64) void chem_coop_head_kernel(MechDev mg, StepArgs a, CellQueue q, int head_blocks) {
+    extern __shared__ double lds[];
+    constexpr int C2 = Coop<K, RPL, 2>::CPB, C1 = Coop<K, RPL, 1>::CPB;
+    const int b = int(blockIdx.x);
+    if (b < head_blocks)
+        coop_static_block<K, RPL, 2>(mg, a, q, int64_t(b) * C2, lds);
+    else
+        coop_static_block<K, RPL, 1>(mg, a, q, int64_t(head_blocks) * C2 + int64_t(b - head_blocks) * C1, lds);
 }
 
 // Queue schedule: a persistent grid.  Blocks [0, head_blocks) run four 16-lane groups that
@@ -843,13 +865,39 @@ static df_status launch_coop_kh(const MechDev &m, const StepArgs &a, const CellQ
     return DF_OK;
 }
 
-// 32-lane cells when asked for and the reaction slots divide between two halves (the taped
-// step keeps the 16-lane layout of the adjoint's tape writer)
+// cells of the cost order's head that the head variant runs at 32 lanes (the hot-kernel field's
+// cells within half of the longest chain of sub-steps are its 538 hottest)
+constexpr int64_t kCoopHeadCells = 512;
+
+template <int K, int RPL>
+static df_status launch_coop_head(const MechDev &m, const StepArgs &a, const CellQueue &q, hipStream_t stream) {
+    using C1 = Coop<K, RPL, 1>;
+    using C2 = Coop<K, RPL, 2>;
+    const int64_t head = a.n < kCoopHeadCells ? a.n : kCoopHeadCells;
+    const int64_t hb = (head + C2::CPB - 1) / C2::CPB;
+    const int64_t rest = a.n - hb * C2::CPB;
+    const int64_t blocks = hb + (rest > 0 ? (rest + C1::CPB - 1) / C1::CPB : 0);
+    if (blocks > 0x7fffffff) return fail(DF_E_UNSUPPORTED, "chem_step: too many cells for one launch");
+    const size_t lds = C1::lds_bytes() > C2::lds_bytes() ? C1::lds_bytes() : C2::lds_bytes();
+    hipLaunchKernelGGL((chem_coop_head_kernel<K, RPL>), dim3(unsigned(blocks)), dim3(64), lds, stream, m, a, q,
+                       int(hb));
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(DF_E_HIP, std::string("chem_step launch: ") + hipGetErrorString(e));
+    return DF_OK;
+}
+
+// halves: 1 = 16-lane cells, 2 = 32-lane cells, 3 = 32-lane cells for the head of the cost order
+// and 16-lane cells for the rest.  32 lanes only where the reaction slots divide between two
+// halves; the taped step keeps the 16-lane layout of the adjoint's tape writer, and the head
+// variant needs the cost order (and no fallback list)
 template <int K, int RPL>
 static df_status launch_coop_k(const MechDev &m, const StepArgs &a, const CellQueue &q, hipStream_t stream,
                                int halves) {
     if constexpr (RPL % 2 == 0) {
         if (halves == 2 && !a.tape) return launch_coop_kh<K, RPL, 2>(m, a, q, stream);
+        if (halves == 3 && !a.tape && q.cidx && !q.dcount &&
+            Coop<K, RPL, 1>::lds_bytes() <= kCoopMaxLds && Coop<K, RPL, 2>::lds_bytes() <= kCoopMaxLds)
+            return launch_coop_head<K, RPL>(m, a, q, stream);
     }
     return launch_coop_kh<K, RPL, 1>(m, a, q, stream);
 }

@@ -452,10 +452,10 @@ static void pack_wave_tables(const HostMech &m, const CoopTables &ct, WaveTables
 
 df_status validate_chem_opts(const df_chem_opts &o) {
     if (!(o.rtol > 0 && o.rtol < 1) || !(o.atol_T > 0) || !(o.atol_Y > 0) || !(o.h_min > 0) || o.max_steps < 1 ||
-        o.mapping < 0 || o.mapping > 4 || o.schedule < 0 || o.schedule > 2 || o.coop_blocks < -1 ||
+        o.mapping < 0 || o.mapping > 5 || o.schedule < 0 || o.schedule > 2 || o.coop_blocks < -1 ||
         !std::isfinite(o.atol_T) || !std::isfinite(o.atol_Y) || !std::isfinite(o.h_min))
         return fail(DF_E_INVALID, "df_chem_opts: need 0 < rtol < 1, atol_T, atol_Y, h_min > 0 and finite, "
-                                  "max_steps >= 1, mapping in {0, 1, 2, 3, 4}, schedule in {0, 1, 2}, coop_blocks >= -1");
+                                  "max_steps >= 1, mapping in {0, 1, 2, 3, 4, 5}, schedule in {0, 1, 2}, coop_blocks >= -1");
     return DF_OK;
 }
 

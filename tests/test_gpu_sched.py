@@ -62,6 +62,7 @@ SCHEDULES = [
     ("static, one cell per lane", dict(schedule=1, mapping=1)),
     ("static, 16 lanes per cell", dict(schedule=1, mapping=2)),
     ("static, 32 lanes per cell", dict(schedule=1, mapping=4)),
+    ("static, 32 lanes for the head of the cost order, 16 for the rest", dict(schedule=1, mapping=5)),
     ("queue, all waves 16-lane groups", dict(schedule=2, coop_blocks=0)),
     ("queue, 8 waves 16-lane groups from the start", dict(schedule=2, coop_blocks=8)),
     ("queue, every wave first takes cold cells per lane", dict(schedule=2, coop_blocks=-1)),
@@ -104,7 +105,7 @@ def test_unusable_step_lengths(h2_path, h2_mech):
 def test_queue_equals_static_bitwise(h2_path, h2_mech):
     """The 16-lane body does the same arithmetic for a cell whichever group takes it, and the
     32-lane layout (the second 16 lanes taking half the rate constants) the same as the 16-lane
-    one."""
+    one, also when only the head of the cost order (512 of the 4096 cells) takes it."""
     import paper_2210_07094_amd as df
     gm = df.Mechanism(h2_path)
     f = fields.hot_kernel_field_2d(h2_mech, nx=64, ny=64)
@@ -113,9 +114,13 @@ def test_queue_equals_static_bitwise(h2_path, h2_mech):
     b = _run(gm, f, df.chem_opts(schedule=2, coop_blocks=0))
     c = _run(gm, f, df.chem_opts(schedule=2, coop_blocks=5))
     d = _run(gm, f, df.chem_opts(schedule=1, mapping=4))
+    e = _run(gm, f, df.chem_opts(schedule=1, mapping=5))
+    z = _run(gm, f, df.chem_opts(schedule=1, mapping=0))
     for k in ("status", "n_acc", "n_rej", "T", "Y"):
         assert np.array_equal(a[k], b[k]), k
         assert np.array_equal(a[k], d[k]), k
+        assert np.array_equal(a[k], e[k]), k
+        assert np.array_equal(a[k], z[k]), k
     # with five group waves the cold cells go one per lane first (rounding may differ there);
     # the hot cells go to 16-lane groups in every schedule: bitwise equal results
     assert np.array_equal(a["status"], c["status"])
