@@ -8,9 +8,11 @@
 // LDS 32 or 64 deep in K (64 where K allows it) with the next stage's global
 // loads issued before the current stage's MFMAs.  The MFMAs take the weight
 // fragment as their first operand, so that each lane ends with four consecutive
-// outputs of one row: the epilogue converts them with one packed bf16 conversion
-// pair and writes them with one 8-byte store.  Tiles sharing the same rows of A
-// are mapped to the same XCD so the A panel is fetched into that XCD's L2 once.
+// outputs of one row, converted with one packed bf16 conversion pair: the
+// training epilogues write them with one 8-byte store, the inference epilogue
+// (GELU from an LDS table) stages them per wave in LDS and writes 16-byte row
+// pieces.  Tiles sharing the same rows of A are mapped to the same XCD so the A
+// panel is fetched into that XCD's L2 once.
 #include <algorithm>
 #include <cmath>
 
@@ -72,7 +74,7 @@ __device__ __forceinline__ float gelu_grad(float x) {
 // float32 evaluation the result is within about 1e-7 of x Phi(x), as close as gelu_erfc, so that
 // the bf16 rounding that follows differs from that of the exact value as rarely.  Beyond the table
 // Phi is 0 (x < -6 - 12/256, where the exact value is below 7e-10) or 1 (x >= 6).  NaN stays NaN;
-// GELU(+inf) = +inf and GELU(-inf) = NaN, as x Phi(x) gives.  About 10 VALU instructions and one
+// GELU(+inf) = +inf and GELU(-inf) = NaN, as x Phi(x) gives.  About 11 VALU instructions and one
 // 16-byte LDS read per value, against about 28 instruction slots for gelu_erfc (reciprocal and
 // exponential at a quarter of the rate).
 constexpr int kPhiLdsFloats = 4 * kPhiEntries;  // 4,128 bytes of LDS per block
