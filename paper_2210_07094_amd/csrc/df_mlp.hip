@@ -504,6 +504,22 @@ __global__ __launch_bounds__(kThreads, 2) void gemm_fp8_kernel(const uint8_t *__
     uint32_t rs = 0;
     const u32x4 z4 = {0u, 0u, 0u, 0u};
     auto load = [&](int k0) {
+        if (k0 + KD8 <= K) {
+            // a whole stage within K (the same for the block): no guards, and the four block
+            // scales of a row as one little-endian word (4-byte aligned: sst % 16 = 0, k0 % 128 = 0)
+#pragma unroll
+            for (int i = 0; i < kAPer; ++i) {
+                const int c = t + i * kThreads, r = c / kCh, k = k0 + (c % kCh) * 16;
+                ra[i] = *reinterpret_cast<const u32x4 *>(A8 + (row0 + r) * lda + k);
+            }
+#pragma unroll
+            for (int i = 0; i < kBPer; ++i) {
+                const int c = t + i * kThreads, r = c / kCh, k = k0 + (c % kCh) * 16;
+                rb[i] = *reinterpret_cast<const u32x4 *>(W8 + int64_t(col0 + r) * ldb + k);
+            }
+            if (t < BM) rs = *reinterpret_cast<const uint32_t *>(SA + (row0 + t) * sst + k0 / kFp8Block);
+            return;
+        }
 #pragma unroll
         for (int i = 0; i < kAPer; ++i) {
             const int c = t + i * kThreads, r = c / kCh, k = k0 + (c % kCh) * 16;
@@ -722,6 +738,7 @@ df_status launch_gemm_fp8(const uint8_t *A8, int lda, const uint8_t *S, int sst,
         sst < K / kFp8Block || (SC && (ldc % 16 || sstc % 16 || sstc < N / kFp8Block)))
         return fail(DF_E_INVALID, "gemm fp8: shapes must be multiples of the tile sizes (rows of 16 bytes)");
     if (!A8 || !S || !W8 || !wexp) return fail(DF_E_INVALID, "gemm fp8: null activation, scale, weight or exponent array");
+    if (reinterpret_cast<uintptr_t>(S) & 3) return fail(DF_E_INVALID, "gemm fp8: the scale array must be 4-byte aligned");
     if ((reinterpret_cast<uintptr_t>(C) & 15) || ldc % 8)  // outputs written as 16-byte row pieces
         return fail(DF_E_INVALID, "gemm fp8: the output rows must be 16-byte aligned");
     if (M == 0) return DF_OK;
