@@ -131,6 +131,21 @@ def test_queue_equals_static_bitwise(h2_path, h2_mech):
     assert np.array_equal(a["Y"][:, hot], c["Y"][:, hot])
 
 
+@pytest.mark.parametrize("n", [300, 1])
+def test_head_variant_smaller_than_its_head(h2_path, h2_mech, n):
+    """Fewer cells than the 32-lane head of the cost order (512): every cell is a 32-lane cell and
+    no 16-lane block runs; same bits as 16 lanes per cell."""
+    import paper_2210_07094_amd as df
+    gm = df.Mechanism(h2_path)
+    f = _cells(h2_mech, n=n, seed=17)
+    print(f"case: head variant, {n} cells", flush=True)
+    a = _run(gm, f, df.chem_opts(schedule=1, mapping=2))
+    e = _run(gm, f, df.chem_opts(schedule=1, mapping=5))
+    for k in ("status", "n_acc", "n_rej", "T", "Y"):
+        assert np.array_equal(a[k], e[k]), k
+    assert np.all(a["status"] == df.CELL_OK)
+
+
 def test_queue_needs_workspace(h2_path, h2_mech):
     import paper_2210_07094_amd as df
     torch = _torch()
