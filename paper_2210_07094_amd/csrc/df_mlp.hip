@@ -8,10 +8,10 @@
 // LDS 32 or 64 deep in K (64 where K allows it) with the next stage's global
 // loads issued before the current stage's MFMAs.  The MFMAs take the weight
 // fragment as their first operand, so that each lane ends with four consecutive
-// outputs of one row, converted with one packed bf16 conversion pair: the
-// training epilogues write them with one 8-byte store, the inference epilogue
-// (GELU from an LDS table) stages them per wave in LDS and writes 16-byte row
-// pieces.  Tiles sharing the same rows of A are mapped to the same XCD so the A
+// outputs of one row, converted with one packed bf16 conversion pair: the GELU
+// epilogues (inference, with GELU from an LDS table, and the training forward and
+// backward) stage them per wave in LDS and write 16-byte row pieces; the linear
+// epilogue writes them with one 8-byte store.  Tiles sharing the same rows of A are mapped to the same XCD so the A
 // panel is fetched into that XCD's L2 once.
 #include <algorithm>
 #include <cmath>
@@ -230,51 +230,70 @@ __global__ __launch_bounds__(kThreads, KD == 32 ? 3 : 1) void gemm_kernel(const 
 
     // epilogue: with the weights as the first MFMA operand, lane l holds row (l % 16) and the four
     // columns 4 * (l / 16) + r of each 16 x 16 tile
-    if constexpr (EPI == kEpiGelu) {
-        // staged through the operand buffers, in two halves of 32 rows per wave
+    if constexpr (EPI != kEpiLinear) {
+        // staged through the operand buffers, in two halves of 32 rows per wave; the training
+        // forward stages its pre-activations (P) first and then its outputs
         static_assert(4 * 32 * kStgStrideB <= (BM + BN) * LDKD * 2 && WN * 2 == kStgRowB, "staging");
         __syncthreads();  // every wave has read its last operand fragments
         uint8_t *const stg = reinterpret_cast<uint8_t *>(ABs) + w * (32 * kStgStrideB);
         const int64_t ldb_c = 2 * int64_t(ldc);
-        uint8_t *const dst = reinterpret_cast<uint8_t *>(C) + (row0 + wm * WM) * ldb_c + 2 * (col0 + wn * WN);
+        const int64_t off0 = (row0 + wm * WM) * ldb_c + 2 * (col0 + wn * WN);
+        const int fc = (lane >> 4) * 4;  // the lane's first column in a 16 x 16 tile
 #pragma unroll
         for (int hf = 0; hf < 2; ++hf) {
+            floatx4 v[TN][2];
 #pragma unroll
             for (int j = 0; j < TN; ++j) {
-                const floatx4 bc = *reinterpret_cast<const floatx4 *>(bias + col0 + wn * WN + j * 16 + (lane >> 4) * 4);
+                const floatx4 bc = (EPI == kEpiGeluGrad)
+                                       ? floatx4{0.f, 0.f, 0.f, 0.f}
+                                       : *reinterpret_cast<const floatx4 *>(bias + col0 + wn * WN + j * 16 + fc);
+#pragma unroll
+                for (int ii = 0; ii < 2; ++ii) v[j][ii] = acc[2 * hf + ii][j] + bc;
+            }
+            if constexpr (EPI == kEpiGeluSave) {
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+#pragma unroll
+                    for (int ii = 0; ii < 2; ++ii)
+                        *reinterpret_cast<bf16x4 *>(stg + (ii * 16 + fr) * kStgStrideB + 2 * (j * 16 + fc)) =
+                            to_bf16x4(v[j][ii]);
+                stage_flush<32>(stg, reinterpret_cast<uint8_t *>(P) + off0 + hf * 32 * ldb_c, ldb_c, lane);
+            }
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
 #pragma unroll
                 for (int ii = 0; ii < 2; ++ii) {
-                    floatx4 v = acc[2 * hf + ii][j] + bc;
+                    floatx4 x = v[j][ii];
+                    if constexpr (EPI == kEpiGelu) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) v[r] = gelu_tab(v[r], Ptab);
-                    *reinterpret_cast<bf16x4 *>(stg + (ii * 16 + fr) * kStgStrideB + 2 * (j * 16 + (lane >> 4) * 4)) =
-                        to_bf16x4(v);
+                        for (int r = 0; r < 4; ++r) x[r] = gelu_tab(x[r], Ptab);
+                    } else if constexpr (EPI == kEpiGeluSave) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) x[r] = gelu_erfc(x[r]);
+                    } else {
+                        const int64_t row = row0 + wm * WM + (2 * hf + ii) * 16 + fr;
+                        const bf16x4 pv =
+                            *reinterpret_cast<const bf16x4 *>(P + row * ldc + col0 + wn * WN + j * 16 + fc);
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) x[r] *= gelu_grad(float(pv[r]));
+                    }
+                    *reinterpret_cast<bf16x4 *>(stg + (ii * 16 + fr) * kStgStrideB + 2 * (j * 16 + fc)) =
+                        to_bf16x4(x);
                 }
-            }
-            stage_flush<32>(stg, dst + hf * 32 * ldb_c, ldb_c, lane);
+            stage_flush<32>(stg, reinterpret_cast<uint8_t *>(C) + off0 + hf * 32 * ldb_c, ldb_c, lane);
         }
         return;
     }
+    // the linear epilogue (bias only) stores in the MFMA layout
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
         const int col = col0 + wn * WN + j * 16 + (lane >> 4) * 4;
-        const floatx4 bc = (EPI == kEpiGeluGrad) ? floatx4{0.f, 0.f, 0.f, 0.f}
-                                                 : *reinterpret_cast<const floatx4 *>(bias + col);
+        const floatx4 bc = *reinterpret_cast<const floatx4 *>(bias + col);
 #pragma unroll
         for (int i = 0; i < TM; ++i) {
             const int64_t row = row0 + wm * WM + i * 16 + fr;
             const int64_t off = row * ldc + col;
-            floatx4 v = acc[i][j] + bc;
-            if (EPI == kEpiGeluSave) *reinterpret_cast<bf16x4 *>(P + off) = to_bf16x4(v);
-            if (EPI == kEpiGeluSave) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) v[r] = gelu_erfc(v[r]);
-            }
-            if (EPI == kEpiGeluGrad) {
-                const bf16x4 pv = *reinterpret_cast<const bf16x4 *>(P + off);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) v[r] *= gelu_grad(float(pv[r]));
-            }
+            const floatx4 v = acc[i][j] + bc;
             *reinterpret_cast<bf16x4 *>(C + off) = to_bf16x4(v);
         }
     }
@@ -685,8 +704,9 @@ df_status launch_gemm_bf16_epi(const bf16_t *A, int lda, const bf16_t *B, int ld
                                int ldc, int64_t M, int N, int K, GemmEpi epi, bf16_t *P, hipStream_t stream) {
     if (M % BM || N % BN || K % BK || K <= 0 || lda % 8 || ldb % 8)
         return fail(DF_E_INVALID, "gemm: shapes must be multiples of the tile sizes");
-    // the inference outputs are written as 16-byte row pieces
-    if (epi == GemmEpi::gelu && ((reinterpret_cast<uintptr_t>(C) & 15) || ldc % 8))
+    // the outputs of every epilogue but the linear one are written as 16-byte row pieces
+    if (epi != GemmEpi::linear && ((reinterpret_cast<uintptr_t>(C) & 15) || ldc % 8 ||
+                                   (epi == GemmEpi::gelu_save && (reinterpret_cast<uintptr_t>(P) & 15))))
         return fail(DF_E_INVALID, "gemm: the output rows must be 16-byte aligned");
     if ((epi == GemmEpi::gelu_save || epi == GemmEpi::gelu_grad) && !P)
         return fail(DF_E_INVALID, "gemm: the epilogue needs the pre-activation array");
