@@ -287,8 +287,8 @@ df_status df_chem_autotune_workspace_size(const df_mech *mech, int64_t n_cells, 
  * Pick the schedule of df_chem_step / df_chem_step_cells for a workload (the cells-per-wave
  * choice of uneven stiffness: one cell per 16 or 32 lanes, or one cell per lane for all cells or
  * for the cold cells first): time one step of each candidate -- static schedule with the cost
- * order, with the given mapping and (for the automatic or 16-lane mapping) with 32 lanes per
- * cell and with one cell per lane (where that kernel is compiled for the species count); queue
+ * order, with the given mapping (the automatic one runs the 32-lane head of mapping 5 there) and
+ * (for the automatic or 16-lane mapping) with 32 lanes per cell and with one cell per lane (where that kernel is compiled for the species count); queue
  * schedule with every wave as 16-lane groups; queue schedule with a half or a quarter of the
  * waves as 16-lane groups from the start -- on copies of the input, and write the fastest into
  * opts->schedule, opts->coop_blocks and opts->mapping (the other fields are kept and used for
